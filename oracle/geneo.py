@@ -1,0 +1,170 @@
+"""Oracle: GenEO local eigenproblems, coarse space and coarse matrix.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Section 3.1 defines the local Dirichlet matrices A_j = R_j A R_j^T.  Section
+3.2 (eq-geneo) defines, on each subdomain, the generalised eigenproblem
+a_{Omega_j}(p, v) = lambda a_{Omega_j^o}(Xi_j p, Xi_j v) for all v in
+V_h(Omega_j); Section 3.3.2 (eqm:matrixForm) writes it as
+A_{Omega_j} p = lambda X A_{Omega_j^o} X p with ascending eigenvalues and
+||p||_2 = 1, solved in shift-and-invert mode with a small shift.  The GenEO
+coarse space (its Definition in Section 3.2) is spanned by R_j^T Xi_j p_k^j,
+k <= m_j; Section 3.3.2 numbers the basis Phi_{i(j,k)} = X^(j) p_k^j padded by
+zeros, N_H = sum_j m_j; Section 3.3.3 defines A_H = R_H A R_H^T.
+
+The oracle computes the eigenpairs with dense linear algebra: with
+P = A_N + s B (SPD for s > 0) and its Cholesky factor L, the pencil is
+equivalent to the symmetric problem  L^-1 B L^-T w = nu w  with
+lambda = 1/nu - s and p = L^-T w.  A_H is formed from its global definition
+Phi^T (A Phi), not from the local products the GPU uses.
+
+Readings: the shift is s = 1e-2 (algorithmic only: the eigenvalues do not
+depend on it, and a test runs two shifts); m_j is either a fixed count or the
+number of eigenvalues strictly below a threshold (capped), then extended while
+the next eigenvalue is equal to the last within 1e-8 relative (+1e-10
+absolute) so that a degenerate cluster is never split; each eigenvector is
+scaled to unit 2-norm with its largest-magnitude entry positive (lowest index
+on ties).
+
+Pins (tests/test_oracle_geneo.py): eigen residual ||A_N p - lambda B p||,
+B-orthogonality, exactly 6 (elasticity) / 1 (scalar) zero eigenvalues on
+floating subdomains and none on clamped ones, independence of the shift, a
+brute-force characteristic-polynomial check on a tiny pencil, A_H by local
+products equal to the global product, A_H SPD.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from .dd import Decomposition
+from .fem import elem_dofs
+
+
+def local_dirichlet(A, I) -> np.ndarray:
+    """A_j = R_j A R_j^T as a dense matrix (Section 3.1)."""
+    return A[I][:, I].toarray()
+
+
+def local_assembly(w, dec: Decomposition, Ke: np.ndarray, j: int, elem_mask: np.ndarray,
+                   dofs_local: np.ndarray) -> np.ndarray:
+    """Sum of K_e over the masked elements on the DOF list ``dofs_local`` (free ids)."""
+    pos = -np.ones(w.n_free, dtype=np.int64)
+    pos[dofs_local] = np.arange(len(dofs_local))
+    n = len(dofs_local)
+    M = np.zeros((n, n))
+    el = np.flatnonzero(elem_mask)
+    fd = dec.free_of_full[elem_dofs(w, dec.en[el])]
+    for t in range(len(el)):
+        f = fd[t]
+        keep = f >= 0
+        loc = pos[f[keep]]
+        if np.any(loc < 0):
+            raise ValueError("element DOF outside the local DOF set")
+        M[np.ix_(loc, loc)] += Ke[el[t]][np.ix_(keep, keep)]
+    return M
+
+
+def pencil(w, dec: Decomposition, Ke: np.ndarray, j: int):
+    """(A_N, B) on Ibar_j: A_N = A_{Omega_j}, B = X A_{Omega_j^o} X."""
+    Ib = dec.Ibar[j]
+    AN = local_assembly(w, dec, Ke, j, dec.E[j], Ib)
+    AO = local_assembly(w, dec, Ke, j, dec.E_ov[j], Ib)
+    X = dec.X[j]
+    B = X[:, None] * AO * X[None, :]
+    return AN, B
+
+
+def pencil_eig(AN: np.ndarray, B: np.ndarray, shift: float = 1e-2):
+    """All eigenpairs (ascending lambda, inf for the null space of B)."""
+    P = AN + shift * B
+    L = np.linalg.cholesky(P)
+    Linv_B = sla.solve_triangular(L, B, lower=True)
+    C = sla.solve_triangular(L, Linv_B.T, lower=True)    # L^-1 B L^-T (symmetric)
+    C = 0.5 * (C + C.T)
+    nu, W = np.linalg.eigh(C)
+    order = np.argsort(-nu)                                # largest nu first
+    nu, W = nu[order], W[:, order]
+    with np.errstate(divide="ignore"):
+        lam = np.where(nu > 1e-14 / shift, 1.0 / nu - shift, np.inf)
+    Pv = sla.solve_triangular(L.T, W, lower=False)
+    Pv = normalise(Pv)
+    return lam, Pv
+
+
+def normalise(Pv: np.ndarray) -> np.ndarray:
+    """Unit 2-norm columns, largest-magnitude entry positive (first on ties)."""
+    Pv = Pv / np.linalg.norm(Pv, axis=0, keepdims=True)
+    idx = np.argmax(np.abs(Pv), axis=0)
+    sgn = np.sign(Pv[idx, np.arange(Pv.shape[1])])
+    sgn[sgn == 0] = 1.0
+    return Pv * sgn[None, :]
+
+
+def select_count(lam: np.ndarray, nev: int, threshold: float, nev_max: int) -> int:
+    """m_j: fixed count, or #{lambda < threshold} capped; then cluster completion."""
+    finite = int(np.sum(np.isfinite(lam)))
+    if nev > 0:
+        m = min(nev, finite)
+    else:
+        m = int(np.sum(lam < threshold))
+        if nev_max > 0:
+            m = min(m, nev_max)
+    cap = nev_max if nev_max > 0 else finite
+    cap = max(cap, m)
+    while 0 < m < min(cap, finite) and lam[m] - lam[m - 1] <= 1e-8 * abs(lam[m - 1]) + 1e-10:
+        m += 1
+    return m
+
+
+class GenEO:
+    """Local factors, eigenpairs, coarse basis and coarse matrix."""
+
+    def __init__(self, w, A, Ke, dec: Decomposition | None = None, shift: float = 1e-2,
+                 coarse: bool = True, keep_all: bool = False):
+        self.w = w
+        self.A = A
+        self.dec = dec if dec is not None else Decomposition(w)
+        self.shift = shift
+        d = self.dec
+        self.Aj_chol = []
+        for I in d.I:
+            self.Aj_chol.append(sla.cho_factor(local_dirichlet(A, I), lower=True))
+        self.lam, self.m, self.P = [], [], []
+        if not coarse:
+            self.NH = 0
+            return
+        for j in range(d.n_sub):
+            AN, B = pencil(w, d, Ke, j)
+            lam, Pv = pencil_eig(AN, B, shift)
+            m = select_count(lam, w.nev, w.threshold, w.nev_max)
+            self.lam.append(lam if keep_all else lam[: max(m + 8, 16)])
+            self.m.append(m)
+            self.P.append(Pv[:, :m])
+        self.offsets = np.concatenate([[0], np.cumsum(self.m)]).astype(np.int64)
+        self.NH = int(self.offsets[-1])
+        Phi = np.zeros((w.n_free, self.NH))
+        for j in range(d.n_sub):
+            Ib = d.Ibar[j]
+            Phi[Ib, self.offsets[j]: self.offsets[j + 1]] = d.X[j][:, None] * self.P[j]
+        self.Phi = Phi
+        self.AH = Phi.T @ (A @ Phi)
+        self.AH = 0.5 * (self.AH + self.AH.T)
+        self.AH_chol = sla.cho_factor(self.AH, lower=True) if self.NH > 0 else None
+
+    def apply_as1(self, r: np.ndarray) -> np.ndarray:
+        """One-level additive Schwarz sum_j R_j^T A_j^-1 R_j r (eqn:onelevelAS)."""
+        z = np.zeros_like(r)
+        for I, c in zip(self.dec.I, self.Aj_chol):
+            z[I] += sla.cho_solve(c, r[I])
+        return z
+
+    def apply_coarse(self, r: np.ndarray) -> np.ndarray:
+        """R_H^T A_H^-1 R_H r with (R_H v)_i = Phi_i^T v (Section 3.3.3)."""
+        if self.NH == 0:
+            return np.zeros_like(r)
+        return self.Phi @ sla.cho_solve(self.AH_chol, self.Phi.T @ r)
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        """Two-level additive Schwarz M^-1_{AS,2} r (Section 3.1)."""
+        return self.apply_as1(r) + self.apply_coarse(r)

@@ -1,0 +1,110 @@
+"""Pins of the oracle's GenEO eigenproblems and coarse space (Sections 3.2, 3.3)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import dd, fem, geneo
+from workloads import generate as gen
+
+
+def _setup(kind, seed=0, **kw):
+    w = gen.small_case(kind, seed=seed, **kw)
+    A, b, free = fem.assemble(w)
+    Ke = fem.element_matrices(w)
+    d = dd.Decomposition(w)
+    return w, A, b, Ke, d
+
+
+def test_known_spectrum_pencil():
+    # A = V^-T Da V^-1, B = V^-T Db V^-1 has eigenvalues Da/Db (inf where Db = 0)
+    rng = np.random.default_rng(3)
+    n = 9
+    V = rng.standard_normal((n, n)) + 3 * np.eye(n)
+    Vi = np.linalg.inv(V)
+    Da = np.array([0.0, 0.0, 0.3, 1.0, 2.0, 5.0, 7.0, 1.0, 4.0])
+    Db = np.array([1.0, 2.0, 1.0, 0.5, 1.0, 1.0, 0.0, 0.0, 2.0])
+    A = Vi.T @ np.diag(Da + 1e-300) @ Vi
+    A = A + Vi.T @ np.diag((Db == 0) * 3.0) @ Vi   # keep A + sB definite on null(B)
+    B = Vi.T @ np.diag(Db) @ Vi
+    A, B = 0.5 * (A + A.T), 0.5 * (B + B.T)
+    lam, P = geneo.pencil_eig(A, B, shift=1e-2)
+    expect = np.sort(np.where(Db > 0, Da / np.where(Db > 0, Db, 1), np.inf))
+    fin = np.isfinite(expect)
+    assert np.allclose(lam[fin], expect[fin], atol=1e-10)
+    assert np.all(~np.isfinite(lam[~fin]) | (lam[~fin] > 1e8))
+
+
+@pytest.mark.parametrize("kind,kw,zero_modes", [
+    ("laminate", dict(nxy=(8, 6), n_ply=2, nparts=(2, 2, 1)), 6),
+    ("diffusion", dict(ne=(10, 8, 6), nparts=(2, 2, 2), dirichlet_faces=("x0",)), 1),
+])
+def test_eigen_residual_zero_modes_and_shift_independence(kind, kw, zero_modes):
+    w, A, b, Ke, d = _setup(kind, seed=4, **kw)
+    boxes = dd.subdomain_boxes(w)
+    for j in range(d.n_sub):
+        AN, B = geneo.pencil(w, d, Ke, j)
+        lam, P = geneo.pencil_eig(AN, B, 1e-2)
+        k = 12
+        nA = np.linalg.norm(AN, 2)
+        for i in range(k):
+            r = AN @ P[:, i] - lam[i] * (B @ P[:, i])
+            assert np.linalg.norm(r) <= 1e-10 * nA, (j, i)
+        G = P[:, :k].T @ B @ P[:, :k]
+        off = G - np.diag(np.diag(G))
+        assert np.max(np.abs(off)) <= 1e-9 * np.max(np.abs(np.diag(G)))
+        floating = boxes[j][0][0] > 0           # not touching the Dirichlet face x = 0
+        nzero = int(np.sum(np.abs(lam) < 1e-8))
+        assert nzero == (zero_modes if floating else 0), (j, lam[:8])
+        lam2, _ = geneo.pencil_eig(AN, B, 1e-1)
+        sel = lam[:k] > 1e-6
+        assert np.allclose(lam2[:k][sel], lam[:k][sel], rtol=1e-9)
+
+
+def test_selection_rule_and_cluster_completion():
+    lam = np.array([0.0, 0.0, 0.01, 0.05, 0.05 * (1 + 1e-12), 0.2, np.inf])
+    assert geneo.select_count(lam, 4, 0, 0) == 5          # cluster completed
+    assert geneo.select_count(lam, 2, 0, 0) == 2
+    assert geneo.select_count(lam, 0, 0.15, 0) == 5
+    assert geneo.select_count(lam, 0, 0.15, 3) == 3
+    assert geneo.select_count(lam, 0, 0.3, 0) == 6
+
+
+def test_local_dirichlet_matrix_equals_local_assembly():
+    w, A, b, Ke, d = _setup("laminate", seed=2, nxy=(8, 6), n_ply=2, nparts=(2, 2, 1))
+    for j in range(d.n_sub):
+        Aj = geneo.local_dirichlet(A, d.I[j])
+        loc = geneo.local_assembly(w, d, Ke, j, d.E[j], d.Ibar[j])
+        pos = np.searchsorted(d.Ibar[j], d.I[j])
+        assert np.allclose(Aj, loc[np.ix_(pos, pos)], rtol=0, atol=1e-9 * abs(Aj).max())
+
+
+@pytest.mark.parametrize("kind,kw", [
+    ("laminate", dict(nxy=(8, 6), n_ply=2, nparts=(2, 2, 1), nev=6)),
+    ("diffusion", dict(ne=(10, 8, 6), nparts=(2, 2, 2), threshold=0.3, nev_max=10)),
+])
+def test_coarse_matrix_local_products_equal_global(kind, kw):
+    w, A, b, Ke, d = _setup(kind, seed=3, **kw)
+    g = geneo.GenEO(w, A, Ke, d)
+    assert g.NH == sum(g.m) and g.NH > 0
+    # Section 3.3.3: (A_H)_{il} = Phi_i^T  Atilde_{j(i)} Phi_l with Atilde_j = A on Ibar_j
+    AH = np.zeros((g.NH, g.NH))
+    for j in range(d.n_sub):
+        Ib = d.Ibar[j]
+        At = A[Ib][:, Ib]
+        rows = slice(g.offsets[j], g.offsets[j + 1])
+        AH[rows, :] = g.Phi[Ib, rows].T @ (At @ g.Phi[Ib, :])
+    assert np.allclose(AH, g.AH, rtol=0, atol=1e-10 * np.abs(g.AH).max())
+    ev = np.linalg.eigvalsh(g.AH)
+    assert ev[0] > 0
+
+
+def test_coarse_correction_invariant_under_basis_change():
+    w, A, b, Ke, d = _setup("laminate", seed=3, nxy=(8, 6), n_ply=2, nparts=(2, 2, 1), nev=5)
+    g = geneo.GenEO(w, A, Ke, d)
+    r = np.random.default_rng(1).standard_normal(w.n_free)
+    z1 = g.apply_coarse(r)
+    Gm = np.random.default_rng(2).standard_normal((g.NH, g.NH)) + 4 * np.eye(g.NH)
+    Phi2 = g.Phi @ Gm
+    AH2 = Phi2.T @ (A @ Phi2)
+    z2 = Phi2 @ np.linalg.solve(AH2, Phi2.T @ r)
+    assert np.allclose(z1, z2, rtol=1e-8, atol=1e-10 * np.abs(z1).max())

@@ -1,0 +1,76 @@
+"""Pins of the oracle's PCG, preconditioners and condition estimate (Section 3.1)."""
+import numpy as np
+import pytest
+
+from oracle import dd, fem, geneo, pcg
+from workloads import generate as gen
+
+
+def _setup(kind, seed=0, **kw):
+    w = gen.small_case(kind, seed=seed, **kw)
+    A, b, free = fem.assemble(w)
+    Ke = fem.element_matrices(w)
+    return w, A, b, Ke
+
+
+@pytest.mark.parametrize("kind,kw", [
+    ("laminate", dict(nxy=(6, 4), n_ply=2, nparts=(2, 2, 1), nev=6)),
+    ("diffusion", dict(ne=(8, 6, 5), nparts=(2, 2, 1), threshold=0.2, nev_max=8)),
+])
+def test_pcg_matches_dense_direct_solve(kind, kw):
+    w, A, b, Ke = _setup(kind, seed=1, **kw)
+    u_ref = np.linalg.solve(A.toarray(), b[:, 0])
+    g = geneo.GenEO(w, A, Ke)
+    u, info = pcg.pcg(A, b[:, 0], g.apply, rtol=1e-13, maxit=500)
+    assert info["converged"]
+    assert np.linalg.norm(u - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+    # attainable true residual is ~ eps * ||A|| ||u|| / ||b|| (thin resin layers make A ill-conditioned)
+    assert info["true_rel_res"] <= 1e-9
+
+
+def test_single_subdomain_is_exact_inverse():
+    w, A, b, Ke = _setup("laminate", seed=2, nxy=(5, 4), n_ply=2, nparts=(1, 1, 1), nev=0,
+                         threshold=0.0)
+    g = geneo.GenEO(w, A, Ke, coarse=False)
+    u, info = pcg.pcg(A, b[:, 0], g.apply, rtol=1e-10)
+    assert info["iters"] == 1
+
+
+@pytest.mark.parametrize("coarse", [False, True])
+def test_preconditioner_symmetric_positive_definite(coarse):
+    w, A, b, Ke = _setup("laminate", seed=3, nxy=(6, 4), n_ply=2, nparts=(3, 2, 1), nev=4)
+    g = geneo.GenEO(w, A, Ke, coarse=coarse)
+    n = w.n_free
+    M = np.stack([g.apply(e) for e in np.eye(n)], axis=1)
+    assert np.max(np.abs(M - M.T)) <= 1e-10 * np.max(np.abs(M))
+    assert np.linalg.eigvalsh(0.5 * (M + M.T))[0] > 0
+
+
+def test_kappa_estimate_against_dense_spectrum():
+    w, A, b, Ke = _setup("laminate", seed=4, nxy=(6, 4), n_ply=2, nparts=(2, 2, 1), nev=4)
+    g = geneo.GenEO(w, A, Ke)
+    n = w.n_free
+    M = np.stack([g.apply(e) for e in np.eye(n)], axis=1)
+    ev = np.sort(np.linalg.eigvals(M @ A.toarray()).real)
+    kappa = ev[-1] / ev[0]
+    rhs = np.random.default_rng(0).standard_normal(n)
+    _, info = pcg.pcg(A, rhs, g.apply, rtol=1e-14, maxit=400)
+    assert abs(info["kappa"] - kappa) <= 1e-3 * kappa
+
+
+def test_geneo_flat_where_one_level_grows():
+    # qualitative Table 1 pattern: more subdomains -> one-level AS condition number
+    # and iterations grow, while the GenEO estimate stays O(10)
+    it_as, it_g, k_as, k_g = [], [], [], []
+    for nparts in [(2, 1, 1), (8, 2, 1)]:
+        w, A, b, Ke = _setup("laminate", seed=5, nxy=(16, 4), n_ply=3, nparts=nparts, nev=8)
+        g = geneo.GenEO(w, A, Ke)
+        _, i1 = pcg.pcg(A, b[:, 0], g.apply_as1, rtol=1e-8, maxit=2000)
+        _, i2 = pcg.pcg(A, b[:, 0], g.apply, rtol=1e-8, maxit=2000)
+        it_as.append(i1["iters"])
+        it_g.append(i2["iters"])
+        k_as.append(i1["kappa"])
+        k_g.append(i2["kappa"])
+    assert it_as[1] > 2 * it_as[0] and k_as[1] > 10 * k_as[0]
+    assert max(k_g) < 20
+    assert it_g[1] < it_as[1] / 2
