@@ -1,0 +1,201 @@
+/*
+ * genpcg.h -- C ABI of the MI355X GenEO-preconditioned CG library.
+ *
+ * The library solves the Q1 finite-element system A u = b of anisotropic
+ * linear elasticity or scalar diffusion (Butler et al., arXiv 1901.05188,
+ * Section 2: eq:strongForm, eq-fe, eqn:fe_matrix_system; Section 6: eqn:Darcy,
+ * eq-fe-darcy) by conjugate gradients (Section 3.1, eqn:KrylovSubspace)
+ * preconditioned with two-level additive Schwarz (Section 3.1, eqn:onelevelAS
+ * and M^-1_{AS,2}) whose coarse space is GenEO (Section 3.2, eq-geneo and the
+ * coarse-space definition; Section 3.3, eqm:matrixForm and the coarse
+ * assembly).
+ *
+ * Conventions shared by every entry point:
+ *  - Structured grid of ne[0] x ne[1] x ne[2] hexahedra; node (i,j,k) has id
+ *    i + (ne[0]+1)*(j + (ne[1]+1)*k); element (ex,ey,ez) has id
+ *    ex + ne[0]*(ey + ne[1]*ez).
+ *  - DOF vectors exchanged through the ABI use the FREE numbering: node id
+ *    ascending, component fastest within a node, homogeneous Dirichlet DOFs
+ *    removed.  Multi-column vectors are column-major with leading dimension
+ *    ld >= n_free.
+ *  - Host arrays (const pointers in the option/input structs) are read during
+ *    the call and not retained.  Pointers documented as device pointers must
+ *    point to device memory of the current HIP device (e.g. a torch tensor's
+ *    data_ptr()) and are accessed in stream order on the given stream.
+ *  - `stream` is a hipStream_t (NULL = the default stream).
+ *  - Handles own their device memory until gn_destroy_*.  No C++ exception
+ *    crosses the ABI.  On error *out is set to NULL, inputs are untouched, a
+ *    negative status is returned and gn_last_error() describes the failure
+ *    (thread-local string, valid until the next call on the same thread).
+ */
+#ifndef GENPCG_H
+#define GENPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gn_status;
+enum {
+  GN_OK = 0,
+  GN_WARN_MAXIT = 1,          /* solve stopped at maxit; last iterate returned   */
+  GN_ERR_ARG = -1,            /* invalid argument / inconsistent sizes           */
+  GN_ERR_OOM = -2,            /* device allocation failed                        */
+  GN_ERR_NOT_SPD = -3,        /* a Cholesky factorisation met a non-positive pivot */
+  GN_ERR_EIG_NOCONV = -4,     /* a GenEO eigensolve did not converge in eig_maxit */
+  GN_ERR_COARSE_SINGULAR = -5,/* coarse matrix A_H not positive definite         */
+  GN_ERR_DEVICE = -6,         /* HIP runtime error                               */
+  GN_ERR_BREAKDOWN = -7       /* CG breakdown (p^T A p <= 0)                     */
+};
+
+typedef struct gn_problem gn_problem; /* device-resident A, b, element matrices */
+typedef struct gn_precond gn_precond; /* local factors, coarse basis, coarse factor */
+
+/* Tensor grid.  xn[a] holds ne[a]+1 increasing node coordinates (mm).
+ * map_kind 0: identity.  map_kind 1: ramp, map_par = {x0, x1, angle}: the node
+ * (x,y,z) is placed at (x, y, z + tan(angle)*(clamp(x,x0,x1) - x0)). */
+typedef struct gn_grid {
+  int32_t ne[3];
+  const double* xn[3];
+  int32_t map_kind;
+  const double* map_par;
+} gn_grid;
+
+/* Material description (Section 2, eq-hooke and the ply paragraph).
+ * pde 1 (elasticity): mat holds n_mat rows of 9 engineering constants
+ *   (E1,E2,E3,G12,G13,G23,nu12,nu13,nu23) in MPa; elem_mat[e] selects the row;
+ *   elem_angle[e] (radians, may be NULL = 0) rotates the material about +z
+ *   (counter-clockwise seen from +z); elem_tilt[e] (may be NULL = 0) then tilts
+ *   it about y so that the material x axis becomes (cos t, 0, sin t).
+ * pde 0 (scalar diffusion): elem_k[e] > 0 is the conductivity of element e;
+ *   mat/elem_mat/elem_angle/elem_tilt are ignored. */
+typedef struct gn_material {
+  int32_t pde;
+  int32_t n_mat;
+  const double* mat;
+  const int32_t* elem_mat;
+  const double* elem_angle;
+  const double* elem_tilt;
+  const double* elem_k;
+} gn_material;
+
+/* Boundary conditions and loads (Section 2, eq-boundary, eq:strongForm).
+ * dirichlet[node*ncomp + c] = 1 marks a homogeneous Dirichlet DOF.
+ * body (may be NULL): constant body force per element, ncomp values each.
+ * traction (may be NULL): constant traction on the top face (z = max) of each
+ *   top-layer element, layout [rhs][face = ex + ne[0]*ey][comp].
+ * The assembled load has nrhs columns; the body force is added to each. */
+typedef struct gn_loads {
+  const uint8_t* dirichlet;
+  const double* body;
+  int32_t nrhs;
+  const double* traction;
+} gn_loads;
+
+/* Assemble A (27-point node-block matrix, FP64) and b on the device
+ * (eqn:fe_matrix_system, 2x2x2 Gauss).  Returns a problem handle. */
+gn_status gn_assemble(const gn_grid* grid, const gn_material* mat, const gn_loads* loads,
+                      void* stream, gn_problem** out);
+
+/* Sizes: number of free DOFs, stored matrix entries, number of load columns. */
+gn_status gn_problem_info(const gn_problem* p, int64_t* n_free, int64_t* nnz, int32_t* nrhs);
+
+/* Copy the assembled load (n_free x nrhs, column-major, leading dim ld) into
+ * the device buffer b_dev. */
+gn_status gn_problem_rhs(const gn_problem* p, double* b_dev, int64_t ld, void* stream);
+
+/* y = A x for ncol columns (device pointers, free numbering, leading dim ld). */
+gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t ncol,
+                    int64_t ld, void* stream);
+
+/* Domain decomposition and GenEO options (Section 3.1: non-overlapping boxes
+ * extended by `overlap` element layers; Section 3.2: m_j eigenvectors).
+ * cuts[a] holds nparts[a]+1 increasing element indices from 0 to ne[a].
+ * m_j = nev if nev > 0, else #{lambda < threshold} capped at nev_max (if > 0);
+ * then extended while the next eigenvalue repeats the last within 1e-8
+ * relative + 1e-10 absolute.  coarse = 0 builds the one-level method only.
+ * local_prec 64 stores FP64 local factors, 32 stores them in FP32 (FP64
+ * factorisation, FP32 storage and triangular solves, FP64 accumulation of the
+ * result).  shift > 0 is the shift-and-invert shift (Section 3.3.2; 0 = 1e-2).
+ * eig_tol / eig_maxit bound the batched eigensolver (0 = defaults 1e-12 / 300):
+ * it stops when every wanted Ritz pair has ||P^-1 B v - nu v|| <= eig_tol ||P^-1 B v||,
+ * or when that residual stays below 1e-9 without halving for 15 iterations. */
+typedef struct gn_dd_opts {
+  int32_t nparts[3];
+  const int32_t* cuts[3];
+  int32_t overlap;
+  int32_t nev;
+  double threshold;
+  int32_t nev_max;
+  int32_t local_prec;
+  int32_t coarse;
+  double shift;
+  double eig_tol;
+  int32_t eig_maxit;
+} gn_dd_opts;
+
+typedef struct gn_setup_report {
+  int32_t n_sub;
+  int64_t coarse_dim;
+  int32_t eig_iters;         /* iterations of the batched eigensolver          */
+  int32_t max_local_n;       /* largest local system size                      */
+  int32_t band_tiles;        /* band width in 32-row tiles (largest subdomain) */
+  double t_local_s, t_eigen_s, t_coarse_s, t_total_s;
+  int64_t hbm_bytes;         /* device bytes held by the preconditioner        */
+  double eig_resid;          /* largest final relative Ritz residual           */
+} gn_setup_report;
+
+/* Build the preconditioner: local Dirichlet factors A_j = L_j L_j^T
+ * (Section 3.1), GenEO eigenpairs of A_{Omega_j} p = lambda X A_{Omega_j^o} X p
+ * (eqm:matrixForm), coarse basis Phi_{i(j,k)} = X^(j) p_k^j and coarse matrix
+ * A_H = R_H A R_H^T by local products (Section 3.3.3), and its factor. */
+gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* opts, void* stream,
+                         gn_precond** out, gn_setup_report* report);
+
+/* Eigenvalues lambda_1..lambda_n of subdomain `sub` (ascending), up to cap of
+ * them, into host array out; *m receives m_j, *n_avail the number computed. */
+gn_status gn_precond_eigenvalues(const gn_precond* pc, int32_t sub, double* out, int32_t cap,
+                                 int32_t* m, int32_t* n_avail);
+
+/* z = M^-1 r for one column (device pointers, free numbering). */
+gn_status gn_precond_apply(gn_precond* pc, const double* r_dev, double* z_dev, void* stream);
+
+typedef struct gn_solve_opts {
+  double rtol;          /* stop when ||r||_2 <= rtol ||b||_2                   */
+  int32_t maxit;
+  int32_t check_every;  /* iterations per host convergence check (0 = 8)       */
+} gn_solve_opts;
+
+typedef struct gn_solve_report {
+  int32_t iters;
+  int32_t converged;
+  double rel_res;       /* recursive residual norm / ||b||                    */
+  double true_rel_res;  /* ||b - A x|| / ||b|| recomputed at exit             */
+  double cond_est;      /* extreme eigenvalue ratio of the CG-Lanczos tridiagonal */
+  double t_solve_s;
+} gn_solve_report;
+
+/* Solve A x = b by PCG with x0 = 0 for nrhs columns (device pointers, free
+ * numbering, column-major, leading dim ld).  pc = NULL runs plain CG.
+ * reports (host, nrhs entries) may be NULL. */
+gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev, double* x_dev,
+                   int32_t nrhs, int64_t ld, const gn_solve_opts* opts, void* stream,
+                   gn_solve_report* reports);
+
+/* Per-kernel timing with HIP events on the library's launch stream.  enable=1
+ * starts recording every launch of the named kernel group ("spmv", "trsv",
+ * "prolong", "coarse", "vec"); gn_profile_read returns the summed milliseconds,
+ * the number of launches and the algorithmic bytes those launches move. */
+gn_status gn_profile_enable(int32_t enable);
+gn_status gn_profile_read(const char* group, double* total_ms, int64_t* launches, double* bytes);
+
+void gn_destroy_problem(gn_problem* p);
+void gn_destroy_precond(gn_precond* pc);
+const char* gn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GENPCG_H */

@@ -270,14 +270,14 @@ def load_full(w) -> np.ndarray:
                 b[dofs[e], :] += be[:, None]
     if w.traction is not None:
         nx, ny, nz = w.ne
-        g = w.traction.reshape(nx * ny, nc, w.nrhs)
+        g = w.traction.reshape(w.nrhs, nx * ny, nc)          # [rhs][face][comp]
         top = np.arange(nx * ny) + nx * ny * (nz - 1)
         en = elem_nodes(w, top)
         dofs = elem_dofs(w, en)
         for t in range(nx * ny):
             for r in range(w.nrhs):
-                if np.any(g[t, :, r] != 0):
-                    b[dofs[t], r] += fe_top_traction(X[en[t]], g[t, :, r])
+                if np.any(g[r, t] != 0):
+                    b[dofs[t], r] += fe_top_traction(X[en[t]], g[r, t])
     return b
 
 

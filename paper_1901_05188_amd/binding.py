@@ -1,0 +1,282 @@
+"""ctypes binding of libgenpcg (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts numpy
+host arrays and torch device tensors into the plain pointers and sizes of the
+C ABI (include/genpcg.h) and turns status codes into exceptions.  Importing it
+without the built library raises immediately: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgenpcg.so")
+
+GN_OK, GN_WARN_MAXIT = 0, 1
+STATUS = {0: "OK", 1: "WARN_MAXIT", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_NOT_SPD",
+          -4: "ERR_EIG_NOCONV", -5: "ERR_COARSE_SINGULAR", -6: "ERR_DEVICE", -7: "ERR_BREAKDOWN"}
+EXPORTS = ["gn_assemble", "gn_problem_info", "gn_problem_rhs", "gn_matvec", "gn_setup_geneo",
+           "gn_precond_eigenvalues", "gn_precond_apply", "gn_solve", "gn_profile_enable",
+           "gn_profile_read", "gn_destroy_problem", "gn_destroy_precond", "gn_last_error"]
+
+
+class GenPCGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class gn_grid(C.Structure):
+    _fields_ = [("ne", C.c_int32 * 3), ("xn", C.POINTER(C.c_double) * 3),
+                ("map_kind", C.c_int32), ("map_par", C.POINTER(C.c_double))]
+
+
+class gn_material(C.Structure):
+    _fields_ = [("pde", C.c_int32), ("n_mat", C.c_int32), ("mat", C.POINTER(C.c_double)),
+                ("elem_mat", C.POINTER(C.c_int32)), ("elem_angle", C.POINTER(C.c_double)),
+                ("elem_tilt", C.POINTER(C.c_double)), ("elem_k", C.POINTER(C.c_double))]
+
+
+class gn_loads(C.Structure):
+    _fields_ = [("dirichlet", C.POINTER(C.c_uint8)), ("body", C.POINTER(C.c_double)),
+                ("nrhs", C.c_int32), ("traction", C.POINTER(C.c_double))]
+
+
+class gn_dd_opts(C.Structure):
+    _fields_ = [("nparts", C.c_int32 * 3), ("cuts", C.POINTER(C.c_int32) * 3),
+                ("overlap", C.c_int32), ("nev", C.c_int32), ("threshold", C.c_double),
+                ("nev_max", C.c_int32), ("local_prec", C.c_int32), ("coarse", C.c_int32),
+                ("shift", C.c_double), ("eig_tol", C.c_double), ("eig_maxit", C.c_int32)]
+
+
+class gn_setup_report(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("coarse_dim", C.c_int64), ("eig_iters", C.c_int32),
+                ("max_local_n", C.c_int32), ("band_tiles", C.c_int32),
+                ("t_local_s", C.c_double), ("t_eigen_s", C.c_double), ("t_coarse_s", C.c_double),
+                ("t_total_s", C.c_double), ("hbm_bytes", C.c_int64), ("eig_resid", C.c_double)]
+
+
+class gn_solve_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32)]
+
+
+class gn_solve_report(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double), ("cond_est", C.c_double), ("t_solve_s", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libgenpcg.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.gn_assemble.argtypes = [C.POINTER(gn_grid), C.POINTER(gn_material), C.POINTER(gn_loads), vp,
+                                  C.POINTER(vp)]
+        L.gn_problem_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int32)]
+        L.gn_problem_rhs.argtypes = [vp, vp, C.c_int64, vp]
+        L.gn_matvec.argtypes = [vp, vp, vp, C.c_int32, C.c_int64, vp]
+        L.gn_setup_geneo.argtypes = [vp, C.POINTER(gn_dd_opts), vp, C.POINTER(vp),
+                                     C.POINTER(gn_setup_report)]
+        L.gn_precond_eigenvalues.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                             C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.gn_precond_apply.argtypes = [vp, vp, vp, vp]
+        L.gn_solve.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int64, C.POINTER(gn_solve_opts), vp,
+                               C.POINTER(gn_solve_report)]
+        L.gn_profile_enable.argtypes = [C.c_int32]
+        L.gn_profile_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_double)]
+        L.gn_destroy_problem.argtypes = [vp]
+        L.gn_destroy_problem.restype = None
+        L.gn_destroy_precond.argtypes = [vp]
+        L.gn_destroy_precond.restype = None
+        L.gn_last_error.restype = C.c_char_p
+        for f in EXPORTS:
+            if f not in ("gn_destroy_problem", "gn_destroy_precond", "gn_last_error"):
+                getattr(L, f).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(code: int) -> int:
+    if code < 0:
+        raise GenPCGError(code, lib().gn_last_error().decode())
+    return code
+
+
+def _dptr(a: Optional[np.ndarray], ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _tensor_ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+class Problem:
+    """Assembled system on the device (gn_assemble)."""
+
+    def __init__(self, ne, xn, pde, *, mats=None, elem_mat=None, elem_angle=None, elem_tilt=None,
+                 elem_k=None, dirichlet, body=None, nrhs=1, traction=None, map_kind=0,
+                 map_par=None, stream=None):
+        keep = []
+
+        def arr(a, dt):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a
+
+        g = gn_grid()
+        for a in range(3):
+            g.ne[a] = int(ne[a])
+            g.xn[a] = _dptr(arr(xn[a], np.float64), C.c_double)
+        g.map_kind = int(map_kind)
+        g.map_par = _dptr(arr(map_par, np.float64), C.c_double)
+        m = gn_material()
+        m.pde = int(pde)
+        mats_a = arr(mats, np.float64)
+        m.n_mat = 0 if mats_a is None else mats_a.shape[0]
+        m.mat = _dptr(mats_a, C.c_double)
+        m.elem_mat = _dptr(arr(elem_mat, np.int32), C.c_int32)
+        m.elem_angle = _dptr(arr(elem_angle, np.float64), C.c_double)
+        m.elem_tilt = _dptr(arr(elem_tilt, np.float64), C.c_double)
+        m.elem_k = _dptr(arr(elem_k, np.float64), C.c_double)
+        l = gn_loads()
+        l.dirichlet = _dptr(arr(dirichlet, np.uint8), C.c_uint8)
+        l.body = _dptr(arr(body, np.float64), C.c_double)
+        l.nrhs = int(nrhs)
+        l.traction = _dptr(arr(traction, np.float64), C.c_double)
+        h = C.c_void_p()
+        _check(lib().gn_assemble(C.byref(g), C.byref(m), C.byref(l), _stream(stream), C.byref(h)))
+        self.handle = h
+        nf, nnz, nr = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().gn_problem_info(h, C.byref(nf), C.byref(nnz), C.byref(nr)))
+        self.n_free, self.nnz, self.nrhs = nf.value, nnz.value, nr.value
+
+    @classmethod
+    def from_workload(cls, w, stream=None) -> "Problem":
+        return cls(w.ne, w.xn, w.pde, mats=w.mats, elem_mat=w.elem_mat, elem_angle=w.elem_angle,
+                   elem_tilt=w.elem_tilt, elem_k=w.elem_k, dirichlet=w.dirichlet, body=w.body,
+                   nrhs=w.nrhs, traction=w.traction, map_kind=w.map_kind, map_par=w.map_par,
+                   stream=stream)
+
+    def rhs(self, out, stream=None):
+        """Copy the assembled load into a (nrhs, n_free) float64 CUDA tensor (column = row of out)."""
+        assert out.is_cuda and out.dtype.is_floating_point and out.is_contiguous()
+        assert out.shape[-1] == self.n_free and out.numel() >= self.nrhs * self.n_free
+        _check(lib().gn_problem_rhs(self.handle, _tensor_ptr(out), self.n_free, _stream(stream)))
+        return out
+
+    def matvec(self, x, y, stream=None):
+        """y = A x for (ncol, n_free) float64 CUDA tensors."""
+        ncol = 1 if x.dim() == 1 else x.shape[0]
+        assert x.shape == y.shape and x.shape[-1] == self.n_free and x.is_contiguous() and y.is_contiguous()
+        _check(lib().gn_matvec(self.handle, _tensor_ptr(x), _tensor_ptr(y), ncol, self.n_free,
+                               _stream(stream)))
+        return y
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gn_destroy_problem(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Preconditioner:
+    """GenEO two-level additive Schwarz preconditioner (gn_setup_geneo)."""
+
+    def __init__(self, prob: Problem, nparts: Sequence[int], cuts, overlap=1, nev=0, threshold=0.0,
+                 nev_max=0, local_prec=64, coarse=True, shift=0.0, eig_tol=0.0, eig_maxit=0,
+                 stream=None):
+        o = gn_dd_opts()
+        keep = []
+        for a in range(3):
+            o.nparts[a] = int(nparts[a])
+            c = np.ascontiguousarray(cuts[a], dtype=np.int32)
+            keep.append(c)
+            o.cuts[a] = _dptr(c, C.c_int32)
+        o.overlap, o.nev, o.threshold, o.nev_max = int(overlap), int(nev), float(threshold), int(nev_max)
+        o.local_prec, o.coarse = int(local_prec), int(bool(coarse))
+        o.shift, o.eig_tol, o.eig_maxit = float(shift), float(eig_tol), int(eig_maxit)
+        rep = gn_setup_report()
+        h = C.c_void_p()
+        _check(lib().gn_setup_geneo(prob.handle, C.byref(o), _stream(stream), C.byref(h), C.byref(rep)))
+        self.handle = h
+        self.prob = prob
+        self.report = {f: getattr(rep, f) for f, _ in gn_setup_report._fields_}
+
+    @classmethod
+    def from_workload(cls, prob: Problem, w, local_prec=64, coarse=True, stream=None, **kw):
+        return cls(prob, w.nparts, w.cuts, overlap=w.overlap, nev=w.nev, threshold=w.threshold,
+                   nev_max=w.nev_max, local_prec=local_prec, coarse=coarse, stream=stream, **kw)
+
+    def eigenvalues(self, sub: int):
+        buf = (C.c_double * 128)()
+        m, n = C.c_int32(), C.c_int32()
+        _check(lib().gn_precond_eigenvalues(self.handle, int(sub), buf, 128, C.byref(m), C.byref(n)))
+        return np.array(buf[: n.value]), m.value
+
+    def apply(self, r, z, stream=None):
+        assert r.shape == z.shape and r.shape[-1] == self.prob.n_free
+        _check(lib().gn_precond_apply(self.handle, _tensor_ptr(r), _tensor_ptr(z), _stream(stream)))
+        return z
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gn_destroy_precond(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(prob: Problem, pc: Optional[Preconditioner], b, x, rtol=1e-8, maxit=1000, check_every=8,
+          stream=None):
+    """PCG (x0 = 0) on (nrhs, n_free) float64 CUDA tensors; returns (status, reports)."""
+    nrhs = 1 if b.dim() == 1 else b.shape[0]
+    assert b.shape == x.shape and b.shape[-1] == prob.n_free and b.is_contiguous() and x.is_contiguous()
+    o = gn_solve_opts(float(rtol), int(maxit), int(check_every))
+    reps = (gn_solve_report * nrhs)()
+    st = _check(lib().gn_solve(prob.handle, pc.handle if pc is not None else None, _tensor_ptr(b),
+                               _tensor_ptr(x), nrhs, prob.n_free, C.byref(o), _stream(stream), reps))
+    return st, [{f: getattr(r, f) for f, _ in gn_solve_report._fields_} for r in reps]
+
+
+def profile_enable(on: bool = True):
+    _check(lib().gn_profile_enable(1 if on else 0))
+
+
+def profile_read(group: str):
+    ms, n, by = C.c_double(), C.c_int64(), C.c_double()
+    _check(lib().gn_profile_read(group.encode(), C.byref(ms), C.byref(n), C.byref(by)))
+    return ms.value, n.value, by.value

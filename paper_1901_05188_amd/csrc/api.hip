@@ -1,0 +1,902 @@
+// Host orchestration behind the C ABI declared in include/genpcg.h.
+//
+// gn_assemble     : Section 2 (eq-fe, eqn:fe_matrix_system) on the device.
+// gn_setup_geneo  : Section 3.1 (overlapping boxes, A_j), Section 3.2 (PoU,
+//                   eq-geneo, coarse space), Section 3.3 (eqm:matrixForm,
+//                   coarse assembly by local products, coarse factor).
+// gn_solve        : Section 3.1 (preconditioned CG, x0 = 0), with the
+//                   CG-Lanczos condition estimate the tables report.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "gn_internal.h"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+void gn_set_error(gn_status code, const std::string& msg) {
+  (void)code;
+  g_last_error = msg;
+}
+extern "C" const char* gn_last_error(void) { return g_last_error.c_str(); }
+
+#define GN_TRY try {
+#define GN_CATCH                                                  \
+  }                                                               \
+  catch (const gn_error& e) {                                     \
+    gn_set_error(e.code, e.msg);                                  \
+    return e.code;                                                \
+  }                                                               \
+  catch (const std::bad_alloc&) {                                 \
+    gn_set_error(GN_ERR_OOM, "host allocation failed");           \
+    return GN_ERR_OOM;                                            \
+  }                                                               \
+  catch (...) {                                                   \
+    gn_set_error(GN_ERR_DEVICE, "unexpected exception");          \
+    return GN_ERR_DEVICE;                                         \
+  }
+
+static void argfail(const std::string& m) { throw gn_error{GN_ERR_ARG, m}; }
+
+template <typename T>
+static T* dalloc(std::vector<void*>& owned, size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  GN_HIP(hipMalloc(&p, count * sizeof(T)));
+  owned.push_back(p);
+  return (T*)p;
+}
+static void dfree_all(std::vector<void*>& owned) {
+  for (void* p : owned) (void)hipFree(p);
+  owned.clear();
+}
+template <typename T>
+static T* upload(std::vector<void*>& owned, const T* h, size_t count, hipStream_t s) {
+  T* d = dalloc<T>(owned, count);
+  GN_HIP(hipMemcpyAsync(d, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+  return d;
+}
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// kernel-group profiling with HIP events
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfRec {
+  int group;
+  double bytes;
+  hipEvent_t e0, e1;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+double g_prof_ms[PROF_NGROUP] = {0};
+double g_prof_bytes[PROF_NGROUP] = {0};
+int64_t g_prof_n[PROF_NGROUP] = {0};
+const char* g_prof_names[PROF_NGROUP] = {"spmv", "trsv", "prolong", "coarse", "vec"};
+
+void prof_drain() {
+  for (auto& r : g_prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+      g_prof_ms[r.group] += ms;
+      g_prof_bytes[r.group] += r.bytes;
+      g_prof_n[r.group] += 1;
+    }
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  g_prof_pending.clear();
+}
+}  // namespace
+
+GnProfScope::GnProfScope(int g, double b, hipStream_t st) : group(g), bytes(b), s(st), on(false) {
+  if (!g_prof_on) return;
+  if (hipEventCreate(&e0) != hipSuccess) return;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return;
+  }
+  (void)hipEventRecord(e0, s);
+  on = true;
+}
+GnProfScope::~GnProfScope() {
+  if (!on) return;
+  (void)hipEventRecord(e1, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_pending.push_back(ProfRec{group, bytes, e0, e1});
+}
+
+extern "C" gn_status gn_profile_enable(int32_t enable) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_drain();
+  g_prof_on = enable != 0;
+  for (int i = 0; i < PROF_NGROUP; ++i) g_prof_ms[i] = g_prof_bytes[i] = 0.0, g_prof_n[i] = 0;
+  return GN_OK;
+}
+
+extern "C" gn_status gn_profile_read(const char* group, double* total_ms, int64_t* launches,
+                                     double* bytes) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_drain();
+  for (int i = 0; i < PROF_NGROUP; ++i) {
+    if (group && std::strcmp(group, g_prof_names[i]) == 0) {
+      if (total_ms) *total_ms = g_prof_ms[i];
+      if (launches) *launches = g_prof_n[i];
+      if (bytes) *bytes = g_prof_bytes[i];
+      return GN_OK;
+    }
+  }
+  gn_set_error(GN_ERR_ARG, "unknown profile group");
+  return GN_ERR_ARG;
+}
+
+// ---------------------------------------------------------------------------
+// assembly
+// ---------------------------------------------------------------------------
+extern "C" gn_status gn_assemble(const gn_grid* grid, const gn_material* mat, const gn_loads* loads,
+                                 void* stream, gn_problem** out) {
+  if (out) *out = nullptr;
+  gn_problem* p = nullptr;
+  GN_TRY
+  if (!grid || !mat || !loads || !out) argfail("null argument");
+  hipStream_t s = (hipStream_t)stream;
+  for (int a = 0; a < 3; ++a) {
+    if (grid->ne[a] < 1) argfail("ne must be >= 1 on every axis");
+    if (!grid->xn[a]) argfail("missing node coordinates");
+    for (int i = 0; i < grid->ne[a]; ++i)
+      if (!(grid->xn[a][i + 1] > grid->xn[a][i])) argfail("node coordinates must increase");
+  }
+  if (mat->pde != 0 && mat->pde != 1) argfail("pde must be 0 (diffusion) or 1 (elasticity)");
+  if (grid->map_kind != 0 && grid->map_kind != 1) argfail("map_kind must be 0 or 1");
+  if (grid->map_kind == 1 && !grid->map_par) argfail("ramp map needs map_par");
+  if (!loads->dirichlet) argfail("missing Dirichlet mask");
+  if (loads->nrhs < 1) argfail("nrhs must be >= 1");
+  p = new gn_problem();
+  p->pde = mat->pde;
+  p->nc = mat->pde == 1 ? 3 : 1;
+  for (int a = 0; a < 3; ++a) {
+    p->ne[a] = grid->ne[a];
+    p->nn[a] = grid->ne[a] + 1;
+  }
+  p->n_node = (int64_t)p->nn[0] * p->nn[1] * p->nn[2];
+  p->n_elem = (int64_t)p->ne[0] * p->ne[1] * p->ne[2];
+  p->n_dof = p->n_node * p->nc;
+  if (p->n_dof >= (int64_t)1 << 31) argfail("problem too large for 32-bit DOF indices");
+  p->nrhs = loads->nrhs;
+  p->map_kind = grid->map_kind;
+  if (grid->map_kind == 1)
+    for (int a = 0; a < 3; ++a) p->map_par[a] = grid->map_par[a];
+  const int nc = p->nc;
+  // host-side validation of element data
+  if (p->pde == 1) {
+    if (!mat->mat || !mat->elem_mat || mat->n_mat < 1) argfail("elasticity needs materials");
+    for (int m = 0; m < mat->n_mat; ++m) {
+      const double* c = mat->mat + 9 * m;
+      for (int k = 0; k < 6; ++k)
+        if (!(c[k] > 0.0)) argfail("moduli must be positive");
+    }
+    for (int64_t e = 0; e < p->n_elem; ++e)
+      if (mat->elem_mat[e] < 0 || mat->elem_mat[e] >= mat->n_mat) argfail("elem_mat out of range");
+  } else {
+    if (!mat->elem_k) argfail("diffusion needs elem_k");
+    for (int64_t e = 0; e < p->n_elem; ++e)
+      if (!(mat->elem_k[e] > 0.0) || !std::isfinite(mat->elem_k[e])) argfail("elem_k must be positive");
+  }
+  if (loads->body)
+    for (int64_t i = 0; i < p->n_elem * nc; ++i)
+      if (!std::isfinite(loads->body[i])) argfail("non-finite body force");
+  if (loads->traction)
+    for (int64_t i = 0; i < (int64_t)loads->nrhs * p->ne[0] * p->ne[1] * nc; ++i)
+      if (!std::isfinite(loads->traction[i])) argfail("non-finite traction");
+  // free numbering
+  std::vector<int> f2f;
+  f2f.reserve((size_t)p->n_dof);
+  for (int64_t d = 0; d < p->n_dof; ++d)
+    if (!loads->dirichlet[d]) f2f.push_back((int)d);
+  p->n_free = (int64_t)f2f.size();
+  if (p->n_free == 0) argfail("no free DOFs");
+  std::vector<void*> tmp;
+  for (int a = 0; a < 3; ++a) p->d_xn[a] = upload(p->owned, grid->xn[a], (size_t)p->nn[a], s);
+  p->d_dir = upload(p->owned, loads->dirichlet, (size_t)p->n_dof, s);
+  p->d_free2full = upload(p->owned, f2f.data(), f2f.size(), s);
+  const int nd = 8 * nc;
+  p->d_Ke = dalloc<double>(p->owned, (size_t)p->n_elem * nd * nd);
+  p->d_A = dalloc<double>(p->owned, (size_t)p->n_node * 27 * nc * nc);
+  p->d_b = dalloc<double>(p->owned, (size_t)p->n_dof * p->nrhs);
+  const double *d_mats = nullptr, *d_eang = nullptr, *d_etilt = nullptr, *d_ek = nullptr;
+  const int* d_emat = nullptr;
+  if (p->pde == 1) {
+    d_mats = upload(tmp, mat->mat, (size_t)9 * mat->n_mat, s);
+    d_emat = upload(tmp, mat->elem_mat, (size_t)p->n_elem, s);
+    if (mat->elem_angle) d_eang = upload(tmp, mat->elem_angle, (size_t)p->n_elem, s);
+    if (mat->elem_tilt) d_etilt = upload(tmp, mat->elem_tilt, (size_t)p->n_elem, s);
+  } else {
+    d_ek = upload(tmp, mat->elem_k, (size_t)p->n_elem, s);
+  }
+  const double *d_body = nullptr, *d_trac = nullptr;
+  if (loads->body) d_body = upload(tmp, loads->body, (size_t)p->n_elem * nc, s);
+  if (loads->traction)
+    d_trac = upload(tmp, loads->traction, (size_t)loads->nrhs * p->ne[0] * p->ne[1] * nc, s);
+  gnk::element_matrices(p, d_mats, mat->n_mat, d_emat, d_eang, d_etilt, d_ek, s);
+  gnk::assemble_matrix(p, s);
+  gnk::assemble_load(p, d_body, d_trac, s);
+  GN_HIP(hipStreamSynchronize(s));
+  dfree_all(tmp);
+  // CG workspace
+  p->d_x = dalloc<double>(p->owned, (size_t)p->n_dof);
+  p->d_r = dalloc<double>(p->owned, (size_t)p->n_dof);
+  p->d_p = dalloc<double>(p->owned, (size_t)p->n_dof);
+  p->d_q = dalloc<double>(p->owned, (size_t)p->n_dof);
+  p->d_z = dalloc<double>(p->owned, (size_t)p->n_dof);
+  int nb = std::max(std::max(gnk::spmv_blocks(p), gnk::reduce_blocks()), gnk::prolong_blocks(p));
+  p->d_part = dalloc<double>(p->owned, (size_t)nb);
+  p->d_scal = dalloc<double>(p->owned, 64);
+  GN_HIP(hipMemsetAsync(p->d_p, 0, sizeof(double) * p->n_dof, s));
+  GN_HIP(hipMemsetAsync(p->d_scal, 0, sizeof(double) * 64, s));
+  GN_HIP(hipStreamSynchronize(s));
+  *out = p;
+  return GN_OK;
+  }
+  catch (const gn_error& e) {
+    if (p) { dfree_all(p->owned); delete p; }
+    gn_set_error(e.code, e.msg);
+    return e.code;
+  }
+  catch (...) {
+    if (p) { dfree_all(p->owned); delete p; }
+    gn_set_error(GN_ERR_DEVICE, "unexpected exception in gn_assemble");
+    return GN_ERR_DEVICE;
+  }
+}
+
+extern "C" gn_status gn_problem_info(const gn_problem* p, int64_t* n_free, int64_t* nnz, int32_t* nrhs) {
+  if (!p) {
+    gn_set_error(GN_ERR_ARG, "null problem");
+    return GN_ERR_ARG;
+  }
+  if (n_free) *n_free = p->n_free;
+  if (nnz) *nnz = p->n_node * 27 * p->nc * p->nc;
+  if (nrhs) *nrhs = p->nrhs;
+  return GN_OK;
+}
+
+extern "C" gn_status gn_problem_rhs(const gn_problem* p, double* b_dev, int64_t ld, void* stream) {
+  GN_TRY
+  if (!p || !b_dev) argfail("null argument");
+  if (ld < p->n_free) argfail("ld < n_free");
+  hipStream_t s = (hipStream_t)stream;
+  for (int c = 0; c < p->nrhs; ++c) gnk::gather_free(p, p->d_b + (int64_t)c * p->n_dof, b_dev + c * ld, s);
+  return GN_OK;
+  GN_CATCH
+}
+
+extern "C" gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t ncol,
+                               int64_t ld, void* stream) {
+  GN_TRY
+  if (!p || !x_dev || !y_dev) argfail("null argument");
+  if (ncol < 1 || ld < p->n_free) argfail("bad ncol/ld");
+  hipStream_t s = (hipStream_t)stream;
+  for (int c = 0; c < ncol; ++c) {
+    gnk::scatter_free(p, x_dev + c * ld, p->d_p, s);
+    gnk::spmv_flag(p, p->d_p, p->d_q, nullptr, nullptr, s);
+    gnk::gather_free(p, p->d_q, y_dev + c * ld, s);
+  }
+  return GN_OK;
+  GN_CATCH
+}
+
+// ---------------------------------------------------------------------------
+// decomposition + GenEO set-up
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BandRefH {
+  int64_t offT, offD;
+  int NB, w;
+};
+
+void axis_perm(const int n[3], int perm[3]) {
+  perm[0] = 0, perm[1] = 1, perm[2] = 2;
+  std::stable_sort(perm, perm + 3, [&](int a, int b) { return n[a] < n[b]; });
+}
+
+int band_width_dofs(const int n[3], const int perm[3], int nc) {
+  int64_t d0 = n[perm[0]], d1 = n[perm[1]];
+  return (int)((1 + d0 + d0 * d1) * nc + nc - 1);
+}
+
+// eigenvalues of a symmetric tridiagonal matrix by Sturm bisection
+void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e, double* lo, double* hi) {
+  int n = (int)d.size();
+  double gl = 1e300, gu = -1e300;
+  for (int i = 0; i < n; ++i) {
+    double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+    gl = std::min(gl, d[i] - r);
+    gu = std::max(gu, d[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < n; ++i) {
+      double e2 = i > 0 ? e[i - 1] * e[i - 1] : 0.0;
+      q = d[i] - x - (i > 0 ? e2 / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  auto kth = [&](int k) {  // k-th smallest (0-based)
+    double a = gl, b = gu;
+    for (int it = 0; it < 200; ++it) {
+      double m = 0.5 * (a + b);
+      if (count_below(m) > k) b = m; else a = m;
+      if (b - a <= 1e-15 * std::max(std::fabs(a), std::fabs(b))) break;
+    }
+    return 0.5 * (a + b);
+  };
+  *lo = kth(0);
+  *hi = kth(n - 1);
+}
+
+}  // namespace
+
+extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* stream, gn_precond** out,
+                                    gn_setup_report* rep) {
+  if (out) *out = nullptr;
+  gn_precond* pc = nullptr;
+  std::vector<void*> tmp;
+  GN_TRY
+  if (!p || !o || !out) argfail("null argument");
+  hipStream_t s = (hipStream_t)stream;
+  const double t0 = now_s();
+  const int nc = p->nc;
+  for (int a = 0; a < 3; ++a) {
+    if (o->nparts[a] < 1) argfail("nparts must be >= 1");
+    if (!o->cuts[a]) argfail("missing cuts");
+    if (o->cuts[a][0] != 0 || o->cuts[a][o->nparts[a]] != p->ne[a]) argfail("cuts must span 0..ne");
+    for (int q = 0; q < o->nparts[a]; ++q)
+      if (o->cuts[a][q + 1] <= o->cuts[a][q]) argfail("cuts must increase");
+  }
+  const int n_sub = o->nparts[0] * o->nparts[1] * o->nparts[2];
+  if (n_sub > 1 && o->overlap < 1) argfail("overlap must be >= 1");
+  if (o->local_prec != 64 && o->local_prec != 32) argfail("local_prec must be 64 or 32");
+  const int O = std::max(o->overlap, 0);
+  const double shift = o->shift > 0 ? o->shift : 1e-2;
+  const double eig_tol = o->eig_tol > 0 ? o->eig_tol : 1e-12;
+  const int eig_maxit = o->eig_maxit > 0 ? o->eig_maxit : 300;
+  if (o->coarse && o->nev <= 0 && !(o->threshold > 0)) argfail("coarse space needs nev > 0 or threshold > 0");
+  if (o->coarse && o->nev > 48) argfail("nev must be <= 48");
+  if (o->coarse && o->nev <= 0 && (o->nev_max <= 0 || o->nev_max > 48))
+    argfail("threshold mode needs 0 < nev_max <= 48");
+  pc = new gn_precond();
+  pc->prob = p;
+  pc->n_sub = n_sub;
+  pc->overlap = O;
+  pc->local_prec = o->local_prec;
+  for (int a = 0; a < 3; ++a) {
+    pc->nparts[a] = o->nparts[a];
+    pc->cuts[a].assign(o->cuts[a], o->cuts[a] + o->nparts[a] + 1);
+  }
+  // per-axis ranges: element range of part q, its I node range and Ibar node range
+  std::vector<int> eR0[3], eR1[3], iR0[3], iR1[3];
+  for (int a = 0; a < 3; ++a) {
+    int P = o->nparts[a], ne = p->ne[a];
+    std::vector<int> cnt(ne + 1, 0), plo(ne + 1, -1), ec(ne, 0);
+    for (int q = 0; q < P; ++q) {
+      int e0 = std::max(0, pc->cuts[a][q] - O), e1 = std::min(ne, pc->cuts[a][q + 1] + O);
+      int i0 = e0 + (e0 > 0 ? 1 : 0), i1 = e1 - (e1 < ne ? 1 : 0);   // inclusive node range
+      eR0[a].push_back(e0);
+      eR1[a].push_back(e1);
+      iR0[a].push_back(i0);
+      iR1[a].push_back(i1);
+      for (int i = i0; i <= i1; ++i) {
+        if (cnt[i] == 0) plo[i] = q;
+        ++cnt[i];
+      }
+      for (int e = e0; e < e1; ++e) ++ec[e];
+    }
+    for (int i = 0; i <= ne; ++i)
+      if (cnt[i] == 0) argfail("a node lies in no subdomain interior: overlap too small");
+    for (int i = 0; i <= ne; ++i)
+      if (cnt[i] > 0)
+        for (int q = plo[i]; q < plo[i] + cnt[i]; ++q)
+          if (i < iR0[a][q] || i > iR1[a][q]) argfail("non-contiguous subdomain cover");
+    pc->d_cnt[a] = upload(pc->owned, cnt.data(), cnt.size(), s);
+    pc->d_plo[a] = upload(pc->owned, plo.data(), plo.size(), s);
+    pc->d_ecnt[a] = upload(pc->owned, ec.data(), ec.size(), s);
+  }
+  // subdomain descriptors
+  pc->sub.resize(n_sub);
+  int64_t offTI = 0, offDI = 0, offVI = 0, offTB = 0, offDB = 0, offVB = 0;
+  int maxNBI = 0, maxNBB = 0, maxNI = 0, maxNB_ = 0, maxw = 0;
+  for (int r = 0; r < o->nparts[2]; ++r)
+    for (int q = 0; q < o->nparts[1]; ++q)
+      for (int pp = 0; pp < o->nparts[0]; ++pp) {
+        int j = pp + o->nparts[0] * (q + o->nparts[1] * r);
+        SubDesc& sd = pc->sub[j];
+        std::memset(&sd, 0, sizeof(sd));
+        int idx[3] = {pp, q, r};
+        for (int a = 0; a < 3; ++a) {
+          sd.elo[a] = eR0[a][idx[a]];
+          sd.ehi[a] = eR1[a][idx[a]];
+          sd.ilo[a] = iR0[a][idx[a]];
+          sd.in_[a] = iR1[a][idx[a]] - iR0[a][idx[a]] + 1;
+          sd.blo[a] = sd.elo[a];
+          sd.bn[a] = sd.ehi[a] - sd.elo[a] + 1;
+        }
+        axis_perm(sd.in_, sd.permI);
+        axis_perm(sd.bn, sd.permB);
+        sd.nI = sd.in_[0] * sd.in_[1] * sd.in_[2] * nc;
+        sd.nB = sd.bn[0] * sd.bn[1] * sd.bn[2] * nc;
+        sd.NBI = (sd.nI + TILE - 1) / TILE;
+        sd.NBB = (sd.nB + TILE - 1) / TILE;
+        sd.wI = std::min(sd.NBI - 1, (band_width_dofs(sd.in_, sd.permI, nc) + TILE - 1) / TILE);
+        sd.wB = std::min(sd.NBB - 1, (band_width_dofs(sd.bn, sd.permB, nc) + TILE - 1) / TILE);
+        sd.wI = std::max(sd.wI, 0);
+        sd.wB = std::max(sd.wB, 0);
+        sd.offTI = offTI;
+        sd.offDI = offDI;
+        sd.offVI = offVI;
+        sd.offTB = offTB;
+        sd.offDB = offDB;
+        sd.offVB = offVB;
+        offTI += (int64_t)sd.NBI * (sd.wI + 1);
+        offDI += sd.NBI;
+        offVI += (int64_t)sd.NBI * TILE;
+        offTB += (int64_t)sd.NBB * (sd.wB + 1);
+        offDB += sd.NBB;
+        offVB += (int64_t)sd.NBB * TILE;
+        maxNBI = std::max(maxNBI, sd.NBI);
+        maxNBB = std::max(maxNBB, sd.NBB);
+        maxNI = std::max(maxNI, sd.nI);
+        maxNB_ = std::max(maxNB_, sd.nB);
+        maxw = std::max(maxw, sd.wI);
+      }
+  pc->tilesI = offTI;
+  pc->vecI = offVI;
+  pc->maxNBI = maxNBI;
+  pc->d_sub = upload(pc->owned, pc->sub.data(), pc->sub.size(), s);
+  int* d_info = dalloc<int>(tmp, (size_t)std::max(n_sub, 1) + 64);
+  GN_HIP(hipMemsetAsync(d_info, 0, sizeof(int) * (n_sub + 64), s));
+  std::vector<int> info(n_sub + 64);
+
+  // ---- local Dirichlet factors -------------------------------------------
+  double* LI = dalloc<double>(tmp, (size_t)offTI * TILE2);
+  double* DI = dalloc<double>(tmp, (size_t)offDI * TILE2);
+  GN_HIP(hipMemsetAsync(LI, 0, sizeof(double) * (size_t)offTI * TILE2, s));
+  gnk::extract_local(p, pc, LI, maxNBI, s);
+  std::vector<BandRefH> refs(n_sub);
+  for (int j = 0; j < n_sub; ++j) refs[j] = BandRefH{pc->sub[j].offTI, pc->sub[j].offDI, pc->sub[j].NBI, pc->sub[j].wI};
+  BandRefH* d_refs = upload(tmp, refs.data(), refs.size(), s);
+  gnk::band_chol(d_refs, n_sub, LI, DI, d_info, s);
+  GN_HIP(hipMemcpyAsync(info.data(), d_info, sizeof(int) * n_sub, hipMemcpyDeviceToHost, s));
+  GN_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < n_sub; ++j)
+    if (info[j]) throw gn_error{GN_ERR_NOT_SPD, "local matrix of subdomain " + std::to_string(j) +
+                                                    " not positive definite (row " + std::to_string(info[j] - 1) + ")"};
+  if (o->local_prec == 32) {
+    pc->d_LIf = dalloc<float>(pc->owned, (size_t)offTI * TILE2);
+    pc->d_DIf = dalloc<float>(pc->owned, (size_t)offDI * TILE2);
+    gnk::to_f32((int64_t)offTI * TILE2, LI, pc->d_LIf, s);
+    gnk::to_f32((int64_t)offDI * TILE2, DI, pc->d_DIf, s);
+  } else {
+    // keep the FP64 factor: move ownership from tmp to pc
+    tmp.erase(std::remove(tmp.begin(), tmp.end(), (void*)LI), tmp.end());
+    tmp.erase(std::remove(tmp.begin(), tmp.end(), (void*)DI), tmp.end());
+    pc->owned.push_back(LI);
+    pc->owned.push_back(DI);
+    pc->d_LI = LI;
+    pc->d_DI = DI;
+  }
+  pc->d_t = dalloc<double>(pc->owned, (size_t)offVI);
+  GN_HIP(hipMemsetAsync(pc->d_t, 0, sizeof(double) * offVI, s));
+  GN_HIP(hipStreamSynchronize(s));
+  const double t1 = now_s();
+  double t2 = t1, t3 = t1;
+  int eig_iters = 0;
+  double eig_resid = 0.0;
+
+  // ---- GenEO eigenproblems -------------------------------------------------
+  pc->NH = 0;
+  if (o->coarse && n_sub > 1) {
+    const bool fixed = o->nev > 0;
+    const int guard = 8;
+    int b = fixed ? std::min(64, o->nev + std::max(guard, o->nev / 2)) : std::min(64, o->nev_max + guard);
+    double* LB = dalloc<double>(tmp, (size_t)offTB * TILE2);
+    double* DB = dalloc<double>(tmp, (size_t)offDB * TILE2);
+    GN_HIP(hipMemsetAsync(LB, 0, sizeof(double) * (size_t)offTB * TILE2, s));
+    gnk::extract_pencil(p, pc, shift, LB, maxNBB, s);
+    for (int j = 0; j < n_sub; ++j) refs[j] = BandRefH{pc->sub[j].offTB, pc->sub[j].offDB, pc->sub[j].NBB, pc->sub[j].wB};
+    GN_HIP(hipMemcpyAsync(d_refs, refs.data(), sizeof(BandRefH) * n_sub, hipMemcpyHostToDevice, s));
+    GN_HIP(hipMemsetAsync(d_info, 0, sizeof(int) * n_sub, s));
+    gnk::band_chol(d_refs, n_sub, LB, DB, d_info, s);
+    GN_HIP(hipMemcpyAsync(info.data(), d_info, sizeof(int) * n_sub, hipMemcpyDeviceToHost, s));
+    GN_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < n_sub; ++j)
+      if (info[j]) throw gn_error{GN_ERR_NOT_SPD, "GenEO pencil of subdomain " + std::to_string(j) + " not definite"};
+    const size_t vlen = (size_t)offVB * b;
+    double* V = dalloc<double>(tmp, vlen);
+    double* Z = dalloc<double>(tmp, vlen);
+    double* BV = dalloc<double>(tmp, vlen);
+    double* BZ = dalloc<double>(tmp, vlen);
+    double* GP = dalloc<double>(tmp, (size_t)n_sub * b * b);
+    double* GB = dalloc<double>(tmp, (size_t)n_sub * b * b);
+    double* Y = dalloc<double>(tmp, (size_t)n_sub * b * b);
+    double* nu = dalloc<double>(tmp, (size_t)n_sub * b);
+    double* res = dalloc<double>(tmp, (size_t)n_sub * 2 * b);
+    GN_HIP(hipMemsetAsync(nu, 0, sizeof(double) * n_sub * b, s));
+    GN_HIP(hipMemsetAsync(d_info, 0, sizeof(int) * n_sub, s));
+    gnk::eig_vinit(pc, b, maxNBB, V, s);
+    std::vector<double> h_nu((size_t)n_sub * b), h_res((size_t)n_sub * 2 * b);
+    std::vector<int> nwant(n_sub, 0);
+    std::vector<double> worst_hist;
+    bool converged = false;
+    for (int it = 0; it < eig_maxit; ++it) {
+      gnk::eig_bapply(p, pc, b, maxNBB, V, BV, s);
+      GN_HIP(hipMemcpyAsync(Z, BV, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
+      gnk::eig_trsm(pc, b, LB, DB, Z, s);
+      gnk::eig_bapply(p, pc, b, maxNBB, Z, BZ, s);
+      gnk::eig_gram(pc, b, Z, BV, BZ, V, nu, GP, GB, res, s);
+      gnk::eig_small(n_sub, b, GP, GB, Y, nu, nullptr, s);
+      gnk::eig_vupdate(pc, b, maxNBB, Z, Y, V, s);
+      GN_HIP(hipMemcpyAsync(h_res.data(), res, sizeof(double) * h_res.size(), hipMemcpyDeviceToHost, s));
+      // residuals refer to the Ritz pairs of the previous iteration (h_nu before this copy)
+      std::vector<double> prev_nu = h_nu;
+      GN_HIP(hipMemcpyAsync(h_nu.data(), nu, sizeof(double) * h_nu.size(), hipMemcpyDeviceToHost, s));
+      GN_HIP(hipStreamSynchronize(s));
+      eig_iters = it + 1;
+      if (it == 0) continue;
+      bool all = true;
+      double worst = 0.0;   // largest relative residual over the wanted pairs
+      for (int j = 0; j < n_sub; ++j) {
+        // wanted pairs: nev+1 (fixed) or those below 1.5*threshold plus one (capped)
+        int nw;
+        if (fixed) {
+          nw = std::min(b - guard / 2, o->nev + 1);
+        } else {
+          nw = 0;
+          for (int k = 0; k < b; ++k) {
+            double nk = prev_nu[(size_t)j * b + k];
+            double lam = nk > 0 ? 1.0 / nk - shift : 1e300;
+            if (lam < 1.5 * o->threshold) nw = k + 1;
+          }
+          nw = std::min(std::min(nw + 1, o->nev_max + 1), b - guard / 2);
+        }
+        nwant[j] = nw;
+        for (int k = 0; k < nw; ++k) {
+          double nk = prev_nu[(size_t)j * b + k];
+          double rs = h_res[(size_t)j * 2 * b + k], zz = h_res[(size_t)j * 2 * b + b + k];
+          if (nk <= 1e-12 / shift) continue;      // null space of B: lambda = inf
+          double rel = zz > 0 ? std::sqrt(rs / zz) : 0.0;
+          if (!(rel <= eig_tol)) all = false;
+          if (!(rel <= worst)) worst = std::isfinite(rel) ? std::max(worst, rel) : 1e300;
+        }
+      }
+      worst_hist.push_back(worst);
+      eig_resid = worst;
+      // accept a residual that has reached the rounding floor: no halving over
+      // 15 iterations once it is below 1e-9
+      size_t h = worst_hist.size();
+      bool stagnated = h > 20 && worst <= 1e-9 && worst > 0.5 * worst_hist[h - 16];
+      if (all || stagnated) {
+        converged = true;
+        break;
+      }
+    }
+    if (!converged)
+      throw gn_error{GN_ERR_EIG_NOCONV, "GenEO eigensolver did not converge in " + std::to_string(eig_maxit) +
+                                            " iterations"};
+    // V now holds the Ritz vectors of the last Rayleigh-Ritz step (h_nu)
+    pc->n_eval = b;
+    pc->lam.assign((size_t)n_sub * b, 0.0);
+    pc->lam_n.assign(n_sub, b);
+    int coff = 0, maxm = 0;
+    for (int j = 0; j < n_sub; ++j) {
+      std::vector<double> lam(b);
+      for (int k = 0; k < b; ++k) {
+        double nk = h_nu[(size_t)j * b + k];
+        lam[k] = nk > 1e-12 / shift ? 1.0 / nk - shift : INFINITY;
+        pc->lam[(size_t)j * b + k] = lam[k];
+      }
+      int finite = 0;
+      for (int k = 0; k < b; ++k)
+        if (std::isfinite(lam[k])) ++finite;
+      int m;
+      if (fixed) {
+        m = std::min(o->nev, finite);
+      } else {
+        m = 0;
+        for (int k = 0; k < b; ++k)
+          if (lam[k] < o->threshold) ++m;
+        if (o->nev_max > 0) m = std::min(m, o->nev_max);
+      }
+      int cap = std::max(o->nev_max > 0 ? o->nev_max : finite, m);
+      cap = std::min(cap, b - 1);
+      while (m > 0 && m < std::min(cap, finite) && lam[m] - lam[m - 1] <= 1e-8 * std::fabs(lam[m - 1]) + 1e-10) ++m;
+      pc->sub[j].m = m;
+      pc->sub[j].coff = coff;
+      coff += m;
+      maxm = std::max(maxm, m);
+    }
+    pc->NH = coff;
+    gnk::eig_normalise(pc, b, maxm, V, s);
+    t2 = now_s();
+    // ---- coarse basis, coarse matrix, coarse factor ------------------------
+    if (pc->NH > 0) {
+      int64_t phi = 0;
+      for (int j = 0; j < n_sub; ++j) {
+        pc->sub[j].offPhi = phi;
+        phi += (int64_t)pc->sub[j].nI * pc->sub[j].m;
+      }
+      pc->phi_len = phi;
+      GN_HIP(hipMemcpyAsync(pc->d_sub, pc->sub.data(), sizeof(SubDesc) * n_sub, hipMemcpyHostToDevice, s));
+      pc->d_Phi = dalloc<double>(pc->owned, (size_t)phi);
+      gnk::build_phi(p, pc, b, maxNI, V, s);
+      gnk::aphi(p, pc, b, maxNB_, Z, s);
+      // pairs (j1, j2) with I_j1 cap Ibar_j2 nonempty
+      std::vector<char> pbuf;
+      int np = 0;
+      const int psz = gnk::pair_size();
+      for (int j1 = 0; j1 < n_sub; ++j1)
+        for (int j2 = 0; j2 < n_sub; ++j2) {
+          const SubDesc &a1 = pc->sub[j1], &a2 = pc->sub[j2];
+          if (a1.m == 0 || a2.m == 0) continue;
+          int lo[3], hi[3];
+          bool ok = true;
+          for (int a = 0; a < 3; ++a) {
+            lo[a] = std::max(a1.ilo[a], a2.blo[a]);
+            hi[a] = std::min(a1.ilo[a] + a1.in_[a], a2.blo[a] + a2.bn[a]);
+            ok &= hi[a] > lo[a];
+          }
+          if (!ok) continue;
+          pbuf.resize((size_t)(np + 1) * psz);
+          gnk::make_pair(pbuf.data() + (size_t)np * psz, j1, j2, lo, hi);
+          ++np;
+        }
+      char* d_pairs = upload(tmp, pbuf.data(), pbuf.size(), s);
+      pc->NBH = (pc->NH + TILE - 1) / TILE;
+      const size_t ahlen = (size_t)pc->NBH * pc->NBH * TILE2;
+      double* AH = dalloc<double>(tmp, ahlen);
+      double* DH = dalloc<double>(tmp, (size_t)pc->NBH * TILE2);
+      GN_HIP(hipMemsetAsync(AH, 0, sizeof(double) * ahlen, s));
+      gnk::ah_pairs(p, pc, d_pairs, np, b, Z, AH, s);
+      GN_HIP(hipMemsetAsync(d_info + n_sub, 0, sizeof(int), s));
+      gnk::dense_chol(pc->NBH, AH, DH, d_info + n_sub, s);
+      int hinfo = 0;
+      GN_HIP(hipMemcpyAsync(&hinfo, d_info + n_sub, sizeof(int), hipMemcpyDeviceToHost, s));
+      GN_HIP(hipStreamSynchronize(s));
+      if (hinfo) throw gn_error{GN_ERR_COARSE_SINGULAR, "coarse matrix not positive definite"};
+      pc->d_Z = dalloc<double>(pc->owned, ahlen);
+      gnk::tri_inv(pc->NBH, AH, DH, pc->d_Z, s);
+      pc->d_g = dalloc<double>(pc->owned, (size_t)pc->NBH * TILE);
+      pc->d_u = dalloc<double>(pc->owned, (size_t)pc->NBH * TILE);
+      pc->d_y = dalloc<double>(pc->owned, (size_t)pc->NBH * TILE);
+      GN_HIP(hipMemsetAsync(pc->d_g, 0, sizeof(double) * pc->NBH * TILE, s));
+      GN_HIP(hipMemsetAsync(pc->d_u, 0, sizeof(double) * pc->NBH * TILE, s));
+      GN_HIP(hipMemsetAsync(pc->d_y, 0, sizeof(double) * pc->NBH * TILE, s));
+    }
+    GN_HIP(hipStreamSynchronize(s));
+    t3 = now_s();
+  } else {
+    GN_HIP(hipMemcpyAsync(pc->d_sub, pc->sub.data(), sizeof(SubDesc) * n_sub, hipMemcpyHostToDevice, s));
+  }
+  GN_HIP(hipStreamSynchronize(s));
+  dfree_all(tmp);
+  // algorithmic bytes of one preconditioner application (for the roofline report)
+  {
+    const double fb = pc->local_prec == 32 ? 4.0 : 8.0;
+    double tb = 0.0, pb = 0.0;
+    for (const SubDesc& sd : pc->sub) {
+      // forward + backward sweep over the band (lower-triangle tiles touched) + inverse diagonals
+      double tiles = 0.0;
+      for (int K = 0; K < sd.NBI; ++K) tiles += std::min(K, sd.wI);
+      tb += 2.0 * (tiles + sd.NBI) * TILE2 * fb + (double)sd.nI * 8.0 * (1 + 1) + (double)sd.nI * sd.m * 8.0;
+      pb += (double)sd.nI * 8.0 + (double)sd.nI * sd.m * 8.0;
+    }
+    pc->trsv_bytes = tb;
+    pc->prolong_bytes = pb + (double)p->n_dof * 8.0 * 2.0;
+  }
+  int64_t hb = 0;
+  hb += (int64_t)pc->tilesI * TILE2 * (pc->local_prec == 32 ? 4 : 8);
+  hb += (int64_t)pc->sub.size() * 0;
+  hb += pc->phi_len * 8 + (int64_t)pc->NBH * pc->NBH * TILE2 * 8 + pc->vecI * 8;
+  if (rep) {
+    rep->n_sub = n_sub;
+    rep->coarse_dim = pc->NH;
+    rep->eig_iters = eig_iters;
+    rep->max_local_n = maxNI;
+    rep->band_tiles = maxw;
+    rep->t_local_s = t1 - t0;
+    rep->t_eigen_s = t2 - t1;
+    rep->t_coarse_s = t3 - t2;
+    rep->t_total_s = now_s() - t0;
+    rep->hbm_bytes = hb;
+    rep->eig_resid = eig_resid;
+  }
+  *out = pc;
+  return GN_OK;
+  }
+  catch (const gn_error& e) {
+    dfree_all(tmp);
+    if (pc) { dfree_all(pc->owned); delete pc; }
+    gn_set_error(e.code, e.msg);
+    return e.code;
+  }
+  catch (...) {
+    dfree_all(tmp);
+    if (pc) { dfree_all(pc->owned); delete pc; }
+    gn_set_error(GN_ERR_DEVICE, "unexpected exception in gn_setup_geneo");
+    return GN_ERR_DEVICE;
+  }
+}
+
+extern "C" gn_status gn_precond_eigenvalues(const gn_precond* pc, int32_t sub, double* out, int32_t cap,
+                                            int32_t* m, int32_t* n_avail) {
+  if (!pc || sub < 0 || sub >= pc->n_sub) {
+    gn_set_error(GN_ERR_ARG, "bad precond/subdomain");
+    return GN_ERR_ARG;
+  }
+  int n = pc->lam.empty() ? 0 : pc->n_eval;
+  if (m) *m = pc->sub[sub].m;
+  if (n_avail) *n_avail = n;
+  if (out)
+    for (int k = 0; k < std::min(n, (int)cap); ++k) out[k] = pc->lam[(size_t)sub * pc->n_eval + k];
+  return GN_OK;
+}
+
+// z = M^-1 r on full-numbering device vectors
+static void precond_full(gn_problem* p, gn_precond* pc, const double* r, double* z, double* part,
+                         const double* done, hipStream_t s) {
+  gnk::local_solve(p, pc, r, done, s);
+  gnk::coarse_solve(pc, done, s);
+  gnk::prolong(p, pc, r, z, part, done, s);
+}
+
+extern "C" gn_status gn_precond_apply(gn_precond* pc, const double* r_dev, double* z_dev, void* stream) {
+  GN_TRY
+  if (!pc || !r_dev || !z_dev) argfail("null argument");
+  gn_problem* p = pc->prob;
+  hipStream_t s = (hipStream_t)stream;
+  gnk::scatter_free(p, r_dev, p->d_r, s);
+  precond_full(p, pc, p->d_r, p->d_z, nullptr, nullptr, s);
+  gnk::gather_free(p, p->d_z, z_dev, s);
+  GN_HIP(hipStreamSynchronize(s));
+  return GN_OK;
+  GN_CATCH
+}
+
+// ---------------------------------------------------------------------------
+// PCG
+// ---------------------------------------------------------------------------
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITER, S_MAXIT, S_BREAK };
+enum { OP_BB = 0, OP_RZ0, OP_ALPHA, OP_RR, OP_BETA };
+
+extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev, double* x_dev,
+                              int32_t nrhs, int64_t ld, const gn_solve_opts* opts, void* stream,
+                              gn_solve_report* reports) {
+  GN_TRY
+  if (!p || !b_dev || !x_dev || !opts) argfail("null argument");
+  if (nrhs < 1 || ld < p->n_free) argfail("bad nrhs/ld");
+  if (!(opts->rtol > 0) || opts->maxit < 1) argfail("rtol > 0 and maxit >= 1 required");
+  if (pc && pc->prob != p) argfail("preconditioner built for another problem");
+  hipStream_t s = (hipStream_t)stream;
+  const int chunk = opts->check_every > 0 ? opts->check_every : 8;
+  const int64_t n = p->n_dof;
+  if (p->hist_cap < 2 * opts->maxit + 2) {
+    if (p->d_hist) {
+      (void)hipFree(p->d_hist);
+      p->owned.erase(std::remove(p->owned.begin(), p->owned.end(), (void*)p->d_hist), p->owned.end());
+    }
+    p->d_hist = dalloc<double>(p->owned, (size_t)2 * opts->maxit + 2);
+    p->hist_cap = 2 * opts->maxit + 2;
+  }
+  double* scal = p->d_scal;
+  const double* done = scal + S_DONE;
+  gn_status ret = GN_OK;
+  const int nbs = gnk::spmv_blocks(p), nbr = gnk::reduce_blocks(), nbp = gnk::prolong_blocks(p);
+  for (int col = 0; col < nrhs; ++col) {
+    const double tstart = now_s();
+    // r = b (x0 = 0), x = 0
+    gnk::scatter_free(p, b_dev + col * ld, p->d_r, s);
+    GN_HIP(hipMemsetAsync(p->d_x, 0, sizeof(double) * n, s));
+    double maxit_d = (double)opts->maxit;
+    GN_HIP(hipMemcpyAsync(scal + S_MAXIT, &maxit_d, sizeof(double), hipMemcpyHostToDevice, s));
+    gnk::dot_partial(n, p->d_r, p->d_r, p->d_part, nullptr, s);
+    gnk::finalize(p->d_part, nbr, OP_BB, scal, p->d_hist, opts->rtol, s);
+    if (pc) {
+      precond_full(p, pc, p->d_r, p->d_z, p->d_part, done, s);
+      gnk::finalize(p->d_part, nbp, OP_RZ0, scal, p->d_hist, opts->rtol, s);
+    } else {
+      gnk::copy(n, p->d_z, p->d_r, done, s);
+      gnk::dot_partial(n, p->d_r, p->d_z, p->d_part, done, s);
+      gnk::finalize(p->d_part, nbr, OP_RZ0, scal, p->d_hist, opts->rtol, s);
+    }
+    gnk::copy(n, p->d_p, p->d_z, done, s);
+    double hs[16];
+    int iters = 0;
+    bool fin = false;
+    while (!fin) {
+      for (int k = 0; k < chunk; ++k) {
+        gnk::spmv_flag(p, p->d_p, p->d_q, p->d_part, done, s);
+        gnk::finalize(p->d_part, nbs, OP_ALPHA, scal, p->d_hist, opts->rtol, s);
+        gnk::update_xr(n, p->d_x, p->d_r, p->d_p, p->d_q, scal, p->d_part, s);
+        gnk::finalize(p->d_part, nbr, OP_RR, scal, p->d_hist, opts->rtol, s);
+        if (pc) {
+          precond_full(p, pc, p->d_r, p->d_z, p->d_part, done, s);
+          gnk::finalize(p->d_part, nbp, OP_BETA, scal, p->d_hist, opts->rtol, s);
+        } else {
+          gnk::copy(n, p->d_z, p->d_r, done, s);
+          gnk::dot_partial(n, p->d_r, p->d_z, p->d_part, done, s);
+          gnk::finalize(p->d_part, nbr, OP_BETA, scal, p->d_hist, opts->rtol, s);
+        }
+        gnk::update_p(n, p->d_p, p->d_z, scal, s);
+      }
+      GN_HIP(hipMemcpyAsync(hs, scal, sizeof(double) * 11, hipMemcpyDeviceToHost, s));
+      GN_HIP(hipStreamSynchronize(s));
+      iters = (int)hs[S_ITER];
+      fin = hs[S_DONE] != 0.0;
+    }
+    const double tsolve = now_s() - tstart;
+    // true residual
+    gnk::spmv_flag(p, p->d_x, p->d_q, nullptr, nullptr, s);
+    gnk::scatter_free(p, b_dev + col * ld, p->d_z, s);
+    gnk::residual_partial(n, p->d_z, p->d_q, p->d_part, s);
+    double bb = hs[S_BB], rr = hs[S_RR];
+    std::vector<double> part(nbr);
+    GN_HIP(hipMemcpyAsync(part.data(), p->d_part, sizeof(double) * nbr, hipMemcpyDeviceToHost, s));
+    std::vector<double> hist((size_t)2 * std::max(iters, 1));
+    if (iters > 0)
+      GN_HIP(hipMemcpyAsync(hist.data(), p->d_hist, sizeof(double) * 2 * iters, hipMemcpyDeviceToHost, s));
+    gnk::gather_free(p, p->d_x, x_dev + col * ld, s);
+    GN_HIP(hipStreamSynchronize(s));
+    double tr = 0.0;
+    for (double v : part) tr += v;
+    bool conv = bb == 0.0 || rr <= hs[S_TOL2];
+    if (hs[S_BREAK] != 0.0) ret = GN_ERR_BREAKDOWN;
+    else if (!conv && ret == GN_OK) ret = GN_WARN_MAXIT;
+    if (reports) {
+      gn_solve_report& R = reports[col];
+      R.iters = iters;
+      R.converged = conv ? 1 : 0;
+      R.rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+      R.true_rel_res = bb > 0 ? std::sqrt(tr / bb) : 0.0;
+      R.t_solve_s = tsolve;
+      // CG-Lanczos tridiagonal: T_ii = 1/a_i + b_{i-1}/a_{i-1}, T_{i,i+1} = sqrt(b_i)/a_i
+      R.cond_est = 1.0;
+      if (iters > 0) {
+        std::vector<double> d(iters), e(std::max(iters - 1, 0));
+        for (int i = 0; i < iters; ++i) {
+          double a = hist[2 * i];
+          d[i] = 1.0 / a + (i > 0 ? hist[2 * (i - 1) + 1] / hist[2 * (i - 1)] : 0.0);
+          if (i + 1 < iters) e[i] = std::sqrt(std::max(hist[2 * i + 1], 0.0)) / a;
+        }
+        double lo, hi;
+        tridiag_extremes(d, e, &lo, &hi);
+        R.cond_est = lo > 0 ? hi / lo : INFINITY;
+      }
+    }
+  }
+  return ret;
+  GN_CATCH
+}
+
+extern "C" void gn_destroy_problem(gn_problem* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  dfree_all(p->owned);
+  delete p;
+}
+
+extern "C" void gn_destroy_precond(gn_precond* pc) {
+  if (!pc) return;
+  (void)hipDeviceSynchronize();
+  dfree_all(pc->owned);
+  delete pc;
+}

@@ -1,0 +1,878 @@
+// GenEO set-up kernels: batched shift-and-invert subspace iteration for the
+// local generalised eigenproblems, coarse basis, coarse matrix by local
+// products, and the dense tiled Cholesky of the coarse matrix.
+//
+// Section 3.2 (eq-geneo) and Section 3.3.2 (eqm:matrixForm): on each
+// subdomain, A_{Omega_j} p = lambda X A_{Omega_j^o} X p, smallest lambda first,
+// ||p||_2 = 1, solved in shift-and-invert mode with a small shift.  With
+// P = A_N + s B and B = X A_O X, the pencil B p = nu P p has nu = 1/(lambda+s);
+// the wanted eigenpairs are the largest nu.  All subdomains iterate in one
+// batched launch per step: V <- P^-1 B V (banded triangular solves with the
+// factor of P), Rayleigh-Ritz on span(P^-1 B V) with the small pencil
+// (Z^T B Z, Z^T P Z) solved by Cholesky + cyclic Jacobi in LDS.
+// Section 3.3.2: Phi_{i(j,k)} = X^(j) p_k^j; Section 3.3.3: A_H entries are
+// the local products Phi_i^T (Atilde_{j(i)} Phi_l), nonzero only for
+// overlapping subdomains.
+#include "gn_internal.h"
+
+namespace {
+
+constexpr int NT = 256;
+
+// ---------------------------------------------------------------------------
+// B V on the Ibar box (matrix-free from element matrices), b columns
+// ---------------------------------------------------------------------------
+struct PouAx {
+  const int* cnt0; const int* cnt1; const int* cnt2;
+  const int* ec0; const int* ec1; const int* ec2;
+};
+
+__device__ inline double xpou(const SubDesc& sd, const PouAx& pa, const uint8_t* dir, int NX, int NY,
+                              int NC, int gi, int gj, int gk, int c) {
+  if (gi < sd.ilo[0] || gi >= sd.ilo[0] + sd.in_[0] || gj < sd.ilo[1] ||
+      gj >= sd.ilo[1] + sd.in_[1] || gk < sd.ilo[2] || gk >= sd.ilo[2] + sd.in_[2])
+    return 0.0;
+  int64_t node = gi + (int64_t)NX * (gj + (int64_t)NY * gk);
+  if (dir[node * NC + c]) return 0.0;
+  return 1.0 / (double)(pa.cnt0[gi] * pa.cnt1[gj] * pa.cnt2[gk]);
+}
+
+template <int NC>
+__global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs, int nex, int ney, int nez,
+                                               const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
+                                               PouAx pa, int b, const double* __restrict__ V,
+                                               double* __restrict__ out) {
+  const SubDesc& sd = subs[blockIdx.y];
+  int r = blockIdx.x * NT + threadIdx.x;
+  int npad = sd.NBB * TILE;
+  if (r >= npad) return;
+  const double* Vb = V + sd.offVB * b;
+  double* Ob = out + sd.offVB * b;
+  if (r >= sd.nB) {
+    for (int col = 0; col < b; ++col) Ob[(int64_t)r * b + col] = 0.0;
+    return;
+  }
+  const int NX = nex + 1, NY = ney + 1;
+  int ln = r / NC, c = r % NC;
+  int g[3];
+  box_global_node(sd.blo, sd.bn, sd.permB, ln, g);
+  double xr = xpou(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
+  for (int col0 = 0; col0 < b; col0 += 8) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (xr != 0.0) {
+      for (int ez = max(g[2] - 1, sd.elo[2]); ez <= min(g[2], sd.ehi[2] - 1); ++ez)
+        for (int ey = max(g[1] - 1, sd.elo[1]); ey <= min(g[1], sd.ehi[1] - 1); ++ey)
+          for (int ex = max(g[0] - 1, sd.elo[0]); ex <= min(g[0], sd.ehi[0] - 1); ++ex) {
+            if (pa.ec0[ex] * pa.ec1[ey] * pa.ec2[ez] < 2) continue;   // not in Omega_j^o
+            int64_t e = ex + (int64_t)nex * (ey + (int64_t)ney * ez);
+            int a1 = (g[0] - ex) + 2 * (g[1] - ey) + 4 * (g[2] - ez);
+            const double* row = Ke + e * (64 * NC * NC) + (int64_t)(a1 * NC + c) * (8 * NC);
+            for (int a2 = 0; a2 < 8; ++a2) {
+              int h0 = ex + (a2 & 1), h1 = ey + ((a2 >> 1) & 1), h2 = ez + ((a2 >> 2) & 1);
+              int ln2 = box_local_node(sd.blo, sd.bn, sd.permB, h0, h1, h2);
+#pragma unroll
+              for (int c2 = 0; c2 < NC; ++c2) {
+                double x2 = xpou(sd, pa, dir, NX, NY, NC, h0, h1, h2, c2);
+                if (x2 == 0.0) continue;
+                double kv = row[a2 * NC + c2] * x2;
+                const double* vr = Vb + (int64_t)(ln2 * NC + c2) * b + col0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                  if (col0 + q < b) acc[q] += kv * vr[q];
+              }
+            }
+          }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (col0 + q < b) Ob[(int64_t)r * b + col0 + q] = xr * acc[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// in-place V <- P^-1 V with the banded factor of P (forward then backward), b columns
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_trsm_pencil(const SubDesc* __restrict__ subs, int b,
+                                                    const double* __restrict__ T, const double* __restrict__ D,
+                                                    double* __restrict__ V) {
+  __shared__ double S[TILE][64 + 1];
+  const SubDesc& sd = subs[blockIdx.x];
+  const int NB = sd.NBB, w = sd.wB;
+  const double* Tb = T + sd.offTB * TILE2;
+  const double* Db = D + sd.offDB * TILE2;
+  double* Vb = V + sd.offVB * b;
+  const int i = threadIdx.x % TILE, cg = threadIdx.x / TILE;
+  const int nq = (b + 7) / 8;
+  // forward
+  for (int K = 0; K < NB; ++K) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = 0; t < w; ++t) {
+      int J = K - w + t;
+      if (J < 0) continue;
+      const double* tile = Tb + ((int64_t)K * (w + 1) + t) * TILE2;
+      const double* yj = Vb + (int64_t)J * TILE * b;
+      for (int c = 0; c < TILE; ++c) {
+        double l = tile[c * TILE + i];
+        for (int q = 0; q < nq; ++q) {
+          int col = cg + 8 * q;
+          if (col < b) acc[q] += l * yj[c * b + col];
+        }
+      }
+    }
+    for (int q = 0; q < nq; ++q) {
+      int col = cg + 8 * q;
+      if (col < b) S[i][col] = Vb[(int64_t)(K * TILE + i) * b + col] - acc[q];
+    }
+    __syncthreads();
+    const double* dk = Db + (int64_t)K * TILE2;
+    for (int q = 0; q < nq; ++q) {
+      int col = cg + 8 * q;
+      if (col >= b) continue;
+      double s = 0.0;
+      for (int c = 0; c < TILE; ++c) s += dk[c * TILE + i] * S[c][col];
+      Vb[(int64_t)(K * TILE + i) * b + col] = s;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // backward
+  for (int K = NB - 1; K >= 0; --K) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int d = 1; d <= w; ++d) {
+      if (K + d >= NB) break;
+      const double* tile = Tb + ((int64_t)(K + d) * (w + 1) + (w - d)) * TILE2;
+      const double* xj = Vb + (int64_t)(K + d) * TILE * b;
+      for (int rr = 0; rr < TILE; ++rr) {
+        double l = tile[i * TILE + rr];   // L(rr, i) of block (K+d, K)
+        for (int q = 0; q < nq; ++q) {
+          int col = cg + 8 * q;
+          if (col < b) acc[q] += l * xj[rr * b + col];
+        }
+      }
+    }
+    for (int q = 0; q < nq; ++q) {
+      int col = cg + 8 * q;
+      if (col < b) S[i][col] = Vb[(int64_t)(K * TILE + i) * b + col] - acc[q];
+    }
+    __syncthreads();
+    const double* dk = Db + (int64_t)K * TILE2;
+    for (int q = 0; q < nq; ++q) {
+      int col = cg + 8 * q;
+      if (col >= b) continue;
+      double s = 0.0;
+      for (int rr = 0; rr < TILE; ++rr) s += dk[i * TILE + rr] * S[rr][col];
+      Vb[(int64_t)(K * TILE + i) * b + col] = s;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gram matrices  GP = Z^T (B V) = Z^T P Z,  GB = Z^T (B Z);  residuals
+// res_k = ||Z_k - nu_k V_k||^2, zz_k = ||Z_k||^2   (one workgroup per subdomain)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, int b,
+                                             const double* __restrict__ Z, const double* __restrict__ BV,
+                                             const double* __restrict__ BZ, const double* __restrict__ V,
+                                             const double* __restrict__ nu, double* __restrict__ GP,
+                                             double* __restrict__ GB, double* __restrict__ res) {
+  constexpr int R = 8;
+  __shared__ double sZ[R][64], sBV[R][64], sBZ[R][64], sV[R][64];
+  const SubDesc& sd = subs[blockIdx.x];
+  const int64_t base = sd.offVB * b;
+  const int n = sd.nB;
+  const int np = b * b;
+  double aP[16], aB[16];
+  for (int q = 0; q < 16; ++q) aP[q] = aB[q] = 0.0;
+  double rs = 0.0, zz = 0.0;
+  const double* nus = nu + (int64_t)blockIdx.x * b;
+  for (int r0 = 0; r0 < n; r0 += R) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * b; e += NT) {
+      int rr = e / b, col = e % b;
+      int row = r0 + rr;
+      bool ok = row < n;
+      int64_t o = base + (int64_t)row * b + col;
+      sZ[rr][col] = ok ? Z[o] : 0.0;
+      sBV[rr][col] = ok ? BV[o] : 0.0;
+      sBZ[rr][col] = ok ? BZ[o] : 0.0;
+      sV[rr][col] = ok ? V[o] : 0.0;
+    }
+    __syncthreads();
+    for (int q = 0; q < 16; ++q) {
+      int pidx = threadIdx.x + q * NT;
+      if (pidx >= np) break;
+      int k = pidx / b, l = pidx % b;
+      double sp = 0.0, sb = 0.0;
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        sp += sZ[rr][k] * sBV[rr][l];
+        sb += sZ[rr][k] * sBZ[rr][l];
+      }
+      aP[q] += sp;
+      aB[q] += sb;
+    }
+    if (threadIdx.x < b) {
+      int k = threadIdx.x;
+      double nk = nus[k];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        double d = sZ[rr][k] - nk * sV[rr][k];
+        rs += d * d;
+        zz += sZ[rr][k] * sZ[rr][k];
+      }
+    }
+  }
+  double* gp = GP + (int64_t)blockIdx.x * np;
+  double* gb = GB + (int64_t)blockIdx.x * np;
+  for (int q = 0; q < 16; ++q) {
+    int pidx = threadIdx.x + q * NT;
+    if (pidx >= np) break;
+    gp[pidx] = aP[q];
+    gb[pidx] = aB[q];
+  }
+  if (threadIdx.x < b) {
+    res[(int64_t)blockIdx.x * 2 * b + threadIdx.x] = rs;
+    res[(int64_t)blockIdx.x * 2 * b + b + threadIdx.x] = zz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small generalised eigenproblem GB y = nu GP y (b <= 64), one workgroup each:
+// diagonal scaling, Cholesky GP = R R^T, C = R^-1 GB R^-T, cyclic Jacobi,
+// y = D R^-T w, sorted by decreasing nu; Y^T GP Y = I.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_small_eig(int b, const double* __restrict__ GP,
+                                                  const double* __restrict__ GB, double* __restrict__ Y,
+                                                  double* __restrict__ nu_out, int* __restrict__ flag) {
+  extern __shared__ double sm[];
+  const int ld = b + 1;
+  double* P = sm;              // b x ld
+  double* C = P + b * ld;      // b x ld
+  double* W = C + b * ld;      // b x ld
+  __shared__ double dsc[64];
+  __shared__ double cs[32], sn[32];
+  __shared__ int pp[32], qq[32];
+  __shared__ int order[64];
+  __shared__ double offn;
+  const double* gp = GP + (int64_t)blockIdx.x * b * b;
+  const double* gb = GB + (int64_t)blockIdx.x * b * b;
+  const int tid = threadIdx.x;
+  if (tid < b) {
+    double d = gp[tid * b + tid];
+    dsc[tid] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < b * b; e += NT) {
+    int k = e / b, l = e % b;
+    double s = dsc[k] * dsc[l];
+    P[k * ld + l] = 0.5 * (gp[k * b + l] + gp[l * b + k]) * s;
+    C[k * ld + l] = 0.5 * (gb[k * b + l] + gb[l * b + k]) * s;
+  }
+  __syncthreads();
+  // Cholesky of P (lower, in place)
+  for (int k = 0; k < b; ++k) {
+    if (tid == 0) {
+      double d = P[k * ld + k];
+      if (!(d > 1e-26)) {
+        if (flag) atomicOr(flag + blockIdx.x, 1);
+        d = 1e-26;
+      }
+      P[k * ld + k] = sqrt(d);
+    }
+    __syncthreads();
+    double piv = P[k * ld + k];
+    if (tid > k && tid < b) P[tid * ld + k] /= piv;
+    __syncthreads();
+    for (int e = tid; e < b * b; e += NT) {
+      int rr = e / b, cc = e % b;
+      if (cc > k && rr >= cc) P[rr * ld + cc] -= P[rr * ld + k] * P[cc * ld + k];
+    }
+    __syncthreads();
+  }
+  // W = R^-1 (lower triangular inverse), column per thread
+  if (tid < b) {
+    int cc = tid;
+    for (int rr = 0; rr < b; ++rr) W[rr * ld + cc] = 0.0;
+    for (int rr = cc; rr < b; ++rr) {
+      double s = (rr == cc) ? 1.0 : 0.0;
+      for (int k = cc; k < rr; ++k) s -= P[rr * ld + k] * W[k * ld + cc];
+      W[rr * ld + cc] = s / P[rr * ld + rr];
+    }
+  }
+  __syncthreads();
+  // C <- W C W^T  (use P's strict upper part is no longer needed: reuse P as temp)
+  for (int e = tid; e < b * b; e += NT) {
+    int rr = e / b, cc = e % b;
+    double s = 0.0;
+    for (int k = 0; k <= rr; ++k) s += W[rr * ld + k] * C[k * ld + cc];
+    P[rr * ld + cc] = s;   // T = W C
+  }
+  __syncthreads();
+  for (int e = tid; e < b * b; e += NT) {
+    int rr = e / b, cc = e % b;
+    double s = 0.0;
+    for (int k = 0; k <= cc; ++k) s += P[rr * ld + k] * W[cc * ld + k];
+    C[rr * ld + cc] = s;   // T W^T
+  }
+  __syncthreads();
+  for (int e = tid; e < b * b; e += NT) {
+    int rr = e / b, cc = e % b;
+    if (rr < cc) {
+      double s = 0.5 * (C[rr * ld + cc] + C[cc * ld + rr]);
+      C[rr * ld + cc] = s;
+      C[cc * ld + rr] = s;
+    }
+  }
+  // keep W = R^-1 for the back transform in P (copy), eigenvector accumulator in W
+  __syncthreads();
+  for (int e = tid; e < b * b; e += NT) {
+    int rr = e / b, cc = e % b;
+    P[rr * ld + cc] = W[rr * ld + cc];
+  }
+  __syncthreads();
+  for (int e = tid; e < b * b; e += NT) {
+    int rr = e / b, cc = e % b;
+    W[rr * ld + cc] = (rr == cc) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // cyclic Jacobi with round-robin pairing (b even: pad logic handles odd b)
+  const int m = (b + 1) & ~1;   // players
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) {
+      double off = 0.0, dn = 0.0;
+      for (int k = 0; k < b; ++k)
+        for (int l = 0; l < b; ++l) {
+          double v = C[k * ld + l] * C[k * ld + l];
+          if (k == l) dn += v; else off += v;
+        }
+      offn = (off <= 1e-32 * dn) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (offn != 0.0) break;
+    for (int round = 0; round < m - 1; ++round) {
+      if (tid < m / 2) {
+        // circle method: player m-1 fixed, others rotate
+        int a = (tid == 0) ? m - 1 : (round + tid) % (m - 1);
+        int c2 = (round + m - 1 - tid) % (m - 1);
+        if (tid == 0) c2 = round % (m - 1);
+        int p = min(a, c2), q = max(a, c2);
+        pp[tid] = p;
+        qq[tid] = q;
+        double c = 1.0, s = 0.0;
+        if (q < b && p != q) {
+          double apq = C[p * ld + q];
+          if (apq != 0.0) {
+            double app = C[p * ld + p], aqq = C[q * ld + q];
+            double theta = (aqq - app) / (2.0 * apq);
+            double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+        }
+        cs[tid] = c;
+        sn[tid] = s;
+      }
+      __syncthreads();
+      // rows: C <- J^T C
+      for (int e = tid; e < (m / 2) * b; e += NT) {
+        int pr = e / b, col = e % b;
+        int p = pp[pr], q = qq[pr];
+        if (q >= b || p == q) continue;
+        double c = cs[pr], s = sn[pr];
+        double xp = C[p * ld + col], xq = C[q * ld + col];
+        C[p * ld + col] = c * xp - s * xq;
+        C[q * ld + col] = s * xp + c * xq;
+      }
+      __syncthreads();
+      // columns: C <- C J, W <- W J
+      for (int e = tid; e < (m / 2) * b; e += NT) {
+        int pr = e / b, row = e % b;
+        int p = pp[pr], q = qq[pr];
+        if (q >= b || p == q) continue;
+        double c = cs[pr], s = sn[pr];
+        double xp = C[row * ld + p], xq = C[row * ld + q];
+        C[row * ld + p] = c * xp - s * xq;
+        C[row * ld + q] = s * xp + c * xq;
+        double wp = W[row * ld + p], wq = W[row * ld + q];
+        W[row * ld + p] = c * wp - s * wq;
+        W[row * ld + q] = s * wp + c * wq;
+      }
+      __syncthreads();
+    }
+  }
+  // sort by decreasing eigenvalue (rank sort, ties by index)
+  if (tid < b) {
+    double v = C[tid * ld + tid];
+    int rank = 0;
+    for (int k = 0; k < b; ++k) {
+      double u = C[k * ld + k];
+      if (u > v || (u == v && k < tid)) ++rank;
+    }
+    order[rank] = tid;
+  }
+  __syncthreads();
+  // Y(:, k) = D R^-T w_{order[k]}
+  double* Yb = Y + (int64_t)blockIdx.x * b * b;
+  for (int e = tid; e < b * b; e += NT) {
+    int rr = e / b, k = e % b;
+    int src = order[k];
+    double s = 0.0;
+    for (int l = rr; l < b; ++l) s += P[l * ld + rr] * W[l * ld + src];   // (R^-T)(rr,l) = R^-1(l,rr)
+    Yb[rr * b + k] = dsc[rr] * s;
+  }
+  if (tid < b) nu_out[(int64_t)blockIdx.x * b + tid] = C[order[tid] * ld + order[tid]];
+}
+
+// V = Z Y  (rows of one subdomain per grid.y; Y in LDS)
+__global__ __launch_bounds__(NT) void k_vupdate(const SubDesc* __restrict__ subs, int b,
+                                                const double* __restrict__ Z, const double* __restrict__ Y,
+                                                double* __restrict__ V) {
+  __shared__ double sY[64 * 64];
+  const SubDesc& sd = subs[blockIdx.y];
+  const double* Yb = Y + (int64_t)blockIdx.y * b * b;
+  for (int e = threadIdx.x; e < b * b; e += NT) sY[e] = Yb[e];
+  __syncthreads();
+  int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= sd.NBB * TILE) return;
+  const double* zr = Z + sd.offVB * b + (int64_t)r * b;
+  double* vr = V + sd.offVB * b + (int64_t)r * b;
+  double zl[64];
+  for (int k = 0; k < b; ++k) zl[k] = zr[k];
+  for (int l = 0; l < b; ++l) {
+    double s = 0.0;
+    for (int k = 0; k < b; ++k) s += zl[k] * sY[k * b + l];
+    vr[l] = s;
+  }
+}
+
+// deterministic start block: hash of (subdomain, row, col) -> (-1, 1); zero on padding
+__global__ void k_vinit(const SubDesc* __restrict__ subs, int b, double* __restrict__ V) {
+  const SubDesc& sd = subs[blockIdx.y];
+  int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= sd.NBB * TILE) return;
+  for (int col = 0; col < b; ++col) {
+    uint64_t h = ((uint64_t)blockIdx.y * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)r * 0xBF58476D1CE4E5B9ull) ^
+                 ((uint64_t)col * 0x94D049BB133111EBull);
+    h ^= h >> 31;
+    h *= 0xD6E8FEB86659FD93ull;
+    h ^= h >> 32;
+    double u = (double)(h >> 11) * (1.0 / 9007199254740992.0);
+    V[sd.offVB * b + (int64_t)r * b + col] = (r < sd.nB) ? 2.0 * u - 1.0 : 0.0;
+  }
+}
+
+// unit 2-norm, largest-magnitude entry positive (lowest index on ties), first ncol columns
+__global__ __launch_bounds__(NT) void k_normalise(const SubDesc* __restrict__ subs, int b, int ncol,
+                                                  double* __restrict__ V) {
+  __shared__ double sh[16];
+  __shared__ double bestv[NT];
+  __shared__ int besti[NT];
+  const SubDesc& sd = subs[blockIdx.x];
+  double* Vb = V + sd.offVB * b;
+  for (int k = 0; k < ncol; ++k) {
+    double s = 0.0, mv = -1.0;
+    int mi = 0x7fffffff;
+    for (int r = threadIdx.x; r < sd.nB; r += NT) {
+      double v = Vb[(int64_t)r * b + k];
+      s += v * v;
+      double a = fabs(v);
+      if (a > mv) { mv = a; mi = r; }
+    }
+    double nrm2 = block_sum(s, sh);
+    bestv[threadIdx.x] = mv;
+    besti[threadIdx.x] = mi;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) {
+        double a = bestv[threadIdx.x + off];
+        int ai = besti[threadIdx.x + off];
+        if (a > bestv[threadIdx.x] || (a == bestv[threadIdx.x] && ai < besti[threadIdx.x])) {
+          bestv[threadIdx.x] = a;
+          besti[threadIdx.x] = ai;
+        }
+      }
+      __syncthreads();
+    }
+    double sg = Vb[(int64_t)besti[0] * b + k] < 0.0 ? -1.0 : 1.0;
+    double scale = sg / sqrt(nrm2);
+    __syncthreads();
+    for (int r = threadIdx.x; r < sd.nB; r += NT) Vb[(int64_t)r * b + k] *= scale;
+    __syncthreads();
+  }
+}
+
+// Phi_j (I-box rows x m_j, row-major) = X p on the I box
+template <int NC>
+__global__ __launch_bounds__(NT) void k_build_phi(const SubDesc* __restrict__ subs, int NX, int NY,
+                                                  const uint8_t* __restrict__ dir, PouAx pa, int b,
+                                                  const double* __restrict__ V, double* __restrict__ Phi) {
+  const SubDesc& sd = subs[blockIdx.y];
+  int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= sd.nI || sd.m == 0) return;
+  int g[3];
+  box_global_node(sd.ilo, sd.in_, sd.permI, r / NC, g);
+  int c = r % NC;
+  double x = xpou(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
+  int rb = box_local_node(sd.blo, sd.bn, sd.permB, g[0], g[1], g[2]) * NC + c;
+  const double* vr = V + sd.offVB * b + (int64_t)rb * b;
+  double* out = Phi + sd.offPhi + (int64_t)r * sd.m;
+  for (int k = 0; k < sd.m; ++k) out[k] = x * vr[k];
+}
+
+// Y_j = A Phi_j on the Ibar box (nB rows x m_j, row-major, stride b)
+template <int NC>
+__global__ __launch_bounds__(NT) void k_aphi(const SubDesc* __restrict__ subs, int NX, int NY, int NZ,
+                                             const double* __restrict__ A, const double* __restrict__ Phi,
+                                             int b, double* __restrict__ Y) {
+  const SubDesc& sd = subs[blockIdx.y];
+  int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= sd.nB || sd.m == 0) return;
+  const int64_t n_node = (int64_t)NX * NY * NZ;
+  int g[3];
+  box_global_node(sd.blo, sd.bn, sd.permB, r / NC, g);
+  int c = r % NC;
+  int64_t node = g[0] + (int64_t)NX * (g[1] + (int64_t)NY * g[2]);
+  double* yr = Y + sd.offVB * b + (int64_t)r * b;
+  for (int k0 = 0; k0 < sd.m; k0 += 8) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int d = 0; d < 27; ++d) {
+      int h[3] = {g[0] + d % 3 - 1, g[1] + (d / 3) % 3 - 1, g[2] + d / 9 - 1};
+      bool in = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) in &= (h[a] >= sd.ilo[a] && h[a] < sd.ilo[a] + sd.in_[a]);
+      if (!in) continue;
+      int ln2 = box_local_node(sd.ilo, sd.in_, sd.permI, h[0], h[1], h[2]);
+#pragma unroll
+      for (int c2 = 0; c2 < NC; ++c2) {
+        double av = A[((int64_t)(d * NC + c) * NC + c2) * n_node + node];
+        const double* ph = Phi + sd.offPhi + (int64_t)(ln2 * NC + c2) * sd.m + k0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + q < sd.m) acc[q] += av * ph[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (k0 + q < sd.m) yr[k0 + q] = acc[q];
+  }
+}
+
+// A_H block (j1, j2): sum over nodes of I_j1 cap Ibar_j2 of Phi_j1^T Y_j2, written
+// into dense tiles (tile (K,J) column-major at (K*NBH + J)*TILE2)
+struct Pair { int j1, j2; int lo[3], hi[3]; };
+
+template <int NC>
+__global__ __launch_bounds__(NT) void k_ah_pairs(const SubDesc* __restrict__ subs, const Pair* __restrict__ pairs,
+                                                 const double* __restrict__ Phi, int b,
+                                                 const double* __restrict__ Y, int NBH,
+                                                 double* __restrict__ AH) {
+  const Pair pr = pairs[blockIdx.x];
+  const SubDesc& s1 = subs[pr.j1];
+  const SubDesc& s2 = subs[pr.j2];
+  const int m1 = s1.m, m2 = s2.m;
+  if (m1 == 0 || m2 == 0) return;
+  int n0 = pr.hi[0] - pr.lo[0], n1 = pr.hi[1] - pr.lo[1], n2 = pr.hi[2] - pr.lo[2];
+  int nnodes = n0 * n1 * n2;
+  for (int pidx = threadIdx.x; pidx < m1 * m2; pidx += NT) {
+    int k = pidx / m2, l = pidx % m2;
+    double s = 0.0;
+    for (int t = 0; t < nnodes; ++t) {
+      int gi = pr.lo[0] + t % n0, gj = pr.lo[1] + (t / n0) % n1, gk = pr.lo[2] + t / (n0 * n1);
+      int l1 = box_local_node(s1.ilo, s1.in_, s1.permI, gi, gj, gk);
+      int l2 = box_local_node(s2.blo, s2.bn, s2.permB, gi, gj, gk);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        s += Phi[s1.offPhi + (int64_t)(l1 * NC + c) * m1 + k] * Y[s2.offVB * b + (int64_t)(l2 * NC + c) * b + l];
+    }
+    int row = s1.coff + k, col = s2.coff + l;
+    AH[((int64_t)(row / TILE) * NBH + col / TILE) * TILE2 + (col % TILE) * TILE + row % TILE] = s;
+  }
+}
+
+// symmetrise the dense tiled A_H, identity on padding rows
+__global__ void k_ah_sym(int NH, int NBH, double* __restrict__ AH) {
+  int64_t n = (int64_t)NBH * TILE;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  int64_t row = t / n, col = t % n;
+  if (col > row) return;
+  auto at = [&](int64_t r, int64_t c) -> double& {
+    return AH[((r / TILE) * NBH + c / TILE) * TILE2 + (c % TILE) * TILE + r % TILE];
+  };
+  if (row >= NH || col >= NH) {
+    double v = (row == col) ? 1.0 : 0.0;
+    at(row, col) = v;
+    at(col, row) = v;
+    return;
+  }
+  double v = 0.5 * (at(row, col) + at(col, row));
+  at(row, col) = v;
+  at(col, row) = v;
+}
+
+// ---------------------------------------------------------------------------
+// dense tiled Cholesky (right-looking) of the coarse matrix and Z = L^-1
+// tiles: (K,J) at (K*NB + J)*TILE2, column-major inside a tile
+// ---------------------------------------------------------------------------
+__device__ inline void lds_tile(double* dst, const double* src) {
+  for (int t = threadIdx.x; t < TILE2; t += NT) {
+    int col = t / TILE, row = t % TILE;
+    dst[col * (TILE + 1) + row] = src[t];
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_potrf_tile(int NB, int K, double* __restrict__ A,
+                                                   double* __restrict__ Dinv, int* __restrict__ info) {
+  __shared__ double S[TILE * (TILE + 1)];
+  double* tk = A + ((int64_t)K * NB + K) * TILE2;
+  lds_tile(S, tk);
+  __syncthreads();
+  for (int k = 0; k < TILE; ++k) {
+    if (threadIdx.x == 0) {
+      double d = S[k * (TILE + 1) + k];
+      if (!(d > 0.0)) {
+        if (*info == 0) *info = K * TILE + k + 1;
+        d = 1.0;
+      }
+      S[k * (TILE + 1) + k] = sqrt(d);
+    }
+    __syncthreads();
+    double piv = S[k * (TILE + 1) + k];
+    if (threadIdx.x > k && threadIdx.x < TILE) S[k * (TILE + 1) + threadIdx.x] /= piv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < TILE2; e += NT) {
+      int rr = e % TILE, cc = e / TILE;
+      if (cc > k && rr >= cc) S[cc * (TILE + 1) + rr] -= S[k * (TILE + 1) + rr] * S[k * (TILE + 1) + cc];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < TILE2; e += NT) {
+    int rr = e % TILE, cc = e / TILE;
+    tk[cc * TILE + rr] = (rr >= cc) ? S[cc * (TILE + 1) + rr] : 0.0;
+  }
+  if (threadIdx.x < TILE) {
+    int cc = threadIdx.x;
+    double* dk = Dinv + (int64_t)K * TILE2;
+    for (int r2 = 0; r2 < cc; ++r2) dk[cc * TILE + r2] = 0.0;
+    for (int r2 = cc; r2 < TILE; ++r2) {
+      double s = (r2 == cc) ? 1.0 : 0.0;
+      for (int k = cc; k < r2; ++k) s -= S[k * (TILE + 1) + r2] * dk[cc * TILE + k];
+      dk[cc * TILE + r2] = s / S[r2 * (TILE + 1) + r2];
+    }
+  }
+}
+
+// L(I,K) = A(I,K) Dinv_K^T for I = K+1+blockIdx.x
+__global__ __launch_bounds__(NT) void k_trsm_tile(int NB, int K, double* __restrict__ A,
+                                                  const double* __restrict__ Dinv) {
+  __shared__ double X[TILE * (TILE + 1)], Dk[TILE * (TILE + 1)];
+  int I = K + 1 + blockIdx.x;
+  double* t = A + ((int64_t)I * NB + K) * TILE2;
+  lds_tile(X, t);
+  lds_tile(Dk, Dinv + (int64_t)K * TILE2);
+  __syncthreads();
+  const int i = threadIdx.x % TILE, c0 = threadIdx.x / TILE;
+  for (int q = 0; q < 4; ++q) {
+    int c = c0 + 8 * q;
+    double s = 0.0;
+    for (int k = 0; k < TILE; ++k) s += X[k * (TILE + 1) + i] * Dk[k * (TILE + 1) + c];
+    t[c * TILE + i] = s;
+  }
+}
+
+// A(I,J) -= L(I,K) L(J,K)^T for K < J <= I (blockIdx.x enumerates the pairs)
+__global__ __launch_bounds__(NT) void k_syrk_tile(int NB, int K, double* __restrict__ A) {
+  __shared__ double X[TILE * (TILE + 1)], Yt[TILE * (TILE + 1)];
+  int m = NB - K - 1;
+  int idx = blockIdx.x;
+  // row-major enumeration of the lower triangle of an m x m block matrix
+  int I0 = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+  while ((I0 + 1) * (I0 + 2) / 2 <= idx) ++I0;
+  while (I0 * (I0 + 1) / 2 > idx) --I0;
+  int J0 = idx - I0 * (I0 + 1) / 2;
+  if (I0 >= m) return;
+  int I = K + 1 + I0, J = K + 1 + J0;
+  lds_tile(X, A + ((int64_t)I * NB + K) * TILE2);
+  lds_tile(Yt, A + ((int64_t)J * NB + K) * TILE2);
+  __syncthreads();
+  double* t = A + ((int64_t)I * NB + J) * TILE2;
+  const int i = threadIdx.x % TILE, c0 = threadIdx.x / TILE;
+  for (int q = 0; q < 4; ++q) {
+    int c = c0 + 8 * q;
+    double s = 0.0;
+    for (int k = 0; k < TILE; ++k) s += X[k * (TILE + 1) + i] * Yt[k * (TILE + 1) + c];
+    t[c * TILE + i] -= s;
+  }
+}
+
+// Z(:, J) = L^-1 E_J for block column J = blockIdx.x (forward substitution by tiles)
+__global__ __launch_bounds__(NT) void k_tri_inv(int NB, const double* __restrict__ L,
+                                                const double* __restrict__ Dinv, double* __restrict__ Z) {
+  __shared__ double X[TILE * (TILE + 1)], Yt[TILE * (TILE + 1)], S[TILE * (TILE + 1)];
+  const int J = blockIdx.x;
+  const int i = threadIdx.x % TILE, c0 = threadIdx.x / TILE;
+  for (int I = 0; I < NB; ++I) {
+    double* zt = Z + ((int64_t)I * NB + J) * TILE2;
+    if (I < J) {
+      for (int e = threadIdx.x; e < TILE2; e += NT) zt[e] = 0.0;
+      continue;
+    }
+    double acc[4];
+    for (int q = 0; q < 4; ++q) acc[q] = (I == J && i == c0 + 8 * q) ? 1.0 : 0.0;
+    for (int K = J; K < I; ++K) {
+      __syncthreads();
+      lds_tile(X, L + ((int64_t)I * NB + K) * TILE2);   // L(I,K)
+      lds_tile(Yt, Z + ((int64_t)K * NB + J) * TILE2);  // Z(K,J)
+      __syncthreads();
+      for (int q = 0; q < 4; ++q) {
+        int c = c0 + 8 * q;
+        double s = 0.0;
+        for (int k = 0; k < TILE; ++k) s += X[k * (TILE + 1) + i] * Yt[c * (TILE + 1) + k];
+        acc[q] -= s;
+      }
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) S[(c0 + 8 * q) * (TILE + 1) + i] = acc[q];
+    lds_tile(X, Dinv + (int64_t)I * TILE2);
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      int c = c0 + 8 * q;
+      double s = 0.0;
+      for (int k = 0; k < TILE; ++k) s += X[k * (TILE + 1) + i] * S[c * (TILE + 1) + k];
+      zt[c * TILE + i] = s;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+namespace gnk {
+
+static PouAx pou_axes(const gn_precond* pc) {
+  return PouAx{pc->d_cnt[0], pc->d_cnt[1], pc->d_cnt[2], pc->d_ecnt[0], pc->d_ecnt[1], pc->d_ecnt[2]};
+}
+
+void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s) {
+  hipLaunchKernelGGL(k_vinit, dim3((maxNBB * TILE + NT - 1) / NT, pc->n_sub), dim3(NT), 0, s,
+                     pc->d_sub, b, V);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_bapply(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, const double* V,
+                double* out, hipStream_t s) {
+  dim3 grid((maxNBB * TILE + NT - 1) / NT, pc->n_sub);
+  if (p->nc == 3)
+    hipLaunchKernelGGL(k_bapply<3>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->ne[2],
+                       p->d_Ke, p->d_dir, pou_axes(pc), b, V, out);
+  else
+    hipLaunchKernelGGL(k_bapply<1>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->ne[2],
+                       p->d_Ke, p->d_dir, pou_axes(pc), b, V, out);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, double* V, hipStream_t s) {
+  hipLaunchKernelGGL(k_trsm_pencil, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, T, D, V);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, const double* BZ,
+              const double* V, const double* nu, double* GP, double* GB, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, Z, BV, BZ, V, nu, GP, GB,
+                     res);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_small(int n_sub, int b, const double* GP, const double* GB, double* Y, double* nu, int* flag,
+               hipStream_t s) {
+  size_t lds = sizeof(double) * 3 * b * (b + 1);
+  GN_HIP(hipFuncSetAttribute((const void*)k_small_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  hipLaunchKernelGGL(k_small_eig, dim3(n_sub), dim3(NT), lds, s, b, GP, GB, Y, nu, flag);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const double* Y, double* V,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_vupdate, dim3((maxNBB * TILE + NT - 1) / NT, pc->n_sub), dim3(NT), 0, s,
+                     pc->d_sub, b, Z, Y, V);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_normalise(const gn_precond* pc, int b, int ncol, double* V, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalise, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, ncol, V);
+  GN_CHECK_LAUNCH();
+}
+
+void build_phi(const gn_problem* p, const gn_precond* pc, int b, int maxNI, const double* V,
+               hipStream_t s) {
+  dim3 grid((maxNI + NT - 1) / NT, pc->n_sub);
+  if (p->nc == 3)
+    hipLaunchKernelGGL(k_build_phi<3>, grid, dim3(NT), 0, s, pc->d_sub, p->nn[0], p->nn[1], p->d_dir,
+                       pou_axes(pc), b, V, pc->d_Phi);
+  else
+    hipLaunchKernelGGL(k_build_phi<1>, grid, dim3(NT), 0, s, pc->d_sub, p->nn[0], p->nn[1], p->d_dir,
+                       pou_axes(pc), b, V, pc->d_Phi);
+  GN_CHECK_LAUNCH();
+}
+
+void aphi(const gn_problem* p, const gn_precond* pc, int b, int maxNB, double* Y, hipStream_t s) {
+  dim3 grid((maxNB + NT - 1) / NT, pc->n_sub);
+  if (p->nc == 3)
+    hipLaunchKernelGGL(k_aphi<3>, grid, dim3(NT), 0, s, pc->d_sub, p->nn[0], p->nn[1], p->nn[2],
+                       p->d_A, pc->d_Phi, b, Y);
+  else
+    hipLaunchKernelGGL(k_aphi<1>, grid, dim3(NT), 0, s, pc->d_sub, p->nn[0], p->nn[1], p->nn[2],
+                       p->d_A, pc->d_Phi, b, Y);
+  GN_CHECK_LAUNCH();
+}
+
+void ah_pairs(const gn_problem* p, const gn_precond* pc, const void* d_pairs, int npairs, int b,
+              const double* Y, double* AH, hipStream_t s) {
+  if (p->nc == 3)
+    hipLaunchKernelGGL(k_ah_pairs<3>, dim3(npairs), dim3(NT), 0, s, pc->d_sub, (const Pair*)d_pairs,
+                       pc->d_Phi, b, Y, pc->NBH, AH);
+  else
+    hipLaunchKernelGGL(k_ah_pairs<1>, dim3(npairs), dim3(NT), 0, s, pc->d_sub, (const Pair*)d_pairs,
+                       pc->d_Phi, b, Y, pc->NBH, AH);
+  GN_CHECK_LAUNCH();
+  int64_t n = (int64_t)pc->NBH * TILE;
+  hipLaunchKernelGGL(k_ah_sym, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, pc->NH,
+                     pc->NBH, AH);
+  GN_CHECK_LAUNCH();
+}
+
+int pair_size() { return (int)sizeof(Pair); }
+void make_pair(void* dst, int j1, int j2, const int lo[3], const int hi[3]) {
+  Pair* p = (Pair*)dst;
+  p->j1 = j1;
+  p->j2 = j2;
+  for (int a = 0; a < 3; ++a) {
+    p->lo[a] = lo[a];
+    p->hi[a] = hi[a];
+  }
+}
+
+void dense_chol(int NB, double* A, double* Dinv, int* info, hipStream_t s) {
+  for (int K = 0; K < NB; ++K) {
+    hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(NT), 0, s, NB, K, A, Dinv, info);
+    GN_CHECK_LAUNCH();
+    int m = NB - K - 1;
+    if (m > 0) {
+      hipLaunchKernelGGL(k_trsm_tile, dim3(m), dim3(NT), 0, s, NB, K, A, Dinv);
+      GN_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_syrk_tile, dim3(m * (m + 1) / 2), dim3(NT), 0, s, NB, K, A);
+      GN_CHECK_LAUNCH();
+    }
+  }
+}
+
+void tri_inv(int NB, const double* L, const double* Dinv, double* Z, hipStream_t s) {
+  hipLaunchKernelGGL(k_tri_inv, dim3(NB), dim3(NT), 0, s, NB, L, Dinv, Z);
+  GN_CHECK_LAUNCH();
+}
+
+}  // namespace gnk

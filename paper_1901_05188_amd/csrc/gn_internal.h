@@ -1,0 +1,229 @@
+// Internal declarations shared by the HIP translation units of libgenpcg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "genpcg.h"
+
+// Band tiles are TILE x TILE, column-major inside a tile.
+#define TILE 32
+#define TILE2 (TILE * TILE)
+
+// ---------------------------------------------------------------------------
+// error handling
+// ---------------------------------------------------------------------------
+struct gn_error {
+  gn_status code;
+  std::string msg;
+};
+void gn_set_error(gn_status code, const std::string& msg);
+
+#define GN_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw gn_error{e_ == hipErrorOutOfMemory ? GN_ERR_OOM : GN_ERR_DEVICE,          \
+                     std::string(#call) + ": " + hipGetErrorString(e_)};              \
+  } while (0)
+
+#define GN_CHECK_LAUNCH() GN_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// per-subdomain description (plain data, mirrored on the device)
+// ---------------------------------------------------------------------------
+struct SubDesc {
+  int elo[3], ehi[3];   // element box of Omega_j: [elo, ehi)
+  int ilo[3], in_[3];   // node box of V_h0(Omega_j) (local Dirichlet system): first node, count
+  int blo[3], bn[3];    // node box of V_h(Omega_j) (pencil): first node, count
+  int permI[3];         // axis order of the local numbering on the I box (perm[0] fastest)
+  int permB[3];         // axis order on the Ibar box
+  int nI, nB;           // DOFs of the boxes (nodes * ncomp)
+  int NBI, wI;          // tile rows and band width in tiles, local system
+  int NBB, wB;          // same for the pencil
+  int64_t offTI, offTB; // offsets (in tiles) into the band storage
+  int64_t offDI, offDB; // offsets (in tiles) into the inverse-diagonal storage
+  int64_t offVI, offVB; // offsets (in doubles) into per-subdomain vector storage (padded)
+  int m;                // number of coarse vectors
+  int coff;             // first coarse index i(j, 0)
+  int64_t offPhi;       // offset (doubles) of Phi_j (NBI*TILE rows x m, row-major)
+};
+
+// local DOF index <-> global node on a box with an axis permutation
+__host__ __device__ inline int box_local_node(const int lo[3], const int n[3], const int perm[3],
+                                              int gi, int gj, int gk) {
+  int g[3] = {gi - lo[0], gj - lo[1], gk - lo[2]};
+  return g[perm[0]] + n[perm[0]] * (g[perm[1]] + n[perm[1]] * g[perm[2]]);
+}
+__host__ __device__ inline void box_global_node(const int lo[3], const int n[3], const int perm[3],
+                                                int local, int* gijk) {
+  int u0 = local % n[perm[0]];
+  int t = local / n[perm[0]];
+  int u1 = t % n[perm[1]];
+  int u2 = t / n[perm[1]];
+  int g[3];
+  g[perm[0]] = u0;
+  g[perm[1]] = u1;
+  g[perm[2]] = u2;
+  gijk[0] = g[0] + lo[0];
+  gijk[1] = g[1] + lo[1];
+  gijk[2] = g[2] + lo[2];
+}
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct gn_problem {
+  int pde = 0, nc = 1;
+  int ne[3] = {0, 0, 0}, nn[3] = {0, 0, 0};
+  int64_t n_node = 0, n_elem = 0, n_dof = 0, n_free = 0;
+  int nrhs = 1;
+  int map_kind = 0;
+  double map_par[3] = {0, 0, 0};
+  double* d_xn[3] = {nullptr, nullptr, nullptr};
+  double* d_Ke = nullptr;      // element matrices, n_elem x nd x nd (row-major)
+  double* d_A = nullptr;       // node-block matrix, [27][nc][nc][n_node]
+  double* d_b = nullptr;       // load, full numbering, n_dof x nrhs
+  uint8_t* d_dir = nullptr;    // Dirichlet mask, full numbering
+  int* d_free2full = nullptr;  // n_free
+  // CG workspace (full numbering)
+  double *d_x = nullptr, *d_r = nullptr, *d_p = nullptr, *d_q = nullptr, *d_z = nullptr;
+  double* d_part = nullptr;    // block partial sums
+  double* d_scal = nullptr;    // device scalars
+  double* d_hist = nullptr;    // alpha/beta history
+  int hist_cap = 0;
+  std::vector<void*> owned;
+};
+
+struct gn_precond {
+  gn_problem* prob = nullptr;
+  int n_sub = 0, nparts[3] = {1, 1, 1}, overlap = 1;
+  std::vector<int> cuts[3];
+  std::vector<SubDesc> sub;
+  SubDesc* d_sub = nullptr;
+  int local_prec = 64;
+  // per-axis node coverage (PoU counts) and part ranges for the gather-form prolongation
+  int* d_cnt[3] = {nullptr, nullptr, nullptr};   // #parts whose I-range holds node index
+  int* d_plo[3] = {nullptr, nullptr, nullptr};   // first such part
+  int* d_ecnt[3] = {nullptr, nullptr, nullptr};  // #parts whose element range holds element
+  // local factors
+  double* d_LI = nullptr;    // band tiles (FP64) or nullptr
+  float* d_LIf = nullptr;    // band tiles (FP32) or nullptr
+  double* d_DI = nullptr;    // inverse diagonal tiles (FP64)
+  float* d_DIf = nullptr;
+  double* d_t = nullptr;     // local vectors (sum of NBI*TILE)
+  int64_t tilesI = 0, vecI = 0;
+  // coarse
+  int NH = 0;
+  double* d_Phi = nullptr;   // concatenated Phi_j
+  int64_t phi_len = 0;
+  double* d_g = nullptr;     // coarse vectors (NH padded)
+  double* d_u = nullptr;
+  double* d_y = nullptr;
+  int maxNBI = 0;
+  double trsv_bytes = 0.0, prolong_bytes = 0.0;
+  double* d_Z = nullptr;     // L_H^-1 as dense tiles (NBH x NBH tiles, lower)
+  int NBH = 0;
+  std::vector<double> lam;   // eigenvalues per subdomain (n_eval each)
+  std::vector<int> lam_n;
+  int n_eval = 0;
+  std::vector<void*> owned;
+};
+
+// ---------------------------------------------------------------------------
+// launch helpers implemented in the kernel translation units
+// ---------------------------------------------------------------------------
+namespace gnk {
+// fem.hip
+void element_matrices(gn_problem* p, const double* d_mats, int n_mat, const int* d_emat,
+                      const double* d_eang, const double* d_etilt, const double* d_ek,
+                      hipStream_t s);
+void assemble_matrix(gn_problem* p, hipStream_t s);
+void assemble_load(gn_problem* p, const double* d_body, const double* d_trac, hipStream_t s);
+// linalg.hip
+void spmv_flag(const gn_problem* p, const double* x, double* y, double* part, const double* done,
+               hipStream_t s);
+int spmv_blocks(const gn_problem* p);
+void scatter_free(const gn_problem* p, const double* xf, double* xfull, hipStream_t s);
+void gather_free(const gn_problem* p, const double* xfull, double* xf, hipStream_t s);
+int reduce_blocks();
+int scal_count();
+void dot_partial(int64_t n, const double* a, const double* b, double* part, const double* done,
+                 hipStream_t s);
+void finalize(const double* part, int nb, int op, double* scal, double* hist, double rtol, hipStream_t s);
+void update_xr(int64_t n, double* x, double* r, const double* p, const double* q, const double* scal,
+               double* part, hipStream_t s);
+void update_p(int64_t n, double* p, const double* z, const double* scal, hipStream_t s);
+void copy(int64_t n, double* dst, const double* src, const double* done, hipStream_t s);
+void residual_partial(int64_t n, const double* b, const double* q, double* part, hipStream_t s);
+// band.hip
+void extract_local(const gn_problem* p, const gn_precond* pc, double* L, int maxNB, hipStream_t s);
+void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, double* L, int maxNB,
+                    hipStream_t s);
+void band_chol(const void* d_refs, int n, double* T, double* D, int* info, hipStream_t s);
+void to_f32(int64_t n, const double* a, float* b, hipStream_t s);
+// precond.hip
+void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, const double* done,
+                 hipStream_t s);
+void coarse_solve(const gn_precond* pc, const double* done, hipStream_t s);
+int prolong_blocks(const gn_problem* p);
+void prolong(const gn_problem* p, const gn_precond* pc, const double* r, double* z, double* part,
+             const double* done, hipStream_t s);
+// geneo.hip
+void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s);
+void eig_bapply(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, const double* V,
+                double* out, hipStream_t s);
+void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, double* V, hipStream_t s);
+void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, const double* BZ,
+              const double* V, const double* nu, double* GP, double* GB, double* res, hipStream_t s);
+void eig_small(int n_sub, int b, const double* GP, const double* GB, double* Y, double* nu, int* flag,
+               hipStream_t s);
+void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const double* Y, double* V,
+                 hipStream_t s);
+void eig_normalise(const gn_precond* pc, int b, int ncol, double* V, hipStream_t s);
+void build_phi(const gn_problem* p, const gn_precond* pc, int b, int maxNI, const double* V,
+               hipStream_t s);
+void aphi(const gn_problem* p, const gn_precond* pc, int b, int maxNB, double* Y, hipStream_t s);
+void ah_pairs(const gn_problem* p, const gn_precond* pc, const void* d_pairs, int npairs, int b,
+              const double* Y, double* AH, hipStream_t s);
+int pair_size();
+void make_pair(void* dst, int j1, int j2, const int lo[3], const int hi[3]);
+void dense_chol(int NB, double* A, double* Dinv, int* info, hipStream_t s);
+void tri_inv(int NB, const double* L, const double* Dinv, double* Z, hipStream_t s);
+}  // namespace gnk
+
+// profiling of kernel groups (api.hip)
+struct GnProfScope {
+  int group;
+  double bytes;
+  hipStream_t s;
+  hipEvent_t e0, e1;
+  bool on;
+  GnProfScope(int g, double b, hipStream_t st);
+  ~GnProfScope();
+};
+enum { PROF_SPMV = 0, PROF_TRSV, PROF_PROLONG, PROF_COARSE, PROF_VEC, PROF_NGROUP };
+
+// ---------------------------------------------------------------------------
+// device reduction helpers (fixed order: deterministic for a fixed launch shape)
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+// sum over a block of up to 1024 threads; result valid in every thread
+__device__ inline double block_sum(double v, double* sh /* >= 16 doubles */) {
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += sh[i];
+  return t;
+}

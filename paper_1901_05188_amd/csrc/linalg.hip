@@ -1,0 +1,271 @@
+// Sparse matrix-vector product on the 27-point node-block matrix, CG vector
+// updates and deterministic reductions (Section 3.1: the CG iteration).
+//
+// The assembled matrix is stored structure-of-arrays, A[d][c][c'][node], with
+// d the lattice offset (dx,dy,dz) in {-1,0,1}^3; column indices are implicit
+// in the structured grid, so a row moves 27*nc*nc*8 bytes of values only.
+// Dirichlet DOFs are identity rows/columns in the full numbering and hold 0 in
+// every vector, which keeps every kernel free of index maps.
+#include "gn_internal.h"
+
+namespace {
+
+constexpr int RBLK = 512;   // blocks of the fixed-shape vector reductions
+constexpr int RTHR = 256;
+
+template <int NC>
+__global__ __launch_bounds__(256) void k_spmv(int NX, int NY, int NZ, const double* __restrict__ A,
+                                              const double* __restrict__ x, double* __restrict__ y,
+                                              double* __restrict__ part,
+                                              const double* __restrict__ done) {
+  __shared__ double sh[16];
+  if (done && *done != 0.0) return;
+  const int64_t n_node = (int64_t)NX * NY * NZ;
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double dotv = 0.0;
+  if (node < n_node) {
+    int i = (int)(node % NX), j = (int)((node / NX) % NY), k = (int)(node / ((int64_t)NX * NY));
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+      if (k + dz < 0 || k + dz >= NZ) continue;
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        if (j + dy < 0 || j + dy >= NY) continue;
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (i + dx < 0 || i + dx >= NX) continue;
+          const int d = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+          int64_t nb = node + dx + (int64_t)NX * (dy + (int64_t)NY * dz);
+          double xv[NC];
+#pragma unroll
+          for (int c2 = 0; c2 < NC; ++c2) xv[c2] = x[nb * NC + c2];
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int c2 = 0; c2 < NC; ++c2)
+              acc[c] += A[((int64_t)(d * NC + c) * NC + c2) * n_node + node] * xv[c2];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      y[node * NC + c] = acc[c];
+      dotv += acc[c] * x[node * NC + c];
+    }
+  }
+  if (part) {
+    double s = block_sum(dotv, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+  }
+}
+
+__global__ void k_scatter_free(int64_t n_free, const int* __restrict__ f2f, const double* __restrict__ xf,
+                               double* __restrict__ xfull) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_free) xfull[f2f[t]] = xf[t];
+}
+__global__ void k_gather_free(int64_t n_free, const int* __restrict__ f2f, const double* __restrict__ xfull,
+                              double* __restrict__ xf) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_free) xf[t] = xfull[f2f[t]];
+}
+
+}  // namespace
+
+namespace gnk {
+
+int reduce_blocks() { return RBLK; }
+
+void spmv_flag(const gn_problem* p, const double* x, double* y, double* part, const double* done,
+               hipStream_t s) {
+  dim3 grid((unsigned)((p->n_node + 255) / 256));
+  GnProfScope prof(PROF_SPMV, (double)p->n_node * (27.0 * p->nc * p->nc * 8.0 + 2.0 * p->nc * 8.0), s);
+  if (p->nc == 3)
+    hipLaunchKernelGGL(k_spmv<3>, grid, dim3(256), 0, s, p->nn[0], p->nn[1], p->nn[2], p->d_A, x,
+                       y, part, done);
+  else
+    hipLaunchKernelGGL(k_spmv<1>, grid, dim3(256), 0, s, p->nn[0], p->nn[1], p->nn[2], p->d_A, x,
+                       y, part, done);
+  GN_CHECK_LAUNCH();
+}
+
+int spmv_blocks(const gn_problem* p) { return (int)((p->n_node + 255) / 256); }
+
+void scatter_free(const gn_problem* p, const double* xf, double* xfull, hipStream_t s) {
+  GN_HIP(hipMemsetAsync(xfull, 0, sizeof(double) * p->n_dof, s));
+  hipLaunchKernelGGL(k_scatter_free, dim3((unsigned)((p->n_free + 255) / 256)), dim3(256), 0, s,
+                     p->n_free, p->d_free2full, xf, xfull);
+  GN_CHECK_LAUNCH();
+}
+
+void gather_free(const gn_problem* p, const double* xfull, double* xf, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_free, dim3((unsigned)((p->n_free + 255) / 256)), dim3(256), 0, s,
+                     p->n_free, p->d_free2full, xfull, xf);
+  GN_CHECK_LAUNCH();
+}
+
+}  // namespace gnk
+
+// ---------------------------------------------------------------------------
+// CG vector kernels with device-resident scalars.
+// scal layout: see enum in cg.h-like block below.
+// ---------------------------------------------------------------------------
+namespace {
+
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITER, S_MAXIT, S_BREAK, S_N };
+
+__global__ __launch_bounds__(RTHR) void k_dot(int64_t n, const double* __restrict__ a,
+                                              const double* __restrict__ b, double* __restrict__ part,
+                                              const double* __restrict__ done) {
+  __shared__ double sh[16];
+  if (done && *done != 0.0) return;
+  double v = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    v += a[t] * b[t];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// x += alpha p ; r -= alpha q ; partial r.r
+__global__ __launch_bounds__(RTHR) void k_update_xr(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    const double* __restrict__ scal, double* __restrict__ part) {
+  __shared__ double sh[16];
+  if (scal[S_DONE] != 0.0) return;
+  double alpha = scal[S_ALPHA];
+  double v = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    x[t] += alpha * p[t];
+    double rv = r[t] - alpha * q[t];
+    r[t] = rv;
+    v += rv * rv;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(RTHR) void k_update_p(int64_t n, double* __restrict__ p, const double* __restrict__ z,
+                                                   const double* __restrict__ scal) {
+  if (scal[S_DONE] != 0.0) return;
+  double beta = scal[S_BETA];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = z[t] + beta * p[t];
+}
+
+__global__ __launch_bounds__(RTHR) void k_resid(int64_t n, const double* __restrict__ b,
+                                                const double* __restrict__ q, double* __restrict__ part) {
+  __shared__ double sh[16];
+  double v = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    double d = b[t] - q[t];
+    v += d * d;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ void k_copy(int64_t n, double* __restrict__ dst, const double* __restrict__ src,
+                       const double* __restrict__ done) {
+  if (done && *done != 0.0) return;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+
+enum { OP_BB = 0, OP_RZ0, OP_ALPHA, OP_RR, OP_BETA };
+
+// single block: fixed-order sum of the partials, then the scalar recurrence
+__global__ void k_finalize(const double* __restrict__ part, int nb, int op, double* __restrict__ scal,
+                           double* __restrict__ hist, double rtol) {
+  __shared__ double sh[16];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += part[i];
+  double s = block_sum(v, sh);
+  if (threadIdx.x != 0) return;
+  if (op == OP_BB) {
+    scal[S_BB] = s;
+    scal[S_RR] = s;
+    scal[S_TOL2] = rtol * rtol * s;
+    scal[S_DONE] = (s == 0.0) ? 1.0 : 0.0;
+    scal[S_ITER] = 0.0;
+    scal[S_BREAK] = 0.0;
+    return;
+  }
+  if (scal[S_DONE] != 0.0) return;
+  int it = (int)scal[S_ITER];
+  switch (op) {
+    case OP_RZ0:
+      scal[S_RZ] = s;
+      break;
+    case OP_ALPHA:
+      scal[S_PQ] = s;
+      if (!(s > 0.0)) {
+        scal[S_BREAK] = 1.0;
+        scal[S_DONE] = 1.0;
+        scal[S_ALPHA] = 0.0;
+      } else {
+        scal[S_ALPHA] = scal[S_RZ] / s;
+      }
+      break;
+    case OP_RR:
+      scal[S_RR] = s;
+      hist[2 * it] = scal[S_ALPHA];
+      scal[S_ITER] = it + 1;
+      if (s <= scal[S_TOL2] || it + 1 >= (int)scal[S_MAXIT]) scal[S_DONE] = 1.0;
+      break;
+    case OP_BETA: {
+      double beta = s / scal[S_RZ];
+      scal[S_BETA] = beta;
+      scal[S_RZ] = s;
+      hist[2 * (it - 1) + 1] = beta;
+      break;
+    }
+  }
+}
+
+}  // namespace
+
+namespace gnk {
+
+int scal_count() { return S_N; }
+
+void dot_partial(int64_t n, const double* a, const double* b, double* part, const double* done,
+                 hipStream_t s) {
+  GnProfScope prof(PROF_VEC, 16.0 * n, s);
+  hipLaunchKernelGGL(k_dot, dim3(RBLK), dim3(RTHR), 0, s, n, a, b, part, done);
+  GN_CHECK_LAUNCH();
+}
+void finalize(const double* part, int nb, int op, double* scal, double* hist, double rtol,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, part, nb, op, scal, hist, rtol);
+  GN_CHECK_LAUNCH();
+}
+void update_xr(int64_t n, double* x, double* r, const double* p, const double* q, const double* scal,
+               double* part, hipStream_t s) {
+  GnProfScope prof(PROF_VEC, 48.0 * n, s);
+  hipLaunchKernelGGL(k_update_xr, dim3(RBLK), dim3(RTHR), 0, s, n, x, r, p, q, scal, part);
+  GN_CHECK_LAUNCH();
+}
+void update_p(int64_t n, double* p, const double* z, const double* scal, hipStream_t s) {
+  GnProfScope prof(PROF_VEC, 24.0 * n, s);
+  hipLaunchKernelGGL(k_update_p, dim3(RBLK), dim3(RTHR), 0, s, n, p, z, scal);
+  GN_CHECK_LAUNCH();
+}
+void residual_partial(int64_t n, const double* b, const double* q, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_resid, dim3(RBLK), dim3(RTHR), 0, s, n, b, q, part);
+  GN_CHECK_LAUNCH();
+}
+void copy(int64_t n, double* dst, const double* src, const double* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(RBLK), dim3(RTHR), 0, s, n, dst, src, done);
+  GN_CHECK_LAUNCH();
+}
+
+}  // namespace gnk

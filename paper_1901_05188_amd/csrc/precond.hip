@@ -1,0 +1,326 @@
+// Application of the two-level additive Schwarz preconditioner
+//   M^-1 r = sum_j R_j^T A_j^-1 R_j r + R_H^T A_H^-1 R_H r
+// (Section 3.1, eqn:onelevelAS and M^-1_{AS,2}; Section 3.3.3 for the coarse
+// restriction (R_H v)_i = Phi_i^T v and the prolongation R_H^T v_H).
+//
+// k_local_solve: one workgroup per subdomain gathers r on its node box (R_j is a
+//   box gather in the structured numbering), forms Phi_j^T r_j, and runs the
+//   forward and backward banded triangular solves with the subdomain vector
+//   held in LDS.
+// k_coarse_fwd / k_coarse_bwd: y = Z^T (Z g) with Z = L_H^-1 stored as dense
+//   tiles (the coarse factor inverse), one workgroup per tile row / column.
+// k_prolong: gather-form sum z = sum_j R_j^T (t_j + Phi_j y_j): each output DOF
+//   visits the (at most 8) subdomains whose box holds it, in a fixed order, so
+//   the result is deterministic without atomics; fused with the partial r.z.
+#include "gn_internal.h"
+
+namespace {
+
+constexpr int NT = 256;
+
+template <typename FT>
+struct FactorPtr {
+  const FT* T;
+  const FT* D;
+};
+
+template <typename FT, int NC, bool LDSVEC>
+__global__ __launch_bounds__(NT) void k_local_solve(const SubDesc* __restrict__ subs, int NX, int NY,
+                                                    const double* __restrict__ r, const FT* __restrict__ T,
+                                                    const FT* __restrict__ D, double* __restrict__ tvec,
+                                                    const double* __restrict__ Phi, double* __restrict__ g,
+                                                    const double* __restrict__ done) {
+  extern __shared__ double smem[];
+  __shared__ double red[8][TILE + 1];
+  __shared__ double sv[TILE];
+  if (done && *done != 0.0) return;
+  const SubDesc& sd = subs[blockIdx.x];
+  const int NB = sd.NBI, w = sd.wI;
+  const int npad = NB * TILE;
+  double* vec = LDSVEC ? smem : (tvec + sd.offVI);
+  // gather r_j = R_j r
+  for (int row = threadIdx.x; row < npad; row += NT) {
+    double v = 0.0;
+    if (row < sd.nI) {
+      int gn[3];
+      box_global_node(sd.ilo, sd.in_, sd.permI, row / NC, gn);
+      int64_t node = gn[0] + (int64_t)NX * (gn[1] + (int64_t)NY * gn[2]);
+      v = r[node * NC + row % NC];
+    }
+    vec[row] = v;
+  }
+  __syncthreads();
+  // coarse restriction g_j = Phi_j^T r_j
+  if (Phi && sd.m > 0) {
+    const double* ph = Phi + sd.offPhi;
+    for (int k0 = 0; k0 < sd.m; k0 += 8) {
+      double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int row = threadIdx.x; row < sd.nI; row += NT) {
+        double v = vec[row];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + q < sd.m) acc[q] += ph[(int64_t)row * sd.m + k0 + q] * v;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        double s = block_sum(acc[q], &red[0][0]);
+        if (threadIdx.x == 0 && k0 + q < sd.m) g[sd.coff + k0 + q] = s;
+      }
+    }
+    __syncthreads();
+  }
+  const int i = threadIdx.x % TILE, part = threadIdx.x / TILE;
+  const FT* Tb = T + sd.offTI * TILE2;
+  const FT* Db = D + sd.offDI * TILE2;
+  // forward: y_K = Dinv_K (r_K - sum_t L(K,t) y_{K-w+t})
+  for (int K = 0; K < NB; ++K) {
+    double acc = 0.0;
+    for (int t = part; t < w; t += 8) {
+      int J = K - w + t;
+      if (J < 0) continue;
+      const FT* tile = Tb + ((int64_t)K * (w + 1) + t) * TILE2;
+      const double* yj = vec + J * TILE;
+#pragma unroll 8
+      for (int c = 0; c < TILE; ++c) acc += (double)tile[c * TILE + i] * yj[c];
+    }
+    red[part][i] = acc;
+    __syncthreads();
+    if (threadIdx.x < TILE) {
+      double s = vec[K * TILE + i];
+#pragma unroll
+      for (int p2 = 0; p2 < 8; ++p2) s -= red[p2][i];
+      sv[i] = s;
+    }
+    __syncthreads();
+    {
+      const FT* dk = Db + (int64_t)K * TILE2;
+      double a2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int c = part * 4 + q;
+        a2 += (double)dk[c * TILE + i] * sv[c];
+      }
+      red[part][i] = a2;
+    }
+    __syncthreads();
+    if (threadIdx.x < TILE) {
+      double s = 0.0;
+#pragma unroll
+      for (int p2 = 0; p2 < 8; ++p2) s += red[p2][i];
+      vec[K * TILE + i] = s;
+    }
+    __syncthreads();
+  }
+  // backward: x_K = Dinv_K^T (y_K - sum_d L(K+d, w-d)^T x_{K+d})
+  for (int K = NB - 1; K >= 0; --K) {
+    double acc = 0.0;
+    for (int d = 1 + part; d <= w; d += 8) {
+      if (K + d >= NB) continue;
+      const FT* tile = Tb + ((int64_t)(K + d) * (w + 1) + (w - d)) * TILE2;
+      const double* xj = vec + (K + d) * TILE;
+      // column i of the tile (contiguous)
+#pragma unroll 8
+      for (int rr = 0; rr < TILE; ++rr) acc += (double)tile[i * TILE + rr] * xj[rr];
+    }
+    red[part][i] = acc;
+    __syncthreads();
+    if (threadIdx.x < TILE) {
+      double s = vec[K * TILE + i];
+#pragma unroll
+      for (int p2 = 0; p2 < 8; ++p2) s -= red[p2][i];
+      sv[i] = s;
+    }
+    __syncthreads();
+    {
+      const FT* dk = Db + (int64_t)K * TILE2;
+      double a2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int rr = part * 4 + q;
+        a2 += (double)dk[i * TILE + rr] * sv[rr];   // Dinv^T: (i, rr) <- Dinv(rr, i)
+      }
+      red[part][i] = a2;
+    }
+    __syncthreads();
+    if (threadIdx.x < TILE) {
+      double s = 0.0;
+#pragma unroll
+      for (int p2 = 0; p2 < 8; ++p2) s += red[p2][i];
+      vec[K * TILE + i] = s;
+    }
+    __syncthreads();
+  }
+  if (LDSVEC) {
+    double* out = tvec + sd.offVI;
+    for (int row = threadIdx.x; row < npad; row += NT) out[row] = vec[row];
+  }
+}
+
+// u_K = sum_{J<=K} Z(K,J) g_J   (one workgroup per tile row)
+__global__ __launch_bounds__(NT) void k_coarse_fwd(int NBH, const double* __restrict__ Z,
+                                                   const double* __restrict__ g, double* __restrict__ u,
+                                                   const double* __restrict__ done) {
+  __shared__ double red[8][TILE + 1];
+  if (done && *done != 0.0) return;
+  int K = blockIdx.x;
+  const int i = threadIdx.x % TILE, part = threadIdx.x / TILE;
+  double acc = 0.0;
+  for (int J = part; J <= K; J += 8) {
+    const double* tile = Z + ((int64_t)K * NBH + J) * TILE2;
+#pragma unroll 8
+    for (int c = 0; c < TILE; ++c) acc += tile[c * TILE + i] * g[J * TILE + c];
+  }
+  red[part][i] = acc;
+  __syncthreads();
+  if (threadIdx.x < TILE) {
+    double s = 0.0;
+    for (int p2 = 0; p2 < 8; ++p2) s += red[p2][i];
+    u[K * TILE + i] = s;
+  }
+}
+
+// y_J = sum_{K>=J} Z(K,J)^T u_K   (one workgroup per tile column)
+__global__ __launch_bounds__(NT) void k_coarse_bwd(int NBH, const double* __restrict__ Z,
+                                                   const double* __restrict__ u, double* __restrict__ y,
+                                                   const double* __restrict__ done) {
+  __shared__ double red[8][TILE + 1];
+  if (done && *done != 0.0) return;
+  int J = blockIdx.x;
+  const int c = threadIdx.x % TILE, part = threadIdx.x / TILE;
+  double acc = 0.0;
+  for (int K = J + part; K < NBH; K += 8) {
+    const double* tile = Z + ((int64_t)K * NBH + J) * TILE2;
+#pragma unroll 8
+    for (int rr = 0; rr < TILE; ++rr) acc += tile[c * TILE + rr] * u[K * TILE + rr];
+  }
+  red[part][c] = acc;
+  __syncthreads();
+  if (threadIdx.x < TILE) {
+    double s = 0.0;
+    for (int p2 = 0; p2 < 8; ++p2) s += red[p2][c];
+    y[J * TILE + c] = s;
+  }
+}
+
+struct PartAxes {
+  const int* cnt0; const int* cnt1; const int* cnt2;
+  const int* plo0; const int* plo1; const int* plo2;
+};
+
+template <int NC>
+__global__ __launch_bounds__(NT) void k_prolong(const SubDesc* __restrict__ subs, int NX, int NY, int NZ,
+                                                int P0, int P1, PartAxes pa, const uint8_t* __restrict__ dir,
+                                                const double* __restrict__ tvec, const double* __restrict__ Phi,
+                                                const double* __restrict__ y, const double* __restrict__ r,
+                                                double* __restrict__ z, double* __restrict__ part,
+                                                const double* __restrict__ done) {
+  __shared__ double sh[16];
+  if (done && *done != 0.0) return;
+  const int64_t n_node = (int64_t)NX * NY * NZ;
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double dotv = 0.0;
+  if (node < n_node) {
+    int gi = (int)(node % NX), gj = (int)((node / NX) % NY), gk = (int)(node / ((int64_t)NX * NY));
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    int c0 = pa.cnt0[gi], c1 = pa.cnt1[gj], c2 = pa.cnt2[gk];
+    int p0 = pa.plo0[gi], p1 = pa.plo1[gj], p2 = pa.plo2[gk];
+    for (int b2 = 0; b2 < c2; ++b2)
+      for (int b1 = 0; b1 < c1; ++b1)
+        for (int b0 = 0; b0 < c0; ++b0) {
+          int j = (p0 + b0) + P0 * ((p1 + b1) + P1 * (p2 + b2));
+          const SubDesc& sd = subs[j];
+          int ln = box_local_node(sd.ilo, sd.in_, sd.permI, gi, gj, gk);
+          const double* tv = tvec + sd.offVI + (int64_t)ln * NC;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            double v = tv[c];
+            if (Phi && sd.m > 0) {
+              const double* ph = Phi + sd.offPhi + ((int64_t)ln * NC + c) * sd.m;
+              const double* yy = y + sd.coff;
+              for (int k = 0; k < sd.m; ++k) v += ph[k] * yy[k];
+            }
+            acc[c] += v;
+          }
+        }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double v = dir[node * NC + c] ? 0.0 : acc[c];
+      z[node * NC + c] = v;
+      if (r) dotv += v * r[node * NC + c];
+    }
+  }
+  if (part) {
+    double s = block_sum(dotv, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+  }
+}
+
+}  // namespace
+
+namespace gnk {
+
+int max_lds_doubles() { return 18 * 1024; }
+
+void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, const double* done,
+                 hipStream_t s) {
+  const bool f32 = pc->local_prec == 32;
+  const double* Phi = pc->NH > 0 ? pc->d_Phi : nullptr;
+  size_t lds = (size_t)pc->maxNBI * TILE * sizeof(double);
+  bool ldsvec = pc->maxNBI * TILE <= max_lds_doubles();
+  size_t dyn = ldsvec ? lds : 0;
+  double bytes = pc->trsv_bytes;
+  GnProfScope prof(PROF_TRSV, bytes, s);
+#define GN_LS(FT, NC, L)                                                                         \
+  do {                                                                                           \
+    auto kfn = k_local_solve<FT, NC, L>;                                                         \
+    if (L) GN_HIP(hipFuncSetAttribute((const void*)kfn,                                          \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));    \
+    hipLaunchKernelGGL(kfn, dim3(pc->n_sub), dim3(NT), dyn, s, pc->d_sub, p->nn[0], p->nn[1], r, \
+                       (const FT*)(f32 ? (const void*)pc->d_LIf : (const void*)pc->d_LI),        \
+                       (const FT*)(f32 ? (const void*)pc->d_DIf : (const void*)pc->d_DI),        \
+                       pc->d_t, Phi, pc->d_g, done);                                             \
+  } while (0)
+  if (f32) {
+    if (p->nc == 3) { if (ldsvec) GN_LS(float, 3, true); else GN_LS(float, 3, false); }
+    else { if (ldsvec) GN_LS(float, 1, true); else GN_LS(float, 1, false); }
+  } else {
+    if (p->nc == 3) { if (ldsvec) GN_LS(double, 3, true); else GN_LS(double, 3, false); }
+    else { if (ldsvec) GN_LS(double, 1, true); else GN_LS(double, 1, false); }
+  }
+#undef GN_LS
+  GN_CHECK_LAUNCH();
+}
+
+void coarse_solve(const gn_precond* pc, const double* done, hipStream_t s) {
+  if (pc->NH == 0) return;
+  GnProfScope prof(PROF_COARSE, (double)pc->NBH * (pc->NBH + 1) * TILE2 * 8.0, s);
+  hipLaunchKernelGGL(k_coarse_fwd, dim3(pc->NBH), dim3(NT), 0, s, pc->NBH, pc->d_Z, pc->d_g,
+                     pc->d_u, done);
+  GN_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_coarse_bwd, dim3(pc->NBH), dim3(NT), 0, s, pc->NBH, pc->d_Z, pc->d_u,
+                     pc->d_y, done);
+  GN_CHECK_LAUNCH();
+}
+
+int prolong_blocks(const gn_problem* p) { return (int)((p->n_node + NT - 1) / NT); }
+
+void prolong(const gn_problem* p, const gn_precond* pc, const double* r, double* z, double* part,
+             const double* done, hipStream_t s) {
+  PartAxes pa{pc->d_cnt[0], pc->d_cnt[1], pc->d_cnt[2], pc->d_plo[0], pc->d_plo[1], pc->d_plo[2]};
+  const double* Phi = pc->NH > 0 ? pc->d_Phi : nullptr;
+  GnProfScope prof(PROF_PROLONG, pc->prolong_bytes, s);
+  dim3 grid((unsigned)((p->n_node + NT - 1) / NT));
+  if (p->nc == 3)
+    hipLaunchKernelGGL(k_prolong<3>, grid, dim3(NT), 0, s, pc->d_sub, p->nn[0], p->nn[1], p->nn[2],
+                       pc->nparts[0], pc->nparts[1], pa, p->d_dir, pc->d_t, Phi, pc->d_y, r, z,
+                       part, done);
+  else
+    hipLaunchKernelGGL(k_prolong<1>, grid, dim3(NT), 0, s, pc->d_sub, p->nn[0], p->nn[1], p->nn[2],
+                       pc->nparts[0], pc->nparts[1], pa, p->d_dir, pc->d_t, Phi, pc->d_y, r, z,
+                       part, done);
+  GN_CHECK_LAUNCH();
+}
+
+}  // namespace gnk
