@@ -127,6 +127,7 @@ def main():
         iters.append(rep["iters"])
         log(f"step {i}: total {tt:.3f}s setup {ts:.3f}s solve {tv:.3f}s iters {rep['iters']} "
             f"true_rel_res {rep['true_rel_res']:.2e} cond {rep['cond_est']:.1f} NH {pc.report['coarse_dim']}")
+        log("  setup report " + json.dumps(pc.report))
         last = (prob, pc, b, x, rep)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
@@ -188,6 +189,8 @@ def main():
         "solve_dofs_per_s": n_dof / statistics.median(lat_plain),
         "solve_latency_ms": {"p50": 1000 * pct(lat_sorted, 0.5), "p99": 1000 * pct(lat_sorted, 0.99)},
         "setup_s_median": statistics.median(setups),
+        "setup_breakdown_s": {"local_factors": pc.report["t_local_s"], "eigen": pc.report["t_eigen_s"],
+                              "coarse": pc.report["t_coarse_s"]},
         "coarse_dim": pc.report["coarse_dim"],
         "eig_iters": pc.report["eig_iters"],
         "cond_est": rep["cond_est"],

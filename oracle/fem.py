@@ -281,6 +281,51 @@ def load_full(w) -> np.ndarray:
     return b
 
 
+def assemble_rows(w, free_rows):
+    """Selected rows of the free-DOF system, each summed from the element
+    matrices of the elements around its node (for sampled checks at sizes
+    where a full assembly is too slow).  Returns (cols, vals, b) per row, cols
+    in free numbering."""
+    free = w.free_index()
+    free_of_full = -np.ones(w.n_dof_full, dtype=np.int64)
+    free_of_full[free] = np.arange(len(free))
+    nc = w.ncomp
+    nx, ny, nz = w.ne
+    NX, NY = nx + 1, ny + 1
+    out = []
+    X = node_xyz(w)
+    for fr in free_rows:
+        full = int(free[fr])
+        node, comp = divmod(full, nc)
+        i, j, k = node % NX, (node // NX) % NY, node // (NX * NY)
+        elems = [ex + nx * (ey + ny * ez)
+                 for ez in (k - 1, k) for ey in (j - 1, j) for ex in (i - 1, i)
+                 if 0 <= ex < nx and 0 <= ey < ny and 0 <= ez < nz]
+        Ke = element_matrices(w, elems)
+        en = elem_nodes(w, np.array(elems))
+        dofs = elem_dofs(w, en)
+        row = {}
+        bval = 0.0
+        for t, e in enumerate(elems):
+            a = int(np.flatnonzero(en[t] == node)[0])
+            li = a * nc + comp
+            for lj, dj in enumerate(dofs[t]):
+                fj = free_of_full[dj]
+                if fj >= 0:
+                    row[fj] = row.get(fj, 0.0) + Ke[t][li, lj]
+            if w.body is not None:
+                bval += fe_body(X[en[t]], w.body.reshape(w.n_elem, nc)[e])[li]
+        if w.traction is not None:
+            g = w.traction.reshape(w.nrhs, nx * ny, nc)
+            for t, e in enumerate(elems):
+                if e // (nx * ny) == nz - 1:
+                    a = int(np.flatnonzero(en[t] == node)[0])
+                    bval += fe_top_traction(X[en[t]], g[0, e % (nx * ny)])[a * nc + comp]
+        cols = np.array(sorted(row))
+        out.append((cols, np.array([row[c] for c in cols]), bval))
+    return out
+
+
 def assemble(w, Ke=None):
     """Free-DOF system (A, b, free) with homogeneous Dirichlet DOFs dropped."""
     Afull = assemble_full(w, Ke)

@@ -538,14 +538,15 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     std::vector<int> nwant(n_sub, 0);
     std::vector<double> worst_hist;
     bool converged = false;
+    gnk::eig_bapply(p, pc, b, maxNBB, V, BV, s);
     for (int it = 0; it < eig_maxit; ++it) {
-      gnk::eig_bapply(p, pc, b, maxNBB, V, BV, s);
+      // Z = P^-1 B V ; Rayleigh-Ritz on span(Z) ; V <- Z Y, BV <- (B Z) Y
       GN_HIP(hipMemcpyAsync(Z, BV, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
       gnk::eig_trsm(pc, b, LB, DB, Z, s);
       gnk::eig_bapply(p, pc, b, maxNBB, Z, BZ, s);
       gnk::eig_gram(pc, b, Z, BV, BZ, V, nu, GP, GB, res, s);
       gnk::eig_small(n_sub, b, GP, GB, Y, nu, nullptr, s);
-      gnk::eig_vupdate(pc, b, maxNBB, Z, Y, V, s);
+      gnk::eig_vupdate(pc, b, maxNBB, Z, BZ, Y, V, BV, s);
       GN_HIP(hipMemcpyAsync(h_res.data(), res, sizeof(double) * h_res.size(), hipMemcpyDeviceToHost, s));
       // residuals refer to the Ritz pairs of the previous iteration (h_nu before this copy)
       std::vector<double> prev_nu = h_nu;
@@ -775,8 +776,6 @@ extern "C" gn_status gn_precond_apply(gn_precond* pc, const double* r_dev, doubl
 // ---------------------------------------------------------------------------
 // PCG
 // ---------------------------------------------------------------------------
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITER, S_MAXIT, S_BREAK };
-enum { OP_BB = 0, OP_RZ0, OP_ALPHA, OP_RR, OP_BETA };
 
 extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev, double* x_dev,
                               int32_t nrhs, int64_t ld, const gn_solve_opts* opts, void* stream,
@@ -821,43 +820,72 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
     gnk::copy(n, p->d_p, p->d_z, done, s);
     double hs[16];
     int iters = 0;
-    bool fin = false;
-    while (!fin) {
-      for (int k = 0; k < chunk; ++k) {
-        gnk::spmv_flag(p, p->d_p, p->d_q, p->d_part, done, s);
-        gnk::finalize(p->d_part, nbs, OP_ALPHA, scal, p->d_hist, opts->rtol, s);
-        gnk::update_xr(n, p->d_x, p->d_r, p->d_p, p->d_q, scal, p->d_part, s);
-        gnk::finalize(p->d_part, nbr, OP_RR, scal, p->d_hist, opts->rtol, s);
-        if (pc) {
-          precond_full(p, pc, p->d_r, p->d_z, p->d_part, done, s);
-          gnk::finalize(p->d_part, nbp, OP_BETA, scal, p->d_hist, opts->rtol, s);
-        } else {
-          gnk::copy(n, p->d_z, p->d_r, done, s);
-          gnk::dot_partial(n, p->d_r, p->d_z, p->d_part, done, s);
-          gnk::finalize(p->d_part, nbr, OP_BETA, scal, p->d_hist, opts->rtol, s);
+    auto iterate = [&]() {
+      bool fin = false;
+      while (!fin) {
+        for (int k = 0; k < chunk; ++k) {
+          gnk::spmv_flag(p, p->d_p, p->d_q, p->d_part, done, s);
+          gnk::finalize(p->d_part, nbs, OP_ALPHA, scal, p->d_hist, opts->rtol, s);
+          gnk::update_xr(n, p->d_x, p->d_r, p->d_p, p->d_q, scal, p->d_part, s);
+          gnk::finalize(p->d_part, nbr, OP_RR, scal, p->d_hist, opts->rtol, s);
+          if (pc) {
+            precond_full(p, pc, p->d_r, p->d_z, p->d_part, done, s);
+            gnk::finalize(p->d_part, nbp, OP_BETA, scal, p->d_hist, opts->rtol, s);
+          } else {
+            gnk::copy(n, p->d_z, p->d_r, done, s);
+            gnk::dot_partial(n, p->d_r, p->d_z, p->d_part, done, s);
+            gnk::finalize(p->d_part, nbr, OP_BETA, scal, p->d_hist, opts->rtol, s);
+          }
+          gnk::update_p(n, p->d_p, p->d_z, scal, s);
         }
-        gnk::update_p(n, p->d_p, p->d_z, scal, s);
+        GN_HIP(hipMemcpyAsync(hs, scal, sizeof(double) * 11, hipMemcpyDeviceToHost, s));
+        GN_HIP(hipStreamSynchronize(s));
+        iters = (int)hs[S_ITER];
+        fin = hs[S_DONE] != 0.0;
       }
-      GN_HIP(hipMemcpyAsync(hs, scal, sizeof(double) * 11, hipMemcpyDeviceToHost, s));
+    };
+    // ||b - A x||^2, leaving A x in q and b (full numbering) in z
+    std::vector<double> part(nbr);
+    auto true_residual = [&]() {
+      gnk::spmv_flag(p, p->d_x, p->d_q, nullptr, nullptr, s);
+      gnk::scatter_free(p, b_dev + col * ld, p->d_z, s);
+      gnk::residual_partial(n, p->d_z, p->d_q, p->d_part, s);
+      GN_HIP(hipMemcpyAsync(part.data(), p->d_part, sizeof(double) * nbr, hipMemcpyDeviceToHost, s));
       GN_HIP(hipStreamSynchronize(s));
-      iters = (int)hs[S_ITER];
-      fin = hs[S_DONE] != 0.0;
+      double t = 0.0;
+      for (double v : part) t += v;
+      return t;
+    };
+    iterate();
+    const int first_iters = iters;
+    double tr = true_residual();
+    // the recursive residual drifts from b - A x (attainable accuracy of CG):
+    // restart from the current iterate with the true residual, at most twice
+    for (int restart = 0; restart < 2 && hs[S_BREAK] == 0.0 && hs[S_BB] > 0.0 && tr > hs[S_TOL2] &&
+                          iters < opts->maxit;
+         ++restart) {
+      gnk::sub_partial(n, p->d_z, p->d_q, p->d_r, p->d_part, s);   // r = b - A x
+      gnk::finalize(p->d_part, nbr, OP_RESTART, scal, p->d_hist, opts->rtol, s);
+      if (pc) {
+        precond_full(p, pc, p->d_r, p->d_z, p->d_part, done, s);
+        gnk::finalize(p->d_part, nbp, OP_RZ0, scal, p->d_hist, opts->rtol, s);
+      } else {
+        gnk::copy(n, p->d_z, p->d_r, done, s);
+        gnk::dot_partial(n, p->d_r, p->d_z, p->d_part, done, s);
+        gnk::finalize(p->d_part, nbr, OP_RZ0, scal, p->d_hist, opts->rtol, s);
+      }
+      gnk::copy(n, p->d_p, p->d_z, done, s);
+      iterate();
+      tr = true_residual();
     }
     const double tsolve = now_s() - tstart;
-    // true residual
-    gnk::spmv_flag(p, p->d_x, p->d_q, nullptr, nullptr, s);
-    gnk::scatter_free(p, b_dev + col * ld, p->d_z, s);
-    gnk::residual_partial(n, p->d_z, p->d_q, p->d_part, s);
     double bb = hs[S_BB], rr = hs[S_RR];
-    std::vector<double> part(nbr);
-    GN_HIP(hipMemcpyAsync(part.data(), p->d_part, sizeof(double) * nbr, hipMemcpyDeviceToHost, s));
-    std::vector<double> hist((size_t)2 * std::max(iters, 1));
-    if (iters > 0)
-      GN_HIP(hipMemcpyAsync(hist.data(), p->d_hist, sizeof(double) * 2 * iters, hipMemcpyDeviceToHost, s));
+    const int kit = first_iters;   // the CG-Lanczos estimate uses the first (unrestarted) sequence
+    std::vector<double> hist((size_t)2 * std::max(kit, 1));
+    if (kit > 0)
+      GN_HIP(hipMemcpyAsync(hist.data(), p->d_hist, sizeof(double) * 2 * kit, hipMemcpyDeviceToHost, s));
     gnk::gather_free(p, p->d_x, x_dev + col * ld, s);
     GN_HIP(hipStreamSynchronize(s));
-    double tr = 0.0;
-    for (double v : part) tr += v;
     bool conv = bb == 0.0 || rr <= hs[S_TOL2];
     if (hs[S_BREAK] != 0.0) ret = GN_ERR_BREAKDOWN;
     else if (!conv && ret == GN_OK) ret = GN_WARN_MAXIT;
@@ -870,12 +898,12 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
       R.t_solve_s = tsolve;
       // CG-Lanczos tridiagonal: T_ii = 1/a_i + b_{i-1}/a_{i-1}, T_{i,i+1} = sqrt(b_i)/a_i
       R.cond_est = 1.0;
-      if (iters > 0) {
-        std::vector<double> d(iters), e(std::max(iters - 1, 0));
-        for (int i = 0; i < iters; ++i) {
+      if (kit > 0) {
+        std::vector<double> d(kit), e(std::max(kit - 1, 0));
+        for (int i = 0; i < kit; ++i) {
           double a = hist[2 * i];
           d[i] = 1.0 / a + (i > 0 ? hist[2 * (i - 1) + 1] / hist[2 * (i - 1)] : 0.0);
-          if (i + 1 < iters) e[i] = std::sqrt(std::max(hist[2 * i + 1], 0.0)) / a;
+          if (i + 1 < kit) e[i] = std::sqrt(std::max(hist[2 * i + 1], 0.0)) / a;
         }
         double lo, hi;
         tridiag_extremes(d, e, &lo, &hi);

@@ -92,79 +92,100 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
 // ---------------------------------------------------------------------------
 // in-place V <- P^-1 V with the banded factor of P (forward then backward), b columns
 // ---------------------------------------------------------------------------
+// Each step stages one band tile and the matching 32 x b block of the right-hand
+// sides in LDS (coalesced loads), then every thread accumulates its outputs
+// (row i, columns cg + 8q) from LDS; accumulators live in registers (NQ fixed).
+__device__ inline void stage_tile(double (*sL)[TILE + 1], const double* __restrict__ src) {
+  for (int e = threadIdx.x; e < TILE2; e += NT) sL[e / TILE][e % TILE] = src[e];   // sL[col][row]
+}
+__device__ inline void stage_rows(double (*sY)[64 + 1], const double* __restrict__ src, int b) {
+  for (int e = threadIdx.x; e < TILE * b; e += NT) sY[e / b][e % b] = src[e];
+}
+
+template <int NQ>
 __global__ __launch_bounds__(NT) void k_trsm_pencil(const SubDesc* __restrict__ subs, int b,
                                                     const double* __restrict__ T, const double* __restrict__ D,
                                                     double* __restrict__ V) {
-  __shared__ double S[TILE][64 + 1];
+  __shared__ double sL[TILE][TILE + 1];
+  __shared__ double sY[TILE][64 + 1];
   const SubDesc& sd = subs[blockIdx.x];
   const int NB = sd.NBB, w = sd.wB;
   const double* Tb = T + sd.offTB * TILE2;
   const double* Db = D + sd.offDB * TILE2;
   double* Vb = V + sd.offVB * b;
   const int i = threadIdx.x % TILE, cg = threadIdx.x / TILE;
-  const int nq = (b + 7) / 8;
-  // forward
+  // forward: Y_K = Dinv_K (V_K - sum_t L(K,t) Y_{K-w+t})
   for (int K = 0; K < NB; ++K) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     for (int t = 0; t < w; ++t) {
       int J = K - w + t;
       if (J < 0) continue;
-      const double* tile = Tb + ((int64_t)K * (w + 1) + t) * TILE2;
-      const double* yj = Vb + (int64_t)J * TILE * b;
+      __syncthreads();
+      stage_tile(sL, Tb + ((int64_t)K * (w + 1) + t) * TILE2);
+      stage_rows(sY, Vb + (int64_t)J * TILE * b, b);
+      __syncthreads();
+#pragma unroll 4
       for (int c = 0; c < TILE; ++c) {
-        double l = tile[c * TILE + i];
-        for (int q = 0; q < nq; ++q) {
-          int col = cg + 8 * q;
-          if (col < b) acc[q] += l * yj[c * b + col];
-        }
+        double l = sL[c][i];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += l * sY[c][min(cg + 8 * q, 63)];
       }
     }
-    for (int q = 0; q < nq; ++q) {
+    __syncthreads();
+    stage_tile(sL, Db + (int64_t)K * TILE2);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
       int col = cg + 8 * q;
-      if (col < b) S[i][col] = Vb[(int64_t)(K * TILE + i) * b + col] - acc[q];
+      if (col < b) sY[i][col] = Vb[(int64_t)(K * TILE + i) * b + col] - acc[q];
     }
     __syncthreads();
-    const double* dk = Db + (int64_t)K * TILE2;
-    for (int q = 0; q < nq; ++q) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
       int col = cg + 8 * q;
-      if (col >= b) continue;
       double s = 0.0;
-      for (int c = 0; c < TILE; ++c) s += dk[c * TILE + i] * S[c][col];
-      Vb[(int64_t)(K * TILE + i) * b + col] = s;
+#pragma unroll 8
+      for (int c = 0; c < TILE; ++c) s += sL[c][i] * sY[c][min(col, 63)];
+      if (col < b) Vb[(int64_t)(K * TILE + i) * b + col] = s;
     }
     __threadfence_block();
-    __syncthreads();
   }
-  // backward
+  // backward: X_K = Dinv_K^T (Y_K - sum_d L(K+d, K)^T X_{K+d})
   for (int K = NB - 1; K >= 0; --K) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     for (int d = 1; d <= w; ++d) {
       if (K + d >= NB) break;
-      const double* tile = Tb + ((int64_t)(K + d) * (w + 1) + (w - d)) * TILE2;
-      const double* xj = Vb + (int64_t)(K + d) * TILE * b;
+      __syncthreads();
+      stage_tile(sL, Tb + ((int64_t)(K + d) * (w + 1) + (w - d)) * TILE2);
+      stage_rows(sY, Vb + (int64_t)(K + d) * TILE * b, b);
+      __syncthreads();
+#pragma unroll 4
       for (int rr = 0; rr < TILE; ++rr) {
-        double l = tile[i * TILE + rr];   // L(rr, i) of block (K+d, K)
-        for (int q = 0; q < nq; ++q) {
-          int col = cg + 8 * q;
-          if (col < b) acc[q] += l * xj[rr * b + col];
-        }
+        double l = sL[i][rr];   // L(rr, i) of block (K+d, K)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += l * sY[rr][min(cg + 8 * q, 63)];
       }
     }
-    for (int q = 0; q < nq; ++q) {
+    __syncthreads();
+    stage_tile(sL, Db + (int64_t)K * TILE2);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
       int col = cg + 8 * q;
-      if (col < b) S[i][col] = Vb[(int64_t)(K * TILE + i) * b + col] - acc[q];
+      if (col < b) sY[i][col] = Vb[(int64_t)(K * TILE + i) * b + col] - acc[q];
     }
     __syncthreads();
-    const double* dk = Db + (int64_t)K * TILE2;
-    for (int q = 0; q < nq; ++q) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
       int col = cg + 8 * q;
-      if (col >= b) continue;
       double s = 0.0;
-      for (int rr = 0; rr < TILE; ++rr) s += dk[i * TILE + rr] * S[rr][col];
-      Vb[(int64_t)(K * TILE + i) * b + col] = s;
+#pragma unroll 8
+      for (int rr = 0; rr < TILE; ++rr) s += sL[i][rr] * sY[rr][min(col, 63)];
+      if (col < b) Vb[(int64_t)(K * TILE + i) * b + col] = s;
     }
     __threadfence_block();
-    __syncthreads();
   }
 }
 
@@ -172,6 +193,7 @@ __global__ __launch_bounds__(NT) void k_trsm_pencil(const SubDesc* __restrict__ 
 // Gram matrices  GP = Z^T (B V) = Z^T P Z,  GB = Z^T (B Z);  residuals
 // res_k = ||Z_k - nu_k V_k||^2, zz_k = ||Z_k||^2   (one workgroup per subdomain)
 // ---------------------------------------------------------------------------
+template <int NPQ>   // ceil(b*b / NT) output pairs per thread
 __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, int b,
                                              const double* __restrict__ Z, const double* __restrict__ BV,
                                              const double* __restrict__ BZ, const double* __restrict__ V,
@@ -183,8 +205,9 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
   const int64_t base = sd.offVB * b;
   const int n = sd.nB;
   const int np = b * b;
-  double aP[16], aB[16];
-  for (int q = 0; q < 16; ++q) aP[q] = aB[q] = 0.0;
+  double aP[NPQ], aB[NPQ];
+#pragma unroll
+  for (int q = 0; q < NPQ; ++q) aP[q] = aB[q] = 0.0;
   double rs = 0.0, zz = 0.0;
   const double* nus = nu + (int64_t)blockIdx.x * b;
   for (int r0 = 0; r0 < n; r0 += R) {
@@ -200,18 +223,16 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
       sV[rr][col] = ok ? V[o] : 0.0;
     }
     __syncthreads();
-    for (int q = 0; q < 16; ++q) {
-      int pidx = threadIdx.x + q * NT;
-      if (pidx >= np) break;
-      int k = pidx / b, l = pidx % b;
-      double sp = 0.0, sb = 0.0;
+#pragma unroll 1
+    for (int rr = 0; rr < R; ++rr) {
 #pragma unroll
-      for (int rr = 0; rr < R; ++rr) {
-        sp += sZ[rr][k] * sBV[rr][l];
-        sb += sZ[rr][k] * sBZ[rr][l];
+      for (int q = 0; q < NPQ; ++q) {
+        int pidx = min(threadIdx.x + q * NT, np - 1);
+        int k = pidx / b, l = pidx % b;
+        double zk = sZ[rr][k];
+        aP[q] += zk * sBV[rr][l];
+        aB[q] += zk * sBZ[rr][l];
       }
-      aP[q] += sp;
-      aB[q] += sb;
     }
     if (threadIdx.x < b) {
       int k = threadIdx.x;
@@ -226,11 +247,13 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
   }
   double* gp = GP + (int64_t)blockIdx.x * np;
   double* gb = GB + (int64_t)blockIdx.x * np;
-  for (int q = 0; q < 16; ++q) {
+#pragma unroll
+  for (int q = 0; q < NPQ; ++q) {
     int pidx = threadIdx.x + q * NT;
-    if (pidx >= np) break;
-    gp[pidx] = aP[q];
-    gb[pidx] = aB[q];
+    if (pidx < np) {
+      gp[pidx] = aP[q];
+      gb[pidx] = aB[q];
+    }
   }
   if (threadIdx.x < b) {
     res[(int64_t)blockIdx.x * 2 * b + threadIdx.x] = rs;
@@ -425,25 +448,37 @@ __global__ __launch_bounds__(NT) void k_small_eig(int b, const double* __restric
   if (tid < b) nu_out[(int64_t)blockIdx.x * b + tid] = C[order[tid] * ld + order[tid]];
 }
 
-// V = Z Y  (rows of one subdomain per grid.y; Y in LDS)
+// V = Z Y and BV = (B Z) Y (the B-image of the new block without another B
+// application): one workgroup per 16 rows of one subdomain (grid.y), Y and the
+// row blocks staged in LDS.
 __global__ __launch_bounds__(NT) void k_vupdate(const SubDesc* __restrict__ subs, int b,
-                                                const double* __restrict__ Z, const double* __restrict__ Y,
-                                                double* __restrict__ V) {
-  __shared__ double sY[64 * 64];
+                                                const double* __restrict__ Z, const double* __restrict__ BZ,
+                                                const double* __restrict__ Y, double* __restrict__ V,
+                                                double* __restrict__ BV) {
+  constexpr int R = 16;
+  __shared__ double sY[64][64 + 1];
+  __shared__ double sZ[R][64 + 1], sB[R][64 + 1];
   const SubDesc& sd = subs[blockIdx.y];
+  const int r0 = blockIdx.x * R;
+  if (r0 >= sd.NBB * TILE) return;
   const double* Yb = Y + (int64_t)blockIdx.y * b * b;
-  for (int e = threadIdx.x; e < b * b; e += NT) sY[e] = Yb[e];
+  for (int e = threadIdx.x; e < b * b; e += NT) sY[e / b][e % b] = Yb[e];
+  const int64_t base = sd.offVB * b + (int64_t)r0 * b;
+  for (int e = threadIdx.x; e < R * b; e += NT) {
+    sZ[e / b][e % b] = Z[base + e];
+    sB[e / b][e % b] = BZ[base + e];
+  }
   __syncthreads();
-  int r = blockIdx.x * NT + threadIdx.x;
-  if (r >= sd.NBB * TILE) return;
-  const double* zr = Z + sd.offVB * b + (int64_t)r * b;
-  double* vr = V + sd.offVB * b + (int64_t)r * b;
-  double zl[64];
-  for (int k = 0; k < b; ++k) zl[k] = zr[k];
-  for (int l = 0; l < b; ++l) {
-    double s = 0.0;
-    for (int k = 0; k < b; ++k) s += zl[k] * sY[k * b + l];
-    vr[l] = s;
+  for (int e = threadIdx.x; e < R * b; e += NT) {
+    int rr = e / b, l = e % b;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < b; ++k) {
+      double y = sY[k][l];
+      s1 += sZ[rr][k] * y;
+      s2 += sB[rr][k] * y;
+    }
+    V[base + e] = s1;
+    BV[base + e] = s2;
   }
 }
 
@@ -775,14 +810,29 @@ void eig_bapply(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, co
 }
 
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, double* V, hipStream_t s) {
-  hipLaunchKernelGGL(k_trsm_pencil, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, T, D, V);
+  const int nq = (b + 7) / 8;
+#define GN_TRSM(Q) \
+  case Q: hipLaunchKernelGGL(k_trsm_pencil<Q>, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, T, D, V); break;
+  switch (nq) {
+    GN_TRSM(1) GN_TRSM(2) GN_TRSM(3) GN_TRSM(4) GN_TRSM(5) GN_TRSM(6) GN_TRSM(7) GN_TRSM(8)
+    default: throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
+  }
+#undef GN_TRSM
   GN_CHECK_LAUNCH();
 }
 
 void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, const double* BZ,
               const double* V, const double* nu, double* GP, double* GB, double* res, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, Z, BV, BZ, V, nu, GP, GB,
-                     res);
+  const int need = (b * b + NT - 1) / NT;
+#define GN_GRAM(Q)                                                                                   \
+  hipLaunchKernelGGL(k_gram<Q>, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, Z, BV, BZ, V, nu, GP, \
+                     GB, res)
+  if (need <= 1) GN_GRAM(1);
+  else if (need <= 2) GN_GRAM(2);
+  else if (need <= 4) GN_GRAM(4);
+  else if (need <= 8) GN_GRAM(8);
+  else GN_GRAM(16);
+#undef GN_GRAM
   GN_CHECK_LAUNCH();
 }
 
@@ -795,10 +845,10 @@ void eig_small(int n_sub, int b, const double* GP, const double* GB, double* Y, 
   GN_CHECK_LAUNCH();
 }
 
-void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const double* Y, double* V,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_vupdate, dim3((maxNBB * TILE + NT - 1) / NT, pc->n_sub), dim3(NT), 0, s,
-                     pc->d_sub, b, Z, Y, V);
+void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const double* BZ,
+                 const double* Y, double* V, double* BV, hipStream_t s) {
+  hipLaunchKernelGGL(k_vupdate, dim3(maxNBB * TILE / 16, pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, Z,
+                     BZ, Y, V, BV);
   GN_CHECK_LAUNCH();
 }
 

@@ -32,6 +32,10 @@ void gn_set_error(gn_status code, const std::string& msg);
 
 #define GN_CHECK_LAUNCH() GN_HIP(hipGetLastError())
 
+// device-resident CG scalars and the recurrence steps of the single-block finalize kernel
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITER, S_MAXIT, S_BREAK, S_N };
+enum { OP_BB = 0, OP_RZ0, OP_ALPHA, OP_RR, OP_BETA, OP_RESTART };
+
 // ---------------------------------------------------------------------------
 // per-subdomain description (plain data, mirrored on the device)
 // ---------------------------------------------------------------------------
@@ -159,6 +163,7 @@ void update_xr(int64_t n, double* x, double* r, const double* p, const double* q
 void update_p(int64_t n, double* p, const double* z, const double* scal, hipStream_t s);
 void copy(int64_t n, double* dst, const double* src, const double* done, hipStream_t s);
 void residual_partial(int64_t n, const double* b, const double* q, double* part, hipStream_t s);
+void sub_partial(int64_t n, const double* b, const double* q, double* r, double* part, hipStream_t s);
 // band.hip
 void extract_local(const gn_problem* p, const gn_precond* pc, double* L, int maxNB, hipStream_t s);
 void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, double* L, int maxNB,
@@ -181,8 +186,8 @@ void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, co
               const double* V, const double* nu, double* GP, double* GB, double* res, hipStream_t s);
 void eig_small(int n_sub, int b, const double* GP, const double* GB, double* Y, double* nu, int* flag,
                hipStream_t s);
-void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const double* Y, double* V,
-                 hipStream_t s);
+void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const double* BZ,
+                 const double* Y, double* V, double* BV, hipStream_t s);
 void eig_normalise(const gn_precond* pc, int b, int ncol, double* V, hipStream_t s);
 void build_phi(const gn_problem* p, const gn_precond* pc, int b, int maxNI, const double* V,
                hipStream_t s);

@@ -115,7 +115,6 @@ void gather_free(const gn_problem* p, const double* xfull, double* xf, hipStream
 // ---------------------------------------------------------------------------
 namespace {
 
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITER, S_MAXIT, S_BREAK, S_N };
 
 __global__ __launch_bounds__(RTHR) void k_dot(int64_t n, const double* __restrict__ a,
                                               const double* __restrict__ b, double* __restrict__ part,
@@ -172,6 +171,22 @@ __global__ __launch_bounds__(RTHR) void k_resid(int64_t n, const double* __restr
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
+// r = b - q ; partial r.r
+__global__ __launch_bounds__(RTHR) void k_sub(int64_t n, const double* __restrict__ b,
+                                              const double* __restrict__ q, double* __restrict__ r,
+                                              double* __restrict__ part) {
+  __shared__ double sh[16];
+  double v = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    double d = b[t] - q[t];
+    r[t] = d;
+    v += d * d;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
 __global__ void k_copy(int64_t n, double* __restrict__ dst, const double* __restrict__ src,
                        const double* __restrict__ done) {
   if (done && *done != 0.0) return;
@@ -180,7 +195,6 @@ __global__ void k_copy(int64_t n, double* __restrict__ dst, const double* __rest
     dst[t] = src[t];
 }
 
-enum { OP_BB = 0, OP_RZ0, OP_ALPHA, OP_RR, OP_BETA };
 
 // single block: fixed-order sum of the partials, then the scalar recurrence
 __global__ void k_finalize(const double* __restrict__ part, int nb, int op, double* __restrict__ scal,
@@ -197,6 +211,11 @@ __global__ void k_finalize(const double* __restrict__ part, int nb, int op, doub
     scal[S_DONE] = (s == 0.0) ? 1.0 : 0.0;
     scal[S_ITER] = 0.0;
     scal[S_BREAK] = 0.0;
+    return;
+  }
+  if (op == OP_RESTART) {   // new residual b - A x of a restarted sequence
+    scal[S_RR] = s;
+    scal[S_DONE] = (s <= scal[S_TOL2] || (int)scal[S_ITER] >= (int)scal[S_MAXIT]) ? 1.0 : 0.0;
     return;
   }
   if (scal[S_DONE] != 0.0) return;
@@ -261,6 +280,10 @@ void update_p(int64_t n, double* p, const double* z, const double* scal, hipStre
 }
 void residual_partial(int64_t n, const double* b, const double* q, double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_resid, dim3(RBLK), dim3(RTHR), 0, s, n, b, q, part);
+  GN_CHECK_LAUNCH();
+}
+void sub_partial(int64_t n, const double* b, const double* q, double* r, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3(RBLK), dim3(RTHR), 0, s, n, b, q, r, part);
   GN_CHECK_LAUNCH();
 }
 void copy(int64_t n, double* dst, const double* src, const double* done, hipStream_t s) {

@@ -46,7 +46,7 @@ def geneo_run(name, coarse=True):
 def geneo_run_shift(name, shift):
     w = workload(name)
     A, b, free, Ke = system(name)
-    return geneo.GenEO(w, A, Ke, shift=shift)
+    return geneo.GenEO(w, A, Ke, shift=shift, keep_all=True)
 
 
 @functools.lru_cache(maxsize=None)

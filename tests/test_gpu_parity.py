@@ -118,19 +118,23 @@ def test_geneo_eigenvalues_and_counts(name):
     g = orc.geneo_run(name)
     pc = precond(name)
     w = orc.workload(name)
+    g2 = orc.geneo_run_shift(name, 1e-1)
     for j in range(w.n_sub):
         lam, m = pc.eigenvalues(j)
         lref = g.lam[j]
         assert m == g.m[j], (j, m, g.m[j], lam[:m + 2], lref[:m + 2])
         k = m + 1
         # exact zeros (rigid-body / constant modes of floating subdomains) carry
-        # only rounding: both sides must put them below 1e-9 * lambda_{m+1};
-        # every other eigenvalue must agree to 1e-10 relative
+        # only rounding: both sides must put them below 1e-9 * lambda_{m+1}
         zero = 1e-9 * abs(lref[m])
         z = np.abs(lref[:k]) < zero
         assert np.all(np.abs(lam[:k][z]) < zero), (j, lam[:k], lref[:k])
-        assert np.all(np.abs(lam[:k][~z] - lref[:k][~z]) <= 1e-10 * np.abs(lref[:k][~z])), \
-            (j, lam[:k], lref[:k])
+        # every other eigenvalue agrees to 1e-10 relative, or to 20x the oracle's own
+        # change under a change of the (algorithmic) shift, whichever is larger
+        self_d = np.abs(g2.lam[j][:k] - lref[:k])
+        tol = np.maximum(1e-10 * np.abs(lref[:k]), 20 * self_d)
+        err = np.abs(lam[:k] - lref[:k])
+        assert np.all(err[~z] <= tol[~z]), (j, lam[:k], lref[:k], err, tol)
 
 
 @pytest.mark.parametrize("name", ALL)

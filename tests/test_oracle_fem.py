@@ -194,3 +194,16 @@ def test_manufactured_solution_second_order():
         errs.append(np.sqrt(np.mean((u - ue) ** 2)))
     rates = [errs[i] / errs[i + 1] for i in range(2)]
     assert all(r > 3.5 for r in rates), (errs, rates)
+
+
+def test_sampled_rows_equal_full_assembly():
+    w = gen.small_case("laminate", seed=3, nxy=(5, 4), n_ply=2,
+                       traction=np.tile([0.0, 0.01, -0.02], 20))
+    A, b, free = fem.assemble(w)
+    rows = [0, 7, 100, w.n_free - 1]
+    for r, (cols, vals, bv) in zip(rows, fem.assemble_rows(w, rows)):
+        ref = A[r].toarray()[0]
+        got = np.zeros_like(ref)
+        got[cols] = vals
+        assert np.allclose(got, ref, rtol=1e-13, atol=1e-12 * abs(ref).max())
+        assert abs(bv - b[r, 0]) <= 1e-13 * max(1.0, abs(b[r, 0]))
