@@ -175,6 +175,8 @@ typedef struct gn_solve_report {
   double true_rel_res;  /* ||b - A x|| / ||b|| recomputed at exit             */
   double cond_est;      /* extreme eigenvalue ratio of the CG-Lanczos tridiagonal */
   double t_solve_s;
+  int32_t iters_first;  /* iterations of the first (un-restarted) CG sequence   */
+  int32_t restarts;     /* restarts from b - A x taken to meet rtol on the true residual */
 } gn_solve_report;
 
 /* Solve A x = b by PCG with x0 = 0 for nrhs columns (device pointers, free

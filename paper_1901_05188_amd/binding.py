@@ -66,7 +66,8 @@ class gn_solve_opts(C.Structure):
 
 class gn_solve_report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_res", C.c_double),
-                ("true_rel_res", C.c_double), ("cond_est", C.c_double), ("t_solve_s", C.c_double)]
+                ("true_rel_res", C.c_double), ("cond_est", C.c_double), ("t_solve_s", C.c_double),
+                ("iters_first", C.c_int32), ("restarts", C.c_int32)]
 
 
 _lib = None

@@ -462,6 +462,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   pc->tilesI = offTI;
   pc->vecI = offVI;
   pc->maxNBI = maxNBI;
+  pc->maxwI = maxw;
   pc->d_sub = upload(pc->owned, pc->sub.data(), pc->sub.size(), s);
   int* d_info = dalloc<int>(tmp, (size_t)std::max(n_sub, 1) + 64);
   GN_HIP(hipMemsetAsync(d_info, 0, sizeof(int) * (n_sub + 64), s));
@@ -497,6 +498,10 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   }
   pc->d_t = dalloc<double>(pc->owned, (size_t)offVI);
   GN_HIP(hipMemsetAsync(pc->d_t, 0, sizeof(double) * offVI, s));
+  pc->d_z0 = dalloc<double>(pc->owned, TILE2);
+  pc->d_zf = dalloc<float>(pc->owned, TILE2);
+  GN_HIP(hipMemsetAsync(pc->d_z0, 0, sizeof(double) * TILE2, s));
+  GN_HIP(hipMemsetAsync(pc->d_zf, 0, sizeof(float) * TILE2, s));
   GN_HIP(hipStreamSynchronize(s));
   const double t1 = now_s();
   double t2 = t1, t3 = t1;
@@ -861,9 +866,9 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
     double tr = true_residual();
     // the recursive residual drifts from b - A x (attainable accuracy of CG):
     // restart from the current iterate with the true residual, at most twice
-    for (int restart = 0; restart < 2 && hs[S_BREAK] == 0.0 && hs[S_BB] > 0.0 && tr > hs[S_TOL2] &&
-                          iters < opts->maxit;
-         ++restart) {
+    int restarts = 0;
+    for (; restarts < 2 && hs[S_BREAK] == 0.0 && hs[S_BB] > 0.0 && tr > hs[S_TOL2] && iters < opts->maxit;
+         ++restarts) {
       gnk::sub_partial(n, p->d_z, p->d_q, p->d_r, p->d_part, s);   // r = b - A x
       gnk::finalize(p->d_part, nbr, OP_RESTART, scal, p->d_hist, opts->rtol, s);
       if (pc) {
@@ -896,6 +901,8 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
       R.rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
       R.true_rel_res = bb > 0 ? std::sqrt(tr / bb) : 0.0;
       R.t_solve_s = tsolve;
+      R.iters_first = first_iters;
+      R.restarts = restarts;
       // CG-Lanczos tridiagonal: T_ii = 1/a_i + b_{i-1}/a_{i-1}, T_{i,i+1} = sqrt(b_i)/a_i
       R.cond_est = 1.0;
       if (kit > 0) {

@@ -127,7 +127,9 @@ struct gn_precond {
   double* d_g = nullptr;     // coarse vectors (NH padded)
   double* d_u = nullptr;
   double* d_y = nullptr;
-  int maxNBI = 0;
+  int maxNBI = 0, maxwI = 0;
+  double* d_z0 = nullptr;    // one zero tile (FP64) read by masked prefetch slots
+  float* d_zf = nullptr;     // one zero tile (FP32)
   double trsv_bytes = 0.0, prolong_bytes = 0.0;
   double* d_Z = nullptr;     // L_H^-1 as dense tiles (NBH x NBH tiles, lower)
   int NBH = 0;

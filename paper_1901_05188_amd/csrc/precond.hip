@@ -156,6 +156,172 @@ __global__ __launch_bounds__(NT) void k_local_solve(const SubDesc* __restrict__ 
   }
 }
 
+// Barrier that orders LDS traffic only: outstanding global loads (the prefetch of
+// the next block row) stay in flight across it.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Pipelined variant of k_local_solve.  Thread (i, gq) owns, in every block row,
+// the 4w band entries of row i in columns 4gq..4gq+3 of each off-diagonal tile
+// (forward) or rows 4gq..4gq+3 of column i (backward), plus 4 entries of the
+// inverse diagonal tile; the next block row's entries are loaded into registers
+// while the current one is reduced, and only LDS-ordering barriers separate the
+// steps.  The subdomain vector lives in LDS with w zero tiles of padding on both
+// sides, so no step needs a bounds branch.  SP >= 4w register slots.
+template <typename FT, int NC, int SP, int G>
+__global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __restrict__ subs, int NX, int NY,
+                                                           const double* __restrict__ r, const FT* __restrict__ T,
+                                                           const FT* __restrict__ D, double* __restrict__ tvec,
+                                                           const double* __restrict__ Phi, double* __restrict__ g,
+                                                           const double* __restrict__ done, int padw,
+                                                           const FT* __restrict__ Z0) {
+  constexpr int NT = 32 * G;      // threads: 32 rows x G column groups
+  constexpr int CW = TILE / G;    // columns (forward) / rows (backward) per group
+  extern __shared__ double smem[];
+  __shared__ double red[G][TILE + 1];
+  __shared__ double red2[G][TILE + 1];
+  if (done && *done != 0.0) return;
+  const SubDesc& sd = subs[blockIdx.x];
+  const int NB = sd.NBI, w = sd.wI;
+  const int npad = NB * TILE;
+  double* vec = smem + padw * TILE;
+  for (int e = threadIdx.x; e < padw * TILE; e += NT) {
+    smem[e] = 0.0;
+    vec[npad + e] = 0.0;
+  }
+  for (int row = threadIdx.x; row < npad; row += NT) {
+    double v = 0.0;
+    if (row < sd.nI) {
+      int gn[3];
+      box_global_node(sd.ilo, sd.in_, sd.permI, row / NC, gn);
+      int64_t node = gn[0] + (int64_t)NX * (gn[1] + (int64_t)NY * gn[2]);
+      v = r[node * NC + row % NC];
+    }
+    vec[row] = v;
+  }
+  __syncthreads();
+  if (Phi && sd.m > 0) {
+    const double* ph = Phi + sd.offPhi;
+    for (int k0 = 0; k0 < sd.m; k0 += 8) {
+      double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int row = threadIdx.x; row < sd.nI; row += NT) {
+        double v = vec[row];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + q < sd.m) acc[q] += ph[(int64_t)row * sd.m + k0 + q] * v;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        double s = block_sum(acc[q], &red[0][0]);
+        if (threadIdx.x == 0 && k0 + q < sd.m) g[sd.coff + k0 + q] = s;
+      }
+    }
+    __syncthreads();
+  }
+  const int i = threadIdx.x % TILE, gq = threadIdx.x / TILE;
+  const FT* Tb = T + sd.offTI * TILE2;
+  const FT* Db = D + sd.offDI * TILE2;
+  const int ns = CW * w;
+  FT lv[SP], dv[CW], dn[CW];
+  // Slots u < CW*w address band entries; the rest read a shared zero tile, so
+  // every load is unconditional and the unrolled loops carry no branches.
+  // Single-buffer pipeline: the registers of row K are consumed, then reissued
+  // for the next row, whose loads overlap the three reduction barriers.
+  // ---- forward ----
+#define GN_LOAD_FWD(K_)                                                                  \
+  {                                                                                      \
+    const FT* rowp = Tb + (int64_t)(K_) * (w + 1) * TILE2;                               \
+    _Pragma("unroll") for (int u = 0; u < SP; ++u) {                                     \
+      int t = u / CW, c = CW * gq + (u % CW);                                            \
+      const FT* src = (u < ns) ? rowp + (t * TILE + c) * TILE + i : Z0 + i;              \
+      lv[u] = *src;                                                                      \
+    }                                                                                    \
+    const FT* dk = Db + (int64_t)(K_) * TILE2;                                           \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) dn[q] = dk[(CW * gq + q) * TILE + i]; \
+  }
+  GN_LOAD_FWD(0)
+  for (int K = 0; K < NB; ++K) {
+    const double* yw = vec + (K - w) * TILE + CW * gq;
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < SP; ++u) acc += (double)lv[u] * yw[(u / CW) * TILE + (u % CW)];
+#pragma unroll
+    for (int q = 0; q < CW; ++q) dv[q] = dn[q];
+    GN_LOAD_FWD(min(K + 1, NB - 1))
+    red[gq][i] = acc;
+    lds_barrier();
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      int c = CW * gq + q;
+      double s = vec[K * TILE + c];
+#pragma unroll
+      for (int g2 = 0; g2 < G; ++g2) s -= red[g2][c];
+      part += (double)dv[q] * s;
+    }
+    red2[gq][i] = part;
+    lds_barrier();
+    if (gq == 0) {
+      double y = 0.0;
+#pragma unroll
+      for (int g2 = 0; g2 < G; ++g2) y += red2[g2][i];
+      vec[K * TILE + i] = y;
+    }
+    lds_barrier();
+  }
+#undef GN_LOAD_FWD
+  // ---- backward ----
+#define GN_LOAD_BWD(K_)                                                                  \
+  {                                                                                      \
+    _Pragma("unroll") for (int u = 0; u < SP; ++u) {                                     \
+      int d = (u / CW) + 1, rr = CW * gq + (u % CW);                                     \
+      int kk = min((K_) + d, NB - 1);                                                    \
+      const FT* src = (u < ns) ? Tb + ((int64_t)kk * (w + 1) + (w - d)) * TILE2 + i * TILE + rr \
+                               : Z0 + i;                                                 \
+      lv[u] = *src;                                                                      \
+    }                                                                                    \
+    const FT* dk = Db + (int64_t)(K_) * TILE2;                                           \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) dn[q] = dk[i * TILE + CW * gq + q];   \
+  }
+  GN_LOAD_BWD(NB - 1)
+  for (int K = NB - 1; K >= 0; --K) {
+    const double* xw = vec + (K + 1) * TILE + CW * gq;
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < SP; ++u) acc += (double)lv[u] * xw[(u / CW) * TILE + (u % CW)];
+#pragma unroll
+    for (int q = 0; q < CW; ++q) dv[q] = dn[q];
+    GN_LOAD_BWD(max(K - 1, 0))
+    red[gq][i] = acc;
+    lds_barrier();
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      int rr = CW * gq + q;
+      double s = vec[K * TILE + rr];
+#pragma unroll
+      for (int g2 = 0; g2 < G; ++g2) s -= red[g2][rr];
+      part += (double)dv[q] * s;
+    }
+    red2[gq][i] = part;
+    lds_barrier();
+    if (gq == 0) {
+      double x = 0.0;
+#pragma unroll
+      for (int g2 = 0; g2 < G; ++g2) x += red2[g2][i];
+      vec[K * TILE + i] = x;
+    }
+    lds_barrier();
+  }
+#undef GN_LOAD_BWD
+  __syncthreads();
+  double* out = tvec + sd.offVI;
+  for (int row = threadIdx.x; row < npad; row += NT) out[row] = vec[row];
+}
+
 // u_K = sum_{J<=K} Z(K,J) g_J   (one workgroup per tile row)
 __global__ __launch_bounds__(NT) void k_coarse_fwd(int NBH, const double* __restrict__ Z,
                                                    const double* __restrict__ g, double* __restrict__ u,
@@ -267,11 +433,46 @@ void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, con
                  hipStream_t s) {
   const bool f32 = pc->local_prec == 32;
   const double* Phi = pc->NH > 0 ? pc->d_Phi : nullptr;
+  double bytes = pc->trsv_bytes;
+  GnProfScope prof(PROF_TRSV, bytes, s);
+  constexpr int PF_G = 16;                       // 512 threads: 32 rows x 16 groups of 2 columns
+  const int need_sp = (TILE / PF_G) * pc->maxwI;
+  // zero tiles on both sides of the LDS vector: covers every window read, which
+  // reaches at most SP / 2 <= maxw + 16 tiles past either end
+  const int padw = pc->maxwI + 16;
+  // register budget: up to SP = 32 slots (band of at most 16 tiles) fit without spills
+  if ((pc->maxNBI + 2 * padw) * TILE <= max_lds_doubles() && need_sp <= 32) {
+    size_t dynpf = (size_t)(pc->maxNBI + 2 * padw) * TILE * sizeof(double);
+#define GN_PF(FT, NC, SPV)                                                                        \
+  do {                                                                                            \
+    auto kfn = k_local_solve_pf<FT, NC, SPV, PF_G>;                                               \
+    GN_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,      \
+                               (int)dynpf));                                                      \
+    hipLaunchKernelGGL(kfn, dim3(pc->n_sub), dim3(32 * PF_G), dynpf, s, pc->d_sub, p->nn[0],       \
+                       p->nn[1], r,                                                               \
+                       (const FT*)(f32 ? (const void*)pc->d_LIf : (const void*)pc->d_LI),         \
+                       (const FT*)(f32 ? (const void*)pc->d_DIf : (const void*)pc->d_DI),         \
+                       pc->d_t, Phi, pc->d_g, done, padw,                                         \
+                       (const FT*)(f32 ? (const void*)pc->d_zf : (const void*)pc->d_z0));         \
+  } while (0)
+#define GN_PF_SP(FT, NC)                                  \
+  do {                                                    \
+    if (need_sp <= 16) GN_PF(FT, NC, 16);                 \
+    else GN_PF(FT, NC, 32);                               \
+  } while (0)
+    if (f32) {
+      if (p->nc == 3) GN_PF_SP(float, 3); else GN_PF_SP(float, 1);
+    } else {
+      if (p->nc == 3) GN_PF_SP(double, 3); else GN_PF_SP(double, 1);
+    }
+#undef GN_PF_SP
+#undef GN_PF
+    GN_CHECK_LAUNCH();
+    return;
+  }
   size_t lds = (size_t)pc->maxNBI * TILE * sizeof(double);
   bool ldsvec = pc->maxNBI * TILE <= max_lds_doubles();
   size_t dyn = ldsvec ? lds : 0;
-  double bytes = pc->trsv_bytes;
-  GnProfScope prof(PROF_TRSV, bytes, s);
 #define GN_LS(FT, NC, L)                                                                         \
   do {                                                                                           \
     auto kfn = k_local_solve<FT, NC, L>;                                                         \
