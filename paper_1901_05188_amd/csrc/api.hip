@@ -527,10 +527,13 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     for (int j = 0; j < n_sub; ++j)
       if (info[j]) throw gn_error{GN_ERR_NOT_SPD, "GenEO pencil of subdomain " + std::to_string(j) + " not definite"};
     const size_t vlen = (size_t)offVB * b;
-    double* V = dalloc<double>(tmp, vlen);
-    double* Z = dalloc<double>(tmp, vlen);
-    double* BV = dalloc<double>(tmp, vlen);
-    double* BZ = dalloc<double>(tmp, vlen);
+    // 64 doubles of tail padding: the matrix-core solve reads whole 16-column
+    // blocks past column b of the last row (those values are masked out)
+    double* V = dalloc<double>(tmp, vlen + 64);
+    double* Z = dalloc<double>(tmp, vlen + 64);
+    double* BV = dalloc<double>(tmp, vlen + 64);
+    double* BZ = dalloc<double>(tmp, vlen + 64);
+    for (double* t : {V, Z, BV, BZ}) GN_HIP(hipMemsetAsync(t + vlen, 0, sizeof(double) * 64, s));
     double* GP = dalloc<double>(tmp, (size_t)n_sub * b * b);
     double* GB = dalloc<double>(tmp, (size_t)n_sub * b * b);
     double* Y = dalloc<double>(tmp, (size_t)n_sub * b * b);
@@ -543,12 +546,14 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     std::vector<int> nwant(n_sub, 0);
     std::vector<double> worst_hist;
     bool converged = false;
-    gnk::eig_bapply(p, pc, b, maxNBB, V, BV, s);
+    double* BE = dalloc<double>(tmp, (size_t)offVB * 27 * nc);
+    gnk::eig_extract_b(p, pc, maxNBB, BE, s);
+    gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);
     for (int it = 0; it < eig_maxit; ++it) {
       // Z = P^-1 B V ; Rayleigh-Ritz on span(Z) ; V <- Z Y, BV <- (B Z) Y
       GN_HIP(hipMemcpyAsync(Z, BV, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
       gnk::eig_trsm(pc, b, LB, DB, Z, s);
-      gnk::eig_bapply(p, pc, b, maxNBB, Z, BZ, s);
+      gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
       gnk::eig_gram(pc, b, Z, BV, BZ, V, nu, GP, GB, res, s);
       gnk::eig_small(n_sub, b, GP, GB, Y, nu, nullptr, s);
       gnk::eig_vupdate(pc, b, maxNBB, Z, BZ, Y, V, BV, s);

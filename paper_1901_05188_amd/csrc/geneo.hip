@@ -37,227 +37,312 @@ __device__ inline double xpou(const SubDesc& sd, const PouAx& pa, const uint8_t*
   return 1.0 / (double)(pa.cnt0[gi] * pa.cnt1[gj] * pa.cnt2[gk]);
 }
 
+// B = X A_O X stored once per set-up in node-ELL form on the Ibar box:
+// BE[k][r], k = d*NC + c2 (27 lattice offsets x components), structure of
+// arrays over the padded rows of each subdomain (base offVB * 27 * NC).
 template <int NC>
-__global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs, int nex, int ney, int nez,
-                                               const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
-                                               PouAx pa, int b, const double* __restrict__ V,
-                                               double* __restrict__ out) {
+__global__ __launch_bounds__(NT) void k_extract_b(const SubDesc* __restrict__ subs, int nex, int ney,
+                                                  const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
+                                                  PouAx pa, double* __restrict__ BE) {
   const SubDesc& sd = subs[blockIdx.y];
-  int r = blockIdx.x * NT + threadIdx.x;
-  int npad = sd.NBB * TILE;
+  const int r = blockIdx.x * NT + threadIdx.x;
+  const int npad = sd.NBB * TILE;
   if (r >= npad) return;
-  const double* Vb = V + sd.offVB * b;
-  double* Ob = out + sd.offVB * b;
+  double* base = BE + sd.offVB * (27 * NC);
   if (r >= sd.nB) {
-    for (int col = 0; col < b; ++col) Ob[(int64_t)r * b + col] = 0.0;
+    for (int k = 0; k < 27 * NC; ++k) base[(int64_t)k * npad + r] = 0.0;
     return;
   }
   const int NX = nex + 1, NY = ney + 1;
-  int ln = r / NC, c = r % NC;
+  const int ln = r / NC, c = r % NC;
   int g[3];
   box_global_node(sd.blo, sd.bn, sd.permB, ln, g);
-  double xr = xpou(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
-  for (int col0 = 0; col0 < b; col0 += 8) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (xr != 0.0) {
-      for (int ez = max(g[2] - 1, sd.elo[2]); ez <= min(g[2], sd.ehi[2] - 1); ++ez)
-        for (int ey = max(g[1] - 1, sd.elo[1]); ey <= min(g[1], sd.ehi[1] - 1); ++ey)
-          for (int ex = max(g[0] - 1, sd.elo[0]); ex <= min(g[0], sd.ehi[0] - 1); ++ex) {
+  const double xr = xpou(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
+  for (int d = 0; d < 27; ++d) {
+    int h[3] = {g[0] + d % 3 - 1, g[1] + (d / 3) % 3 - 1, g[2] + d / 9 - 1};
+    double vO[NC];
+#pragma unroll
+    for (int c2 = 0; c2 < NC; ++c2) vO[c2] = 0.0;
+    bool in = xr != 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) in &= (h[a] >= sd.blo[a] && h[a] < sd.blo[a] + sd.bn[a]);
+    if (in) {
+      int lo[3], hi[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = max(max(g[a], h[a]) - 1, sd.elo[a]);
+        hi[a] = min(min(g[a], h[a]), sd.ehi[a] - 1);
+      }
+      for (int ez = lo[2]; ez <= hi[2]; ++ez)
+        for (int ey = lo[1]; ey <= hi[1]; ++ey)
+          for (int ex = lo[0]; ex <= hi[0]; ++ex) {
             if (pa.ec0[ex] * pa.ec1[ey] * pa.ec2[ez] < 2) continue;   // not in Omega_j^o
             int64_t e = ex + (int64_t)nex * (ey + (int64_t)ney * ez);
             int a1 = (g[0] - ex) + 2 * (g[1] - ey) + 4 * (g[2] - ez);
-            const double* row = Ke + e * (64 * NC * NC) + (int64_t)(a1 * NC + c) * (8 * NC);
-            for (int a2 = 0; a2 < 8; ++a2) {
-              int h0 = ex + (a2 & 1), h1 = ey + ((a2 >> 1) & 1), h2 = ez + ((a2 >> 2) & 1);
-              int ln2 = box_local_node(sd.blo, sd.bn, sd.permB, h0, h1, h2);
+            int a2 = (h[0] - ex) + 2 * (h[1] - ey) + 4 * (h[2] - ez);
+            const double* row = Ke + e * (64 * NC * NC) + (int64_t)(a1 * NC + c) * (8 * NC) + a2 * NC;
 #pragma unroll
-              for (int c2 = 0; c2 < NC; ++c2) {
-                double x2 = xpou(sd, pa, dir, NX, NY, NC, h0, h1, h2, c2);
-                if (x2 == 0.0) continue;
-                double kv = row[a2 * NC + c2] * x2;
-                const double* vr = Vb + (int64_t)(ln2 * NC + c2) * b + col0;
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                  if (col0 + q < b) acc[q] += kv * vr[q];
-              }
-            }
+            for (int c2 = 0; c2 < NC; ++c2) vO[c2] += row[c2];
           }
+#pragma unroll
+      for (int c2 = 0; c2 < NC; ++c2) vO[c2] *= xr * xpou(sd, pa, dir, NX, NY, NC, h[0], h[1], h[2], c2);
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (col0 + q < b) Ob[(int64_t)r * b + col0 + q] = xr * acc[q];
+    for (int c2 = 0; c2 < NC; ++c2) base[(int64_t)(d * NC + c2) * npad + r] = vO[c2];
   }
 }
 
-// ---------------------------------------------------------------------------
-// in-place V <- P^-1 V with the banded factor of P (forward then backward), b columns
-// ---------------------------------------------------------------------------
-// Each step stages one band tile and the matching 32 x b block of the right-hand
-// sides in LDS (coalesced loads), then every thread accumulates its outputs
-// (row i, columns cg + 8q) from LDS; accumulators live in registers (NQ fixed).
-__device__ inline void stage_tile(double (*sL)[TILE + 1], const double* __restrict__ src) {
-  for (int e = threadIdx.x; e < TILE2; e += NT) sL[e / TILE][e % TILE] = src[e];   // sL[col][row]
-}
-__device__ inline void stage_rows(double (*sY)[64 + 1], const double* __restrict__ src, int b) {
-  for (int e = threadIdx.x; e < TILE * b; e += NT) sY[e / b][e % b] = src[e];
+// out = B V for b columns: thread per (row, 8-column chunk)
+template <int NC>
+__global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs, const double* __restrict__ BE,
+                                               int b, const double* __restrict__ V, double* __restrict__ out) {
+  const SubDesc& sd = subs[blockIdx.y];
+  const int npad = sd.NBB * TILE;
+  const int nchunk = (b + 7) / 8;
+  const int tid = blockIdx.x * NT + threadIdx.x;
+  const int r = tid / nchunk, col0 = (tid % nchunk) * 8;
+  if (r >= npad) return;
+  const double* Vb = V + sd.offVB * b;
+  const double* base = BE + sd.offVB * (27 * NC);
+  // local node strides along the global axes
+  int st[3];
+  st[sd.permB[0]] = 1;
+  st[sd.permB[1]] = sd.bn[sd.permB[0]];
+  st[sd.permB[2]] = sd.bn[sd.permB[0]] * sd.bn[sd.permB[1]];
+  const int ln = r / NC;
+  const int nmax = sd.nB - 1;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int d = 0; d < 27; ++d) {
+    const int dn = (d % 3 - 1) * st[0] + ((d / 3) % 3 - 1) * st[1] + (d / 9 - 1) * st[2];
+#pragma unroll
+    for (int c2 = 0; c2 < NC; ++c2) {
+      double bv = base[(int64_t)(d * NC + c2) * npad + r];
+      int r2 = min(max((ln + dn) * NC + c2, 0), nmax);   // out-of-box neighbours have bv = 0
+      const double* vr = Vb + (int64_t)r2 * b + col0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (col0 + q < b) acc[q] += bv * vr[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (col0 + q < b) out[sd.offVB * b + (int64_t)r * b + col0 + q] = acc[q];
 }
 
-template <int NQ>
+// ---------------------------------------------------------------------------
+// in-place V <- P^-1 V with the banded factor of P (forward then backward), b <= 64
+// columns, on FP64 matrix cores.  Each block-row step is a dense contraction of
+// 32 x 32 band tiles with 32 x b right-hand-side blocks:
+//   forward   Y_K = Dinv_K (V_K - sum_t L(K,t) Y_{K-w+t})
+//   backward  X_K = Dinv_K^T (Y_K - sum_d L(K+d,K)^T X_{K+d})
+// v_mfma_f64_16x16x4f64 lane layout: A[l%16][l/16], B[l/16][l%16],
+// result item j of lane l = D[4j + l/16][l%16].  Wave wid owns output rows
+// 16*(wid&1).. and column blocks (wid>>1) and (wid>>1)+2.
+// ---------------------------------------------------------------------------
+typedef double gn_d4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(NT) void k_trsm_pencil(const SubDesc* __restrict__ subs, int b,
                                                     const double* __restrict__ T, const double* __restrict__ D,
                                                     double* __restrict__ V) {
-  __shared__ double sL[TILE][TILE + 1];
-  __shared__ double sY[TILE][64 + 1];
+  __shared__ double sS[TILE][64 + 1];
   const SubDesc& sd = subs[blockIdx.x];
   const int NB = sd.NBB, w = sd.wB;
   const double* Tb = T + sd.offTB * TILE2;
   const double* Db = D + sd.offDB * TILE2;
   double* Vb = V + sd.offVB * b;
-  const int i = threadIdx.x % TILE, cg = threadIdx.x / TILE;
-  // forward: Y_K = Dinv_K (V_K - sum_t L(K,t) Y_{K-w+t})
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int rb = (wid & 1) * 16;
+  const int ncb = (b + 15) / 16;
+  int colq[2];
+  bool okq[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    int cb = (wid >> 1) + 2 * q;
+    colq[q] = min(cb * 16 + lr, 63);
+    okq[q] = cb < ncb && cb * 16 + lr < b;
+  }
+  const bool anyq1 = (wid >> 1) + 2 < ncb;
+  // ---- forward ----
   for (int K = 0; K < NB; ++K) {
-    double acc[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    gn_d4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
     for (int t = 0; t < w; ++t) {
-      int J = K - w + t;
+      const int J = K - w + t;
       if (J < 0) continue;
-      __syncthreads();
-      stage_tile(sL, Tb + ((int64_t)K * (w + 1) + t) * TILE2);
-      stage_rows(sY, Vb + (int64_t)J * TILE * b, b);
-      __syncthreads();
-#pragma unroll 4
-      for (int c = 0; c < TILE; ++c) {
-        double l = sL[c][i];
+      const double* tile = Tb + ((int64_t)K * (w + 1) + t) * TILE2;
+      const double* yj = Vb + (int64_t)J * TILE * b;
+      // all operand loads of the tile first (unconditional: the right-hand-side
+      // buffer carries 64 doubles of padding), then the MFMAs
+      double av[8], bv0[8], bv1[8];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] += l * sY[c][min(cg + 8 * q, 63)];
+      for (int ks = 0; ks < 8; ++ks) {
+        const int k = 4 * ks + lk;
+        av[ks] = tile[k * TILE + rb + lr];
+        bv0[ks] = yj[k * b + colq[0]];
+        bv1[ks] = yj[k * b + colq[1]];
+      }
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], okq[0] ? bv0[ks] : 0.0, acc[0], 0, 0, 0);
+        if (anyq1)
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], okq[1] ? bv1[ks] : 0.0, acc[1], 0, 0, 0);
       }
     }
-    __syncthreads();
-    stage_tile(sL, Db + (int64_t)K * TILE2);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      int col = cg + 8 * q;
-      if (col < b) sY[i][col] = Vb[(int64_t)(K * TILE + i) * b + col] - acc[q];
-    }
-    __syncthreads();
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      int col = cg + 8 * q;
-      double s = 0.0;
-#pragma unroll 8
-      for (int c = 0; c < TILE; ++c) s += sL[c][i] * sY[c][min(col, 63)];
-      if (col < b) Vb[(int64_t)(K * TILE + i) * b + col] = s;
+      for (int j = 0; j < 4; ++j) {
+        int row = rb + 4 * j + lk;
+        if (okq[q]) sS[row][colq[q]] = Vb[(int64_t)(K * TILE + row) * b + colq[q]] - acc[q][j];
+      }
+    __syncthreads();
+    const double* dk = Db + (int64_t)K * TILE2;
+    gn_d4 o[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int k = 4 * ks + lk;
+      double a = dk[k * TILE + rb + lr];
+      double s0 = sS[k][colq[0]], s1 = sS[k][colq[1]];
+      o[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, okq[0] ? s0 : 0.0, o[0], 0, 0, 0);
+      if (anyq1) o[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, okq[1] ? s1 : 0.0, o[1], 0, 0, 0);
     }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int row = rb + 4 * j + lk;
+        if (okq[q]) Vb[(int64_t)(K * TILE + row) * b + colq[q]] = o[q][j];
+      }
     __threadfence_block();
+    __syncthreads();
   }
-  // backward: X_K = Dinv_K^T (Y_K - sum_d L(K+d, K)^T X_{K+d})
+  // ---- backward ----
   for (int K = NB - 1; K >= 0; --K) {
-    double acc[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    gn_d4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
     for (int d = 1; d <= w; ++d) {
       if (K + d >= NB) break;
-      __syncthreads();
-      stage_tile(sL, Tb + ((int64_t)(K + d) * (w + 1) + (w - d)) * TILE2);
-      stage_rows(sY, Vb + (int64_t)(K + d) * TILE * b, b);
-      __syncthreads();
-#pragma unroll 4
-      for (int rr = 0; rr < TILE; ++rr) {
-        double l = sL[i][rr];   // L(rr, i) of block (K+d, K)
+      const double* tile = Tb + ((int64_t)(K + d) * (w + 1) + (w - d)) * TILE2;
+      const double* xj = Vb + (int64_t)(K + d) * TILE * b;
+      double av[8], bv0[8], bv1[8];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] += l * sY[rr][min(cg + 8 * q, 63)];
+      for (int ks = 0; ks < 8; ++ks) {
+        const int k = 4 * ks + lk;
+        av[ks] = tile[(rb + lr) * TILE + k];   // L(k, row) of block (K+d, K): transposed operand
+        bv0[ks] = xj[k * b + colq[0]];
+        bv1[ks] = xj[k * b + colq[1]];
+      }
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], okq[0] ? bv0[ks] : 0.0, acc[0], 0, 0, 0);
+        if (anyq1)
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], okq[1] ? bv1[ks] : 0.0, acc[1], 0, 0, 0);
       }
     }
-    __syncthreads();
-    stage_tile(sL, Db + (int64_t)K * TILE2);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      int col = cg + 8 * q;
-      if (col < b) sY[i][col] = Vb[(int64_t)(K * TILE + i) * b + col] - acc[q];
-    }
-    __syncthreads();
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      int col = cg + 8 * q;
-      double s = 0.0;
-#pragma unroll 8
-      for (int rr = 0; rr < TILE; ++rr) s += sL[i][rr] * sY[rr][min(col, 63)];
-      if (col < b) Vb[(int64_t)(K * TILE + i) * b + col] = s;
+      for (int j = 0; j < 4; ++j) {
+        int row = rb + 4 * j + lk;
+        if (okq[q]) sS[row][colq[q]] = Vb[(int64_t)(K * TILE + row) * b + colq[q]] - acc[q][j];
+      }
+    __syncthreads();
+    const double* dk = Db + (int64_t)K * TILE2;
+    gn_d4 o[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int k = 4 * ks + lk;
+      double a = dk[(rb + lr) * TILE + k];         // Dinv(k, row): transposed operand
+      double s0 = sS[k][colq[0]], s1 = sS[k][colq[1]];
+      o[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, okq[0] ? s0 : 0.0, o[0], 0, 0, 0);
+      if (anyq1) o[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, okq[1] ? s1 : 0.0, o[1], 0, 0, 0);
     }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int row = rb + 4 * j + lk;
+        if (okq[q]) Vb[(int64_t)(K * TILE + row) * b + colq[q]] = o[q][j];
+      }
     __threadfence_block();
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Gram matrices  GP = Z^T (B V) = Z^T P Z,  GB = Z^T (B Z);  residuals
-// res_k = ||Z_k - nu_k V_k||^2, zz_k = ||Z_k||^2   (one workgroup per subdomain)
+// Gram matrices GP = Z^T (B V) = Z^T P Z and GB = Z^T (B Z) on FP64 matrix
+// cores, and the Ritz residuals res_k = ||Z_k - nu_k V_k||^2, zz_k = ||Z_k||^2.
+// One workgroup per subdomain streams its rows four at a time (the K dimension
+// of v_mfma_f64_16x16x4f64); wave wid owns the 16-row block kb = wid of both
+// Gram matrices (column blocks 0..3).  Padding rows are zero in Z, BV and BZ;
+// columns past b only feed output entries that are not stored.
 // ---------------------------------------------------------------------------
-template <int NPQ>   // ceil(b*b / NT) output pairs per thread
 __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, int b,
                                              const double* __restrict__ Z, const double* __restrict__ BV,
                                              const double* __restrict__ BZ, const double* __restrict__ V,
                                              const double* __restrict__ nu, double* __restrict__ GP,
                                              double* __restrict__ GB, double* __restrict__ res) {
-  constexpr int R = 8;
-  __shared__ double sZ[R][64], sBV[R][64], sBZ[R][64], sV[R][64];
+  __shared__ double sres[4][64], szz[4][64];
   const SubDesc& sd = subs[blockIdx.x];
   const int64_t base = sd.offVB * b;
-  const int n = sd.nB;
-  const int np = b * b;
-  double aP[NPQ], aB[NPQ];
+  const int nrows = sd.NBB * TILE;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int ncb = (b + 15) / 16;
+  const bool active = wid < ncb;
+  const int acol = min(wid * 16 + lr, 63);
+  gn_d4 gp[4], gb[4];
 #pragma unroll
-  for (int q = 0; q < NPQ; ++q) aP[q] = aB[q] = 0.0;
+  for (int q = 0; q < 4; ++q) gp[q] = gb[q] = gn_d4{0, 0, 0, 0};
+  if (active) {
+    for (int r0 = 0; r0 < nrows; r0 += 4) {
+      const int64_t ro = base + (int64_t)(r0 + lk) * b;
+      double a = Z[ro + acol];
+      double bvv[4], bzv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int col = min(q * 16 + lr, 63);
+        bvv[q] = BV[ro + col];
+        bzv[q] = BZ[ro + col];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q < ncb) {
+          gp[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bvv[q], gp[q], 0, 0, 0);
+          gb[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bzv[q], gb[q], 0, 0, 0);
+        }
+      }
+    }
+    double* gpo = GP + (int64_t)blockIdx.x * b * b;
+    double* gbo = GB + (int64_t)blockIdx.x * b * b;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int row = wid * 16 + 4 * j + lk, col = q * 16 + lr;
+        if (q < ncb && row < b && col < b) {
+          gpo[row * b + col] = gp[q][j];
+          gbo[row * b + col] = gb[q][j];
+        }
+      }
+  }
+  // residuals: lane = column, waves split the rows
+  const double nk = lane < b ? nu[(int64_t)blockIdx.x * b + lane] : 0.0;
   double rs = 0.0, zz = 0.0;
-  const double* nus = nu + (int64_t)blockIdx.x * b;
-  for (int r0 = 0; r0 < n; r0 += R) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < R * b; e += NT) {
-      int rr = e / b, col = e % b;
-      int row = r0 + rr;
-      bool ok = row < n;
-      int64_t o = base + (int64_t)row * b + col;
-      sZ[rr][col] = ok ? Z[o] : 0.0;
-      sBV[rr][col] = ok ? BV[o] : 0.0;
-      sBZ[rr][col] = ok ? BZ[o] : 0.0;
-      sV[rr][col] = ok ? V[o] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int rr = 0; rr < R; ++rr) {
-#pragma unroll
-      for (int q = 0; q < NPQ; ++q) {
-        int pidx = min(threadIdx.x + q * NT, np - 1);
-        int k = pidx / b, l = pidx % b;
-        double zk = sZ[rr][k];
-        aP[q] += zk * sBV[rr][l];
-        aB[q] += zk * sBZ[rr][l];
-      }
-    }
-    if (threadIdx.x < b) {
-      int k = threadIdx.x;
-      double nk = nus[k];
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr) {
-        double d = sZ[rr][k] - nk * sV[rr][k];
-        rs += d * d;
-        zz += sZ[rr][k] * sZ[rr][k];
-      }
+  if (lane < b) {
+    for (int r = wid; r < sd.nB; r += 4) {
+      double z = Z[base + (int64_t)r * b + lane];
+      double d = z - nk * V[base + (int64_t)r * b + lane];
+      rs += d * d;
+      zz += z * z;
     }
   }
-  double* gp = GP + (int64_t)blockIdx.x * np;
-  double* gb = GB + (int64_t)blockIdx.x * np;
-#pragma unroll
-  for (int q = 0; q < NPQ; ++q) {
-    int pidx = threadIdx.x + q * NT;
-    if (pidx < np) {
-      gp[pidx] = aP[q];
-      gb[pidx] = aB[q];
-    }
-  }
+  sres[wid][lane] = rs;
+  szz[wid][lane] = zz;
+  __syncthreads();
   if (threadIdx.x < b) {
-    res[(int64_t)blockIdx.x * 2 * b + threadIdx.x] = rs;
-    res[(int64_t)blockIdx.x * 2 * b + b + threadIdx.x] = zz;
+    int k = threadIdx.x;
+    res[(int64_t)blockIdx.x * 2 * b + k] = sres[0][k] + sres[1][k] + sres[2][k] + sres[3][k];
+    res[(int64_t)blockIdx.x * 2 * b + b + k] = szz[0][k] + szz[1][k] + szz[2][k] + szz[3][k];
   }
 }
 
@@ -797,42 +882,38 @@ void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s
   GN_CHECK_LAUNCH();
 }
 
-void eig_bapply(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, const double* V,
-                double* out, hipStream_t s) {
+void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double* BE, hipStream_t s) {
   dim3 grid((maxNBB * TILE + NT - 1) / NT, pc->n_sub);
   if (p->nc == 3)
-    hipLaunchKernelGGL(k_bapply<3>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->ne[2],
-                       p->d_Ke, p->d_dir, pou_axes(pc), b, V, out);
+    hipLaunchKernelGGL(k_extract_b<3>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke,
+                       p->d_dir, pou_axes(pc), BE);
   else
-    hipLaunchKernelGGL(k_bapply<1>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->ne[2],
-                       p->d_Ke, p->d_dir, pou_axes(pc), b, V, out);
+    hipLaunchKernelGGL(k_extract_b<1>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke,
+                       p->d_dir, pou_axes(pc), BE);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int b, int maxNBB,
+                const double* V, double* out, hipStream_t s) {
+  const int nchunk = (b + 7) / 8;
+  dim3 grid((maxNBB * TILE * nchunk + NT - 1) / NT, pc->n_sub);
+  if (p->nc == 3)
+    hipLaunchKernelGGL(k_bapply<3>, grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out);
+  else
+    hipLaunchKernelGGL(k_bapply<1>, grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out);
   GN_CHECK_LAUNCH();
 }
 
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, double* V, hipStream_t s) {
-  const int nq = (b + 7) / 8;
-#define GN_TRSM(Q) \
-  case Q: hipLaunchKernelGGL(k_trsm_pencil<Q>, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, T, D, V); break;
-  switch (nq) {
-    GN_TRSM(1) GN_TRSM(2) GN_TRSM(3) GN_TRSM(4) GN_TRSM(5) GN_TRSM(6) GN_TRSM(7) GN_TRSM(8)
-    default: throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
-  }
-#undef GN_TRSM
+  if (b > 64) throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
+  hipLaunchKernelGGL(k_trsm_pencil, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, T, D, V);
   GN_CHECK_LAUNCH();
 }
 
 void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, const double* BZ,
               const double* V, const double* nu, double* GP, double* GB, double* res, hipStream_t s) {
-  const int need = (b * b + NT - 1) / NT;
-#define GN_GRAM(Q)                                                                                   \
-  hipLaunchKernelGGL(k_gram<Q>, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, Z, BV, BZ, V, nu, GP, \
-                     GB, res)
-  if (need <= 1) GN_GRAM(1);
-  else if (need <= 2) GN_GRAM(2);
-  else if (need <= 4) GN_GRAM(4);
-  else if (need <= 8) GN_GRAM(8);
-  else GN_GRAM(16);
-#undef GN_GRAM
+  hipLaunchKernelGGL(k_gram, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, Z, BV, BZ, V, nu, GP, GB,
+                     res);
   GN_CHECK_LAUNCH();
 }
 

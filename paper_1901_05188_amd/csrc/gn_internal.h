@@ -181,8 +181,9 @@ void prolong(const gn_problem* p, const gn_precond* pc, const double* r, double*
              const double* done, hipStream_t s);
 // geneo.hip
 void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s);
-void eig_bapply(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, const double* V,
-                double* out, hipStream_t s);
+void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double* BE, hipStream_t s);
+void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int b, int maxNBB,
+                const double* V, double* out, hipStream_t s);
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, double* V, hipStream_t s);
 void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, const double* BZ,
               const double* V, const double* nu, double* GP, double* GB, double* res, hipStream_t s);
