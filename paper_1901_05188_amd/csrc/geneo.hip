@@ -112,6 +112,7 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
   const int ln = r / NC;
   const int nmax = sd.nB - 1;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 9
   for (int d = 0; d < 27; ++d) {
     const int dn = (d % 3 - 1) * st[0] + ((d / 3) % 3 - 1) * st[1] + (d / 9 - 1) * st[2];
 #pragma unroll
@@ -132,140 +133,120 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
 // ---------------------------------------------------------------------------
 // in-place V <- P^-1 V with the banded factor of P (forward then backward), b <= 64
 // columns, on FP64 matrix cores.  Each block-row step is a dense contraction of
-// 32 x 32 band tiles with 32 x b right-hand-side blocks:
+// 32 x 32 band tiles with 32 x 16 right-hand-side blocks:
 //   forward   Y_K = Dinv_K (V_K - sum_t L(K,t) Y_{K-w+t})
 //   backward  X_K = Dinv_K^T (Y_K - sum_d L(K+d,K)^T X_{K+d})
+// The columns are independent, so workgroup (j, cb) solves columns cb*16..+15 of
+// subdomain j with two waves (rows 0..15 and 16..31).  The linear workgroup id
+// j + n_sub*cb keeps every column block of a subdomain on one XCD (n_sub is
+// padded to a multiple of 8 by the launcher), so the factor stream is shared
+// through that XCD's L2.
 // v_mfma_f64_16x16x4f64 lane layout: A[l%16][l/16], B[l/16][l%16],
-// result item j of lane l = D[4j + l/16][l%16].  Wave wid owns output rows
-// 16*(wid&1).. and column blocks (wid>>1) and (wid>>1)+2.
+// result item j of lane l = D[4j + l/16][l%16].
 // ---------------------------------------------------------------------------
 typedef double gn_d4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(NT) void k_trsm_pencil(const SubDesc* __restrict__ subs, int b,
-                                                    const double* __restrict__ T, const double* __restrict__ D,
-                                                    double* __restrict__ V) {
-  __shared__ double sS[TILE][64 + 1];
-  const SubDesc& sd = subs[blockIdx.x];
+__global__ __launch_bounds__(128) void k_trsm_pencil(const SubDesc* __restrict__ subs, int n_sub, int b,
+                                                     const double* __restrict__ T, const double* __restrict__ D,
+                                                     double* __restrict__ V) {
+  __shared__ double sS[TILE][16 + 1];
+  const int j = blockIdx.x, cb = blockIdx.y;
+  if (j >= n_sub) return;
+  const SubDesc& sd = subs[j];
   const int NB = sd.NBB, w = sd.wB;
   const double* Tb = T + sd.offTB * TILE2;
   const double* Db = D + sd.offDB * TILE2;
   double* Vb = V + sd.offVB * b;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
-  const int rb = (wid & 1) * 16;
-  const int ncb = (b + 15) / 16;
-  int colq[2];
-  bool okq[2];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    int cb = (wid >> 1) + 2 * q;
-    colq[q] = min(cb * 16 + lr, 63);
-    okq[q] = cb < ncb && cb * 16 + lr < b;
-  }
-  const bool anyq1 = (wid >> 1) + 2 < ncb;
+  const int rb = wid * 16;
+  const int col = cb * 16 + lr;          // < 64: the buffers carry 64 doubles of tail padding
+  const bool ok = col < b;
+  gn_d4 acc[4];
+#define GN_ZERO4(X_) _Pragma("unroll") for (int u = 0; u < 4; ++u) X_[u] = gn_d4{0, 0, 0, 0};
   // ---- forward ----
   for (int K = 0; K < NB; ++K) {
-    gn_d4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-    for (int t = 0; t < w; ++t) {
-      const int J = K - w + t;
-      if (J < 0) continue;
+    GN_ZERO4(acc)
+    for (int t = max(0, w - K); t < w; ++t) {
       const double* tile = Tb + ((int64_t)K * (w + 1) + t) * TILE2;
-      const double* yj = Vb + (int64_t)J * TILE * b;
-      // all operand loads of the tile first (unconditional: the right-hand-side
-      // buffer carries 64 doubles of padding), then the MFMAs
-      double av[8], bv0[8], bv1[8];
+      const double* yj = Vb + (int64_t)(K - w + t) * TILE * b;
+      double av[8], bv[8];
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
         const int k = 4 * ks + lk;
         av[ks] = tile[k * TILE + rb + lr];
-        bv0[ks] = yj[k * b + colq[0]];
-        bv1[ks] = yj[k * b + colq[1]];
+        bv[ks] = yj[k * b + col];
       }
 #pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], okq[0] ? bv0[ks] : 0.0, acc[0], 0, 0, 0);
-        if (anyq1)
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], okq[1] ? bv1[ks] : 0.0, acc[1], 0, 0, 0);
-      }
+      for (int ks = 0; ks < 8; ++ks)
+        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], ok ? bv[ks] : 0.0, acc[ks & 3], 0, 0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int row = rb + 4 * j + lk;
-        if (okq[q]) sS[row][colq[q]] = Vb[(int64_t)(K * TILE + row) * b + colq[q]] - acc[q][j];
-      }
+    for (int i = 0; i < 4; ++i) {
+      int row = rb + 4 * i + lk;
+      double a4 = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+      sS[row][lr] = ok ? Vb[(int64_t)(K * TILE + row) * b + col] - a4 : 0.0;
+    }
     __syncthreads();
     const double* dk = Db + (int64_t)K * TILE2;
-    gn_d4 o[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    GN_ZERO4(acc)
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       const int k = 4 * ks + lk;
-      double a = dk[k * TILE + rb + lr];
-      double s0 = sS[k][colq[0]], s1 = sS[k][colq[1]];
-      o[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, okq[0] ? s0 : 0.0, o[0], 0, 0, 0);
-      if (anyq1) o[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, okq[1] ? s1 : 0.0, o[1], 0, 0, 0);
+      acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dk[k * TILE + rb + lr], sS[k][lr], acc[ks & 3], 0, 0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int row = rb + 4 * j + lk;
-        if (okq[q]) Vb[(int64_t)(K * TILE + row) * b + colq[q]] = o[q][j];
-      }
+    for (int i = 0; i < 4; ++i) {
+      int row = rb + 4 * i + lk;
+      double o4 = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+      if (ok) Vb[(int64_t)(K * TILE + row) * b + col] = o4;
+    }
     __threadfence_block();
     __syncthreads();
   }
   // ---- backward ----
   for (int K = NB - 1; K >= 0; --K) {
-    gn_d4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-    for (int d = 1; d <= w; ++d) {
-      if (K + d >= NB) break;
+    GN_ZERO4(acc)
+    const int dmax = min(w, NB - 1 - K);
+    for (int d = 1; d <= dmax; ++d) {
       const double* tile = Tb + ((int64_t)(K + d) * (w + 1) + (w - d)) * TILE2;
       const double* xj = Vb + (int64_t)(K + d) * TILE * b;
-      double av[8], bv0[8], bv1[8];
+      double av[8], bv[8];
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
         const int k = 4 * ks + lk;
         av[ks] = tile[(rb + lr) * TILE + k];   // L(k, row) of block (K+d, K): transposed operand
-        bv0[ks] = xj[k * b + colq[0]];
-        bv1[ks] = xj[k * b + colq[1]];
+        bv[ks] = xj[k * b + col];
       }
 #pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], okq[0] ? bv0[ks] : 0.0, acc[0], 0, 0, 0);
-        if (anyq1)
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], okq[1] ? bv1[ks] : 0.0, acc[1], 0, 0, 0);
-      }
+      for (int ks = 0; ks < 8; ++ks)
+        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], ok ? bv[ks] : 0.0, acc[ks & 3], 0, 0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int row = rb + 4 * j + lk;
-        if (okq[q]) sS[row][colq[q]] = Vb[(int64_t)(K * TILE + row) * b + colq[q]] - acc[q][j];
-      }
+    for (int i = 0; i < 4; ++i) {
+      int row = rb + 4 * i + lk;
+      double a4 = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+      sS[row][lr] = ok ? Vb[(int64_t)(K * TILE + row) * b + col] - a4 : 0.0;
+    }
     __syncthreads();
     const double* dk = Db + (int64_t)K * TILE2;
-    gn_d4 o[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    GN_ZERO4(acc)
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       const int k = 4 * ks + lk;
-      double a = dk[(rb + lr) * TILE + k];         // Dinv(k, row): transposed operand
-      double s0 = sS[k][colq[0]], s1 = sS[k][colq[1]];
-      o[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, okq[0] ? s0 : 0.0, o[0], 0, 0, 0);
-      if (anyq1) o[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, okq[1] ? s1 : 0.0, o[1], 0, 0, 0);
+      acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dk[(rb + lr) * TILE + k], sS[k][lr], acc[ks & 3], 0, 0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int row = rb + 4 * j + lk;
-        if (okq[q]) Vb[(int64_t)(K * TILE + row) * b + colq[q]] = o[q][j];
-      }
+    for (int i = 0; i < 4; ++i) {
+      int row = rb + 4 * i + lk;
+      double o4 = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+      if (ok) Vb[(int64_t)(K * TILE + row) * b + col] = o4;
+    }
     __threadfence_block();
     __syncthreads();
   }
+#undef GN_ZERO4
 }
 
 // ---------------------------------------------------------------------------
@@ -285,7 +266,8 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
   const SubDesc& sd = subs[blockIdx.x];
   const int64_t base = sd.offVB * b;
   const int nrows = sd.NBB * TILE;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   const int ncb = (b + 15) / 16;
   const bool active = wid < ncb;
@@ -294,23 +276,30 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
 #pragma unroll
   for (int q = 0; q < 4; ++q) gp[q] = gb[q] = gn_d4{0, 0, 0, 0};
   if (active) {
-    for (int r0 = 0; r0 < nrows; r0 += 4) {
-      const int64_t ro = base + (int64_t)(r0 + lk) * b;
-      double a = Z[ro + acol];
-      double bvv[4], bzv[4];
+    // rows streamed 16 at a time (4 MFMA K-steps), all loads of a step issued first;
+    // padded row counts are multiples of 32
+    for (int r0 = 0; r0 < nrows; r0 += 16) {
+      double a[4], bvv[4][4], bzv[4][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int col = min(q * 16 + lr, 63);
-        bvv[q] = BV[ro + col];
-        bzv[q] = BZ[ro + col];
-      }
+      for (int u = 0; u < 4; ++u) {
+        const int64_t ro = base + (int64_t)(r0 + 4 * u + lk) * b;
+        a[u] = Z[ro + acol];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q < ncb) {
-          gp[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bvv[q], gp[q], 0, 0, 0);
-          gb[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bzv[q], gb[q], 0, 0, 0);
+        for (int q = 0; q < 4; ++q) {
+          int col = min(q * 16 + lr, 63);
+          bvv[u][q] = BV[ro + col];
+          bzv[u][q] = BZ[ro + col];
         }
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q < ncb) {
+            gp[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bvv[u][q], gp[q], 0, 0, 0);
+            gb[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bzv[u][q], gb[q], 0, 0, 0);
+          }
+        }
     }
     double* gpo = GP + (int64_t)blockIdx.x * b * b;
     double* gbo = GB + (int64_t)blockIdx.x * b * b;
@@ -906,7 +895,9 @@ void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int
 
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, double* V, hipStream_t s) {
   if (b > 64) throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
-  hipLaunchKernelGGL(k_trsm_pencil, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, T, D, V);
+  // grid.x padded to a multiple of 8 so (j, cb) and (j, cb') share an XCD
+  const int gx = (pc->n_sub + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_trsm_pencil, dim3(gx, (b + 15) / 16), dim3(128), 0, s, pc->d_sub, pc->n_sub, b, T, D, V);
   GN_CHECK_LAUNCH();
 }
 
