@@ -166,6 +166,11 @@ typedef struct gn_solve_opts {
   double rtol;          /* stop when ||r||_2 <= rtol ||b||_2                   */
   int32_t maxit;
   int32_t check_every;  /* iterations per host convergence check (0 = 8)       */
+  int32_t sequential;   /* nrhs > 1: 0 = batches of up to 16 columns share every
+                           launch (one pass over each local factor per iteration
+                           for the whole batch, per-column alpha, beta and
+                           stopping); 1 = the columns are solved one after
+                           another.  Ignored for nrhs = 1.                      */
 } gn_solve_opts;
 
 typedef struct gn_solve_report {
@@ -181,7 +186,13 @@ typedef struct gn_solve_report {
 
 /* Solve A x = b by PCG with x0 = 0 for nrhs columns (device pointers, free
  * numbering, column-major, leading dim ld).  pc = NULL runs plain CG.
- * reports (host, nrhs entries) may be NULL. */
+ * reports (host, nrhs entries) may be NULL.
+ * Each column runs its own CG recurrence (Section 3.1, eqn:KrylovSubspace):
+ * its own alpha, beta, stopping test and restarts, so a column's iterates do
+ * not depend on the other columns of its batch beyond rounding (batched
+ * columns use the MFMA block solves, single columns the scalar sweeps).
+ * Returns GN_WARN_MAXIT if a column stopped at maxit, GN_ERR_BREAKDOWN if a
+ * column met p^T A p <= 0; the other columns are still solved. */
 gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev, double* x_dev,
                    int32_t nrhs, int64_t ld, const gn_solve_opts* opts, void* stream,
                    gn_solve_report* reports);

@@ -713,6 +713,16 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     }
     pc->trsv_bytes = tb;
     pc->prolong_bytes = pb + (double)p->n_dof * 8.0 * 2.0;
+    // batched: the band is read once for all 16 columns; the gather writes the
+    // 16-wide local vectors, which both sweeps read and write once more
+    double tbm = 0.0;
+    for (const SubDesc& sd : pc->sub) {
+      double tiles = 0.0;
+      for (int K = 0; K < sd.NBI; ++K) tiles += std::min(K, sd.wI);
+      tbm += 2.0 * (tiles + sd.NBI) * TILE2 * fb + (double)sd.NBI * TILE * 16.0 * 8.0 * 5.0 +
+             (double)sd.nI * sd.m * 8.0;
+    }
+    pc->trsv_bytes_mc = tbm;
   }
   int64_t hb = 0;
   hb += (int64_t)pc->tilesI * TILE2 * (pc->local_prec == 32 ? 4 : 8);
@@ -787,6 +797,184 @@ extern "C" gn_status gn_precond_apply(gn_precond* pc, const double* r_dev, doubl
 // PCG
 // ---------------------------------------------------------------------------
 
+// CG-Lanczos tridiagonal of the first kit steps: T_ii = 1/a_i + b_{i-1}/a_{i-1},
+// T_{i,i+1} = sqrt(b_i)/a_i; returns its extreme eigenvalue ratio
+static double cond_from_hist(const double* hist, int kit) {
+  if (kit <= 0) return 1.0;
+  std::vector<double> d(kit), e(std::max(kit - 1, 0));
+  for (int i = 0; i < kit; ++i) {
+    double a = hist[2 * i];
+    d[i] = 1.0 / a + (i > 0 ? hist[2 * (i - 1) + 1] / hist[2 * (i - 1)] : 0.0);
+    if (i + 1 < kit) e[i] = std::sqrt(std::max(hist[2 * i + 1], 0.0)) / a;
+  }
+  double lo, hi;
+  tridiag_extremes(d, e, &lo, &hi);
+  return lo > 0 ? hi / lo : INFINITY;
+}
+
+// batched workspace for up to 16 columns, allocated on first use
+static void ensure_batch_workspace(gn_problem* p, gn_precond* pc, int maxit, hipStream_t s) {
+  const int KC = gnk::mc_width();
+  const int64_t n = p->n_dof;
+  if (!p->d_Xm) {
+    p->d_Xm = dalloc<double>(p->owned, (size_t)n * KC);
+    p->d_Rm = dalloc<double>(p->owned, (size_t)n * KC);
+    p->d_Pm = dalloc<double>(p->owned, (size_t)n * KC);
+    p->d_Qm = dalloc<double>(p->owned, (size_t)n * KC);
+    p->d_Zm = dalloc<double>(p->owned, (size_t)n * KC);
+    for (double* v : {p->d_Xm, p->d_Rm, p->d_Pm, p->d_Qm, p->d_Zm})
+      GN_HIP(hipMemsetAsync(v, 0, sizeof(double) * n * KC, s));
+    p->pstride_m = std::max(std::max(gnk::spmv_blocks(p), gnk::reduce_blocks()), gnk::prolong_blocks(p));
+    p->d_partm = dalloc<double>(p->owned, (size_t)p->pstride_m * KC);
+    p->d_scalm = dalloc<double>(p->owned, (size_t)S_N * KC);
+  }
+  if (p->histm_stride < 2 * maxit + 2) {
+    if (p->d_histm) {
+      (void)hipFree(p->d_histm);
+      p->owned.erase(std::remove(p->owned.begin(), p->owned.end(), (void*)p->d_histm), p->owned.end());
+    }
+    p->histm_stride = 2 * maxit + 2;
+    p->d_histm = dalloc<double>(p->owned, (size_t)p->histm_stride * KC);
+  }
+  if (pc && !pc->d_tm) {
+    pc->d_tm = dalloc<double>(pc->owned, (size_t)pc->vecI * KC);
+    GN_HIP(hipMemsetAsync(pc->d_tm, 0, sizeof(double) * pc->vecI * KC, s));
+    const size_t nh = (size_t)std::max(pc->NBH, 1) * TILE * KC;
+    pc->d_gm = dalloc<double>(pc->owned, nh);
+    pc->d_um = dalloc<double>(pc->owned, nh);
+    pc->d_ym = dalloc<double>(pc->owned, nh);
+    for (double* v : {pc->d_gm, pc->d_um, pc->d_ym}) GN_HIP(hipMemsetAsync(v, 0, sizeof(double) * nh, s));
+  }
+}
+
+// k <= 16 columns of one batch: each column runs its own CG recurrence, the
+// launches are shared.  Same steps, stopping test and restart policy as the
+// single-column path in gn_solve.
+static gn_status solve_batch(gn_problem* p, gn_precond* pc, const double* b_dev, double* x_dev, int c0,
+                             int k, int64_t ld, const gn_solve_opts* opts, hipStream_t s,
+                             gn_solve_report* reports) {
+  ensure_batch_workspace(p, pc, opts->maxit, s);
+  const int64_t n = p->n_dof;
+  const int chunk = opts->check_every > 0 ? opts->check_every : 8;
+  const int ps = p->pstride_m, hs_ = p->histm_stride;
+  const int nbs = gnk::spmv_blocks(p), nbr = gnk::reduce_blocks(), nbp = gnk::prolong_blocks(p);
+  double *X = p->d_Xm, *R = p->d_Rm, *P = p->d_Pm, *Q = p->d_Qm, *Zv = p->d_Zm;
+  double* part = p->d_partm;
+  double* scal = p->d_scalm;
+  double* hist = p->d_histm;
+  const double tstart = now_s();
+  for (int c = 0; c < k; ++c) gnk::scatter_free(p, b_dev + (c0 + c) * ld, R + c * n, s);
+  GN_HIP(hipMemsetAsync(X, 0, sizeof(double) * n * k, s));
+  std::vector<double> hsc((size_t)k * S_N, 0.0);
+  for (int c = 0; c < k; ++c) hsc[(size_t)c * S_N + S_MAXIT] = (double)opts->maxit;
+  GN_HIP(hipMemcpyAsync(scal, hsc.data(), sizeof(double) * k * S_N, hipMemcpyHostToDevice, s));
+  auto apply_m = [&](int op) {   // z = M^-1 r for the live columns, then the r.z recurrence step
+    if (pc) {
+      gnk::precond_mc(p, pc, R, Zv, k, part, ps, scal, pc->d_tm, pc->d_gm, pc->d_um, pc->d_ym, s);
+      gnk::finalize_mc(part, ps, nbp, op, k, scal, hist, hs_, opts->rtol, s);
+    } else {
+      gnk::copy_mc(n, k, Zv, R, scal, s);
+      gnk::dot_mc(n, k, R, Zv, part, ps, scal, s);
+      gnk::finalize_mc(part, ps, nbr, op, k, scal, hist, hs_, opts->rtol, s);
+    }
+  };
+  gnk::dot_mc(n, k, R, R, part, ps, nullptr, s);
+  gnk::finalize_mc(part, ps, nbr, OP_BB, k, scal, hist, hs_, opts->rtol, s);
+  apply_m(OP_RZ0);
+  gnk::copy_mc(n, k, P, Zv, scal, s);
+  auto read_scal = [&]() {
+    GN_HIP(hipMemcpyAsync(hsc.data(), scal, sizeof(double) * k * S_N, hipMemcpyDeviceToHost, s));
+    GN_HIP(hipStreamSynchronize(s));
+  };
+  auto iterate = [&]() {
+    for (;;) {
+      for (int it = 0; it < chunk; ++it) {
+        gnk::spmv_mc(p, P, Q, k, part, ps, scal, s);
+        gnk::finalize_mc(part, ps, nbs, OP_ALPHA, k, scal, hist, hs_, opts->rtol, s);
+        gnk::update_xr_mc(n, k, X, R, P, Q, scal, part, ps, s);
+        gnk::finalize_mc(part, ps, nbr, OP_RR, k, scal, hist, hs_, opts->rtol, s);
+        apply_m(OP_BETA);
+        gnk::update_p_mc(n, k, P, Zv, scal, s);
+      }
+      read_scal();
+      bool fin = true;
+      for (int c = 0; c < k; ++c) fin &= hsc[(size_t)c * S_N + S_DONE] != 0.0;
+      if (fin) return;
+    }
+  };
+  // ||b_c - A x_c||^2 per column; leaves A x in Q and b (full numbering) in Zv
+  std::vector<double> hpart((size_t)ps * k);
+  std::vector<double> tr(k, 0.0);
+  auto true_residual = [&]() {
+    gnk::spmv_mc(p, X, Q, k, nullptr, ps, nullptr, s);
+    for (int c = 0; c < k; ++c) gnk::scatter_free(p, b_dev + (c0 + c) * ld, Zv + c * n, s);
+    gnk::sub_mc(n, k, Zv, Q, nullptr, part, ps, s);
+    GN_HIP(hipMemcpyAsync(hpart.data(), part, sizeof(double) * ps * k, hipMemcpyDeviceToHost, s));
+    GN_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < k; ++c) {
+      double t = 0.0;
+      for (int i = 0; i < nbr; ++i) t += hpart[(size_t)c * ps + i];
+      tr[c] = t;
+    }
+  };
+  iterate();
+  std::vector<double> fin_hs(hsc);       // per-column scalars at the end of its last sequence
+  std::vector<int> first_iters(k), restarts(k, 0);
+  for (int c = 0; c < k; ++c) first_iters[c] = (int)hsc[(size_t)c * S_N + S_ITER];
+  std::vector<double> hhist((size_t)hs_ * k);
+  GN_HIP(hipMemcpyAsync(hhist.data(), hist, sizeof(double) * hs_ * k, hipMemcpyDeviceToHost, s));
+  true_residual();
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<char> again(k, 0);
+    bool any = false;
+    for (int c = 0; c < k; ++c) {
+      const double* h = &fin_hs[(size_t)c * S_N];
+      again[c] = h[S_BREAK] == 0.0 && h[S_BB] > 0.0 && tr[c] > h[S_TOL2] && (int)h[S_ITER] < opts->maxit;
+      any |= again[c] != 0;
+    }
+    if (!any) break;
+    // columns that do not restart are stopped through their iteration limit
+    read_scal();
+    for (int c = 0; c < k; ++c)
+      if (!again[c]) hsc[(size_t)c * S_N + S_MAXIT] = hsc[(size_t)c * S_N + S_ITER];
+    GN_HIP(hipMemcpyAsync(scal, hsc.data(), sizeof(double) * k * S_N, hipMemcpyHostToDevice, s));
+    gnk::sub_mc(n, k, Zv, Q, R, part, ps, s);   // r = b - A x
+    gnk::finalize_mc(part, ps, nbr, OP_RESTART, k, scal, hist, hs_, opts->rtol, s);
+    apply_m(OP_RZ0);
+    gnk::copy_mc(n, k, P, Zv, scal, s);
+    iterate();
+    for (int c = 0; c < k; ++c)
+      if (again[c]) {
+        std::copy(&hsc[(size_t)c * S_N], &hsc[(size_t)c * S_N] + S_N, &fin_hs[(size_t)c * S_N]);
+        ++restarts[c];
+      }
+    true_residual();
+  }
+  const double tsolve = now_s() - tstart;
+  for (int c = 0; c < k; ++c) gnk::gather_free(p, X + c * n, x_dev + (c0 + c) * ld, s);
+  GN_HIP(hipStreamSynchronize(s));
+  gn_status ret = GN_OK;
+  for (int c = 0; c < k; ++c) {
+    const double* h = &fin_hs[(size_t)c * S_N];
+    const double bb = h[S_BB], rr = h[S_RR];
+    const bool conv = bb == 0.0 || rr <= h[S_TOL2];
+    if (h[S_BREAK] != 0.0) ret = GN_ERR_BREAKDOWN;
+    else if (!conv && ret == GN_OK) ret = GN_WARN_MAXIT;
+    if (reports) {
+      gn_solve_report& Rp = reports[c0 + c];
+      Rp.iters = (int)h[S_ITER];
+      Rp.converged = conv ? 1 : 0;
+      Rp.rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+      Rp.true_rel_res = bb > 0 ? std::sqrt(tr[c] / bb) : 0.0;
+      Rp.t_solve_s = tsolve;
+      Rp.iters_first = first_iters[c];
+      Rp.restarts = restarts[c];
+      Rp.cond_est = cond_from_hist(&hhist[(size_t)c * hs_], first_iters[c]);
+    }
+  }
+  return ret;
+}
+
 extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev, double* x_dev,
                               int32_t nrhs, int64_t ld, const gn_solve_opts* opts, void* stream,
                               gn_solve_report* reports) {
@@ -809,6 +997,15 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
   double* scal = p->d_scal;
   const double* done = scal + S_DONE;
   gn_status ret = GN_OK;
+  if (nrhs > 1 && !opts->sequential) {
+    const int KC = gnk::mc_width();
+    for (int c0 = 0; c0 < nrhs; c0 += KC) {
+      gn_status st = solve_batch(p, pc, b_dev, x_dev, c0, std::min(KC, nrhs - c0), ld, opts, s, reports);
+      if (st < 0 && ret >= 0) ret = st;
+      else if (st > 0 && ret == GN_OK) ret = st;
+    }
+    return ret;
+  }
   const int nbs = gnk::spmv_blocks(p), nbr = gnk::reduce_blocks(), nbp = gnk::prolong_blocks(p);
   for (int col = 0; col < nrhs; ++col) {
     const double tstart = now_s();
@@ -908,19 +1105,7 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
       R.t_solve_s = tsolve;
       R.iters_first = first_iters;
       R.restarts = restarts;
-      // CG-Lanczos tridiagonal: T_ii = 1/a_i + b_{i-1}/a_{i-1}, T_{i,i+1} = sqrt(b_i)/a_i
-      R.cond_est = 1.0;
-      if (kit > 0) {
-        std::vector<double> d(kit), e(std::max(kit - 1, 0));
-        for (int i = 0; i < kit; ++i) {
-          double a = hist[2 * i];
-          d[i] = 1.0 / a + (i > 0 ? hist[2 * (i - 1) + 1] / hist[2 * (i - 1)] : 0.0);
-          if (i + 1 < kit) e[i] = std::sqrt(std::max(hist[2 * i + 1], 0.0)) / a;
-        }
-        double lo, hi;
-        tridiag_extremes(d, e, &lo, &hi);
-        R.cond_est = lo > 0 ? hi / lo : INFINITY;
-      }
+      R.cond_est = cond_from_hist(hist.data(), kit);
     }
   }
   return ret;

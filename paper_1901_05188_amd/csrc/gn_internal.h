@@ -99,6 +99,11 @@ struct gn_problem {
   double* d_scal = nullptr;    // device scalars
   double* d_hist = nullptr;    // alpha/beta history
   int hist_cap = 0;
+  // batched (multi-RHS) CG workspace: 16 columns of each vector, per-column
+  // partial sums, scalars and alpha/beta history
+  double *d_Xm = nullptr, *d_Rm = nullptr, *d_Pm = nullptr, *d_Qm = nullptr, *d_Zm = nullptr;
+  double *d_partm = nullptr, *d_scalm = nullptr, *d_histm = nullptr;
+  int histm_stride = 0, pstride_m = 0;
   std::vector<void*> owned;
 };
 
@@ -131,6 +136,9 @@ struct gn_precond {
   double* d_z0 = nullptr;    // one zero tile (FP64) read by masked prefetch slots
   float* d_zf = nullptr;     // one zero tile (FP32)
   double trsv_bytes = 0.0, prolong_bytes = 0.0;
+  double trsv_bytes_mc = 0.0;  // gather + banded solves of one 16-column batch
+  double* d_tm = nullptr;      // local vectors of a batch: (offVI + row) * 16 + column
+  double *d_gm = nullptr, *d_um = nullptr, *d_ym = nullptr;  // coarse vectors, column * NBH*TILE
   double* d_Z = nullptr;     // L_H^-1 as dense tiles (NBH x NBH tiles, lower)
   int NBH = 0;
   std::vector<double> lam;   // eigenvalues per subdomain (n_eval each)
@@ -179,6 +187,23 @@ void coarse_solve(const gn_precond* pc, const double* done, hipStream_t s);
 int prolong_blocks(const gn_problem* p);
 void prolong(const gn_problem* p, const gn_precond* pc, const double* r, double* z, double* part,
              const double* done, hipStream_t s);
+// multi.hip (batched columns; scal == nullptr means every column is live)
+int mc_width();
+void spmv_mc(const gn_problem* p, const double* x, double* y, int k, double* part, int pstride,
+             const double* scal, hipStream_t s);
+void dot_mc(int64_t n, int k, const double* a, const double* b, double* part, int pstride, const double* scal,
+            hipStream_t s);
+void update_xr_mc(int64_t n, int k, double* x, double* r, const double* p, const double* q, const double* scal,
+                  double* part, int pstride, hipStream_t s);
+void update_p_mc(int64_t n, int k, double* p, const double* z, const double* scal, hipStream_t s);
+void copy_mc(int64_t n, int k, double* dst, const double* src, const double* scal, hipStream_t s);
+void sub_mc(int64_t n, int k, const double* b, const double* q, double* r, double* part, int pstride,
+            hipStream_t s);
+void finalize_mc(const double* part, int pstride, int nb, int op, int k, double* scal, double* hist,
+                 int hstride, double rtol, hipStream_t s);
+int mc_band_lds_bytes(int maxw);
+void precond_mc(const gn_problem* p, const gn_precond* pc, const double* r, double* z, int k, double* part,
+                int pstride, const double* scal, double* tm, double* gm, double* um, double* ym, hipStream_t s);
 // geneo.hip
 void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s);
 void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double* BE, hipStream_t s);
