@@ -44,7 +44,7 @@ def make_workload(name):
 
 def cpu_baseline():
     """Oracle (as written, untuned) on a bounded sample of the same workload:
-    a 16x36x14-cell crop of the SPE10-shaped field, 2x2x2 subdomains, overlap 2,
+    a 20x40x16-cell crop of the SPE10-shaped field, 2x2x2 subdomains, overlap 2,
     threshold 0.15; timed end to end (assembly + GenEO set-up + PCG to 1e-8) on
     one host core (BLAS limited to one thread)."""
     from threadpoolctl import threadpool_limits
@@ -52,7 +52,7 @@ def cpu_baseline():
     from oracle import fem, geneo, pcg
     from workloads import generate as gen
     w_full = gen.spe10_like()
-    ne = (16, 36, 14)
+    ne = (20, 40, 16)
     kfull = w_full.elem_k.reshape(85, 220, 60)          # [z][y][x]
     kc = kfull[:ne[2], :ne[1], :ne[0]]
     w = gen.diffusion_box(ne, kc.ravel(), (2, 2, 2), overlap=2, threshold=0.15, nev_max=32,
@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solve-reps", type=int, default=5, help="warm solves per step for latency")
+    ap.add_argument("--multi-rhs", type=int, default=16,
+                    help="columns of the batched multi-RHS leg (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only"}))
@@ -175,6 +177,33 @@ def main():
             "working_launches": applications, "bytes_per_working_launch": bytes_per_app,
             "bytes_per_launch": bytes_per_launch}
     lat_sorted = sorted(lat_plain)
+    # batched multi-RHS leg: the workload's load plus seeded random loads, all
+    # columns in one batched solve (the warm operator and preconditioner)
+    multi = None
+    if args.multi_rhs > 1:
+        k = args.multi_rhs
+        gen_t = torch.Generator(device=dev)
+        gen_t.manual_seed(1234)
+        B = torch.randn((k, prob.n_free), dtype=torch.float64, device=dev, generator=gen_t)
+        B[0].copy_(b[0])
+        X = torch.zeros_like(B)
+        gp.solve(prob, pc, B, X, rtol=args.rtol, maxit=5000, check_every=16)   # warm
+        mt = []
+        for r in range(2):
+            X.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, mrep = gp.solve(prob, pc, B, X, rtol=args.rtol, maxit=5000, check_every=16)
+            torch.cuda.synchronize()
+            mt.append(time.perf_counter() - t0)
+        tm = min(mt)
+        multi = {"k": k, "solve_s": tm, "solve_dofs_per_s": prob.n_free * k / tm,
+                 "speedup_vs_single": (prob.n_free * k / tm) / (n_dof / statistics.median(lat_plain)),
+                 "iters": [c["iters"] for c in mrep],
+                 "max_true_rel_res": max(c["true_rel_res"] for c in mrep),
+                 "all_converged": all(c["converged"] == 1 for c in mrep)}
+        log(f"multi-RHS k={k}: {tm:.3f}s, {multi['solve_dofs_per_s']:.3e} DOFs/s, "
+            f"x{multi['speedup_vs_single']:.2f} vs one column")
 
     def pct(v, q):
         k = min(len(v) - 1, max(0, int(round(q * (len(v) - 1)))))
@@ -207,6 +236,8 @@ def main():
         "kernel_groups_ms_per_solve": {k: v["ms_total"] / args.solve_reps for k, v in groups.items()},
         "roofline": roof,
     }
+    if multi is not None:
+        res["multi_rhs"] = multi
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline()

@@ -534,8 +534,10 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     double* BV = dalloc<double>(tmp, vlen + 64);
     double* BZ = dalloc<double>(tmp, vlen + 64);
     for (double* t : {V, Z, BV, BZ}) GN_HIP(hipMemsetAsync(t + vlen, 0, sizeof(double) * 64, s));
-    double* GP = dalloc<double>(tmp, (size_t)n_sub * b * b);
-    double* GB = dalloc<double>(tmp, (size_t)n_sub * b * b);
+    const int gsplit = gnk::gram_split();
+    double* GP = dalloc<double>(tmp, (size_t)n_sub * gsplit * b * b);
+    double* GB = dalloc<double>(tmp, (size_t)n_sub * gsplit * b * b);
+    double* resp = dalloc<double>(tmp, (size_t)n_sub * gsplit * 2 * b);
     double* Y = dalloc<double>(tmp, (size_t)n_sub * b * b);
     double* nu = dalloc<double>(tmp, (size_t)n_sub * b);
     double* res = dalloc<double>(tmp, (size_t)n_sub * 2 * b);
@@ -554,8 +556,8 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
       GN_HIP(hipMemcpyAsync(Z, BV, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
       gnk::eig_trsm(pc, b, LB, DB, Z, s);
       gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
-      gnk::eig_gram(pc, b, Z, BV, BZ, V, nu, GP, GB, res, s);
-      gnk::eig_small(n_sub, b, GP, GB, Y, nu, nullptr, s);
+      gnk::eig_gram(pc, b, Z, BV, BZ, V, nu, GP, GB, resp, s);
+      gnk::eig_small(n_sub, b, GP, GB, resp, res, Y, nu, nullptr, s);
       gnk::eig_vupdate(pc, b, maxNBB, Z, BZ, Y, V, BV, s);
       GN_HIP(hipMemcpyAsync(h_res.data(), res, sizeof(double) * h_res.size(), hipMemcpyDeviceToHost, s));
       // residuals refer to the Ritz pairs of the previous iteration (h_nu before this copy)

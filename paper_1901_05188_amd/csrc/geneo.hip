@@ -119,10 +119,11 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
     for (int c2 = 0; c2 < NC; ++c2) {
       double bv = base[(int64_t)(d * NC + c2) * npad + r];
       int r2 = min(max((ln + dn) * NC + c2, 0), nmax);   // out-of-box neighbours have bv = 0
+      // a chunk may run up to 7 columns past the row end into the next row or the
+      // 64-double tail of the buffer: loads stay unconditional, stores are masked
       const double* vr = Vb + (int64_t)r2 * b + col0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (col0 + q < b) acc[q] += bv * vr[q];
+      for (int q = 0; q < 8; ++q) acc[q] += bv * vr[q];
     }
   }
 #pragma unroll
@@ -252,20 +253,28 @@ __global__ __launch_bounds__(128) void k_trsm_pencil(const SubDesc* __restrict__
 // ---------------------------------------------------------------------------
 // Gram matrices GP = Z^T (B V) = Z^T P Z and GB = Z^T (B Z) on FP64 matrix
 // cores, and the Ritz residuals res_k = ||Z_k - nu_k V_k||^2, zz_k = ||Z_k||^2.
-// One workgroup per subdomain streams its rows four at a time (the K dimension
-// of v_mfma_f64_16x16x4f64); wave wid owns the 16-row block kb = wid of both
+// Workgroup (j, g) streams rows [g*chunk, (g+1)*chunk) of subdomain j four at a
+// time (the K dimension of v_mfma_f64_16x16x4f64) and writes partial Gram
+// matrices and residual sums of its rows; k_small_eig adds the GRAM_SPLIT
+// partials in a fixed order.  Wave wid owns the 16-row block kb = wid of both
 // Gram matrices (column blocks 0..3).  Padding rows are zero in Z, BV and BZ;
 // columns past b only feed output entries that are not stored.
 // ---------------------------------------------------------------------------
+constexpr int GRAM_SPLIT = 8;
+
 __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, int b,
                                              const double* __restrict__ Z, const double* __restrict__ BV,
                                              const double* __restrict__ BZ, const double* __restrict__ V,
-                                             const double* __restrict__ nu, double* __restrict__ GP,
-                                             double* __restrict__ GB, double* __restrict__ res) {
+                                             const double* __restrict__ nu, double* __restrict__ GPp,
+                                             double* __restrict__ GBp, double* __restrict__ resp) {
   __shared__ double sres[4][64], szz[4][64];
   const SubDesc& sd = subs[blockIdx.x];
   const int64_t base = sd.offVB * b;
-  const int nrows = sd.NBB * TILE;
+  const int g = blockIdx.y;
+  const int nall = sd.NBB * TILE;
+  const int chunk = ((nall + GRAM_SPLIT * 16 - 1) / (GRAM_SPLIT * 16)) * 16;
+  const int rlo = min(g * chunk, nall), rhi = min(rlo + chunk, nall);
+  const int64_t part = (int64_t)blockIdx.x * GRAM_SPLIT + g;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
@@ -278,7 +287,7 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
   if (active) {
     // rows streamed 16 at a time (4 MFMA K-steps), all loads of a step issued first;
     // padded row counts are multiples of 32
-    for (int r0 = 0; r0 < nrows; r0 += 16) {
+    for (int r0 = rlo; r0 < rhi; r0 += 16) {
       double a[4], bvv[4][4], bzv[4][4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -301,8 +310,8 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
           }
         }
     }
-    double* gpo = GP + (int64_t)blockIdx.x * b * b;
-    double* gbo = GB + (int64_t)blockIdx.x * b * b;
+    double* gpo = GPp + part * b * b;
+    double* gbo = GBp + part * b * b;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -318,7 +327,7 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
   const double nk = lane < b ? nu[(int64_t)blockIdx.x * b + lane] : 0.0;
   double rs = 0.0, zz = 0.0;
   if (lane < b) {
-    for (int r = wid; r < sd.nB; r += 4) {
+    for (int r = rlo + wid; r < min(rhi, sd.nB); r += 4) {
       double z = Z[base + (int64_t)r * b + lane];
       double d = z - nk * V[base + (int64_t)r * b + lane];
       rs += d * d;
@@ -330,8 +339,8 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
   __syncthreads();
   if (threadIdx.x < b) {
     int k = threadIdx.x;
-    res[(int64_t)blockIdx.x * 2 * b + k] = sres[0][k] + sres[1][k] + sres[2][k] + sres[3][k];
-    res[(int64_t)blockIdx.x * 2 * b + b + k] = szz[0][k] + szz[1][k] + szz[2][k] + szz[3][k];
+    resp[part * 2 * b + k] = sres[0][k] + sres[1][k] + sres[2][k] + sres[3][k];
+    resp[part * 2 * b + b + k] = szz[0][k] + szz[1][k] + szz[2][k] + szz[3][k];
   }
 }
 
@@ -340,8 +349,9 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
 // diagonal scaling, Cholesky GP = R R^T, C = R^-1 GB R^-T, cyclic Jacobi,
 // y = D R^-T w, sorted by decreasing nu; Y^T GP Y = I.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_small_eig(int b, const double* __restrict__ GP,
-                                                  const double* __restrict__ GB, double* __restrict__ Y,
+__global__ __launch_bounds__(NT) void k_small_eig(int b, const double* __restrict__ GPp,
+                                                  const double* __restrict__ GBp, const double* __restrict__ resp,
+                                                  double* __restrict__ res, double* __restrict__ Y,
                                                   double* __restrict__ nu_out, int* __restrict__ flag) {
   extern __shared__ double sm[];
   const int ld = b + 1;
@@ -353,19 +363,47 @@ __global__ __launch_bounds__(NT) void k_small_eig(int b, const double* __restric
   __shared__ int pp[32], qq[32];
   __shared__ int order[64];
   __shared__ double offn;
-  const double* gp = GP + (int64_t)blockIdx.x * b * b;
-  const double* gb = GB + (int64_t)blockIdx.x * b * b;
   const int tid = threadIdx.x;
+  // sum the row-split partials of the Gram matrices and residuals (fixed order)
+  {
+    const double* gp = GPp + (int64_t)blockIdx.x * GRAM_SPLIT * b * b;
+    const double* gb = GBp + (int64_t)blockIdx.x * GRAM_SPLIT * b * b;
+    for (int e = tid; e < b * b; e += NT) {
+      double sp = 0.0, sb = 0.0;
+      for (int g = 0; g < GRAM_SPLIT; ++g) {
+        sp += gp[(int64_t)g * b * b + e];
+        sb += gb[(int64_t)g * b * b + e];
+      }
+      W[(e / b) * ld + e % b] = sp;
+      C[(e / b) * ld + e % b] = sb;
+    }
+    const double* rp = resp + (int64_t)blockIdx.x * GRAM_SPLIT * 2 * b;
+    for (int e = tid; e < 2 * b; e += NT) {
+      double t = 0.0;
+      for (int g = 0; g < GRAM_SPLIT; ++g) t += rp[g * 2 * b + e];
+      res[(int64_t)blockIdx.x * 2 * b + e] = t;
+    }
+  }
+  __syncthreads();
   if (tid < b) {
-    double d = gp[tid * b + tid];
+    double d = W[tid * ld + tid];
     dsc[tid] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
   }
   __syncthreads();
   for (int e = tid; e < b * b; e += NT) {
     int k = e / b, l = e % b;
     double s = dsc[k] * dsc[l];
-    P[k * ld + l] = 0.5 * (gp[k * b + l] + gp[l * b + k]) * s;
-    C[k * ld + l] = 0.5 * (gb[k * b + l] + gb[l * b + k]) * s;
+    P[k * ld + l] = 0.5 * (W[k * ld + l] + W[l * ld + k]) * s;
+  }
+  __syncthreads();
+  for (int e = tid; e < b * b; e += NT) {
+    int k = e / b, l = e % b;
+    if (k <= l) {
+      double s = dsc[k] * dsc[l];
+      double v = 0.5 * (C[k * ld + l] + C[l * ld + k]) * s;
+      C[k * ld + l] = v;
+      C[l * ld + k] = v;
+    }
   }
   __syncthreads();
   // Cholesky of P (lower, in place)
@@ -901,19 +939,21 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, dou
   GN_CHECK_LAUNCH();
 }
 
+int gram_split() { return GRAM_SPLIT; }
+
 void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, const double* BZ,
-              const double* V, const double* nu, double* GP, double* GB, double* res, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, Z, BV, BZ, V, nu, GP, GB,
-                     res);
+              const double* V, const double* nu, double* GPp, double* GBp, double* resp, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram, dim3(pc->n_sub, GRAM_SPLIT), dim3(NT), 0, s, pc->d_sub, b, Z, BV, BZ, V, nu,
+                     GPp, GBp, resp);
   GN_CHECK_LAUNCH();
 }
 
-void eig_small(int n_sub, int b, const double* GP, const double* GB, double* Y, double* nu, int* flag,
-               hipStream_t s) {
+void eig_small(int n_sub, int b, const double* GPp, const double* GBp, const double* resp, double* res,
+               double* Y, double* nu, int* flag, hipStream_t s) {
   size_t lds = sizeof(double) * 3 * b * (b + 1);
   GN_HIP(hipFuncSetAttribute((const void*)k_small_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
-  hipLaunchKernelGGL(k_small_eig, dim3(n_sub), dim3(NT), lds, s, b, GP, GB, Y, nu, flag);
+  hipLaunchKernelGGL(k_small_eig, dim3(n_sub), dim3(NT), lds, s, b, GPp, GBp, resp, res, Y, nu, flag);
   GN_CHECK_LAUNCH();
 }
 

@@ -210,10 +210,11 @@ void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double
 void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int b, int maxNBB,
                 const double* V, double* out, hipStream_t s);
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, double* V, hipStream_t s);
+int gram_split();
 void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, const double* BZ,
-              const double* V, const double* nu, double* GP, double* GB, double* res, hipStream_t s);
-void eig_small(int n_sub, int b, const double* GP, const double* GB, double* Y, double* nu, int* flag,
-               hipStream_t s);
+              const double* V, const double* nu, double* GPp, double* GBp, double* resp, hipStream_t s);
+void eig_small(int n_sub, int b, const double* GPp, const double* GBp, const double* resp, double* res,
+               double* Y, double* nu, int* flag, hipStream_t s);
 void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const double* BZ,
                  const double* Y, double* V, double* BV, hipStream_t s);
 void eig_normalise(const gn_precond* pc, int b, int ncol, double* V, hipStream_t s);
