@@ -121,7 +121,12 @@ gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t n
  * result).  shift > 0 is the shift-and-invert shift (Section 3.3.2; 0 = 1e-2).
  * eig_tol / eig_maxit bound the batched eigensolver (0 = defaults 1e-12 / 300):
  * it stops when every wanted Ritz pair has ||P^-1 B v - nu v|| <= eig_tol ||P^-1 B v||,
- * or when that residual stays below 1e-9 without halving for 15 iterations. */
+ * or when that residual stays below 1e-9 without halving for 15 iterations.
+ * eig_block is the subspace block size (0 = automatic: nev + max(8, nev/2), or
+ * nev_max + 8, at most 64); a given value must lie in [(nev or nev_max) + 5, 64].
+ * eig_filter is the largest Chebyshev filter degree per Rayleigh-Ritz step
+ * (0 = 4; 1 = plain subspace iteration); the degree ramps up 1, 2, ... from the
+ * first step. */
 typedef struct gn_dd_opts {
   int32_t nparts[3];
   const int32_t* cuts[3];
@@ -134,17 +139,20 @@ typedef struct gn_dd_opts {
   double shift;
   double eig_tol;
   int32_t eig_maxit;
+  int32_t eig_block;
+  int32_t eig_filter;
 } gn_dd_opts;
 
 typedef struct gn_setup_report {
   int32_t n_sub;
   int64_t coarse_dim;
-  int32_t eig_iters;         /* iterations of the batched eigensolver          */
+  int32_t eig_iters;         /* Rayleigh-Ritz steps of the batched eigensolver */
   int32_t max_local_n;       /* largest local system size                      */
   int32_t band_tiles;        /* band width in 32-row tiles (largest subdomain) */
   double t_local_s, t_eigen_s, t_coarse_s, t_total_s;
   int64_t hbm_bytes;         /* device bytes held by the preconditioner        */
   double eig_resid;          /* largest final relative Ritz residual           */
+  int32_t eig_solves;        /* block solves with the pencil factors            */
 } gn_setup_report;
 
 /* Build the preconditioner: local Dirichlet factors A_j = L_j L_j^T

@@ -50,14 +50,16 @@ class gn_dd_opts(C.Structure):
     _fields_ = [("nparts", C.c_int32 * 3), ("cuts", C.POINTER(C.c_int32) * 3),
                 ("overlap", C.c_int32), ("nev", C.c_int32), ("threshold", C.c_double),
                 ("nev_max", C.c_int32), ("local_prec", C.c_int32), ("coarse", C.c_int32),
-                ("shift", C.c_double), ("eig_tol", C.c_double), ("eig_maxit", C.c_int32)]
+                ("shift", C.c_double), ("eig_tol", C.c_double), ("eig_maxit", C.c_int32),
+                ("eig_block", C.c_int32), ("eig_filter", C.c_int32)]
 
 
 class gn_setup_report(C.Structure):
     _fields_ = [("n_sub", C.c_int32), ("coarse_dim", C.c_int64), ("eig_iters", C.c_int32),
                 ("max_local_n", C.c_int32), ("band_tiles", C.c_int32),
                 ("t_local_s", C.c_double), ("t_eigen_s", C.c_double), ("t_coarse_s", C.c_double),
-                ("t_total_s", C.c_double), ("hbm_bytes", C.c_int64), ("eig_resid", C.c_double)]
+                ("t_total_s", C.c_double), ("hbm_bytes", C.c_int64), ("eig_resid", C.c_double),
+                ("eig_solves", C.c_int32)]
 
 
 class gn_solve_opts(C.Structure):
@@ -216,7 +218,7 @@ class Preconditioner:
 
     def __init__(self, prob: Problem, nparts: Sequence[int], cuts, overlap=1, nev=0, threshold=0.0,
                  nev_max=0, local_prec=64, coarse=True, shift=0.0, eig_tol=0.0, eig_maxit=0,
-                 stream=None):
+                 eig_block=0, eig_filter=0, stream=None):
         o = gn_dd_opts()
         keep = []
         for a in range(3):
@@ -227,6 +229,7 @@ class Preconditioner:
         o.overlap, o.nev, o.threshold, o.nev_max = int(overlap), int(nev), float(threshold), int(nev_max)
         o.local_prec, o.coarse = int(local_prec), int(bool(coarse))
         o.shift, o.eig_tol, o.eig_maxit = float(shift), float(eig_tol), int(eig_maxit)
+        o.eig_block, o.eig_filter = int(eig_block), int(eig_filter)
         rep = gn_setup_report()
         h = C.c_void_p()
         _check(lib().gn_setup_geneo(prob.handle, C.byref(o), _stream(stream), C.byref(h), C.byref(rep)))

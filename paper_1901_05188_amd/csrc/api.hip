@@ -371,6 +371,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   const double shift = o->shift > 0 ? o->shift : 1e-2;
   const double eig_tol = o->eig_tol > 0 ? o->eig_tol : 1e-12;
   const int eig_maxit = o->eig_maxit > 0 ? o->eig_maxit : 300;
+  if (o->eig_filter < 0 || o->eig_filter > 8) argfail("eig_filter must lie in [0, 8]");
   if (o->coarse && o->nev <= 0 && !(o->threshold > 0)) argfail("coarse space needs nev > 0 or threshold > 0");
   if (o->coarse && o->nev > 48) argfail("nev must be <= 48");
   if (o->coarse && o->nev <= 0 && (o->nev_max <= 0 || o->nev_max > 48))
@@ -505,7 +506,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   GN_HIP(hipStreamSynchronize(s));
   const double t1 = now_s();
   double t2 = t1, t3 = t1;
-  int eig_iters = 0;
+  int eig_iters = 0, eig_solves = 0;
   double eig_resid = 0.0;
 
   // ---- GenEO eigenproblems -------------------------------------------------
@@ -514,6 +515,12 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     const bool fixed = o->nev > 0;
     const int guard = 8;
     int b = fixed ? std::min(64, o->nev + std::max(guard, o->nev / 2)) : std::min(64, o->nev_max + guard);
+    if (o->eig_block > 0) {
+      const int need = (fixed ? o->nev : o->nev_max) + 1 + guard / 2;
+      if (o->eig_block < need || o->eig_block > 64)
+        argfail("eig_block must lie in [" + std::to_string(need) + ", 64]");
+      b = o->eig_block;
+    }
     double* LB = dalloc<double>(tmp, (size_t)offTB * TILE2);
     double* DB = dalloc<double>(tmp, (size_t)offDB * TILE2);
     GN_HIP(hipMemsetAsync(LB, 0, sizeof(double) * (size_t)offTB * TILE2, s));
@@ -551,12 +558,72 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     double* BE = dalloc<double>(tmp, (size_t)offVB * 27 * nc);
     gnk::eig_extract_b(p, pc, maxNBB, BE, s);
     gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);
+    // Chebyshev-filtered subspace iteration: outer iteration it applies a filter
+    // of degree d = min(dmax, it + 1) in T = P^-1 B (d block solves), then one
+    // Rayleigh-Ritz step; d = 1 is plain subspace iteration
+    const int dmax = o->eig_filter > 0 ? o->eig_filter : 4;
+    const int ncoef = std::max(2, 2 * dmax - 2);
+    double *A1 = nullptr, *B1 = nullptr, *d_coef = nullptr;
+    if (dmax > 1) {
+      A1 = dalloc<double>(tmp, vlen + 64);
+      B1 = dalloc<double>(tmp, vlen + 64);
+      for (double* t : {A1, B1}) GN_HIP(hipMemsetAsync(t + vlen, 0, sizeof(double) * 64, s));
+      d_coef = dalloc<double>(tmp, (size_t)n_sub * ncoef);
+    }
+    std::vector<double> h_coef((size_t)n_sub * ncoef, 0.0);
+    std::vector<int> solves_hist;
+    int solves = 0;
     for (int it = 0; it < eig_maxit; ++it) {
-      // Z = P^-1 B V ; Rayleigh-Ritz on span(Z) ; V <- Z Y, BV <- (B Z) Y
+      const int d = std::min(dmax, it + 1);
+      // Z = T V = P^-1 B V
       GN_HIP(hipMemcpyAsync(Z, BV, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
       gnk::eig_trsm(pc, b, LB, DB, Z, s);
-      gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
-      gnk::eig_gram(pc, b, Z, BV, BZ, V, nu, GP, GB, resp, s);
+      ++solves;
+      if (d == 1) {
+        // Rayleigh-Ritz on span(Z): P Z = B V, so Z^T P Z = Z^T (B V)
+        gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
+        gnk::eig_gram(pc, b, Z, BV, BZ, V, nu, GP, GB, resp, s);
+      } else {
+        // filter interval [0, nu_cut] per subdomain, nu_cut = smallest Ritz value
+        // of the last Rayleigh-Ritz step; scaled so that nu = 1/s maps to 1
+        const double nuref = 1.0 / shift;
+        for (int j = 0; j < n_sub; ++j) {
+          double nucut = h_nu[(size_t)j * b + b - 1];
+          nucut = std::min(std::max(nucut, 1e-12 * nuref), 0.5 * nuref);
+          const double e = 0.5 * nucut, c = 0.5 * nucut;
+          const double s1 = e / (nuref - c);
+          double* cf = &h_coef[(size_t)j * ncoef];
+          cf[0] = s1 / e;
+          cf[1] = c;
+          double sig = s1;
+          for (int i = 2; i < d; ++i) {
+            const double sn = 1.0 / (2.0 / s1 - sig);
+            cf[2 + 2 * (i - 2)] = 2.0 * sn / e;
+            cf[3 + 2 * (i - 2)] = sig * sn;
+            sig = sn;
+          }
+        }
+        GN_HIP(hipMemcpyAsync(d_coef, h_coef.data(), sizeof(double) * h_coef.size(), hipMemcpyHostToDevice, s));
+        // Y1 = a1 (Z - c V), with the Ritz residuals of the current block
+        gnk::eig_cheb_first(pc, b, Z, V, nu, d_coef, ncoef, A1, resp, s);
+        double *Y0 = V, *BY0 = BV, *Yc = A1, *BYc = B1;
+        gnk::eig_bapply(p, pc, BE, b, maxNBB, Yc, BYc, s);
+        for (int i = 2; i < d; ++i) {
+          GN_HIP(hipMemcpyAsync(Z, BYc, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
+          gnk::eig_trsm(pc, b, LB, DB, Z, s);
+          ++solves;
+          gnk::eig_cheb_step(pc, b, maxNBB, Z, Yc, Y0, d_coef, ncoef, i - 2, s);   // Y0 <- Y_i
+          gnk::eig_bapply(p, pc, BE, b, maxNBB, Y0, BY0, s);
+          std::swap(Y0, Yc);
+          std::swap(BY0, BYc);
+        }
+        // W = T Y_{d-1}: Rayleigh-Ritz on span(W) with P W = B Y_{d-1}
+        GN_HIP(hipMemcpyAsync(Z, BYc, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
+        gnk::eig_trsm(pc, b, LB, DB, Z, s);
+        ++solves;
+        gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
+        gnk::eig_gram(pc, b, Z, BYc, BZ, nullptr, nullptr, GP, GB, nullptr, s);
+      }
       gnk::eig_small(n_sub, b, GP, GB, resp, res, Y, nu, nullptr, s);
       gnk::eig_vupdate(pc, b, maxNBB, Z, BZ, Y, V, BV, s);
       GN_HIP(hipMemcpyAsync(h_res.data(), res, sizeof(double) * h_res.size(), hipMemcpyDeviceToHost, s));
@@ -565,6 +632,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
       GN_HIP(hipMemcpyAsync(h_nu.data(), nu, sizeof(double) * h_nu.size(), hipMemcpyDeviceToHost, s));
       GN_HIP(hipStreamSynchronize(s));
       eig_iters = it + 1;
+      eig_solves = solves;
       if (it == 0) continue;
       bool all = true;
       double worst = 0.0;   // largest relative residual over the wanted pairs
@@ -593,11 +661,18 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
         }
       }
       worst_hist.push_back(worst);
+      solves_hist.push_back(solves);
       eig_resid = worst;
       // accept a residual that has reached the rounding floor: no halving over
-      // 15 iterations once it is below 1e-9
-      size_t h = worst_hist.size();
-      bool stagnated = h > 20 && worst <= 1e-9 && worst > 0.5 * worst_hist[h - 16];
+      // the last 15 block solves once it is below 1e-9
+      bool stagnated = false;
+      if (solves > 20 && worst <= 1e-9) {
+        for (size_t q = worst_hist.size(); q-- > 0;)
+          if (solves_hist[q] <= solves - 15) {
+            stagnated = worst > 0.5 * worst_hist[q];
+            break;
+          }
+      }
       if (all || stagnated) {
         converged = true;
         break;
@@ -734,6 +809,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     rep->n_sub = n_sub;
     rep->coarse_dim = pc->NH;
     rep->eig_iters = eig_iters;
+    rep->eig_solves = eig_solves;
     rep->max_local_n = maxNI;
     rep->band_tiles = maxw;
     rep->t_local_s = t1 - t0;

@@ -323,7 +323,8 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
         }
       }
   }
-  // residuals: lane = column, waves split the rows
+  // residuals: lane = column, waves split the rows (nu == nullptr: formed elsewhere)
+  if (!nu) return;
   const double nk = lane < b ? nu[(int64_t)blockIdx.x * b + lane] : 0.0;
   double rs = 0.0, zz = 0.0;
   if (lane < b) {
@@ -592,6 +593,69 @@ __global__ __launch_bounds__(NT) void k_vupdate(const SubDesc* __restrict__ subs
     V[base + e] = s1;
     BV[base + e] = s2;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev filter steps of the subspace iteration.  With T = P^-1 B (Ritz
+// values nu of the block in (0, 1/s]) the unwanted part of the spectrum lies in
+// [0, nu_cut], nu_cut = the smallest Ritz value of the block; the scaled
+// three-term recurrence of the Chebyshev polynomials on that interval damps it
+// and amplifies the wanted nu > nu_cut (per subdomain coefficients):
+//   Y1 = a1 (T V - c V),   Y_{i+1} = a_i (T Y_i - c Y_i) - beta_i Y_{i-1}.
+// k_cheb_first also forms the Ritz residuals of the current block from T V, in
+// the same row-split layout as k_gram.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_cheb_first(const SubDesc* __restrict__ subs, int b,
+                                                   const double* __restrict__ Z, const double* __restrict__ V,
+                                                   const double* __restrict__ nu, const double* __restrict__ coef,
+                                                   int ncoef, double* __restrict__ Y1, double* __restrict__ resp) {
+  __shared__ double sres[4][64], szz[4][64];
+  const SubDesc& sd = subs[blockIdx.x];
+  const int64_t base = sd.offVB * b;
+  const int g = blockIdx.y;
+  const int nall = sd.NBB * TILE;
+  const int chunk = ((nall + GRAM_SPLIT * 16 - 1) / (GRAM_SPLIT * 16)) * 16;
+  const int rlo = min(g * chunk, nall), rhi = min(rlo + chunk, nall);
+  const int64_t part = (int64_t)blockIdx.x * GRAM_SPLIT + g;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const double a1 = coef[(int64_t)blockIdx.x * ncoef + 0], c = coef[(int64_t)blockIdx.x * ncoef + 1];
+  const double nk = lane < b ? nu[(int64_t)blockIdx.x * b + lane] : 0.0;
+  double rs = 0.0, zz = 0.0;
+  if (lane < b) {
+    for (int r = rlo + wid; r < rhi; r += 4) {
+      const double z = Z[base + (int64_t)r * b + lane];
+      const double v = V[base + (int64_t)r * b + lane];
+      Y1[base + (int64_t)r * b + lane] = a1 * (z - c * v);
+      if (r < sd.nB) {
+        const double d = z - nk * v;
+        rs += d * d;
+        zz += z * z;
+      }
+    }
+  }
+  sres[wid][lane] = rs;
+  szz[wid][lane] = zz;
+  __syncthreads();
+  if (threadIdx.x < b) {
+    int k = threadIdx.x;
+    resp[part * 2 * b + k] = sres[0][k] + sres[1][k] + sres[2][k] + sres[3][k];
+    resp[part * 2 * b + b + k] = szz[0][k] + szz[1][k] + szz[2][k] + szz[3][k];
+  }
+}
+
+// Y0 <- a (TY - c Y1) - beta Y0 in place (step i: coef[2 + 2(i-2)], coef[3 + 2(i-2)])
+__global__ __launch_bounds__(NT) void k_cheb_step(const SubDesc* __restrict__ subs, int b,
+                                                  const double* __restrict__ TY, const double* __restrict__ Y1,
+                                                  double* __restrict__ Y0, const double* __restrict__ coef,
+                                                  int ncoef, int step) {
+  const SubDesc& sd = subs[blockIdx.y];
+  const int64_t n = (int64_t)sd.NBB * TILE * b;
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= n) return;
+  const double* cf = coef + (int64_t)blockIdx.y * ncoef;
+  const double c = cf[1], a = cf[2 + 2 * step], beta = cf[3 + 2 * step];
+  const int64_t o = sd.offVB * b + e;
+  Y0[o] = a * (TY[o] - c * Y1[o]) - beta * Y0[o];
 }
 
 // deterministic start block: hash of (subdomain, row, col) -> (-1, 1); zero on padding
@@ -940,6 +1004,20 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, dou
 }
 
 int gram_split() { return GRAM_SPLIT; }
+
+void eig_cheb_first(const gn_precond* pc, int b, const double* Z, const double* V, const double* nu,
+                    const double* coef, int ncoef, double* Y1, double* resp, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_first, dim3(pc->n_sub, GRAM_SPLIT), dim3(NT), 0, s, pc->d_sub, b, Z, V, nu, coef,
+                     ncoef, Y1, resp);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_cheb_step(const gn_precond* pc, int b, int maxNBB, const double* TY, const double* Y1, double* Y0,
+                   const double* coef, int ncoef, int step, hipStream_t s) {
+  dim3 grid((unsigned)(((int64_t)maxNBB * TILE * b + NT - 1) / NT), pc->n_sub);
+  hipLaunchKernelGGL(k_cheb_step, grid, dim3(NT), 0, s, pc->d_sub, b, TY, Y1, Y0, coef, ncoef, step);
+  GN_CHECK_LAUNCH();
+}
 
 void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, const double* BZ,
               const double* V, const double* nu, double* GPp, double* GBp, double* resp, hipStream_t s) {

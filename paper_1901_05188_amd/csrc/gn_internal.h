@@ -211,6 +211,10 @@ void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int
                 const double* V, double* out, hipStream_t s);
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, double* V, hipStream_t s);
 int gram_split();
+void eig_cheb_first(const gn_precond* pc, int b, const double* Z, const double* V, const double* nu,
+                    const double* coef, int ncoef, double* Y1, double* resp, hipStream_t s);
+void eig_cheb_step(const gn_precond* pc, int b, int maxNBB, const double* TY, const double* Y1, double* Y0,
+                   const double* coef, int ncoef, int step, hipStream_t s);
 void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, const double* BZ,
               const double* V, const double* nu, double* GPp, double* GBp, double* resp, hipStream_t s);
 void eig_small(int n_sub, int b, const double* GPp, const double* GBp, const double* resp, double* res,
