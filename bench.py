@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--solve-reps", type=int, default=5, help="warm solves per step for latency")
     ap.add_argument("--multi-rhs", type=int, default=16,
                     help="columns of the batched multi-RHS leg (0 = skip)")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="end with a device-to-device copy of this many GiB (a reference "
+                         "kernel of known traffic for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only"}))
@@ -241,6 +244,15 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline()
+    if args.copy_calibration_gib > 0:
+        n = int(args.copy_calibration_gib * (1 << 30)) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n * 8} bytes read and written")
+        del src, dst
     print(json.dumps(res))
 
 

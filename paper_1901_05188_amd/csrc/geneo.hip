@@ -95,11 +95,21 @@ __global__ __launch_bounds__(NT) void k_extract_b(const SubDesc* __restrict__ su
 // out = B V for b columns: thread per (row, 8-column chunk)
 template <int NC>
 __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs, const double* __restrict__ BE,
-                                               int b, const double* __restrict__ V, double* __restrict__ out) {
-  const SubDesc& sd = subs[blockIdx.y];
+                                               int b, const double* __restrict__ V, double* __restrict__ out,
+                                               int gx, int ntot) {
+  // consecutive workgroups are dealt round-robin to the 8 XCDs; the 1-D grid
+  // holds 8 * per workgroups and is remapped so that each XCD walks a
+  // contiguous range of items (subdomain, row block): the neighbour rows of a
+  // block then sit in the same XCD's L2
+  const int per = (ntot + 7) / 8;
+  const int lin = blockIdx.x;
+  const int item = (lin % 8) * per + lin / 8;
+  if (item >= ntot) return;
+  const int bx = item % gx, by = item / gx;
+  const SubDesc& sd = subs[by];
   const int npad = sd.NBB * TILE;
   const int nchunk = (b + 7) / 8;
-  const int tid = blockIdx.x * NT + threadIdx.x;
+  const int tid = bx * NT + threadIdx.x;
   const int r = tid / nchunk, col0 = (tid % nchunk) * 8;
   if (r >= npad) return;
   const double* Vb = V + sd.offVB * b;
@@ -137,21 +147,20 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
 // 32 x 32 band tiles with 32 x 16 right-hand-side blocks:
 //   forward   Y_K = Dinv_K (V_K - sum_t L(K,t) Y_{K-w+t})
 //   backward  X_K = Dinv_K^T (Y_K - sum_d L(K+d,K)^T X_{K+d})
-// The columns are independent, so workgroup (j, cb) solves columns cb*16..+15 of
-// subdomain j with two waves (rows 0..15 and 16..31).  The linear workgroup id
-// j + n_sub*cb keeps every column block of a subdomain on one XCD (n_sub is
-// padded to a multiple of 8 by the launcher), so the factor stream is shared
-// through that XCD's L2.
+// The columns are independent: workgroup j holds two waves (rows 0..15 and
+// 16..31 of the block row) per 16-column block of subdomain j.  The waves of a
+// row half load the same tiles at nearly the same time, so each band tile is
+// fetched from HBM once per sweep for all column blocks.
 // v_mfma_f64_16x16x4f64 lane layout: A[l%16][l/16], B[l/16][l%16],
 // result item j of lane l = D[4j + l/16][l%16].
 // ---------------------------------------------------------------------------
 typedef double gn_d4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(128) void k_trsm_pencil(const SubDesc* __restrict__ subs, int n_sub, int b,
+__global__ __launch_bounds__(512) void k_trsm_pencil(const SubDesc* __restrict__ subs, int n_sub, int b,
                                                      const double* __restrict__ T, const double* __restrict__ D,
                                                      double* __restrict__ V) {
-  __shared__ double sS[TILE][16 + 1];
-  const int j = blockIdx.x, cb = blockIdx.y;
+  __shared__ double sSall[4][TILE][16 + 1];
+  const int j = blockIdx.x;
   if (j >= n_sub) return;
   const SubDesc& sd = subs[j];
   const int NB = sd.NBB, w = sd.wB;
@@ -159,7 +168,9 @@ __global__ __launch_bounds__(128) void k_trsm_pencil(const SubDesc* __restrict__
   const double* Db = D + sd.offDB * TILE2;
   double* Vb = V + sd.offVB * b;
   const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wid = wv & 1, cb = wv >> 1;   // row half, column block
+  double (*sS)[16 + 1] = sSall[cb];
   const int lr = lane & 15, lk = lane >> 4;
   const int rb = wid * 16;
   const int col = cb * 16 + lr;          // < 64: the buffers carry 64 doubles of tail padding
@@ -987,19 +998,22 @@ void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double
 void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int b, int maxNBB,
                 const double* V, double* out, hipStream_t s) {
   const int nchunk = (b + 7) / 8;
-  dim3 grid((maxNBB * TILE * nchunk + NT - 1) / NT, pc->n_sub);
+  const int gx = (maxNBB * TILE * nchunk + NT - 1) / NT;
+  const int ntot = gx * pc->n_sub;
+  dim3 grid((unsigned)(8 * ((ntot + 7) / 8)));
   if (p->nc == 3)
-    hipLaunchKernelGGL(k_bapply<3>, grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out);
+    hipLaunchKernelGGL(k_bapply<3>, grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out, gx, ntot);
   else
-    hipLaunchKernelGGL(k_bapply<1>, grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out);
+    hipLaunchKernelGGL(k_bapply<1>, grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out, gx, ntot);
   GN_CHECK_LAUNCH();
 }
 
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, double* V, hipStream_t s) {
   if (b > 64) throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
-  // grid.x padded to a multiple of 8 so (j, cb) and (j, cb') share an XCD
-  const int gx = (pc->n_sub + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_trsm_pencil, dim3(gx, (b + 15) / 16), dim3(128), 0, s, pc->d_sub, pc->n_sub, b, T, D, V);
+  // one workgroup per subdomain, two waves (row halves) per 16-column block: the
+  // waves of a row half read the same band tiles, so each tile leaves HBM once
+  hipLaunchKernelGGL(k_trsm_pencil, dim3(pc->n_sub), dim3(128 * ((b + 15) / 16)), 0, s, pc->d_sub, pc->n_sub, b,
+                     T, D, V);
   GN_CHECK_LAUNCH();
 }
 
