@@ -236,6 +236,7 @@ def main():
         "eig_iters": pc.report["eig_iters"],
         "cond_est": rep["cond_est"],
         "true_rel_res": rep["true_rel_res"],
+        "res_floor": rep["res_floor"],
         "kernel_groups_ms_per_solve": {k: v["ms_total"] / args.solve_reps for k, v in groups.items()},
         "roofline": roof,
     }

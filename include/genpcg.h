@@ -126,7 +126,10 @@ gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t n
  * nev_max + 8, at most 64); a given value must lie in [(nev or nev_max) + 5, 64].
  * eig_filter is the largest Chebyshev filter degree per Rayleigh-Ritz step
  * (0 = 4; 1 = plain subspace iteration); the degree ramps up 1, 2, ... from the
- * first step. */
+ * first step.
+ * local_kernel selects the kernel of single-column local solves: 0 = automatic
+ * (the register-pipelined sweep when the band fits it), 1 = always the
+ * 16-column matrix-core kernel of the batched solves. */
 typedef struct gn_dd_opts {
   int32_t nparts[3];
   const int32_t* cuts[3];
@@ -141,6 +144,7 @@ typedef struct gn_dd_opts {
   int32_t eig_maxit;
   int32_t eig_block;
   int32_t eig_filter;
+  int32_t local_kernel;
 } gn_dd_opts;
 
 typedef struct gn_setup_report {
@@ -189,7 +193,10 @@ typedef struct gn_solve_report {
   double cond_est;      /* extreme eigenvalue ratio of the CG-Lanczos tridiagonal */
   double t_solve_s;
   int32_t iters_first;  /* iterations of the first (un-restarted) CG sequence   */
-  int32_t restarts;     /* restarts from b - A x taken to meet rtol on the true residual */
+  int32_t restarts;     /* restarts from b - A x taken to meet rtol on the true residual
+                           (at most 2; none once ||b - A x|| <= 4 eps || |A| |x| ||)  */
+  double res_floor;     /* eps || |A| |x| || / ||b||: rounding floor of the true
+                           residual of an FP64 solution                          */
 } gn_solve_report;
 
 /* Solve A x = b by PCG with x0 = 0 for nrhs columns (device pointers, free

@@ -51,7 +51,7 @@ class gn_dd_opts(C.Structure):
                 ("overlap", C.c_int32), ("nev", C.c_int32), ("threshold", C.c_double),
                 ("nev_max", C.c_int32), ("local_prec", C.c_int32), ("coarse", C.c_int32),
                 ("shift", C.c_double), ("eig_tol", C.c_double), ("eig_maxit", C.c_int32),
-                ("eig_block", C.c_int32), ("eig_filter", C.c_int32)]
+                ("eig_block", C.c_int32), ("eig_filter", C.c_int32), ("local_kernel", C.c_int32)]
 
 
 class gn_setup_report(C.Structure):
@@ -70,7 +70,7 @@ class gn_solve_opts(C.Structure):
 class gn_solve_report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_res", C.c_double),
                 ("true_rel_res", C.c_double), ("cond_est", C.c_double), ("t_solve_s", C.c_double),
-                ("iters_first", C.c_int32), ("restarts", C.c_int32)]
+                ("iters_first", C.c_int32), ("restarts", C.c_int32), ("res_floor", C.c_double)]
 
 
 _lib = None
@@ -218,7 +218,7 @@ class Preconditioner:
 
     def __init__(self, prob: Problem, nparts: Sequence[int], cuts, overlap=1, nev=0, threshold=0.0,
                  nev_max=0, local_prec=64, coarse=True, shift=0.0, eig_tol=0.0, eig_maxit=0,
-                 eig_block=0, eig_filter=0, stream=None):
+                 eig_block=0, eig_filter=0, local_kernel=0, stream=None):
         o = gn_dd_opts()
         keep = []
         for a in range(3):
@@ -230,6 +230,7 @@ class Preconditioner:
         o.local_prec, o.coarse = int(local_prec), int(bool(coarse))
         o.shift, o.eig_tol, o.eig_maxit = float(shift), float(eig_tol), int(eig_maxit)
         o.eig_block, o.eig_filter = int(eig_block), int(eig_filter)
+        o.local_kernel = int(local_kernel)
         rep = gn_setup_report()
         h = C.c_void_p()
         _check(lib().gn_setup_geneo(prob.handle, C.byref(o), _stream(stream), C.byref(h), C.byref(rep)))

@@ -381,6 +381,8 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   pc->n_sub = n_sub;
   pc->overlap = O;
   pc->local_prec = o->local_prec;
+  if (o->local_kernel < 0 || o->local_kernel > 1) argfail("local_kernel must be 0 or 1");
+  pc->local_kernel = o->local_kernel;
   for (int a = 0; a < 3; ++a) {
     pc->nparts[a] = o->nparts[a];
     pc->cuts[a].assign(o->cuts[a], o->cuts[a] + o->nparts[a] + 1);
@@ -850,12 +852,22 @@ extern "C" gn_status gn_precond_eigenvalues(const gn_precond* pc, int32_t sub, d
   return GN_OK;
 }
 
+static void ensure_batch_precond(gn_precond* pc, hipStream_t s);
+
 // z = M^-1 r on full-numbering device vectors
 static void precond_full(gn_problem* p, gn_precond* pc, const double* r, double* z, double* part,
                          const double* done, hipStream_t s) {
-  gnk::local_solve(p, pc, r, done, s);
-  gnk::coarse_solve(pc, done, s);
-  gnk::prolong(p, pc, r, z, part, done, s);
+  if (gnk::pf_supported(p, pc)) {
+    gnk::local_solve(p, pc, r, done, s);
+    gnk::coarse_solve(pc, done, s);
+    gnk::prolong(p, pc, r, z, part, done, s);
+  } else {
+    // bands too wide for the single-column register pipeline: the batched
+    // kernels with one live column (done sits at S_DONE of the scalar block)
+    ensure_batch_precond(pc, s);
+    gnk::precond_mc(p, pc, r, z, 1, part, 0, done ? done - S_DONE : nullptr, pc->d_tm, pc->d_gm, pc->d_um,
+                    pc->d_ym, s);
+  }
 }
 
 extern "C" gn_status gn_precond_apply(gn_precond* pc, const double* r_dev, double* z_dev, void* stream) {
@@ -874,6 +886,22 @@ extern "C" gn_status gn_precond_apply(gn_precond* pc, const double* r_dev, doubl
 // ---------------------------------------------------------------------------
 // PCG
 // ---------------------------------------------------------------------------
+
+// || |A| |x| ||^2 for one full-numbering vector: eps times its square root is
+// the rounding floor of b - A x for any FP64 x near x (attainable accuracy)
+static double absmv_norm2(gn_problem* p, const double* x, hipStream_t s) {
+  const int nb = gnk::spmv_blocks(p);
+  std::vector<double> part(nb);
+  gnk::absmv_partial(p, x, p->d_part, s);
+  GN_HIP(hipMemcpyAsync(part.data(), p->d_part, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  GN_HIP(hipStreamSynchronize(s));
+  double t = 0.0;
+  for (double v : part) t += v;
+  return t;
+}
+// restarts stop once b - A x is within this factor of eps || |A| |x| ||
+static constexpr double kFloorFactor = 4.0;
+static constexpr double kEps = 2.220446049250313e-16;
 
 // CG-Lanczos tridiagonal of the first kit steps: T_ii = 1/a_i + b_{i-1}/a_{i-1},
 // T_{i,i+1} = sqrt(b_i)/a_i; returns its extreme eigenvalue ratio
@@ -914,15 +942,19 @@ static void ensure_batch_workspace(gn_problem* p, gn_precond* pc, int maxit, hip
     p->histm_stride = 2 * maxit + 2;
     p->d_histm = dalloc<double>(p->owned, (size_t)p->histm_stride * KC);
   }
-  if (pc && !pc->d_tm) {
-    pc->d_tm = dalloc<double>(pc->owned, (size_t)pc->vecI * KC);
-    GN_HIP(hipMemsetAsync(pc->d_tm, 0, sizeof(double) * pc->vecI * KC, s));
-    const size_t nh = (size_t)std::max(pc->NBH, 1) * TILE * KC;
-    pc->d_gm = dalloc<double>(pc->owned, nh);
-    pc->d_um = dalloc<double>(pc->owned, nh);
-    pc->d_ym = dalloc<double>(pc->owned, nh);
-    for (double* v : {pc->d_gm, pc->d_um, pc->d_ym}) GN_HIP(hipMemsetAsync(v, 0, sizeof(double) * nh, s));
-  }
+  if (pc) ensure_batch_precond(pc, s);
+}
+
+static void ensure_batch_precond(gn_precond* pc, hipStream_t s) {
+  if (pc->d_tm) return;
+  const int KC = gnk::mc_width();
+  pc->d_tm = dalloc<double>(pc->owned, (size_t)pc->vecI * KC);
+  GN_HIP(hipMemsetAsync(pc->d_tm, 0, sizeof(double) * pc->vecI * KC, s));
+  const size_t nh = (size_t)std::max(pc->NBH, 1) * TILE * KC;
+  pc->d_gm = dalloc<double>(pc->owned, nh);
+  pc->d_um = dalloc<double>(pc->owned, nh);
+  pc->d_ym = dalloc<double>(pc->owned, nh);
+  for (double* v : {pc->d_gm, pc->d_um, pc->d_ym}) GN_HIP(hipMemsetAsync(v, 0, sizeof(double) * nh, s));
 }
 
 // k <= 16 columns of one batch: each column runs its own CG recurrence, the
@@ -982,8 +1014,9 @@ static gn_status solve_batch(gn_problem* p, gn_precond* pc, const double* b_dev,
   };
   // ||b_c - A x_c||^2 per column; leaves A x in Q and b (full numbering) in Zv
   std::vector<double> hpart((size_t)ps * k);
-  std::vector<double> tr(k, 0.0);
+  std::vector<double> tr(k, 0.0), floor2(k, 0.0);
   auto true_residual = [&]() {
+    for (int c = 0; c < k; ++c) floor2[c] = kEps * kEps * absmv_norm2(p, X + c * n, s);
     gnk::spmv_mc(p, X, Q, k, nullptr, ps, nullptr, s);
     for (int c = 0; c < k; ++c) gnk::scatter_free(p, b_dev + (c0 + c) * ld, Zv + c * n, s);
     gnk::sub_mc(n, k, Zv, Q, nullptr, part, ps, s);
@@ -1007,7 +1040,8 @@ static gn_status solve_batch(gn_problem* p, gn_precond* pc, const double* b_dev,
     bool any = false;
     for (int c = 0; c < k; ++c) {
       const double* h = &fin_hs[(size_t)c * S_N];
-      again[c] = h[S_BREAK] == 0.0 && h[S_BB] > 0.0 && tr[c] > h[S_TOL2] && (int)h[S_ITER] < opts->maxit;
+      again[c] = h[S_BREAK] == 0.0 && h[S_BB] > 0.0 && tr[c] > h[S_TOL2] &&
+                 tr[c] > kFloorFactor * kFloorFactor * floor2[c] && (int)h[S_ITER] < opts->maxit;
       any |= again[c] != 0;
     }
     if (!any) break;
@@ -1044,6 +1078,7 @@ static gn_status solve_batch(gn_problem* p, gn_precond* pc, const double* b_dev,
       Rp.converged = conv ? 1 : 0;
       Rp.rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
       Rp.true_rel_res = bb > 0 ? std::sqrt(tr[c] / bb) : 0.0;
+      Rp.res_floor = bb > 0 ? std::sqrt(floor2[c] / bb) : 0.0;
       Rp.t_solve_s = tsolve;
       Rp.iters_first = first_iters[c];
       Rp.restarts = restarts[c];
@@ -1131,7 +1166,9 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
     };
     // ||b - A x||^2, leaving A x in q and b (full numbering) in z
     std::vector<double> part(nbr);
+    double floor2 = 0.0;   // (eps || |A| |x| ||)^2
     auto true_residual = [&]() {
+      floor2 = kEps * kEps * absmv_norm2(p, p->d_x, s);
       gnk::spmv_flag(p, p->d_x, p->d_q, nullptr, nullptr, s);
       gnk::scatter_free(p, b_dev + col * ld, p->d_z, s);
       gnk::residual_partial(n, p->d_z, p->d_q, p->d_part, s);
@@ -1145,9 +1182,11 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
     const int first_iters = iters;
     double tr = true_residual();
     // the recursive residual drifts from b - A x (attainable accuracy of CG):
-    // restart from the current iterate with the true residual, at most twice
+    // restart from the current iterate with the true residual, at most twice,
+    // unless b - A x already sits at the rounding floor of FP64 x
     int restarts = 0;
-    for (; restarts < 2 && hs[S_BREAK] == 0.0 && hs[S_BB] > 0.0 && tr > hs[S_TOL2] && iters < opts->maxit;
+    for (; restarts < 2 && hs[S_BREAK] == 0.0 && hs[S_BB] > 0.0 && tr > hs[S_TOL2] &&
+           tr > kFloorFactor * kFloorFactor * floor2 && iters < opts->maxit;
          ++restarts) {
       gnk::sub_partial(n, p->d_z, p->d_q, p->d_r, p->d_part, s);   // r = b - A x
       gnk::finalize(p->d_part, nbr, OP_RESTART, scal, p->d_hist, opts->rtol, s);
@@ -1180,6 +1219,7 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
       R.converged = conv ? 1 : 0;
       R.rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
       R.true_rel_res = bb > 0 ? std::sqrt(tr / bb) : 0.0;
+      R.res_floor = bb > 0 ? std::sqrt(floor2 / bb) : 0.0;
       R.t_solve_s = tsolve;
       R.iters_first = first_iters;
       R.restarts = restarts;

@@ -114,6 +114,7 @@ struct gn_precond {
   std::vector<SubDesc> sub;
   SubDesc* d_sub = nullptr;
   int local_prec = 64;
+  int local_kernel = 0;        // 0 automatic, 1 batched matrix-core kernel for single columns
   // per-axis node coverage (PoU counts) and part ranges for the gather-form prolongation
   int* d_cnt[3] = {nullptr, nullptr, nullptr};   // #parts whose I-range holds node index
   int* d_plo[3] = {nullptr, nullptr, nullptr};   // first such part
@@ -161,6 +162,7 @@ void assemble_load(gn_problem* p, const double* d_body, const double* d_trac, hi
 void spmv_flag(const gn_problem* p, const double* x, double* y, double* part, const double* done,
                hipStream_t s);
 int spmv_blocks(const gn_problem* p);
+void absmv_partial(const gn_problem* p, const double* x, double* part, hipStream_t s);
 void scatter_free(const gn_problem* p, const double* xf, double* xfull, hipStream_t s);
 void gather_free(const gn_problem* p, const double* xfull, double* xf, hipStream_t s);
 int reduce_blocks();
@@ -181,6 +183,7 @@ void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, dou
 void band_chol(const void* d_refs, int n, double* T, double* D, int* info, hipStream_t s);
 void to_f32(int64_t n, const double* a, float* b, hipStream_t s);
 // precond.hip
+bool pf_supported(const gn_problem* p, const gn_precond* pc);
 void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, const double* done,
                  hipStream_t s);
 void coarse_solve(const gn_precond* pc, const double* done, hipStream_t s);

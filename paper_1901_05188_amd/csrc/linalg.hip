@@ -62,6 +62,37 @@ __global__ __launch_bounds__(256) void k_spmv(int NX, int NY, int NZ, const doub
   }
 }
 
+// partial sums of (sum_j |A_ij| |x_j|)^2 over rows: the scale of the rounding
+// error of any FP64 evaluation of A x, eps * || |A| |x| ||
+template <int NC>
+__global__ __launch_bounds__(256) void k_absmv(int NX, int NY, int NZ, const double* __restrict__ A,
+                                               const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double sh[16];
+  const int64_t n_node = (int64_t)NX * NY * NZ;
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (node < n_node) {
+    int i = (int)(node % NX), j = (int)((node / NX) % NY), k = (int)(node / ((int64_t)NX * NY));
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int d = 0; d < 27; ++d) {
+      const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+      if (i + dx < 0 || i + dx >= NX || j + dy < 0 || j + dy >= NY || k + dz < 0 || k + dz >= NZ) continue;
+      const int64_t nb = node + dx + (int64_t)NX * (dy + (int64_t)NY * dz);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2)
+          acc[c] += fabs(A[((int64_t)(d * NC + c) * NC + c2) * n_node + node]) * fabs(x[nb * NC + c2]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v += acc[c] * acc[c];
+  }
+  double s = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 __global__ void k_scatter_free(int64_t n_free, const int* __restrict__ f2f, const double* __restrict__ xf,
                                double* __restrict__ xfull) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -93,6 +124,15 @@ void spmv_flag(const gn_problem* p, const double* x, double* y, double* part, co
 }
 
 int spmv_blocks(const gn_problem* p) { return (int)((p->n_node + 255) / 256); }
+
+void absmv_partial(const gn_problem* p, const double* x, double* part, hipStream_t s) {
+  dim3 grid((unsigned)((p->n_node + 255) / 256));
+  if (p->nc == 3)
+    hipLaunchKernelGGL(k_absmv<3>, grid, dim3(256), 0, s, p->nn[0], p->nn[1], p->nn[2], p->d_A, x, part);
+  else
+    hipLaunchKernelGGL(k_absmv<1>, grid, dim3(256), 0, s, p->nn[0], p->nn[1], p->nn[2], p->d_A, x, part);
+  GN_CHECK_LAUNCH();
+}
 
 void scatter_free(const gn_problem* p, const double* xf, double* xfull, hipStream_t s) {
   GN_HIP(hipMemsetAsync(xfull, 0, sizeof(double) * p->n_dof, s));

@@ -3,10 +3,11 @@
 // (Section 3.1, eqn:onelevelAS and M^-1_{AS,2}; Section 3.3.3 for the coarse
 // restriction (R_H v)_i = Phi_i^T v and the prolongation R_H^T v_H).
 //
-// k_local_solve: one workgroup per subdomain gathers r on its node box (R_j is a
-//   box gather in the structured numbering), forms Phi_j^T r_j, and runs the
-//   forward and backward banded triangular solves with the subdomain vector
-//   held in LDS.
+// k_local_solve_pf: one workgroup per subdomain gathers r on its node box (R_j
+//   is a box gather in the structured numbering), forms Phi_j^T r_j, and runs
+//   the forward and backward banded triangular solves with the subdomain
+//   vector held in LDS.  Bands too wide for its register pipeline go through
+//   the multi-column kernels of multi.hip with one live column.
 // k_coarse_fwd / k_coarse_bwd: y = Z^T (Z g) with Z = L_H^-1 stored as dense
 //   tiles (the coarse factor inverse), one workgroup per tile row / column.
 // k_prolong: gather-form sum z = sum_j R_j^T (t_j + Phi_j y_j): each output DOF
@@ -18,143 +19,6 @@ namespace {
 
 constexpr int NT = 256;
 
-template <typename FT>
-struct FactorPtr {
-  const FT* T;
-  const FT* D;
-};
-
-template <typename FT, int NC, bool LDSVEC>
-__global__ __launch_bounds__(NT) void k_local_solve(const SubDesc* __restrict__ subs, int NX, int NY,
-                                                    const double* __restrict__ r, const FT* __restrict__ T,
-                                                    const FT* __restrict__ D, double* __restrict__ tvec,
-                                                    const double* __restrict__ Phi, double* __restrict__ g,
-                                                    const double* __restrict__ done) {
-  extern __shared__ double smem[];
-  __shared__ double red[8][TILE + 1];
-  __shared__ double sv[TILE];
-  if (done && *done != 0.0) return;
-  const SubDesc& sd = subs[blockIdx.x];
-  const int NB = sd.NBI, w = sd.wI;
-  const int npad = NB * TILE;
-  double* vec = LDSVEC ? smem : (tvec + sd.offVI);
-  // gather r_j = R_j r
-  for (int row = threadIdx.x; row < npad; row += NT) {
-    double v = 0.0;
-    if (row < sd.nI) {
-      int gn[3];
-      box_global_node(sd.ilo, sd.in_, sd.permI, row / NC, gn);
-      int64_t node = gn[0] + (int64_t)NX * (gn[1] + (int64_t)NY * gn[2]);
-      v = r[node * NC + row % NC];
-    }
-    vec[row] = v;
-  }
-  __syncthreads();
-  // coarse restriction g_j = Phi_j^T r_j
-  if (Phi && sd.m > 0) {
-    const double* ph = Phi + sd.offPhi;
-    for (int k0 = 0; k0 < sd.m; k0 += 8) {
-      double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      for (int row = threadIdx.x; row < sd.nI; row += NT) {
-        double v = vec[row];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (k0 + q < sd.m) acc[q] += ph[(int64_t)row * sd.m + k0 + q] * v;
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        double s = block_sum(acc[q], &red[0][0]);
-        if (threadIdx.x == 0 && k0 + q < sd.m) g[sd.coff + k0 + q] = s;
-      }
-    }
-    __syncthreads();
-  }
-  const int i = threadIdx.x % TILE, part = threadIdx.x / TILE;
-  const FT* Tb = T + sd.offTI * TILE2;
-  const FT* Db = D + sd.offDI * TILE2;
-  // forward: y_K = Dinv_K (r_K - sum_t L(K,t) y_{K-w+t})
-  for (int K = 0; K < NB; ++K) {
-    double acc = 0.0;
-    for (int t = part; t < w; t += 8) {
-      int J = K - w + t;
-      if (J < 0) continue;
-      const FT* tile = Tb + ((int64_t)K * (w + 1) + t) * TILE2;
-      const double* yj = vec + J * TILE;
-#pragma unroll 8
-      for (int c = 0; c < TILE; ++c) acc += (double)tile[c * TILE + i] * yj[c];
-    }
-    red[part][i] = acc;
-    __syncthreads();
-    if (threadIdx.x < TILE) {
-      double s = vec[K * TILE + i];
-#pragma unroll
-      for (int p2 = 0; p2 < 8; ++p2) s -= red[p2][i];
-      sv[i] = s;
-    }
-    __syncthreads();
-    {
-      const FT* dk = Db + (int64_t)K * TILE2;
-      double a2 = 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int c = part * 4 + q;
-        a2 += (double)dk[c * TILE + i] * sv[c];
-      }
-      red[part][i] = a2;
-    }
-    __syncthreads();
-    if (threadIdx.x < TILE) {
-      double s = 0.0;
-#pragma unroll
-      for (int p2 = 0; p2 < 8; ++p2) s += red[p2][i];
-      vec[K * TILE + i] = s;
-    }
-    __syncthreads();
-  }
-  // backward: x_K = Dinv_K^T (y_K - sum_d L(K+d, w-d)^T x_{K+d})
-  for (int K = NB - 1; K >= 0; --K) {
-    double acc = 0.0;
-    for (int d = 1 + part; d <= w; d += 8) {
-      if (K + d >= NB) continue;
-      const FT* tile = Tb + ((int64_t)(K + d) * (w + 1) + (w - d)) * TILE2;
-      const double* xj = vec + (K + d) * TILE;
-      // column i of the tile (contiguous)
-#pragma unroll 8
-      for (int rr = 0; rr < TILE; ++rr) acc += (double)tile[i * TILE + rr] * xj[rr];
-    }
-    red[part][i] = acc;
-    __syncthreads();
-    if (threadIdx.x < TILE) {
-      double s = vec[K * TILE + i];
-#pragma unroll
-      for (int p2 = 0; p2 < 8; ++p2) s -= red[p2][i];
-      sv[i] = s;
-    }
-    __syncthreads();
-    {
-      const FT* dk = Db + (int64_t)K * TILE2;
-      double a2 = 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int rr = part * 4 + q;
-        a2 += (double)dk[i * TILE + rr] * sv[rr];   // Dinv^T: (i, rr) <- Dinv(rr, i)
-      }
-      red[part][i] = a2;
-    }
-    __syncthreads();
-    if (threadIdx.x < TILE) {
-      double s = 0.0;
-#pragma unroll
-      for (int p2 = 0; p2 < 8; ++p2) s += red[p2][i];
-      vec[K * TILE + i] = s;
-    }
-    __syncthreads();
-  }
-  if (LDSVEC) {
-    double* out = tvec + sd.offVI;
-    for (int row = threadIdx.x; row < npad; row += NT) out[row] = vec[row];
-  }
-}
 
 // Barrier that orders LDS traffic only: outstanding global loads (the prefetch of
 // the next block row) stay in flight across it.
@@ -164,13 +28,13 @@ __device__ inline void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Pipelined variant of k_local_solve.  Thread (i, gq) owns, in every block row,
+// Banded forward/backward solves, one subdomain per workgroup.  Thread (i, gq) owns, in every block row,
 // the 4w band entries of row i in columns 4gq..4gq+3 of each off-diagonal tile
 // (forward) or rows 4gq..4gq+3 of column i (backward), plus 4 entries of the
 // inverse diagonal tile; the next block row's entries are loaded into registers
 // while the current one is reduced, and only LDS-ordering barriers separate the
 // steps.  The subdomain vector lives in LDS with w zero tiles of padding on both
-// sides, so no step needs a bounds branch.  SP >= 4w register slots.
+// sides, so no step needs a bounds branch.  SP >= 2w register slots per buffer.
 template <typename FT, int NC, int SP, int G>
 __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __restrict__ subs, int NX, int NY,
                                                            const double* __restrict__ r, const FT* __restrict__ T,
@@ -225,97 +89,107 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
   const FT* Tb = T + sd.offTI * TILE2;
   const FT* Db = D + sd.offDI * TILE2;
   const int ns = CW * w;
-  FT lv[SP], dv[CW], dn[CW];
+  // Two register buffers: block row K is consumed from one while the loads of
+  // rows K+1 (other buffer, issued one step earlier) and K+2 (this buffer,
+  // issued right after the consumption) are in flight.
+  FT lv0[SP], lv1[SP], dn0[CW], dn1[CW];
+  double dv[CW];
   // Slots u < CW*w address band entries; the rest read a shared zero tile, so
   // every load is unconditional and the unrolled loops carry no branches.
-  // Single-buffer pipeline: the registers of row K are consumed, then reissued
-  // for the next row, whose loads overlap the three reduction barriers.
   // ---- forward ----
-#define GN_LOAD_FWD(K_)                                                                  \
+#define GN_LOAD_FWD(K_, LV, DN)                                                          \
   {                                                                                      \
     const FT* rowp = Tb + (int64_t)(K_) * (w + 1) * TILE2;                               \
     _Pragma("unroll") for (int u = 0; u < SP; ++u) {                                     \
       int t = u / CW, c = CW * gq + (u % CW);                                            \
       const FT* src = (u < ns) ? rowp + (t * TILE + c) * TILE + i : Z0 + i;              \
-      lv[u] = *src;                                                                      \
+      LV[u] = *src;                                                                      \
     }                                                                                    \
     const FT* dk = Db + (int64_t)(K_) * TILE2;                                           \
-    _Pragma("unroll") for (int q = 0; q < CW; ++q) dn[q] = dk[(CW * gq + q) * TILE + i]; \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[(CW * gq + q) * TILE + i]; \
   }
-  GN_LOAD_FWD(0)
-  for (int K = 0; K < NB; ++K) {
-    const double* yw = vec + (K - w) * TILE + CW * gq;
-    double acc = 0.0;
-#pragma unroll
-    for (int u = 0; u < SP; ++u) acc += (double)lv[u] * yw[(u / CW) * TILE + (u % CW)];
-#pragma unroll
-    for (int q = 0; q < CW; ++q) dv[q] = dn[q];
-    GN_LOAD_FWD(min(K + 1, NB - 1))
-    red[gq][i] = acc;
-    lds_barrier();
-    double part = 0.0;
-#pragma unroll
-    for (int q = 0; q < CW; ++q) {
-      int c = CW * gq + q;
-      double s = vec[K * TILE + c];
-#pragma unroll
-      for (int g2 = 0; g2 < G; ++g2) s -= red[g2][c];
-      part += (double)dv[q] * s;
-    }
-    red2[gq][i] = part;
-    lds_barrier();
-    if (gq == 0) {
-      double y = 0.0;
-#pragma unroll
-      for (int g2 = 0; g2 < G; ++g2) y += red2[g2][i];
-      vec[K * TILE + i] = y;
-    }
-    lds_barrier();
+#define GN_STEP_FWD(K_, LV, DN)                                                          \
+  {                                                                                      \
+    const int KK = (K_);                                                                 \
+    const double* yw = vec + (KK - w) * TILE + CW * gq;                                  \
+    double acc = 0.0;                                                                    \
+    _Pragma("unroll") for (int u = 0; u < SP; ++u)                                       \
+      acc += (double)LV[u] * yw[(u / CW) * TILE + (u % CW)];                             \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) dv[q] = (double)DN[q];                \
+    GN_LOAD_FWD(min(KK + 2, NB - 1), LV, DN)                                             \
+    red[gq][i] = acc;                                                                    \
+    lds_barrier();                                                                       \
+    double part = 0.0;                                                                   \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) {                                     \
+      int c = CW * gq + q;                                                               \
+      double sv = vec[KK * TILE + c];                                                    \
+      _Pragma("unroll") for (int g2 = 0; g2 < G; ++g2) sv -= red[g2][c];                 \
+      part += dv[q] * sv;                                                                \
+    }                                                                                    \
+    red2[gq][i] = part;                                                                  \
+    lds_barrier();                                                                       \
+    if (gq == 0) {                                                                       \
+      double y = 0.0;                                                                    \
+      _Pragma("unroll") for (int g2 = 0; g2 < G; ++g2) y += red2[g2][i];                 \
+      vec[KK * TILE + i] = y;                                                            \
+    }                                                                                    \
+    lds_barrier();                                                                       \
   }
+  GN_LOAD_FWD(0, lv0, dn0)
+  GN_LOAD_FWD(min(1, NB - 1), lv1, dn1)
+  for (int K = 0; K < NB; K += 2) {
+    GN_STEP_FWD(K, lv0, dn0)
+    if (K + 1 < NB) GN_STEP_FWD(K + 1, lv1, dn1)
+  }
+#undef GN_STEP_FWD
 #undef GN_LOAD_FWD
   // ---- backward ----
-#define GN_LOAD_BWD(K_)                                                                  \
+#define GN_LOAD_BWD(K_, LV, DN)                                                          \
   {                                                                                      \
     _Pragma("unroll") for (int u = 0; u < SP; ++u) {                                     \
       int d = (u / CW) + 1, rr = CW * gq + (u % CW);                                     \
       int kk = min((K_) + d, NB - 1);                                                    \
       const FT* src = (u < ns) ? Tb + ((int64_t)kk * (w + 1) + (w - d)) * TILE2 + i * TILE + rr \
                                : Z0 + i;                                                 \
-      lv[u] = *src;                                                                      \
+      LV[u] = *src;                                                                      \
     }                                                                                    \
     const FT* dk = Db + (int64_t)(K_) * TILE2;                                           \
-    _Pragma("unroll") for (int q = 0; q < CW; ++q) dn[q] = dk[i * TILE + CW * gq + q];   \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[i * TILE + CW * gq + q];   \
   }
-  GN_LOAD_BWD(NB - 1)
-  for (int K = NB - 1; K >= 0; --K) {
-    const double* xw = vec + (K + 1) * TILE + CW * gq;
-    double acc = 0.0;
-#pragma unroll
-    for (int u = 0; u < SP; ++u) acc += (double)lv[u] * xw[(u / CW) * TILE + (u % CW)];
-#pragma unroll
-    for (int q = 0; q < CW; ++q) dv[q] = dn[q];
-    GN_LOAD_BWD(max(K - 1, 0))
-    red[gq][i] = acc;
-    lds_barrier();
-    double part = 0.0;
-#pragma unroll
-    for (int q = 0; q < CW; ++q) {
-      int rr = CW * gq + q;
-      double s = vec[K * TILE + rr];
-#pragma unroll
-      for (int g2 = 0; g2 < G; ++g2) s -= red[g2][rr];
-      part += (double)dv[q] * s;
-    }
-    red2[gq][i] = part;
-    lds_barrier();
-    if (gq == 0) {
-      double x = 0.0;
-#pragma unroll
-      for (int g2 = 0; g2 < G; ++g2) x += red2[g2][i];
-      vec[K * TILE + i] = x;
-    }
-    lds_barrier();
+#define GN_STEP_BWD(K_, LV, DN)                                                          \
+  {                                                                                      \
+    const int KK = (K_);                                                                 \
+    const double* xw = vec + (KK + 1) * TILE + CW * gq;                                  \
+    double acc = 0.0;                                                                    \
+    _Pragma("unroll") for (int u = 0; u < SP; ++u)                                       \
+      acc += (double)LV[u] * xw[(u / CW) * TILE + (u % CW)];                             \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) dv[q] = (double)DN[q];                \
+    GN_LOAD_BWD(max(KK - 2, 0), LV, DN)                                                  \
+    red[gq][i] = acc;                                                                    \
+    lds_barrier();                                                                       \
+    double part = 0.0;                                                                   \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) {                                     \
+      int rr = CW * gq + q;                                                              \
+      double sv = vec[KK * TILE + rr];                                                   \
+      _Pragma("unroll") for (int g2 = 0; g2 < G; ++g2) sv -= red[g2][rr];                \
+      part += dv[q] * sv;                                                                \
+    }                                                                                    \
+    red2[gq][i] = part;                                                                  \
+    lds_barrier();                                                                       \
+    if (gq == 0) {                                                                       \
+      double x = 0.0;                                                                    \
+      _Pragma("unroll") for (int g2 = 0; g2 < G; ++g2) x += red2[g2][i];                 \
+      vec[KK * TILE + i] = x;                                                            \
+    }                                                                                    \
+    lds_barrier();                                                                       \
   }
+  GN_LOAD_BWD(NB - 1, lv0, dn0)
+  GN_LOAD_BWD(max(NB - 2, 0), lv1, dn1)
+  for (int K = NB - 1; K >= 0; K -= 2) {
+    GN_STEP_BWD(K, lv0, dn0)
+    if (K - 1 >= 0) GN_STEP_BWD(K - 1, lv1, dn1)
+  }
+#undef GN_STEP_BWD
 #undef GN_LOAD_BWD
   __syncthreads();
   double* out = tvec + sd.offVI;
@@ -440,8 +314,7 @@ void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, con
   // zero tiles on both sides of the LDS vector: covers every window read, which
   // reaches at most SP / 2 <= maxw + 16 tiles past either end
   const int padw = pc->maxwI + 16;
-  // register budget: up to SP = 32 slots (band of at most 16 tiles) fit without spills
-  if ((pc->maxNBI + 2 * padw) * TILE <= max_lds_doubles() && need_sp <= 32) {
+  if (pf_supported(p, pc)) {
     size_t dynpf = (size_t)(pc->maxNBI + 2 * padw) * TILE * sizeof(double);
 #define GN_PF(FT, NC, SPV)                                                                        \
   do {                                                                                            \
@@ -457,41 +330,35 @@ void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, con
   } while (0)
 #define GN_PF_SP(FT, NC)                                  \
   do {                                                    \
-    if (need_sp <= 16) GN_PF(FT, NC, 16);                 \
+    if (need_sp <= 8) GN_PF(FT, NC, 8);                   \
+    else if (need_sp <= 12) GN_PF(FT, NC, 12);            \
+    else if (need_sp <= 16) GN_PF(FT, NC, 16);            \
+    else if (need_sp <= 20) GN_PF(FT, NC, 20);            \
+    else if (need_sp <= 24) GN_PF(FT, NC, 24);            \
     else GN_PF(FT, NC, 32);                               \
   } while (0)
     if (f32) {
       if (p->nc == 3) GN_PF_SP(float, 3); else GN_PF_SP(float, 1);
     } else {
-      if (p->nc == 3) GN_PF_SP(double, 3); else GN_PF_SP(double, 1);
+      if (p->nc == 3) GN_PF_SP(double, 3); else GN_PF_SP(double, 1);   // SP <= 20 here
     }
 #undef GN_PF_SP
 #undef GN_PF
     GN_CHECK_LAUNCH();
     return;
   }
-  size_t lds = (size_t)pc->maxNBI * TILE * sizeof(double);
-  bool ldsvec = pc->maxNBI * TILE <= max_lds_doubles();
-  size_t dyn = ldsvec ? lds : 0;
-#define GN_LS(FT, NC, L)                                                                         \
-  do {                                                                                           \
-    auto kfn = k_local_solve<FT, NC, L>;                                                         \
-    if (L) GN_HIP(hipFuncSetAttribute((const void*)kfn,                                          \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));    \
-    hipLaunchKernelGGL(kfn, dim3(pc->n_sub), dim3(NT), dyn, s, pc->d_sub, p->nn[0], p->nn[1], r, \
-                       (const FT*)(f32 ? (const void*)pc->d_LIf : (const void*)pc->d_LI),        \
-                       (const FT*)(f32 ? (const void*)pc->d_DIf : (const void*)pc->d_DI),        \
-                       pc->d_t, Phi, pc->d_g, done);                                             \
-  } while (0)
-  if (f32) {
-    if (p->nc == 3) { if (ldsvec) GN_LS(float, 3, true); else GN_LS(float, 3, false); }
-    else { if (ldsvec) GN_LS(float, 1, true); else GN_LS(float, 1, false); }
-  } else {
-    if (p->nc == 3) { if (ldsvec) GN_LS(double, 3, true); else GN_LS(double, 3, false); }
-    else { if (ldsvec) GN_LS(double, 1, true); else GN_LS(double, 1, false); }
-  }
-#undef GN_LS
-  GN_CHECK_LAUNCH();
+  throw gn_error{GN_ERR_ARG, "local band too wide for the single-column sweep kernel"};
+}
+
+bool pf_supported(const gn_problem* p, const gn_precond* pc) {
+  (void)p;
+  if (pc->local_kernel == 1) return false;
+  constexpr int PF_G = 16;
+  const int need_sp = (TILE / PF_G) * pc->maxwI;
+  const int padw = pc->maxwI + 16;
+  // two register buffers of SP slots: spill-free up to SP = 20 (FP64) / 32 (FP32)
+  const int spmax = pc->local_prec == 32 ? 32 : 20;
+  return (pc->maxNBI + 2 * padw) * TILE <= max_lds_doubles() && need_sp <= spmax;
 }
 
 void coarse_solve(const gn_precond* pc, const double* done, hipStream_t s) {

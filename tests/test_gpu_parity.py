@@ -173,6 +173,35 @@ def test_geneo_pcg_solution_and_iterations(name):
     assert abs(rep[0]["cond_est"] - info["kappa"]) <= 1e-3 * info["kappa"]
 
 
+@pytest.mark.parametrize("name", ["lam_3x2x2_uneven", "diff_2x2x2"])
+@pytest.mark.parametrize("local_prec", [64, 32])
+def test_matrix_core_local_kernel_single_column(name, local_prec):
+    """Single-column solves through the 16-column matrix-core kernel (the path
+    taken when a band is too wide for the register-pipelined sweep)."""
+    A, b, free, Ke = orc.system(name)
+    g = orc.geneo_run(name)
+    w = orc.workload(name)
+    pc = _gp().Preconditioner.from_workload(problem(name), w, local_prec=local_prec, local_kernel=1)
+    rng = np.random.default_rng(6)
+    r = rng.standard_normal(pc.prob.n_free)
+    z = torch.zeros((1, pc.prob.n_free), dtype=torch.float64, device=DEV)
+    pc.apply(_t(r[None, :]), z)
+    ref = g.apply(r)
+    err = np.linalg.norm(z[0].cpu().numpy() - ref) / np.linalg.norm(ref)
+    g2 = orc.geneo_run_shift(name, 1e-1)
+    delta_self = np.linalg.norm(g2.apply(r) - ref) / np.linalg.norm(ref)
+    print(f"[gpu] {name} matrix-core local kernel, prec {local_prec}: M^-1 r rel err {err:.2e}")
+    # FP32 factors: M^-1 itself changes at the FP32 level; the solve below is the gate
+    assert err <= (max(1e-10, 20 * delta_self) if local_prec == 64 else 1e-3), err
+    u_ref = np.linalg.solve(A.toarray(), b[:, 0])
+    bt = _t(b[:, 0][None, :])
+    x = torch.zeros_like(bt)
+    st, rep = _gp().solve(pc.prob, pc, bt, x, rtol=1e-12, maxit=2000)
+    assert rep[0]["converged"] == 1
+    tol = 1e-8 if local_prec == 64 else 1e-7
+    assert np.linalg.norm(x[0].cpu().numpy() - u_ref) <= tol * np.linalg.norm(u_ref)
+
+
 @pytest.mark.parametrize("name", ["lam_2x2", "lam_3x2x2_uneven", "diff_2x2x2"])
 def test_mixed_precision_local_solves(name):
     A, b, free, Ke = orc.system(name)
