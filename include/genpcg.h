@@ -194,7 +194,7 @@ typedef struct gn_solve_report {
   double t_solve_s;
   int32_t iters_first;  /* iterations of the first (un-restarted) CG sequence   */
   int32_t restarts;     /* restarts from b - A x taken to meet rtol on the true residual
-                           (at most 2; none once ||b - A x|| <= 4 eps || |A| |x| ||)  */
+                           (at most 2; none once ||b - A x|| <= eps || |A| |x| ||)     */
   double res_floor;     /* eps || |A| |x| || / ||b||: rounding floor of the true
                            residual of an FP64 solution                          */
 } gn_solve_report;

@@ -900,7 +900,7 @@ static double absmv_norm2(gn_problem* p, const double* x, hipStream_t s) {
   return t;
 }
 // restarts stop once b - A x is within this factor of eps || |A| |x| ||
-static constexpr double kFloorFactor = 4.0;
+static constexpr double kFloorFactor = 1.0;
 static constexpr double kEps = 2.220446049250313e-16;
 
 // CG-Lanczos tridiagonal of the first kit steps: T_ii = 1/a_i + b_{i-1}/a_{i-1},

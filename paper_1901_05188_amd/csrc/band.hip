@@ -180,6 +180,157 @@ __device__ inline void load_tile_lds(double* dst, const double* src) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Left-looking band Cholesky on FP64 matrix cores.  Block row K, tile t (column
+// block J = K - w + t):
+//   S = A(K,J) - sum_{t2 < t} L(K,J2) L(J,J2)^T,
+//   L(K,J) = S Dinv_J^T (t < w),   L(K,K) L(K,K)^T = S, Dinv_K = L(K,K)^-1 (t = w).
+// The four waves split the tile products of S (wave q takes t2 = t0 + q + 4m,
+// each a full 32 x 32 product on v_mfma_f64_16x16x4f64 with the operands of the
+// next product already in flight) and add their partials through LDS; the
+// diagonal tile is factored and inverted by one wave.
+// ---------------------------------------------------------------------------
+typedef double bc_d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void bc_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict__ mats, double* __restrict__ T,
+                                                       double* __restrict__ D, int* __restrict__ info) {
+  __shared__ double part[4][TILE][TILE + 1];
+  __shared__ double Ss[TILE][TILE + 1];
+  __shared__ double Xs[TILE][TILE + 1];
+  __shared__ int fail;
+  const BandRef br = mats[blockIdx.x];
+  const int w = br.w, NB = br.NB;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int qr = wid & 1, qc = wid >> 1;
+  if (threadIdx.x == 0) fail = 0;
+  __syncthreads();
+  double xa0[2][8], yb0[2][8], xa1[2][8], yb1[2][8];
+  bc_d4 acc[4];
+#define BC_LOAD(XA, YB, T2)                                                                    \
+  {                                                                                            \
+    const double* xp = T + tile_off(br.offT, K, (T2), w);                                      \
+    const double* yp = (t == w) ? xp : T + tile_off(br.offT, J, (T2) - t + w, w);              \
+    _Pragma("unroll") for (int q = 0; q < 2; ++q)                                              \
+      _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) {                                       \
+        XA[q][ks] = xp[(4 * ks + lk) * TILE + q * 16 + lr];                                    \
+        YB[q][ks] = yp[(4 * ks + lk) * TILE + q * 16 + lr];                                    \
+      }                                                                                        \
+  }
+#define BC_MFMA(XA, YB)                                                                        \
+  _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                             \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q)                                              \
+      acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(XA[q >> 1][ks], YB[q & 1][ks], acc[q], 0, 0, 0);
+  for (int K = 0; K < NB; ++K) {
+    const int t0 = max(0, w - K);
+    for (int t = t0; t <= w; ++t) {
+      const int J = K - w + t;
+      double* tk = T + tile_off(br.offT, K, t, w);
+      double aval[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = threadIdx.x + NT * u;
+        aval[u] = tk[(e / TILE) * TILE + e % TILE];
+      }
+      double dj[8];
+      if (t < w) {
+        const double* Dj = D + (br.offD + J) * TILE2;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) dj[ks] = Dj[(4 * ks + lk) * TILE + qc * 16 + lr];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = bc_d4{0, 0, 0, 0};
+      int t2 = t0 + wid;
+      if (t2 < t) BC_LOAD(xa0, yb0, t2)
+      if (t2 + 4 < t) BC_LOAD(xa1, yb1, t2 + 4)
+      while (t2 < t) {
+        BC_MFMA(xa0, yb0)
+        if (t2 + 8 < t) BC_LOAD(xa0, yb0, t2 + 8)
+        if (t2 + 4 < t) {
+          BC_MFMA(xa1, yb1)
+          if (t2 + 12 < t) BC_LOAD(xa1, yb1, t2 + 12)
+        }
+        t2 += 8;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part[wid][(q >> 1) * 16 + 4 * i + lk][(q & 1) * 16 + lr] = acc[q][i];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = threadIdx.x + NT * u;
+        const int r = e % TILE, c = e / TILE;
+        Ss[r][c] = aval[u] - ((part[0][r][c] + part[1][r][c]) + (part[2][r][c] + part[3][r][c]));
+      }
+      __syncthreads();
+      if (t < w) {
+        // L(K,J) = S Dinv_J^T: quadrant (qr, qc) of this wave
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = bc_d4{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks)
+          acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ss[qr * 16 + lr][4 * ks + lk], dj[ks], acc[ks & 3], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = qr * 16 + 4 * i + lk, col = qc * 16 + lr;
+          tk[col * TILE + row] = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+        }
+      } else if (wid == 0) {
+        // dense Cholesky of the diagonal tile (lower), one wave
+        for (int k = 0; k < TILE; ++k) {
+          double dkk = Ss[k][k];
+          if (!(dkk > 0.0)) {
+            if (lane == 0 && !fail) fail = K * TILE + k + 1;
+            dkk = 1.0;
+          }
+          const double piv = sqrt(dkk);
+          bc_lds_fence();
+          if (lane == k) Ss[k][k] = piv;
+          if (lane > k && lane < TILE) Ss[lane][k] = Ss[lane][k] / piv;
+          bc_lds_fence();
+          for (int e = (k + 1) * TILE + lane; e < TILE2; e += 64) {
+            const int r = e % TILE, c = e / TILE;
+            if (r >= c) Ss[r][c] -= Ss[r][k] * Ss[c][k];
+          }
+          bc_lds_fence();
+        }
+        // inverse of the lower-triangular factor, column per lane
+        if (lane < TILE) {
+          const int c = lane;
+          for (int r = 0; r < TILE; ++r) {
+            double sv = 0.0;
+            if (r >= c) {
+              sv = (r == c) ? 1.0 : 0.0;
+              for (int k = c; k < r; ++k) sv -= Ss[r][k] * Xs[k][c];
+              sv /= Ss[r][r];
+            }
+            Xs[r][c] = sv;
+          }
+        }
+        bc_lds_fence();
+        double* dk = D + (br.offD + K) * TILE2;
+        for (int e = lane; e < TILE2; e += 64) {
+          const int r = e % TILE, c = e / TILE;
+          tk[c * TILE + r] = (r >= c) ? Ss[r][c] : 0.0;
+          dk[c * TILE + r] = Xs[r][c];
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+  }
+#undef BC_MFMA
+#undef BC_LOAD
+  if (threadIdx.x == 0) info[blockIdx.x] = fail;
+}
+
 __global__ __launch_bounds__(NT) void k_band_chol(const BandRef* __restrict__ mats, double* __restrict__ T,
                                                   double* __restrict__ D, int* __restrict__ info) {
   __shared__ double Xs[TILE * (TILE + 1)];
@@ -316,7 +467,7 @@ void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, dou
 }
 
 void band_chol(const void* d_refs, int n, double* T, double* D, int* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_band_chol, dim3(n), dim3(NT), 0, s, (const BandRef*)d_refs, T, D, info);
+  hipLaunchKernelGGL(k_band_chol_mfma, dim3(n), dim3(NT), 0, s, (const BandRef*)d_refs, T, D, info);
   GN_CHECK_LAUNCH();
 }
 

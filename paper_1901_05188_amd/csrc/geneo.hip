@@ -262,6 +262,205 @@ __global__ __launch_bounds__(512) void k_trsm_pencil(const SubDesc* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Same solves, pipelined: one workgroup per subdomain with two waves (row
+// halves) per 16-column block.  The solved block rows of the current window
+// live in an LDS ring of w + 1 block rows (all b columns), and the band tiles
+// stream through a rolling register prefetch four tiles deep: after the
+// matrix-core products of tile t, the registers it used are reloaded with tile
+// t + 4 of the same step, or of the next step.  The step body is unrolled over
+// W >= w tile slots (W a multiple of 4); slots t >= w read a zero tile.  Only
+// LDS-ordering barriers separate the steps, so the prefetch stays in flight.
+// Operand reads are unmasked: columns past b read neighbouring finite values
+// (the ring is zeroed, V carries 64 doubles of tail padding) and only feed
+// output columns that are never stored; ring slots of blocks outside the
+// subdomain stay zero, so no bounds mask is needed either.
+// ---------------------------------------------------------------------------
+__device__ inline void geneo_lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int W>
+__global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ subs, int b, int ringlen,
+                                                   const double* __restrict__ T, const double* __restrict__ D,
+                                                   const double* __restrict__ Z0, double* __restrict__ V) {
+  constexpr int P = 4;
+  static_assert(W % P == 0, "W must be a multiple of the prefetch depth");
+  extern __shared__ double smem[];
+  double* ring = smem;                      // W1 slots x TILE rows x b columns (+16 pad)
+  const SubDesc& sd = subs[blockIdx.x];
+  const int NB = sd.NBB, w = sd.wB, W1 = w + 1;
+  const double* Tb = T + sd.offTB * TILE2;
+  const double* Db = D + sd.offDB * TILE2;
+  double* Vb = V + sd.offVB * b;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rh = wv & 1, cb = wv >> 1;
+  double* sS = smem + ringlen + cb * (TILE * 17);   // this column block's 32 x 16 (+1) exchange tile
+  const int lr = lane & 15, lk = lane >> 4;
+  const int rb = rh * 16;
+  const int col = cb * 16 + lr;
+  const bool ok = col < b;
+  const int nthr = blockDim.x;
+  for (int e = threadIdx.x; e < ringlen; e += nthr) ring[e] = 0.0;
+  double a[P][8];
+  double dv[8], vv[4];
+  gn_d4 acc[4];
+#define TR_ZERO() _Pragma("unroll") for (int u = 0; u < 4; ++u) acc[u] = gn_d4{0, 0, 0, 0};
+  // ---- forward: Y_K = Dinv_K (V_K - sum_t L(K,t) Y_{K-w+t}) ----
+#define TR_FWD_TILE(K_, t_) (((t_) < w) ? Tb + ((int64_t)(K_) * W1 + (t_)) * TILE2 : Z0)
+#define TR_LOAD_A_FWD(S_, K_, t_)                                                              \
+  {                                                                                            \
+    const double* tp = TR_FWD_TILE(K_, t_);                                                    \
+    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) a[S_][ks] = tp[(4 * ks + lk) * TILE + rb + lr]; \
+  }
+#define TR_LOAD_DV_FWD(K_)                                                                     \
+  {                                                                                            \
+    const double* dk = Db + (int64_t)(K_) * TILE2;                                             \
+    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dv[ks] = dk[(4 * ks + lk) * TILE + rb + lr]; \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i)                                              \
+      vv[i] = Vb[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + col];                           \
+  }
+#pragma unroll
+  for (int sl = 0; sl < P; ++sl) TR_LOAD_A_FWD(sl, 0, sl)
+  TR_LOAD_DV_FWD(0)
+  __syncthreads();
+  const int rstride = TILE * b;
+  const int lofs = lk * b + col;
+  for (int K = 0; K < NB; ++K) {
+    TR_ZERO()
+    // ring slot of tile t: block K - w + t; the B operands of tile t + 1 are
+    // read from LDS while the products of tile t run
+    int slot = (K + 1) % W1;          // (K - w + W1) mod W1
+    double bcur[8], bnxt[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      const int sl = t % P;
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) bcur[ks] = bnxt[ks];
+      if (t + 1 < W) {
+        slot = (slot + 1 == W1) ? 0 : slot + 1;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
+      }
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks)
+        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][ks], bcur[ks], acc[ks & 3], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (t + P < W) TR_LOAD_A_FWD(sl, K, t + P)
+      else TR_LOAD_A_FWD(sl, min(K + 1, NB - 1), t + P - W)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    double dcur[8], vcur[4];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) dcur[ks] = dv[ks];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) vcur[i] = vv[i];
+    TR_LOAD_DV_FWD(min(K + 1, NB - 1))
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      sS[(rb + 4 * i + lk) * 17 + lr] = vcur[i] - ((acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]));
+    geneo_lds_barrier();
+    TR_ZERO()
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+      acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dcur[ks], sS[(4 * ks + lk) * 17 + lr], acc[ks & 3], 0, 0, 0);
+    double* yk = ring + (K % W1) * (TILE * b);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = rb + 4 * i + lk;
+      const double y = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+      if (ok) {
+        yk[row * b + col] = y;
+        Vb[(int64_t)(K * TILE + row) * b + col] = y;
+      }
+    }
+    geneo_lds_barrier();
+  }
+#undef TR_LOAD_DV_FWD
+#undef TR_LOAD_A_FWD
+#undef TR_FWD_TILE
+  __syncthreads();
+  for (int e = threadIdx.x; e < ringlen; e += nthr) ring[e] = 0.0;
+  // ---- backward: X_K = Dinv_K^T (Y_K - sum_d L(K+d,K)^T X_{K+d}), d = t + 1 ----
+#define TR_BWD_TILE(K_, t_) \
+  (((t_) < w) ? Tb + ((int64_t)min((K_) + 1 + (t_), NB - 1) * W1 + (w - 1 - (t_))) * TILE2 : Z0)
+#define TR_LOAD_A_BWD(S_, K_, t_)                                                              \
+  {                                                                                            \
+    const double* tp = TR_BWD_TILE(K_, t_);                                                    \
+    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) a[S_][ks] = tp[(rb + lr) * TILE + 4 * ks + lk]; \
+  }
+#define TR_LOAD_DV_BWD(K_)                                                                     \
+  {                                                                                            \
+    const double* dk = Db + (int64_t)(K_) * TILE2;                                             \
+    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dv[ks] = dk[(rb + lr) * TILE + 4 * ks + lk]; \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i)                                              \
+      vv[i] = Vb[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + col];                           \
+  }
+#pragma unroll
+  for (int sl = 0; sl < P; ++sl) TR_LOAD_A_BWD(sl, NB - 1, sl)
+  TR_LOAD_DV_BWD(NB - 1)
+  __syncthreads();
+  for (int K = NB - 1; K >= 0; --K) {
+    TR_ZERO()
+    int slot = (K + 1) % W1;          // ring slot of tile t: block K + 1 + t
+    double bcur[8], bnxt[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      const int sl = t % P;
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) bcur[ks] = bnxt[ks];
+      if (t + 1 < W) {
+        slot = (slot + 1 == W1) ? 0 : slot + 1;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
+      }
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks)
+        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][ks], bcur[ks], acc[ks & 3], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (t + P < W) TR_LOAD_A_BWD(sl, K, t + P)
+      else TR_LOAD_A_BWD(sl, max(K - 1, 0), t + P - W)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    double dcur[8], vcur[4];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) dcur[ks] = dv[ks];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) vcur[i] = vv[i];
+    TR_LOAD_DV_BWD(max(K - 1, 0))
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      sS[(rb + 4 * i + lk) * 17 + lr] = vcur[i] - ((acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]));
+    geneo_lds_barrier();
+    TR_ZERO()
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+      acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dcur[ks], sS[(4 * ks + lk) * 17 + lr], acc[ks & 3], 0, 0, 0);
+    double* xk = ring + (K % W1) * (TILE * b);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = rb + 4 * i + lk;
+      const double x = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+      if (ok) {
+        xk[row * b + col] = x;
+        Vb[(int64_t)(K * TILE + row) * b + col] = x;
+      }
+    }
+    geneo_lds_barrier();
+  }
+#undef TR_LOAD_DV_BWD
+#undef TR_LOAD_A_BWD
+#undef TR_BWD_TILE
+#undef TR_ZERO
+}
+
+// ---------------------------------------------------------------------------
 // Gram matrices GP = Z^T (B V) = Z^T P Z and GB = Z^T (B Z) on FP64 matrix
 // cores, and the Ritz residuals res_k = ||Z_k - nu_k V_k||^2, zz_k = ||Z_k||^2.
 // Workgroup (j, g) streams rows [g*chunk, (g+1)*chunk) of subdomain j four at a
@@ -1010,6 +1209,34 @@ void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int
 
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, double* V, hipStream_t s) {
   if (b > 64) throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
+  int maxw = 0;
+  for (const SubDesc& sd : pc->sub) maxw = std::max(maxw, sd.wB);
+  const int ncb = (b + 15) / 16;
+  const int ringlen = (maxw + 1) * TILE * b + 16;
+  const size_t lds = sizeof(double) * ((size_t)ringlen + (size_t)ncb * TILE * 17);
+  const int W = std::max(4, (maxw + 3) / 4 * 4);
+  if (lds <= 160 * 1024 && W <= 32 && pc->d_z0) {
+#define GN_TR(WV)                                                                                    \
+  do {                                                                                               \
+    GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                               (int)lds));                                                           \
+    hipLaunchKernelGGL(k_trsm_ring<WV>, dim3(pc->n_sub), dim3(128 * ncb), lds, s, pc->d_sub, b, ringlen, T, \
+                       D, pc->d_z0, V);                                                              \
+  } while (0)
+    switch (W) {
+      case 4: GN_TR(4); break;
+      case 8: GN_TR(8); break;
+      case 12: GN_TR(12); break;
+      case 16: GN_TR(16); break;
+      case 20: GN_TR(20); break;
+      case 24: GN_TR(24); break;
+      case 28: GN_TR(28); break;
+      default: GN_TR(32); break;
+    }
+#undef GN_TR
+    GN_CHECK_LAUNCH();
+    return;
+  }
   // one workgroup per subdomain, two waves (row halves) per 16-column block: the
   // waves of a row half read the same band tiles, so each tile leaves HBM once
   hipLaunchKernelGGL(k_trsm_pencil, dim3(pc->n_sub), dim3(128 * ((b + 15) / 16)), 0, s, pc->d_sub, pc->n_sub, b,
