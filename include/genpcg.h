@@ -122,8 +122,11 @@ gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t n
  * eig_tol / eig_maxit bound the batched eigensolver (0 = defaults 1e-12 / 300):
  * it stops when every wanted Ritz pair has ||P^-1 B v - nu v|| <= eig_tol ||P^-1 B v||,
  * or when that residual stays below 1e-9 without halving for 15 iterations.
- * eig_block is the subspace block size (0 = automatic: nev + max(8, nev/2), or
- * nev_max + 8, at most 64); a given value must lie in [(nev or nev_max) + 5, 64].
+ * eig_block is the subspace block size.  0 = automatic: nev + max(8, nev/2)
+ * (at most 64) for a fixed nev; for a threshold min(32, nev_max + 8), grown by
+ * 16 up to 64 and the eigensolve repeated while the eigenvalues below
+ * 1.5 x threshold (plus 4 guard vectors) do not fit.  A given value must lie
+ * in [nev + 5 (or 5), 64]; if it proves too small, GN_ERR_EIG_NOCONV.
  * eig_filter is the largest Chebyshev filter degree per Rayleigh-Ritz step
  * (0 = 4; 1 = plain subspace iteration); the degree ramps up 1, 2, ... from the
  * first step.

@@ -516,13 +516,16 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   if (o->coarse && n_sub > 1) {
     const bool fixed = o->nev > 0;
     const int guard = 8;
-    int b = fixed ? std::min(64, o->nev + std::max(guard, o->nev / 2)) : std::min(64, o->nev_max + guard);
+    // block size: fixed m_j plus a guard band; threshold mode starts at 32 and
+    // grows by 16 (to 64) when the eigenvalues below 1.5 x threshold do not fit
+    int b = fixed ? std::min(64, o->nev + std::max(guard, o->nev / 2)) : std::min(32, o->nev_max + guard);
     if (o->eig_block > 0) {
-      const int need = (fixed ? o->nev : o->nev_max) + 1 + guard / 2;
+      const int need = (fixed ? o->nev : 0) + 1 + guard / 2;
       if (o->eig_block < need || o->eig_block > 64)
         argfail("eig_block must lie in [" + std::to_string(need) + ", 64]");
       b = o->eig_block;
     }
+    bool block_short = false;   // a wanted set reached the guard band of the block
     double* LB = dalloc<double>(tmp, (size_t)offTB * TILE2);
     double* DB = dalloc<double>(tmp, (size_t)offDB * TILE2);
     GN_HIP(hipMemsetAsync(LB, 0, sizeof(double) * (size_t)offTB * TILE2, s));
@@ -535,154 +538,173 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     GN_HIP(hipStreamSynchronize(s));
     for (int j = 0; j < n_sub; ++j)
       if (info[j]) throw gn_error{GN_ERR_NOT_SPD, "GenEO pencil of subdomain " + std::to_string(j) + " not definite"};
-    const size_t vlen = (size_t)offVB * b;
-    // 64 doubles of tail padding: the matrix-core solve reads whole 16-column
-    // blocks past column b of the last row (those values are masked out)
-    double* V = dalloc<double>(tmp, vlen + 64);
-    double* Z = dalloc<double>(tmp, vlen + 64);
-    double* BV = dalloc<double>(tmp, vlen + 64);
-    double* BZ = dalloc<double>(tmp, vlen + 64);
-    for (double* t : {V, Z, BV, BZ}) GN_HIP(hipMemsetAsync(t + vlen, 0, sizeof(double) * 64, s));
-    const int gsplit = gnk::gram_split();
-    double* GP = dalloc<double>(tmp, (size_t)n_sub * gsplit * b * b);
-    double* GB = dalloc<double>(tmp, (size_t)n_sub * gsplit * b * b);
-    double* resp = dalloc<double>(tmp, (size_t)n_sub * gsplit * 2 * b);
-    double* Y = dalloc<double>(tmp, (size_t)n_sub * b * b);
-    double* nu = dalloc<double>(tmp, (size_t)n_sub * b);
-    double* res = dalloc<double>(tmp, (size_t)n_sub * 2 * b);
-    GN_HIP(hipMemsetAsync(nu, 0, sizeof(double) * n_sub * b, s));
-    GN_HIP(hipMemsetAsync(d_info, 0, sizeof(int) * n_sub, s));
-    gnk::eig_vinit(pc, b, maxNBB, V, s);
-    std::vector<double> h_nu((size_t)n_sub * b), h_res((size_t)n_sub * 2 * b);
-    std::vector<int> nwant(n_sub, 0);
-    std::vector<double> worst_hist;
-    bool converged = false;
-    double* BE = dalloc<double>(tmp, (size_t)offVB * 27 * nc);
-    gnk::eig_extract_b(p, pc, maxNBB, BE, s);
-    gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);
-    // Chebyshev-filtered subspace iteration: outer iteration it applies a filter
-    // of degree d = min(dmax, it + 1) in T = P^-1 B (d block solves), then one
-    // Rayleigh-Ritz step; d = 1 is plain subspace iteration
-    const int dmax = o->eig_filter > 0 ? o->eig_filter : 4;
-    const int ncoef = std::max(2, 2 * dmax - 2);
-    double *A1 = nullptr, *B1 = nullptr, *d_coef = nullptr;
-    if (dmax > 1) {
-      A1 = dalloc<double>(tmp, vlen + 64);
-      B1 = dalloc<double>(tmp, vlen + 64);
-      for (double* t : {A1, B1}) GN_HIP(hipMemsetAsync(t + vlen, 0, sizeof(double) * 64, s));
-      d_coef = dalloc<double>(tmp, (size_t)n_sub * ncoef);
-    }
-    std::vector<double> h_coef((size_t)n_sub * ncoef, 0.0);
-    std::vector<int> solves_hist;
-    int solves = 0;
-    for (int it = 0; it < eig_maxit; ++it) {
-      const int d = std::min(dmax, it + 1);
-      // Z = T V = P^-1 B V
-      GN_HIP(hipMemcpyAsync(Z, BV, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
-      gnk::eig_trsm(pc, b, LB, DB, Z, s);
-      ++solves;
-      if (d == 1) {
-        // Rayleigh-Ritz on span(Z): P Z = B V, so Z^T P Z = Z^T (B V)
-        gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
-        gnk::eig_gram(pc, b, Z, BV, BZ, V, nu, GP, GB, resp, s);
-      } else {
-        // filter interval [0, nu_cut] per subdomain, nu_cut = smallest Ritz value
-        // of the last Rayleigh-Ritz step; scaled so that nu = 1/s maps to 1
-        const double nuref = 1.0 / shift;
-        for (int j = 0; j < n_sub; ++j) {
-          double nucut = h_nu[(size_t)j * b + b - 1];
-          nucut = std::min(std::max(nucut, 1e-12 * nuref), 0.5 * nuref);
-          const double e = 0.5 * nucut, c = 0.5 * nucut;
-          const double s1 = e / (nuref - c);
-          double* cf = &h_coef[(size_t)j * ncoef];
-          cf[0] = s1 / e;
-          cf[1] = c;
-          double sig = s1;
-          for (int i = 2; i < d; ++i) {
-            const double sn = 1.0 / (2.0 / s1 - sig);
-            cf[2 + 2 * (i - 2)] = 2.0 * sn / e;
-            cf[3 + 2 * (i - 2)] = sig * sn;
-            sig = sn;
+    const bool auto_block = o->eig_block <= 0;
+    double *V = nullptr, *Z = nullptr;
+    std::vector<double> h_nu;
+    int solves_prev = 0;   // block solves of earlier attempts with a smaller block
+    for (;;) {
+      const size_t vlen = (size_t)offVB * b;
+      // 64 doubles of tail padding: the matrix-core solve reads whole 16-column
+      // blocks past column b of the last row (those values are masked out)
+      V = dalloc<double>(tmp, vlen + 64);
+      Z = dalloc<double>(tmp, vlen + 64);
+      double* BV = dalloc<double>(tmp, vlen + 64);
+      double* BZ = dalloc<double>(tmp, vlen + 64);
+      for (double* t : {V, Z, BV, BZ}) GN_HIP(hipMemsetAsync(t + vlen, 0, sizeof(double) * 64, s));
+      const int gsplit = gnk::gram_split();
+      double* GP = dalloc<double>(tmp, (size_t)n_sub * gsplit * b * b);
+      double* GB = dalloc<double>(tmp, (size_t)n_sub * gsplit * b * b);
+      double* resp = dalloc<double>(tmp, (size_t)n_sub * gsplit * 2 * b);
+      double* Y = dalloc<double>(tmp, (size_t)n_sub * b * b);
+      double* nu = dalloc<double>(tmp, (size_t)n_sub * b);
+      double* res = dalloc<double>(tmp, (size_t)n_sub * 2 * b);
+      GN_HIP(hipMemsetAsync(nu, 0, sizeof(double) * n_sub * b, s));
+      GN_HIP(hipMemsetAsync(d_info, 0, sizeof(int) * n_sub, s));
+      gnk::eig_vinit(pc, b, maxNBB, V, s);
+      h_nu.assign((size_t)n_sub * b, 0.0);
+      std::vector<double> h_res((size_t)n_sub * 2 * b);
+      std::vector<int> nwant(n_sub, 0);
+      std::vector<double> worst_hist;
+      bool converged = false;
+      double* BE = dalloc<double>(tmp, (size_t)offVB * 27 * nc);
+      gnk::eig_extract_b(p, pc, maxNBB, BE, s);
+      gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);
+      // Chebyshev-filtered subspace iteration: outer iteration it applies a filter
+      // of degree d = min(dmax, it + 1) in T = P^-1 B (d block solves), then one
+      // Rayleigh-Ritz step; d = 1 is plain subspace iteration
+      const int dmax = o->eig_filter > 0 ? o->eig_filter : 4;
+      const int ncoef = std::max(2, 2 * dmax - 2);
+      double *A1 = nullptr, *B1 = nullptr, *d_coef = nullptr;
+      if (dmax > 1) {
+        A1 = dalloc<double>(tmp, vlen + 64);
+        B1 = dalloc<double>(tmp, vlen + 64);
+        for (double* t : {A1, B1}) GN_HIP(hipMemsetAsync(t + vlen, 0, sizeof(double) * 64, s));
+        d_coef = dalloc<double>(tmp, (size_t)n_sub * ncoef);
+      }
+      std::vector<double> h_coef((size_t)n_sub * ncoef, 0.0);
+      std::vector<int> solves_hist;
+      int solves = 0;
+      for (int it = 0; it < eig_maxit; ++it) {
+        const int d = std::min(dmax, it + 1);
+        // Z = T V = P^-1 B V
+        GN_HIP(hipMemcpyAsync(Z, BV, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
+        gnk::eig_trsm(pc, b, LB, DB, Z, s);
+        ++solves;
+        if (d == 1) {
+          // Rayleigh-Ritz on span(Z): P Z = B V, so Z^T P Z = Z^T (B V)
+          gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
+          gnk::eig_gram(pc, b, Z, BV, BZ, V, nu, GP, GB, resp, s);
+        } else {
+          // filter interval [0, nu_cut] per subdomain, nu_cut = smallest Ritz value
+          // of the last Rayleigh-Ritz step; scaled so that nu = 1/s maps to 1
+          const double nuref = 1.0 / shift;
+          for (int j = 0; j < n_sub; ++j) {
+            double nucut = h_nu[(size_t)j * b + b - 1];
+            nucut = std::min(std::max(nucut, 1e-12 * nuref), 0.5 * nuref);
+            const double e = 0.5 * nucut, c = 0.5 * nucut;
+            const double s1 = e / (nuref - c);
+            double* cf = &h_coef[(size_t)j * ncoef];
+            cf[0] = s1 / e;
+            cf[1] = c;
+            double sig = s1;
+            for (int i = 2; i < d; ++i) {
+              const double sn = 1.0 / (2.0 / s1 - sig);
+              cf[2 + 2 * (i - 2)] = 2.0 * sn / e;
+              cf[3 + 2 * (i - 2)] = sig * sn;
+              sig = sn;
+            }
           }
-        }
-        GN_HIP(hipMemcpyAsync(d_coef, h_coef.data(), sizeof(double) * h_coef.size(), hipMemcpyHostToDevice, s));
-        // Y1 = a1 (Z - c V), with the Ritz residuals of the current block
-        gnk::eig_cheb_first(pc, b, Z, V, nu, d_coef, ncoef, A1, resp, s);
-        double *Y0 = V, *BY0 = BV, *Yc = A1, *BYc = B1;
-        gnk::eig_bapply(p, pc, BE, b, maxNBB, Yc, BYc, s);
-        for (int i = 2; i < d; ++i) {
+          GN_HIP(hipMemcpyAsync(d_coef, h_coef.data(), sizeof(double) * h_coef.size(), hipMemcpyHostToDevice, s));
+          // Y1 = a1 (Z - c V), with the Ritz residuals of the current block
+          gnk::eig_cheb_first(pc, b, Z, V, nu, d_coef, ncoef, A1, resp, s);
+          double *Y0 = V, *BY0 = BV, *Yc = A1, *BYc = B1;
+          gnk::eig_bapply(p, pc, BE, b, maxNBB, Yc, BYc, s);
+          for (int i = 2; i < d; ++i) {
+            GN_HIP(hipMemcpyAsync(Z, BYc, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
+            gnk::eig_trsm(pc, b, LB, DB, Z, s);
+            ++solves;
+            gnk::eig_cheb_step(pc, b, maxNBB, Z, Yc, Y0, d_coef, ncoef, i - 2, s);   // Y0 <- Y_i
+            gnk::eig_bapply(p, pc, BE, b, maxNBB, Y0, BY0, s);
+            std::swap(Y0, Yc);
+            std::swap(BY0, BYc);
+          }
+          // W = T Y_{d-1}: Rayleigh-Ritz on span(W) with P W = B Y_{d-1}
           GN_HIP(hipMemcpyAsync(Z, BYc, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
           gnk::eig_trsm(pc, b, LB, DB, Z, s);
           ++solves;
-          gnk::eig_cheb_step(pc, b, maxNBB, Z, Yc, Y0, d_coef, ncoef, i - 2, s);   // Y0 <- Y_i
-          gnk::eig_bapply(p, pc, BE, b, maxNBB, Y0, BY0, s);
-          std::swap(Y0, Yc);
-          std::swap(BY0, BYc);
+          gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
+          gnk::eig_gram(pc, b, Z, BYc, BZ, nullptr, nullptr, GP, GB, nullptr, s);
         }
-        // W = T Y_{d-1}: Rayleigh-Ritz on span(W) with P W = B Y_{d-1}
-        GN_HIP(hipMemcpyAsync(Z, BYc, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
-        gnk::eig_trsm(pc, b, LB, DB, Z, s);
-        ++solves;
-        gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
-        gnk::eig_gram(pc, b, Z, BYc, BZ, nullptr, nullptr, GP, GB, nullptr, s);
-      }
-      gnk::eig_small(n_sub, b, GP, GB, resp, res, Y, nu, nullptr, s);
-      gnk::eig_vupdate(pc, b, maxNBB, Z, BZ, Y, V, BV, s);
-      GN_HIP(hipMemcpyAsync(h_res.data(), res, sizeof(double) * h_res.size(), hipMemcpyDeviceToHost, s));
-      // residuals refer to the Ritz pairs of the previous iteration (h_nu before this copy)
-      std::vector<double> prev_nu = h_nu;
-      GN_HIP(hipMemcpyAsync(h_nu.data(), nu, sizeof(double) * h_nu.size(), hipMemcpyDeviceToHost, s));
-      GN_HIP(hipStreamSynchronize(s));
-      eig_iters = it + 1;
-      eig_solves = solves;
-      if (it == 0) continue;
-      bool all = true;
-      double worst = 0.0;   // largest relative residual over the wanted pairs
-      for (int j = 0; j < n_sub; ++j) {
-        // wanted pairs: nev+1 (fixed) or those below 1.5*threshold plus one (capped)
-        int nw;
-        if (fixed) {
-          nw = std::min(b - guard / 2, o->nev + 1);
-        } else {
-          nw = 0;
-          for (int k = 0; k < b; ++k) {
+        gnk::eig_small(n_sub, b, GP, GB, resp, res, Y, nu, nullptr, s);
+        gnk::eig_vupdate(pc, b, maxNBB, Z, BZ, Y, V, BV, s);
+        GN_HIP(hipMemcpyAsync(h_res.data(), res, sizeof(double) * h_res.size(), hipMemcpyDeviceToHost, s));
+        // residuals refer to the Ritz pairs of the previous iteration (h_nu before this copy)
+        std::vector<double> prev_nu = h_nu;
+        GN_HIP(hipMemcpyAsync(h_nu.data(), nu, sizeof(double) * h_nu.size(), hipMemcpyDeviceToHost, s));
+        GN_HIP(hipStreamSynchronize(s));
+        eig_iters = it + 1;
+        eig_solves = solves_prev + solves;
+        if (it == 0) continue;
+        bool all = true;
+        block_short = false;
+        double worst = 0.0;   // largest relative residual over the wanted pairs
+        for (int j = 0; j < n_sub; ++j) {
+          // wanted pairs: nev+1 (fixed) or those below 1.5*threshold plus one (capped)
+          int nw;
+          if (fixed) {
+            nw = std::min(b - guard / 2, o->nev + 1);
+          } else {
+            nw = 0;
+            for (int k = 0; k < b; ++k) {
+              double nk = prev_nu[(size_t)j * b + k];
+              double lam = nk > 0 ? 1.0 / nk - shift : 1e300;
+              if (lam < 1.5 * o->threshold) nw = k + 1;
+            }
+            if (std::min(nw + 1, o->nev_max + 1) > b - guard / 2) block_short = true;
+            nw = std::min(std::min(nw + 1, o->nev_max + 1), b - guard / 2);
+          }
+          nwant[j] = nw;
+          for (int k = 0; k < nw; ++k) {
             double nk = prev_nu[(size_t)j * b + k];
-            double lam = nk > 0 ? 1.0 / nk - shift : 1e300;
-            if (lam < 1.5 * o->threshold) nw = k + 1;
+            double rs = h_res[(size_t)j * 2 * b + k], zz = h_res[(size_t)j * 2 * b + b + k];
+            if (nk <= 1e-12 / shift) continue;      // null space of B: lambda = inf
+            double rel = zz > 0 ? std::sqrt(rs / zz) : 0.0;
+            if (!(rel <= eig_tol)) all = false;
+            if (!(rel <= worst)) worst = std::isfinite(rel) ? std::max(worst, rel) : 1e300;
           }
-          nw = std::min(std::min(nw + 1, o->nev_max + 1), b - guard / 2);
         }
-        nwant[j] = nw;
-        for (int k = 0; k < nw; ++k) {
-          double nk = prev_nu[(size_t)j * b + k];
-          double rs = h_res[(size_t)j * 2 * b + k], zz = h_res[(size_t)j * 2 * b + b + k];
-          if (nk <= 1e-12 / shift) continue;      // null space of B: lambda = inf
-          double rel = zz > 0 ? std::sqrt(rs / zz) : 0.0;
-          if (!(rel <= eig_tol)) all = false;
-          if (!(rel <= worst)) worst = std::isfinite(rel) ? std::max(worst, rel) : 1e300;
+        worst_hist.push_back(worst);
+        solves_hist.push_back(solves);
+        eig_resid = worst;
+        // accept a residual that has reached the rounding floor: no halving over
+        // the last 15 block solves once it is below 1e-9
+        bool stagnated = false;
+        if (solves > 20 && worst <= 1e-9) {
+          for (size_t q = worst_hist.size(); q-- > 0;)
+            if (solves_hist[q] <= solves - 15) {
+              stagnated = worst > 0.5 * worst_hist[q];
+              break;
+            }
+        }
+        if (all || stagnated) {
+          converged = true;
+          break;
         }
       }
-      worst_hist.push_back(worst);
-      solves_hist.push_back(solves);
-      eig_resid = worst;
-      // accept a residual that has reached the rounding floor: no halving over
-      // the last 15 block solves once it is below 1e-9
-      bool stagnated = false;
-      if (solves > 20 && worst <= 1e-9) {
-        for (size_t q = worst_hist.size(); q-- > 0;)
-          if (solves_hist[q] <= solves - 15) {
-            stagnated = worst > 0.5 * worst_hist[q];
-            break;
-          }
+      if (!converged)
+        throw gn_error{GN_ERR_EIG_NOCONV, "GenEO eigensolver did not converge in " + std::to_string(eig_maxit) +
+                                              " iterations"};
+      if (block_short && auto_block && b < 64) {
+        b = std::min(64, b + 16);   // more eigenvalues below 1.5 x threshold than the block holds
+        solves_prev = eig_solves;
+        continue;
       }
-      if (all || stagnated) {
-        converged = true;
-        break;
-      }
+      if (block_short)
+        throw gn_error{GN_ERR_EIG_NOCONV, "GenEO eigensolver block of " + std::to_string(b) +
+                                              " vectors too small for the eigenvalues below 1.5 x threshold "
+                                              "(raise eig_block)"};
+      break;
     }
-    if (!converged)
-      throw gn_error{GN_ERR_EIG_NOCONV, "GenEO eigensolver did not converge in " + std::to_string(eig_maxit) +
-                                            " iterations"};
     // V now holds the Ritz vectors of the last Rayleigh-Ritz step (h_nu)
     pc->n_eval = b;
     pc->lam.assign((size_t)n_sub * b, 0.0);

@@ -265,10 +265,10 @@ __global__ __launch_bounds__(512) void k_trsm_pencil(const SubDesc* __restrict__
 // Same solves, pipelined: one workgroup per subdomain with two waves (row
 // halves) per 16-column block.  The solved block rows of the current window
 // live in an LDS ring of w + 1 block rows (all b columns), and the band tiles
-// stream through a rolling register prefetch four tiles deep: after the
+// stream through a rolling register prefetch P tiles deep: after the
 // matrix-core products of tile t, the registers it used are reloaded with tile
-// t + 4 of the same step, or of the next step.  The step body is unrolled over
-// W >= w tile slots (W a multiple of 4); slots t >= w read a zero tile.  Only
+// t + P of the same step, or of the next step.  The step body is unrolled over
+// W >= w tile slots (W a multiple of P); slots t >= w read a zero tile.  Only
 // LDS-ordering barriers separate the steps, so the prefetch stays in flight.
 // Operand reads are unmasked: columns past b read neighbouring finite values
 // (the ring is zeroed, V carries 64 doubles of tail padding) and only feed
@@ -281,11 +281,10 @@ __device__ inline void geneo_lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int W>
+template <int W, int P>
 __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ subs, int b, int ringlen,
                                                    const double* __restrict__ T, const double* __restrict__ D,
                                                    const double* __restrict__ Z0, double* __restrict__ V) {
-  constexpr int P = 4;
   static_assert(W % P == 0, "W must be a multiple of the prefetch depth");
   extern __shared__ double smem[];
   double* ring = smem;                      // W1 slots x TILE rows x b columns (+16 pad)
@@ -1214,24 +1213,22 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, dou
   const int ncb = (b + 15) / 16;
   const int ringlen = (maxw + 1) * TILE * b + 16;
   const size_t lds = sizeof(double) * ((size_t)ringlen + (size_t)ncb * TILE * 17);
-  const int W = std::max(4, (maxw + 3) / 4 * 4);
-  if (lds <= 160 * 1024 && W <= 32 && pc->d_z0) {
+  // tile slots per step: the smallest multiple of the prefetch depth (6) >= w
+  const int W = std::max(6, (maxw + 5) / 6 * 6);
+  if (lds <= 160 * 1024 && W <= 30 && pc->d_z0) {
 #define GN_TR(WV)                                                                                    \
   do {                                                                                               \
-    GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+    GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                (int)lds));                                                           \
-    hipLaunchKernelGGL(k_trsm_ring<WV>, dim3(pc->n_sub), dim3(128 * ncb), lds, s, pc->d_sub, b, ringlen, T, \
-                       D, pc->d_z0, V);                                                              \
+    hipLaunchKernelGGL((k_trsm_ring<WV, 6>), dim3(pc->n_sub), dim3(128 * ncb), lds, s, pc->d_sub, b, ringlen, \
+                       T, D, pc->d_z0, V);                                                           \
   } while (0)
     switch (W) {
-      case 4: GN_TR(4); break;
-      case 8: GN_TR(8); break;
+      case 6: GN_TR(6); break;
       case 12: GN_TR(12); break;
-      case 16: GN_TR(16); break;
-      case 20: GN_TR(20); break;
+      case 18: GN_TR(18); break;
       case 24: GN_TR(24); break;
-      case 28: GN_TR(28); break;
-      default: GN_TR(32); break;
+      default: GN_TR(30); break;
     }
 #undef GN_TR
     GN_CHECK_LAUNCH();
