@@ -245,6 +245,20 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline()
+    # streaming reference on the same device: a 1 GiB device-to-device copy
+    # (read + write bytes over its event-timed duration), context for the roofline
+    nref = (1 << 30) // 8
+    src = torch.ones(nref, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    res["hbm_copy_GBps"] = round(5 * 2 * nref * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del src, dst
     if args.copy_calibration_gib > 0:
         n = int(args.copy_calibration_gib * (1 << 30)) // 8
         src = torch.ones(n, dtype=torch.float64, device=dev)

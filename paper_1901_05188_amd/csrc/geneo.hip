@@ -281,11 +281,12 @@ __device__ inline void geneo_lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int W, int P>
+template <int W, int P, int S>
 __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ subs, int b, int ringlen,
                                                    const double* __restrict__ T, const double* __restrict__ D,
                                                    const double* __restrict__ Z0, double* __restrict__ V) {
-  static_assert(W % P == 0, "W must be a multiple of the prefetch depth");
+  static_assert(W % S == 0 && (W / S) % P == 0, "W / S must be a multiple of the prefetch depth");
+  constexpr int WS = W / S;                 // tile slots per wave and step
   extern __shared__ double smem[];
   double* ring = smem;                      // W1 slots x TILE rows x b columns (+16 pad)
   const SubDesc& sd = subs[blockIdx.x];
@@ -295,8 +296,12 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
   double* Vb = V + sd.offVB * b;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int rh = wv & 1, cb = wv >> 1;
-  double* sS = smem + ringlen + cb * (TILE * 17);   // this column block's 32 x 16 (+1) exchange tile
+  const int ncb = (b + 15) / 16;
+  const int half = wv / (2 * ncb);          // tile parity handled by this wave (S = 2)
+  const int rem = wv % (2 * ncb);
+  const int rh = rem & 1, cb = rem >> 1;
+  double* sS = smem + ringlen + cb * (TILE * 17);               // 32 x 16 (+1) exchange tile
+  double* sP = smem + ringlen + (ncb + cb) * (TILE * 17);       // partial of the odd tiles
   const int lr = lane & 15, lk = lane >> 4;
   const int rb = rh * 16;
   const int col = cb * 16 + lr;
@@ -305,8 +310,8 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
   for (int e = threadIdx.x; e < ringlen; e += nthr) ring[e] = 0.0;
   double a[P][8];
   double dv[8], vv[4];
-  gn_d4 acc[4];
-#define TR_ZERO() _Pragma("unroll") for (int u = 0; u < 4; ++u) acc[u] = gn_d4{0, 0, 0, 0};
+  gn_d4 acc[8];   // eight independent chains in the tile products
+#define TR_ZERO() _Pragma("unroll") for (int u = 0; u < 8; ++u) acc[u] = gn_d4{0, 0, 0, 0};
   // ---- forward: Y_K = Dinv_K (V_K - sum_t L(K,t) Y_{K-w+t}) ----
 #define TR_FWD_TILE(K_, t_) (((t_) < w) ? Tb + ((int64_t)(K_) * W1 + (t_)) * TILE2 : Z0)
 #define TR_LOAD_A_FWD(S_, K_, t_)                                                              \
@@ -322,8 +327,8 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
       vv[i] = Vb[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + col];                           \
   }
 #pragma unroll
-  for (int sl = 0; sl < P; ++sl) TR_LOAD_A_FWD(sl, 0, sl)
-  TR_LOAD_DV_FWD(0)
+  for (int sl = 0; sl < P; ++sl) TR_LOAD_A_FWD(sl, 0, S * sl + half)
+  if (half == 0) TR_LOAD_DV_FWD(0)
   __syncthreads();
   const int rstride = TILE * b;
   const int lofs = lk * b + col;
@@ -331,26 +336,27 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
     TR_ZERO()
     // ring slot of tile t: block K - w + t; the B operands of tile t + 1 are
     // read from LDS while the products of tile t run
-    int slot = (K + 1) % W1;          // (K - w + W1) mod W1
+    int slot = (K + 1 + half) % W1;   // (K - w + half + W1) mod W1
     double bcur[8], bnxt[8];
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
 #pragma unroll
-    for (int t = 0; t < W; ++t) {
-      const int sl = t % P;
+    for (int m = 0; m < WS; ++m) {
+      const int sl = m % P;
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) bcur[ks] = bnxt[ks];
-      if (t + 1 < W) {
-        slot = (slot + 1 == W1) ? 0 : slot + 1;
+      if (m + 1 < WS) {
+        slot += S;
+        while (slot >= W1) slot -= W1;
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
       }
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks)
-        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][ks], bcur[ks], acc[ks & 3], 0, 0, 0);
+        acc[ks] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][ks], bcur[ks], acc[ks], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
-      if (t + P < W) TR_LOAD_A_FWD(sl, K, t + P)
-      else TR_LOAD_A_FWD(sl, min(K + 1, NB - 1), t + P - W)
+      if (m + P < WS) TR_LOAD_A_FWD(sl, K, S * (m + P) + half)
+      else TR_LOAD_A_FWD(sl, min(K + 1, NB - 1), S * (m + P - WS) + half)
       __builtin_amdgcn_sched_barrier(0);
     }
     double dcur[8], vcur[4];
@@ -358,10 +364,23 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
     for (int ks = 0; ks < 8; ++ks) dcur[ks] = dv[ks];
 #pragma unroll
     for (int i = 0; i < 4; ++i) vcur[i] = vv[i];
-    TR_LOAD_DV_FWD(min(K + 1, NB - 1))
+    if (half == 0) TR_LOAD_DV_FWD(min(K + 1, NB - 1))
+    double psum[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      sS[(rb + 4 * i + lk) * 17 + lr] = vcur[i] - ((acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]));
+      psum[i] = ((acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i])) + ((acc[4][i] + acc[5][i]) + (acc[6][i] + acc[7][i]));
+    if (S == 2) {
+      if (half == 1) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sP[(rb + 4 * i + lk) * 17 + lr] = psum[i];
+      }
+      geneo_lds_barrier();
+    }
+    if (half == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        sS[(rb + 4 * i + lk) * 17 + lr] = vcur[i] - (S == 2 ? psum[i] + sP[(rb + 4 * i + lk) * 17 + lr] : psum[i]);
+    }
     geneo_lds_barrier();
     TR_ZERO()
 #pragma unroll
@@ -372,7 +391,7 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
     for (int i = 0; i < 4; ++i) {
       const int row = rb + 4 * i + lk;
       const double y = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
-      if (ok) {
+      if (ok && half == 0) {
         yk[row * b + col] = y;
         Vb[(int64_t)(K * TILE + row) * b + col] = y;
       }
@@ -400,31 +419,32 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
       vv[i] = Vb[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + col];                           \
   }
 #pragma unroll
-  for (int sl = 0; sl < P; ++sl) TR_LOAD_A_BWD(sl, NB - 1, sl)
-  TR_LOAD_DV_BWD(NB - 1)
+  for (int sl = 0; sl < P; ++sl) TR_LOAD_A_BWD(sl, NB - 1, S * sl + half)
+  if (half == 0) TR_LOAD_DV_BWD(NB - 1)
   __syncthreads();
   for (int K = NB - 1; K >= 0; --K) {
     TR_ZERO()
-    int slot = (K + 1) % W1;          // ring slot of tile t: block K + 1 + t
+    int slot = (K + 1 + half) % W1;   // ring slot of tile t: block K + 1 + t
     double bcur[8], bnxt[8];
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
 #pragma unroll
-    for (int t = 0; t < W; ++t) {
-      const int sl = t % P;
+    for (int m = 0; m < WS; ++m) {
+      const int sl = m % P;
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) bcur[ks] = bnxt[ks];
-      if (t + 1 < W) {
-        slot = (slot + 1 == W1) ? 0 : slot + 1;
+      if (m + 1 < WS) {
+        slot += S;
+        while (slot >= W1) slot -= W1;
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
       }
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks)
-        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][ks], bcur[ks], acc[ks & 3], 0, 0, 0);
+        acc[ks] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][ks], bcur[ks], acc[ks], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
-      if (t + P < W) TR_LOAD_A_BWD(sl, K, t + P)
-      else TR_LOAD_A_BWD(sl, max(K - 1, 0), t + P - W)
+      if (m + P < WS) TR_LOAD_A_BWD(sl, K, S * (m + P) + half)
+      else TR_LOAD_A_BWD(sl, max(K - 1, 0), S * (m + P - WS) + half)
       __builtin_amdgcn_sched_barrier(0);
     }
     double dcur[8], vcur[4];
@@ -432,10 +452,23 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
     for (int ks = 0; ks < 8; ++ks) dcur[ks] = dv[ks];
 #pragma unroll
     for (int i = 0; i < 4; ++i) vcur[i] = vv[i];
-    TR_LOAD_DV_BWD(max(K - 1, 0))
+    if (half == 0) TR_LOAD_DV_BWD(max(K - 1, 0))
+    double psum[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      sS[(rb + 4 * i + lk) * 17 + lr] = vcur[i] - ((acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]));
+      psum[i] = ((acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i])) + ((acc[4][i] + acc[5][i]) + (acc[6][i] + acc[7][i]));
+    if (S == 2) {
+      if (half == 1) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sP[(rb + 4 * i + lk) * 17 + lr] = psum[i];
+      }
+      geneo_lds_barrier();
+    }
+    if (half == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        sS[(rb + 4 * i + lk) * 17 + lr] = vcur[i] - (S == 2 ? psum[i] + sP[(rb + 4 * i + lk) * 17 + lr] : psum[i]);
+    }
     geneo_lds_barrier();
     TR_ZERO()
 #pragma unroll
@@ -446,7 +479,7 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
     for (int i = 0; i < 4; ++i) {
       const int row = rb + 4 * i + lk;
       const double x = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
-      if (ok) {
+      if (ok && half == 0) {
         xk[row * b + col] = x;
         Vb[(int64_t)(K * TILE + row) * b + col] = x;
       }
@@ -1212,16 +1245,23 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, dou
   for (const SubDesc& sd : pc->sub) maxw = std::max(maxw, sd.wB);
   const int ncb = (b + 15) / 16;
   const int ringlen = (maxw + 1) * TILE * b + 16;
-  const size_t lds = sizeof(double) * ((size_t)ringlen + (size_t)ncb * TILE * 17);
+  // two waves per (row half, column block) splitting the tiles when they fit in 512 threads
+  const int split = ncb <= 2 ? 2 : 1;
+  const size_t lds = sizeof(double) * ((size_t)ringlen + (size_t)2 * ncb * TILE * 17);
   // tile slots per step: the smallest multiple of the prefetch depth (6) >= w
   const int W = std::max(6, (maxw + 5) / 6 * 6);
   if (lds <= 160 * 1024 && W <= 30 && pc->d_z0) {
-#define GN_TR(WV)                                                                                    \
+#define GN_TR1(WV, PV, SV)                                                                           \
   do {                                                                                               \
-    GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                               (int)lds));                                                           \
-    hipLaunchKernelGGL((k_trsm_ring<WV, 6>), dim3(pc->n_sub), dim3(128 * ncb), lds, s, pc->d_sub, b, ringlen, \
-                       T, D, pc->d_z0, V);                                                           \
+    GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV, PV, SV>,                                 \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));               \
+    hipLaunchKernelGGL((k_trsm_ring<WV, PV, SV>), dim3(pc->n_sub), dim3(128 * ncb * SV), lds, s, pc->d_sub, b, \
+                       ringlen, T, D, pc->d_z0, V);                                                  \
+  } while (0)
+#define GN_TR(WV)                                   \
+  do {                                              \
+    if (split == 2) GN_TR1(WV, 3, 2);               \
+    else GN_TR1(WV, 6, 1);                          \
   } while (0)
     switch (W) {
       case 6: GN_TR(6); break;
@@ -1231,6 +1271,7 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, dou
       default: GN_TR(30); break;
     }
 #undef GN_TR
+#undef GN_TR1
     GN_CHECK_LAUNCH();
     return;
   }
