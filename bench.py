@@ -39,6 +39,8 @@ def make_workload(name):
         return gen.config_c1()
     if name == "c3":
         return gen.config_c3()
+    if name == "c5":
+        return gen.config_c5()
     raise ValueError(name)
 
 

@@ -1136,8 +1136,30 @@ __global__ __launch_bounds__(NT) void k_trsm_tile(int NB, int K, double* __restr
 }
 
 // A(I,J) -= L(I,K) L(J,K)^T for K < J <= I (blockIdx.x enumerates the pairs)
+// one 16 x 16 quadrant per wave of the tile product X Y, X(r,k) at xs[k*TILE + r];
+// Y(k,c) at ys[c*TILE + k] (TRANSY = false) or ys[k*TILE + c] (TRANSY = true)
+template <bool TRANSY>
+__device__ inline void tile_mma(const double* __restrict__ xs, const double* __restrict__ ys, int qr, int qc,
+                                int lr, int lk, double out[4]) {
+  gn_d4 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = gn_d4{0, 0, 0, 0};
+  double av[8], bv[8];
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) {
+    const int k = 4 * ks + lk;
+    av[ks] = xs[k * TILE + qr * 16 + lr];
+    bv[ks] = TRANSY ? ys[k * TILE + qc * 16 + lr] : ys[(qc * 16 + lr) * TILE + k];
+  }
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], acc[ks & 3], 0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) out[i] = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+}
+
+// trailing update A(I,J) -= L(I,K) L(J,K)^T for the lower block triangle, one tile
+// per workgroup on FP64 matrix cores
 __global__ __launch_bounds__(NT) void k_syrk_tile(int NB, int K, double* __restrict__ A) {
-  __shared__ double X[TILE * (TILE + 1)], Yt[TILE * (TILE + 1)];
   int m = NB - K - 1;
   int idx = blockIdx.x;
   // row-major enumeration of the lower triangle of an m x m block matrix
@@ -1147,59 +1169,49 @@ __global__ __launch_bounds__(NT) void k_syrk_tile(int NB, int K, double* __restr
   int J0 = idx - I0 * (I0 + 1) / 2;
   if (I0 >= m) return;
   int I = K + 1 + I0, J = K + 1 + J0;
-  lds_tile(X, A + ((int64_t)I * NB + K) * TILE2);
-  lds_tile(Yt, A + ((int64_t)J * NB + K) * TILE2);
-  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4, qr = wid & 1, qc = wid >> 1;
+  double o[4];
+  tile_mma<true>(A + ((int64_t)I * NB + K) * TILE2, A + ((int64_t)J * NB + K) * TILE2, qr, qc, lr, lk, o);
   double* t = A + ((int64_t)I * NB + J) * TILE2;
-  const int i = threadIdx.x % TILE, c0 = threadIdx.x / TILE;
-  for (int q = 0; q < 4; ++q) {
-    int c = c0 + 8 * q;
-    double s = 0.0;
-    for (int k = 0; k < TILE; ++k) s += X[k * (TILE + 1) + i] * Yt[k * (TILE + 1) + c];
-    t[c * TILE + i] -= s;
-  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t[(qc * 16 + lr) * TILE + qr * 16 + 4 * i + lk] -= o[i];
 }
 
-// Z(:, J) = L^-1 E_J for block column J = blockIdx.x (forward substitution by tiles)
-__global__ __launch_bounds__(NT) void k_tri_inv(int NB, const double* __restrict__ L,
-                                                const double* __restrict__ Dinv, double* __restrict__ Z) {
-  __shared__ double X[TILE * (TILE + 1)], Yt[TILE * (TILE + 1)], S[TILE * (TILE + 1)];
+// Explicit inverse Z = L^-1 of the coarse factor, right-looking over block
+// rows K: row K is finished (Z(K,J) = -Dinv_K sum_{J<=M<K} L(K,M) Z(M,J) for
+// J < K, Z(K,K) = Dinv_K), then every later row I accumulates L(I,K) Z(K,J).
+// Z starts at zero and keeps the running sums in its unfinished rows.
+__global__ __launch_bounds__(NT) void k_trinv_row(int NB, int K, const double* __restrict__ Dinv,
+                                                  double* __restrict__ Z) {
   const int J = blockIdx.x;
-  const int i = threadIdx.x % TILE, c0 = threadIdx.x / TILE;
-  for (int I = 0; I < NB; ++I) {
-    double* zt = Z + ((int64_t)I * NB + J) * TILE2;
-    if (I < J) {
-      for (int e = threadIdx.x; e < TILE2; e += NT) zt[e] = 0.0;
-      continue;
-    }
-    double acc[4];
-    for (int q = 0; q < 4; ++q) acc[q] = (I == J && i == c0 + 8 * q) ? 1.0 : 0.0;
-    for (int K = J; K < I; ++K) {
-      __syncthreads();
-      lds_tile(X, L + ((int64_t)I * NB + K) * TILE2);   // L(I,K)
-      lds_tile(Yt, Z + ((int64_t)K * NB + J) * TILE2);  // Z(K,J)
-      __syncthreads();
-      for (int q = 0; q < 4; ++q) {
-        int c = c0 + 8 * q;
-        double s = 0.0;
-        for (int k = 0; k < TILE; ++k) s += X[k * (TILE + 1) + i] * Yt[c * (TILE + 1) + k];
-        acc[q] -= s;
-      }
-    }
-    __syncthreads();
-    for (int q = 0; q < 4; ++q) S[(c0 + 8 * q) * (TILE + 1) + i] = acc[q];
-    lds_tile(X, Dinv + (int64_t)I * TILE2);
-    __syncthreads();
-    for (int q = 0; q < 4; ++q) {
-      int c = c0 + 8 * q;
-      double s = 0.0;
-      for (int k = 0; k < TILE; ++k) s += X[k * (TILE + 1) + i] * S[c * (TILE + 1) + k];
-      zt[c * TILE + i] = s;
-    }
-    __threadfence_block();
-    __syncthreads();
+  double* zt = Z + ((int64_t)K * NB + J) * TILE2;
+  const double* dk = Dinv + (int64_t)K * TILE2;
+  if (J == K) {
+    for (int e = threadIdx.x; e < TILE2; e += NT) zt[e] = dk[e];
+    return;
   }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4, qr = wid & 1, qc = wid >> 1;
+  double o[4];
+  tile_mma<false>(dk, zt, qr, qc, lr, lk, o);
+  __syncthreads();   // every wave has read its column block of the running sum
+#pragma unroll
+  for (int i = 0; i < 4; ++i) zt[(qc * 16 + lr) * TILE + qr * 16 + 4 * i + lk] = -o[i];
 }
+
+__global__ __launch_bounds__(NT) void k_trinv_update(int NB, int K, const double* __restrict__ L,
+                                                     double* __restrict__ Z) {
+  const int I = K + 1 + blockIdx.x / (K + 1), J = blockIdx.x % (K + 1);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4, qr = wid & 1, qc = wid >> 1;
+  double o[4];
+  tile_mma<false>(L + ((int64_t)I * NB + K) * TILE2, Z + ((int64_t)K * NB + J) * TILE2, qr, qc, lr, lk, o);
+  double* zt = Z + ((int64_t)I * NB + J) * TILE2;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) zt[(qc * 16 + lr) * TILE + qr * 16 + 4 * i + lk] += o[i];
+}
+
 
 }  // namespace
 
@@ -1390,8 +1402,15 @@ void dense_chol(int NB, double* A, double* Dinv, int* info, hipStream_t s) {
 }
 
 void tri_inv(int NB, const double* L, const double* Dinv, double* Z, hipStream_t s) {
-  hipLaunchKernelGGL(k_tri_inv, dim3(NB), dim3(NT), 0, s, NB, L, Dinv, Z);
-  GN_CHECK_LAUNCH();
+  GN_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)NB * NB * TILE2, s));
+  for (int K = 0; K < NB; ++K) {
+    hipLaunchKernelGGL(k_trinv_row, dim3(K + 1), dim3(NT), 0, s, NB, K, Dinv, Z);
+    GN_CHECK_LAUNCH();
+    if (K + 1 < NB) {
+      hipLaunchKernelGGL(k_trinv_update, dim3((NB - K - 1) * (K + 1)), dim3(NT), 0, s, NB, K, L, Z);
+      GN_CHECK_LAUNCH();
+    }
+  }
 }
 
 }  // namespace gnk
