@@ -208,3 +208,34 @@ def test_c3_precond_symmetric(c3):
     pc.apply(v, mv)
     a1, a2 = float((v * mu).sum()), float((u * mv).sum())
     assert abs(a1 - a2) <= 1e-10 * max(abs(a1), abs(a2))
+
+
+def test_c5_largest_single_solve():
+    """6,054,912-DOF ramped laminate, 1536 subdomains, FP32 local factors inside
+    FP64 PCG, 12 eigenvectors each (N_H = 18,432): sampled rows of A and b
+    against the oracle, and the solve reaches 1e-8 or the FP64 rounding floor."""
+    w = gen.config_c5()
+    print(f"[gpu] c5 n_free={w.n_free}", flush=True)
+    prob = _gp().Problem.from_workload(w)
+    rows = np.sort(np.random.default_rng(9).choice(w.n_free, size=24, replace=False))
+    sampled = fem.assemble_rows(w, rows)
+    x = np.random.default_rng(3).standard_normal(prob.n_free)
+    y = torch.zeros((1, prob.n_free), dtype=torch.float64, device=DEV)
+    prob.matvec(_t(x[None, :]), y)
+    b = torch.zeros((1, prob.n_free), dtype=torch.float64, device=DEV)
+    prob.rhs(b)
+    yh, bh = y[0].cpu().numpy(), b[0].cpu().numpy()
+    for r, (cols, vals, bv) in zip(rows, sampled):
+        assert abs(yh[r] - vals @ x[cols]) <= 1e-12 * (np.abs(vals) @ np.abs(x[cols]))
+        assert abs(bh[r] - bv) <= 1e-13 * max(abs(bv), 1e-300) + 1e-300
+    pc = _gp().Preconditioner.from_workload(prob, w, local_prec=32)
+    assert pc.report["coarse_dim"] >= 12 * w.n_sub
+    xs = torch.zeros_like(b)
+    st, rep = _gp().solve(prob, pc, b, xs, rtol=1e-8, maxit=3000, check_every=16)
+    r = rep[0]
+    print(f"[gpu] c5 iters {r['iters']} kappa {r['cond_est']:.1f} NH {pc.report['coarse_dim']} "
+          f"true {r['true_rel_res']:.2e} floor {r['res_floor']:.2e}", flush=True)
+    assert r["converged"] == 1
+    assert r["true_rel_res"] <= max(1e-8, 4 * r["res_floor"])
+    pc.close()
+    prob.close()
