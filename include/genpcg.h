@@ -120,8 +120,11 @@ gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t n
  * factorisation, FP32 storage and triangular solves, FP64 accumulation of the
  * result).  shift > 0 is the shift-and-invert shift (Section 3.3.2; 0 = 1e-2).
  * eig_tol / eig_maxit bound the batched eigensolver (0 = defaults 1e-12 / 300):
- * it stops when every wanted Ritz pair has ||P^-1 B v - nu v|| <= eig_tol ||P^-1 B v||,
- * or when that residual stays below 1e-9 without halving for 15 iterations.
+ * it stops when every Ritz pair that enters the coarse space has
+ * ||P^-1 B v - nu v|| <= eig_tol ||P^-1 B v|| and the other wanted pairs (those
+ * below 1.5 x threshold, and the first one past the selection, which only fix
+ * m_j through their eigenvalues) have it below sqrt(eig_tol), or when the
+ * residual stays below 1e-9 without halving over 15 block solves.
  * eig_block is the subspace block size.  0 = automatic: nev + max(8, nev/2)
  * (at most 64) for a fixed nev; for a threshold min(32, nev_max + 8), grown by
  * 16 up to 64 and the eigensolve repeated while the eigenvalues below
@@ -158,7 +161,7 @@ typedef struct gn_setup_report {
   int32_t band_tiles;        /* band width in 32-row tiles (largest subdomain) */
   double t_local_s, t_eigen_s, t_coarse_s, t_total_s;
   int64_t hbm_bytes;         /* device bytes held by the preconditioner        */
-  double eig_resid;          /* largest final relative Ritz residual           */
+  double eig_resid;          /* largest final relative Ritz residual of the pairs in the coarse space */
   int32_t eig_solves;        /* block solves with the pencil factors            */
 } gn_setup_report;
 

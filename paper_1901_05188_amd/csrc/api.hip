@@ -647,7 +647,8 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
         if (it == 0) continue;
         bool all = true;
         block_short = false;
-        double worst = 0.0;   // largest relative residual over the wanted pairs
+        double worst = 0.0;          // largest scaled residual over the wanted pairs
+        double strict_worst = 0.0;   // largest relative residual of the coarse-space pairs
         for (int j = 0; j < n_sub; ++j) {
           // wanted pairs: nev+1 (fixed) or those below 1.5*threshold plus one (capped)
           int nw;
@@ -664,18 +665,38 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
             nw = std::min(std::min(nw + 1, o->nev_max + 1), b - guard / 2);
           }
           nwant[j] = nw;
+          // pairs whose eigenvectors enter the coarse space (m_j of them, with a
+          // generous cluster margin) need the full residual tolerance; the others
+          // only decide m_j through their eigenvalues, whose error is of the order
+          // of the squared residual, so sqrt(eig_tol) suffices for them
+          auto lam_of = [&](int k) {
+            double nk = prev_nu[(size_t)j * b + k];
+            return nk > 0 ? 1.0 / nk - shift : 1e300;
+          };
+          int nin = 0;
+          if (fixed) {
+            nin = std::min(o->nev, nw);
+          } else {
+            while (nin < nw && lam_of(nin) < o->threshold) ++nin;
+            nin = std::min(nin, o->nev_max);
+          }
+          while (nin > 0 && nin < nw && lam_of(nin) - lam_of(nin - 1) <= 1e-6 * std::fabs(lam_of(nin - 1)) + 1e-8)
+            ++nin;
           for (int k = 0; k < nw; ++k) {
             double nk = prev_nu[(size_t)j * b + k];
             double rs = h_res[(size_t)j * 2 * b + k], zz = h_res[(size_t)j * 2 * b + b + k];
             if (nk <= 1e-12 / shift) continue;      // null space of B: lambda = inf
             double rel = zz > 0 ? std::sqrt(rs / zz) : 0.0;
-            if (!(rel <= eig_tol)) all = false;
-            if (!(rel <= worst)) worst = std::isfinite(rel) ? std::max(worst, rel) : 1e300;
+            // scaled so that the tolerance of every pair reads as eig_tol
+            const double scaled = k < nin ? rel : rel * (eig_tol / std::sqrt(eig_tol));
+            if (!(scaled <= eig_tol)) all = false;
+            if (!(scaled <= worst)) worst = std::isfinite(scaled) ? std::max(worst, scaled) : 1e300;
+            if (k < nin && std::isfinite(rel)) strict_worst = std::max(strict_worst, rel);
           }
         }
         worst_hist.push_back(worst);
         solves_hist.push_back(solves);
-        eig_resid = worst;
+        eig_resid = strict_worst;
         // accept a residual that has reached the rounding floor: no halving over
         // the last 15 block solves once it is below 1e-9
         bool stagnated = false;
