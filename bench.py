@@ -144,6 +144,7 @@ def main():
     ap.add_argument("--local-prec", type=int, default=64)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-local-factor comparison leg")
     ap.add_argument("--solve-reps", type=int, default=5, help="warm solves per step for latency")
     ap.add_argument("--multi-rhs", type=int, default=16,
                     help="columns of the batched multi-RHS leg (0 = skip)")
@@ -259,6 +260,29 @@ def main():
             "working_launches": applications, "bytes_per_working_launch": bytes_per_app,
             "bytes_per_launch": bytes_per_launch}
     lat_sorted = sorted(lat_plain)
+    # mixed-precision leg: the same operator with FP32 local factors inside the
+    # FP64 outer PCG (warm solves), its error against the FP64 solution above
+    mixed = None
+    if args.local_prec == 64 and not args.no_mixed:
+        pc32 = gp.Preconditioner.from_workload(prob, w, local_prec=32)
+        x32 = torch.zeros_like(b)
+        gp.solve(prob, pc32, b, x32, rtol=args.rtol, maxit=5000, check_every=16)   # warm
+        mt = []
+        for r in range(3):
+            x32.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, mrep = gp.solve(prob, pc32, b, x32, rtol=args.rtol, maxit=5000, check_every=16)
+            torch.cuda.synchronize()
+            mt.append(time.perf_counter() - t0)
+        tmix = statistics.median(mt)
+        mixed = {"local_prec": 32, "solve_s": tmix, "solve_dofs_per_s": n_dof / tmix,
+                 "speedup_vs_fp64_solve": statistics.median(lat_plain) / tmix,
+                 "iters": mrep[0]["iters"], "true_rel_res": mrep[0]["true_rel_res"],
+                 "rel_diff_vs_fp64_solution": float(torch.linalg.norm(x32 - x) / torch.linalg.norm(x)),
+                 "setup_s": pc32.report["t_total_s"]}
+        log(f"mixed precision: {tmix:.3f}s per solve, {mrep[0]['iters']} iters, x{mixed['speedup_vs_fp64_solve']:.2f}")
+        pc32.close()
     # batched multi-RHS leg: the workload's load plus seeded random loads, all
     # columns in one batched solve (the warm operator and preconditioner)
     multi = None
@@ -319,6 +343,8 @@ def main():
         "kernel_groups_ms_per_solve": {k: v["ms_total"] / args.solve_reps for k, v in groups.items()},
         "roofline": roof,
     }
+    if mixed is not None:
+        res["mixed_precision"] = mixed
     if multi is not None:
         res["multi_rhs"] = multi
     if not args.no_cpu_baseline:
