@@ -41,6 +41,7 @@ typedef int32_t gn_status;
 enum {
   GN_OK = 0,
   GN_WARN_MAXIT = 1,          /* solve stopped at maxit; last iterate returned   */
+  GN_PENDING = 2,             /* gn_server_wait: request not finished in time    */
   GN_ERR_ARG = -1,            /* invalid argument / inconsistent sizes           */
   GN_ERR_OOM = -2,            /* device allocation failed                        */
   GN_ERR_NOT_SPD = -3,        /* a Cholesky factorisation met a non-positive pivot */
@@ -105,6 +106,17 @@ gn_status gn_problem_info(const gn_problem* p, int64_t* n_free, int64_t* nnz, in
 /* Copy the assembled load (n_free x nrhs, column-major, leading dim ld) into
  * the device buffer b_dev. */
 gn_status gn_problem_rhs(const gn_problem* p, double* b_dev, int64_t ld, void* stream);
+
+/* Load vectors alone, on the mesh and Dirichlet mask of p (Section 2: the
+ * right-hand side of eq-fe, body force plus top-face traction, 2x2x2 and 2x2
+ * Gauss as in gn_assemble), for new load cases of an assembled operator.
+ * body (host, may be NULL): n_elem * ncomp values, added to every column.
+ * traction (host, may be NULL): layout [rhs][face = ex + ne[0]*ey][comp].
+ * b_dev (device): nrhs columns in the free numbering, leading dimension ld.
+ * Temporary device memory of n_dof * nrhs doubles is allocated and freed;
+ * the call returns after b_dev is written. */
+gn_status gn_load_vectors(gn_problem* p, const double* body, int32_t nrhs, const double* traction,
+                          double* b_dev, int64_t ld, void* stream);
 
 /* y = A x for ncol columns (device pointers, free numbering, leading dim ld). */
 gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t ncol,
@@ -217,6 +229,68 @@ typedef struct gn_solve_report {
 gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev, double* x_dev,
                    int32_t nrhs, int64_t ld, const gn_solve_opts* opts, void* stream,
                    gn_solve_report* reports);
+
+/* Device bytes held by p and pc (pc may be NULL): assembled operator,
+ * element matrices, workspaces, local factors, coarse basis and factor. */
+gn_status gn_footprint(const gn_problem* p, const gn_precond* pc, int64_t* bytes);
+
+/* Request server (the multi-right-hand-side path of Section 3.1 for a stream
+ * of load cases): operators stay resident with their preconditioners; each
+ * has its own HIP stream and a host worker thread that runs up to `slots`
+ * right-hand sides in every launch (the batched kernels of gn_solve).  Each
+ * column keeps its own CG recurrence, stopping test and restarts, so a
+ * column's result is the same, bit for bit, whichever slot it takes and
+ * whatever else is in flight.  A column that finishes frees its slot, and the
+ * next queued column of that operator starts at the following check (every
+ * check_every iterations) while the others keep iterating.  Operators'
+ * workers run concurrently, so different operators overlap on the device.
+ *  - hbm_budget: device bytes the resident operators may hold together
+ *    (gn_footprint after the batched workspace is allocated); 0 = the
+ *    device's total memory.  gn_server_add fails with GN_ERR_OOM beyond it.
+ *  - slots: columns per operator batch, 1..16 (0 = 16).
+ *  - check_every: CG iterations between slot updates (0 = 8).
+ *  - maxit_cap: largest maxit a request may ask for (0 = 2000). */
+typedef struct gn_server_opts {
+  int64_t hbm_budget;
+  int32_t slots;
+  int32_t check_every;
+  int32_t maxit_cap;
+} gn_server_opts;
+typedef struct gn_server gn_server;
+
+gn_status gn_server_create(const gn_server_opts* opts, gn_server** out);
+
+/* Register a resident operator (pc may be NULL: plain CG).  The caller keeps
+ * ownership of p and pc, must have finished its own work on them, and must
+ * not use them elsewhere (gn_solve, gn_precond_apply, another server) until
+ * gn_server_remove returns.  *op receives the operator id, *bytes (may be
+ * NULL) its footprint. */
+gn_status gn_server_add(gn_server* sv, gn_problem* p, gn_precond* pc, int32_t* op, int64_t* bytes);
+
+/* Finish the operator's queued and running columns, stop its worker and
+ * return its footprint to the budget. */
+gn_status gn_server_remove(gn_server* sv, int32_t op);
+
+/* Queue nrhs right-hand sides of operator op (device pointers, free
+ * numbering, column-major with leading dimension ld; x0 = 0).  b_dev must be
+ * complete on the device when this is called, no pending work may access
+ * x_dev, and both must stay allocated and untouched until gn_server_wait has
+ * returned the ticket (the operator's worker writes x_dev on its own stream).  Returns at once;
+ * *ticket identifies the request. */
+gn_status gn_server_submit(gn_server* sv, int32_t op, const double* b_dev, double* x_dev, int32_t nrhs,
+                           int64_t ld, double rtol, int32_t maxit, int64_t* ticket);
+
+/* Wait up to timeout_s seconds (< 0: no limit) for a request.  When it has
+ * finished: x_dev is complete, reports (host, nrhs entries, may be NULL) and
+ * *latency_s (submit to the last column's completion, may be NULL) are
+ * filled, the ticket is released and the request's status is returned
+ * (worst over its columns, as gn_solve).  Otherwise GN_PENDING. */
+gn_status gn_server_wait(gn_server* sv, int64_t ticket, double timeout_s, gn_solve_report* reports,
+                         double* latency_s);
+
+/* Finish every queued request, stop all workers and free the server (the
+ * operators stay with the caller). */
+void gn_server_destroy(gn_server* sv);
 
 /* Per-kernel timing with HIP events on the library's launch stream.  enable=1
  * starts recording every launch of the named kernel group ("spmv", "trsv",

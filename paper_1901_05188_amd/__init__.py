@@ -4,8 +4,8 @@ The compute path is libgenpcg.so (HIP, gfx950); :mod:`.binding` only marshals
 arguments.  Build it with ``python -m paper_1901_05188_amd.build_lib`` or
 ``__graft_entry__.build()``.
 """
-from .binding import (Problem, Preconditioner, solve, profile_enable, profile_read, lib,
-                      GenPCGError, EXPORTS, LIB_PATH)
+from .binding import (Problem, Preconditioner, Server, solve, footprint, profile_enable, profile_read,
+                      lib, GenPCGError, EXPORTS, LIB_PATH)
 
-__all__ = ["Problem", "Preconditioner", "solve", "profile_enable", "profile_read", "lib",
-           "GenPCGError", "EXPORTS", "LIB_PATH"]
+__all__ = ["Problem", "Preconditioner", "Server", "solve", "footprint", "profile_enable", "profile_read",
+           "lib", "GenPCGError", "EXPORTS", "LIB_PATH"]

@@ -16,12 +16,14 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgenpcg.so")
 
-GN_OK, GN_WARN_MAXIT = 0, 1
-STATUS = {0: "OK", 1: "WARN_MAXIT", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_NOT_SPD",
+GN_OK, GN_WARN_MAXIT, GN_PENDING = 0, 1, 2
+STATUS = {0: "OK", 1: "WARN_MAXIT", 2: "PENDING", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_NOT_SPD",
           -4: "ERR_EIG_NOCONV", -5: "ERR_COARSE_SINGULAR", -6: "ERR_DEVICE", -7: "ERR_BREAKDOWN"}
-EXPORTS = ["gn_assemble", "gn_problem_info", "gn_problem_rhs", "gn_matvec", "gn_setup_geneo",
-           "gn_precond_eigenvalues", "gn_precond_apply", "gn_solve", "gn_profile_enable",
-           "gn_profile_read", "gn_destroy_problem", "gn_destroy_precond", "gn_last_error"]
+EXPORTS = ["gn_assemble", "gn_problem_info", "gn_problem_rhs", "gn_load_vectors", "gn_matvec",
+           "gn_setup_geneo", "gn_precond_eigenvalues", "gn_precond_apply", "gn_solve", "gn_footprint",
+           "gn_server_create", "gn_server_add", "gn_server_remove", "gn_server_submit", "gn_server_wait",
+           "gn_server_destroy", "gn_profile_enable", "gn_profile_read", "gn_destroy_problem",
+           "gn_destroy_precond", "gn_last_error"]
 
 
 class GenPCGError(RuntimeError):
@@ -67,6 +69,11 @@ class gn_solve_opts(C.Structure):
                 ("sequential", C.c_int32)]
 
 
+class gn_server_opts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("slots", C.c_int32), ("check_every", C.c_int32),
+                ("maxit_cap", C.c_int32)]
+
+
 class gn_solve_report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_res", C.c_double),
                 ("true_rel_res", C.c_double), ("cond_est", C.c_double), ("t_solve_s", C.c_double),
@@ -89,7 +96,19 @@ def lib():
         L.gn_problem_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int32)]
         L.gn_problem_rhs.argtypes = [vp, vp, C.c_int64, vp]
+        L.gn_load_vectors.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double), vp,
+                                      C.c_int64, vp]
         L.gn_matvec.argtypes = [vp, vp, vp, C.c_int32, C.c_int64, vp]
+        L.gn_footprint.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+        L.gn_server_create.argtypes = [C.POINTER(gn_server_opts), C.POINTER(vp)]
+        L.gn_server_add.argtypes = [vp, vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.gn_server_remove.argtypes = [vp, C.c_int32]
+        L.gn_server_submit.argtypes = [vp, C.c_int32, vp, vp, C.c_int32, C.c_int64, C.c_double, C.c_int32,
+                                       C.POINTER(C.c_int64)]
+        L.gn_server_wait.argtypes = [vp, C.c_int64, C.c_double, C.POINTER(gn_solve_report),
+                                     C.POINTER(C.c_double)]
+        L.gn_server_destroy.argtypes = [vp]
+        L.gn_server_destroy.restype = None
         L.gn_setup_geneo.argtypes = [vp, C.POINTER(gn_dd_opts), vp, C.POINTER(vp),
                                      C.POINTER(gn_setup_report)]
         L.gn_precond_eigenvalues.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.c_int32,
@@ -106,7 +125,7 @@ def lib():
         L.gn_destroy_precond.restype = None
         L.gn_last_error.restype = C.c_char_p
         for f in EXPORTS:
-            if f not in ("gn_destroy_problem", "gn_destroy_precond", "gn_last_error"):
+            if f not in ("gn_destroy_problem", "gn_destroy_precond", "gn_server_destroy", "gn_last_error"):
                 getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -191,6 +210,20 @@ class Problem:
         assert out.is_cuda and out.dtype.is_floating_point and out.is_contiguous()
         assert out.shape[-1] == self.n_free and out.numel() >= self.nrhs * self.n_free
         _check(lib().gn_problem_rhs(self.handle, _tensor_ptr(out), self.n_free, _stream(stream)))
+        return out
+
+    def load_vectors(self, out, body=None, traction=None, stream=None):
+        """Load vectors of new load cases into a (nrhs, n_free) float64 CUDA tensor.
+
+        body: (n_elem * ncomp,) host array added to every column, or None;
+        traction: (nrhs * ne[0] * ne[1] * ncomp,) host array, layout [rhs][face][comp], or None."""
+        nrhs = 1 if out.dim() == 1 else out.shape[0]
+        assert out.is_cuda and out.dtype.is_floating_point and out.is_contiguous()
+        assert out.shape[-1] == self.n_free
+        bd = None if body is None else np.ascontiguousarray(body, dtype=np.float64)
+        tr = None if traction is None else np.ascontiguousarray(traction, dtype=np.float64)
+        _check(lib().gn_load_vectors(self.handle, _dptr(bd, C.c_double), nrhs, _dptr(tr, C.c_double),
+                                     _tensor_ptr(out), self.n_free, _stream(stream)))
         return out
 
     def matvec(self, x, y, stream=None):
@@ -279,6 +312,72 @@ def solve(prob: Problem, pc: Optional[Preconditioner], b, x, rtol=1e-8, maxit=10
     st = _check(lib().gn_solve(prob.handle, pc.handle if pc is not None else None, _tensor_ptr(b),
                                _tensor_ptr(x), nrhs, prob.n_free, C.byref(o), _stream(stream), reps))
     return st, [{f: getattr(r, f) for f, _ in gn_solve_report._fields_} for r in reps]
+
+
+def footprint(prob: Problem, pc: Optional[Preconditioner] = None) -> int:
+    """Device bytes held by a problem and (optionally) its preconditioner."""
+    b = C.c_int64()
+    _check(lib().gn_footprint(prob.handle, pc.handle if pc is not None else None, C.byref(b)))
+    return b.value
+
+
+class Server:
+    """Request server (gn_server_*): resident operators, up to `slots` columns
+    per operator in every launch, finished columns replaced at each check."""
+
+    def __init__(self, hbm_budget=0, slots=0, check_every=0, maxit_cap=0):
+        o = gn_server_opts(int(hbm_budget), int(slots), int(check_every), int(maxit_cap))
+        h = C.c_void_p()
+        _check(lib().gn_server_create(C.byref(o), C.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def add(self, prob: Problem, pc: Optional[Preconditioner] = None) -> int:
+        """Register an operator; returns its id (raises GenPCGError ERR_OOM beyond the budget)."""
+        op, by = C.c_int32(), C.c_int64()
+        _check(lib().gn_server_add(self.handle, prob.handle, pc.handle if pc is not None else None,
+                                   C.byref(op), C.byref(by)))
+        self.last_add_bytes = by.value
+        return op.value
+
+    def remove(self, op: int):
+        _check(lib().gn_server_remove(self.handle, int(op)))
+
+    def submit(self, op: int, n_free: int, b, x, rtol=1e-8, maxit=1000) -> int:
+        """Queue the rows of (nrhs, n_free) float64 CUDA tensors b -> x; returns a ticket.
+        b must be complete on the device (synchronise its producer first)."""
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        assert b.shape == x.shape and b.shape[-1] == n_free and b.is_contiguous() and x.is_contiguous()
+        t = C.c_int64()
+        _check(lib().gn_server_submit(self.handle, int(op), _tensor_ptr(b), _tensor_ptr(x), nrhs, n_free,
+                                      float(rtol), int(maxit), C.byref(t)))
+        self._keep[t.value] = (b, x, nrhs)
+        return t.value
+
+    def wait(self, ticket: int, timeout=-1.0):
+        """Block until the request finishes (or timeout seconds pass: returns None).
+        Returns (status, reports, latency_s)."""
+        b, x, nrhs = self._keep[ticket]
+        reps = (gn_solve_report * nrhs)()
+        lat = C.c_double()
+        st = lib().gn_server_wait(self.handle, int(ticket), float(timeout), reps, C.byref(lat))
+        if st == GN_PENDING:
+            return None
+        del self._keep[ticket]
+        _check(st)
+        return st, [{f: getattr(r, f) for f, _ in gn_solve_report._fields_} for r in reps], lat.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gn_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_enable(on: bool = True):

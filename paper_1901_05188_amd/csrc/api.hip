@@ -60,8 +60,18 @@ static T* upload(std::vector<void*>& owned, const T* h, size_t count, hipStream_
   GN_HIP(hipMemcpyAsync(d, h, count * sizeof(T), hipMemcpyHostToDevice, s));
   return d;
 }
-static double now_s() {
+double gnh::now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+using gnh::now_s;
+
+int64_t gnh::resident_bytes(const std::vector<void*>& owned) {
+  int64_t t = 0;
+  for (void* q : owned) {
+    size_t sz = 0;
+    if (hipMemPtrGetInfo(q, &sz) == hipSuccess) t += (int64_t)sz;
+  }
+  return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -226,7 +236,7 @@ extern "C" gn_status gn_assemble(const gn_grid* grid, const gn_material* mat, co
     d_trac = upload(tmp, loads->traction, (size_t)loads->nrhs * p->ne[0] * p->ne[1] * nc, s);
   gnk::element_matrices(p, d_mats, mat->n_mat, d_emat, d_eang, d_etilt, d_ek, s);
   gnk::assemble_matrix(p, s);
-  gnk::assemble_load(p, d_body, d_trac, s);
+  gnk::assemble_load(p, d_body, d_trac, p->nrhs, p->d_b, s);
   GN_HIP(hipStreamSynchronize(s));
   dfree_all(tmp);
   // CG workspace
@@ -273,6 +283,38 @@ extern "C" gn_status gn_problem_rhs(const gn_problem* p, double* b_dev, int64_t 
   if (ld < p->n_free) argfail("ld < n_free");
   hipStream_t s = (hipStream_t)stream;
   for (int c = 0; c < p->nrhs; ++c) gnk::gather_free(p, p->d_b + (int64_t)c * p->n_dof, b_dev + c * ld, s);
+  return GN_OK;
+  GN_CATCH
+}
+
+extern "C" gn_status gn_load_vectors(gn_problem* p, const double* body, int32_t nrhs, const double* traction,
+                                     double* b_dev, int64_t ld, void* stream) {
+  GN_TRY
+  if (!p || !b_dev) argfail("null argument");
+  if (nrhs < 1 || ld < p->n_free) argfail("bad nrhs/ld");
+  hipStream_t s = (hipStream_t)stream;
+  const int nc = p->nc;
+  if (body)
+    for (int64_t i = 0; i < p->n_elem * nc; ++i)
+      if (!std::isfinite(body[i])) argfail("non-finite body force");
+  if (traction)
+    for (int64_t i = 0; i < (int64_t)nrhs * p->ne[0] * p->ne[1] * nc; ++i)
+      if (!std::isfinite(traction[i])) argfail("non-finite traction");
+  std::vector<void*> tmp;
+  try {
+    const double *d_body = nullptr, *d_trac = nullptr;
+    if (body) d_body = upload(tmp, body, (size_t)p->n_elem * nc, s);
+    if (traction) d_trac = upload(tmp, traction, (size_t)nrhs * p->ne[0] * p->ne[1] * nc, s);
+    double* d_full = dalloc<double>(tmp, (size_t)p->n_dof * nrhs);
+    gnk::assemble_load(p, d_body, d_trac, nrhs, d_full, s);
+    for (int c = 0; c < nrhs; ++c) gnk::gather_free(p, d_full + (int64_t)c * p->n_dof, b_dev + c * ld, s);
+    GN_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    dfree_all(tmp);
+    throw;
+  }
+  dfree_all(tmp);
   return GN_OK;
   GN_CATCH
 }
@@ -932,7 +974,7 @@ extern "C" gn_status gn_precond_apply(gn_precond* pc, const double* r_dev, doubl
 
 // || |A| |x| ||^2 for one full-numbering vector: eps times its square root is
 // the rounding floor of b - A x for any FP64 x near x (attainable accuracy)
-static double absmv_norm2(gn_problem* p, const double* x, hipStream_t s) {
+double gnh::absmv_norm2(gn_problem* p, const double* x, hipStream_t s) {
   const int nb = gnk::spmv_blocks(p);
   std::vector<double> part(nb);
   gnk::absmv_partial(p, x, p->d_part, s);
@@ -942,13 +984,13 @@ static double absmv_norm2(gn_problem* p, const double* x, hipStream_t s) {
   for (double v : part) t += v;
   return t;
 }
-// restarts stop once b - A x is within this factor of eps || |A| |x| ||
-static constexpr double kFloorFactor = 1.0;
-static constexpr double kEps = 2.220446049250313e-16;
+using gnh::kEps;
+using gnh::kFloorFactor;
+using gnh::absmv_norm2;
 
 // CG-Lanczos tridiagonal of the first kit steps: T_ii = 1/a_i + b_{i-1}/a_{i-1},
 // T_{i,i+1} = sqrt(b_i)/a_i; returns its extreme eigenvalue ratio
-static double cond_from_hist(const double* hist, int kit) {
+double gnh::cond_from_hist(const double* hist, int kit) {
   if (kit <= 0) return 1.0;
   std::vector<double> d(kit), e(std::max(kit - 1, 0));
   for (int i = 0; i < kit; ++i) {
@@ -961,8 +1003,10 @@ static double cond_from_hist(const double* hist, int kit) {
   return lo > 0 ? hi / lo : INFINITY;
 }
 
+using gnh::cond_from_hist;
+
 // batched workspace for up to 16 columns, allocated on first use
-static void ensure_batch_workspace(gn_problem* p, gn_precond* pc, int maxit, hipStream_t s) {
+void gnh::ensure_batch_workspace(gn_problem* p, gn_precond* pc, int maxit, hipStream_t s) {
   const int KC = gnk::mc_width();
   const int64_t n = p->n_dof;
   if (!p->d_Xm) {
@@ -1000,137 +1044,6 @@ static void ensure_batch_precond(gn_precond* pc, hipStream_t s) {
   for (double* v : {pc->d_gm, pc->d_um, pc->d_ym}) GN_HIP(hipMemsetAsync(v, 0, sizeof(double) * nh, s));
 }
 
-// k <= 16 columns of one batch: each column runs its own CG recurrence, the
-// launches are shared.  Same steps, stopping test and restart policy as the
-// single-column path in gn_solve.
-static gn_status solve_batch(gn_problem* p, gn_precond* pc, const double* b_dev, double* x_dev, int c0,
-                             int k, int64_t ld, const gn_solve_opts* opts, hipStream_t s,
-                             gn_solve_report* reports) {
-  ensure_batch_workspace(p, pc, opts->maxit, s);
-  const int64_t n = p->n_dof;
-  const int chunk = opts->check_every > 0 ? opts->check_every : 8;
-  const int ps = p->pstride_m, hs_ = p->histm_stride;
-  const int nbs = gnk::spmv_blocks(p), nbr = gnk::reduce_blocks(), nbp = gnk::prolong_blocks(p);
-  double *X = p->d_Xm, *R = p->d_Rm, *P = p->d_Pm, *Q = p->d_Qm, *Zv = p->d_Zm;
-  double* part = p->d_partm;
-  double* scal = p->d_scalm;
-  double* hist = p->d_histm;
-  const double tstart = now_s();
-  for (int c = 0; c < k; ++c) gnk::scatter_free(p, b_dev + (c0 + c) * ld, R + c * n, s);
-  GN_HIP(hipMemsetAsync(X, 0, sizeof(double) * n * k, s));
-  std::vector<double> hsc((size_t)k * S_N, 0.0);
-  for (int c = 0; c < k; ++c) hsc[(size_t)c * S_N + S_MAXIT] = (double)opts->maxit;
-  GN_HIP(hipMemcpyAsync(scal, hsc.data(), sizeof(double) * k * S_N, hipMemcpyHostToDevice, s));
-  auto apply_m = [&](int op) {   // z = M^-1 r for the live columns, then the r.z recurrence step
-    if (pc) {
-      gnk::precond_mc(p, pc, R, Zv, k, part, ps, scal, pc->d_tm, pc->d_gm, pc->d_um, pc->d_ym, s);
-      gnk::finalize_mc(part, ps, nbp, op, k, scal, hist, hs_, opts->rtol, s);
-    } else {
-      gnk::copy_mc(n, k, Zv, R, scal, s);
-      gnk::dot_mc(n, k, R, Zv, part, ps, scal, s);
-      gnk::finalize_mc(part, ps, nbr, op, k, scal, hist, hs_, opts->rtol, s);
-    }
-  };
-  gnk::dot_mc(n, k, R, R, part, ps, nullptr, s);
-  gnk::finalize_mc(part, ps, nbr, OP_BB, k, scal, hist, hs_, opts->rtol, s);
-  apply_m(OP_RZ0);
-  gnk::copy_mc(n, k, P, Zv, scal, s);
-  auto read_scal = [&]() {
-    GN_HIP(hipMemcpyAsync(hsc.data(), scal, sizeof(double) * k * S_N, hipMemcpyDeviceToHost, s));
-    GN_HIP(hipStreamSynchronize(s));
-  };
-  auto iterate = [&]() {
-    for (;;) {
-      for (int it = 0; it < chunk; ++it) {
-        gnk::spmv_mc(p, P, Q, k, part, ps, scal, s);
-        gnk::finalize_mc(part, ps, nbs, OP_ALPHA, k, scal, hist, hs_, opts->rtol, s);
-        gnk::update_xr_mc(n, k, X, R, P, Q, scal, part, ps, s);
-        gnk::finalize_mc(part, ps, nbr, OP_RR, k, scal, hist, hs_, opts->rtol, s);
-        apply_m(OP_BETA);
-        gnk::update_p_mc(n, k, P, Zv, scal, s);
-      }
-      read_scal();
-      bool fin = true;
-      for (int c = 0; c < k; ++c) fin &= hsc[(size_t)c * S_N + S_DONE] != 0.0;
-      if (fin) return;
-    }
-  };
-  // ||b_c - A x_c||^2 per column; leaves A x in Q and b (full numbering) in Zv
-  std::vector<double> hpart((size_t)ps * k);
-  std::vector<double> tr(k, 0.0), floor2(k, 0.0);
-  auto true_residual = [&]() {
-    for (int c = 0; c < k; ++c) floor2[c] = kEps * kEps * absmv_norm2(p, X + c * n, s);
-    gnk::spmv_mc(p, X, Q, k, nullptr, ps, nullptr, s);
-    for (int c = 0; c < k; ++c) gnk::scatter_free(p, b_dev + (c0 + c) * ld, Zv + c * n, s);
-    gnk::sub_mc(n, k, Zv, Q, nullptr, part, ps, s);
-    GN_HIP(hipMemcpyAsync(hpart.data(), part, sizeof(double) * ps * k, hipMemcpyDeviceToHost, s));
-    GN_HIP(hipStreamSynchronize(s));
-    for (int c = 0; c < k; ++c) {
-      double t = 0.0;
-      for (int i = 0; i < nbr; ++i) t += hpart[(size_t)c * ps + i];
-      tr[c] = t;
-    }
-  };
-  iterate();
-  std::vector<double> fin_hs(hsc);       // per-column scalars at the end of its last sequence
-  std::vector<int> first_iters(k), restarts(k, 0);
-  for (int c = 0; c < k; ++c) first_iters[c] = (int)hsc[(size_t)c * S_N + S_ITER];
-  std::vector<double> hhist((size_t)hs_ * k);
-  GN_HIP(hipMemcpyAsync(hhist.data(), hist, sizeof(double) * hs_ * k, hipMemcpyDeviceToHost, s));
-  true_residual();
-  for (int pass = 0; pass < 2; ++pass) {
-    std::vector<char> again(k, 0);
-    bool any = false;
-    for (int c = 0; c < k; ++c) {
-      const double* h = &fin_hs[(size_t)c * S_N];
-      again[c] = h[S_BREAK] == 0.0 && h[S_BB] > 0.0 && tr[c] > h[S_TOL2] &&
-                 tr[c] > kFloorFactor * kFloorFactor * floor2[c] && (int)h[S_ITER] < opts->maxit;
-      any |= again[c] != 0;
-    }
-    if (!any) break;
-    // columns that do not restart are stopped through their iteration limit
-    read_scal();
-    for (int c = 0; c < k; ++c)
-      if (!again[c]) hsc[(size_t)c * S_N + S_MAXIT] = hsc[(size_t)c * S_N + S_ITER];
-    GN_HIP(hipMemcpyAsync(scal, hsc.data(), sizeof(double) * k * S_N, hipMemcpyHostToDevice, s));
-    gnk::sub_mc(n, k, Zv, Q, R, part, ps, s);   // r = b - A x
-    gnk::finalize_mc(part, ps, nbr, OP_RESTART, k, scal, hist, hs_, opts->rtol, s);
-    apply_m(OP_RZ0);
-    gnk::copy_mc(n, k, P, Zv, scal, s);
-    iterate();
-    for (int c = 0; c < k; ++c)
-      if (again[c]) {
-        std::copy(&hsc[(size_t)c * S_N], &hsc[(size_t)c * S_N] + S_N, &fin_hs[(size_t)c * S_N]);
-        ++restarts[c];
-      }
-    true_residual();
-  }
-  const double tsolve = now_s() - tstart;
-  for (int c = 0; c < k; ++c) gnk::gather_free(p, X + c * n, x_dev + (c0 + c) * ld, s);
-  GN_HIP(hipStreamSynchronize(s));
-  gn_status ret = GN_OK;
-  for (int c = 0; c < k; ++c) {
-    const double* h = &fin_hs[(size_t)c * S_N];
-    const double bb = h[S_BB], rr = h[S_RR];
-    const bool conv = bb == 0.0 || rr <= h[S_TOL2];
-    if (h[S_BREAK] != 0.0) ret = GN_ERR_BREAKDOWN;
-    else if (!conv && ret == GN_OK) ret = GN_WARN_MAXIT;
-    if (reports) {
-      gn_solve_report& Rp = reports[c0 + c];
-      Rp.iters = (int)h[S_ITER];
-      Rp.converged = conv ? 1 : 0;
-      Rp.rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
-      Rp.true_rel_res = bb > 0 ? std::sqrt(tr[c] / bb) : 0.0;
-      Rp.res_floor = bb > 0 ? std::sqrt(floor2[c] / bb) : 0.0;
-      Rp.t_solve_s = tsolve;
-      Rp.iters_first = first_iters[c];
-      Rp.restarts = restarts[c];
-      Rp.cond_est = cond_from_hist(&hhist[(size_t)c * hs_], first_iters[c]);
-    }
-  }
-  return ret;
-}
-
 extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev, double* x_dev,
                               int32_t nrhs, int64_t ld, const gn_solve_opts* opts, void* stream,
                               gn_solve_report* reports) {
@@ -1154,12 +1067,32 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
   const double* done = scal + S_DONE;
   gn_status ret = GN_OK;
   if (nrhs > 1 && !opts->sequential) {
-    const int KC = gnk::mc_width();
-    for (int c0 = 0; c0 < nrhs; c0 += KC) {
-      gn_status st = solve_batch(p, pc, b_dev, x_dev, c0, std::min(KC, nrhs - c0), ld, opts, s, reports);
-      if (st < 0 && ret >= 0) ret = st;
-      else if (st > 0 && ret == GN_OK) ret = st;
+    // up to 16 columns share every launch; a finished column's slot takes the
+    // next column at the following chunk boundary
+    const double tstart = now_s();
+    SlotEngine eng(p, pc, std::min(gnk::mc_width(), (int)nrhs), chunk, opts->maxit, s);
+    std::vector<SlotResult> res;
+    int next = 0;
+    while (next < nrhs || eng.busy()) {
+      while (next < nrhs && eng.free_slots() > 0) {
+        SlotColumn c;
+        c.b = b_dev + next * ld;
+        c.x = x_dev + next * ld;
+        c.rtol = opts->rtol;
+        c.maxit = opts->maxit;
+        c.index = next++;
+        eng.admit(c);
+      }
+      res.clear();
+      eng.step(res);
+      for (const SlotResult& r : res) {
+        if (reports) reports[r.col.index] = r.rep;
+        if (r.st < 0 && ret >= 0) ret = r.st;
+        else if (r.st > 0 && ret == GN_OK) ret = r.st;
+      }
     }
+    if (reports)
+      for (int c = 0; c < nrhs; ++c) reports[c].t_solve_s = now_s() - tstart;
     return ret;
   }
   const int nbs = gnk::spmv_blocks(p), nbr = gnk::reduce_blocks(), nbp = gnk::prolong_blocks(p);
@@ -1201,7 +1134,7 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
           }
           gnk::update_p(n, p->d_p, p->d_z, scal, s);
         }
-        GN_HIP(hipMemcpyAsync(hs, scal, sizeof(double) * 11, hipMemcpyDeviceToHost, s));
+        GN_HIP(hipMemcpyAsync(hs, scal, sizeof(double) * S_N, hipMemcpyDeviceToHost, s));
         GN_HIP(hipStreamSynchronize(s));
         iters = (int)hs[S_ITER];
         fin = hs[S_DONE] != 0.0;

@@ -399,15 +399,16 @@ void assemble_matrix(gn_problem* p, hipStream_t s) {
   GN_CHECK_LAUNCH();
 }
 
-void assemble_load(gn_problem* p, const double* d_body, const double* d_trac, hipStream_t s) {
+void assemble_load(const gn_problem* p, const double* d_body, const double* d_trac, int nrhs, double* d_out,
+                   hipStream_t s) {
   Geo g = make_geo(p);
   dim3 grid((unsigned)((p->n_node + 127) / 128));
   if (p->nc == 3)
     hipLaunchKernelGGL(k_load<3>, grid, dim3(128), 0, s, g, p->ne[0], p->ne[1], p->ne[2],
-                       p->nrhs, d_body, d_trac, p->d_dir, p->d_b);
+                       nrhs, d_body, d_trac, p->d_dir, d_out);
   else
     hipLaunchKernelGGL(k_load<1>, grid, dim3(128), 0, s, g, p->ne[0], p->ne[1], p->ne[2],
-                       p->nrhs, d_body, d_trac, p->d_dir, p->d_b);
+                       nrhs, d_body, d_trac, p->d_dir, d_out);
   GN_CHECK_LAUNCH();
 }
 

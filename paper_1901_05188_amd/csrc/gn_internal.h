@@ -32,8 +32,9 @@ void gn_set_error(gn_status code, const std::string& msg);
 
 #define GN_CHECK_LAUNCH() GN_HIP(hipGetLastError())
 
-// device-resident CG scalars and the recurrence steps of the single-block finalize kernel
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITER, S_MAXIT, S_BREAK, S_N };
+// device-resident CG scalars and the recurrence steps of the single-block finalize kernel;
+// S_RTOL is the relative tolerance of a batched column (0: the launch argument)
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITER, S_MAXIT, S_BREAK, S_RTOL, S_N };
 enum { OP_BB = 0, OP_RZ0, OP_ALPHA, OP_RR, OP_BETA, OP_RESTART };
 
 // ---------------------------------------------------------------------------
@@ -157,7 +158,8 @@ void element_matrices(gn_problem* p, const double* d_mats, int n_mat, const int*
                       const double* d_eang, const double* d_etilt, const double* d_ek,
                       hipStream_t s);
 void assemble_matrix(gn_problem* p, hipStream_t s);
-void assemble_load(gn_problem* p, const double* d_body, const double* d_trac, hipStream_t s);
+void assemble_load(const gn_problem* p, const double* d_body, const double* d_trac, int nrhs, double* d_out,
+                   hipStream_t s);
 // linalg.hip
 void spmv_flag(const gn_problem* p, const double* x, double* y, double* part, const double* done,
                hipStream_t s);
@@ -201,7 +203,7 @@ void update_xr_mc(int64_t n, int k, double* x, double* r, const double* p, const
 void update_p_mc(int64_t n, int k, double* p, const double* z, const double* scal, hipStream_t s);
 void copy_mc(int64_t n, int k, double* dst, const double* src, const double* scal, hipStream_t s);
 void sub_mc(int64_t n, int k, const double* b, const double* q, double* r, double* part, int pstride,
-            hipStream_t s);
+            const double* scal, hipStream_t s);
 void finalize_mc(const double* part, int pstride, int nb, int op, int k, double* scal, double* hist,
                  int hstride, double rtol, hipStream_t s);
 int mc_band_lds_bytes(int maxw);
@@ -235,6 +237,67 @@ void make_pair(void* dst, int j1, int j2, const int lo[3], const int hi[3]);
 void dense_chol(int NB, double* A, double* Dinv, int* info, hipStream_t s);
 void tri_inv(int NB, const double* L, const double* Dinv, double* Z, hipStream_t s);
 }  // namespace gnk
+
+// ---------------------------------------------------------------------------
+// host helpers of the solve paths (api.hip)
+// ---------------------------------------------------------------------------
+namespace gnh {
+constexpr double kEps = 2.220446049250313e-16;
+// restarts stop once b - A x is within this factor of eps || |A| |x| ||
+constexpr double kFloorFactor = 1.0;
+double now_s();
+double absmv_norm2(gn_problem* p, const double* x, hipStream_t s);
+double cond_from_hist(const double* hist, int kit);
+void ensure_batch_workspace(gn_problem* p, gn_precond* pc, int maxit, hipStream_t s);
+int64_t resident_bytes(const std::vector<void*>& owned);
+}  // namespace gnh
+
+// ---------------------------------------------------------------------------
+// slot engine of the batched solves (serve.hip): up to 16 right-hand sides of
+// one operator share every launch; a slot whose column has finished takes the
+// next queued column at the following chunk boundary
+// ---------------------------------------------------------------------------
+struct SlotColumn {
+  const double* b = nullptr;   // right-hand side, free numbering (device)
+  double* x = nullptr;         // solution column, free numbering (device)
+  double rtol = 1e-8;
+  int maxit = 1000;
+  void* tag = nullptr;         // owner, handed back with the result
+  int index = 0;               // column index within the owner
+};
+struct SlotResult {
+  SlotColumn col;
+  gn_solve_report rep;
+  gn_status st;
+};
+class SlotEngine {
+ public:
+  SlotEngine(gn_problem* p, gn_precond* pc, int slots, int chunk, int maxit_cap, hipStream_t s);
+  int slots() const { return k_; }
+  int free_slots() const;
+  bool busy() const;
+  void admit(const SlotColumn& c);                 // needs free_slots() > 0
+  void step(std::vector<SlotResult>& out);         // start admitted columns, one chunk, retire
+ private:
+  struct Slot {
+    bool used = false, fresh = false;
+    SlotColumn col;
+    int restarts = 0, first_iters = -1;
+    double t0 = 0.0;
+    std::vector<double> fin;                       // scalars at the end of the last CG sequence
+  };
+  void apply_m(int op);
+  void read_scal();
+  void write_rows(const std::vector<int>& cols);
+  void phase_begin(const std::vector<int>& cols, std::vector<int>& held);
+  void phase_end(const std::vector<int>& held);
+  gn_problem* p_;
+  gn_precond* pc_;
+  int k_, chunk_, maxit_cap_;
+  hipStream_t s_;
+  std::vector<Slot> slot_;
+  std::vector<double> hsc_;                        // host mirror of the per-column scalars
+};
 
 // profiling of kernel groups (api.hip)
 struct GnProfScope {

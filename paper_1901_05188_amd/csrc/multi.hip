@@ -181,9 +181,11 @@ __global__ __launch_bounds__(RTHR) void k_copy_mc(int64_t n, double* __restrict_
 // r_c = b_c - q_c with the partial r.r (restart from the true residual); with
 // r == nullptr only the partial ||b - q||^2
 __global__ __launch_bounds__(RTHR) void k_sub_mc(int64_t n, const double* __restrict__ b, const double* __restrict__ q,
-                                                 double* __restrict__ r, double* __restrict__ part, int pstride) {
+                                                 double* __restrict__ r, double* __restrict__ part, int pstride,
+                                                 const double* __restrict__ scal) {
   __shared__ double sh[16];
   const int c = blockIdx.y;
+  if (scal && !col_live(scal, c)) return;
   const int64_t o = (int64_t)c * n;
   double v = 0.0;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
@@ -196,7 +198,9 @@ __global__ __launch_bounds__(RTHR) void k_sub_mc(int64_t n, const double* __rest
 }
 
 // one block per column: fixed-order sum of the partials, then the recurrence of
-// that column (same steps as the single-column finalize)
+// that column (same steps as the single-column finalize).  Only live columns
+// take a step: a column is started (OP_BB) or restarted (OP_RESTART) by
+// clearing its done flag while the others are held with theirs set.
 __global__ void k_finalize_mc(const double* __restrict__ part, int pstride, int nb, int op,
                               double* __restrict__ scal_all, double* __restrict__ hist_all, int hstride,
                               double rtol) {
@@ -204,16 +208,17 @@ __global__ void k_finalize_mc(const double* __restrict__ part, int pstride, int 
   const int c = blockIdx.x;
   double* scal = scal_all + c * S_N;
   double* hist = hist_all + (int64_t)c * hstride;
-  if (op != OP_BB && op != OP_RESTART && scal[S_DONE] != 0.0) return;
+  if (scal[S_DONE] != 0.0) return;
   const double* pc = part + (int64_t)c * pstride;
   double v = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) v += pc[i];
   double s = block_sum(v, sh);
   if (threadIdx.x != 0) return;
   if (op == OP_BB) {
+    const double rt = scal[S_RTOL] > 0.0 ? scal[S_RTOL] : rtol;
     scal[S_BB] = s;
     scal[S_RR] = s;
-    scal[S_TOL2] = rtol * rtol * s;
+    scal[S_TOL2] = rt * rt * s;
     scal[S_DONE] = (s == 0.0) ? 1.0 : 0.0;
     scal[S_ITER] = 0.0;
     scal[S_BREAK] = 0.0;
@@ -642,8 +647,8 @@ void copy_mc(int64_t n, int k, double* dst, const double* src, const double* sca
 }
 
 void sub_mc(int64_t n, int k, const double* b, const double* q, double* r, double* part, int pstride,
-            hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_mc, dim3(RBLK, k), dim3(RTHR), 0, s, n, b, q, r, part, pstride);
+            const double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_mc, dim3(RBLK, k), dim3(RTHR), 0, s, n, b, q, r, part, pstride, scal);
   GN_CHECK_LAUNCH();
 }
 

@@ -330,6 +330,72 @@ def config_c3(seed: int = 3) -> Workload:
                           meta=dict(angles=[float(a) for a in angles]))
 
 
+def _c4_operator(size_dofs: float, n_ply: int, rng: np.random.Generator, h: float = 0.5,
+                 aspect: float = 5.0, target_nj: float = 5000.0, name: str = "c4") -> Workload:
+    """One laminate of the serving catalogue: c3's element rule (3 elements
+    per ply, 1 per resin interlayer) at in-plane size h, in-plane aspect
+    `aspect`:1, about `size_dofs` DOFs, near-cubic subdomains of about
+    `target_nj` local DOFs, overlap 1, 12 eigenvectors; clamped at x = 0 and
+    loaded only by the tractions of each request (no body force)."""
+    nz = 4 * n_ply - 1
+    ny = max(2, int(round(math.sqrt(size_dofs / (3.0 * (nz + 1) * aspect)))) - 1)
+    nx = max(2, int(round(aspect * (ny + 1))) - 1)
+    layers, angles = _random_layup(n_ply, rng, 3, nz)
+    ne = (nx, ny, nz)
+    n_sub = max(1.0, size_dofs / target_nj)
+    side = (nx * ny * nz / n_sub) ** (1.0 / 3.0)
+    nparts = tuple(max(1, min(ne[a] // 3, int(round(ne[a] / side)))) for a in range(3))
+    return laminate_plate((nx, ny), (nx * h, ny * h), layers, nparts=nparts, overlap=1, nev=12,
+                          body=None, name=name, meta=dict(angles=[float(a) for a in angles]))
+
+
+def config_c4_catalogue(seed: int = 4, sizes=(0.2e6, 0.5e6, 1.0e6, 2.0e6), layups: int = 4,
+                        ply_range=(8, 24)) -> List[Workload]:
+    """Serving catalogue: len(sizes) x `layups` laminate operators, 8-24 random
+    plies each (angles iid from {0, 90, 45, -45})."""
+    rng = np.random.default_rng(seed)
+    cat = []
+    for si, S in enumerate(sizes):
+        for li in range(layups):
+            n_ply = int(rng.integers(ply_range[0], ply_range[1] + 1))
+            cat.append(_c4_operator(S, n_ply, rng, name=f"c4_op{si}{li}_{int(S / 1e3)}k_{n_ply}ply"))
+    return cat
+
+
+def patch_tractions(w: Workload, k: int, rng: np.random.Generator, sigma: float = 0.01,
+                    side=(0.1, 0.5)) -> np.ndarray:
+    """k load cases: each a uniform traction, components ~ N(0, sigma) MPa, on
+    an axis-aligned patch of the top face whose sides are U(side) x the face's
+    length along that axis.  Layout [rhs][face = ex + nx * ey][comp]."""
+    nx, ny = w.ne[0], w.ne[1]
+    xc = 0.5 * (w.xn[0][:-1] + w.xn[0][1:])
+    yc = 0.5 * (w.xn[1][:-1] + w.xn[1][1:])
+    Lx, Ly = w.xn[0][-1] - w.xn[0][0], w.xn[1][-1] - w.xn[1][0]
+    out = np.zeros((k, ny, nx, 3))
+    for r in range(k):
+        ax, ay = rng.uniform(*side) * Lx, rng.uniform(*side) * Ly
+        x0 = w.xn[0][0] + rng.uniform(0.0, Lx - ax)
+        y0 = w.xn[1][0] + rng.uniform(0.0, Ly - ay)
+        g = rng.normal(0.0, sigma, size=3)
+        mx = (xc >= x0) & (xc <= x0 + ax)
+        my = (yc >= y0) & (yc <= y0 + ay)
+        out[r][np.ix_(my, mx)] = g
+    return out.reshape(-1)
+
+
+def c4_requests(n_ops: int, n_req: int = 1000, rate: float = 20.0, max_rhs: int = 16,
+                seed: int = 4) -> List[dict]:
+    """Poisson arrivals (mean `rate` per second): arrival time, operator index
+    (uniform) and number of right-hand sides U{1..max_rhs}; each request's
+    tractions come from patch_tractions with the generator seeded by
+    (seed, request index)."""
+    rng = np.random.default_rng([seed, 1])
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    ops = rng.integers(0, n_ops, size=n_req)
+    ks = rng.integers(1, max_rhs + 1, size=n_req)
+    return [dict(t=float(t[i]), op=int(ops[i]), k=int(ks[i]), seed=(seed, 2, i)) for i in range(n_req)]
+
+
 def config_c5() -> Workload:
     """384x72x71 ramped laminate, 24 plies x 2 elements + 23 resin, resin
     contrast 1e3, top pressure 0.01 MPa, 32x12x4 subdomains."""
