@@ -135,6 +135,89 @@ def measured_traffic():
         return None
 
 
+def serving_leg(gp, n_req, rate, rtol, dev):
+    """Serving stream: the 16-operator laminate catalogue (4 sizes 0.2-2M DOFs x
+    4 random layups, FP32 local factors inside FP64 PCG) resident on the GPU,
+    the first n_req requests of the Poisson stream (1-16 patch-traction load
+    cases each) submitted at their arrival times to the request server;
+    latency is submit to completion of the request's last column."""
+    import numpy as np
+    import torch
+    from workloads import generate as gen
+    cat = gen.config_c4_catalogue()
+    t0 = time.perf_counter()
+    ops = []
+    for w in cat:
+        prob = gp.Problem.from_workload(w)
+        pc = gp.Preconditioner.from_workload(prob, w, local_prec=32)
+        ops.append((w, prob, pc))
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    srv = gp.Server(maxit_cap=5000)
+    ids = [srv.add(p, pc) for (_, p, pc) in ops]
+    resident = sum(gp.footprint(p, pc) for (_, p, pc) in ops)
+    log(f"serving: catalogue of {len(ops)} operators built in {t_build:.1f}s, {resident / 1e9:.1f} GB resident")
+    reqs = gen.c4_requests(len(ops), n_req=n_req, rate=rate)
+    loads = []
+    for r in reqs:
+        w, p, _ = ops[r["op"]]
+        b = torch.zeros((r["k"], p.n_free), dtype=torch.float64, device=dev)
+        p.load_vectors(b, traction=gen.patch_tractions(w, r["k"], np.random.default_rng(r["seed"])))
+        loads.append((b, torch.zeros_like(b)))
+    torch.cuda.synchronize()
+    tickets = []
+    tstart = time.perf_counter()
+    for i, r in enumerate(reqs):
+        dt = tstart + r["t"] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        b, x = loads[i]
+        tickets.append(srv.submit(ids[r["op"]], ops[r["op"]][1].n_free, b, x, rtol=rtol, maxit=5000))
+    lat, iters, worst, conv, dofcols = [], [], 0.0, True, 0
+    for i, t in enumerate(tickets):
+        st, rep, l = srv.wait(t)
+        lat.append(l)
+        iters += [c["iters"] for c in rep]
+        worst = max(worst, max(c["true_rel_res"] for c in rep))
+        conv &= st == 0 and all(c["converged"] == 1 for c in rep)
+        dofcols += len(rep) * ops[reqs[i]["op"]][1].n_free
+    wall = time.perf_counter() - tstart
+    # one request again, alone on an idle server: the same bits as in the mix
+    i0 = max(range(len(reqs)), key=lambda i: reqs[i]["k"])
+    b0, x0 = loads[i0]
+    xa = torch.zeros_like(x0)
+    torch.cuda.synchronize()
+    srv.wait(srv.submit(ids[reqs[i0]["op"]], ops[reqs[i0]["op"]][1].n_free, b0, xa, rtol=rtol, maxit=5000))
+    same = bool(torch.equal(xa, x0))
+    srv.close()
+    # its error against FP64 local factors on the same operator
+    w, p, _ = ops[reqs[i0]["op"]]
+    pc64 = gp.Preconditioner.from_workload(p, w, local_prec=64)
+    x64 = torch.zeros_like(x0)
+    gp.solve(p, pc64, b0, x64, rtol=rtol, maxit=5000)
+    err64 = float(torch.max(torch.linalg.norm(x0 - x64, dim=1) / torch.linalg.norm(x64, dim=1)))
+    pc64.close()
+    for (_, p, pc) in ops:
+        pc.close()
+        p.close()
+    lat_s = sorted(lat)
+    q = lambda f: lat_s[min(len(lat_s) - 1, int(round(f * (len(lat_s) - 1))))]
+    out = {"workload": "laminate catalogue 16 operators (0.2/0.5/1/2 M DOFs x 4 layups), FP32 local factors, "
+                       "Poisson arrivals, 1-16 patch tractions per request",
+           "requests": len(reqs), "columns": len(iters), "arrival_rate_per_s": rate,
+           "arrival_span_s": reqs[-1]["t"], "wall_s": wall,
+           "requests_per_s": len(reqs) / wall, "dof_rhs_per_s": dofcols / wall,
+           "latency_ms": {"p50": 1000 * q(0.5), "p99": 1000 * q(0.99)},
+           "pcg_iters": {"mean": float(np.mean(iters)), "max": int(max(iters))},
+           "all_converged": bool(conv), "max_true_rel_res": worst,
+           "alone_equals_mix_bitwise": same, "rel_err_vs_fp64_local": err64,
+           "catalogue_build_s": t_build, "resident_GB": resident / 1e9}
+    log(f"serving: {len(reqs)} requests ({len(iters)} columns) in {wall:.1f}s, p50 {out['latency_ms']['p50']:.0f} ms "
+        f"p99 {out['latency_ms']['p99']:.0f} ms, {out['dof_rhs_per_s']:.3e} DOF-RHS/s, alone==mix {same}, "
+        f"err vs FP64 {err64:.1e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +231,9 @@ def main():
     ap.add_argument("--solve-reps", type=int, default=5, help="warm solves per step for latency")
     ap.add_argument("--multi-rhs", type=int, default=16,
                     help="columns of the batched multi-RHS leg (0 = skip)")
+    ap.add_argument("--serve", type=int, default=60,
+                    help="requests of the serving stream to replay (0 skips the serving leg)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="end with a device-to-device copy of this many GiB (a reference "
                          "kernel of known traffic for hardware-counter runs)")
@@ -315,6 +401,8 @@ def main():
         k = min(len(v) - 1, max(0, int(round(q * (len(v) - 1)))))
         return v[k]
 
+    serving = serving_leg(gp, args.serve, args.serve_rate, args.rtol, dev) if args.serve > 0 else None
+
     res = {
         "metric": "solved DOFs/s + PCG iters to 1e-8 rel. residual; p50/p99 solve latency",
         "value": n_dof / (t_total / args.steps),
@@ -347,6 +435,8 @@ def main():
         res["mixed_precision"] = mixed
     if multi is not None:
         res["multi_rhs"] = multi
+    if serving is not None:
+        res["serving"] = serving
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline()

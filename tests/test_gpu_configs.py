@@ -7,6 +7,8 @@ oracle computes sampled rows of A and b one by one, and the GPU solution is
 checked through those rows (sampled residuals), plus properties that hold at
 any size (symmetry of M^-1, true residual, deterministic replay).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -239,3 +241,86 @@ def test_c5_largest_single_solve():
     assert r["true_rel_res"] <= max(1e-8, 4 * r["res_floor"])
     pc.close()
     prob.close()
+
+
+def test_c4_serving_catalogue_sample():
+    """Serving catalogue, one operator of each size (0.2/0.5/1/2 M DOFs), FP32
+    local factors inside FP64 PCG, resident together on one request server.
+    Twelve requests of the Poisson stream (1-16 patch-traction load cases each)
+    are submitted at once: every column reaches 1e-8 (or the FP64 rounding
+    floor); sampled rows of a request's load vector against the oracle, and the
+    oracle rows' residuals b_i - A_i x of its solution; two requests solved
+    again alone give the same bits; one request against FP64 local factors
+    (mixed-precision gate 1e-7)."""
+    gp = _gp()
+    cat = gen.config_c4_catalogue()
+    pick = [0, 4, 8, 12]
+    ops = []
+    for i in pick:
+        w = cat[i]
+        print(f"[gpu] c4 {w.name} n_free={w.n_free} subdomains={w.n_sub}", flush=True)
+        prob = gp.Problem.from_workload(w)
+        pc = gp.Preconditioner.from_workload(prob, w, local_prec=32)
+        ops.append((w, prob, pc))
+    stream = [r for r in gen.c4_requests(16, n_req=200) if r["op"] in pick][:12]
+    srv = gp.Server(maxit_cap=3000)
+    try:
+        ids = [srv.add(p, pc) for (_, p, pc) in ops]
+        loads = []
+        for r in stream:
+            w, p, _ = ops[pick.index(r["op"])]
+            b = torch.zeros((r["k"], p.n_free), dtype=torch.float64, device=DEV)
+            p.load_vectors(b, traction=gen.patch_tractions(w, r["k"], np.random.default_rng(r["seed"])))
+            loads.append((b, torch.zeros_like(b)))
+        torch.cuda.synchronize()
+        tickets = [srv.submit(ids[pick.index(r["op"])], ops[pick.index(r["op"])][1].n_free, b, x,
+                              rtol=1e-8, maxit=3000) for r, (b, x) in zip(stream, loads)]
+        reps = []
+        for t in tickets:
+            st, rep, lat = srv.wait(t)
+            assert st == 0
+            for c in rep:
+                assert c["converged"] == 1
+                assert c["true_rel_res"] <= max(1e-8, 4 * c["res_floor"])
+            reps.append(rep)
+            print(f"[gpu] c4 request: k={len(rep)} latency {lat * 1e3:.0f} ms iters "
+                  f"{min(c['iters'] for c in rep)}-{max(c['iters'] for c in rep)}", flush=True)
+        for i in (0, len(stream) - 1):
+            b, x = loads[i]
+            xa = torch.zeros_like(x)
+            torch.cuda.synchronize()
+            st, rep, lat = srv.wait(srv.submit(ids[pick.index(stream[i]["op"])], b.shape[1], b, xa,
+                                               rtol=1e-8, maxit=3000))
+            assert torch.equal(xa, x)
+    finally:
+        srv.close()
+    # oracle rows of the smallest operator's first request (first load case)
+    i0 = next(i for i, r in enumerate(stream) if r["op"] == pick[0])
+    w, p, _ = ops[0]
+    trac = gen.patch_tractions(w, stream[i0]["k"], np.random.default_rng(stream[i0]["seed"]))
+    w1 = dataclasses.replace(w, traction=trac[: w.ne[0] * w.ne[1] * 3], nrhs=1)
+    rows = np.sort(np.random.default_rng(11).choice(w.n_free, size=24, replace=False))
+    sampled = fem.assemble_rows(w1, rows)
+    b, x = loads[i0]
+    bh, xh = b[0].cpu().numpy(), x[0].cpu().numpy()
+    nb = np.linalg.norm(bh)
+    bound = max(1e-8, 4 * reps[i0][0]["res_floor"]) * nb * 1.01
+    for r, (cols, vals, bv) in zip(rows, sampled):
+        assert abs(bh[r] - bv) <= 1e-13 * max(abs(bv), np.abs(bh).max())
+        assert abs(bv - vals @ xh[cols]) <= bound
+    # FP32 against FP64 local factors on the same operator, both run to 1e-11
+    pc_f32 = ops[0][2]
+    pc64 = gp.Preconditioner.from_workload(p, w, local_prec=64)
+    xs = [torch.zeros_like(b[:1]) for _ in range(2)]
+    for pcx, xx in zip((pc_f32, pc64), xs):
+        st, rep = gp.solve(p, pcx, b[:1], xx, rtol=1e-11, maxit=3000)
+        assert rep[0]["converged"] == 1
+    err = float(torch.linalg.norm(xs[0] - xs[1]) / torch.linalg.norm(xs[1]))
+    served = float(torch.linalg.norm(x[:1] - xs[1]) / torch.linalg.norm(xs[1]))
+    print(f"[gpu] c4 FP32-local vs FP64-local solution: {err:.2e}; served (1e-8) vs FP64: {served:.2e}",
+          flush=True)
+    assert err <= 1e-7
+    pc64.close()
+    for (_, p, pc) in ops:
+        pc.close()
+        p.close()
