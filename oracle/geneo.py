@@ -26,6 +26,16 @@ absolute) so that a degenerate cluster is never split; each eigenvector is
 scaled to unit 2-norm with its largest-magnitude entry positive (lowest index
 on ties).
 
+The zero-energy-mode (ZEM) coarse space the paper compares against (Section 5,
+Example 1b: no coarse space, only the zero energy modes, or GenEO) takes on
+each subdomain the kernel of its Neumann matrix A_{Omega_j}: the constant
+(scalar diffusion) or the six rigid-body translations and rotations
+(elasticity).  Reading: only floating subdomains, whose elements touch no
+Dirichlet DOF, contribute (a subdomain meeting a clamped face has no kernel);
+this is also what the coarse dimensions of the paper's Example 1b table
+count (six per subdomain off the clamped end).  Its basis is X_j z_k like the
+GenEO one.
+
 Pins (tests/test_oracle_geneo.py): eigen residual ||A_N p - lambda B p||,
 B-orthogonality, exactly 6 (elasticity) / 1 (scalar) zero eigenvalues on
 floating subdomains and none on clamped ones, independence of the shift, a
@@ -37,6 +47,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
+from . import fem
 from .dd import Decomposition
 from .fem import elem_dofs
 
@@ -101,6 +112,38 @@ def normalise(Pv: np.ndarray) -> np.ndarray:
     return Pv * sgn[None, :]
 
 
+def zem_basis(w, dec: Decomposition, j: int) -> np.ndarray:
+    """Zero-energy modes on Ibar_j (columns, unit 2-norm): the constant for the
+    scalar problem, the three translations and three infinitesimal rotations
+    u = theta x (x - c) about the box centre c for elasticity; an empty basis
+    when the subdomain's nodes carry a Dirichlet DOF."""
+    nc = w.ncomp
+    nodes = np.unique(dec.en[dec.E[j]].ravel())
+    dofs_all = (nodes[:, None] * nc + np.arange(nc)[None, :]).ravel()
+    Ib = dec.Ibar[j]
+    if np.any(w.dirichlet[dofs_all] != 0):
+        return np.zeros((len(Ib), 0))
+    full = w.free_index()[Ib]
+    node, comp = full // nc, full % nc
+    if nc == 1:
+        Z = np.ones((len(Ib), 1))
+    else:
+        X = fem.node_xyz(w)[node]
+        allx = fem.node_xyz(w)[nodes]
+        c = 0.5 * (allx.min(axis=0) + allx.max(axis=0))
+        d = X - c
+        Z = np.zeros((len(Ib), 6))
+        for a in range(3):
+            Z[:, a] = (comp == a)
+        # rotations about x, y, z: theta_a e_a x d
+        for a in range(3):
+            th = np.zeros(3)
+            th[a] = 1.0
+            u = np.cross(th[None, :], d)
+            Z[:, 3 + a] = u[np.arange(len(Ib)), comp]
+    return Z / np.linalg.norm(Z, axis=0, keepdims=True)
+
+
 def select_count(lam: np.ndarray, nev: int, threshold: float, nev_max: int) -> int:
     """m_j: fixed count, or #{lambda < threshold} capped; then cluster completion."""
     finite = int(np.sum(np.isfinite(lam)))
@@ -121,7 +164,9 @@ class GenEO:
     """Local factors, eigenpairs, coarse basis and coarse matrix."""
 
     def __init__(self, w, A, Ke, dec: Decomposition | None = None, shift: float = 1e-2,
-                 coarse: bool = True, keep_all: bool = False):
+                 coarse=True, keep_all: bool = False):
+        """coarse: True (or "geneo") for the GenEO coarse space, "zem" for the
+        zero-energy modes of floating subdomains, False for one level only."""
         self.w = w
         self.A = A
         self.dec = dec if dec is not None else Decomposition(w)
@@ -135,6 +180,11 @@ class GenEO:
             self.NH = 0
             return
         for j in range(d.n_sub):
+            if coarse == "zem":
+                Zj = zem_basis(w, d, j)
+                self.m.append(Zj.shape[1])
+                self.P.append(Zj)
+                continue
             AN, B = pencil(w, d, Ke, j)
             lam, Pv = pencil_eig(AN, B, shift)
             m = select_count(lam, w.nev, w.threshold, w.nev_max)
