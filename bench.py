@@ -218,6 +218,46 @@ def serving_leg(gp, n_req, rate, rtol, dev):
     return out
 
 
+def robustness_leg(gp, dev):
+    """The paper's Example 1b comparison (one-level AS, zero-energy modes,
+    GenEO) at a 1e-5 residual reduction: the Example 1 plate (30,240 DOFs)
+    split into N = 4, 8, 16, 32 subdomains, and a channelled diffusion box
+    (33,759 DOFs, 32 subdomains) with contrast 1 to 1e6.  Iterations,
+    CG-Lanczos kappa and coarse dimension per preconditioner."""
+    import torch
+    from workloads import generate as gen
+
+    def run(w):
+        prob = gp.Problem.from_workload(w)
+        b = torch.zeros((1, prob.n_free), dtype=torch.float64, device=dev)
+        prob.rhs(b)
+        row = {"n_free": prob.n_free, "subdomains": list(w.nparts)}
+        for name, coarse in (("AS", 0), ("ZEM", 2), ("GenEO", 1)):
+            pc = gp.Preconditioner.from_workload(prob, w, coarse=coarse)
+            x = torch.zeros_like(b)
+            _, rep = gp.solve(prob, pc, b, x, rtol=1e-5, maxit=5000)
+            row[name] = {"iters": rep[0]["iters_first"], "kappa": round(rep[0]["cond_est"], 1),
+                         "dim_VH": pc.report["coarse_dim"]}
+            pc.close()
+        prob.close()
+        return row
+
+    plate = {}
+    for N, parts in ((4, (2, 2, 1)), (8, (8, 1, 1)), (16, (8, 2, 1)), (32, (8, 4, 1))):
+        plate[str(N)] = run(gen.example1b_plate(parts))
+        r = plate[str(N)]
+        log(f"robustness plate N={N}: AS {r['AS']['iters']} it / kappa {r['AS']['kappa']}, "
+            f"ZEM {r['ZEM']['iters']} / {r['ZEM']['kappa']} / dim {r['ZEM']['dim_VH']}, "
+            f"GenEO {r['GenEO']['iters']} / {r['GenEO']['kappa']} / dim {r['GenEO']['dim_VH']}")
+    contrast = {}
+    for cst in (1.0, 1e2, 1e4, 1e6):
+        contrast[f"{cst:g}"] = run(gen.contrast_box(cst, (4, 4, 2)))
+        r = contrast[f"{cst:g}"]
+        log(f"robustness contrast {cst:g}: AS {r['AS']['iters']}, ZEM {r['ZEM']['iters']}, "
+            f"GenEO {r['GenEO']['iters']} (dim {r['GenEO']['dim_VH']})")
+    return {"rtol": 1e-5, "example1b_plate_by_N": plate, "diffusion_32_subdomains_by_contrast": contrast}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +273,8 @@ def main():
                     help="columns of the batched multi-RHS leg (0 = skip)")
     ap.add_argument("--serve", type=int, default=60,
                     help="requests of the serving stream to replay (0 skips the serving leg)")
+    ap.add_argument("--no-robustness", action="store_true",
+                    help="skip the AS / ZEM / GenEO comparison over subdomain counts and contrasts")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="end with a device-to-device copy of this many GiB (a reference "
@@ -402,6 +444,7 @@ def main():
         return v[k]
 
     serving = serving_leg(gp, args.serve, args.serve_rate, args.rtol, dev) if args.serve > 0 else None
+    robust = None if args.no_robustness else robustness_leg(gp, dev)
 
     res = {
         "metric": "solved DOFs/s + PCG iters to 1e-8 rel. residual; p50/p99 solve latency",
@@ -437,6 +480,8 @@ def main():
         res["multi_rhs"] = multi
     if serving is not None:
         res["serving"] = serving
+    if robust is not None:
+        res["coarse_space_comparison"] = robust
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline()

@@ -127,7 +127,13 @@ gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t n
  * cuts[a] holds nparts[a]+1 increasing element indices from 0 to ne[a].
  * m_j = nev if nev > 0, else #{lambda < threshold} capped at nev_max (if > 0);
  * then extended while the next eigenvalue repeats the last within 1e-8
- * relative + 1e-10 absolute.  coarse = 0 builds the one-level method only.
+ * relative + 1e-10 absolute.  coarse = 1 builds that GenEO coarse space,
+ * coarse = 0 the one-level method only, and coarse = 2 the zero-energy-mode
+ * space the paper compares against (Section 5, Example 1b): on each subdomain
+ * whose nodes carry no Dirichlet DOF, the kernel of its Neumann matrix
+ * A_{Omega_j} (the constant for diffusion, the three translations and three
+ * rotations for elasticity), times X_j; nev/threshold are then ignored and
+ * gn_precond_eigenvalues reports no eigenvalues.
  * local_prec 64 stores FP64 local factors, 32 stores them in FP32 (FP64
  * factorisation, FP32 storage and triangular solves, FP64 accumulation of the
  * result).  shift > 0 is the shift-and-invert shift (Section 3.3.2; 0 = 1e-2).

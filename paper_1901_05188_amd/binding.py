@@ -247,7 +247,9 @@ class Problem:
 
 
 class Preconditioner:
-    """GenEO two-level additive Schwarz preconditioner (gn_setup_geneo)."""
+    """GenEO two-level additive Schwarz preconditioner (gn_setup_geneo).
+
+    coarse: True / 1 / "geneo" (GenEO), "zem" / 2 (zero-energy modes), False / 0 / "none" (one level)."""
 
     def __init__(self, prob: Problem, nparts: Sequence[int], cuts, overlap=1, nev=0, threshold=0.0,
                  nev_max=0, local_prec=64, coarse=True, shift=0.0, eig_tol=0.0, eig_maxit=0,
@@ -260,7 +262,8 @@ class Preconditioner:
             keep.append(c)
             o.cuts[a] = _dptr(c, C.c_int32)
         o.overlap, o.nev, o.threshold, o.nev_max = int(overlap), int(nev), float(threshold), int(nev_max)
-        o.local_prec, o.coarse = int(local_prec), int(bool(coarse))
+        o.local_prec = int(local_prec)
+        o.coarse = {"geneo": 1, "zem": 2, "none": 0}[coarse] if isinstance(coarse, str) else int(coarse)
         o.shift, o.eig_tol, o.eig_maxit = float(shift), float(eig_tol), int(eig_maxit)
         o.eig_block, o.eig_filter = int(eig_block), int(eig_filter)
         o.local_kernel = int(local_kernel)

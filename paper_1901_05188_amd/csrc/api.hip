@@ -215,6 +215,7 @@ extern "C" gn_status gn_assemble(const gn_grid* grid, const gn_material* mat, co
   std::vector<void*> tmp;
   for (int a = 0; a < 3; ++a) p->d_xn[a] = upload(p->owned, grid->xn[a], (size_t)p->nn[a], s);
   p->d_dir = upload(p->owned, loads->dirichlet, (size_t)p->n_dof, s);
+  p->h_dir.assign(loads->dirichlet, loads->dirichlet + p->n_dof);
   p->d_free2full = upload(p->owned, f2f.data(), f2f.size(), s);
   const int nd = 8 * nc;
   p->d_Ke = dalloc<double>(p->owned, (size_t)p->n_elem * nd * nd);
@@ -414,9 +415,10 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   const double eig_tol = o->eig_tol > 0 ? o->eig_tol : 1e-12;
   const int eig_maxit = o->eig_maxit > 0 ? o->eig_maxit : 300;
   if (o->eig_filter < 0 || o->eig_filter > 8) argfail("eig_filter must lie in [0, 8]");
-  if (o->coarse && o->nev <= 0 && !(o->threshold > 0)) argfail("coarse space needs nev > 0 or threshold > 0");
-  if (o->coarse && o->nev > 48) argfail("nev must be <= 48");
-  if (o->coarse && o->nev <= 0 && (o->nev_max <= 0 || o->nev_max > 48))
+  if (o->coarse < 0 || o->coarse > 2) argfail("coarse must be 0, 1 or 2");
+  if (o->coarse == 1 && o->nev <= 0 && !(o->threshold > 0)) argfail("coarse space needs nev > 0 or threshold > 0");
+  if (o->coarse == 1 && o->nev > 48) argfail("nev must be <= 48");
+  if (o->coarse == 1 && o->nev <= 0 && (o->nev_max <= 0 || o->nev_max > 48))
     argfail("threshold mode needs 0 < nev_max <= 48");
   pc = new gn_precond();
   pc->prob = p;
@@ -555,12 +557,47 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
 
   // ---- GenEO eigenproblems -------------------------------------------------
   pc->NH = 0;
-  if (o->coarse && n_sub > 1) {
+  if (o->coarse != 0 && n_sub > 1) {
+    // columns per subdomain of the basis buffer V (eigen block or mode count)
+    int b = 0, maxm = 0;
+    double *V = nullptr, *Z = nullptr;
+    if (o->coarse == 2) {
+      // zero-energy modes: the kernel of the Neumann matrix A_{Omega_j} on the
+      // Ibar_j box, present when no node of the box carries a Dirichlet DOF
+      b = nc == 3 ? 6 : 1;
+      int coff = 0;
+      for (int j = 0; j < n_sub; ++j) {
+        SubDesc& sd = pc->sub[j];
+        bool floating = true;
+        for (int k = 0; k < sd.bn[2] && floating; ++k)
+          for (int jj = 0; jj < sd.bn[1] && floating; ++jj)
+            for (int i = 0; i < sd.bn[0] && floating; ++i) {
+              const int64_t node = (sd.blo[0] + i) + (int64_t)p->nn[0] * ((sd.blo[1] + jj) +
+                                   (int64_t)p->nn[1] * (sd.blo[2] + k));
+              for (int c = 0; c < nc; ++c) floating &= p->h_dir[node * nc + c] == 0;
+            }
+        sd.m = floating ? b : 0;
+        sd.coff = coff;
+        coff += sd.m;
+        maxm = std::max(maxm, sd.m);
+      }
+      pc->NH = coff;
+      pc->n_eval = 0;
+      pc->lam.clear();
+      pc->lam_n.assign(n_sub, 0);
+      const size_t vlen = (size_t)offVB * b;
+      V = dalloc<double>(tmp, vlen + 64);
+      Z = dalloc<double>(tmp, vlen + 64);
+      GN_HIP(hipMemsetAsync(V, 0, sizeof(double) * (vlen + 64), s));
+      GN_HIP(hipMemcpyAsync(pc->d_sub, pc->sub.data(), sizeof(SubDesc) * n_sub, hipMemcpyHostToDevice, s));
+      gnk::zem_modes(p, pc, b, maxNBB, V, s);
+      if (maxm > 0) gnk::eig_normalise(pc, b, maxm, V, s);
+    } else {
     const bool fixed = o->nev > 0;
     const int guard = 8;
     // block size: fixed m_j plus a guard band; threshold mode starts at 32 and
     // grows by 16 (to 64) when the eigenvalues below 1.5 x threshold do not fit
-    int b = fixed ? std::min(64, o->nev + std::max(guard, o->nev / 2)) : std::min(32, o->nev_max + guard);
+    b = fixed ? std::min(64, o->nev + std::max(guard, o->nev / 2)) : std::min(32, o->nev_max + guard);
     if (o->eig_block > 0) {
       const int need = (fixed ? o->nev : 0) + 1 + guard / 2;
       if (o->eig_block < need || o->eig_block > 64)
@@ -581,7 +618,6 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     for (int j = 0; j < n_sub; ++j)
       if (info[j]) throw gn_error{GN_ERR_NOT_SPD, "GenEO pencil of subdomain " + std::to_string(j) + " not definite"};
     const bool auto_block = o->eig_block <= 0;
-    double *V = nullptr, *Z = nullptr;
     std::vector<double> h_nu;
     int solves_prev = 0;   // block solves of earlier attempts with a smaller block
     for (;;) {
@@ -772,7 +808,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     pc->n_eval = b;
     pc->lam.assign((size_t)n_sub * b, 0.0);
     pc->lam_n.assign(n_sub, b);
-    int coff = 0, maxm = 0;
+    int coff = 0;
     for (int j = 0; j < n_sub; ++j) {
       std::vector<double> lam(b);
       for (int k = 0; k < b; ++k) {
@@ -802,6 +838,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     }
     pc->NH = coff;
     gnk::eig_normalise(pc, b, maxm, V, s);
+    }
     t2 = now_s();
     // ---- coarse basis, coarse matrix, coarse factor ------------------------
     if (pc->NH > 0) {

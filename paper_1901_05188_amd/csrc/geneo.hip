@@ -900,6 +900,46 @@ __global__ __launch_bounds__(NT) void k_cheb_step(const SubDesc* __restrict__ su
   Y0[o] = a * (TY[o] - c * Y1[o]) - beta * Y0[o];
 }
 
+// Zero-energy modes on the Ibar box of the subdomains with m_j > 0 (their
+// nodes carry no Dirichlet DOF): the constant (NC = 1), or the translations
+// e_x, e_y, e_z and the infinitesimal rotations e_a x (x - c) about the box
+// centre c (NC = 3), at the physical node positions (ramp map included).
+// Rows in the pencil's box numbering; other subdomains and padding rows zero.
+template <int NC>
+__global__ __launch_bounds__(NT) void k_zem_modes(const SubDesc* __restrict__ subs, const double* __restrict__ xn0,
+                                                  const double* __restrict__ xn1, const double* __restrict__ xn2,
+                                                  int map_kind, double mx0, double mx1, double mtan, int b,
+                                                  double* __restrict__ V) {
+  const SubDesc& sd = subs[blockIdx.y];
+  const int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= sd.NBB * TILE) return;
+  double* out = V + sd.offVB * b + (int64_t)r * b;
+  if (r >= sd.nB || sd.m == 0) {
+    for (int k = 0; k < b; ++k) out[k] = 0.0;
+    return;
+  }
+  if (NC == 1) {
+    out[0] = 1.0;
+    return;
+  }
+  int g[3];
+  box_global_node(sd.blo, sd.bn, sd.permB, r / NC, g);
+  const int c = r % NC;
+  const double x = xn0[g[0]], y = xn1[g[1]];
+  double z = xn2[g[2]];
+  if (map_kind == 1) z += mtan * (fmin(fmax(x, mx0), mx1) - mx0);
+  const double d0 = x - 0.5 * (xn0[sd.blo[0]] + xn0[sd.blo[0] + sd.bn[0] - 1]);
+  const double d1 = y - 0.5 * (xn1[sd.blo[1]] + xn1[sd.blo[1] + sd.bn[1] - 1]);
+  const double d2 = z - 0.5 * (xn2[sd.blo[2]] + xn2[sd.blo[2] + sd.bn[2] - 1]);
+  out[0] = c == 0 ? 1.0 : 0.0;
+  out[1] = c == 1 ? 1.0 : 0.0;
+  out[2] = c == 2 ? 1.0 : 0.0;
+  // e_x x d = (0, -d2, d1), e_y x d = (d2, 0, -d0), e_z x d = (-d1, d0, 0)
+  out[3] = c == 0 ? 0.0 : (c == 1 ? -d2 : d1);
+  out[4] = c == 0 ? d2 : (c == 1 ? 0.0 : -d0);
+  out[5] = c == 0 ? -d1 : (c == 1 ? d0 : 0.0);
+}
+
 // deterministic start block: hash of (subdomain, row, col) -> (-1, 1); zero on padding
 __global__ void k_vinit(const SubDesc* __restrict__ subs, int b, double* __restrict__ V) {
   const SubDesc& sd = subs[blockIdx.y];
@@ -949,7 +989,7 @@ __global__ __launch_bounds__(NT) void k_normalise(const SubDesc* __restrict__ su
       __syncthreads();
     }
     double sg = Vb[(int64_t)besti[0] * b + k] < 0.0 ? -1.0 : 1.0;
-    double scale = sg / sqrt(nrm2);
+    double scale = nrm2 > 0.0 ? sg / sqrt(nrm2) : 1.0;   // a zero column stays zero
     __syncthreads();
     for (int r = threadIdx.x; r < sd.nB; r += NT) Vb[(int64_t)r * b + k] *= scale;
     __syncthreads();
@@ -1224,6 +1264,19 @@ static PouAx pou_axes(const gn_precond* pc) {
 void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s) {
   hipLaunchKernelGGL(k_vinit, dim3((maxNBB * TILE + NT - 1) / NT, pc->n_sub), dim3(NT), 0, s,
                      pc->d_sub, b, V);
+  GN_CHECK_LAUNCH();
+}
+
+void zem_modes(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s) {
+  if (b != (p->nc == 3 ? 6 : 1)) throw gn_error{GN_ERR_ARG, "zero-energy modes: 6 columns (elasticity) or 1"};
+  dim3 grid((maxNBB * TILE + NT - 1) / NT, pc->n_sub);
+  const double mtan = p->map_kind == 1 ? tan(p->map_par[2]) : 0.0;
+  if (p->nc == 3)
+    hipLaunchKernelGGL(k_zem_modes<3>, grid, dim3(NT), 0, s, pc->d_sub, p->d_xn[0], p->d_xn[1], p->d_xn[2],
+                       p->map_kind, p->map_par[0], p->map_par[1], mtan, b, V);
+  else
+    hipLaunchKernelGGL(k_zem_modes<1>, grid, dim3(NT), 0, s, pc->d_sub, p->d_xn[0], p->d_xn[1], p->d_xn[2],
+                       p->map_kind, p->map_par[0], p->map_par[1], mtan, b, V);
   GN_CHECK_LAUNCH();
 }
 

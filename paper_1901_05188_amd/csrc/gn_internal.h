@@ -93,6 +93,7 @@ struct gn_problem {
   double* d_A = nullptr;       // node-block matrix, [27][nc][nc][n_node]
   double* d_b = nullptr;       // load, full numbering, n_dof x nrhs
   uint8_t* d_dir = nullptr;    // Dirichlet mask, full numbering
+  std::vector<uint8_t> h_dir;  // the same mask on the host
   int* d_free2full = nullptr;  // n_free
   // CG workspace (full numbering)
   double *d_x = nullptr, *d_r = nullptr, *d_p = nullptr, *d_q = nullptr, *d_z = nullptr;
@@ -227,6 +228,7 @@ void eig_small(int n_sub, int b, const double* GPp, const double* GBp, const dou
 void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const double* BZ,
                  const double* Y, double* V, double* BV, hipStream_t s);
 void eig_normalise(const gn_precond* pc, int b, int ncol, double* V, hipStream_t s);
+void zem_modes(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s);
 void build_phi(const gn_problem* p, const gn_precond* pc, int b, int maxNI, const double* V,
                hipStream_t s);
 void aphi(const gn_problem* p, const gn_precond* pc, int b, int maxNB, double* Y, hipStream_t s);

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from tests import oracle_runs as orc
+from oracle import pcg as opcg
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -171,6 +172,48 @@ def test_geneo_pcg_solution_and_iterations(name):
     # the un-restarted PCG sequence is the oracle's algorithm
     assert abs(rep[0]["iters_first"] - info["iters"]) <= max(1, int(0.02 * info["iters"]))
     assert abs(rep[0]["cond_est"] - info["kappa"]) <= 1e-3 * info["kappa"]
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_zero_energy_mode_coarse_space_matches_oracle(name):
+    """Zero-energy-mode coarse space (the paper's ZEM comparison): the same
+    coarse dimension and per-subdomain counts as the oracle, M^-1 r to 1e-10
+    (the correction does not depend on the basis of the span), the PCG
+    solution at 1e-12 (1e-8), and the iteration count and CG-Lanczos kappa at
+    the 1e-5 residual reduction of the paper's Example 1b table (max(1, 2 %),
+    1e-2).  The count is compared there and not at 1e-12: with ZEM the
+    preconditioned kappa is in the thousands, and past 1e-8 the finite-precision
+    CG trajectory (loss of orthogonality) shifts by several percent under
+    rounding-level changes of M^-1, the oracle against itself included."""
+    g = orc.geneo_run(name, coarse="zem")
+    pc = precond(name, coarse="zem")
+    assert pc.report["coarse_dim"] == g.NH
+    for j in range(orc.workload(name).n_sub):
+        lam, m = pc.eigenvalues(j)
+        assert m == g.m[j] and len(lam) == 0
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(pc.prob.n_free)
+    z = torch.zeros((1, pc.prob.n_free), dtype=torch.float64, device=DEV)
+    pc.apply(_t(r[None, :]), z)
+    ref = g.apply(r)
+    err = np.linalg.norm(z[0].cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"[gpu] {name} ZEM N_H {g.NH} M^-1 r rel err {err:.2e}", flush=True)
+    assert err <= 1e-10
+    A, b, free, Ke = orc.system(name)
+    u_ref, info = opcg.pcg(A, b[:, 0], g.apply, rtol=1e-12, maxit=3000)
+    bt = _t(b.T[:1])
+    x = torch.zeros_like(bt)
+    st, rep = _gp().solve(pc.prob, pc, bt, x, rtol=1e-12, maxit=3000)
+    assert rep[0]["converged"] == 1
+    assert np.linalg.norm(x[0].cpu().numpy() - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
+    u5, info5 = opcg.pcg(A, b[:, 0], g.apply, rtol=1e-5, maxit=3000)
+    x.zero_()
+    st, rep5 = _gp().solve(pc.prob, pc, bt, x, rtol=1e-5, maxit=3000)
+    print(f"[gpu] {name} ZEM iterations at 1e-5: {rep5[0]['iters_first']} (oracle {info5['iters']}), "
+          f"kappa {rep5[0]['cond_est']:.1f} (oracle {info5['kappa']:.1f}); at 1e-12: "
+          f"{rep[0]['iters_first']} (oracle {info['iters']})", flush=True)
+    assert abs(rep5[0]["iters_first"] - info5["iters"]) <= max(1, int(0.02 * info5["iters"]))
+    assert abs(rep5[0]["cond_est"] - info5["kappa"]) <= 1e-2 * info5["kappa"]
 
 
 @pytest.mark.parametrize("name", ["lam_3x2x2_uneven", "diff_2x2x2"])

@@ -396,6 +396,44 @@ def c4_requests(n_ops: int, n_req: int = 1000, rate: float = 20.0, max_rhs: int 
     return [dict(t=float(t[i]), op=int(ops[i]), k=int(ks[i]), seed=(seed, 2, i)) for i in range(n_req)]
 
 
+EXAMPLE1_STACK = [-45.0, 45.0, 0.0, 90.0, 45.0, -45.0, -45.0, 45.0, 90.0, 0.0, 45.0, -45.0]
+
+
+def example1b_plate(nparts, nxy=(35, 7), threshold=0.15, nev_max=32) -> Workload:
+    """The flat plate of the paper's Example 1 (Section 5): 100 mm x 20 mm, the
+    12-ply stacking sequence of eqn:stackingSeq_Example01 with 11 resin
+    interfaces, 2 elements per ply and 1 per interface through the thickness,
+    clamped at x = 0, uniform pressure 0.01 MPa on the top face.  Q1 elements
+    (35 x 7 in plane: 30,240 free DOFs, near the 30,000 of the Example 1b
+    table); GenEO by threshold."""
+    layers = []
+    for p, a in enumerate(EXAMPLE1_STACK):
+        layers.append(("ply", a, 2, PLY_T))
+        if p != len(EXAMPLE1_STACK) - 1:
+            layers.append(("resin", 0.0, 1, RESIN_T))
+    nx, ny = nxy
+    trac = np.tile(np.array([0.0, 0.0, -0.01]), nx * ny)
+    return laminate_plate((nx, ny), (100.0, 20.0), layers, nparts=nparts, overlap=1, nev=0,
+                          threshold=threshold, nev_max=nev_max, body=None, traction=trac, nrhs=1,
+                          name=f"example1b_{nparts[0]}x{nparts[1]}x{nparts[2]}")
+
+
+def contrast_box(contrast: float, nparts, ne=(32, 32, 32), seed: int = 12, threshold=0.15,
+                 nev_max=32) -> Workload:
+    """Scalar diffusion on a unit-cell box, u = 0 on the x faces, f = 1: k = 1
+    with every fifth z-layer crossed by three channels (3 cells wide, along y)
+    of conductivity `contrast` (the same channels for every contrast)."""
+    rng = np.random.default_rng(seed)
+    k = np.ones(ne)
+    for L in range(2, ne[2], 5):
+        for _ in range(3):
+            x0 = rng.uniform(2, ne[0] - 2)
+            k[np.abs(np.arange(ne[0]) + 0.5 - x0) <= 1.5, :, L] = contrast
+    kel = np.transpose(k, (2, 1, 0)).ravel()
+    return diffusion_box(ne, kel, nparts, overlap=1, threshold=threshold, nev_max=nev_max,
+                         name=f"contrast_{contrast:g}_{nparts[0]}x{nparts[1]}x{nparts[2]}", seed=seed)
+
+
 def config_c5() -> Workload:
     """384x72x71 ramped laminate, 24 plies x 2 elements + 23 resin, resin
     contrast 1e3, top pressure 0.01 MPa, 32x12x4 subdomains."""
