@@ -529,6 +529,12 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   for (int j = 0; j < n_sub; ++j)
     if (info[j]) throw gn_error{GN_ERR_NOT_SPD, "local matrix of subdomain " + std::to_string(j) +
                                                     " not positive definite (row " + std::to_string(info[j] - 1) + ")"};
+  if (gnk::pf_supported(p, pc)) {
+    // transposed backward band: the backward sweep streams it like the forward one
+    if (o->local_prec == 32) pc->d_LIb = dalloc<float>(pc->owned, (size_t)offTI * TILE2);
+    else pc->d_LIb = dalloc<double>(pc->owned, (size_t)offTI * TILE2);
+    gnk::band_transpose(d_refs, n_sub, maxNBI, LI, DI, pc->d_LIb, o->local_prec == 32, s);
+  }
   if (o->local_prec == 32) {
     pc->d_LIf = dalloc<float>(pc->owned, (size_t)offTI * TILE2);
     pc->d_DIf = dalloc<float>(pc->owned, (size_t)offDI * TILE2);
@@ -926,7 +932,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     pc->trsv_bytes_mc = tbm;
   }
   int64_t hb = 0;
-  hb += (int64_t)pc->tilesI * TILE2 * (pc->local_prec == 32 ? 4 : 8);
+  hb += (int64_t)pc->tilesI * TILE2 * (pc->local_prec == 32 ? 4 : 8) * (pc->d_LIb ? 2 : 1);
   hb += (int64_t)pc->sub.size() * 0;
   hb += pc->phi_len * 8 + (int64_t)pc->NBH * pc->NBH * TILE2 * 8 + pc->vecI * 8;
   if (rep) {

@@ -432,6 +432,31 @@ __global__ __launch_bounds__(NT) void k_band_chol(const BandRef* __restrict__ ma
 // ---------------------------------------------------------------------------
 // FP64 -> FP32 copy of the local factors (mixed-precision local solves)
 // ---------------------------------------------------------------------------
+// Backward band of the single-column sweep: for block row K, tile d - 1
+// (d = 1..w) holds L(K+d, K)^T and tile w holds D_K^T (D_K = L(K,K)^-1),
+// column-major like every tile, zero where K + d is past the last block row.
+// The backward sweep then reads, like the forward one, contiguous tile
+// columns across the lanes.  One workgroup per (block row, subdomain).
+template <typename FT>
+__global__ __launch_bounds__(256) void k_band_transpose(const BandRef* __restrict__ refs, const double* __restrict__ T,
+                                                       const double* __restrict__ D, FT* __restrict__ TB) {
+  const BandRef rf = refs[blockIdx.y];
+  const int K = blockIdx.x;
+  if (K >= rf.NB) return;
+  const int w = rf.w, W1 = w + 1;
+  FT* out = TB + (rf.offT + (int64_t)K * W1) * TILE2;
+  for (int d = 1; d <= w + 1; ++d) {
+    const double* src = nullptr;
+    if (d <= w && K + d < rf.NB) src = T + (rf.offT + (int64_t)(K + d) * W1 + (w - d)) * TILE2;
+    if (d == w + 1) src = D + (rf.offD + (int64_t)K) * TILE2;
+    FT* o = out + (int64_t)(d - 1) * TILE2;
+    for (int e = threadIdx.x; e < TILE2; e += 256) {
+      const int i = e % TILE, rr = e / TILE;   // output (row i, column rr) at rr * TILE + i
+      o[e] = src ? (FT)src[i * TILE + rr] : (FT)0;
+    }
+  }
+}
+
 __global__ void k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (int64_t)gridDim.x * blockDim.x)
@@ -468,6 +493,16 @@ void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, dou
 
 void band_chol(const void* d_refs, int n, double* T, double* D, int* info, hipStream_t s) {
   hipLaunchKernelGGL(k_band_chol_mfma, dim3(n), dim3(NT), 0, s, (const BandRef*)d_refs, T, D, info);
+  GN_CHECK_LAUNCH();
+}
+
+void band_transpose(const void* d_refs, int n, int maxNB, const double* T, const double* D, void* TB, bool f32,
+                    hipStream_t s) {
+  dim3 grid((unsigned)maxNB, (unsigned)n);
+  if (f32)
+    hipLaunchKernelGGL(k_band_transpose<float>, grid, dim3(256), 0, s, (const BandRef*)d_refs, T, D, (float*)TB);
+  else
+    hipLaunchKernelGGL(k_band_transpose<double>, grid, dim3(256), 0, s, (const BandRef*)d_refs, T, D, (double*)TB);
   GN_CHECK_LAUNCH();
 }
 

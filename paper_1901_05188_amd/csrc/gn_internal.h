@@ -126,6 +126,7 @@ struct gn_precond {
   float* d_LIf = nullptr;    // band tiles (FP32) or nullptr
   double* d_DI = nullptr;    // inverse diagonal tiles (FP64)
   float* d_DIf = nullptr;
+  void* d_LIb = nullptr;     // backward band of the single-column sweep (FP64 or FP32), or nullptr
   double* d_t = nullptr;     // local vectors (sum of NBI*TILE)
   int64_t tilesI = 0, vecI = 0;
   // coarse
@@ -185,6 +186,8 @@ void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, dou
                     hipStream_t s);
 void band_chol(const void* d_refs, int n, double* T, double* D, int* info, hipStream_t s);
 void to_f32(int64_t n, const double* a, float* b, hipStream_t s);
+void band_transpose(const void* d_refs, int n, int maxNB, const double* T, const double* D, void* TB, bool f32,
+                    hipStream_t s);
 // precond.hip
 bool pf_supported(const gn_problem* p, const gn_precond* pc);
 void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, const double* done,

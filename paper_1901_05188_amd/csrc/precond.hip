@@ -38,7 +38,8 @@ __device__ inline void lds_barrier() {
 template <typename FT, int NC, int SP, int G>
 __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __restrict__ subs, int NX, int NY,
                                                            const double* __restrict__ r, const FT* __restrict__ T,
-                                                           const FT* __restrict__ D, double* __restrict__ tvec,
+                                                           const FT* __restrict__ D, const FT* __restrict__ TBk,
+                                                           double* __restrict__ tvec,
                                                            const double* __restrict__ Phi, double* __restrict__ g,
                                                            const double* __restrict__ done, int padw,
                                                            const FT* __restrict__ Z0) {
@@ -144,17 +145,19 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
 #undef GN_STEP_FWD
 #undef GN_LOAD_FWD
   // ---- backward ----
+  // backward block row K: tile d-1 of row K of the transposed band holds
+  // L(K+d, K)^T (entry (i, rr) = L(K+d, K)(rr, i)) and tile w holds D_K^T
+  const FT* TBb = TBk + sd.offTI * TILE2;
 #define GN_LOAD_BWD(K_, LV, DN)                                                          \
   {                                                                                      \
+    const FT* rowp = TBb + (int64_t)(K_) * (w + 1) * TILE2;                              \
     _Pragma("unroll") for (int u = 0; u < SP; ++u) {                                     \
-      int d = (u / CW) + 1, rr = CW * gq + (u % CW);                                     \
-      int kk = min((K_) + d, NB - 1);                                                    \
-      const FT* src = (u < ns) ? Tb + ((int64_t)kk * (w + 1) + (w - d)) * TILE2 + i * TILE + rr \
-                               : Z0 + i;                                                 \
+      int t = u / CW, rr = CW * gq + (u % CW);                                           \
+      const FT* src = (u < ns) ? rowp + (t * TILE + rr) * TILE + i : Z0 + i;             \
       LV[u] = *src;                                                                      \
     }                                                                                    \
-    const FT* dk = Db + (int64_t)(K_) * TILE2;                                           \
-    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[i * TILE + CW * gq + q];   \
+    const FT* dk = rowp + (int64_t)w * TILE2;                                            \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[(CW * gq + q) * TILE + i]; \
   }
 #define GN_STEP_BWD(K_, LV, DN)                                                          \
   {                                                                                      \
@@ -315,6 +318,7 @@ void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, con
   // reaches at most SP / 2 <= maxw + 16 tiles past either end
   const int padw = pc->maxwI + 16;
   if (pf_supported(p, pc)) {
+    if (!pc->d_LIb) throw gn_error{GN_ERR_ARG, "backward band missing for the single-column sweep"};
     size_t dynpf = (size_t)(pc->maxNBI + 2 * padw) * TILE * sizeof(double);
 #define GN_PF(FT, NC, SPV)                                                                        \
   do {                                                                                            \
@@ -325,7 +329,7 @@ void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, con
                        p->nn[1], r,                                                               \
                        (const FT*)(f32 ? (const void*)pc->d_LIf : (const void*)pc->d_LI),         \
                        (const FT*)(f32 ? (const void*)pc->d_DIf : (const void*)pc->d_DI),         \
-                       pc->d_t, Phi, pc->d_g, done, padw,                                         \
+                       (const FT*)pc->d_LIb, pc->d_t, Phi, pc->d_g, done, padw,                   \
                        (const FT*)(f32 ? (const void*)pc->d_zf : (const void*)pc->d_z0));         \
   } while (0)
 #define GN_PF_SP(FT, NC)                                  \
