@@ -529,8 +529,8 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   for (int j = 0; j < n_sub; ++j)
     if (info[j]) throw gn_error{GN_ERR_NOT_SPD, "local matrix of subdomain " + std::to_string(j) +
                                                     " not positive definite (row " + std::to_string(info[j] - 1) + ")"};
-  if (gnk::pf_supported(p, pc)) {
-    // transposed backward band: the backward sweep streams it like the forward one
+  {
+    // transposed backward band: the backward sweeps stream it like the forward ones
     if (o->local_prec == 32) pc->d_LIb = dalloc<float>(pc->owned, (size_t)offTI * TILE2);
     else pc->d_LIb = dalloc<double>(pc->owned, (size_t)offTI * TILE2);
     gnk::band_transpose(d_refs, n_sub, maxNBI, LI, DI, pc->d_LIb, o->local_prec == 32, s);

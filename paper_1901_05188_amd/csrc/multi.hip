@@ -330,7 +330,8 @@ __device__ inline double to_d(FT v) { return (double)v; }
 
 template <typename FT, int SPW>
 __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict__ subs, const FT* __restrict__ T,
-                                                       const FT* __restrict__ D, double* __restrict__ tm,
+                                                       const FT* __restrict__ D, const FT* __restrict__ TBk,
+                                                       double* __restrict__ tm,
                                                        const FT* __restrict__ Z0, int k,
                                                        const double* __restrict__ scal) {
   extern __shared__ double ring[];           // (w + 1) block rows of TILE x MC_K
@@ -418,21 +419,21 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
   }
 #undef MC_LOAD_FWD
   for (int e = threadIdx.x; e < W1 * TILE * MC_K; e += 512) ring[e] = 0.0;
-  // backward tile of slot s at block row K: L(K + d, K) stored at (K + d, w - d),
-  // d = 1 + kg + 4 s, used transposed; rows past the end read a real tile
-  // against a zero ring slot
+  // backward tile of slot s at block row K: L(K + d, K)^T, d = 1 + kg + 4 s,
+  // tile d - 1 of row K of the transposed band (zero past the last block row),
+  // and D_K^T in its tile w: the same contiguous lane pattern as the forward
+  const FT* TBb = TBk + sd.offTI * TILE2;
 #define MC_LOAD_BWD(K_)                                                                         \
   {                                                                                             \
     const int KK = (K_);                                                                        \
     _Pragma("unroll") for (int s = 0; s < SPW; ++s) {                                           \
       const int d = 1 + kg + 4 * s;                                                             \
-      const int kk = min(KK + d, NB - 1);                                                       \
-      const FT* tile = (d <= w) ? Tb + ((int64_t)kk * W1 + (w - d)) * TILE2 : Z0;               \
-      _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) av[s][ks] = tile[(rb + lr) * TILE + 4 * ks + lk]; \
+      const FT* tile = (d <= w) ? TBb + ((int64_t)KK * W1 + (d - 1)) * TILE2 : Z0;              \
+      _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) av[s][ks] = tile[(4 * ks + lk) * TILE + rb + lr]; \
     }                                                                                           \
     if (lead) {                                                                                 \
-      const FT* dk = Db + (int64_t)KK * TILE2;                                                  \
-      _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dv[ks] = to_d(dk[(rb + lr) * TILE + 4 * ks + lk]); \
+      const FT* dk = TBb + ((int64_t)KK * W1 + w) * TILE2;                                      \
+      _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dv[ks] = to_d(dk[(4 * ks + lk) * TILE + rb + lr]); \
       _Pragma("unroll") for (int i = 0; i < 4; ++i) vv[i] = tj[(int64_t)(KK * TILE + rb + 4 * i + lk) * MC_K + lr]; \
     }                                                                                           \
   }
@@ -663,6 +664,7 @@ int mc_band_lds_bytes(int maxw) { return (maxw + 1) * TILE * MC_K * (int)sizeof(
 void precond_mc(const gn_problem* p, const gn_precond* pc, const double* r, double* z, int k, double* part,
                 int pstride, const double* scal, double* tm, double* gm, double* um, double* ym, hipStream_t s) {
   if (k < 1 || k > MC_K) throw gn_error{GN_ERR_ARG, "multi-RHS batch must hold 1..16 columns"};
+  if (!pc->d_LIb) throw gn_error{GN_ERR_ARG, "backward band missing"};
   const bool f32 = pc->local_prec == 32;
   const double* Phi = pc->NH > 0 ? pc->d_Phi : nullptr;
   const int NHP = pc->NBH * TILE;
@@ -683,7 +685,8 @@ void precond_mc(const gn_problem* p, const gn_precond* pc, const double* r, doub
     GN_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));     \
     hipLaunchKernelGGL(kfn, dim3(pc->n_sub), dim3(512), lds, s, pc->d_sub,                             \
                        (const FT*)(f32 ? (const void*)pc->d_LIf : (const void*)pc->d_LI),              \
-                       (const FT*)(f32 ? (const void*)pc->d_DIf : (const void*)pc->d_DI), tm,          \
+                       (const FT*)(f32 ? (const void*)pc->d_DIf : (const void*)pc->d_DI),              \
+                       (const FT*)pc->d_LIb, tm,                                                       \
                        (const FT*)(f32 ? (const void*)pc->d_zf : (const void*)pc->d_z0), k, scal);     \
   } while (0)
 #define GN_MC_S(FT)                            \
