@@ -623,6 +623,9 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     GN_HIP(hipStreamSynchronize(s));
     for (int j = 0; j < n_sub; ++j)
       if (info[j]) throw gn_error{GN_ERR_NOT_SPD, "GenEO pencil of subdomain " + std::to_string(j) + " not definite"};
+    // transposed pencil band for the backward sweeps of the block solves
+    double* TBB = dalloc<double>(tmp, (size_t)offTB * TILE2);
+    gnk::band_transpose(d_refs, n_sub, maxNBB, LB, DB, TBB, false, s);
     const bool auto_block = o->eig_block <= 0;
     std::vector<double> h_nu;
     int solves_prev = 0;   // block solves of earlier attempts with a smaller block
@@ -672,7 +675,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
         const int d = std::min(dmax, it + 1);
         // Z = T V = P^-1 B V
         GN_HIP(hipMemcpyAsync(Z, BV, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
-        gnk::eig_trsm(pc, b, LB, DB, Z, s);
+        gnk::eig_trsm(pc, b, LB, DB, TBB, Z, s);
         ++solves;
         if (d == 1) {
           // Rayleigh-Ritz on span(Z): P Z = B V, so Z^T P Z = Z^T (B V)
@@ -705,7 +708,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
           gnk::eig_bapply(p, pc, BE, b, maxNBB, Yc, BYc, s);
           for (int i = 2; i < d; ++i) {
             GN_HIP(hipMemcpyAsync(Z, BYc, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
-            gnk::eig_trsm(pc, b, LB, DB, Z, s);
+            gnk::eig_trsm(pc, b, LB, DB, TBB, Z, s);
             ++solves;
             gnk::eig_cheb_step(pc, b, maxNBB, Z, Yc, Y0, d_coef, ncoef, i - 2, s);   // Y0 <- Y_i
             gnk::eig_bapply(p, pc, BE, b, maxNBB, Y0, BY0, s);
@@ -714,7 +717,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
           }
           // W = T Y_{d-1}: Rayleigh-Ritz on span(W) with P W = B Y_{d-1}
           GN_HIP(hipMemcpyAsync(Z, BYc, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
-          gnk::eig_trsm(pc, b, LB, DB, Z, s);
+          gnk::eig_trsm(pc, b, LB, DB, TBB, Z, s);
           ++solves;
           gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
           gnk::eig_gram(pc, b, Z, BYc, BZ, nullptr, nullptr, GP, GB, nullptr, s);

@@ -284,6 +284,7 @@ __device__ inline void geneo_lds_barrier() {
 template <int W, int P, int S>
 __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ subs, int b, int ringlen,
                                                    const double* __restrict__ T, const double* __restrict__ D,
+                                                   const double* __restrict__ TBk,
                                                    const double* __restrict__ Z0, double* __restrict__ V) {
   static_assert(W % S == 0 && (W / S) % P == 0, "W / S must be a multiple of the prefetch depth");
   constexpr int WS = W / S;                 // tile slots per wave and step
@@ -404,17 +405,19 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
   __syncthreads();
   for (int e = threadIdx.x; e < ringlen; e += nthr) ring[e] = 0.0;
   // ---- backward: X_K = Dinv_K^T (Y_K - sum_d L(K+d,K)^T X_{K+d}), d = t + 1 ----
-#define TR_BWD_TILE(K_, t_) \
-  (((t_) < w) ? Tb + ((int64_t)min((K_) + 1 + (t_), NB - 1) * W1 + (w - 1 - (t_))) * TILE2 : Z0)
+  // L(K+d,K)^T is tile t of row K of the transposed band (zero past the last
+  // block row) and Dinv_K^T its tile w: contiguous tile columns across lanes
+  const double* TBb = TBk + sd.offTB * TILE2;
+#define TR_BWD_TILE(K_, t_) (((t_) < w) ? TBb + ((int64_t)(K_) * W1 + (t_)) * TILE2 : Z0)
 #define TR_LOAD_A_BWD(S_, K_, t_)                                                              \
   {                                                                                            \
     const double* tp = TR_BWD_TILE(K_, t_);                                                    \
-    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) a[S_][ks] = tp[(rb + lr) * TILE + 4 * ks + lk]; \
+    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) a[S_][ks] = tp[(4 * ks + lk) * TILE + rb + lr]; \
   }
 #define TR_LOAD_DV_BWD(K_)                                                                     \
   {                                                                                            \
-    const double* dk = Db + (int64_t)(K_) * TILE2;                                             \
-    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dv[ks] = dk[(rb + lr) * TILE + 4 * ks + lk]; \
+    const double* dk = TBb + ((int64_t)(K_) * W1 + w) * TILE2;                                 \
+    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dv[ks] = dk[(4 * ks + lk) * TILE + rb + lr]; \
     _Pragma("unroll") for (int i = 0; i < 4; ++i)                                              \
       vv[i] = Vb[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + col];                           \
   }
@@ -1304,7 +1307,8 @@ void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int
   GN_CHECK_LAUNCH();
 }
 
-void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, double* V, hipStream_t s) {
+void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, const double* TB, double* V,
+              hipStream_t s) {
   if (b > 64) throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
   int maxw = 0;
   for (const SubDesc& sd : pc->sub) maxw = std::max(maxw, sd.wB);
@@ -1315,13 +1319,13 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, dou
   const size_t lds = sizeof(double) * ((size_t)ringlen + (size_t)2 * ncb * TILE * 17);
   // tile slots per step: the smallest multiple of the prefetch depth (6) >= w
   const int W = std::max(6, (maxw + 5) / 6 * 6);
-  if (lds <= 160 * 1024 && W <= 30 && pc->d_z0) {
+  if (lds <= 160 * 1024 && W <= 30 && pc->d_z0 && TB) {
 #define GN_TR1(WV, PV, SV)                                                                           \
   do {                                                                                               \
     GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV, PV, SV>,                                 \
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));               \
     hipLaunchKernelGGL((k_trsm_ring<WV, PV, SV>), dim3(pc->n_sub), dim3(128 * ncb * SV), lds, s, pc->d_sub, b, \
-                       ringlen, T, D, pc->d_z0, V);                                                  \
+                       ringlen, T, D, TB, pc->d_z0, V);                                              \
   } while (0)
 #define GN_TR(WV)                                   \
   do {                                              \
