@@ -128,9 +128,13 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
 #pragma unroll
     for (int c2 = 0; c2 < NC; ++c2) {
       double bv = base[(int64_t)(d * NC + c2) * npad + r];
+      // B = X A_O X vanishes away from the overlap: rows of the subdomain's
+      // core, and neighbours outside overlap elements, carry bv = 0 and skip
+      // their V loads (whole waves of rows at once, the zeros come in blocks)
+      if (bv == 0.0) continue;
       int r2 = min(max((ln + dn) * NC + c2, 0), nmax);   // out-of-box neighbours have bv = 0
       // a chunk may run up to 7 columns past the row end into the next row or the
-      // 64-double tail of the buffer: loads stay unconditional, stores are masked
+      // 64-double tail of the buffer: loads stay in bounds, stores are masked
       const double* vr = Vb + (int64_t)r2 * b + col0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc[q] += bv * vr[q];
