@@ -192,6 +192,13 @@ __device__ inline void load_tile_lds(double* dst, const double* src) {
 // ---------------------------------------------------------------------------
 typedef double bc_d4 __attribute__((ext_vector_type(4)));
 
+__device__ inline double bc_readlane(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ inline void bc_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
@@ -283,35 +290,52 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
           tk[col * TILE + row] = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
         }
       } else if (wid == 0) {
-        // dense Cholesky of the diagonal tile (lower), one wave
+        // dense Cholesky of the diagonal tile (lower), one wave, in registers:
+        // lane r (and its mirror r + 32) holds row r; column k's entries come
+        // from lane c by readlane
+        const int r = lane & (TILE - 1);
+        double a[TILE];
+#pragma unroll
+        for (int c = 0; c < TILE; ++c) a[c] = Ss[r][c];
+#pragma unroll
         for (int k = 0; k < TILE; ++k) {
-          double dkk = Ss[k][k];
+          double dkk = bc_readlane(a[k], k);
           if (!(dkk > 0.0)) {
             if (lane == 0 && !fail) fail = K * TILE + k + 1;
             dkk = 1.0;
           }
           const double piv = sqrt(dkk);
-          bc_lds_fence();
-          if (lane == k) Ss[k][k] = piv;
-          if (lane > k && lane < TILE) Ss[lane][k] = Ss[lane][k] / piv;
-          bc_lds_fence();
-          for (int e = (k + 1) * TILE + lane; e < TILE2; e += 64) {
-            const int r = e % TILE, c = e / TILE;
-            if (r >= c) Ss[r][c] -= Ss[r][k] * Ss[c][k];
+          a[k] = r == k ? piv : (r > k ? a[k] / piv : a[k]);
+#pragma unroll
+          for (int c = k + 1; c < TILE; ++c) {
+            const double lck = bc_readlane(a[k], c);
+            if (r >= c) a[c] -= a[k] * lck;
           }
-          bc_lds_fence();
         }
-        // inverse of the lower-triangular factor, column per lane
+        bc_lds_fence();
         if (lane < TILE) {
-          const int c = lane;
-          for (int r = 0; r < TILE; ++r) {
-            double sv = 0.0;
-            if (r >= c) {
-              sv = (r == c) ? 1.0 : 0.0;
-              for (int k = c; k < r; ++k) sv -= Ss[r][k] * Xs[k][c];
-              sv /= Ss[r][r];
+#pragma unroll
+          for (int c = 0; c < TILE; ++c) Ss[r][c] = c <= r ? a[c] : 0.0;
+        }
+        bc_lds_fence();
+        // inverse of the lower-triangular factor: lane c forms column c in
+        // registers, reading the rows of the factor from LDS (broadcast)
+        {
+          const int c = r;
+          double xc[TILE];
+#pragma unroll
+          for (int i = 0; i < TILE; ++i) {
+            double s0 = i == c ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < i; k += 2) {
+              s0 -= Ss[i][k] * xc[k];
+              if (k + 1 < i) s1 -= Ss[i][k + 1] * xc[k + 1];
             }
-            Xs[r][c] = sv;
+            xc[i] = i >= c ? (s0 + s1) / Ss[i][i] : 0.0;
+          }
+          if (lane < TILE) {
+#pragma unroll
+            for (int i = 0; i < TILE; ++i) Xs[i][c] = xc[i];
           }
         }
         bc_lds_fence();
