@@ -173,13 +173,15 @@ def serving_leg(gp, n_req, rate, rtol, dev):
             time.sleep(dt)
         b, x = loads[i]
         tickets.append(srv.submit(ids[r["op"]], ops[r["op"]][1].n_free, b, x, rtol=rtol, maxit=5000))
-    lat, iters, worst, conv, dofcols = [], [], 0.0, True, 0
+    lat, iters, worst, conv, dofcols, at_target = [], [], 0.0, True, 0, True
     for i, t in enumerate(tickets):
         st, rep, l = srv.wait(t)
         lat.append(l)
         iters += [c["iters"] for c in rep]
         worst = max(worst, max(c["true_rel_res"] for c in rep))
         conv &= st == 0 and all(c["converged"] == 1 for c in rep)
+        # the true residual meets rtol, or sits at the FP64 rounding floor of its x
+        at_target &= all(c["true_rel_res"] <= max(rtol, 4 * c["res_floor"]) for c in rep)
         dofcols += len(rep) * ops[reqs[i]["op"]][1].n_free
     wall = time.perf_counter() - tstart
     # one request again, alone on an idle server: the same bits as in the mix
@@ -210,6 +212,7 @@ def serving_leg(gp, n_req, rate, rtol, dev):
            "latency_ms": {"p50": 1000 * q(0.5), "p99": 1000 * q(0.99)},
            "pcg_iters": {"mean": float(np.mean(iters)), "max": int(max(iters))},
            "all_converged": bool(conv), "max_true_rel_res": worst,
+           "all_true_res_at_rtol_or_fp64_floor": bool(at_target),
            "alone_equals_mix_bitwise": same, "rel_err_vs_fp64_local": err64,
            "catalogue_build_s": t_build, "resident_GB": resident / 1e9}
     log(f"serving: {len(reqs)} requests ({len(iters)} columns) in {wall:.1f}s, p50 {out['latency_ms']['p50']:.0f} ms "

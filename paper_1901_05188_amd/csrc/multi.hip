@@ -281,8 +281,10 @@ __global__ __launch_bounds__(256) void k_gather_mc(const SubDesc* __restrict__ s
   double* tj = tm + sd.offVI * MC_K;
   const double* ph = Phi ? Phi + sd.offPhi : nullptr;
   for (int r0 = 0; r0 < npad; r0 += RC) {
+    // read column-wise (consecutive lanes take consecutive local rows of one
+    // column: runs of contiguous global DOFs), write row-wise through LDS
     for (int e = threadIdx.x; e < RC * MC_K; e += 256) {
-      const int rr = e / MC_K, c = e % MC_K, row = r0 + rr;
+      const int c = e / RC, rr = e % RC, row = r0 + rr;
       double v = 0.0;
       if (row < sd.nI && c < k) {
         int gn[3];
@@ -290,8 +292,12 @@ __global__ __launch_bounds__(256) void k_gather_mc(const SubDesc* __restrict__ s
         int64_t node = gn[0] + (int64_t)NX * (gn[1] + (int64_t)NY * gn[2]);
         v = r[(int64_t)c * n_dof + node * NC + row % NC];
       }
-      if (row < npad) tj[(int64_t)row * MC_K + c] = v;
       sR[rr][c] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < RC * MC_K; e += 256) {
+      const int rr = e / MC_K, c = e % MC_K, row = r0 + rr;
+      if (row < npad) tj[(int64_t)row * MC_K + c] = sR[rr][c];
     }
     if (m > 0) {
       for (int e = threadIdx.x; e < RC * m; e += 256) {
