@@ -207,6 +207,12 @@ typedef struct gn_solve_opts {
                            for the whole batch, per-column alpha, beta and
                            stopping); 1 = the columns are solved one after
                            another.  Ignored for nrhs = 1.                      */
+  int32_t graphs;       /* single-column solves: 1 = each chunk of check_every
+                           iterations is replayed from a HIP graph captured on
+                           first use (kept with the preconditioner, or with the
+                           problem for plain CG, until destroyed); 0 = kernel
+                           by kernel.  Same arithmetic either way.  Not used
+                           while kernel profiling (gn_profile_enable) is on.    */
 } gn_solve_opts;
 
 typedef struct gn_solve_report {

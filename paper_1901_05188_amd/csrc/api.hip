@@ -1162,24 +1162,66 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
     gnk::copy(n, p->d_p, p->d_z, done, s);
     double hs[16];
     int iters = 0;
+    // one chunk of iterations; kernels of finished solves return at once
+    auto launch_chunk = [&](hipStream_t st) {
+      for (int k = 0; k < chunk; ++k) {
+        gnk::spmv_flag(p, p->d_p, p->d_q, p->d_part, done, st);
+        gnk::finalize(p->d_part, nbs, OP_ALPHA, scal, p->d_hist, opts->rtol, st);
+        gnk::update_xr(n, p->d_x, p->d_r, p->d_p, p->d_q, scal, p->d_part, st);
+        gnk::finalize(p->d_part, nbr, OP_RR, scal, p->d_hist, opts->rtol, st);
+        if (pc) {
+          precond_full(p, pc, p->d_r, p->d_z, p->d_part, done, st);
+          gnk::finalize(p->d_part, nbp, OP_BETA, scal, p->d_hist, opts->rtol, st);
+        } else {
+          gnk::copy(n, p->d_z, p->d_r, done, st);
+          gnk::dot_partial(n, p->d_r, p->d_z, p->d_part, done, st);
+          gnk::finalize(p->d_part, nbr, OP_BETA, scal, p->d_hist, opts->rtol, st);
+        }
+        gnk::update_p(n, p->d_p, p->d_z, scal, st);
+      }
+    };
+    const bool use_graph = opts->graphs != 0 && !g_prof_on;
+    ChunkGraph& cg = pc ? pc->cg : p->cg;
+    auto run_chunk = [&]() {
+      if (!use_graph) {
+        launch_chunk(s);
+        return;
+      }
+      if (!cg.exec || cg.chunk != chunk || cg.hist != p->d_hist) {
+        // capture on a private stream (the caller's may be the null stream),
+        // replay on the caller's
+        cg.release();
+        hipStream_t cs = nullptr;
+        GN_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          try {
+            launch_chunk(cs);
+          } catch (...) {
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipStreamDestroy(cs);
+            throw;
+          }
+          e = hipStreamEndCapture(cs, &g);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&cg.exec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+          cg.exec = nullptr;
+          throw gn_error{GN_ERR_DEVICE, std::string("CG chunk graph capture: ") + hipGetErrorString(e)};
+        }
+        cg.chunk = chunk;
+        cg.hist = p->d_hist;
+      }
+      GN_HIP(hipGraphLaunch(cg.exec, s));
+    };
     auto iterate = [&]() {
       bool fin = false;
       while (!fin) {
-        for (int k = 0; k < chunk; ++k) {
-          gnk::spmv_flag(p, p->d_p, p->d_q, p->d_part, done, s);
-          gnk::finalize(p->d_part, nbs, OP_ALPHA, scal, p->d_hist, opts->rtol, s);
-          gnk::update_xr(n, p->d_x, p->d_r, p->d_p, p->d_q, scal, p->d_part, s);
-          gnk::finalize(p->d_part, nbr, OP_RR, scal, p->d_hist, opts->rtol, s);
-          if (pc) {
-            precond_full(p, pc, p->d_r, p->d_z, p->d_part, done, s);
-            gnk::finalize(p->d_part, nbp, OP_BETA, scal, p->d_hist, opts->rtol, s);
-          } else {
-            gnk::copy(n, p->d_z, p->d_r, done, s);
-            gnk::dot_partial(n, p->d_r, p->d_z, p->d_part, done, s);
-            gnk::finalize(p->d_part, nbr, OP_BETA, scal, p->d_hist, opts->rtol, s);
-          }
-          gnk::update_p(n, p->d_p, p->d_z, scal, s);
-        }
+        run_chunk();
         GN_HIP(hipMemcpyAsync(hs, scal, sizeof(double) * S_N, hipMemcpyDeviceToHost, s));
         GN_HIP(hipStreamSynchronize(s));
         iters = (int)hs[S_ITER];
@@ -1255,6 +1297,7 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
 extern "C" void gn_destroy_problem(gn_problem* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
+  p->cg.release();
   dfree_all(p->owned);
   delete p;
 }
@@ -1262,6 +1305,7 @@ extern "C" void gn_destroy_problem(gn_problem* p) {
 extern "C" void gn_destroy_precond(gn_precond* pc) {
   if (!pc) return;
   (void)hipDeviceSynchronize();
+  pc->cg.release();
   dfree_all(pc->owned);
   delete pc;
 }

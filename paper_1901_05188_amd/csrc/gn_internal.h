@@ -81,6 +81,20 @@ __host__ __device__ inline void box_global_node(const int lo[3], const int n[3],
 // ---------------------------------------------------------------------------
 // handles
 // ---------------------------------------------------------------------------
+// One chunk of CG iterations (check_every of them) captured as a HIP graph and
+// replayed by every later solve with the same chunk length and history buffer;
+// every kernel of the chunk reads its scalars from device memory, so the graph
+// holds no per-solve values.
+struct ChunkGraph {
+  hipGraphExec_t exec = nullptr;
+  int chunk = 0;
+  const double* hist = nullptr;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+  }
+};
+
 struct gn_problem {
   int pde = 0, nc = 1;
   int ne[3] = {0, 0, 0}, nn[3] = {0, 0, 0};
@@ -106,6 +120,7 @@ struct gn_problem {
   double *d_Xm = nullptr, *d_Rm = nullptr, *d_Pm = nullptr, *d_Qm = nullptr, *d_Zm = nullptr;
   double *d_partm = nullptr, *d_scalm = nullptr, *d_histm = nullptr;
   int histm_stride = 0, pstride_m = 0;
+  ChunkGraph cg;               // plain-CG chunk graph
   std::vector<void*> owned;
 };
 
@@ -148,6 +163,7 @@ struct gn_precond {
   std::vector<double> lam;   // eigenvalues per subdomain (n_eval each)
   std::vector<int> lam_n;
   int n_eval = 0;
+  ChunkGraph cg;               // PCG chunk graph of this preconditioner
   std::vector<void*> owned;
 };
 

@@ -289,3 +289,29 @@ def test_error_paths():
     x = torch.zeros_like(b)
     st, rep = gp.solve(p, None, b, x, rtol=1e-12, maxit=1)
     assert st == 1 and rep[0]["iters"] == 1 and rep[0]["converged"] == 0
+
+
+@pytest.mark.parametrize("name", ["lam_3x2x2_uneven", "diff_3x3x1"])
+def test_graph_replayed_chunks_match_eager_launches(name):
+    """CG chunks replayed from a captured HIP graph give the bits of the
+    kernel-by-kernel solve: several replays with eager work and synchronisation
+    in between, a second chunk length (a new capture), and plain CG."""
+    A, b, free, Ke = orc.system(name)
+    pc = precond(name)
+    p = pc.prob
+    bt = _t(b.T[:1])
+    ref = torch.zeros_like(bt)
+    st, rep0 = _gp().solve(p, pc, bt, ref, rtol=1e-10, maxit=2000, graphs=False)
+    y = torch.zeros_like(bt)
+    for chunk in (8, 8, 5, 8):
+        x = torch.zeros_like(bt)
+        st, rep = _gp().solve(p, pc, bt, x, rtol=1e-10, maxit=2000, check_every=chunk, graphs=True)
+        assert torch.equal(x, ref), chunk
+        assert rep[0]["iters"] == rep0[0]["iters"] and rep[0]["restarts"] == rep0[0]["restarts"]
+        p.matvec(x, y)                      # eager work between replays
+        torch.cuda.synchronize()
+    xe, xg = torch.zeros_like(bt), torch.zeros_like(bt)
+    _gp().solve(p, None, bt, xe, rtol=1e-10, maxit=20000, graphs=False)
+    _gp().solve(p, None, bt, xg, rtol=1e-10, maxit=20000, graphs=True)
+    _gp().solve(p, None, bt, xg, rtol=1e-10, maxit=20000, graphs=True)
+    assert torch.equal(xe, xg)
