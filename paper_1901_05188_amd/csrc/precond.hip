@@ -98,16 +98,19 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
   // Slots u < CW*w address band entries; the rest read a shared zero tile, so
   // every load is unconditional and the unrolled loops carry no branches.
   // ---- forward ----
+  // every slot address is a uniform tile pointer plus the thread's 32-bit offset
+  // inside the tile (one offset register for all slots)
+  const unsigned toff = (unsigned)((CW * gq) * TILE + i);
 #define GN_LOAD_FWD(K_, LV, DN)                                                          \
   {                                                                                      \
     const FT* rowp = Tb + (int64_t)(K_) * (w + 1) * TILE2;                               \
     _Pragma("unroll") for (int u = 0; u < SP; ++u) {                                     \
-      int t = u / CW, c = CW * gq + (u % CW);                                            \
-      const FT* src = (u < ns) ? rowp + (t * TILE + c) * TILE + i : Z0 + i;              \
-      LV[u] = *src;                                                                      \
+      const int t = u / CW, q = u % CW;                                                  \
+      const FT* tp = (u < ns) ? rowp + t * TILE2 : Z0;                                   \
+      LV[u] = tp[toff + (unsigned)(q * TILE)];                                           \
     }                                                                                    \
     const FT* dk = Db + (int64_t)(K_) * TILE2;                                           \
-    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[(CW * gq + q) * TILE + i]; \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[toff + (unsigned)(q * TILE)]; \
   }
 #define GN_STEP_FWD(K_, LV, DN)                                                          \
   {                                                                                      \
@@ -152,12 +155,12 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
   {                                                                                      \
     const FT* rowp = TBb + (int64_t)(K_) * (w + 1) * TILE2;                              \
     _Pragma("unroll") for (int u = 0; u < SP; ++u) {                                     \
-      int t = u / CW, rr = CW * gq + (u % CW);                                           \
-      const FT* src = (u < ns) ? rowp + (t * TILE + rr) * TILE + i : Z0 + i;             \
-      LV[u] = *src;                                                                      \
+      const int t = u / CW, q = u % CW;                                                  \
+      const FT* tp = (u < ns) ? rowp + t * TILE2 : Z0;                                   \
+      LV[u] = tp[toff + (unsigned)(q * TILE)];                                           \
     }                                                                                    \
     const FT* dk = rowp + (int64_t)w * TILE2;                                            \
-    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[(CW * gq + q) * TILE + i]; \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[toff + (unsigned)(q * TILE)]; \
   }
 #define GN_STEP_BWD(K_, LV, DN)                                                          \
   {                                                                                      \
@@ -306,46 +309,85 @@ namespace gnk {
 
 int max_lds_doubles() { return 18 * 1024; }
 
+namespace {
+// Launch shape of the single-column sweep: G column groups of TILE / G columns.
+// 512 threads (G = 16, two columns per thread and tile) while 2w slots fit the
+// registers; 1024 threads (G = 32, one column) for wider bands.
+struct PfShape {
+  int G, sp, padw;
+  bool ok;
+};
+PfShape pf_shape(const gn_precond* pc) {
+  PfShape sh{16, 0, 0, false};
+  if (pc->local_kernel == 1) return sh;
+  // register slots per buffer without spills: G = 16 (two columns per thread,
+  // up to 256 registers): 32; G = 32 (one column, 128 registers): 16 (FP64) /
+  // 32 (FP32)
+  for (int G : {16, 32}) {
+    const int spmax = (G == 32 && pc->local_prec != 32) ? 16 : 32;
+    const int sp = (TILE / G) * pc->maxwI;
+    if (sp > spmax) continue;
+    // the kernel's slot count: sp rounded up to an instantiated size
+    const int spt = sp <= 8 ? 8 : sp <= 12 ? 12 : sp <= 16 ? 16 : sp <= 20 ? 20 : sp <= 24 ? 24 : 32;
+    // zero tiles on both sides of the LDS vector cover every window read: the
+    // forward window starts w tiles before the row, the reads of the unused
+    // slots reach spt / (TILE / G) tiles past it
+    const int padw = pc->maxwI + spt / (TILE / G) + 1;
+    const int stat = 2 * G * (TILE + 1);     // doubles of the static reduction arrays
+    if ((pc->maxNBI + 2 * padw) * TILE + stat > 20 * 1024 - 64) continue;
+    sh.G = G;
+    sh.sp = sp;
+    sh.padw = padw;
+    sh.ok = true;
+    return sh;
+  }
+  return sh;
+}
+}  // namespace
+
 void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, const double* done,
                  hipStream_t s) {
   const bool f32 = pc->local_prec == 32;
   const double* Phi = pc->NH > 0 ? pc->d_Phi : nullptr;
   double bytes = pc->trsv_bytes;
   GnProfScope prof(PROF_TRSV, bytes, s);
-  constexpr int PF_G = 16;                       // 512 threads: 32 rows x 16 groups of 2 columns
-  const int need_sp = (TILE / PF_G) * pc->maxwI;
-  // zero tiles on both sides of the LDS vector: covers every window read, which
-  // reaches at most SP / 2 <= maxw + 16 tiles past either end
-  const int padw = pc->maxwI + 16;
-  if (pf_supported(p, pc)) {
+  const PfShape sh = pf_shape(pc);
+  if (sh.ok) {
     if (!pc->d_LIb) throw gn_error{GN_ERR_ARG, "backward band missing for the single-column sweep"};
+    const int need_sp = sh.sp, padw = sh.padw;
     size_t dynpf = (size_t)(pc->maxNBI + 2 * padw) * TILE * sizeof(double);
-#define GN_PF(FT, NC, SPV)                                                                        \
+#define GN_PF(FT, NC, SPV, GV)                                                                    \
   do {                                                                                            \
-    auto kfn = k_local_solve_pf<FT, NC, SPV, PF_G>;                                               \
+    auto kfn = k_local_solve_pf<FT, NC, SPV, GV>;                                                 \
     GN_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,      \
                                (int)dynpf));                                                      \
-    hipLaunchKernelGGL(kfn, dim3(pc->n_sub), dim3(32 * PF_G), dynpf, s, pc->d_sub, p->nn[0],       \
+    hipLaunchKernelGGL(kfn, dim3(pc->n_sub), dim3(32 * GV), dynpf, s, pc->d_sub, p->nn[0],         \
                        p->nn[1], r,                                                               \
                        (const FT*)(f32 ? (const void*)pc->d_LIf : (const void*)pc->d_LI),         \
                        (const FT*)(f32 ? (const void*)pc->d_DIf : (const void*)pc->d_DI),         \
                        (const FT*)pc->d_LIb, pc->d_t, Phi, pc->d_g, done, padw,                   \
                        (const FT*)(f32 ? (const void*)pc->d_zf : (const void*)pc->d_z0));         \
   } while (0)
-#define GN_PF_SP(FT, NC)                                  \
+#define GN_PF_SP(FT, NC, GV)                              \
   do {                                                    \
-    if (need_sp <= 8) GN_PF(FT, NC, 8);                   \
-    else if (need_sp <= 12) GN_PF(FT, NC, 12);            \
-    else if (need_sp <= 16) GN_PF(FT, NC, 16);            \
-    else if (need_sp <= 20) GN_PF(FT, NC, 20);            \
-    else if (need_sp <= 24) GN_PF(FT, NC, 24);            \
-    else GN_PF(FT, NC, 32);                               \
+    if (need_sp <= 8) GN_PF(FT, NC, 8, GV);               \
+    else if (need_sp <= 12) GN_PF(FT, NC, 12, GV);        \
+    else if (need_sp <= 16) GN_PF(FT, NC, 16, GV);        \
+    else if (need_sp <= 20) GN_PF(FT, NC, 20, GV);        \
+    else if (need_sp <= 24) GN_PF(FT, NC, 24, GV);        \
+    else GN_PF(FT, NC, 32, GV);                           \
+  } while (0)
+#define GN_PF_G(FT, NC)                                   \
+  do {                                                    \
+    if (sh.G == 16) GN_PF_SP(FT, NC, 16);                 \
+    else GN_PF_SP(FT, NC, 32);                            \
   } while (0)
     if (f32) {
-      if (p->nc == 3) GN_PF_SP(float, 3); else GN_PF_SP(float, 1);
+      if (p->nc == 3) GN_PF_G(float, 3); else GN_PF_G(float, 1);
     } else {
-      if (p->nc == 3) GN_PF_SP(double, 3); else GN_PF_SP(double, 1);   // SP <= 20 here
+      if (p->nc == 3) GN_PF_G(double, 3); else GN_PF_G(double, 1);
     }
+#undef GN_PF_G
 #undef GN_PF_SP
 #undef GN_PF
     GN_CHECK_LAUNCH();
@@ -356,13 +398,7 @@ void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, con
 
 bool pf_supported(const gn_problem* p, const gn_precond* pc) {
   (void)p;
-  if (pc->local_kernel == 1) return false;
-  constexpr int PF_G = 16;
-  const int need_sp = (TILE / PF_G) * pc->maxwI;
-  const int padw = pc->maxwI + 16;
-  // two register buffers of SP slots: spill-free up to SP = 20 (FP64) / 32 (FP32)
-  const int spmax = pc->local_prec == 32 ? 32 : 20;
-  return (pc->maxNBI + 2 * padw) * TILE <= max_lds_doubles() && need_sp <= spmax;
+  return pf_shape(pc).ok;
 }
 
 void coarse_solve(const gn_precond* pc, const double* done, hipStream_t s) {
