@@ -143,8 +143,10 @@ gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t n
  * below 1.5 x threshold, and the first one past the selection, which only fix
  * m_j through their eigenvalues) have it below sqrt(eig_tol), or when the
  * residual stays below 1e-9 without halving over 15 block solves.
- * eig_block is the subspace block size.  0 = automatic: nev + max(8, nev/2)
- * (at most 64) for a fixed nev; for a threshold min(32, nev_max + 8), grown by
+ * eig_block is the subspace block size.  0 = automatic: max(32, nev + max(8,
+ * nev/2)) (at most 64, and at most the smallest pencil's row count unless that
+ * is below nev + max(8, nev/2)) for a fixed nev; for a threshold
+ * min(32, nev_max + 8), grown by
  * 16 up to 64 and the eigensolve repeated while the eigenvalues below
  * 1.5 x threshold (plus 4 guard vectors) do not fit.  A given value must lie
  * in [nev + 5 (or 5), 64]; if it proves too small, GN_ERR_EIG_NOCONV.
