@@ -154,3 +154,17 @@ def test_coarse_spaces_order_like_the_example_1b_table():
         u, info = pcg.pcg(A, b[:, 0], g.apply, rtol=1e-5, maxit=2000)
         its[name] = info["iters"]
     assert its["as"] > its["zem"] > its["geneo"], its
+
+
+def test_zem_dimensions_match_the_example_1b_table():
+    """The oracle's ZEM coarse space on the Example 1 plate has the coarse
+    dimensions the paper prints for N = 4, 8, 16, 32 (tests/golden fixture)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "example1b_zem_coarse_dims.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    for N, px, py, dim in [[int(v) for v in r] for r in rows]:
+        w = gen.example1b_plate((px, py, 1), nxy=(16, 4))
+        assert w.n_sub == N
+        d = dd.Decomposition(w)
+        got = sum(geneo.zem_basis(w, d, j).shape[1] for j in range(w.n_sub))
+        assert got == dim, (N, got, dim)
