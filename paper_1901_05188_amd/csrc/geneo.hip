@@ -286,22 +286,27 @@ __device__ inline void geneo_lds_barrier() {
 }
 
 template <int W, int P, int S>
-__global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ subs, int b, int ringlen,
-                                                   const double* __restrict__ T, const double* __restrict__ D,
-                                                   const double* __restrict__ TBk,
+__global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ subs, int n_sub, int csplit, int b,
+                                                   int ringlen, const double* __restrict__ T,
+                                                   const double* __restrict__ D, const double* __restrict__ TBk,
                                                    const double* __restrict__ Z0, double* __restrict__ V) {
   static_assert(W % S == 0 && (W / S) % P == 0, "W / S must be a multiple of the prefetch depth");
   constexpr int WS = W / S;                 // tile slots per wave and step
   extern __shared__ double smem[];
-  double* ring = smem;                      // W1 slots x TILE rows x b columns (+16 pad)
-  const SubDesc& sd = subs[blockIdx.x];
+  double* ring = smem;                      // W1 slots x TILE rows x RW columns (+16 pad)
+  // csplit = 1: one workgroup takes all b columns of its subdomain; csplit > 1:
+  // workgroup g takes the 16 columns 16 g .. 16 g + 15 (the solves of different
+  // columns are independent; siblings are n_sub workgroups apart)
+  const SubDesc& sd = subs[blockIdx.x % n_sub];
+  const int c0 = csplit > 1 ? (int)(blockIdx.x / n_sub) * 16 : 0;
+  const int RW = csplit > 1 ? 16 : b;       // columns held in the ring
   const int NB = sd.NBB, w = sd.wB, W1 = w + 1;
   const double* Tb = T + sd.offTB * TILE2;
   const double* Db = D + sd.offDB * TILE2;
   double* Vb = V + sd.offVB * b;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int ncb = (b + 15) / 16;
+  const int ncb = csplit > 1 ? 1 : (b + 15) / 16;
   const int half = wv / (2 * ncb);          // tile parity handled by this wave (S = 2)
   const int rem = wv % (2 * ncb);
   const int rh = rem & 1, cb = rem >> 1;
@@ -309,7 +314,8 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
   double* sP = smem + ringlen + (ncb + cb) * (TILE * 17);       // partial of the odd tiles
   const int lr = lane & 15, lk = lane >> 4;
   const int rb = rh * 16;
-  const int col = cb * 16 + lr;
+  const int lcol = cb * 16 + lr;            // column in the ring
+  const int col = c0 + lcol;                // column of V
   const bool ok = col < b;
   const int nthr = blockDim.x;
   for (int e = threadIdx.x; e < ringlen; e += nthr) ring[e] = 0.0;
@@ -335,8 +341,8 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
   for (int sl = 0; sl < P; ++sl) TR_LOAD_A_FWD(sl, 0, S * sl + half)
   if (half == 0) TR_LOAD_DV_FWD(0)
   __syncthreads();
-  const int rstride = TILE * b;
-  const int lofs = lk * b + col;
+  const int rstride = TILE * RW;
+  const int lofs = lk * RW + lcol;
   for (int K = 0; K < NB; ++K) {
     TR_ZERO()
     // ring slot of tile t: block K - w + t; the B operands of tile t + 1 are
@@ -344,7 +350,7 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
     int slot = (K + 1 + half) % W1;   // (K - w + half + W1) mod W1
     double bcur[8], bnxt[8];
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
+    for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * RW + lofs];
 #pragma unroll
     for (int m = 0; m < WS; ++m) {
       const int sl = m % P;
@@ -354,7 +360,7 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
         slot += S;
         while (slot >= W1) slot -= W1;
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
+        for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * RW + lofs];
       }
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks)
@@ -391,13 +397,13 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks)
       acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dcur[ks], sS[(4 * ks + lk) * 17 + lr], acc[ks & 3], 0, 0, 0);
-    double* yk = ring + (K % W1) * (TILE * b);
+    double* yk = ring + (K % W1) * (TILE * RW);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = rb + 4 * i + lk;
       const double y = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
       if (ok && half == 0) {
-        yk[row * b + col] = y;
+        yk[row * RW + lcol] = y;
         Vb[(int64_t)(K * TILE + row) * b + col] = y;
       }
     }
@@ -434,7 +440,7 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
     int slot = (K + 1 + half) % W1;   // ring slot of tile t: block K + 1 + t
     double bcur[8], bnxt[8];
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
+    for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * RW + lofs];
 #pragma unroll
     for (int m = 0; m < WS; ++m) {
       const int sl = m % P;
@@ -444,7 +450,7 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
         slot += S;
         while (slot >= W1) slot -= W1;
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * b + lofs];
+        for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * RW + lofs];
       }
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks)
@@ -481,13 +487,13 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks)
       acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dcur[ks], sS[(4 * ks + lk) * 17 + lr], acc[ks & 3], 0, 0, 0);
-    double* xk = ring + (K % W1) * (TILE * b);
+    double* xk = ring + (K % W1) * (TILE * RW);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = rb + 4 * i + lk;
       const double x = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
       if (ok && half == 0) {
-        xk[row * b + col] = x;
+        xk[row * RW + lcol] = x;
         Vb[(int64_t)(K * TILE + row) * b + col] = x;
       }
     }
@@ -1316,11 +1322,19 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
   if (b > 64) throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
   int maxw = 0;
   for (const SubDesc& sd : pc->sub) maxw = std::max(maxw, sd.wB);
-  const int ncb = (b + 15) / 16;
-  const int ringlen = (maxw + 1) * TILE * b + 16;
+  // one workgroup per subdomain for all b columns when its ring fits in LDS,
+  // else one per subdomain and 16-column block
+  int ncb = (b + 15) / 16, csplit = 1;
+  int ringlen = (maxw + 1) * TILE * b + 16;
+  size_t lds = sizeof(double) * ((size_t)ringlen + (size_t)2 * ncb * TILE * 17);
+  if (lds > 160 * 1024 && ncb > 1) {
+    csplit = ncb;
+    ncb = 1;
+    ringlen = (maxw + 1) * TILE * 16 + 16;
+    lds = sizeof(double) * ((size_t)ringlen + (size_t)2 * TILE * 17);
+  }
   // two waves per (row half, column block) splitting the tiles when they fit in 512 threads
   const int split = ncb <= 2 ? 2 : 1;
-  const size_t lds = sizeof(double) * ((size_t)ringlen + (size_t)2 * ncb * TILE * 17);
   // tile slots per step: the smallest multiple of the prefetch depth (6) >= w
   const int W = std::max(6, (maxw + 5) / 6 * 6);
   if (lds <= 160 * 1024 && W <= 30 && pc->d_z0 && TB) {
@@ -1328,8 +1342,8 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
   do {                                                                                               \
     GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV, PV, SV>,                                 \
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));               \
-    hipLaunchKernelGGL((k_trsm_ring<WV, PV, SV>), dim3(pc->n_sub), dim3(128 * ncb * SV), lds, s, pc->d_sub, b, \
-                       ringlen, T, D, TB, pc->d_z0, V);                                              \
+    hipLaunchKernelGGL((k_trsm_ring<WV, PV, SV>), dim3(pc->n_sub * csplit), dim3(128 * ncb * SV), lds, s,  \
+                       pc->d_sub, pc->n_sub, csplit, b, ringlen, T, D, TB, pc->d_z0, V);            \
   } while (0)
 #define GN_TR(WV)                                   \
   do {                                              \
