@@ -680,6 +680,72 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
       std::vector<double> h_coef((size_t)n_sub * ncoef, 0.0);
       std::vector<int> solves_hist;
       int solves = 0;
+      // convergence of the Ritz pairs pnu whose residuals are in h_res
+      auto check = [&](const std::vector<double>& pnu) -> bool {
+        bool all = true;
+        block_short = false;
+        double worst = 0.0;          // largest scaled residual over the wanted pairs
+        double strict_worst = 0.0;   // largest relative residual of the coarse-space pairs
+        for (int j = 0; j < n_sub; ++j) {
+          // wanted pairs: nev+1 (fixed) or those below 1.5*threshold plus one (capped)
+          int nw;
+          if (fixed) {
+            nw = std::min(b - guard / 2, o->nev + 1);
+          } else {
+            nw = 0;
+            for (int k = 0; k < b; ++k) {
+              double nk = pnu[(size_t)j * b + k];
+              double lam = nk > 0 ? 1.0 / nk - shift : 1e300;
+              if (lam < 1.5 * o->threshold) nw = k + 1;
+            }
+            if (std::min(nw + 1, o->nev_max + 1) > b - guard / 2) block_short = true;
+            nw = std::min(std::min(nw + 1, o->nev_max + 1), b - guard / 2);
+          }
+          nwant[j] = nw;
+          // pairs whose eigenvectors enter the coarse space (m_j of them, with a
+          // generous cluster margin) need the full residual tolerance; the others
+          // only decide m_j through their eigenvalues, whose error is of the order
+          // of the squared residual, so sqrt(eig_tol) suffices for them
+          auto lam_of = [&](int k) {
+            double nk = pnu[(size_t)j * b + k];
+            return nk > 0 ? 1.0 / nk - shift : 1e300;
+          };
+          int nin = 0;
+          if (fixed) {
+            nin = std::min(o->nev, nw);
+          } else {
+            while (nin < nw && lam_of(nin) < o->threshold) ++nin;
+            nin = std::min(nin, o->nev_max);
+          }
+          while (nin > 0 && nin < nw && lam_of(nin) - lam_of(nin - 1) <= 1e-6 * std::fabs(lam_of(nin - 1)) + 1e-8)
+            ++nin;
+          for (int k = 0; k < nw; ++k) {
+            double nk = pnu[(size_t)j * b + k];
+            double rs = h_res[(size_t)j * 2 * b + k], zz = h_res[(size_t)j * 2 * b + b + k];
+            if (nk <= 1e-12 / shift) continue;      // null space of B: lambda = inf
+            double rel = zz > 0 ? std::sqrt(rs / zz) : 0.0;
+            // scaled so that the tolerance of every pair reads as eig_tol
+            const double scaled = k < nin ? rel : rel * (eig_tol / std::sqrt(eig_tol));
+            if (!(scaled <= eig_tol)) all = false;
+            if (!(scaled <= worst)) worst = std::isfinite(scaled) ? std::max(worst, scaled) : 1e300;
+            if (k < nin && std::isfinite(rel)) strict_worst = std::max(strict_worst, rel);
+          }
+        }
+        worst_hist.push_back(worst);
+        solves_hist.push_back(solves);
+        eig_resid = strict_worst;
+        // accept a residual that has reached the rounding floor: no halving over
+        // the last 15 block solves once it is below 1e-9
+        bool stagnated = false;
+        if (solves > 20 && worst <= 1e-9) {
+          for (size_t q = worst_hist.size(); q-- > 0;)
+            if (solves_hist[q] <= solves - 15) {
+              stagnated = worst > 0.5 * worst_hist[q];
+              break;
+            }
+        }
+        return all || stagnated;
+      };
       for (int it = 0; it < eig_maxit; ++it) {
         const int d = std::min(dmax, it + 1);
         // Z = T V = P^-1 B V
@@ -713,6 +779,17 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
           GN_HIP(hipMemcpyAsync(d_coef, h_coef.data(), sizeof(double) * h_coef.size(), hipMemcpyHostToDevice, s));
           // Y1 = a1 (Z - c V), with the Ritz residuals of the current block
           gnk::eig_cheb_first(pc, b, Z, V, nu, d_coef, ncoef, A1, resp, s);
+          // Z = T V gives the residuals of the current pairs (those of the last
+          // Rayleigh-Ritz step): stop here when they have converged
+          gnk::eig_resid_sum(n_sub, b, resp, res, s);
+          GN_HIP(hipMemcpyAsync(h_res.data(), res, sizeof(double) * h_res.size(), hipMemcpyDeviceToHost, s));
+          GN_HIP(hipStreamSynchronize(s));
+          eig_solves = solves_prev + solves;
+          if (check(h_nu)) {
+            converged = true;
+            eig_iters = it;
+            break;
+          }
           double *Y0 = V, *BY0 = BV, *Yc = A1, *BYc = B1;
           gnk::eig_bapply(p, pc, BE, b, maxNBB, Yc, BYc, s);
           for (int i = 2; i < d; ++i) {
@@ -740,70 +817,8 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
         GN_HIP(hipStreamSynchronize(s));
         eig_iters = it + 1;
         eig_solves = solves_prev + solves;
-        if (it == 0) continue;
-        bool all = true;
-        block_short = false;
-        double worst = 0.0;          // largest scaled residual over the wanted pairs
-        double strict_worst = 0.0;   // largest relative residual of the coarse-space pairs
-        for (int j = 0; j < n_sub; ++j) {
-          // wanted pairs: nev+1 (fixed) or those below 1.5*threshold plus one (capped)
-          int nw;
-          if (fixed) {
-            nw = std::min(b - guard / 2, o->nev + 1);
-          } else {
-            nw = 0;
-            for (int k = 0; k < b; ++k) {
-              double nk = prev_nu[(size_t)j * b + k];
-              double lam = nk > 0 ? 1.0 / nk - shift : 1e300;
-              if (lam < 1.5 * o->threshold) nw = k + 1;
-            }
-            if (std::min(nw + 1, o->nev_max + 1) > b - guard / 2) block_short = true;
-            nw = std::min(std::min(nw + 1, o->nev_max + 1), b - guard / 2);
-          }
-          nwant[j] = nw;
-          // pairs whose eigenvectors enter the coarse space (m_j of them, with a
-          // generous cluster margin) need the full residual tolerance; the others
-          // only decide m_j through their eigenvalues, whose error is of the order
-          // of the squared residual, so sqrt(eig_tol) suffices for them
-          auto lam_of = [&](int k) {
-            double nk = prev_nu[(size_t)j * b + k];
-            return nk > 0 ? 1.0 / nk - shift : 1e300;
-          };
-          int nin = 0;
-          if (fixed) {
-            nin = std::min(o->nev, nw);
-          } else {
-            while (nin < nw && lam_of(nin) < o->threshold) ++nin;
-            nin = std::min(nin, o->nev_max);
-          }
-          while (nin > 0 && nin < nw && lam_of(nin) - lam_of(nin - 1) <= 1e-6 * std::fabs(lam_of(nin - 1)) + 1e-8)
-            ++nin;
-          for (int k = 0; k < nw; ++k) {
-            double nk = prev_nu[(size_t)j * b + k];
-            double rs = h_res[(size_t)j * 2 * b + k], zz = h_res[(size_t)j * 2 * b + b + k];
-            if (nk <= 1e-12 / shift) continue;      // null space of B: lambda = inf
-            double rel = zz > 0 ? std::sqrt(rs / zz) : 0.0;
-            // scaled so that the tolerance of every pair reads as eig_tol
-            const double scaled = k < nin ? rel : rel * (eig_tol / std::sqrt(eig_tol));
-            if (!(scaled <= eig_tol)) all = false;
-            if (!(scaled <= worst)) worst = std::isfinite(scaled) ? std::max(worst, scaled) : 1e300;
-            if (k < nin && std::isfinite(rel)) strict_worst = std::max(strict_worst, rel);
-          }
-        }
-        worst_hist.push_back(worst);
-        solves_hist.push_back(solves);
-        eig_resid = strict_worst;
-        // accept a residual that has reached the rounding floor: no halving over
-        // the last 15 block solves once it is below 1e-9
-        bool stagnated = false;
-        if (solves > 20 && worst <= 1e-9) {
-          for (size_t q = worst_hist.size(); q-- > 0;)
-            if (solves_hist[q] <= solves - 15) {
-              stagnated = worst > 0.5 * worst_hist[q];
-              break;
-            }
-        }
-        if (all || stagnated) {
+        if (it == 0 || d > 1) continue;   // filtered steps check right after their first solve
+        if (check(prev_nu)) {
           converged = true;
           break;
         }

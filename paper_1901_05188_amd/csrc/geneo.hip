@@ -953,6 +953,17 @@ __global__ __launch_bounds__(NT) void k_zem_modes(const SubDesc* __restrict__ su
   out[5] = c == 0 ? -d1 : (c == 1 ? d0 : 0.0);
 }
 
+// Ritz residual sums of one subdomain: the GRAM_SPLIT row-split partials added
+// in fixed order (the same sums k_small_eig forms)
+__global__ void k_resid_sum(int b, const double* __restrict__ resp, double* __restrict__ res) {
+  const double* rp = resp + (int64_t)blockIdx.x * GRAM_SPLIT * 2 * b;
+  for (int e = threadIdx.x; e < 2 * b; e += blockDim.x) {
+    double t = 0.0;
+    for (int g = 0; g < GRAM_SPLIT; ++g) t += rp[g * 2 * b + e];
+    res[(int64_t)blockIdx.x * 2 * b + e] = t;
+  }
+}
+
 // deterministic start block: hash of (subdomain, row, col) -> (-1, 1); zero on padding
 __global__ void k_vinit(const SubDesc* __restrict__ subs, int b, double* __restrict__ V) {
   const SubDesc& sd = subs[blockIdx.y];
@@ -1277,6 +1288,11 @@ static PouAx pou_axes(const gn_precond* pc) {
 void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s) {
   hipLaunchKernelGGL(k_vinit, dim3((maxNBB * TILE + NT - 1) / NT, pc->n_sub), dim3(NT), 0, s,
                      pc->d_sub, b, V);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_resid_sum(int n_sub, int b, const double* resp, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(k_resid_sum, dim3(n_sub), dim3(128), 0, s, b, resp, res);
   GN_CHECK_LAUNCH();
 }
 

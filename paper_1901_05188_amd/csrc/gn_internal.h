@@ -249,6 +249,7 @@ void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const
                  const double* Y, double* V, double* BV, hipStream_t s);
 void eig_normalise(const gn_precond* pc, int b, int ncol, double* V, hipStream_t s);
 void zem_modes(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s);
+void eig_resid_sum(int n_sub, int b, const double* resp, double* res, hipStream_t s);
 void build_phi(const gn_problem* p, const gn_precond* pc, int b, int maxNI, const double* V,
                hipStream_t s);
 void aphi(const gn_problem* p, const gn_precond* pc, int b, int maxNB, double* Y, hipStream_t s);
