@@ -749,8 +749,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
       for (int it = 0; it < eig_maxit; ++it) {
         const int d = std::min(dmax, it + 1);
         // Z = T V = P^-1 B V
-        GN_HIP(hipMemcpyAsync(Z, BV, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
-        gnk::eig_trsm(pc, b, LB, DB, TBB, Z, s);
+        gnk::eig_trsm(pc, b, LB, DB, TBB, BV, Z, s);
         ++solves;
         if (d == 1) {
           // Rayleigh-Ritz on span(Z): P Z = B V, so Z^T P Z = Z^T (B V)
@@ -793,8 +792,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
           double *Y0 = V, *BY0 = BV, *Yc = A1, *BYc = B1;
           gnk::eig_bapply(p, pc, BE, b, maxNBB, Yc, BYc, s);
           for (int i = 2; i < d; ++i) {
-            GN_HIP(hipMemcpyAsync(Z, BYc, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
-            gnk::eig_trsm(pc, b, LB, DB, TBB, Z, s);
+            gnk::eig_trsm(pc, b, LB, DB, TBB, BYc, Z, s);
             ++solves;
             gnk::eig_cheb_step(pc, b, maxNBB, Z, Yc, Y0, d_coef, ncoef, i - 2, s);   // Y0 <- Y_i
             gnk::eig_bapply(p, pc, BE, b, maxNBB, Y0, BY0, s);
@@ -802,8 +800,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
             std::swap(BY0, BYc);
           }
           // W = T Y_{d-1}: Rayleigh-Ritz on span(W) with P W = B Y_{d-1}
-          GN_HIP(hipMemcpyAsync(Z, BYc, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
-          gnk::eig_trsm(pc, b, LB, DB, TBB, Z, s);
+          gnk::eig_trsm(pc, b, LB, DB, TBB, BYc, Z, s);
           ++solves;
           gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
           gnk::eig_gram(pc, b, Z, BYc, BZ, nullptr, nullptr, GP, GB, nullptr, s);

@@ -289,7 +289,7 @@ template <int W, int P, int S>
 __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ subs, int n_sub, int csplit, int b,
                                                    int ringlen, const double* __restrict__ T,
                                                    const double* __restrict__ D, const double* __restrict__ TBk,
-                                                   const double* __restrict__ Z0, double* __restrict__ V) {
+                                                   const double* __restrict__ Z0, const double* Vin, double* V) {
   static_assert(W % S == 0 && (W / S) % P == 0, "W / S must be a multiple of the prefetch depth");
   constexpr int WS = W / S;                 // tile slots per wave and step
   extern __shared__ double smem[];
@@ -303,7 +303,8 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
   const int NB = sd.NBB, w = sd.wB, W1 = w + 1;
   const double* Tb = T + sd.offTB * TILE2;
   const double* Db = D + sd.offDB * TILE2;
-  double* Vb = V + sd.offVB * b;
+  double* Vb = V + sd.offVB * b;            // solution (may be Vin: in place)
+  const double* Vi = Vin + sd.offVB * b;    // right-hand sides
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ncb = csplit > 1 ? 1 : (b + 15) / 16;
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
     const double* dk = Db + (int64_t)(K_) * TILE2;                                             \
     _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dv[ks] = dk[(4 * ks + lk) * TILE + rb + lr]; \
     _Pragma("unroll") for (int i = 0; i < 4; ++i)                                              \
-      vv[i] = Vb[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + col];                           \
+      vv[i] = Vi[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + col];                           \
   }
 #pragma unroll
   for (int sl = 0; sl < P; ++sl) TR_LOAD_A_FWD(sl, 0, S * sl + half)
@@ -1333,8 +1334,8 @@ void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int
   GN_CHECK_LAUNCH();
 }
 
-void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, const double* TB, double* V,
-              hipStream_t s) {
+void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, const double* TB, const double* Vin,
+              double* V, hipStream_t s) {
   if (b > 64) throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
   int maxw = 0;
   for (const SubDesc& sd : pc->sub) maxw = std::max(maxw, sd.wB);
@@ -1359,7 +1360,7 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
     GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV, PV, SV>,                                 \
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));               \
     hipLaunchKernelGGL((k_trsm_ring<WV, PV, SV>), dim3(pc->n_sub * csplit), dim3(128 * ncb * SV), lds, s,  \
-                       pc->d_sub, pc->n_sub, csplit, b, ringlen, T, D, TB, pc->d_z0, V);            \
+                       pc->d_sub, pc->n_sub, csplit, b, ringlen, T, D, TB, pc->d_z0, Vin, V);       \
   } while (0)
 #define GN_TR(WV)                                   \
   do {                                              \
@@ -1380,6 +1381,10 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
   }
   // one workgroup per subdomain, two waves (row halves) per 16-column block: the
   // waves of a row half read the same band tiles, so each tile leaves HBM once
+  // (in place: the right-hand sides are copied into V first)
+  size_t vlen = 0;
+  for (const SubDesc& sd : pc->sub) vlen = std::max(vlen, (size_t)(sd.offVB + (int64_t)sd.NBB * TILE) * b);
+  if (Vin != V) GN_HIP(hipMemcpyAsync(V, Vin, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_trsm_pencil, dim3(pc->n_sub), dim3(128 * ((b + 15) / 16)), 0, s, pc->d_sub, pc->n_sub, b,
                      T, D, V);
   GN_CHECK_LAUNCH();

@@ -234,8 +234,8 @@ void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s
 void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double* BE, hipStream_t s);
 void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int b, int maxNBB,
                 const double* V, double* out, hipStream_t s);
-void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, const double* TB, double* V,
-              hipStream_t s);
+void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, const double* TB, const double* Vin,
+              double* V, hipStream_t s);
 int gram_split();
 void eig_cheb_first(const gn_precond* pc, int b, const double* Z, const double* V, const double* nu,
                     const double* coef, int ncoef, double* Y1, double* resp, hipStream_t s);
