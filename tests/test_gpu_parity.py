@@ -11,6 +11,7 @@ import pytest
 
 from tests import oracle_runs as orc
 from oracle import pcg as opcg
+from workloads import generate as gen
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -315,3 +316,59 @@ def test_graph_replayed_chunks_match_eager_launches(name):
     _gp().solve(p, None, bt, xg, rtol=1e-10, maxit=20000, graphs=True)
     _gp().solve(p, None, bt, xg, rtol=1e-10, maxit=20000, graphs=True)
     assert torch.equal(xe, xg)
+
+
+def test_edge_cases_single_subdomain_thin_parts_zero_load_empty_coarse():
+    """Degenerate cases: one subdomain (M^-1 = A^-1: PCG converges in one step,
+    no coarse space), subdomains one element wide (overlap 1), a zero load
+    (x = 0 after no iteration), and a threshold no eigenvalue falls below
+    (N_H = 0 although a coarse space was asked for)."""
+    from oracle import dd, fem, geneo
+    gp = _gp()
+    # one subdomain
+    w = gen.small_case("laminate", seed=41, nxy=(6, 4), n_ply=2, nparts=(1, 1, 1), nev=4)
+    A, b, free = fem.assemble(w)
+    prob = gp.Problem.from_workload(w)
+    pc = gp.Preconditioner.from_workload(prob, w)
+    assert pc.report["coarse_dim"] == 0
+    bt = _t(b.T[:1])
+    x = torch.zeros_like(bt)
+    st, rep = gp.solve(prob, pc, bt, x, rtol=1e-12, maxit=100)
+    u = np.linalg.solve(A.toarray(), b[:, 0])
+    assert rep[0]["iters_first"] <= 2
+    assert np.linalg.norm(x[0].cpu().numpy() - u) <= 1e-10 * np.linalg.norm(u)
+    # zero load, single column
+    z0 = torch.zeros_like(bt)
+    xz = torch.ones_like(bt)
+    st, rep = gp.solve(prob, pc, z0, xz, rtol=1e-8, maxit=100)
+    assert st == 0 and rep[0]["iters"] == 0 and torch.count_nonzero(xz) == 0
+    pc.close()
+    prob.close()
+    # parts one element wide, uneven; and an empty coarse space
+    for cuts, thr in (([np.array([0, 1, 2, 6]), np.array([0, 3, 6]), np.array([0, 4])], 0.15),
+                      ([np.array([0, 6]), np.array([0, 3, 6]), np.array([0, 4])], 1e-9)):
+        rng = np.random.default_rng(7)
+        k = np.exp(rng.normal(0.0, 1.0, 6 * 6 * 4))
+        w = gen.diffusion_box((6, 6, 4), k, tuple(len(c) - 1 for c in cuts), cuts=cuts, overlap=1,
+                              threshold=thr, nev_max=8, dirichlet_faces=("x0",) if thr > 1e-6 else ("x0", "x1"))
+        Ke = fem.element_matrices(w)
+        A, b, free = fem.assemble(w, Ke)
+        g = geneo.GenEO(w, A, Ke)
+        prob = gp.Problem.from_workload(w)
+        pc = gp.Preconditioner.from_workload(prob, w)
+        assert pc.report["coarse_dim"] == g.NH
+        if thr < 1e-6:
+            assert g.NH == 0
+        r = np.random.default_rng(8).standard_normal(prob.n_free)
+        zt = torch.zeros((1, prob.n_free), dtype=torch.float64, device=DEV)
+        pc.apply(_t(r[None, :]), zt)
+        ref = g.apply(r)
+        assert np.linalg.norm(zt[0].cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+        u_ref, info = opcg.pcg(A, b[:, 0], g.apply, rtol=1e-12, maxit=500)
+        bt = _t(b.T[:1])
+        x = torch.zeros_like(bt)
+        st, rep = gp.solve(prob, pc, bt, x, rtol=1e-12, maxit=500)
+        assert np.linalg.norm(x[0].cpu().numpy() - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
+        assert abs(rep[0]["iters_first"] - info["iters"]) <= max(1, int(0.02 * info["iters"]))
+        pc.close()
+        prob.close()
