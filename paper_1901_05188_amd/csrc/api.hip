@@ -60,6 +60,39 @@ static T* upload(std::vector<void*>& owned, const T* h, size_t count, hipStream_
   GN_HIP(hipMemcpyAsync(d, h, count * sizeof(T), hipMemcpyHostToDevice, s));
   return d;
 }
+std::vector<int> gnh::xcd_order(const std::vector<int64_t>& weight) {
+  constexpr int X = 8;
+  const int n = (int)weight.size();
+  std::vector<int> byw(n);
+  for (int j = 0; j < n; ++j) byw[j] = j;
+  std::stable_sort(byw.begin(), byw.end(), [&](int a, int c) { return weight[a] > weight[c]; });
+  std::vector<std::vector<int>> on(X);
+  std::vector<int64_t> load(X, 0);
+  for (int j : byw) {
+    int best = -1;
+    for (int x = 0; x < X; ++x) {
+      const int cap = x < n ? (n - 1 - x) / X + 1 : 0;   // positions q < n with q % X == x
+      if ((int)on[x].size() < cap && (best < 0 || load[x] < load[best])) best = x;
+    }
+    on[best].push_back(j);
+    load[best] += weight[j];
+  }
+  std::vector<int> order(n);
+  for (int x = 0; x < X; ++x)
+    for (size_t i = 0; i < on[x].size(); ++i) order[i * X + x] = on[x][i];
+  return order;
+}
+// device copies of the descriptors: natural order and the two XCD-balanced orders
+static void upload_descs(gn_precond* pc, hipStream_t s) {
+  const int n = pc->n_sub;
+  for (int q = 0; q < n; ++q) {
+    pc->subxI[q] = pc->sub[pc->xorderI[q]];
+    pc->subxB[q] = pc->sub[pc->xorderB[q]];
+  }
+  GN_HIP(hipMemcpyAsync(pc->d_sub, pc->sub.data(), sizeof(SubDesc) * n, hipMemcpyHostToDevice, s));
+  GN_HIP(hipMemcpyAsync(pc->d_subxI, pc->subxI.data(), sizeof(SubDesc) * n, hipMemcpyHostToDevice, s));
+  GN_HIP(hipMemcpyAsync(pc->d_subxB, pc->subxB.data(), sizeof(SubDesc) * n, hipMemcpyHostToDevice, s));
+}
 double gnh::now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -511,6 +544,20 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   pc->maxNBI = maxNBI;
   pc->maxwI = maxw;
   pc->d_sub = upload(pc->owned, pc->sub.data(), pc->sub.size(), s);
+  {
+    std::vector<int64_t> wI(n_sub), wB(n_sub);
+    for (int j = 0; j < n_sub; ++j) {
+      wI[j] = (int64_t)pc->sub[j].NBI * (pc->sub[j].wI + 1);
+      wB[j] = (int64_t)pc->sub[j].NBB * (pc->sub[j].wB + 1);
+    }
+    pc->xorderI = gnh::xcd_order(wI);
+    pc->xorderB = gnh::xcd_order(wB);
+    pc->subxI.resize(n_sub);
+    pc->subxB.resize(n_sub);
+    pc->d_subxI = dalloc<SubDesc>(pc->owned, (size_t)std::max(n_sub, 1));
+    pc->d_subxB = dalloc<SubDesc>(pc->owned, (size_t)std::max(n_sub, 1));
+    upload_descs(pc, s);
+  }
   int* d_info = dalloc<int>(tmp, (size_t)std::max(n_sub, 1) + 64);
   GN_HIP(hipMemsetAsync(d_info, 0, sizeof(int) * (n_sub + 64), s));
   std::vector<int> info(n_sub + 64);
@@ -595,7 +642,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
       V = dalloc<double>(tmp, vlen + 64);
       Z = dalloc<double>(tmp, vlen + 64);
       GN_HIP(hipMemsetAsync(V, 0, sizeof(double) * (vlen + 64), s));
-      GN_HIP(hipMemcpyAsync(pc->d_sub, pc->sub.data(), sizeof(SubDesc) * n_sub, hipMemcpyHostToDevice, s));
+      upload_descs(pc, s);
       gnk::zem_modes(p, pc, b, maxNBB, V, s);
       if (maxm > 0) gnk::eig_normalise(pc, b, maxm, V, s);
     } else {
@@ -878,7 +925,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
         phi += (int64_t)pc->sub[j].nI * pc->sub[j].m;
       }
       pc->phi_len = phi;
-      GN_HIP(hipMemcpyAsync(pc->d_sub, pc->sub.data(), sizeof(SubDesc) * n_sub, hipMemcpyHostToDevice, s));
+      upload_descs(pc, s);
       pc->d_Phi = dalloc<double>(pc->owned, (size_t)phi);
       gnk::build_phi(p, pc, b, maxNI, V, s);
       gnk::aphi(p, pc, b, maxNB_, Z, s);
@@ -927,7 +974,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     GN_HIP(hipStreamSynchronize(s));
     t3 = now_s();
   } else {
-    GN_HIP(hipMemcpyAsync(pc->d_sub, pc->sub.data(), sizeof(SubDesc) * n_sub, hipMemcpyHostToDevice, s));
+    upload_descs(pc, s);
   }
   GN_HIP(hipStreamSynchronize(s));
   dfree_all(tmp);

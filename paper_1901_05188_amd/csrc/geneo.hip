@@ -516,7 +516,7 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
 // Gram matrices (column blocks 0..3).  Padding rows are zero in Z, BV and BZ;
 // columns past b only feed output entries that are not stored.
 // ---------------------------------------------------------------------------
-constexpr int GRAM_SPLIT = 8;
+constexpr int GRAM_SPLIT = 32;
 
 __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, int b,
                                              const double* __restrict__ Z, const double* __restrict__ BV,
@@ -584,11 +584,24 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
   const double nk = lane < b ? nu[(int64_t)blockIdx.x * b + lane] : 0.0;
   double rs = 0.0, zz = 0.0;
   if (lane < b) {
-    for (int r = rlo + wid; r < min(rhi, sd.nB); r += 4) {
-      double z = Z[base + (int64_t)r * b + lane];
-      double d = z - nk * V[base + (int64_t)r * b + lane];
-      rs += d * d;
-      zz += z * z;
+    // four rows per step, all loads of a step issued first (rows in the same order)
+    const int rend = min(rhi, sd.nB);
+    for (int r = rlo + wid; r < rend; r += 16) {
+      double zr[4], vr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int rr = r + 4 * u;
+        zr[u] = rr < rend ? Z[base + (int64_t)rr * b + lane] : 0.0;
+        vr[u] = rr < rend ? V[base + (int64_t)rr * b + lane] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (r + 4 * u < rend) {
+          const double d = zr[u] - nk * vr[u];
+          rs += d * d;
+          zz += zr[u] * zr[u];
+        }
+      }
     }
   }
   sres[wid][lane] = rs;
@@ -620,6 +633,7 @@ __global__ __launch_bounds__(NT) void k_small_eig(int b, const double* __restric
   __shared__ int pp[32], qq[32];
   __shared__ int order[64];
   __shared__ double offn;
+  __shared__ double wred[NT / 64][2];
   const int tid = threadIdx.x;
   // sum the row-split partials of the Gram matrices and residuals (fixed order)
   {
@@ -732,14 +746,30 @@ __global__ __launch_bounds__(NT) void k_small_eig(int b, const double* __restric
   // cyclic Jacobi with round-robin pairing (b even: pad logic handles odd b)
   const int m = (b + 1) & ~1;   // players
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid == 0) {
+    {
+      // off-diagonal and diagonal squared norms: per-thread strided sums, then
+      // wave shuffles and the four wave partials in a fixed order
       double off = 0.0, dn = 0.0;
-      for (int k = 0; k < b; ++k)
-        for (int l = 0; l < b; ++l) {
-          double v = C[k * ld + l] * C[k * ld + l];
-          if (k == l) dn += v; else off += v;
-        }
-      offn = (off <= 1e-32 * dn) ? 1.0 : 0.0;
+      for (int e = tid; e < b * b; e += NT) {
+        const int k = e / b, l = e % b;
+        const double v = C[k * ld + l] * C[k * ld + l];
+        if (k == l) dn += v; else off += v;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        off += __shfl_xor(off, o);
+        dn += __shfl_xor(dn, o);
+      }
+      if ((tid & 63) == 0) {
+        wred[tid >> 6][0] = off;
+        wred[tid >> 6][1] = dn;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const double o4 = (wred[0][0] + wred[1][0]) + (wred[2][0] + wred[3][0]);
+        const double d4 = (wred[0][1] + wred[1][1]) + (wred[2][1] + wred[3][1]);
+        offn = (o4 <= 1e-32 * d4) ? 1.0 : 0.0;
+      }
     }
     __syncthreads();
     if (offn != 0.0) break;
@@ -818,36 +848,64 @@ __global__ __launch_bounds__(NT) void k_small_eig(int b, const double* __restric
 }
 
 // V = Z Y and BV = (B Z) Y (the B-image of the new block without another B
-// application): one workgroup per 16 rows of one subdomain (grid.y), Y and the
-// row blocks staged in LDS.
+// application) on FP64 matrix cores: each wave takes 16 rows of one subdomain
+// (grid.y) and all b columns, A operands straight from Z and BZ (16 rows x 4
+// columns per K-step, all K-steps loaded before the first product), B operands
+// from Y, staged in LDS once per workgroup (rows padded to b + 1 doubles, so
+// the four 16-lane groups of a read hit different banks).  Columns past b are
+// masked to zero on both operands, so no padding value enters a product.
+template <int KS, int CB>   // K-steps and 16-column blocks covered: 4 KS >= b, 16 CB >= b
 __global__ __launch_bounds__(NT) void k_vupdate(const SubDesc* __restrict__ subs, int b,
                                                 const double* __restrict__ Z, const double* __restrict__ BZ,
                                                 const double* __restrict__ Y, double* __restrict__ V,
                                                 double* __restrict__ BV) {
-  constexpr int R = 16;
-  __shared__ double sY[64][64 + 1];
-  __shared__ double sZ[R][64 + 1], sB[R][64 + 1];
+  __shared__ double sY[64 * 65];
   const SubDesc& sd = subs[blockIdx.y];
-  const int r0 = blockIdx.x * R;
-  if (r0 >= sd.NBB * TILE) return;
+  const int nrow = sd.NBB * TILE;           // padded row counts are multiples of 32
+  if (blockIdx.x * (NT / 64) * 16 >= nrow) return;   // the whole workgroup, before the barrier
+  const int ldy = b + 1;
   const double* Yb = Y + (int64_t)blockIdx.y * b * b;
-  for (int e = threadIdx.x; e < b * b; e += NT) sY[e / b][e % b] = Yb[e];
-  const int64_t base = sd.offVB * b + (int64_t)r0 * b;
-  for (int e = threadIdx.x; e < R * b; e += NT) {
-    sZ[e / b][e % b] = Z[base + e];
-    sB[e / b][e % b] = BZ[base + e];
-  }
+  for (int e = threadIdx.x; e < b * b; e += NT) sY[(e / b) * ldy + e % b] = Yb[e];
   __syncthreads();
-  for (int e = threadIdx.x; e < R * b; e += NT) {
-    int rr = e / b, l = e % b;
-    double s1 = 0.0, s2 = 0.0;
-    for (int k = 0; k < b; ++k) {
-      double y = sY[k][l];
-      s1 += sZ[rr][k] * y;
-      s2 += sB[rr][k] * y;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r0 = (blockIdx.x * (NT / 64) + wv) * 16;
+  if (r0 >= nrow) return;                   // no barrier follows
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t arow = sd.offVB * b + (int64_t)(r0 + lr) * b;
+  double za[KS], ba[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = 4 * ks + lk;
+    za[ks] = k < b ? Z[arow + k] : 0.0;
+    ba[ks] = k < b ? BZ[arow + k] : 0.0;
+  }
+  gn_d4 az[CB], ab[CB];
+#pragma unroll
+  for (int q = 0; q < CB; ++q) az[q] = ab[q] = gn_d4{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = 4 * ks + lk;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      const int c = q * 16 + lr;
+      const double y = (k < b && c < b) ? sY[k * ldy + c] : 0.0;
+      az[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(za[ks], y, az[q], 0, 0, 0);
+      ab[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ba[ks], y, ab[q], 0, 0, 0);
     }
-    V[base + e] = s1;
-    BV[base + e] = s2;
+  }
+  const int64_t obase = sd.offVB * b + (int64_t)r0 * b;
+#pragma unroll
+  for (int q = 0; q < CB; ++q) {
+    const int c = q * 16 + lr;
+    if (c < b) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t o = obase + (int64_t)(4 * i + lk) * b + c;
+        V[o] = az[q][i];
+        BV[o] = ab[q][i];
+      }
+    }
   }
 }
 
@@ -878,14 +936,26 @@ __global__ __launch_bounds__(NT) void k_cheb_first(const SubDesc* __restrict__ s
   const double nk = lane < b ? nu[(int64_t)blockIdx.x * b + lane] : 0.0;
   double rs = 0.0, zz = 0.0;
   if (lane < b) {
-    for (int r = rlo + wid; r < rhi; r += 4) {
-      const double z = Z[base + (int64_t)r * b + lane];
-      const double v = V[base + (int64_t)r * b + lane];
-      Y1[base + (int64_t)r * b + lane] = a1 * (z - c * v);
-      if (r < sd.nB) {
-        const double d = z - nk * v;
-        rs += d * d;
-        zz += z * z;
+    // four rows per step, all loads of a step issued first (rows in the same order)
+    for (int r = rlo + wid; r < rhi; r += 16) {
+      double zr[4], vr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int rr = r + 4 * u;
+        zr[u] = rr < rhi ? Z[base + (int64_t)rr * b + lane] : 0.0;
+        vr[u] = rr < rhi ? V[base + (int64_t)rr * b + lane] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int rr = r + 4 * u;
+        if (rr < rhi) {
+          Y1[base + (int64_t)rr * b + lane] = a1 * (zr[u] - c * vr[u]);
+          if (rr < sd.nB) {
+            const double d = zr[u] - nk * vr[u];
+            rs += d * d;
+            zz += zr[u] * zr[u];
+          }
+        }
       }
     }
   }
@@ -981,44 +1051,35 @@ __global__ void k_vinit(const SubDesc* __restrict__ subs, int b, double* __restr
   }
 }
 
-// unit 2-norm, largest-magnitude entry positive (lowest index on ties), first ncol columns
+// unit 2-norm, largest-magnitude entry positive (lowest index on ties), first
+// ncol columns: one wave per column (grid.y blocks of NT / 64 columns), lanes
+// striding the rows, wave-wide shuffle reductions
 __global__ __launch_bounds__(NT) void k_normalise(const SubDesc* __restrict__ subs, int b, int ncol,
                                                   double* __restrict__ V) {
-  __shared__ double sh[16];
-  __shared__ double bestv[NT];
-  __shared__ int besti[NT];
   const SubDesc& sd = subs[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.y * (NT / 64) + (threadIdx.x >> 6);
+  if (k >= ncol) return;                    // wave-uniform, no barrier in this kernel
   double* Vb = V + sd.offVB * b;
-  for (int k = 0; k < ncol; ++k) {
-    double s = 0.0, mv = -1.0;
-    int mi = 0x7fffffff;
-    for (int r = threadIdx.x; r < sd.nB; r += NT) {
-      double v = Vb[(int64_t)r * b + k];
-      s += v * v;
-      double a = fabs(v);
-      if (a > mv) { mv = a; mi = r; }
-    }
-    double nrm2 = block_sum(s, sh);
-    bestv[threadIdx.x] = mv;
-    besti[threadIdx.x] = mi;
-    __syncthreads();
-    for (int off = NT / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) {
-        double a = bestv[threadIdx.x + off];
-        int ai = besti[threadIdx.x + off];
-        if (a > bestv[threadIdx.x] || (a == bestv[threadIdx.x] && ai < besti[threadIdx.x])) {
-          bestv[threadIdx.x] = a;
-          besti[threadIdx.x] = ai;
-        }
-      }
-      __syncthreads();
-    }
-    double sg = Vb[(int64_t)besti[0] * b + k] < 0.0 ? -1.0 : 1.0;
-    double scale = nrm2 > 0.0 ? sg / sqrt(nrm2) : 1.0;   // a zero column stays zero
-    __syncthreads();
-    for (int r = threadIdx.x; r < sd.nB; r += NT) Vb[(int64_t)r * b + k] *= scale;
-    __syncthreads();
+  double s = 0.0, mv = -1.0;
+  int mi = 0x7fffffff;
+  for (int r = lane; r < sd.nB; r += 64) {
+    const double v = Vb[(int64_t)r * b + k];
+    s += v * v;
+    const double a = fabs(v);
+    if (a > mv) { mv = a; mi = r; }         // rows ascend: the lowest index wins ties
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off);
+    const double a = __shfl_xor(mv, off);
+    const int ai = __shfl_xor(mi, off);
+    if (a > mv || (a == mv && ai < mi)) { mv = a; mi = ai; }
+  }
+  if (mi == 0x7fffffff) return;             // no rows
+  const double sg = Vb[(int64_t)mi * b + k] < 0.0 ? -1.0 : 1.0;
+  const double scale = s > 0.0 ? sg / sqrt(s) : 1.0;   // a zero column stays zero
+  for (int r = lane; r < sd.nB; r += 64) Vb[(int64_t)r * b + k] *= scale;
 }
 
 // Phi_j (I-box rows x m_j, row-major) = X p on the I box
@@ -1360,7 +1421,7 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
     GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV, PV, SV>,                                 \
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));               \
     hipLaunchKernelGGL((k_trsm_ring<WV, PV, SV>), dim3(pc->n_sub * csplit), dim3(128 * ncb * SV), lds, s,  \
-                       pc->d_sub, pc->n_sub, csplit, b, ringlen, T, D, TB, pc->d_z0, Vin, V);       \
+                       pc->d_subxB, pc->n_sub, csplit, b, ringlen, T, D, TB, pc->d_z0, Vin, V);     \
   } while (0)
 #define GN_TR(WV)                                   \
   do {                                              \
@@ -1424,13 +1485,20 @@ void eig_small(int n_sub, int b, const double* GPp, const double* GBp, const dou
 
 void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const double* BZ,
                  const double* Y, double* V, double* BV, hipStream_t s) {
-  hipLaunchKernelGGL(k_vupdate, dim3(maxNBB * TILE / 16, pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, Z,
-                     BZ, Y, V, BV);
+  if (b > 64) throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
+  const int waves = maxNBB * TILE / 16;       // 16-row blocks of the largest subdomain
+  const dim3 grid((waves + NT / 64 - 1) / (NT / 64), pc->n_sub);
+  if (b <= 32)
+    hipLaunchKernelGGL((k_vupdate<8, 2>), grid, dim3(NT), 0, s, pc->d_sub, b, Z, BZ, Y, V, BV);
+  else
+    hipLaunchKernelGGL((k_vupdate<16, 4>), grid, dim3(NT), 0, s, pc->d_sub, b, Z, BZ, Y, V, BV);
   GN_CHECK_LAUNCH();
 }
 
 void eig_normalise(const gn_precond* pc, int b, int ncol, double* V, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalise, dim3(pc->n_sub), dim3(NT), 0, s, pc->d_sub, b, ncol, V);
+  if (ncol <= 0 || pc->n_sub <= 0) return;
+  const int cpb = NT / 64;                  // columns per workgroup
+  hipLaunchKernelGGL(k_normalise, dim3(pc->n_sub, (ncol + cpb - 1) / cpb), dim3(NT), 0, s, pc->d_sub, b, ncol, V);
   GN_CHECK_LAUNCH();
 }
 

@@ -130,6 +130,17 @@ struct gn_precond {
   std::vector<int> cuts[3];
   std::vector<SubDesc> sub;
   SubDesc* d_sub = nullptr;
+  // The same descriptors in the launch order of the one-workgroup-per-subdomain
+  // band sweeps.  Workgroup q of a launch runs on XCD q mod 8 (each XCD with its
+  // own L2 and share of the memory fabric), and a subdomain's sweep costs about
+  // its band tile count; the natural order maps one partition column (the
+  // fastest subdomain index) to each XCD, so the XCDs holding the interior
+  // columns carry up to 1.4x the tiles of those holding the boundary columns.
+  // xI spreads the local bands evenly over the XCDs, xB the pencil bands.
+  std::vector<int> xorderI, xorderB;
+  std::vector<SubDesc> subxI, subxB;
+  SubDesc* d_subxI = nullptr;
+  SubDesc* d_subxB = nullptr;
   int local_prec = 64;
   int local_kernel = 0;        // 0 automatic, 1 batched matrix-core kernel for single columns
   // per-axis node coverage (PoU counts) and part ranges for the gather-form prolongation
@@ -273,6 +284,9 @@ double absmv_norm2(gn_problem* p, const double* x, hipStream_t s);
 double cond_from_hist(const double* hist, int kit);
 void ensure_batch_workspace(gn_problem* p, gn_precond* pc, int maxit, hipStream_t s);
 int64_t resident_bytes(const std::vector<void*>& owned);
+// launch order q -> item that gives the XCDs (q mod 8) near-equal total weight:
+// heaviest item first onto the least loaded XCD with a free position
+std::vector<int> xcd_order(const std::vector<int64_t>& weight);
 }  // namespace gnh
 
 // ---------------------------------------------------------------------------

@@ -689,7 +689,7 @@ void precond_mc(const gn_problem* p, const gn_precond* pc, const double* r, doub
   do {                                                                                                 \
     auto kfn = k_band_solve_mc<FT, S>;                                                                 \
     GN_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));     \
-    hipLaunchKernelGGL(kfn, dim3(pc->n_sub), dim3(512), lds, s, pc->d_sub,                             \
+    hipLaunchKernelGGL(kfn, dim3(pc->n_sub), dim3(512), lds, s, pc->d_subxI,                           \
                        (const FT*)(f32 ? (const void*)pc->d_LIf : (const void*)pc->d_LI),              \
                        (const FT*)(f32 ? (const void*)pc->d_DIf : (const void*)pc->d_DI),              \
                        (const FT*)pc->d_LIb, tm,                                                       \

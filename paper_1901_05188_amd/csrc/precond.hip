@@ -20,6 +20,17 @@ namespace {
 constexpr int NT = 256;
 
 
+// The offset `off`, made to depend on `v`: loads addressed with the result are
+// issued after v is computed.  It keeps a register buffer's reload behind the
+// products that read the buffer's old contents; without it the reload is
+// scheduled first, the old values are copied out, and each copy waits for
+// every load still in flight (the memory counter retires in order), which
+// leaves a single block row in flight instead of two.  The asm is empty.
+__device__ inline unsigned gn_after(unsigned off, double v) {
+  asm volatile("" : "+v"(off) : "v"(v));
+  return off;
+}
+
 // Barrier that orders LDS traffic only: outstanding global loads (the prefetch of
 // the next block row) stay in flight across it.
 __device__ inline void lds_barrier() {
@@ -94,23 +105,25 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
   // rows K+1 (other buffer, issued one step earlier) and K+2 (this buffer,
   // issued right after the consumption) are in flight.
   FT lv0[SP], lv1[SP], dn0[CW], dn1[CW];
-  double dv[CW];
   // Slots u < CW*w address band entries; the rest read a shared zero tile, so
   // every load is unconditional and the unrolled loops carry no branches.
   // ---- forward ----
   // every slot address is a uniform tile pointer plus the thread's 32-bit offset
   // inside the tile (one offset register for all slots)
   const unsigned toff = (unsigned)((CW * gq) * TILE + i);
-#define GN_LOAD_FWD(K_, LV, DN)                                                          \
+#define GN_LOAD_FWD_LV(K_, LV, OFF)                                                      \
   {                                                                                      \
     const FT* rowp = Tb + (int64_t)(K_) * (w + 1) * TILE2;                               \
     _Pragma("unroll") for (int u = 0; u < SP; ++u) {                                     \
       const int t = u / CW, q = u % CW;                                                  \
       const FT* tp = (u < ns) ? rowp + t * TILE2 : Z0;                                   \
-      LV[u] = tp[toff + (unsigned)(q * TILE)];                                           \
+      LV[u] = tp[(OFF) + (unsigned)(q * TILE)];                                          \
     }                                                                                    \
+  }
+#define GN_LOAD_FWD_DN(K_, DN, OFF)                                                      \
+  {                                                                                      \
     const FT* dk = Db + (int64_t)(K_) * TILE2;                                           \
-    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[toff + (unsigned)(q * TILE)]; \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[(OFF) + (unsigned)(q * TILE)]; \
   }
 #define GN_STEP_FWD(K_, LV, DN)                                                          \
   {                                                                                      \
@@ -119,8 +132,8 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
     double acc = 0.0;                                                                    \
     _Pragma("unroll") for (int u = 0; u < SP; ++u)                                       \
       acc += (double)LV[u] * yw[(u / CW) * TILE + (u % CW)];                             \
-    _Pragma("unroll") for (int q = 0; q < CW; ++q) dv[q] = (double)DN[q];                \
-    GN_LOAD_FWD(min(KK + 2, NB - 1), LV, DN)                                             \
+    const unsigned toffA = gn_after(toff, acc);                                          \
+    GN_LOAD_FWD_LV(min(KK + 2, NB - 1), LV, toffA)                                       \
     red[gq][i] = acc;                                                                    \
     lds_barrier();                                                                       \
     double part = 0.0;                                                                   \
@@ -128,8 +141,10 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
       int c = CW * gq + q;                                                               \
       double sv = vec[KK * TILE + c];                                                    \
       _Pragma("unroll") for (int g2 = 0; g2 < G; ++g2) sv -= red[g2][c];                 \
-      part += dv[q] * sv;                                                                \
+      part += (double)DN[q] * sv;                                                        \
     }                                                                                    \
+    const unsigned toffP = gn_after(toff, part);                                         \
+    GN_LOAD_FWD_DN(min(KK + 2, NB - 1), DN, toffP)                                       \
     red2[gq][i] = part;                                                                  \
     lds_barrier();                                                                       \
     if (gq == 0) {                                                                       \
@@ -139,28 +154,42 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
     }                                                                                    \
     lds_barrier();                                                                       \
   }
-  GN_LOAD_FWD(0, lv0, dn0)
-  GN_LOAD_FWD(min(1, NB - 1), lv1, dn1)
-  for (int K = 0; K < NB; K += 2) {
+  GN_LOAD_FWD_LV(0, lv0, toff)
+  GN_LOAD_FWD_DN(0, dn0, toff)
+  GN_LOAD_FWD_LV(min(1, NB - 1), lv1, toff)
+  GN_LOAD_FWD_DN(min(1, NB - 1), dn1, toff)
+  // the scheduler may issue the two prologue groups interleaved; draining them
+  // here keeps the waits inside the loop at their steady-state depth (row K's
+  // loads done, row K+1's still in flight) instead of the prologue's order
+  __builtin_amdgcn_s_waitcnt(0);
+  // pairs of rows in the loop and an odd last row after it, so that every path
+  // into the loop header has the same loads in flight
+  int K = 0;
+  for (; K + 1 < NB; K += 2) {
     GN_STEP_FWD(K, lv0, dn0)
-    if (K + 1 < NB) GN_STEP_FWD(K + 1, lv1, dn1)
+    GN_STEP_FWD(K + 1, lv1, dn1)
   }
+  if (K < NB) GN_STEP_FWD(K, lv0, dn0)
 #undef GN_STEP_FWD
-#undef GN_LOAD_FWD
+#undef GN_LOAD_FWD_LV
+#undef GN_LOAD_FWD_DN
   // ---- backward ----
   // backward block row K: tile d-1 of row K of the transposed band holds
   // L(K+d, K)^T (entry (i, rr) = L(K+d, K)(rr, i)) and tile w holds D_K^T
   const FT* TBb = TBk + sd.offTI * TILE2;
-#define GN_LOAD_BWD(K_, LV, DN)                                                          \
+#define GN_LOAD_BWD_LV(K_, LV, OFF)                                                      \
   {                                                                                      \
     const FT* rowp = TBb + (int64_t)(K_) * (w + 1) * TILE2;                              \
     _Pragma("unroll") for (int u = 0; u < SP; ++u) {                                     \
       const int t = u / CW, q = u % CW;                                                  \
       const FT* tp = (u < ns) ? rowp + t * TILE2 : Z0;                                   \
-      LV[u] = tp[toff + (unsigned)(q * TILE)];                                           \
+      LV[u] = tp[(OFF) + (unsigned)(q * TILE)];                                          \
     }                                                                                    \
-    const FT* dk = rowp + (int64_t)w * TILE2;                                            \
-    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[toff + (unsigned)(q * TILE)]; \
+  }
+#define GN_LOAD_BWD_DN(K_, DN, OFF)                                                      \
+  {                                                                                      \
+    const FT* dk = TBb + ((int64_t)(K_) * (w + 1) + w) * TILE2;                          \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[(OFF) + (unsigned)(q * TILE)]; \
   }
 #define GN_STEP_BWD(K_, LV, DN)                                                          \
   {                                                                                      \
@@ -169,8 +198,8 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
     double acc = 0.0;                                                                    \
     _Pragma("unroll") for (int u = 0; u < SP; ++u)                                       \
       acc += (double)LV[u] * xw[(u / CW) * TILE + (u % CW)];                             \
-    _Pragma("unroll") for (int q = 0; q < CW; ++q) dv[q] = (double)DN[q];                \
-    GN_LOAD_BWD(max(KK - 2, 0), LV, DN)                                                  \
+    const unsigned toffA = gn_after(toff, acc);                                          \
+    GN_LOAD_BWD_LV(max(KK - 2, 0), LV, toffA)                                            \
     red[gq][i] = acc;                                                                    \
     lds_barrier();                                                                       \
     double part = 0.0;                                                                   \
@@ -178,8 +207,10 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
       int rr = CW * gq + q;                                                              \
       double sv = vec[KK * TILE + rr];                                                   \
       _Pragma("unroll") for (int g2 = 0; g2 < G; ++g2) sv -= red[g2][rr];                \
-      part += dv[q] * sv;                                                                \
+      part += (double)DN[q] * sv;                                                        \
     }                                                                                    \
+    const unsigned toffP = gn_after(toff, part);                                         \
+    GN_LOAD_BWD_DN(max(KK - 2, 0), DN, toffP)                                            \
     red2[gq][i] = part;                                                                  \
     lds_barrier();                                                                       \
     if (gq == 0) {                                                                       \
@@ -189,14 +220,20 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
     }                                                                                    \
     lds_barrier();                                                                       \
   }
-  GN_LOAD_BWD(NB - 1, lv0, dn0)
-  GN_LOAD_BWD(max(NB - 2, 0), lv1, dn1)
-  for (int K = NB - 1; K >= 0; K -= 2) {
+  GN_LOAD_BWD_LV(NB - 1, lv0, toff)
+  GN_LOAD_BWD_DN(NB - 1, dn0, toff)
+  GN_LOAD_BWD_LV(max(NB - 2, 0), lv1, toff)
+  GN_LOAD_BWD_DN(max(NB - 2, 0), dn1, toff)
+  __builtin_amdgcn_s_waitcnt(0);
+  K = NB - 1;
+  for (; K >= 1; K -= 2) {
     GN_STEP_BWD(K, lv0, dn0)
-    if (K - 1 >= 0) GN_STEP_BWD(K - 1, lv1, dn1)
+    GN_STEP_BWD(K - 1, lv1, dn1)
   }
+  if (K >= 0) GN_STEP_BWD(K, lv0, dn0)
 #undef GN_STEP_BWD
-#undef GN_LOAD_BWD
+#undef GN_LOAD_BWD_LV
+#undef GN_LOAD_BWD_DN
   __syncthreads();
   double* out = tvec + sd.offVI;
   for (int row = threadIdx.x; row < npad; row += NT) out[row] = vec[row];
@@ -361,7 +398,7 @@ void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, con
     auto kfn = k_local_solve_pf<FT, NC, SPV, GV>;                                                 \
     GN_HIP(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,      \
                                (int)dynpf));                                                      \
-    hipLaunchKernelGGL(kfn, dim3(pc->n_sub), dim3(32 * GV), dynpf, s, pc->d_sub, p->nn[0],         \
+    hipLaunchKernelGGL(kfn, dim3(pc->n_sub), dim3(32 * GV), dynpf, s, pc->d_subxI, p->nn[0],       \
                        p->nn[1], r,                                                               \
                        (const FT*)(f32 ? (const void*)pc->d_LIf : (const void*)pc->d_LI),         \
                        (const FT*)(f32 ? (const void*)pc->d_DIf : (const void*)pc->d_DI),         \
