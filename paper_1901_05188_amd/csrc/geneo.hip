@@ -265,41 +265,41 @@ __global__ __launch_bounds__(512) void k_trsm_pencil(const SubDesc* __restrict__
 #undef GN_ZERO4
 }
 
-// ---------------------------------------------------------------------------
-// Same solves, pipelined: one workgroup per subdomain with two waves (row
-// halves) per 16-column block.  The solved block rows of the current window
-// live in an LDS ring of w + 1 block rows (all b columns), and the band tiles
-// stream through a rolling register prefetch P tiles deep: after the
-// matrix-core products of tile t, the registers it used are reloaded with tile
-// t + P of the same step, or of the next step.  The step body is unrolled over
-// W >= w tile slots (W a multiple of P); slots t >= w read a zero tile.  Only
-// LDS-ordering barriers separate the steps, so the prefetch stays in flight.
-// Operand reads are unmasked: columns past b read neighbouring finite values
-// (the ring is zeroed, V carries 64 doubles of tail padding) and only feed
-// output columns that are never stored; ring slots of blocks outside the
-// subdomain stay zero, so no bounds mask is needed either.
-// ---------------------------------------------------------------------------
+// Barrier that orders LDS traffic only: outstanding global loads stay in flight.
 __device__ inline void geneo_lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int W, int P, int S>
-__global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ subs, int n_sub, int csplit, int b,
-                                                   int ringlen, const double* __restrict__ T,
-                                                   const double* __restrict__ D, const double* __restrict__ TBk,
-                                                   const double* __restrict__ Z0, const double* Vin, double* V) {
-  static_assert(W % S == 0 && (W / S) % P == 0, "W / S must be a multiple of the prefetch depth");
-  constexpr int WS = W / S;                 // tile slots per wave and step
+
+// ---------------------------------------------------------------------------
+// Block solves, one wave per SIMD: four waves per workgroup (row half x tile
+// parity), each wave covering NCB 16-column blocks.  Every band tile is loaded
+// once per workgroup (by the wave of its row half and parity) and feeds the
+// products of all NCB column blocks, and a wave has the register room for a
+// prefetch P tiles deep.  The diagonal solve of a block row is split between
+// the two parities: the wave pair of parity h owns column block h (NCB = 2) or
+// parity 0 owns the single block (NCB = 1); the non-owner's partial sums reach
+// the owner through LDS.  A workgroup takes NCB * 16 columns (csplit > 1: the
+// chunk g of 16 NCB columns; siblings are n_sub workgroups apart).  Reads past
+// column b take finite neighbouring values and feed only unstored outputs; ring
+// slots of blocks outside the subdomain stay zero.
+// ---------------------------------------------------------------------------
+template <int W, int P, int NCB>
+__global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ subs, int n_sub, int csplit, int b,
+                                                    int ringlen, const double* __restrict__ T,
+                                                    const double* __restrict__ D, const double* __restrict__ TBk,
+                                                    const double* __restrict__ Z0, const double* Vin, double* V) {
+  constexpr int WS = W / 2;                 // tile slots per wave and step
+  static_assert(W % 2 == 0 && WS % P == 0, "W / 2 must be a multiple of the prefetch depth");
   extern __shared__ double smem[];
   double* ring = smem;                      // W1 slots x TILE rows x RW columns (+16 pad)
-  // csplit = 1: one workgroup takes all b columns of its subdomain; csplit > 1:
-  // workgroup g takes the 16 columns 16 g .. 16 g + 15 (the solves of different
-  // columns are independent; siblings are n_sub workgroups apart)
+  double* sS = smem + ringlen;              // NCB exchange tiles, 32 x 16 (+1)
+  double* sP = sS + NCB * (TILE * 17);      // NCB partial tiles of the non-owner parity
   const SubDesc& sd = subs[blockIdx.x % n_sub];
-  const int c0 = csplit > 1 ? (int)(blockIdx.x / n_sub) * 16 : 0;
-  const int RW = csplit > 1 ? 16 : b;       // columns held in the ring
+  const int c0 = csplit > 1 ? (int)(blockIdx.x / n_sub) * (16 * NCB) : 0;
+  const int RW = csplit > 1 ? 16 * NCB : b; // columns held in the ring
   const int NB = sd.NBB, w = sd.wB, W1 = w + 1;
   const double* Tb = T + sd.offTB * TILE2;
   const double* Db = D + sd.offDB * TILE2;
@@ -307,203 +307,156 @@ __global__ __launch_bounds__(512) void k_trsm_ring(const SubDesc* __restrict__ s
   const double* Vi = Vin + sd.offVB * b;    // right-hand sides
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int ncb = csplit > 1 ? 1 : (b + 15) / 16;
-  const int half = wv / (2 * ncb);          // tile parity handled by this wave (S = 2)
-  const int rem = wv % (2 * ncb);
-  const int rh = rem & 1, cb = rem >> 1;
-  double* sS = smem + ringlen + cb * (TILE * 17);               // 32 x 16 (+1) exchange tile
-  double* sP = smem + ringlen + (ncb + cb) * (TILE * 17);       // partial of the odd tiles
+  const int half = wv >> 1, rh = wv & 1;
   const int lr = lane & 15, lk = lane >> 4;
   const int rb = rh * 16;
-  const int lcol = cb * 16 + lr;            // column in the ring
-  const int col = c0 + lcol;                // column of V
-  const bool ok = col < b;
-  const int nthr = blockDim.x;
-  for (int e = threadIdx.x; e < ringlen; e += nthr) ring[e] = 0.0;
+  // column block whose diagonal solve this wave does, or -1
+  const int own = NCB == 2 ? half : (half == 0 ? 0 : -1);
+  const int ocol = c0 + (own < 0 ? 0 : own) * 16 + lr;   // column of V for the owned block
+  const bool ook = own >= 0 && ocol < b;
+  const int olcol = (own < 0 ? 0 : own) * 16 + lr;       // its column in the ring
+  for (int e = threadIdx.x; e < ringlen; e += 256) ring[e] = 0.0;
   double a[P][8];
   double dv[8], vv[4];
-  gn_d4 acc[8];   // eight independent chains in the tile products
-#define TR_ZERO() _Pragma("unroll") for (int u = 0; u < 8; ++u) acc[u] = gn_d4{0, 0, 0, 0};
-  // ---- forward: Y_K = Dinv_K (V_K - sum_t L(K,t) Y_{K-w+t}) ----
-#define TR_FWD_TILE(K_, t_) (((t_) < w) ? Tb + ((int64_t)(K_) * W1 + (t_)) * TILE2 : Z0)
-#define TR_LOAD_A_FWD(S_, K_, t_)                                                              \
+  gn_d4 acc[NCB][8];
+#define R2_ZERO() _Pragma("unroll") for (int q = 0; q < NCB; ++q) _Pragma("unroll") for (int u = 0; u < 8; ++u) acc[q][u] = gn_d4{0, 0, 0, 0};
+  const int rstride = TILE * RW;
+  // products of one block row: slots m = 0 .. WS-1 of this wave's parity, slot
+  // m multiplying ring slot (SLOT0 + 2 m) mod W1; the A registers of slot m are
+  // reloaded with slot m + P of the row (or of row KN past the end)
+#define R2_PRODUCTS(KR, KN, SLOT0, LOADA)                                                      \
   {                                                                                            \
-    const double* tp = TR_FWD_TILE(K_, t_);                                                    \
+    R2_ZERO()                                                                                  \
+    int slot = (SLOT0);                                                                        \
+    double bcur[NCB][8], bnxt[NCB][8];                                                         \
+    _Pragma("unroll") for (int q = 0; q < NCB; ++q)                                            \
+      _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                         \
+        bnxt[q][ks] = ring[slot * rstride + (4 * ks + lk) * RW + q * 16 + lr];                 \
+    _Pragma("unroll") for (int m = 0; m < WS; ++m) {                                           \
+      const int sl = m % P;                                                                    \
+      _Pragma("unroll") for (int q = 0; q < NCB; ++q)                                          \
+        _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) bcur[q][ks] = bnxt[q][ks];            \
+      if (m + 1 < WS) {                                                                        \
+        slot += 2;                                                                             \
+        while (slot >= W1) slot -= W1;                                                         \
+        _Pragma("unroll") for (int q = 0; q < NCB; ++q)                                        \
+          _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                     \
+            bnxt[q][ks] = ring[slot * rstride + (4 * ks + lk) * RW + q * 16 + lr];             \
+      }                                                                                        \
+      _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                         \
+        _Pragma("unroll") for (int q = 0; q < NCB; ++q)                                        \
+          acc[q][ks] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][ks], bcur[q][ks], acc[q][ks], 0, 0, 0); \
+      __builtin_amdgcn_sched_barrier(0);                                                       \
+      if (m + P < WS) LOADA(sl, (KR), 2 * (m + P) + half)                                      \
+      else LOADA(sl, (KN), 2 * (m + P - WS) + half)                                            \
+      __builtin_amdgcn_sched_barrier(0);                                                       \
+    }                                                                                          \
+  }
+  // exchange, diagonal solve of the owned block and the store of block row K
+  // (to the ring slot K % W1 and to V); three LDS barriers for every wave
+#define R2_FINISH(K, LOADDV, KDV)                                                              \
+  {                                                                                            \
+    double dcur[8], vcur[4];                                                                   \
+    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dcur[ks] = dv[ks];                        \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) vcur[i] = vv[i];                             \
+    if (own >= 0) LOADDV(KDV)                                                                  \
+    double psum[NCB][4];                                                                       \
+    _Pragma("unroll") for (int q = 0; q < NCB; ++q)                                            \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i)                                            \
+        psum[q][i] = ((acc[q][0][i] + acc[q][1][i]) + (acc[q][2][i] + acc[q][3][i])) +         \
+                     ((acc[q][4][i] + acc[q][5][i]) + (acc[q][6][i] + acc[q][7][i]));          \
+    _Pragma("unroll") for (int q = 0; q < NCB; ++q) {                                          \
+      if (q != own) {                                                                          \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i)                                          \
+          sP[q * (TILE * 17) + (rb + 4 * i + lk) * 17 + lr] = psum[q][i];                      \
+      }                                                                                        \
+    }                                                                                          \
+    geneo_lds_barrier();                                                                       \
+    if (own >= 0) {                                                                            \
+      double mine[4];                                                                          \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i) mine[i] = own == 0 ? psum[0][i] : psum[NCB - 1][i]; \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                          \
+        const int o = own * (TILE * 17) + (rb + 4 * i + lk) * 17 + lr;                         \
+        sS[o] = vcur[i] - (mine[i] + sP[o]);                                                   \
+      }                                                                                        \
+    }                                                                                          \
+    geneo_lds_barrier();                                                                       \
+    if (own >= 0) {                                                                            \
+      gn_d4 dq[4];                                                                             \
+      _Pragma("unroll") for (int u = 0; u < 4; ++u) dq[u] = gn_d4{0, 0, 0, 0};                 \
+      _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                         \
+        dq[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(                                     \
+            dcur[ks], sS[own * (TILE * 17) + (4 * ks + lk) * 17 + lr], dq[ks & 3], 0, 0, 0);   \
+      double* yk = ring + ((K) % W1) * rstride;                                                \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                          \
+        const int row = rb + 4 * i + lk;                                                       \
+        const double y = (dq[0][i] + dq[1][i]) + (dq[2][i] + dq[3][i]);                        \
+        if (ook) {                                                                             \
+          yk[row * RW + olcol] = y;                                                            \
+          Vb[(int64_t)((K) * TILE + row) * b + ocol] = y;                                      \
+        }                                                                                      \
+      }                                                                                        \
+    }                                                                                          \
+    geneo_lds_barrier();                                                                       \
+  }
+  // ---- forward: Y_K = Dinv_K (V_K - sum_t L(K,t) Y_{K-w+t}) ----
+#define R2_FWD_TILE(K_, t_) (((t_) < w) ? Tb + ((int64_t)(K_) * W1 + (t_)) * TILE2 : Z0)
+#define R2_LOAD_A_FWD(S_, K_, t_)                                                              \
+  {                                                                                            \
+    const double* tp = R2_FWD_TILE(K_, t_);                                                    \
     _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) a[S_][ks] = tp[(4 * ks + lk) * TILE + rb + lr]; \
   }
-#define TR_LOAD_DV_FWD(K_)                                                                     \
+#define R2_LOAD_DV_FWD(K_)                                                                     \
   {                                                                                            \
     const double* dk = Db + (int64_t)(K_) * TILE2;                                             \
     _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dv[ks] = dk[(4 * ks + lk) * TILE + rb + lr]; \
     _Pragma("unroll") for (int i = 0; i < 4; ++i)                                              \
-      vv[i] = Vi[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + col];                           \
+      vv[i] = Vi[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + ocol];                          \
   }
 #pragma unroll
-  for (int sl = 0; sl < P; ++sl) TR_LOAD_A_FWD(sl, 0, S * sl + half)
-  if (half == 0) TR_LOAD_DV_FWD(0)
+  for (int sl = 0; sl < P; ++sl) R2_LOAD_A_FWD(sl, 0, 2 * sl + half)
+  if (own >= 0) R2_LOAD_DV_FWD(0)
   __syncthreads();
-  const int rstride = TILE * RW;
-  const int lofs = lk * RW + lcol;
   for (int K = 0; K < NB; ++K) {
-    TR_ZERO()
-    // ring slot of tile t: block K - w + t; the B operands of tile t + 1 are
-    // read from LDS while the products of tile t run
-    int slot = (K + 1 + half) % W1;   // (K - w + half + W1) mod W1
-    double bcur[8], bnxt[8];
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * RW + lofs];
-#pragma unroll
-    for (int m = 0; m < WS; ++m) {
-      const int sl = m % P;
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks) bcur[ks] = bnxt[ks];
-      if (m + 1 < WS) {
-        slot += S;
-        while (slot >= W1) slot -= W1;
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * RW + lofs];
-      }
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks)
-        acc[ks] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][ks], bcur[ks], acc[ks], 0, 0, 0);
-      __builtin_amdgcn_sched_barrier(0);
-      if (m + P < WS) TR_LOAD_A_FWD(sl, K, S * (m + P) + half)
-      else TR_LOAD_A_FWD(sl, min(K + 1, NB - 1), S * (m + P - WS) + half)
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    double dcur[8], vcur[4];
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) dcur[ks] = dv[ks];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) vcur[i] = vv[i];
-    if (half == 0) TR_LOAD_DV_FWD(min(K + 1, NB - 1))
-    double psum[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      psum[i] = ((acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i])) + ((acc[4][i] + acc[5][i]) + (acc[6][i] + acc[7][i]));
-    if (S == 2) {
-      if (half == 1) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sP[(rb + 4 * i + lk) * 17 + lr] = psum[i];
-      }
-      geneo_lds_barrier();
-    }
-    if (half == 0) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        sS[(rb + 4 * i + lk) * 17 + lr] = vcur[i] - (S == 2 ? psum[i] + sP[(rb + 4 * i + lk) * 17 + lr] : psum[i]);
-    }
-    geneo_lds_barrier();
-    TR_ZERO()
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks)
-      acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dcur[ks], sS[(4 * ks + lk) * 17 + lr], acc[ks & 3], 0, 0, 0);
-    double* yk = ring + (K % W1) * (TILE * RW);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = rb + 4 * i + lk;
-      const double y = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
-      if (ok && half == 0) {
-        yk[row * RW + lcol] = y;
-        Vb[(int64_t)(K * TILE + row) * b + col] = y;
-      }
-    }
-    geneo_lds_barrier();
+    // ring slot of tile t of row K: block K - w + t, i.e. (K + 1 + t) % W1
+    R2_PRODUCTS(K, min(K + 1, NB - 1), (K + 1 + half) % W1, R2_LOAD_A_FWD)
+    R2_FINISH(K, R2_LOAD_DV_FWD, min(K + 1, NB - 1))
   }
-#undef TR_LOAD_DV_FWD
-#undef TR_LOAD_A_FWD
-#undef TR_FWD_TILE
+#undef R2_LOAD_DV_FWD
+#undef R2_LOAD_A_FWD
+#undef R2_FWD_TILE
   __syncthreads();
-  for (int e = threadIdx.x; e < ringlen; e += nthr) ring[e] = 0.0;
+  for (int e = threadIdx.x; e < ringlen; e += 256) ring[e] = 0.0;
   // ---- backward: X_K = Dinv_K^T (Y_K - sum_d L(K+d,K)^T X_{K+d}), d = t + 1 ----
-  // L(K+d,K)^T is tile t of row K of the transposed band (zero past the last
-  // block row) and Dinv_K^T its tile w: contiguous tile columns across lanes
   const double* TBb = TBk + sd.offTB * TILE2;
-#define TR_BWD_TILE(K_, t_) (((t_) < w) ? TBb + ((int64_t)(K_) * W1 + (t_)) * TILE2 : Z0)
-#define TR_LOAD_A_BWD(S_, K_, t_)                                                              \
+#define R2_BWD_TILE(K_, t_) (((t_) < w) ? TBb + ((int64_t)(K_) * W1 + (t_)) * TILE2 : Z0)
+#define R2_LOAD_A_BWD(S_, K_, t_)                                                              \
   {                                                                                            \
-    const double* tp = TR_BWD_TILE(K_, t_);                                                    \
+    const double* tp = R2_BWD_TILE(K_, t_);                                                    \
     _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) a[S_][ks] = tp[(4 * ks + lk) * TILE + rb + lr]; \
   }
-#define TR_LOAD_DV_BWD(K_)                                                                     \
+#define R2_LOAD_DV_BWD(K_)                                                                     \
   {                                                                                            \
     const double* dk = TBb + ((int64_t)(K_) * W1 + w) * TILE2;                                 \
     _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dv[ks] = dk[(4 * ks + lk) * TILE + rb + lr]; \
     _Pragma("unroll") for (int i = 0; i < 4; ++i)                                              \
-      vv[i] = Vb[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + col];                           \
+      vv[i] = Vb[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + ocol];                          \
   }
 #pragma unroll
-  for (int sl = 0; sl < P; ++sl) TR_LOAD_A_BWD(sl, NB - 1, S * sl + half)
-  if (half == 0) TR_LOAD_DV_BWD(NB - 1)
+  for (int sl = 0; sl < P; ++sl) R2_LOAD_A_BWD(sl, NB - 1, 2 * sl + half)
+  if (own >= 0) R2_LOAD_DV_BWD(NB - 1)
   __syncthreads();
   for (int K = NB - 1; K >= 0; --K) {
-    TR_ZERO()
-    int slot = (K + 1 + half) % W1;   // ring slot of tile t: block K + 1 + t
-    double bcur[8], bnxt[8];
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * RW + lofs];
-#pragma unroll
-    for (int m = 0; m < WS; ++m) {
-      const int sl = m % P;
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks) bcur[ks] = bnxt[ks];
-      if (m + 1 < WS) {
-        slot += S;
-        while (slot >= W1) slot -= W1;
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) bnxt[ks] = ring[slot * rstride + 4 * ks * RW + lofs];
-      }
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks)
-        acc[ks] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][ks], bcur[ks], acc[ks], 0, 0, 0);
-      __builtin_amdgcn_sched_barrier(0);
-      if (m + P < WS) TR_LOAD_A_BWD(sl, K, S * (m + P) + half)
-      else TR_LOAD_A_BWD(sl, max(K - 1, 0), S * (m + P - WS) + half)
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    double dcur[8], vcur[4];
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) dcur[ks] = dv[ks];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) vcur[i] = vv[i];
-    if (half == 0) TR_LOAD_DV_BWD(max(K - 1, 0))
-    double psum[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      psum[i] = ((acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i])) + ((acc[4][i] + acc[5][i]) + (acc[6][i] + acc[7][i]));
-    if (S == 2) {
-      if (half == 1) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sP[(rb + 4 * i + lk) * 17 + lr] = psum[i];
-      }
-      geneo_lds_barrier();
-    }
-    if (half == 0) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        sS[(rb + 4 * i + lk) * 17 + lr] = vcur[i] - (S == 2 ? psum[i] + sP[(rb + 4 * i + lk) * 17 + lr] : psum[i]);
-    }
-    geneo_lds_barrier();
-    TR_ZERO()
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks)
-      acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dcur[ks], sS[(4 * ks + lk) * 17 + lr], acc[ks & 3], 0, 0, 0);
-    double* xk = ring + (K % W1) * (TILE * RW);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = rb + 4 * i + lk;
-      const double x = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
-      if (ok && half == 0) {
-        xk[row * RW + lcol] = x;
-        Vb[(int64_t)(K * TILE + row) * b + col] = x;
-      }
-    }
-    geneo_lds_barrier();
+    // ring slot of tile t of row K: block K + 1 + t
+    R2_PRODUCTS(K, max(K - 1, 0), (K + 1 + half) % W1, R2_LOAD_A_BWD)
+    R2_FINISH(K, R2_LOAD_DV_BWD, max(K - 1, 0))
   }
-#undef TR_LOAD_DV_BWD
-#undef TR_LOAD_A_BWD
-#undef TR_BWD_TILE
-#undef TR_ZERO
+#undef R2_LOAD_DV_BWD
+#undef R2_LOAD_A_BWD
+#undef R2_BWD_TILE
+#undef R2_FINISH
+#undef R2_PRODUCTS
+#undef R2_ZERO
 }
 
 // ---------------------------------------------------------------------------
@@ -1400,45 +1353,47 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
   if (b > 64) throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
   int maxw = 0;
   for (const SubDesc& sd : pc->sub) maxw = std::max(maxw, sd.wB);
-  // one workgroup per subdomain for all b columns when its ring fits in LDS,
-  // else one per subdomain and 16-column block
-  int ncb = (b + 15) / 16, csplit = 1;
-  int ringlen = (maxw + 1) * TILE * b + 16;
-  size_t lds = sizeof(double) * ((size_t)ringlen + (size_t)2 * ncb * TILE * 17);
-  if (lds > 160 * 1024 && ncb > 1) {
-    csplit = ncb;
-    ncb = 1;
-    ringlen = (maxw + 1) * TILE * 16 + 16;
-    lds = sizeof(double) * ((size_t)ringlen + (size_t)2 * TILE * 17);
-  }
-  // two waves per (row half, column block) splitting the tiles when they fit in 512 threads
-  const int split = ncb <= 2 ? 2 : 1;
-  // tile slots per step: the smallest multiple of the prefetch depth (6) >= w
-  const int W = std::max(6, (maxw + 5) / 6 * 6);
-  if (lds <= 160 * 1024 && W <= 30 && pc->d_z0 && TB) {
-#define GN_TR1(WV, PV, SV)                                                                           \
-  do {                                                                                               \
-    GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV, PV, SV>,                                 \
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));               \
-    hipLaunchKernelGGL((k_trsm_ring<WV, PV, SV>), dim3(pc->n_sub * csplit), dim3(128 * ncb * SV), lds, s,  \
-                       pc->d_subxB, pc->n_sub, csplit, b, ringlen, T, D, TB, pc->d_z0, Vin, V);     \
-  } while (0)
-#define GN_TR(WV)                                   \
-  do {                                              \
-    if (split == 2) GN_TR1(WV, 3, 2);               \
-    else GN_TR1(WV, 6, 1);                          \
-  } while (0)
-    switch (W) {
-      case 6: GN_TR(6); break;
-      case 12: GN_TR(12); break;
-      case 18: GN_TR(18); break;
-      case 24: GN_TR(24); break;
-      default: GN_TR(30); break;
+  // four-wave kernel: 32-column chunks, or 16-column ones when that ring does not fit
+  {
+    const int maxw1 = maxw + 1;
+    int ncb2 = b <= 16 ? 1 : 2;
+    int cs2 = (b + 16 * ncb2 - 1) / (16 * ncb2);
+    int rw2 = cs2 > 1 ? 16 * ncb2 : b;
+    int rl2 = maxw1 * TILE * rw2 + 32;
+    size_t lds2 = sizeof(double) * ((size_t)rl2 + (size_t)2 * ncb2 * TILE * 17);
+    if (lds2 > 160 * 1024 && ncb2 == 2) {
+      ncb2 = 1;
+      cs2 = (b + 15) / 16;
+      rw2 = cs2 > 1 ? 16 : b;
+      rl2 = maxw1 * TILE * rw2 + 32;
+      lds2 = sizeof(double) * ((size_t)rl2 + (size_t)2 * TILE * 17);
     }
-#undef GN_TR
-#undef GN_TR1
-    GN_CHECK_LAUNCH();
-    return;
+    const int W2 = std::max(6, (maxw + 5) / 6 * 6);
+    if (lds2 <= 160 * 1024 && W2 <= 30 && pc->d_z0 && TB) {
+#define GN_R2(WV, PV, NV)                                                                             \
+  do {                                                                                                \
+    GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV, PV, NV>,                                 \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));               \
+    hipLaunchKernelGGL((k_trsm_ring<WV, PV, NV>), dim3(pc->n_sub * cs2), dim3(256), lds2, s,         \
+                       pc->d_subxB, pc->n_sub, cs2, b, rl2, T, D, TB, pc->d_z0, Vin, V);              \
+  } while (0)
+#define GN_R2W(WV, PV)                     \
+  do {                                     \
+    if (ncb2 == 2) GN_R2(WV, PV, 2);       \
+    else GN_R2(WV, PV, 1);                 \
+  } while (0)
+      switch (W2) {
+        case 6: GN_R2W(6, 3); break;
+        case 12: GN_R2W(12, 6); break;
+        case 18: GN_R2W(18, 3); break;
+        case 24: GN_R2W(24, 6); break;
+        default: GN_R2W(30, 3); break;
+      }
+#undef GN_R2W
+#undef GN_R2
+      GN_CHECK_LAUNCH();
+      return;
+    }
   }
   // one workgroup per subdomain, two waves (row halves) per 16-column block: the
   // waves of a row half read the same band tiles, so each tile leaves HBM once
