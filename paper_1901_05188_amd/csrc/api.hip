@@ -570,7 +570,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   std::vector<BandRefH> refs(n_sub);
   for (int j = 0; j < n_sub; ++j) refs[j] = BandRefH{pc->sub[j].offTI, pc->sub[j].offDI, pc->sub[j].NBI, pc->sub[j].wI};
   BandRefH* d_refs = upload(tmp, refs.data(), refs.size(), s);
-  gnk::band_chol(d_refs, n_sub, LI, DI, d_info, s);
+  gnk::band_chol(d_refs, n_sub, pc->maxwI, LI, DI, d_info, s);
   GN_HIP(hipMemcpyAsync(info.data(), d_info, sizeof(int) * n_sub, hipMemcpyDeviceToHost, s));
   GN_HIP(hipStreamSynchronize(s));
   for (int j = 0; j < n_sub; ++j)
@@ -674,7 +674,9 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     for (int j = 0; j < n_sub; ++j) refs[j] = BandRefH{pc->sub[j].offTB, pc->sub[j].offDB, pc->sub[j].NBB, pc->sub[j].wB};
     GN_HIP(hipMemcpyAsync(d_refs, refs.data(), sizeof(BandRefH) * n_sub, hipMemcpyHostToDevice, s));
     GN_HIP(hipMemsetAsync(d_info, 0, sizeof(int) * n_sub, s));
-    gnk::band_chol(d_refs, n_sub, LB, DB, d_info, s);
+    int maxwB = 0;
+    for (const SubDesc& sd : pc->sub) maxwB = std::max(maxwB, sd.wB);
+    gnk::band_chol(d_refs, n_sub, maxwB, LB, DB, d_info, s);
     GN_HIP(hipMemcpyAsync(info.data(), d_info, sizeof(int) * n_sub, hipMemcpyDeviceToHost, s));
     GN_HIP(hipStreamSynchronize(s));
     for (int j = 0; j < n_sub; ++j)

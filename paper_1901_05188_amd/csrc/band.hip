@@ -204,8 +204,14 @@ __device__ inline void bc_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// RL: the finished tiles L(K, J) of the current block row are also kept in LDS
+// (dynamic, w tiles with padded columns), so the X operands of the products come
+// from LDS and only the Y operands (earlier block rows) stream from memory: half
+// the traffic of the products, and no memory latency on the X side.
+template <bool RL>
 __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict__ mats, double* __restrict__ T,
                                                        double* __restrict__ D, int* __restrict__ info) {
+  extern __shared__ double rowL[];   // RL: w tiles, column-major with TILE + 1 stride
   __shared__ double part[4][TILE][TILE + 1];
   __shared__ double Ss[TILE][TILE + 1];
   __shared__ double Xs[TILE][TILE + 1];
@@ -222,13 +228,23 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
   bc_d4 acc[4];
 #define BC_LOAD(XA, YB, T2)                                                                    \
   {                                                                                            \
-    const double* xp = T + tile_off(br.offT, K, (T2), w);                                      \
-    const double* yp = (t == w) ? xp : T + tile_off(br.offT, J, (T2) - t + w, w);              \
-    _Pragma("unroll") for (int q = 0; q < 2; ++q)                                              \
-      _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) {                                       \
-        XA[q][ks] = xp[(4 * ks + lk) * TILE + q * 16 + lr];                                    \
-        YB[q][ks] = yp[(4 * ks + lk) * TILE + q * 16 + lr];                                    \
-      }                                                                                        \
+    if (RL) {                                                                                  \
+      const double* xl = rowL + (T2) * (TILE * (TILE + 1));                                    \
+      const double* yp = T + tile_off(br.offT, J, (T2) - t + w, w);                            \
+      _Pragma("unroll") for (int q = 0; q < 2; ++q)                                            \
+        _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) {                                     \
+          XA[q][ks] = xl[(4 * ks + lk) * (TILE + 1) + q * 16 + lr];                            \
+          YB[q][ks] = (t == w) ? XA[q][ks] : yp[(4 * ks + lk) * TILE + q * 16 + lr];           \
+        }                                                                                      \
+    } else {                                                                                   \
+      const double* xp = T + tile_off(br.offT, K, (T2), w);                                    \
+      const double* yp = (t == w) ? xp : T + tile_off(br.offT, J, (T2) - t + w, w);            \
+      _Pragma("unroll") for (int q = 0; q < 2; ++q)                                            \
+        _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) {                                     \
+          XA[q][ks] = xp[(4 * ks + lk) * TILE + q * 16 + lr];                                  \
+          YB[q][ks] = yp[(4 * ks + lk) * TILE + q * 16 + lr];                                  \
+        }                                                                                      \
+    }                                                                                          \
   }
 #define BC_MFMA(XA, YB)                                                                        \
   _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                             \
@@ -287,7 +303,9 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int row = qr * 16 + 4 * i + lk, col = qc * 16 + lr;
-          tk[col * TILE + row] = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+          const double l = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+          tk[col * TILE + row] = l;
+          if (RL) rowL[t * (TILE * (TILE + 1)) + col * (TILE + 1) + row] = l;
         }
       } else if (wid == 0) {
         // dense Cholesky of the diagonal tile (lower), one wave, in registers:
@@ -515,8 +533,17 @@ void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, dou
   GN_CHECK_LAUNCH();
 }
 
-void band_chol(const void* d_refs, int n, double* T, double* D, int* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_band_chol_mfma, dim3(n), dim3(NT), 0, s, (const BandRef*)d_refs, T, D, info);
+void band_chol(const void* d_refs, int n, int maxw, double* T, double* D, int* info, hipStream_t s) {
+  // the row tiles in LDS when they fit beside the kernel's static arrays
+  // (about 50 KB: the four partial products and two exchange tiles)
+  const size_t rl = sizeof(double) * (size_t)std::max(maxw, 1) * TILE * (TILE + 1);
+  if (rl + 52 * 1024 <= 160 * 1024) {
+    GN_HIP(hipFuncSetAttribute((const void*)k_band_chol_mfma<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)rl));
+    hipLaunchKernelGGL(k_band_chol_mfma<true>, dim3(n), dim3(NT), rl, s, (const BandRef*)d_refs, T, D, info);
+  } else {
+    hipLaunchKernelGGL(k_band_chol_mfma<false>, dim3(n), dim3(NT), 0, s, (const BandRef*)d_refs, T, D, info);
+  }
   GN_CHECK_LAUNCH();
 }
 

@@ -211,7 +211,7 @@ void sub_partial(int64_t n, const double* b, const double* q, double* r, double*
 void extract_local(const gn_problem* p, const gn_precond* pc, double* L, int maxNB, hipStream_t s);
 void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, double* L, int maxNB,
                     hipStream_t s);
-void band_chol(const void* d_refs, int n, double* T, double* D, int* info, hipStream_t s);
+void band_chol(const void* d_refs, int n, int maxw, double* T, double* D, int* info, hipStream_t s);
 void to_f32(int64_t n, const double* a, float* b, hipStream_t s);
 void band_transpose(const void* d_refs, int n, int maxNB, const double* T, const double* D, void* TB, bool f32,
                     hipStream_t s);
