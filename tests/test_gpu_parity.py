@@ -115,10 +115,8 @@ def test_one_level_apply_matches_oracle(name):
     assert np.linalg.norm(z[0].cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("name", ALL)
-def test_geneo_eigenvalues_and_counts(name):
+def _check_eigenvalues(name, pc):
     g = orc.geneo_run(name)
-    pc = precond(name)
     w = orc.workload(name)
     g2 = orc.geneo_run_shift(name, 1e-1)
     for j in range(w.n_sub):
@@ -137,6 +135,26 @@ def test_geneo_eigenvalues_and_counts(name):
         tol = np.maximum(1e-10 * np.abs(lref[:k]), 20 * self_d)
         err = np.abs(lam[:k] - lref[:k])
         assert np.all(err[~z] <= tol[~z]), (j, lam[:k], lref[:k], err, tol)
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_geneo_eigenvalues_and_counts(name):
+    _check_eigenvalues(name, precond(name))
+
+
+@pytest.mark.parametrize("name,block", [("lam_3x2x2_uneven", 16), ("lam_3x2x2_uneven", 40),
+                                        ("lam_3x2x2_uneven", 64), ("diff_2x2x2", 40)])
+def test_geneo_block_widths(name, block):
+    """Eigen blocks of one 16-column block, and wider than one workgroup's 32
+    columns (two chunks per subdomain, the last one partial at 40): the block
+    solves take their other workgroup shapes and must give the same pairs."""
+    w = orc.workload(name)
+    print(f"[gpu] setup {name} eig_block={block}", flush=True)
+    pc = _gp().Preconditioner.from_workload(problem(name), w, eig_block=block)
+    try:
+        _check_eigenvalues(name, pc)
+    finally:
+        pc.close()
 
 
 @pytest.mark.parametrize("name", ALL)
