@@ -134,22 +134,24 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
       acc += (double)LV[u] * yw[(u / CW) * TILE + (u % CW)];                             \
     const unsigned toffA = gn_after(toff, acc);                                          \
     GN_LOAD_FWD_LV(min(KK + 2, NB - 1), LV, toffA)                                       \
-    red[gq][i] = acc;                                                                    \
+    acc += __shfl_xor(acc, 32);   /* the wave's two column groups, same row */           \
+    if ((threadIdx.x & 63) < 32) red[gq >> 1][i] = acc;                                  \
     lds_barrier();                                                                       \
     double part = 0.0;                                                                   \
     _Pragma("unroll") for (int q = 0; q < CW; ++q) {                                     \
       int c = CW * gq + q;                                                               \
       double sv = vec[KK * TILE + c];                                                    \
-      _Pragma("unroll") for (int g2 = 0; g2 < G; ++g2) sv -= red[g2][c];                 \
+      _Pragma("unroll") for (int g2 = 0; g2 < G / 2; ++g2) sv -= red[g2][c];             \
       part += (double)DN[q] * sv;                                                        \
     }                                                                                    \
     const unsigned toffP = gn_after(toff, part);                                         \
     GN_LOAD_FWD_DN(min(KK + 2, NB - 1), DN, toffP)                                       \
-    red2[gq][i] = part;                                                                  \
+    part += __shfl_xor(part, 32);                                                        \
+    if ((threadIdx.x & 63) < 32) red2[gq >> 1][i] = part;                                \
     lds_barrier();                                                                       \
     if (gq == 0) {                                                                       \
       double y = 0.0;                                                                    \
-      _Pragma("unroll") for (int g2 = 0; g2 < G; ++g2) y += red2[g2][i];                 \
+      _Pragma("unroll") for (int g2 = 0; g2 < G / 2; ++g2) y += red2[g2][i];             \
       vec[KK * TILE + i] = y;                                                            \
     }                                                                                    \
     lds_barrier();                                                                       \
@@ -200,22 +202,24 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
       acc += (double)LV[u] * xw[(u / CW) * TILE + (u % CW)];                             \
     const unsigned toffA = gn_after(toff, acc);                                          \
     GN_LOAD_BWD_LV(max(KK - 2, 0), LV, toffA)                                            \
-    red[gq][i] = acc;                                                                    \
+    acc += __shfl_xor(acc, 32);   /* the wave's two column groups, same row */           \
+    if ((threadIdx.x & 63) < 32) red[gq >> 1][i] = acc;                                  \
     lds_barrier();                                                                       \
     double part = 0.0;                                                                   \
     _Pragma("unroll") for (int q = 0; q < CW; ++q) {                                     \
       int rr = CW * gq + q;                                                              \
       double sv = vec[KK * TILE + rr];                                                   \
-      _Pragma("unroll") for (int g2 = 0; g2 < G; ++g2) sv -= red[g2][rr];                \
+      _Pragma("unroll") for (int g2 = 0; g2 < G / 2; ++g2) sv -= red[g2][rr];            \
       part += (double)DN[q] * sv;                                                        \
     }                                                                                    \
     const unsigned toffP = gn_after(toff, part);                                         \
     GN_LOAD_BWD_DN(max(KK - 2, 0), DN, toffP)                                            \
-    red2[gq][i] = part;                                                                  \
+    part += __shfl_xor(part, 32);                                                        \
+    if ((threadIdx.x & 63) < 32) red2[gq >> 1][i] = part;                                \
     lds_barrier();                                                                       \
     if (gq == 0) {                                                                       \
       double x = 0.0;                                                                    \
-      _Pragma("unroll") for (int g2 = 0; g2 < G; ++g2) x += red2[g2][i];                 \
+      _Pragma("unroll") for (int g2 = 0; g2 < G / 2; ++g2) x += red2[g2][i];             \
       vec[KK * TILE + i] = x;                                                            \
     }                                                                                    \
     lds_barrier();                                                                       \
