@@ -31,6 +31,19 @@ __device__ inline unsigned gn_after(unsigned off, double v) {
   return off;
 }
 
+// v[l % 32] + v[32 + l % 32] in every lane l of the wave (the sum of lanes l and
+// l ^ 32, bit for bit the same in both): two lane swaps between the halves of
+// the wave, without the LDS crossbar that a general shuffle uses.
+__device__ inline double gn_add_halves(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double lower = __builtin_bit_cast(double, ((unsigned long long)h[0] << 32) | l[0]);
+  const double upper = __builtin_bit_cast(double, ((unsigned long long)h[1] << 32) | l[1]);
+  return lower + upper;
+}
+
 // Barrier that orders LDS traffic only: outstanding global loads (the prefetch of
 // the next block row) stay in flight across it.
 __device__ inline void lds_barrier() {
@@ -134,7 +147,7 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
       acc += (double)LV[u] * yw[(u / CW) * TILE + (u % CW)];                             \
     const unsigned toffA = gn_after(toff, acc);                                          \
     GN_LOAD_FWD_LV(min(KK + 2, NB - 1), LV, toffA)                                       \
-    acc += __shfl_xor(acc, 32);   /* the wave's two column groups, same row */           \
+    acc = gn_add_halves(acc);   /* the wave's two column groups, same row */             \
     if ((threadIdx.x & 63) < 32) red[gq >> 1][i] = acc;                                  \
     lds_barrier();                                                                       \
     double part = 0.0;                                                                   \
@@ -146,7 +159,7 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
     }                                                                                    \
     const unsigned toffP = gn_after(toff, part);                                         \
     GN_LOAD_FWD_DN(min(KK + 2, NB - 1), DN, toffP)                                       \
-    part += __shfl_xor(part, 32);                                                        \
+    part = gn_add_halves(part);                                                          \
     if ((threadIdx.x & 63) < 32) red2[gq >> 1][i] = part;                                \
     lds_barrier();                                                                       \
     if (gq == 0) {                                                                       \
@@ -202,7 +215,7 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
       acc += (double)LV[u] * xw[(u / CW) * TILE + (u % CW)];                             \
     const unsigned toffA = gn_after(toff, acc);                                          \
     GN_LOAD_BWD_LV(max(KK - 2, 0), LV, toffA)                                            \
-    acc += __shfl_xor(acc, 32);   /* the wave's two column groups, same row */           \
+    acc = gn_add_halves(acc);   /* the wave's two column groups, same row */             \
     if ((threadIdx.x & 63) < 32) red[gq >> 1][i] = acc;                                  \
     lds_barrier();                                                                       \
     double part = 0.0;                                                                   \
@@ -214,7 +227,7 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
     }                                                                                    \
     const unsigned toffP = gn_after(toff, part);                                         \
     GN_LOAD_BWD_DN(max(KK - 2, 0), DN, toffP)                                            \
-    part += __shfl_xor(part, 32);                                                        \
+    part = gn_add_halves(part);                                                          \
     if ((threadIdx.x & 63) < 32) red2[gq >> 1][i] = part;                                \
     lds_barrier();                                                                       \
     if (gq == 0) {                                                                       \
