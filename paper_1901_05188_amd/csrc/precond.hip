@@ -10,9 +10,10 @@
 //   the multi-column kernels of multi.hip with one live column.
 // k_coarse_fwd / k_coarse_bwd: y = Z^T (Z g) with Z = L_H^-1 stored as dense
 //   tiles (the coarse factor inverse), one workgroup per tile row / column.
-// k_prolong: gather-form sum z = sum_j R_j^T (t_j + Phi_j y_j): each output DOF
-//   visits the (at most 8) subdomains whose box holds it, in a fixed order, so
-//   the result is deterministic without atomics; fused with the partial r.z.
+// k_phi_add: t_j += Phi_j y_j, streamed per subdomain.
+// k_prolong: gather-form sum z = sum_j R_j^T t_j: each output DOF visits the
+//   (at most 8) subdomains whose box holds it, in a fixed order, so the result
+//   is deterministic without atomics; fused with the partial r.z.
 #include "gn_internal.h"
 
 namespace {
@@ -357,6 +358,25 @@ __global__ __launch_bounds__(NT) void k_prolong(const SubDesc* __restrict__ subs
   }
 }
 
+// t_j += Phi_j y_j on the rows of every subdomain's I box (a thread per row,
+// the rows of Phi_j contiguous), ahead of the gather, which then reads t_j only:
+// the same sum per (row, subdomain) in the same order as forming it inside the
+// gather, streamed over Phi instead of gathered node by node.
+__global__ __launch_bounds__(NT) void k_phi_add(const SubDesc* __restrict__ subs, const double* __restrict__ Phi,
+                                                const double* __restrict__ y, double* __restrict__ tvec,
+                                                const double* __restrict__ done) {
+  if (done && *done != 0.0) return;
+  const SubDesc& sd = subs[blockIdx.y];
+  const int row = blockIdx.x * NT + threadIdx.x;
+  const int m = sd.m;
+  if (m == 0 || row >= sd.nI) return;
+  const double* ph = Phi + sd.offPhi + (int64_t)row * m;
+  const double* yy = y + sd.coff;
+  double v = tvec[sd.offVI + row];
+  for (int k = 0; k < m; ++k) v += ph[k] * yy[k];
+  tvec[sd.offVI + row] = v;
+}
+
 }  // namespace
 
 namespace gnk {
@@ -471,8 +491,13 @@ int prolong_blocks(const gn_problem* p) { return (int)((p->n_node + NT - 1) / NT
 void prolong(const gn_problem* p, const gn_precond* pc, const double* r, double* z, double* part,
              const double* done, hipStream_t s) {
   PartAxes pa{pc->d_cnt[0], pc->d_cnt[1], pc->d_cnt[2], pc->d_plo[0], pc->d_plo[1], pc->d_plo[2]};
-  const double* Phi = pc->NH > 0 ? pc->d_Phi : nullptr;
   GnProfScope prof(PROF_PROLONG, pc->prolong_bytes, s);
+  if (pc->NH > 0) {
+    hipLaunchKernelGGL(k_phi_add, dim3((unsigned)((pc->maxNBI * TILE + NT - 1) / NT), (unsigned)pc->n_sub), dim3(NT),
+                       0, s, pc->d_sub, pc->d_Phi, pc->d_y, pc->d_t, done);
+    GN_CHECK_LAUNCH();
+  }
+  const double* Phi = nullptr;   // folded into the local vectors above
   dim3 grid((unsigned)((p->n_node + NT - 1) / NT));
   if (p->nc == 3)
     hipLaunchKernelGGL(k_prolong<3>, grid, dim3(NT), 0, s, pc->d_sub, p->nn[0], p->nn[1], p->nn[2],
