@@ -542,6 +542,31 @@ struct McAxes {
   const int* plo0; const int* plo1; const int* plo2;
 };
 
+// t_j(row, q) += sum_e Phi_j(row, e) y(coff_j + e, q) for the MC_K columns, a
+// thread per I-box row, streamed over Phi ahead of the gather
+__global__ __launch_bounds__(256) void k_phi_add_mc(const SubDesc* __restrict__ subs, const double* __restrict__ Phi,
+                                                    const double* __restrict__ y, int NHP, double* __restrict__ tm,
+                                                    int k, const double* __restrict__ scal) {
+  if (all_done(scal, k)) return;
+  const SubDesc& sd = subs[blockIdx.y];
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  const int m = sd.m;
+  if (m == 0 || row >= sd.nI) return;
+  const double* ph = Phi + sd.offPhi + (int64_t)row * m;
+  const double* yy = y + sd.coff;
+  double* tv = tm + (sd.offVI + row) * MC_K;
+  double a[MC_K];
+#pragma unroll
+  for (int q = 0; q < MC_K; ++q) a[q] = tv[q];
+  for (int e = 0; e < m; ++e) {
+    const double pv = ph[e];
+#pragma unroll
+    for (int q = 0; q < MC_K; ++q) a[q] += pv * yy[e + (int64_t)q * NHP];
+  }
+#pragma unroll
+  for (int q = 0; q < MC_K; ++q) tv[q] = a[q];
+}
+
 template <int NC>
 __global__ __launch_bounds__(256) void k_prolong_mc(const SubDesc* __restrict__ subs, int NX, int NY, int NZ,
                                                     int P0, int P1, McAxes pa, const uint8_t* __restrict__ dir,
@@ -718,15 +743,21 @@ void precond_mc(const gn_problem* p, const gn_precond* pc, const double* r, doub
   }
   {
     GnProfScope prof(PROF_PROLONG, pc->prolong_bytes, s);
+    if (Phi) {
+      hipLaunchKernelGGL(k_phi_add_mc, dim3((unsigned)((pc->maxNBI * TILE + 255) / 256), (unsigned)pc->n_sub),
+                         dim3(256), 0, s, pc->d_sub, Phi, ym, NHP, tm, k, scal);
+      GN_CHECK_LAUNCH();
+    }
     McAxes pa{pc->d_cnt[0], pc->d_cnt[1], pc->d_cnt[2], pc->d_plo[0], pc->d_plo[1], pc->d_plo[2]};
     dim3 grid((unsigned)((p->n_node + 255) / 256));
+    const double* nophi = nullptr;   // folded into the local vectors above
     if (p->nc == 3)
       hipLaunchKernelGGL(k_prolong_mc<3>, grid, dim3(256), 0, s, pc->d_sub, p->nn[0], p->nn[1], p->nn[2],
-                         pc->nparts[0], pc->nparts[1], pa, p->d_dir, tm, Phi, ym, NHP, r, z, p->n_dof, k, part,
+                         pc->nparts[0], pc->nparts[1], pa, p->d_dir, tm, nophi, ym, NHP, r, z, p->n_dof, k, part,
                          pstride, scal);
     else
       hipLaunchKernelGGL(k_prolong_mc<1>, grid, dim3(256), 0, s, pc->d_sub, p->nn[0], p->nn[1], p->nn[2],
-                         pc->nparts[0], pc->nparts[1], pa, p->d_dir, tm, Phi, ym, NHP, r, z, p->n_dof, k, part,
+                         pc->nparts[0], pc->nparts[1], pa, p->d_dir, tm, nophi, ym, NHP, r, z, p->n_dof, k, part,
                          pstride, scal);
     GN_CHECK_LAUNCH();
   }
