@@ -295,8 +295,8 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
   static_assert(W % 2 == 0 && WS % P == 0, "W / 2 must be a multiple of the prefetch depth");
   extern __shared__ double smem[];
   double* ring = smem;                      // W1 slots x TILE rows x RW columns (+16 pad)
-  double* sS = smem + ringlen;              // NCB exchange tiles, 32 x 16 (+1)
-  double* sP = sS + NCB * (TILE * 17);      // NCB partial tiles of the non-owner parity
+  double* sS = smem + ringlen;              // NCB right-hand-side tiles, 32 x 16 (+1)
+  double* sP = sS + NCB * (TILE * 17);      // partial sums [parity][block], 2 NCB tiles
   const SubDesc& sd = subs[blockIdx.x % n_sub];
   const int c0 = csplit > 1 ? (int)(blockIdx.x / n_sub) * (16 * NCB) : 0;
   const int RW = csplit > 1 ? 16 * NCB : b; // columns held in the ring
@@ -353,40 +353,33 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
     }                                                                                          \
   }
   // exchange, diagonal solve of the owned block and the store of block row K
-  // (to the ring slot K % W1 and to V); three LDS barriers for every wave
-#define R2_FINISH(K, LOADDV, KDV)                                                              \
+  // (to the ring slot K % W1 and to V); two LDS barriers for every wave
+#define R2_FINISH(K)                                                                           \
   {                                                                                            \
-    double dcur[8], vcur[4];                                                                   \
-    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dcur[ks] = dv[ks];                        \
-    _Pragma("unroll") for (int i = 0; i < 4; ++i) vcur[i] = vv[i];                             \
-    if (own >= 0) LOADDV(KDV)                                                                  \
     double psum[NCB][4];                                                                       \
     _Pragma("unroll") for (int q = 0; q < NCB; ++q)                                            \
       _Pragma("unroll") for (int i = 0; i < 4; ++i)                                            \
         psum[q][i] = ((acc[q][0][i] + acc[q][1][i]) + (acc[q][2][i] + acc[q][3][i])) +         \
                      ((acc[q][4][i] + acc[q][5][i]) + (acc[q][6][i] + acc[q][7][i]));          \
-    _Pragma("unroll") for (int q = 0; q < NCB; ++q) {                                          \
-      if (q != own) {                                                                          \
-        _Pragma("unroll") for (int i = 0; i < 4; ++i)                                          \
-          sP[q * (TILE * 17) + (rb + 4 * i + lk) * 17 + lr] = psum[q][i];                      \
-      }                                                                                        \
-    }                                                                                          \
-    geneo_lds_barrier();                                                                       \
+    /* every wave leaves its partial sums of all blocks, the owner its right-hand */          \
+    /* side; after one barrier the owner forms S = V - (P0 + P1) as it reads it */             \
+    _Pragma("unroll") for (int q = 0; q < NCB; ++q)                                            \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i)                                            \
+        sP[(half * NCB + q) * (TILE * 17) + (rb + 4 * i + lk) * 17 + lr] = psum[q][i];         \
     if (own >= 0) {                                                                            \
-      double mine[4];                                                                          \
-      _Pragma("unroll") for (int i = 0; i < 4; ++i) mine[i] = own == 0 ? psum[0][i] : psum[NCB - 1][i]; \
-      _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                          \
-        const int o = own * (TILE * 17) + (rb + 4 * i + lk) * 17 + lr;                         \
-        sS[o] = vcur[i] - (mine[i] + sP[o]);                                                   \
-      }                                                                                        \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i)                                            \
+        sS[own * (TILE * 17) + (rb + 4 * i + lk) * 17 + lr] = vv[i];                           \
     }                                                                                          \
     geneo_lds_barrier();                                                                       \
     if (own >= 0) {                                                                            \
       gn_d4 dq[4];                                                                             \
       _Pragma("unroll") for (int u = 0; u < 4; ++u) dq[u] = gn_d4{0, 0, 0, 0};                 \
-      _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                         \
-        dq[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(                                     \
-            dcur[ks], sS[own * (TILE * 17) + (4 * ks + lk) * 17 + lr], dq[ks & 3], 0, 0, 0);   \
+      _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) {                                       \
+        const int o = (4 * ks + lk) * 17 + lr;                                                 \
+        const double sk = sS[own * (TILE * 17) + o] -                                          \
+                          (sP[own * (TILE * 17) + o] + sP[(NCB + own) * (TILE * 17) + o]);     \
+        dq[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[ks], sk, dq[ks & 3], 0, 0, 0);    \
+      }                                                                                        \
       double* yk = ring + ((K) % W1) * rstride;                                                \
       _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                          \
         const int row = rb + 4 * i + lk;                                                       \
@@ -415,12 +408,16 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
   }
 #pragma unroll
   for (int sl = 0; sl < P; ++sl) R2_LOAD_A_FWD(sl, 0, 2 * sl + half)
-  if (own >= 0) R2_LOAD_DV_FWD(0)
   __syncthreads();
   for (int K = 0; K < NB; ++K) {
+    // the diagonal tile and right-hand side of row K, loaded here and used in
+    // its exchange: the products cover their latency, and no register is copied
+    // before a reload (which would make the wave wait for every load in flight,
+    // the next row's band tiles included)
+    if (own >= 0) R2_LOAD_DV_FWD(K)
     // ring slot of tile t of row K: block K - w + t, i.e. (K + 1 + t) % W1
     R2_PRODUCTS(K, min(K + 1, NB - 1), (K + 1 + half) % W1, R2_LOAD_A_FWD)
-    R2_FINISH(K, R2_LOAD_DV_FWD, min(K + 1, NB - 1))
+    R2_FINISH(K)
   }
 #undef R2_LOAD_DV_FWD
 #undef R2_LOAD_A_FWD
@@ -444,12 +441,12 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
   }
 #pragma unroll
   for (int sl = 0; sl < P; ++sl) R2_LOAD_A_BWD(sl, NB - 1, 2 * sl + half)
-  if (own >= 0) R2_LOAD_DV_BWD(NB - 1)
   __syncthreads();
   for (int K = NB - 1; K >= 0; --K) {
+    if (own >= 0) R2_LOAD_DV_BWD(K)
     // ring slot of tile t of row K: block K + 1 + t
     R2_PRODUCTS(K, max(K - 1, 0), (K + 1 + half) % W1, R2_LOAD_A_BWD)
-    R2_FINISH(K, R2_LOAD_DV_BWD, max(K - 1, 0))
+    R2_FINISH(K)
   }
 #undef R2_LOAD_DV_BWD
 #undef R2_LOAD_A_BWD
@@ -1360,13 +1357,13 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
     int cs2 = (b + 16 * ncb2 - 1) / (16 * ncb2);
     int rw2 = cs2 > 1 ? 16 * ncb2 : b;
     int rl2 = maxw1 * TILE * rw2 + 32;
-    size_t lds2 = sizeof(double) * ((size_t)rl2 + (size_t)2 * ncb2 * TILE * 17);
+    size_t lds2 = sizeof(double) * ((size_t)rl2 + (size_t)3 * ncb2 * TILE * 17);
     if (lds2 > 160 * 1024 && ncb2 == 2) {
       ncb2 = 1;
       cs2 = (b + 15) / 16;
       rw2 = cs2 > 1 ? 16 : b;
       rl2 = maxw1 * TILE * rw2 + 32;
-      lds2 = sizeof(double) * ((size_t)rl2 + (size_t)2 * TILE * 17);
+      lds2 = sizeof(double) * ((size_t)rl2 + (size_t)3 * TILE * 17);
     }
     const int W2 = std::max(6, (maxw + 5) / 6 * 6);
     if (lds2 <= 160 * 1024 && W2 <= 30 && pc->d_z0 && TB) {
