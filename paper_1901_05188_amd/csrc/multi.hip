@@ -369,6 +369,10 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
       const FT* tile = (t < w) ? Tb + ((int64_t)KK * W1 + t) * TILE2 : Z0;                      \
       _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) av[s][ks] = tile[(4 * ks + lk) * TILE + rb + lr]; \
     }                                                                                           \
+  }
+#define MC_LOAD_DV_FWD(K_)                                                                      \
+  {                                                                                             \
+    const int KK = (K_);                                                                        \
     if (lead) {                                                                                 \
       const FT* dk = Db + (int64_t)KK * TILE2;                                                  \
       _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dv[ks] = to_d(dk[(4 * ks + lk) * TILE + rb + lr]); \
@@ -378,6 +382,10 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
   MC_LOAD_FWD(0)
   __syncthreads();
   for (int K = 0; K < NB; ++K) {
+    // the diagonal tile and right-hand side of row K are loaded here and used in
+    // its exchange, without a copy before a reload (a copy of registers still
+    // being loaded makes the wave wait for every load in flight)
+    if (lead) MC_LOAD_DV_FWD(K)
     MC_ZERO4()
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
@@ -389,11 +397,6 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
         acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(to_d(av[s][ks]), yb[(4 * ks + lk) * MC_K + lr],
                                                            acc[ks & 3], 0, 0, 0);
     }
-    double dcur[8], vcur[4];
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) dcur[ks] = dv[ks];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) vcur[i] = vv[i];
     MC_LOAD_FWD(min(K + 1, NB - 1))
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -403,7 +406,7 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = rb + 4 * i + lk;
-        sS[row][lr] = vcur[i] - ((red[0][row][lr] + red[1][row][lr]) + (red[2][row][lr] + red[3][row][lr]));
+        sS[row][lr] = vv[i] - ((red[0][row][lr] + red[1][row][lr]) + (red[2][row][lr] + red[3][row][lr]));
       }
     }
     mc_lds_barrier();
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
       MC_ZERO4()
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks)
-        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dcur[ks], sS[4 * ks + lk][lr], acc[ks & 3], 0, 0, 0);
+        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[ks], sS[4 * ks + lk][lr], acc[ks & 3], 0, 0, 0);
       double* yb = ring + (K % W1) * TILE * MC_K;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -424,6 +427,7 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
     mc_lds_barrier();
   }
 #undef MC_LOAD_FWD
+#undef MC_LOAD_DV_FWD
   for (int e = threadIdx.x; e < W1 * TILE * MC_K; e += 512) ring[e] = 0.0;
   // backward tile of slot s at block row K: L(K + d, K)^T, d = 1 + kg + 4 s,
   // tile d - 1 of row K of the transposed band (zero past the last block row),
@@ -437,6 +441,10 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
       const FT* tile = (d <= w) ? TBb + ((int64_t)KK * W1 + (d - 1)) * TILE2 : Z0;              \
       _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) av[s][ks] = tile[(4 * ks + lk) * TILE + rb + lr]; \
     }                                                                                           \
+  }
+#define MC_LOAD_DV_BWD(K_)                                                                      \
+  {                                                                                             \
+    const int KK = (K_);                                                                        \
     if (lead) {                                                                                 \
       const FT* dk = TBb + ((int64_t)KK * W1 + w) * TILE2;                                      \
       _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) dv[ks] = to_d(dk[(4 * ks + lk) * TILE + rb + lr]); \
@@ -446,6 +454,7 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
   MC_LOAD_BWD(NB - 1)
   __syncthreads();
   for (int K = NB - 1; K >= 0; --K) {
+    if (lead) MC_LOAD_DV_BWD(K)
     MC_ZERO4()
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
@@ -459,11 +468,6 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
         acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(to_d(av[s][ks]), bval, acc[ks & 3], 0, 0, 0);
       }
     }
-    double dcur[8], vcur[4];
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) dcur[ks] = dv[ks];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) vcur[i] = vv[i];
     MC_LOAD_BWD(max(K - 1, 0))
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = rb + 4 * i + lk;
-        sS[row][lr] = vcur[i] - ((red[0][row][lr] + red[1][row][lr]) + (red[2][row][lr] + red[3][row][lr]));
+        sS[row][lr] = vv[i] - ((red[0][row][lr] + red[1][row][lr]) + (red[2][row][lr] + red[3][row][lr]));
       }
     }
     mc_lds_barrier();
@@ -481,7 +485,7 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
       MC_ZERO4()
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks)
-        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dcur[ks], sS[4 * ks + lk][lr], acc[ks & 3], 0, 0, 0);
+        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[ks], sS[4 * ks + lk][lr], acc[ks & 3], 0, 0, 0);
       double* xb = ring + (K % W1) * TILE * MC_K;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -494,6 +498,7 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
     mc_lds_barrier();
   }
 #undef MC_LOAD_BWD
+#undef MC_LOAD_DV_BWD
 #undef MC_ZERO4
 }
 
