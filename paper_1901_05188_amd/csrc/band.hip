@@ -229,13 +229,21 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
 #define BC_LOAD(XA, YB, T2)                                                                    \
   {                                                                                            \
     if (RL) {                                                                                  \
+      /* on the diagonal Y = X; the uniform test sits outside the loads, so that */            \
+      /* each case is straight-line code (not a branch around every load) */                   \
       const double* xl = rowL + (T2) * (TILE * (TILE + 1));                                    \
-      const double* yp = T + tile_off(br.offT, J, (T2) - t + w, w);                            \
       _Pragma("unroll") for (int q = 0; q < 2; ++q)                                            \
-        _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) {                                     \
+        _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                       \
           XA[q][ks] = xl[(4 * ks + lk) * (TILE + 1) + q * 16 + lr];                            \
-          YB[q][ks] = (t == w) ? XA[q][ks] : yp[(4 * ks + lk) * TILE + q * 16 + lr];           \
-        }                                                                                      \
+      if (t == w) {                                                                            \
+        _Pragma("unroll") for (int q = 0; q < 2; ++q)                                          \
+          _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) YB[q][ks] = XA[q][ks];              \
+      } else {                                                                                 \
+        const double* yp = T + tile_off(br.offT, J, (T2) - t + w, w);                          \
+        _Pragma("unroll") for (int q = 0; q < 2; ++q)                                          \
+          _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                     \
+            YB[q][ks] = yp[(4 * ks + lk) * TILE + q * 16 + lr];                                \
+      }                                                                                        \
     } else {                                                                                   \
       const double* xp = T + tile_off(br.offT, K, (T2), w);                                    \
       const double* yp = (t == w) ? xp : T + tile_off(br.offT, J, (T2) - t + w, w);            \
