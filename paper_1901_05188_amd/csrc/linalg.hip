@@ -28,17 +28,22 @@ __global__ __launch_bounds__(256) void k_spmv(int NX, int NY, int NZ, const doub
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    // scalar case: the assembled stencil holds exact zeros for neighbours
+    // outside the grid, so their index is only clamped into range (0 * x adds
+    // nothing): 27 unconditional loads, no divergent branches.  Elasticity keeps
+    // the branches (its 27 x 12 unconditional loads would not fit the registers).
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
-      if (k + dz < 0 || k + dz >= NZ) continue;
+      if (NC > 1 && (k + dz < 0 || k + dz >= NZ)) continue;
 #pragma unroll
       for (int dy = -1; dy <= 1; ++dy) {
-        if (j + dy < 0 || j + dy >= NY) continue;
+        if (NC > 1 && (j + dy < 0 || j + dy >= NY)) continue;
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
-          if (i + dx < 0 || i + dx >= NX) continue;
+          if (NC > 1 && (i + dx < 0 || i + dx >= NX)) continue;
           const int d = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
           int64_t nb = node + dx + (int64_t)NX * (dy + (int64_t)NY * dz);
+          if (NC == 1) nb = nb < 0 ? 0 : (nb >= n_node ? n_node - 1 : nb);
           double xv[NC];
 #pragma unroll
           for (int c2 = 0; c2 < NC; ++c2) xv[c2] = x[nb * NC + c2];
