@@ -92,11 +92,19 @@ __global__ __launch_bounds__(NT) void k_extract_b(const SubDesc* __restrict__ su
   }
 }
 
-// out = B V for b columns: thread per (row, 8-column chunk)
+// out = B V for b columns. A thread computes R consecutive nodes (one
+// component) of one BCW-column chunk. Consecutive nodes lie along the fastest
+// local axis a0 (the box's shortest), where the neighbours of R nodes are R + 2
+// consecutive rows: each of the nine neighbour lines (offsets along the two
+// other axes) costs R + 2 row loads instead of 3 R.
+constexpr int BCW = 4;
+template <int NC>
+constexpr int bapply_rows() { return NC == 1 ? 4 : 2; }
 template <int NC>
 __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs, const double* __restrict__ BE,
                                                int b, const double* __restrict__ V, double* __restrict__ out,
                                                int gx, int ntot) {
+  constexpr int R = bapply_rows<NC>();
   // consecutive workgroups are dealt round-robin to the 8 XCDs; the 1-D grid
   // holds 8 * per workgroups and is remapped so that each XCD walks a
   // contiguous range of items (subdomain, row block): the neighbour rows of a
@@ -108,10 +116,12 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
   const int bx = item % gx, by = item / gx;
   const SubDesc& sd = subs[by];
   const int npad = sd.NBB * TILE;
-  const int nchunk = (b + 7) / 8;
+  const int nchunk = (b + BCW - 1) / BCW;
   const int tid = bx * NT + threadIdx.x;
-  const int r = tid / nchunk, col0 = (tid % nchunk) * 8;
-  if (r >= npad) return;
+  const int col0 = (tid % nchunk) * BCW;
+  const int c = (tid / nchunk) % NC;
+  const int ln0 = (tid / nchunk / NC) * R;
+  if (ln0 * NC + c >= npad) return;
   const double* Vb = V + sd.offVB * b;
   const double* base = BE + sd.offVB * (27 * NC);
   // local node strides along the global axes
@@ -119,30 +129,76 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
   st[sd.permB[0]] = 1;
   st[sd.permB[1]] = sd.bn[sd.permB[0]];
   st[sd.permB[2]] = sd.bn[sd.permB[0]] * sd.bn[sd.permB[1]];
-  const int ln = r / NC;
   const int nmax = sd.nB - 1;
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll 9
-  for (int d = 0; d < 27; ++d) {
-    const int dn = (d % 3 - 1) * st[0] + ((d / 3) % 3 - 1) * st[1] + (d / 9 - 1) * st[2];
+  double acc[R][BCW];
 #pragma unroll
-    for (int c2 = 0; c2 < NC; ++c2) {
-      double bv = base[(int64_t)(d * NC + c2) * npad + r];
-      // B = X A_O X vanishes away from the overlap: rows of the subdomain's
-      // core, and neighbours outside overlap elements, carry bv = 0 and skip
-      // their V loads (whole waves of rows at once, the zeros come in blocks)
-      if (bv == 0.0) continue;
-      int r2 = min(max((ln + dn) * NC + c2, 0), nmax);   // out-of-box neighbours have bv = 0
-      // a chunk may run up to 7 columns past the row end into the next row or the
-      // 64-double tail of the buffer: loads stay in bounds, stores are masked
-      const double* vr = Vb + (int64_t)r2 * b + col0;
+  for (int i = 0; i < R; ++i)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] += bv * vr[q];
+    for (int q = 0; q < BCW; ++q) acc[i][q] = 0.0;
+  // coefficient plane of neighbour (o_x, o_y, o_z) in {0,1,2}^3: o_x + 3 o_y + 9 o_z
+  const int a0 = sd.permB[0];
+  const int ax1 = a0 == 0 ? 1 : 0, ax2 = a0 == 2 ? 1 : 2;
+  const int s0 = a0 == 0 ? 1 : (a0 == 1 ? 3 : 9);
+  const int s1 = ax1 == 0 ? 1 : 3, s2 = ax2 == 1 ? 3 : 9;
+  // B = X A_O X vanishes on the core of the subdomain and on neighbours outside
+  // overlap elements, and the zeros come in blocks of rows: a line whose
+  // coefficients are zero on every lane of the wave is skipped. A lane with a
+  // zero coefficient on a line that runs adds 0 * v = +-0, which leaves its
+  // sums unchanged (v is finite: row indices are clamped into the box and the
+  // buffers' tails are zero). The sums run line by line, then along a0,
+  // components innermost; with a0 = x that is the plane order.
+#pragma unroll
+  for (int yz = 0; yz < 9; ++yz) {
+    const int o1 = yz % 3, o2 = yz / 3;
+    const int dn = (o1 - 1) * st[ax1] + (o2 - 1) * st[ax2];
+    const int dl = o1 * s1 + o2 * s2;
+    double bv[R][3][NC];
+    bool nz = false;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int row = (ln0 + i) * NC + c;
+      const bool rin = row < npad;
+      const int rowc = rin ? row : npad - 1;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2) {
+          const double t = base[(int64_t)((dl + dx * s0) * NC + c2) * npad + rowc];
+          bv[i][dx][c2] = rin ? t : 0.0;
+          nz |= bv[i][dx][c2] != 0.0;
+        }
     }
+    if (!__any(nz)) continue;
+    // rows of nodes ln0 - 1 .. ln0 + R on this line; out-of-box neighbours have bv = 0
+    double v[R + 2][NC][BCW];
+#pragma unroll
+    for (int j = 0; j < R + 2; ++j)
+#pragma unroll
+      for (int c2 = 0; c2 < NC; ++c2) {
+        const int r2 = min(max((ln0 - 1 + j + dn) * NC + c2, 0), nmax);
+        // a chunk may run up to BCW - 1 columns past the row end into the next
+        // row or the 64-double tail of the buffer: loads stay in bounds, stores are masked
+        const double* vr = Vb + (int64_t)r2 * b + col0;
+#pragma unroll
+        for (int q = 0; q < BCW; ++q) v[j][c2][q] = vr[q];
+      }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2)
+#pragma unroll
+          for (int q = 0; q < BCW; ++q) acc[i][q] += bv[i][dx][c2] * v[i + dx][c2][q];
   }
 #pragma unroll
-  for (int q = 0; q < 8; ++q)
-    if (col0 + q < b) out[sd.offVB * b + (int64_t)r * b + col0 + q] = acc[q];
+  for (int i = 0; i < R; ++i) {
+    const int row = (ln0 + i) * NC + c;
+    if (row < npad)
+#pragma unroll
+      for (int q = 0; q < BCW; ++q)
+        if (col0 + q < b) out[sd.offVB * b + (int64_t)row * b + col0 + q] = acc[i][q];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1334,8 +1390,12 @@ void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double
 
 void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int b, int maxNBB,
                 const double* V, double* out, hipStream_t s) {
-  const int nchunk = (b + 7) / 8;
-  const int gx = (maxNBB * TILE * nchunk + NT - 1) / NT;
+  const int nchunk = (b + BCW - 1) / BCW;
+  const int nc = p->nc;
+  const int R = nc == 3 ? bapply_rows<3>() : bapply_rows<1>();
+  // threads per subdomain: node groups of R x components x column chunks
+  const int64_t nodes = (maxNBB * TILE + nc - 1) / nc;
+  const int gx = (int)((((nodes + R - 1) / R) * nc * nchunk + NT - 1) / NT);
   const int ntot = gx * pc->n_sub;
   dim3 grid((unsigned)(8 * ((ntot + 7) / 8)));
   if (p->nc == 3)
