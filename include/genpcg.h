@@ -226,7 +226,10 @@ typedef struct gn_solve_report {
   double t_solve_s;
   int32_t iters_first;  /* iterations of the first (un-restarted) CG sequence   */
   int32_t restarts;     /* restarts from b - A x taken to meet rtol on the true residual
-                           (at most 2; none once ||b - A x|| <= eps || |A| |x| ||)     */
+                           (at most 2; none once ||b - A x|| <= eps || |A| |x| ||); a
+                           restarted sequence stops at max(rtol - res_floor, rtol / 2)
+                           on its recursive residual, so that its drift of about
+                           res_floor still leaves b - A x within rtol              */
   double res_floor;     /* eps || |A| |x| || / ||b||: rounding floor of the true
                            residual of an FP64 solution                          */
 } gn_solve_report;

@@ -1319,11 +1319,15 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
     // restart from the current iterate with the true residual, at most twice,
     // unless b - A x already sits at the rounding floor of FP64 x
     int restarts = 0;
-    for (; restarts < 2 && hs[S_BREAK] == 0.0 && hs[S_BB] > 0.0 && tr > hs[S_TOL2] &&
+    const double tol2 = hs[S_TOL2];   // rtol^2 ||b||^2
+    double tol2r = 0.0;
+    for (; restarts < 2 && hs[S_BREAK] == 0.0 && hs[S_BB] > 0.0 && tr > tol2 &&
            tr > kFloorFactor * kFloorFactor * floor2 && iters < opts->maxit;
          ++restarts) {
       gnk::sub_partial(n, p->d_z, p->d_q, p->d_r, p->d_part, s);   // r = b - A x
       gnk::finalize(p->d_part, nbr, OP_RESTART, scal, p->d_hist, opts->rtol, s);
+      tol2r = gnh::restart_tol2(opts->rtol, floor2, hs[S_BB]);
+      GN_HIP(hipMemcpyAsync(scal + S_TOL2, &tol2r, sizeof(double), hipMemcpyHostToDevice, s));
       if (pc) {
         precond_full(p, pc, p->d_r, p->d_z, p->d_part, done, s);
         gnk::finalize(p->d_part, nbp, OP_RZ0, scal, p->d_hist, opts->rtol, s);
@@ -1344,7 +1348,7 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
       GN_HIP(hipMemcpyAsync(hist.data(), p->d_hist, sizeof(double) * 2 * kit, hipMemcpyDeviceToHost, s));
     gnk::gather_free(p, p->d_x, x_dev + col * ld, s);
     GN_HIP(hipStreamSynchronize(s));
-    bool conv = bb == 0.0 || rr <= hs[S_TOL2];
+    bool conv = bb == 0.0 || rr <= tol2;
     if (hs[S_BREAK] != 0.0) ret = GN_ERR_BREAKDOWN;
     else if (!conv && ret == GN_OK) ret = GN_WARN_MAXIT;
     if (reports) {

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include <string>
 #include <vector>
 
@@ -279,6 +282,15 @@ namespace gnh {
 constexpr double kEps = 2.220446049250313e-16;
 // restarts stop once b - A x is within this factor of eps || |A| |x| ||
 constexpr double kFloorFactor = 1.0;
+// Squared stopping level of a restarted CG sequence, relative to ||b||^2 = bb.
+// Its recursive residual tracks b - A x only to within about the rounding floor
+// eps || |A| |x| || (squared: floor2), so a sequence that stops at rtol leaves
+// b - A x at rtol plus that drift. A restart therefore aims below rtol by the
+// floor, at no less than rtol / 2. The convergence test stays rtol.
+inline double restart_tol2(double rtol, double floor2, double bb) {
+  const double rt = std::max(rtol - std::sqrt(floor2 / bb), 0.5 * rtol);
+  return rt * rt * bb;
+}
 double now_s();
 double absmv_norm2(gn_problem* p, const double* x, hipStream_t s);
 double cond_from_hist(const double* hist, int kit);

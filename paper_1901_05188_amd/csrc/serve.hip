@@ -196,8 +196,11 @@ void SlotEngine::step(std::vector<SlotResult>& out) {
     // the recursive residual drifts from b - A x (attainable accuracy of CG):
     // restart from b - A x unless it meets the tolerance or sits at the
     // rounding floor eps || |A| |x| || of an FP64 solution
-    const bool re = sl.restarts < 2 && h[S_BREAK] == 0.0 && h[S_BB] > 0.0 && t > h[S_TOL2] &&
+    const double tol2 = sl.col.rtol * sl.col.rtol * h[S_BB];
+    const bool re = sl.restarts < 2 && h[S_BREAK] == 0.0 && h[S_BB] > 0.0 && t > tol2 &&
                     t > kFloorFactor * kFloorFactor * floor2[c] && (int)h[S_ITER] < (int)h[S_MAXIT];
+    // a restarted sequence stops below rtol (uploaded with the scalars by phase_begin)
+    if (re) hsc_[(size_t)c * S_N + S_TOL2] = gnh::restart_tol2(sl.col.rtol, floor2[c], h[S_BB]);
     (re ? again : retire).push_back(c);
   }
   if (!again.empty()) {
@@ -227,7 +230,7 @@ void SlotEngine::step(std::vector<SlotResult>& out) {
     Slot& sl = slot_[c];
     const double* h = sl.fin.data();
     const double bb = h[S_BB], rr = h[S_RR];
-    const bool conv = bb == 0.0 || rr <= h[S_TOL2];
+    const bool conv = bb == 0.0 || rr <= sl.col.rtol * sl.col.rtol * bb;
     SlotResult r;
     r.col = sl.col;
     r.st = h[S_BREAK] != 0.0 ? GN_ERR_BREAKDOWN : (conv ? GN_OK : GN_WARN_MAXIT);
