@@ -490,20 +490,39 @@ __global__ __launch_bounds__(NT) void k_band_chol(const BandRef* __restrict__ ma
 template <typename FT>
 __global__ __launch_bounds__(256) void k_band_transpose(const BandRef* __restrict__ refs, const double* __restrict__ T,
                                                        const double* __restrict__ D, FT* __restrict__ TB) {
+  // each of the four waves moves one tile per round: contiguous loads into a
+  // padded LDS tile, then contiguous stores of its transpose
+  __shared__ double sT[4][TILE * (TILE + 1)];
   const BandRef rf = refs[blockIdx.y];
   const int K = blockIdx.x;
   if (K >= rf.NB) return;
   const int w = rf.w, W1 = w + 1;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* st = sT[wv];
   FT* out = TB + (rf.offT + (int64_t)K * W1) * TILE2;
-  for (int d = 1; d <= w + 1; ++d) {
+  for (int d0 = 1; d0 <= w + 1; d0 += 4) {
+    const int d = d0 + wv;
     const double* src = nullptr;
     if (d <= w && K + d < rf.NB) src = T + (rf.offT + (int64_t)(K + d) * W1 + (w - d)) * TILE2;
     if (d == w + 1) src = D + (rf.offD + (int64_t)K) * TILE2;
-    FT* o = out + (int64_t)(d - 1) * TILE2;
-    for (int e = threadIdx.x; e < TILE2; e += 256) {
-      const int i = e % TILE, rr = e / TILE;   // output (row i, column rr) at rr * TILE + i
-      o[e] = src ? (FT)src[i * TILE + rr] : (FT)0;
+    if (src) {
+#pragma unroll
+      for (int j = 0; j < TILE2 / 64; ++j) {
+        const int e = j * 64 + lane;   // source (row e % TILE, column e / TILE)
+        st[(e / TILE) * (TILE + 1) + e % TILE] = src[e];
+      }
     }
+    __syncthreads();
+    if (d <= w + 1) {
+      FT* o = out + (int64_t)(d - 1) * TILE2;
+#pragma unroll
+      for (int j = 0; j < TILE2 / 64; ++j) {
+        const int e = j * 64 + lane;   // output (row i, column rr) at rr * TILE + i
+        const int i = e % TILE, rr = e / TILE;
+        o[e] = src ? (FT)st[i * (TILE + 1) + rr] : (FT)0;
+      }
+    }
+    __syncthreads();
   }
 }
 
