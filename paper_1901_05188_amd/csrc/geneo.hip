@@ -100,11 +100,16 @@ __global__ __launch_bounds__(NT) void k_extract_b(const SubDesc* __restrict__ su
 constexpr int BCW = 4;
 template <int NC>
 constexpr int bapply_rows() { return NC == 1 ? 4 : 2; }
+// Rows of B coefficients a workgroup touches, as an upper bound: its threads
+// cover at most NT / (nchunk NC) + 2 node groups of R nodes.
 template <int NC>
+constexpr int bapply_span(int nchunk) { return (NT / (nchunk * NC) + 2) * bapply_rows<NC>() * NC; }
+template <int NC, bool LDSC>
 __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs, const double* __restrict__ BE,
                                                int b, const double* __restrict__ V, double* __restrict__ out,
                                                int gx, int ntot) {
   constexpr int R = bapply_rows<NC>();
+  extern __shared__ double sBE[];   // LDSC: the workgroup's coefficient rows, 27 NC planes of span
   // consecutive workgroups are dealt round-robin to the 8 XCDs; the 1-D grid
   // holds 8 * per workgroups and is remapped so that each XCD walks a
   // contiguous range of items (subdomain, row block): the neighbour rows of a
@@ -121,9 +126,20 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
   const int col0 = (tid % nchunk) * BCW;
   const int c = (tid / nchunk) % NC;
   const int ln0 = (tid / nchunk / NC) * R;
-  if (ln0 * NC + c >= npad) return;
   const double* Vb = V + sd.offVB * b;
   const double* base = BE + sd.offVB * (27 * NC);
+  // LDSC: the coefficients of the workgroup's rows are loaded once, contiguously,
+  // instead of by each of the nchunk lanes that share a row
+  const int span = bapply_span<NC>(nchunk);
+  const int row_lo = ((bx * NT) / (nchunk * NC)) * R * NC;
+  if (LDSC) {
+    for (int f = threadIdx.x; f < 27 * NC * span; f += NT) {
+      const int pl = f / span, rr = row_lo + f % span;
+      sBE[f] = rr < npad ? base[(int64_t)pl * npad + rr] : 0.0;
+    }
+    __syncthreads();
+  }
+  if (ln0 * NC + c >= npad) return;
   // local node strides along the global axes
   int st[3];
   st[sd.permB[0]] = 1;
@@ -163,7 +179,8 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
       for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
         for (int c2 = 0; c2 < NC; ++c2) {
-          const double t = base[(int64_t)((dl + dx * s0) * NC + c2) * npad + rowc];
+          const int pl = (dl + dx * s0) * NC + c2;
+          const double t = LDSC ? sBE[pl * span + (rowc - row_lo)] : base[(int64_t)pl * npad + rowc];
           bv[i][dx][c2] = rin ? t : 0.0;
           nz |= bv[i][dx][c2] != 0.0;
         }
@@ -1398,10 +1415,20 @@ void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int
   const int gx = (int)((((nodes + R - 1) / R) * nc * nchunk + NT - 1) / NT);
   const int ntot = gx * pc->n_sub;
   dim3 grid((unsigned)(8 * ((ntot + 7) / 8)));
-  if (p->nc == 3)
-    hipLaunchKernelGGL(k_bapply<3>, grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out, gx, ntot);
-  else
-    hipLaunchKernelGGL(k_bapply<1>, grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out, gx, ntot);
+  // coefficient rows in LDS when they fit in 48 KB (b >= 17 scalar, b >= 29 elasticity)
+  const size_t lds = sizeof(double) * 27 * nc * (nc == 3 ? bapply_span<3>(nchunk) : bapply_span<1>(nchunk));
+  const bool in_lds = lds <= 48 * 1024;
+  if (nc == 3) {
+    if (in_lds)
+      hipLaunchKernelGGL((k_bapply<3, true>), grid, dim3(NT), lds, s, pc->d_sub, BE, b, V, out, gx, ntot);
+    else
+      hipLaunchKernelGGL((k_bapply<3, false>), grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out, gx, ntot);
+  } else {
+    if (in_lds)
+      hipLaunchKernelGGL((k_bapply<1, true>), grid, dim3(NT), lds, s, pc->d_sub, BE, b, V, out, gx, ntot);
+    else
+      hipLaunchKernelGGL((k_bapply<1, false>), grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out, gx, ntot);
+  }
   GN_CHECK_LAUNCH();
 }
 
