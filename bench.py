@@ -293,7 +293,7 @@ def main():
         print(json.dumps(out))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only"}))
+        print(json.dumps({"error": "the solver runs on one GPU; sharding over several GPUs is not implemented"}))
         sys.exit(2)
     import numpy as np
     import torch
