@@ -373,7 +373,20 @@ __global__ __launch_bounds__(NT) void k_phi_add(const SubDesc* __restrict__ subs
   const double* ph = Phi + sd.offPhi + (int64_t)row * m;
   const double* yy = y + sd.coff;
   double v = tvec[sd.offVI + row];
-  for (int k = 0; k < m; ++k) v += ph[k] * yy[k];
+  // eight coefficients of the row in flight at once (indices clamped into the
+  // row), then the products in order k = 0 .. m - 1
+  for (int k0 = 0; k0 < m; k0 += 8) {
+    double p[8], q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = min(k0 + u, m - 1);
+      p[u] = ph[k];
+      q[u] = yy[k];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < m) v += p[u] * q[u];
+  }
   tvec[sd.offVI + row] = v;
 }
 
