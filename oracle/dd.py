@@ -20,7 +20,9 @@ Readings:
   of Omega_j; those of V_{h,0}(Omega_j) ("I_j") are the free DOFs at nodes
   all of whose adjacent elements lie in Omega_j;
 * the PoU counts, for each DOF, the subdomains whose I_j contains it (the
-  count over closures would break the partition-of-unity identity).
+  count over closures would break the partition-of-unity identity);
+* the smoother PoU the paper also provides (Sarkis) weights each subdomain by
+  the distance to its artificial boundary (see ``_sarkis_pou``).
 
 Every set is computed by brute force from these definitions (membership
 counts over all subdomains), not from box arithmetic.
@@ -95,13 +97,56 @@ class Decomposition:
         self.count = cnt
         if np.any(cnt == 0):
             raise ValueError("some free DOF lies in no V_h0(Omega_j): overlap too small")
-        # PoU diagonal on Ibar_j: 1/c on I_j, 0 on Ibar_j \ I_j
-        self.X = []
+        self.pou = getattr(w, "pou", "standard")
+        if self.pou == "standard":
+            # PoU diagonal on Ibar_j: 1/c on I_j, 0 on Ibar_j \ I_j
+            self.X = []
+            for Ib, I in zip(self.Ibar, self.I):
+                x = np.zeros(len(Ib))
+                pos = np.searchsorted(Ib, I)
+                x[pos] = 1.0 / cnt[I]
+                self.X.append(x)
+        elif self.pou == "sarkis":
+            self.X = self._sarkis_pou()
+        else:
+            raise ValueError(f"unknown partition of unity {self.pou!r}")
+
+    def _sarkis_pou(self):
+        """Smooth PoU (Section 3.2, the Sarkis variant named after def:pou, and
+        Section 3.3.1): the weight of subdomain j at a DOF of V_h0(Omega_j) is
+        the distance of its node to the artificial boundary of Omega_j, and
+        X_j = w_j / sum_k w_k.  Reading: the artificial boundary is the set of
+        nodes of Omega_j that touch an element outside Omega_j (Ibar_j minus
+        I_j), distances are measured on the node lattice as the largest index
+        difference over the three axes (one element layer = 1), and a
+        subdomain without artificial boundary (a single subdomain) has weight 1.
+        Computed by brute force over all pairs of nodes."""
+        w = self.w
+        nc = w.ncomp
+        nx, ny = w.ne[0] + 1, w.ne[1] + 1
+        full = w.free_index()
+        def ijk(nodes):
+            return np.stack([nodes % nx, (nodes // nx) % ny, nodes // (nx * ny)], axis=1)
+        weights = []
         for Ib, I in zip(self.Ibar, self.I):
+            nodes_I = full[I] // nc
+            nodes_bd = np.setdiff1d(full[Ib] // nc, nodes_I)
+            wj = np.ones(len(I))
+            if len(nodes_bd):
+                P, S = ijk(nodes_I), ijk(nodes_bd)
+                for s0 in range(0, len(P), 2048):
+                    d = np.abs(P[s0:s0 + 2048, None, :] - S[None, :, :]).max(axis=2)
+                    wj[s0:s0 + 2048] = d.min(axis=1)
+            weights.append(wj)
+        total = np.zeros(w.n_free)
+        for I, wj in zip(self.I, weights):
+            total[I] += wj
+        X = []
+        for Ib, I, wj in zip(self.Ibar, self.I, weights):
             x = np.zeros(len(Ib))
-            pos = np.searchsorted(Ib, I)
-            x[pos] = 1.0 / cnt[I]
-            self.X.append(x)
+            x[np.searchsorted(Ib, I)] = wj / total[I]
+            X.append(x)
+        return X
 
     def _free_dofs(self, nodes: np.ndarray) -> np.ndarray:
         nc = self.w.ncomp

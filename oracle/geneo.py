@@ -15,7 +15,9 @@ zeros, N_H = sum_j m_j; Section 3.3.3 defines A_H = R_H A R_H^T.
 The oracle computes the eigenpairs with dense linear algebra: with
 P = A_N + s B (SPD for s > 0) and its Cholesky factor L, the pencil is
 equivalent to the symmetric problem  L^-1 B L^-T w = nu w  with
-lambda = 1/nu - s and p = L^-T w.  A_H is formed from its global definition
+lambda = 1/nu - s and p = L^-T w; each finite eigenvalue is then reported as
+the Rayleigh quotient p^T A_N p / p^T B p of its eigenvector, which does not
+lose the digits that 1/nu - s cancels when lambda is far below s.  A_H is formed from its global definition
 Phi^T (A Phi), not from the local products the GPU uses.
 
 Readings: the shift is s = 1e-2 (algorithmic only: the eigenvalues do not
@@ -100,6 +102,15 @@ def pencil_eig(AN: np.ndarray, B: np.ndarray, shift: float = 1e-2):
         lam = np.where(nu > 1e-14 / shift, 1.0 / nu - shift, np.inf)
     Pv = sla.solve_triangular(L.T, W, lower=False)
     Pv = normalise(Pv)
+    # Each finite eigenvalue is reported as the Rayleigh quotient of its own
+    # pencil, p^T A_N p / p^T B p (eq-geneo with v = p).  Forming 1/nu - s
+    # subtracts two numbers near 1/s when lambda << s and loses about
+    # log10(s / lambda) digits; the quotient of the two energies does not.
+    fin = np.isfinite(lam)
+    if np.any(fin):
+        Pf = Pv[:, fin]
+        lam = lam.copy()
+        lam[fin] = np.einsum("ik,ik->k", Pf, AN @ Pf) / np.einsum("ik,ik->k", Pf, B @ Pf)
     return lam, Pv
 
 
@@ -164,9 +175,17 @@ class GenEO:
     """Local factors, eigenpairs, coarse basis and coarse matrix."""
 
     def __init__(self, w, A, Ke, dec: Decomposition | None = None, shift: float = 1e-2,
-                 coarse=True, keep_all: bool = False):
+                 coarse=True, keep_all: bool = False, coarse_solve: str = "exact",
+                 coarse_rtol: float = 1e-4, coarse_maxit: int = 200):
         """coarse: True (or "geneo") for the GenEO coarse space, "zem" for the
-        zero-energy modes of floating subdomains, False for one level only."""
+        zero-energy modes of floating subdomains, False for one level only.
+        coarse_solve: "exact" (Cholesky of A_H) or "cg" (inexact: conjugate
+        gradients on A_H preconditioned by the inverses of its diagonal blocks,
+        one block per subdomain, x0 = 0, stopped at coarse_rtol relative
+        residual or coarse_maxit iterations; Section 3.3.3, last paragraph)."""
+        self.coarse_solve = coarse_solve
+        self.coarse_rtol, self.coarse_maxit = coarse_rtol, coarse_maxit
+        self.coarse_iters = []
         self.w = w
         self.A = A
         self.dec = dec if dec is not None else Decomposition(w)
@@ -201,6 +220,21 @@ class GenEO:
         self.AH = Phi.T @ (A @ Phi)
         self.AH = 0.5 * (self.AH + self.AH.T)
         self.AH_chol = sla.cho_factor(self.AH, lower=True) if self.NH > 0 else None
+        # diagonal blocks of A_H (one per subdomain) for the inexact coarse solve
+        self.AH_dinv = [np.linalg.inv(self.AH[a:c, a:c]) if c > a else np.zeros((0, 0))
+                        for a, c in zip(self.offsets[:-1], self.offsets[1:])]
+
+    def coarse_cg(self, g: np.ndarray) -> np.ndarray:
+        """Inexact A_H^-1 g: preconditioned CG on A_H, block-Jacobi M^-1 = blockdiag(A_jj)^-1."""
+        def prec(v):
+            out = np.zeros_like(v)
+            for j, Dj in enumerate(self.AH_dinv):
+                a, c = self.offsets[j], self.offsets[j + 1]
+                out[a:c] = Dj @ v[a:c]
+            return out
+        y, info = _inner_pcg(self.AH, g, prec, self.coarse_rtol, self.coarse_maxit)
+        self.coarse_iters.append(info)
+        return y
 
     def apply_as1(self, r: np.ndarray) -> np.ndarray:
         """One-level additive Schwarz sum_j R_j^T A_j^-1 R_j r (eqn:onelevelAS)."""
@@ -213,8 +247,36 @@ class GenEO:
         """R_H^T A_H^-1 R_H r with (R_H v)_i = Phi_i^T v (Section 3.3.3)."""
         if self.NH == 0:
             return np.zeros_like(r)
-        return self.Phi @ sla.cho_solve(self.AH_chol, self.Phi.T @ r)
+        g = self.Phi.T @ r
+        y = self.coarse_cg(g) if self.coarse_solve == "cg" else sla.cho_solve(self.AH_chol, g)
+        return self.Phi @ y
 
     def apply(self, r: np.ndarray) -> np.ndarray:
         """Two-level additive Schwarz M^-1_{AS,2} r (Section 3.1)."""
         return self.apply_as1(r) + self.apply_coarse(r)
+
+
+def _inner_pcg(AH, g, prec, rtol, maxit):
+    """Plain PCG for the coarse system, x0 = 0, stop at ||r|| <= rtol ||g||."""
+    y = np.zeros_like(g)
+    r = g.copy()
+    ng = np.linalg.norm(g)
+    if ng == 0.0:
+        return y, 0
+    z = prec(r)
+    p = z.copy()
+    rz = r @ z
+    k = 0
+    while k < maxit:
+        q = AH @ p
+        a = rz / (p @ q)
+        y += a * p
+        r -= a * q
+        k += 1
+        if np.linalg.norm(r) <= rtol * ng:
+            break
+        z = prec(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return y, k

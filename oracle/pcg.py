@@ -11,7 +11,10 @@ number estimate of M^-1 A; the reading here is the extreme eigenvalues of the
 Lanczos tridiagonal built from the CG coefficients.
 
 Readings: x0 = 0; stop when ||r_k||_2 <= rtol ||b||_2 (unpreconditioned
-residual); the true residual b - A x is recomputed at exit.
+residual); the true residual b - A x is recomputed at exit.  The paper's
+flexible Krylov method for an inexact coarse solve is FGMRES; here the
+flexible variant of CG (Polak-Ribiere beta) takes its place, so that one
+short-recurrence loop serves both cases.
 
 Pins (tests/test_oracle_pcg.py): dense direct solve on tiny meshes, one
 subdomain => one iteration, symmetry of M^-1, kappa estimate against the
@@ -22,8 +25,15 @@ from __future__ import annotations
 import numpy as np
 
 
-def pcg(A, b: np.ndarray, Minv=None, rtol: float = 1e-8, maxit: int = 1000):
-    """Returns (x, info) with iterations, histories, alpha/beta and residuals."""
+def pcg(A, b: np.ndarray, Minv=None, rtol: float = 1e-8, maxit: int = 1000, flexible: bool = False):
+    """Returns (x, info) with iterations, histories, alpha/beta and residuals.
+
+    flexible=True takes the Polak-Ribiere form of beta,
+    beta = z_{k+1}^T (r_{k+1} - r_k) / z_k^T r_k, which equals the standard one
+    when M^-1 is a fixed symmetric operator (then z_{k+1}^T r_k = 0) and keeps
+    CG converging when M^-1 changes from one application to the next (an
+    inexact coarse solve, Section 3.3.3 last paragraph, where the paper switches
+    to a flexible Krylov method)."""
     n = b.shape[0]
     x = np.zeros(n)
     r = b.copy()
@@ -41,6 +51,7 @@ def pcg(A, b: np.ndarray, Minv=None, rtol: float = 1e-8, maxit: int = 1000):
         q = A @ p
         alpha = rz / (p @ q)
         x += alpha * p
+        r_old = r.copy()
         r -= alpha * q
         info["alpha"].append(alpha)
         info["iters"] = k + 1
@@ -51,7 +62,7 @@ def pcg(A, b: np.ndarray, Minv=None, rtol: float = 1e-8, maxit: int = 1000):
             break
         z = Minv(r) if Minv is not None else r.copy()
         rz_new = r @ z
-        beta = rz_new / rz
+        beta = (z @ (r - r_old)) / rz if flexible else rz_new / rz
         info["beta"].append(beta)
         p = z + beta * p
         rz = rz_new

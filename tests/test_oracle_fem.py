@@ -207,3 +207,27 @@ def test_sampled_rows_equal_full_assembly():
         got[cols] = vals
         assert np.allclose(got, ref, rtol=1e-13, atol=1e-12 * abs(ref).max())
         assert abs(bv - b[r, 0]) <= 1e-13 * max(1.0, abs(b[r, 0]))
+
+
+@pytest.mark.parametrize("ramp", [(3.0, 7.0, 0.17), (2.5, 6.5, 0.3)])
+def test_load_resultant_on_the_ramp(ramp):
+    """Top-face traction on the ramped mesh: the resultant of a uniform traction
+    g is g times the true area of the tilted top surface.  With the ramp map
+    z += tan(angle) (clamp(x, x0, x1) - x0), every Q1 top face is planar (z
+    depends on x only, linearly between the face's corner nodes), so its area is
+    dx dy sqrt(1 + (dz/dx)^2): dx dy / cos(angle) on the ramp, dx dy on the
+    flats, and in between where x0 or x1 falls inside a face (second case)."""
+    nx, ny = 10, 4
+    g = np.array([0.003, 0.01, -0.02])
+    w = gen.small_case("laminate", seed=2, nxy=(nx, ny), n_ply=2, traction=np.tile(g, nx * ny),
+                       body=None, ramp=ramp)
+    b = fem.load_full(w)[:, 0].reshape(-1, 3)
+    x0, x1, ang = ramp
+    xn = w.xn[0]
+    zt = np.tan(ang) * (np.clip(xn, x0, x1) - x0)          # top-surface lift at each x node
+    dx = np.diff(xn)
+    dy = np.diff(w.xn[1])
+    area = np.sum(np.sqrt(dx ** 2 + np.diff(zt) ** 2)) * np.sum(dy)
+    flat = (xn[-1] - xn[0]) * (w.xn[1][-1] - w.xn[1][0])
+    assert area > flat * (1 + 1e-3)
+    assert np.allclose(b.sum(axis=0), g * area, rtol=1e-12, atol=1e-15)

@@ -57,7 +57,7 @@ def test_eigen_residual_zero_modes_and_shift_independence(kind, kw, zero_modes):
         assert nzero == (zero_modes if floating else 0), (j, lam[:8])
         lam2, _ = geneo.pencil_eig(AN, B, 1e-1)
         sel = lam[:k] > 1e-6
-        assert np.allclose(lam2[:k][sel], lam[:k][sel], rtol=1e-9)
+        assert np.allclose(lam2[:k][sel], lam[:k][sel], rtol=1e-10, atol=0)
 
 
 def test_selection_rule_and_cluster_completion():
@@ -168,3 +168,31 @@ def test_zem_dimensions_match_the_example_1b_table():
         d = dd.Decomposition(w)
         got = sum(geneo.zem_basis(w, d, j).shape[1] for j in range(w.n_sub))
         assert got == dim, (N, got, dim)
+
+
+@pytest.mark.parametrize("kind,kw", [
+    ("laminate", dict(nxy=(16, 8), n_ply=3, nparts=(4, 2, 1), nev=8, overlap=1)),
+    ("laminate", dict(nxy=(16, 8), n_ply=3, nparts=(4, 2, 1), nev=8, overlap=2)),
+    ("diffusion", dict(ne=(16, 16, 8), nparts=(4, 4, 1), overlap=2, threshold=0.15, nev_max=16)),
+])
+def test_smooth_pou_keeps_geneo_robust(kind, kw):
+    """The smooth (Sarkis) partition of unity in GenEO on equal subdomains: the
+    paper reports little difference from the standard one (at most one
+    iteration).  Checked qualitatively at the 1e-5 reduction of its tables: the
+    smooth PoU needs at most one iteration more than the standard one and keeps
+    the preconditioned condition number O(10).  With overlap 1 the two PoUs
+    coincide (the only shared nodes are equidistant from both boundaries)."""
+    from oracle import pcg
+    w = gen.small_case(kind, seed=7, **kw)
+    Ke = fem.element_matrices(w)
+    A, b, free = fem.assemble(w, Ke)
+    its, kap, X = {}, {}, {}
+    for pou in ("standard", "sarkis"):
+        w.pou = pou
+        g = geneo.GenEO(w, A, Ke)
+        u, info = pcg.pcg(A, b[:, 0], g.apply, rtol=1e-5, maxit=2000)
+        its[pou], kap[pou], X[pou] = info["iters"], info["kappa"], g.dec.X
+    assert its["sarkis"] <= its["standard"] + 1, its
+    assert kap["sarkis"] < 50, kap
+    same = all(np.array_equal(a, c) for a, c in zip(X["standard"], X["sarkis"]))
+    assert same == (w.overlap == 1)

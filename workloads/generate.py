@@ -77,6 +77,7 @@ class Workload:
     threshold: float = 0.0
     nev_max: int = 0
     seed: Optional[int] = None
+    pou: str = "standard"                    # partition of unity: "standard" or "sarkis"
     meta: dict = dataclasses.field(default_factory=dict)
 
     # --- sizes only -----------------------------------------------------
