@@ -8,9 +8,10 @@ GenEO eigensolves + coarse space and factor (gn_setup_geneo), and PCG to a
 time; the solve-only rate, PCG iterations and the p50/p99 solve latency are
 reported beside it.
 
-Default workload: 60x220x85 Q1 scalar diffusion with a log-normal coefficient
-and channelised layers of contrast 1e6 (SPE10-shaped, synthetic), 8x8x4
-subdomains, overlap 2, GenEO threshold 0.15.
+Default workload: the largest single-GPU configuration, the 384x72x71 ramped
+24-ply laminate (6,054,912 free DOFs, 1536 subdomains, 12 GenEO vectors each,
+N_H = 18,432), FP64 local factors.  The SPE10-shaped 60x220x85 diffusion
+(1,121,354 DOFs) is timed beside it as a secondary workload.
 """
 from __future__ import annotations
 
@@ -44,36 +45,80 @@ def make_workload(name):
     raise ValueError(name)
 
 
-def cpu_baseline():
-    """Oracle (as written, untuned) on a bounded sample of the same workload:
-    a 20x40x16-cell crop of the SPE10-shaped field, 2x2x2 subdomains, overlap 2,
-    threshold 0.15; timed end to end (assembly + GenEO set-up + PCG to 1e-8) on
-    one host core (BLAS limited to one thread)."""
-    from threadpoolctl import threadpool_limits
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _crop_workload(config):
+    """A bounded crop of the benched workload for the oracle: the same mesh
+    spacing, layers or coefficient field and loads, with fewer elements and
+    subdomains."""
+    import numpy as np
+    from workloads import generate as gen
+    if config == "c2":
+        w_full = gen.spe10_like()
+        ne = (20, 40, 16)
+        kc = w_full.elem_k.reshape(85, 220, 60)[:ne[2], :ne[1], :ne[0]]
+        w = gen.diffusion_box(ne, kc.ravel(), (2, 2, 2), overlap=2, threshold=0.15, nev_max=32,
+                              name="spe10_crop")
+        return w, f"a {ne[0]}x{ne[1]}x{ne[2]} crop of the same field, 2x2x2 subdomains, overlap 2, threshold 0.15"
+    # the ramped laminate: the clamped end (16 x 6 elements at its 0.5 mm
+    # spacing), its bottom four plies and three resin layers, top pressure, 2x1x1
+    # subdomains with 12 GenEO vectors each
+    layers = []
+    for p in range(4):
+        layers.append(("ply", [0, 90, 45, -45][p % 4], 2, gen.PLY_T))
+        if p != 3:
+            layers.append(("resin", 0.0, 1, gen.RESIN_T))
+    nx, ny = 16, 6
+    w = gen.laminate_plate((nx, ny), (8.0, 3.0), layers, nparts=(2, 1, 1), overlap=1, nev=12, body=None,
+                           traction=np.tile(np.array([0.0, 0.0, -0.01]), nx * ny), nrhs=1,
+                           resin=gen.iso_consts(162.0, 0.35), name="ramp_laminate_crop")
+    return w, ("the clamped end of the same laminate (16x6 elements at its 0.5 mm spacing, the bottom "
+               "4 plies + 3 resin layers, 11 element layers), 2x1x1 subdomains, 12 GenEO vectors")
+
+
+def cpu_baseline(config):
+    """Oracle (as written, untuned) on a bounded sample of the benched workload,
+    timed end to end (assembly + GenEO set-up + PCG to 1e-8) on the host: once
+    with BLAS on every core, once on one core."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import fem, geneo, pcg
-    from workloads import generate as gen
-    w_full = gen.spe10_like()
-    ne = (20, 40, 16)
-    kfull = w_full.elem_k.reshape(85, 220, 60)          # [z][y][x]
-    kc = kfull[:ne[2], :ne[1], :ne[0]]
-    w = gen.diffusion_box(ne, kc.ravel(), (2, 2, 2), overlap=2, threshold=0.15, nev_max=32,
-                          name="spe10_crop")
-    with threadpool_limits(limits=1):
+    w, what = _crop_workload(config)
+
+    def run():
         t0 = time.perf_counter()
         Ke = fem.element_matrices(w)
         A, b, free = fem.assemble(w, Ke)
         g = geneo.GenEO(w, A, Ke)
         x, info = pcg.pcg(A, b[:, 0], g.apply, rtol=1e-8, maxit=2000)
-        dt = time.perf_counter() - t0
-    cores = 1
-    return {"value": w.n_free / dt, "unit": "DOFs/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle end-to-end on a {ne[0]}x{ne[1]}x{ne[2]} crop of the same field "
-                      f"({w.n_free} DOFs, 8 subdomains, {info['iters']} PCG its) in {dt:.1f} s"}
+        return time.perf_counter() - t0, info
+
+    dt_all, info = run()
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    with threadpool_limits(limits=1):
+        dt_one, _ = run()
+    nproc = os.cpu_count() or 1
+    return {"value": w.n_free / dt_all, "unit": "DOFs/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle end-to-end on {what} ({w.n_free} DOFs, {info['iters']} PCG its) "
+                      f"in {dt_all:.1f} s with BLAS on {threads} threads",
+            "single_core": {"value": w.n_free / dt_one, "seconds": dt_one, "cores": 1},
+            "host": {"nproc": nproc, "cpu_model": _cpu_model()}}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "local_solve_traffic.json")
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1901_05188_amd", "csrc", "precond.hip")
+
+
+def traffic_file(workload, prec):
+    return os.path.join(ROOT, "profiles", f"local_solve_traffic_{workload}_fp{prec}.json")
 
 
 def _sha256(path):
@@ -122,11 +167,11 @@ def summarize_counters(fetch_csv, write_csv, kernel_prefix="k_local_solve", floo
     return out
 
 
-def measured_traffic():
+def measured_traffic(workload, prec):
     """HBM bytes per working local-solve launch from the committed counter
     summary, or None if it is missing or was taken on another kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(workload, prec)) as f:
             t = json.load(f)
         if t.get("source_sha256") != _sha256(TRAFFIC_SOURCE):
             return None
@@ -155,7 +200,7 @@ def serving_leg(gp, n_req, rate, rtol, dev):
     t_build = time.perf_counter() - t0
     srv = gp.Server(maxit_cap=5000)
     ids = [srv.add(p, pc) for (_, p, pc) in ops]
-    resident = sum(gp.footprint(p, pc) for (_, p, pc) in ops)
+    resident = sum(gp.resident_bytes(p, pc) for (_, p, pc) in ops)
     log(f"serving: catalogue of {len(ops)} operators built in {t_build:.1f}s, {resident / 1e9:.1f} GB resident")
     reqs = gen.c4_requests(len(ops), n_req=n_req, rate=rate)
     loads = []
@@ -266,7 +311,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c5")
     ap.add_argument("--local-prec", type=int, default=64)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -278,17 +323,22 @@ def main():
                     help="requests of the serving stream to replay (0 skips the serving leg)")
     ap.add_argument("--no-robustness", action="store_true",
                     help="skip the AS / ZEM / GenEO comparison over subdomain counts and contrasts")
+    ap.add_argument("--secondary", default="c2",
+                    help="second workload timed end to end beside the headline ('' = none)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="end with a device-to-device copy of this many GiB (a reference "
                          "kernel of known traffic for hardware-counter runs)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write the local-solve HBM traffic summary from two counter runs and exit")
+                    help="write the local-solve HBM traffic summary of --config/--local-prec from two "
+                         "counter runs and exit")
     args = ap.parse_args()
     if args.summarize_counters:
         out = summarize_counters(*args.summarize_counters)
-        os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
-        with open(TRAFFIC_FILE, "w") as f:
+        name = make_workload(args.config).name
+        path = traffic_file(name, args.local_prec)
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
             json.dump(out, f, indent=1)
         print(json.dumps(out))
         return
@@ -302,15 +352,17 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
     log(f"generating workload {args.config}")
     w = make_workload(args.config)
     log(f"workload {w.name}: ne={w.ne} n_free={w.n_free} subdomains={w.n_sub}")
 
-    def step(profile=False):
+    def step(wl, keep):
+        """One step: assemble, set up, solve.  The handles are closed at the end
+        of the step unless keep (the last timed step keeps them for the warm
+        measurements)."""
         t0 = time.perf_counter()
-        prob = gp.Problem.from_workload(w)
-        pc = gp.Preconditioner.from_workload(prob, w, local_prec=args.local_prec)
+        prob = gp.Problem.from_workload(wl)
+        pc = gp.Preconditioner.from_workload(prob, wl, local_prec=args.local_prec)
         b = torch.zeros((prob.nrhs, prob.n_free), dtype=torch.float64, device=dev)
         prob.rhs(b)
         x = torch.zeros_like(b)
@@ -319,26 +371,31 @@ def main():
         st, rep = gp.solve(prob, pc, b, x, rtol=args.rtol, maxit=5000, check_every=16)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        return prob, pc, b, x, rep[0], t1 - t0, t2 - t1, t2 - t0
+        report = dict(pc.report)
+        if not keep:
+            pc.close()
+            prob.close()
+            prob = pc = b = x = None
+        return prob, pc, b, x, rep[0], report, t1 - t0, t2 - t1, t2 - t0
 
     for i in range(args.warmup):
         log(f"warmup step {i}")
-        out = step()
-        log(f"  setup {out[5]:.3f}s solve {out[6]:.3f}s iters {out[4]['iters']}")
+        out = step(w, keep=False)
+        log(f"  setup {out[6]:.3f}s solve {out[7]:.3f}s iters {out[4]['iters']}")
         del out
     torch.cuda.synchronize()
-    times, setups, solves, iters, reports = [], [], [], [], []
+    times, setups, solves, iters = [], [], [], []
     last = None
     t_start = time.perf_counter()
     for i in range(args.steps):
-        prob, pc, b, x, rep, ts, tv, tt = step()
+        prob, pc, b, x, rep, report, ts, tv, tt = step(w, keep=(i == args.steps - 1))
         times.append(tt)
         setups.append(ts)
         solves.append(tv)
         iters.append(rep["iters"])
         log(f"step {i}: total {tt:.3f}s setup {ts:.3f}s solve {tv:.3f}s iters {rep['iters']} "
-            f"true_rel_res {rep['true_rel_res']:.2e} cond {rep['cond_est']:.1f} NH {pc.report['coarse_dim']}")
-        log("  setup report " + json.dumps(pc.report))
+            f"true_rel_res {rep['true_rel_res']:.2e} cond {rep['cond_est']:.1f} NH {report['coarse_dim']}")
+        log("  setup report " + json.dumps(report))
         last = (prob, pc, b, x, rep)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
@@ -379,16 +436,24 @@ def main():
     bytes_per_app = tr["bytes"] / launches
     bytes_per_launch = bytes_per_app * min(applications, launches) / launches
     tr_gbs = bytes_per_launch / (tr_ms * 1e-3) / 1e9 if tr["launches"] else 0.0
-    traffic = measured_traffic()
+    traffic = measured_traffic(w.name, args.local_prec)
+    tile_bytes = pc.report["apply_tile_bytes"]
     roof = {"bound": "hbm", "kernel": "k_local_solve (batched banded fwd+bwd triangular solves)",
             "achieved": round(tr_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(tr_gbs / HBM_PEAK_GBS, 4),
             # HBM bytes per working launch from the committed counter runs of this
-            # kernel source (null when the source changed since they were taken)
-            "traffic": traffic["hbm_bytes_per_launch"] if traffic and args.config == "c2"
-            and args.local_prec == 64 else None,
+            # kernel source and workload (null when the source changed since)
+            "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
             "avg_launch_ms": round(tr_ms, 4), "launches": tr["launches"],
-            "working_launches": applications, "bytes_per_working_launch": bytes_per_app,
+            "working_launches": applications,
+            # algorithmic bytes: both sweeps over the factors' bands, the r gather,
+            # the z write and Phi_j (the figure `achieved` divides)
+            "bytes_per_working_launch": bytes_per_app,
+            # the same launch over the stored whole 32x32 tiles (padding included)
+            "tile_bytes_per_working_launch": tile_bytes,
+            "tile_over_band": round(tile_bytes / bytes_per_app, 4) if bytes_per_app else None,
+            "traffic_over_band": round(traffic["hbm_bytes_per_launch"] / bytes_per_app, 4)
+            if traffic and bytes_per_app else None,
             "bytes_per_launch": bytes_per_launch}
     lat_sorted = sorted(lat_plain)
     # mixed-precision leg: the same operator with FP32 local factors inside the
@@ -446,6 +511,26 @@ def main():
         k = min(len(v) - 1, max(0, int(round(q * (len(v) - 1)))))
         return v[k]
 
+    # the headline operator is released before the other legs
+    head_report, head_n_free, head_nrhs = dict(pc.report), prob.n_free, prob.nrhs
+    pc.close()
+    prob.close()
+    del pc, prob, b, x
+    secondary = None
+    if args.secondary:
+        w2 = make_workload(args.secondary)
+        log(f"secondary workload {w2.name}: n_free={w2.n_free}")
+        step(w2, keep=False)                       # warm
+        t2s, its2 = [], []
+        for i in range(3):
+            _, _, _, _, rep2, rp2, ts2, tv2, tt2 = step(w2, keep=False)
+            t2s.append(tt2)
+            its2.append(rep2["iters"])
+            log(f"  secondary step {i}: total {tt2:.3f}s setup {ts2:.3f}s solve {tv2:.3f}s")
+        secondary = {"workload": w2.name, "n_free": w2.n_free, "local_prec": args.local_prec,
+                     "value": w2.n_free / statistics.mean(t2s), "unit": "DOFs/s",
+                     "ms_per_step": 1000 * statistics.mean(t2s), "steps": 3, "pcg_iters": its2[-1],
+                     "setup_s_last": rp2["t_total_s"], "coarse_dim": rp2["coarse_dim"]}
     serving = serving_leg(gp, args.serve, args.serve_rate, args.rtol, dev) if args.serve > 0 else None
     robust = None if args.no_robustness else robustness_leg(gp, dev)
 
@@ -458,7 +543,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.local_prec == 64 else "f64+f32-local",
         "data": "synthetic",
-        "config": {"workload": w.name, "ne": list(w.ne), "n_free": prob.n_free, "nrhs": prob.nrhs,
+        "config": {"workload": w.name, "ne": list(w.ne), "n_free": head_n_free, "nrhs": head_nrhs,
                    "subdomains": list(w.nparts), "overlap": w.overlap,
                    "geneo": {"nev": w.nev, "threshold": w.threshold, "nev_max": w.nev_max},
                    "local_prec": args.local_prec, "rtol": args.rtol,
@@ -467,16 +552,22 @@ def main():
         "solve_dofs_per_s": n_dof / statistics.median(lat_plain),
         "solve_latency_ms": {"p50": 1000 * pct(lat_sorted, 0.5), "p99": 1000 * pct(lat_sorted, 0.99)},
         "setup_s_median": statistics.median(setups),
-        "setup_breakdown_s": {"local_factors": pc.report["t_local_s"], "eigen": pc.report["t_eigen_s"],
-                              "coarse": pc.report["t_coarse_s"]},
-        "coarse_dim": pc.report["coarse_dim"],
-        "eig_iters": pc.report["eig_iters"],
+        "step_s": {"median": statistics.median(times), "max": max(times),
+                   "max_over_median": max(times) / statistics.median(times)},
+        "setup_breakdown_s": {"local_factors": head_report["t_local_s"], "eigen": head_report["t_eigen_s"],
+                              "coarse": head_report["t_coarse_s"], "device_alloc": head_report["t_alloc_s"]},
+        "coarse_dim": head_report["coarse_dim"],
+        "eig_iters": head_report["eig_iters"],
+        "eig_solves": head_report["eig_solves"],
+        "preconditioner_bytes": head_report["hbm_bytes"],
         "cond_est": rep["cond_est"],
         "true_rel_res": rep["true_rel_res"],
         "res_floor": rep["res_floor"],
         "kernel_groups_ms_per_solve": {k: v["ms_total"] / args.solve_reps for k, v in groups.items()},
         "roofline": roof,
     }
+    if secondary is not None:
+        res["secondary"] = secondary
     if mixed is not None:
         res["mixed_precision"] = mixed
     if multi is not None:
@@ -487,7 +578,7 @@ def main():
         res["coarse_space_comparison"] = robust
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
-        res["cpu_baseline"] = cpu_baseline()
+        res["cpu_baseline"] = cpu_baseline(args.config)
     # streaming reference on the same device: a 1 GiB device-to-device copy
     # (read + write bytes over its event-timed duration), context for the roofline
     nref = (1 << 30) // 8

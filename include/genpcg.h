@@ -155,7 +155,21 @@ gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t n
  * first step.
  * local_kernel selects the kernel of single-column local solves: 0 = automatic
  * (the register-pipelined sweep when the band fits it), 1 = always the
- * 16-column matrix-core kernel of the batched solves. */
+ * 16-column matrix-core kernel of the batched solves.
+ * pou selects the partition of unity X_j (Section 3.2, def:pou; Section 3.3.1):
+ * 0 = the standard one (one over the number of subdomains whose V_h0 holds the
+ * DOF, zero on the subdomain boundary); 1 = the smoother one of Sarkis that the
+ * paper also provides: subdomain j is weighted by the distance of the node to
+ * the artificial boundary of Omega_j (element layers, the smallest over the
+ * box's faces that are not on the physical boundary), divided by the sum of
+ * those weights over all subdomains.
+ * coarse_solve selects how A_H^-1 is applied (Section 3.3.3, last paragraph):
+ * 0 = exactly, by the dense Cholesky factor of A_H (its explicit inverse);
+ * 1 = inexactly, by conjugate gradients on the block-sparse A_H (blocks only
+ * for overlapping subdomain pairs) preconditioned by the inverses of its
+ * diagonal blocks, stopped at coarse_rtol (0 = 1e-4) relative residual or
+ * coarse_maxit (0 = 200) iterations.  The preconditioner then varies from one
+ * application to the next: solve with gn_solve_opts.flexible = 1. */
 typedef struct gn_dd_opts {
   int32_t nparts[3];
   const int32_t* cuts[3];
@@ -171,6 +185,10 @@ typedef struct gn_dd_opts {
   int32_t eig_block;
   int32_t eig_filter;
   int32_t local_kernel;
+  int32_t pou;
+  int32_t coarse_solve;
+  double coarse_rtol;
+  int32_t coarse_maxit;
 } gn_dd_opts;
 
 typedef struct gn_setup_report {
@@ -183,6 +201,14 @@ typedef struct gn_setup_report {
   int64_t hbm_bytes;         /* device bytes held by the preconditioner        */
   double eig_resid;          /* largest final relative Ritz residual of the pairs in the coarse space */
   int32_t eig_solves;        /* block solves with the pencil factors            */
+  double t_alloc_s;          /* time of this call spent in hipMalloc/hipFree (freed
+                                device blocks are cached and reused by later calls) */
+  double apply_bytes;        /* algorithmic bytes of one single-column local-solve
+                                launch: both sweeps over the factors' bands (row r
+                                of a band holds min(r, bandwidth) + 1 entries), the
+                                gather of r, the write of z_j and Phi_j^T r        */
+  double apply_tile_bytes;   /* the same launch counted over the stored 32 x 32 band
+                                tiles and inverse diagonal tiles                   */
 } gn_setup_report;
 
 /* Build the preconditioner: local Dirichlet factors A_j = L_j L_j^T
@@ -249,7 +275,21 @@ gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev, double* x
 
 /* Device bytes held by p and pc (pc may be NULL): assembled operator,
  * element matrices, workspaces, local factors, coarse basis and factor. */
-gn_status gn_footprint(const gn_problem* p, const gn_precond* pc, int64_t* bytes);
+gn_status gn_resident_bytes(const gn_problem* p, const gn_precond* pc, int64_t* bytes);
+
+/* Resident device bytes of an operator assembled on grid (pde 0 diffusion,
+ * 1 elasticity, one load column) and of its preconditioner built with opts
+ * (opts may be NULL: the operator alone), including the workspace of the
+ * 16-column batched solves and a history of 2000 iterations, as a request
+ * server holds them (Section 3.1's decomposition sizes: subdomain boxes, band
+ * widths, coarse dimension).  Computed on the host from the sizes, before any
+ * assembly or set-up, for admission by footprint.  The coarse dimension is
+ * taken as nev per subdomain (fixed count), nev_max (threshold: an upper
+ * bound) or the mode count (zero-energy modes, every subdomain counted), and
+ * the free-to-full map as if no DOF were fixed, so the figure bounds the
+ * measured gn_resident_bytes from above; a fixed count whose eigenvalue
+ * clusters straddle the cut can add vectors beyond nev. */
+gn_status gn_footprint(const gn_grid* grid, int32_t pde, const gn_dd_opts* opts, int64_t* bytes);
 
 /* Request server (the multi-right-hand-side path of Section 3.1 for a stream
  * of load cases): operators stay resident with their preconditioners; each
@@ -262,8 +302,10 @@ gn_status gn_footprint(const gn_problem* p, const gn_precond* pc, int64_t* bytes
  * check_every iterations) while the others keep iterating.  Operators'
  * workers run concurrently, so different operators overlap on the device.
  *  - hbm_budget: device bytes the resident operators may hold together
- *    (gn_footprint after the batched workspace is allocated); 0 = the
- *    device's total memory.  gn_server_add fails with GN_ERR_OOM beyond it.
+ *    (gn_resident_bytes after the batched workspace is allocated, or the
+ *    gn_footprint estimate while a registered operator is being built); 0 =
+ *    the device's total memory.  gn_server_add evicts idle server-built
+ *    operators to make room and fails with GN_ERR_OOM beyond it.
  *  - slots: columns per operator batch, 1..16 (0 = 16).
  *  - check_every: CG iterations between slot updates (0 = 8).
  *  - maxit_cap: largest maxit a request may ask for (0 = 2000). */
@@ -284,8 +326,30 @@ gn_status gn_server_create(const gn_server_opts* opts, gn_server** out);
  * NULL) its footprint. */
 gn_status gn_server_add(gn_server* sv, gn_problem* p, gn_precond* pc, int32_t* op, int64_t* bytes);
 
+/* Register an operator by its description instead of built handles: the
+ * host arrays of grid, mat, loads and opts are copied (nothing on the device),
+ * *est_bytes (may be NULL) receives its gn_footprint estimate.  The server
+ * builds it (gn_assemble + gn_setup_geneo on the operator's stream) when a
+ * request for it arrives and its estimate fits in the budget; while it does
+ * not fit, the least recently used idle server-built operator (no queued or
+ * running column) is destroyed to make room, and rebuilt when a later request
+ * needs it.  Requests wait meanwhile; they fail with GN_ERR_OOM when even
+ * evicting every idle server-built operator cannot make room, and with the
+ * set-up's status if the build fails.  Right-hand sides use the operator's
+ * free numbering (the mask in loads). */
+gn_status gn_server_register(gn_server* sv, const gn_grid* grid, const gn_material* mat, const gn_loads* loads,
+                             const gn_dd_opts* opts, int32_t* op, int64_t* est_bytes);
+
+/* State of an operator: *resident 1 while its device data exist, *builds and
+ * *evictions the number of builds and evictions so far (server-built
+ * operators), *bytes its measured footprint while resident, else its estimate.
+ * Any output may be NULL. */
+gn_status gn_server_operator_info(gn_server* sv, int32_t op, int32_t* resident, int32_t* builds,
+                                  int32_t* evictions, int64_t* bytes);
+
 /* Finish the operator's queued and running columns, stop its worker and
- * return its footprint to the budget. */
+ * return its footprint to the budget (a server-built operator's device data
+ * are destroyed). */
 gn_status gn_server_remove(gn_server* sv, int32_t op);
 
 /* Queue nrhs right-hand sides of operator op (device pointers, free
@@ -315,6 +379,14 @@ void gn_server_destroy(gn_server* sv);
  * the number of launches and the algorithmic bytes those launches move. */
 gn_status gn_profile_enable(int32_t enable);
 gn_status gn_profile_read(const char* group, double* total_ms, int64_t* launches, double* bytes);
+
+/* Device memory of the library: blocks freed by gn_destroy_*, by the end of
+ * gn_setup_geneo (its temporaries) and by gn_load_vectors are kept by the
+ * process and reused by later allocations of about the same size (repeated
+ * set-ups then allocate nothing new).  gn_trim_memory synchronises the device
+ * and returns every such idle block to the runtime; *released (may be NULL)
+ * receives the bytes returned.  Blocks held by live handles are untouched. */
+gn_status gn_trim_memory(int64_t* released);
 
 void gn_destroy_problem(gn_problem* p);
 void gn_destroy_precond(gn_precond* pc);

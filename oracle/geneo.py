@@ -88,14 +88,19 @@ def pencil(w, dec: Decomposition, Ke: np.ndarray, j: int):
     return AN, B
 
 
-def pencil_eig(AN: np.ndarray, B: np.ndarray, shift: float = 1e-2):
-    """All eigenpairs (ascending lambda, inf for the null space of B)."""
+def pencil_eig(AN: np.ndarray, B: np.ndarray, shift: float = 1e-2, n_eig: int | None = None):
+    """All eigenpairs (ascending lambda, inf for the null space of B), or only
+    the n_eig smallest when n_eig is given."""
     P = AN + shift * B
     L = np.linalg.cholesky(P)
     Linv_B = sla.solve_triangular(L, B, lower=True)
     C = sla.solve_triangular(L, Linv_B.T, lower=True)    # L^-1 B L^-T (symmetric)
     C = 0.5 * (C + C.T)
-    nu, W = np.linalg.eigh(C)
+    n = C.shape[0]
+    if n_eig is not None and n_eig < n:
+        nu, W = sla.eigh(C, subset_by_index=[n - n_eig, n - 1])
+    else:
+        nu, W = np.linalg.eigh(C)
     order = np.argsort(-nu)                                # largest nu first
     nu, W = nu[order], W[:, order]
     with np.errstate(divide="ignore"):
@@ -176,13 +181,15 @@ class GenEO:
 
     def __init__(self, w, A, Ke, dec: Decomposition | None = None, shift: float = 1e-2,
                  coarse=True, keep_all: bool = False, coarse_solve: str = "exact",
-                 coarse_rtol: float = 1e-4, coarse_maxit: int = 200):
+                 coarse_rtol: float = 1e-4, coarse_maxit: int = 200, n_eig: int | None = None):
         """coarse: True (or "geneo") for the GenEO coarse space, "zem" for the
         zero-energy modes of floating subdomains, False for one level only.
         coarse_solve: "exact" (Cholesky of A_H) or "cg" (inexact: conjugate
         gradients on A_H preconditioned by the inverses of its diagonal blocks,
         one block per subdomain, x0 = 0, stopped at coarse_rtol relative
-        residual or coarse_maxit iterations; Section 3.3.3, last paragraph)."""
+        residual or coarse_maxit iterations; Section 3.3.3, last paragraph).
+        n_eig: compute only that many of the smallest eigenpairs per subdomain
+        (large subdomains); the count selected must stay below it."""
         self.coarse_solve = coarse_solve
         self.coarse_rtol, self.coarse_maxit = coarse_rtol, coarse_maxit
         self.coarse_iters = []
@@ -205,8 +212,10 @@ class GenEO:
                 self.P.append(Zj)
                 continue
             AN, B = pencil(w, d, Ke, j)
-            lam, Pv = pencil_eig(AN, B, shift)
+            lam, Pv = pencil_eig(AN, B, shift, n_eig)
             m = select_count(lam, w.nev, w.threshold, w.nev_max)
+            if n_eig is not None and m >= len(lam) - 1:
+                raise ValueError("n_eig too small for the selected eigenvectors")
             self.lam.append(lam if keep_all else lam[: max(m + 8, 16)])
             self.m.append(m)
             self.P.append(Pv[:, :m])

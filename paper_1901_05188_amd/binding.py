@@ -20,9 +20,10 @@ GN_OK, GN_WARN_MAXIT, GN_PENDING = 0, 1, 2
 STATUS = {0: "OK", 1: "WARN_MAXIT", 2: "PENDING", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_NOT_SPD",
           -4: "ERR_EIG_NOCONV", -5: "ERR_COARSE_SINGULAR", -6: "ERR_DEVICE", -7: "ERR_BREAKDOWN"}
 EXPORTS = ["gn_assemble", "gn_problem_info", "gn_problem_rhs", "gn_load_vectors", "gn_matvec",
-           "gn_setup_geneo", "gn_precond_eigenvalues", "gn_precond_apply", "gn_solve", "gn_footprint",
-           "gn_server_create", "gn_server_add", "gn_server_remove", "gn_server_submit", "gn_server_wait",
-           "gn_server_destroy", "gn_profile_enable", "gn_profile_read", "gn_destroy_problem",
+           "gn_setup_geneo", "gn_precond_eigenvalues", "gn_precond_apply", "gn_solve", "gn_footprint", "gn_resident_bytes",
+           "gn_server_create", "gn_server_add", "gn_server_register", "gn_server_operator_info",
+           "gn_server_remove", "gn_server_submit", "gn_server_wait",
+           "gn_server_destroy", "gn_profile_enable", "gn_profile_read", "gn_trim_memory", "gn_destroy_problem",
            "gn_destroy_precond", "gn_last_error"]
 
 
@@ -53,7 +54,9 @@ class gn_dd_opts(C.Structure):
                 ("overlap", C.c_int32), ("nev", C.c_int32), ("threshold", C.c_double),
                 ("nev_max", C.c_int32), ("local_prec", C.c_int32), ("coarse", C.c_int32),
                 ("shift", C.c_double), ("eig_tol", C.c_double), ("eig_maxit", C.c_int32),
-                ("eig_block", C.c_int32), ("eig_filter", C.c_int32), ("local_kernel", C.c_int32)]
+                ("eig_block", C.c_int32), ("eig_filter", C.c_int32), ("local_kernel", C.c_int32),
+                ("pou", C.c_int32), ("coarse_solve", C.c_int32), ("coarse_rtol", C.c_double),
+                ("coarse_maxit", C.c_int32)]
 
 
 class gn_setup_report(C.Structure):
@@ -61,7 +64,8 @@ class gn_setup_report(C.Structure):
                 ("max_local_n", C.c_int32), ("band_tiles", C.c_int32),
                 ("t_local_s", C.c_double), ("t_eigen_s", C.c_double), ("t_coarse_s", C.c_double),
                 ("t_total_s", C.c_double), ("hbm_bytes", C.c_int64), ("eig_resid", C.c_double),
-                ("eig_solves", C.c_int32)]
+                ("eig_solves", C.c_int32), ("t_alloc_s", C.c_double), ("apply_bytes", C.c_double),
+                ("apply_tile_bytes", C.c_double)]
 
 
 class gn_solve_opts(C.Structure):
@@ -99,7 +103,12 @@ def lib():
         L.gn_load_vectors.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double), vp,
                                       C.c_int64, vp]
         L.gn_matvec.argtypes = [vp, vp, vp, C.c_int32, C.c_int64, vp]
-        L.gn_footprint.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+        L.gn_resident_bytes.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+        L.gn_footprint.argtypes = [C.POINTER(gn_grid), C.c_int32, C.POINTER(gn_dd_opts), C.POINTER(C.c_int64)]
+        L.gn_server_register.argtypes = [vp, C.POINTER(gn_grid), C.POINTER(gn_material), C.POINTER(gn_loads),
+                                         C.POINTER(gn_dd_opts), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.gn_server_operator_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                              C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.gn_server_create.argtypes = [C.POINTER(gn_server_opts), C.POINTER(vp)]
         L.gn_server_add.argtypes = [vp, vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.gn_server_remove.argtypes = [vp, C.c_int32]
@@ -117,6 +126,7 @@ def lib():
         L.gn_solve.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int64, C.POINTER(gn_solve_opts), vp,
                                C.POINTER(gn_solve_report)]
         L.gn_profile_enable.argtypes = [C.c_int32]
+        L.gn_trim_memory.argtypes = [C.POINTER(C.c_int64)]
         L.gn_profile_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_double)]
         L.gn_destroy_problem.argtypes = [vp]
@@ -156,41 +166,85 @@ def _tensor_ptr(t) -> int:
     return int(t.data_ptr())
 
 
+def _spec_structs(ne, xn, pde, *, mats=None, elem_mat=None, elem_angle=None, elem_tilt=None, elem_k=None,
+                  dirichlet, body=None, nrhs=1, traction=None, map_kind=0, map_par=None):
+    """gn_grid, gn_material and gn_loads for host arrays; returns them with the
+    arrays they point into (kept alive by the caller for the call)."""
+    keep = []
+
+    def arr(a, dt):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a
+
+    g = gn_grid()
+    for a in range(3):
+        g.ne[a] = int(ne[a])
+        g.xn[a] = _dptr(arr(xn[a], np.float64), C.c_double)
+    g.map_kind = int(map_kind)
+    g.map_par = _dptr(arr(map_par, np.float64), C.c_double)
+    m = gn_material()
+    m.pde = int(pde)
+    mats_a = arr(mats, np.float64)
+    m.n_mat = 0 if mats_a is None else mats_a.shape[0]
+    m.mat = _dptr(mats_a, C.c_double)
+    m.elem_mat = _dptr(arr(elem_mat, np.int32), C.c_int32)
+    m.elem_angle = _dptr(arr(elem_angle, np.float64), C.c_double)
+    m.elem_tilt = _dptr(arr(elem_tilt, np.float64), C.c_double)
+    m.elem_k = _dptr(arr(elem_k, np.float64), C.c_double)
+    l = gn_loads()
+    l.dirichlet = _dptr(arr(dirichlet, np.uint8), C.c_uint8)
+    l.body = _dptr(arr(body, np.float64), C.c_double)
+    l.nrhs = int(nrhs)
+    l.traction = _dptr(arr(traction, np.float64), C.c_double)
+    return g, m, l, keep
+
+
+def _workload_spec(w):
+    return dict(ne=w.ne, xn=w.xn, pde=w.pde, mats=w.mats, elem_mat=w.elem_mat, elem_angle=w.elem_angle,
+                elem_tilt=w.elem_tilt, elem_k=w.elem_k, dirichlet=w.dirichlet, body=w.body, nrhs=w.nrhs,
+                traction=w.traction, map_kind=w.map_kind, map_par=w.map_par)
+
+
+def _dd_struct(nparts, cuts, overlap=1, nev=0, threshold=0.0, nev_max=0, local_prec=64, coarse=True, shift=0.0,
+               eig_tol=0.0, eig_maxit=0, eig_block=0, eig_filter=0, local_kernel=0, pou=0, coarse_solve=0,
+               coarse_rtol=0.0, coarse_maxit=0):
+    o = gn_dd_opts()
+    keep = []
+    for a in range(3):
+        o.nparts[a] = int(nparts[a])
+        c = np.ascontiguousarray(cuts[a], dtype=np.int32)
+        keep.append(c)
+        o.cuts[a] = _dptr(c, C.c_int32)
+    o.overlap, o.nev, o.threshold, o.nev_max = int(overlap), int(nev), float(threshold), int(nev_max)
+    o.local_prec = int(local_prec)
+    o.coarse = {"geneo": 1, "zem": 2, "none": 0}[coarse] if isinstance(coarse, str) else int(coarse)
+    o.shift, o.eig_tol, o.eig_maxit = float(shift), float(eig_tol), int(eig_maxit)
+    o.eig_block, o.eig_filter = int(eig_block), int(eig_filter)
+    o.local_kernel = int(local_kernel)
+    o.pou = {"standard": 0, "sarkis": 1}[pou] if isinstance(pou, str) else int(pou)
+    o.coarse_solve = {"exact": 0, "cg": 1}[coarse_solve] if isinstance(coarse_solve, str) else int(coarse_solve)
+    o.coarse_rtol, o.coarse_maxit = float(coarse_rtol), int(coarse_maxit)
+    return o, keep
+
+
+def _workload_dd(w, **kw):
+    kw.setdefault("pou", getattr(w, "pou", "standard"))
+    return _dd_struct(w.nparts, w.cuts, overlap=w.overlap, nev=w.nev, threshold=w.threshold, nev_max=w.nev_max,
+                      **kw)
+
+
 class Problem:
     """Assembled system on the device (gn_assemble)."""
 
     def __init__(self, ne, xn, pde, *, mats=None, elem_mat=None, elem_angle=None, elem_tilt=None,
                  elem_k=None, dirichlet, body=None, nrhs=1, traction=None, map_kind=0,
                  map_par=None, stream=None):
-        keep = []
-
-        def arr(a, dt):
-            if a is None:
-                return None
-            a = np.ascontiguousarray(a, dtype=dt)
-            keep.append(a)
-            return a
-
-        g = gn_grid()
-        for a in range(3):
-            g.ne[a] = int(ne[a])
-            g.xn[a] = _dptr(arr(xn[a], np.float64), C.c_double)
-        g.map_kind = int(map_kind)
-        g.map_par = _dptr(arr(map_par, np.float64), C.c_double)
-        m = gn_material()
-        m.pde = int(pde)
-        mats_a = arr(mats, np.float64)
-        m.n_mat = 0 if mats_a is None else mats_a.shape[0]
-        m.mat = _dptr(mats_a, C.c_double)
-        m.elem_mat = _dptr(arr(elem_mat, np.int32), C.c_int32)
-        m.elem_angle = _dptr(arr(elem_angle, np.float64), C.c_double)
-        m.elem_tilt = _dptr(arr(elem_tilt, np.float64), C.c_double)
-        m.elem_k = _dptr(arr(elem_k, np.float64), C.c_double)
-        l = gn_loads()
-        l.dirichlet = _dptr(arr(dirichlet, np.uint8), C.c_uint8)
-        l.body = _dptr(arr(body, np.float64), C.c_double)
-        l.nrhs = int(nrhs)
-        l.traction = _dptr(arr(traction, np.float64), C.c_double)
+        g, m, l, keep = _spec_structs(ne, xn, pde, mats=mats, elem_mat=elem_mat, elem_angle=elem_angle,
+                                      elem_tilt=elem_tilt, elem_k=elem_k, dirichlet=dirichlet, body=body,
+                                      nrhs=nrhs, traction=traction, map_kind=map_kind, map_par=map_par)
         h = C.c_void_p()
         _check(lib().gn_assemble(C.byref(g), C.byref(m), C.byref(l), _stream(stream), C.byref(h)))
         self.handle = h
@@ -253,20 +307,11 @@ class Preconditioner:
 
     def __init__(self, prob: Problem, nparts: Sequence[int], cuts, overlap=1, nev=0, threshold=0.0,
                  nev_max=0, local_prec=64, coarse=True, shift=0.0, eig_tol=0.0, eig_maxit=0,
-                 eig_block=0, eig_filter=0, local_kernel=0, stream=None):
-        o = gn_dd_opts()
-        keep = []
-        for a in range(3):
-            o.nparts[a] = int(nparts[a])
-            c = np.ascontiguousarray(cuts[a], dtype=np.int32)
-            keep.append(c)
-            o.cuts[a] = _dptr(c, C.c_int32)
-        o.overlap, o.nev, o.threshold, o.nev_max = int(overlap), int(nev), float(threshold), int(nev_max)
-        o.local_prec = int(local_prec)
-        o.coarse = {"geneo": 1, "zem": 2, "none": 0}[coarse] if isinstance(coarse, str) else int(coarse)
-        o.shift, o.eig_tol, o.eig_maxit = float(shift), float(eig_tol), int(eig_maxit)
-        o.eig_block, o.eig_filter = int(eig_block), int(eig_filter)
-        o.local_kernel = int(local_kernel)
+                 eig_block=0, eig_filter=0, local_kernel=0, pou=0, coarse_solve=0, coarse_rtol=0.0,
+                 coarse_maxit=0, stream=None):
+        o, keep = _dd_struct(nparts, cuts, overlap, nev, threshold, nev_max, local_prec, coarse, shift, eig_tol,
+                             eig_maxit, eig_block, eig_filter, local_kernel, pou, coarse_solve, coarse_rtol,
+                             coarse_maxit)
         rep = gn_setup_report()
         h = C.c_void_p()
         _check(lib().gn_setup_geneo(prob.handle, C.byref(o), _stream(stream), C.byref(h), C.byref(rep)))
@@ -276,6 +321,7 @@ class Preconditioner:
 
     @classmethod
     def from_workload(cls, prob: Problem, w, local_prec=64, coarse=True, stream=None, **kw):
+        kw.setdefault("pou", getattr(w, "pou", "standard"))
         return cls(prob, w.nparts, w.cuts, overlap=w.overlap, nev=w.nev, threshold=w.threshold,
                    nev_max=w.nev_max, local_prec=local_prec, coarse=coarse, stream=stream, **kw)
 
@@ -318,10 +364,23 @@ def solve(prob: Problem, pc: Optional[Preconditioner], b, x, rtol=1e-8, maxit=10
     return st, [{f: getattr(r, f) for f, _ in gn_solve_report._fields_} for r in reps]
 
 
-def footprint(prob: Problem, pc: Optional[Preconditioner] = None) -> int:
+def resident_bytes(prob: Problem, pc: Optional[Preconditioner] = None) -> int:
     """Device bytes held by a problem and (optionally) its preconditioner."""
     b = C.c_int64()
-    _check(lib().gn_footprint(prob.handle, pc.handle if pc is not None else None, C.byref(b)))
+    _check(lib().gn_resident_bytes(prob.handle, pc.handle if pc is not None else None, C.byref(b)))
+    return b.value
+
+
+def footprint(w, local_prec=64, coarse=True, with_precond=True, **kw) -> int:
+    """A-priori resident bytes of a workload's operator (and preconditioner)
+    as a request server holds them (gn_footprint: host arithmetic only)."""
+    g, m, l, keep = _spec_structs(**_workload_spec(w))
+    b = C.c_int64()
+    if with_precond:
+        o, keep2 = _workload_dd(w, local_prec=local_prec, coarse=coarse, **kw)
+        _check(lib().gn_footprint(C.byref(g), int(w.pde), C.byref(o), C.byref(b)))
+    else:
+        _check(lib().gn_footprint(C.byref(g), int(w.pde), None, C.byref(b)))
     return b.value
 
 
@@ -343,6 +402,24 @@ class Server:
                                    C.byref(op), C.byref(by)))
         self.last_add_bytes = by.value
         return op.value
+
+    def register(self, w, local_prec=64, coarse=True, **kw):
+        """Register a workload by its description; the server builds it when a
+        request needs it and the budget allows (gn_server_register).  Returns
+        (operator id, footprint estimate)."""
+        g, m, l, keep = _spec_structs(**_workload_spec(w))
+        o, keep2 = _workload_dd(w, local_prec=local_prec, coarse=coarse, **kw)
+        op, est = C.c_int32(), C.c_int64()
+        _check(lib().gn_server_register(self.handle, C.byref(g), C.byref(m), C.byref(l), C.byref(o),
+                                        C.byref(op), C.byref(est)))
+        return op.value, est.value
+
+    def info(self, op: int):
+        """(resident, builds, evictions, bytes) of an operator."""
+        r, b, e, by = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib().gn_server_operator_info(self.handle, int(op), C.byref(r), C.byref(b), C.byref(e),
+                                             C.byref(by)))
+        return {"resident": bool(r.value), "builds": b.value, "evictions": e.value, "bytes": by.value}
 
     def remove(self, op: int):
         _check(lib().gn_server_remove(self.handle, int(op)))
@@ -382,6 +459,13 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def trim_memory() -> int:
+    """Return the library's cached idle device blocks to the runtime; bytes released."""
+    n = C.c_int64()
+    _check(lib().gn_trim_memory(C.byref(n)))
+    return n.value
 
 
 def profile_enable(on: bool = True):

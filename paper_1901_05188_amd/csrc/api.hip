@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 
 #include "gn_internal.h"
@@ -42,16 +43,108 @@ extern "C" const char* gn_last_error(void) { return g_last_error.c_str(); }
 
 static void argfail(const std::string& m) { throw gn_error{GN_ERR_ARG, m}; }
 
+// ---------------------------------------------------------------------------
+// device memory: a caching allocator
+// ---------------------------------------------------------------------------
+// Set-up allocates and frees many GB per call (pencil bands, block vectors,
+// coarse matrix); fresh hipMalloc/hipFree of that much memory took from
+// milliseconds to seconds from one call to the next.  Freed blocks therefore
+// stay with the process, keyed by their rounded size, and an allocation takes
+// the smallest cached block of at least its size and at most 1/8 larger.  A
+// failed hipMalloc returns every cached block to the runtime and tries once
+// more.  Callers free a block only after the work that used it has finished
+// (a stream or device synchronisation), so a reused block is idle.
+namespace {
+std::mutex g_pool_mu;
+std::multimap<size_t, void*> g_pool_free;   // rounded size -> idle block
+std::map<void*, size_t> g_pool_size;        // every live or idle block -> rounded size
+size_t g_pool_cached = 0;
+double g_pool_alloc_s = 0.0;                // seconds spent in hipMalloc/hipFree
+
+size_t pool_round(size_t bytes) {
+  if (bytes < ((size_t)1 << 20)) return (bytes + 511) & ~(size_t)511;
+  return (bytes + ((size_t)1 << 21) - 1) & ~(((size_t)1 << 21) - 1);
+}
+
+size_t pool_trim_locked() {
+  size_t n = 0;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (auto& kv : g_pool_free) {
+    (void)hipFree(kv.second);
+    g_pool_size.erase(kv.second);
+    n += kv.first;
+  }
+  g_pool_free.clear();
+  g_pool_cached = 0;
+  g_pool_alloc_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return n;
+}
+}  // namespace
+
+void* gnh::dev_alloc(size_t bytes) {
+  const size_t sz = pool_round(std::max(bytes, (size_t)1));
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_pool_free.lower_bound(sz);
+  if (it != g_pool_free.end() && it->first <= sz + sz / 8) {
+    void* p = it->second;
+    g_pool_cached -= it->first;
+    g_pool_free.erase(it);
+    return p;
+  }
+  void* p = nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipError_t e = hipMalloc(&p, sz);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    pool_trim_locked();
+    e = hipMalloc(&p, sz);
+  }
+  g_pool_alloc_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw gn_error{e == hipErrorOutOfMemory ? GN_ERR_OOM : GN_ERR_DEVICE,
+                   "device allocation of " + std::to_string(sz) + " bytes: " + hipGetErrorString(e)};
+  }
+  g_pool_size[p] = sz;
+  return p;
+}
+
+void gnh::dev_free(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_pool_size.find(p);
+  if (it == g_pool_size.end()) return;
+  g_pool_free.emplace(it->second, p);
+  g_pool_cached += it->second;
+}
+
+int64_t gnh::dev_size(const void* p) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_pool_size.find(const_cast<void*>(p));
+  return it == g_pool_size.end() ? 0 : (int64_t)it->second;
+}
+
+double gnh::dev_alloc_seconds() {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  return g_pool_alloc_s;
+}
+
+extern "C" gn_status gn_trim_memory(int64_t* released) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  (void)hipDeviceSynchronize();
+  const size_t n = pool_trim_locked();
+  if (released) *released = (int64_t)n;
+  return GN_OK;
+}
+
 template <typename T>
 static T* dalloc(std::vector<void*>& owned, size_t count) {
-  void* p = nullptr;
-  if (count == 0) count = 1;
-  GN_HIP(hipMalloc(&p, count * sizeof(T)));
+  void* p = gnh::dev_alloc(std::max(count, (size_t)1) * sizeof(T));
   owned.push_back(p);
   return (T*)p;
 }
 static void dfree_all(std::vector<void*>& owned) {
-  for (void* p : owned) (void)hipFree(p);
+  for (void* p : owned) gnh::dev_free(p);
   owned.clear();
 }
 template <typename T>
@@ -93,6 +186,19 @@ static void upload_descs(gn_precond* pc, hipStream_t s) {
   GN_HIP(hipMemcpyAsync(pc->d_subxI, pc->subxI.data(), sizeof(SubDesc) * n, hipMemcpyHostToDevice, s));
   GN_HIP(hipMemcpyAsync(pc->d_subxB, pc->subxB.data(), sizeof(SubDesc) * n, hipMemcpyHostToDevice, s));
 }
+PouDev gnh::pou_dev(const gn_problem* p, const gn_precond* pc) {
+  PouDev d;
+  for (int a = 0; a < 3; ++a) {
+    d.cnt[a] = pc->d_cnt[a];
+    d.plo[a] = pc->d_plo[a];
+    d.ecnt[a] = pc->d_ecnt[a];
+    d.er0[a] = pc->d_er0[a];
+    d.er1[a] = pc->d_er1[a];
+    d.ne[a] = p->ne[a];
+  }
+  d.kind = pc->pou;
+  return d;
+}
 double gnh::now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -100,10 +206,7 @@ using gnh::now_s;
 
 int64_t gnh::resident_bytes(const std::vector<void*>& owned) {
   int64_t t = 0;
-  for (void* q : owned) {
-    size_t sz = 0;
-    if (hipMemPtrGetInfo(q, &sz) == hipSuccess) t += (int64_t)sz;
-  }
+  for (void* q : owned) t += gnh::dev_size(q);
   return t;
 }
 
@@ -282,6 +385,7 @@ extern "C" gn_status gn_assemble(const gn_grid* grid, const gn_material* mat, co
   int nb = std::max(std::max(gnk::spmv_blocks(p), gnk::reduce_blocks()), gnk::prolong_blocks(p));
   p->d_part = dalloc<double>(p->owned, (size_t)nb);
   p->d_scal = dalloc<double>(p->owned, 64);
+  p->d_count = dalloc<unsigned>(p->owned, 1);
   GN_HIP(hipMemsetAsync(p->d_p, 0, sizeof(double) * p->n_dof, s));
   GN_HIP(hipMemsetAsync(p->d_scal, 0, sizeof(double) * 64, s));
   GN_HIP(hipStreamSynchronize(s));
@@ -423,6 +527,189 @@ void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e
 
 }  // namespace
 
+// Overlapping decomposition on the host (Section 3.1): per-axis element ranges
+// of the parts extended by the overlap, their V_h0 (I) node ranges, coverage
+// counts, and the subdomain descriptors with their band widths and storage
+// offsets.  Shared by the set-up and by the a-priori footprint.
+struct DdPlan {
+  std::vector<int> eR0[3], eR1[3], iR0[3], iR1[3];
+  std::vector<int> cnt[3], plo[3], ec[3];
+  std::vector<SubDesc> sub;
+  int64_t offTI = 0, offDI = 0, offVI = 0, offTB = 0, offDB = 0, offVB = 0;
+  int maxNBI = 0, maxNBB = 0, maxNI = 0, maxNB = 0, maxw = 0, maxwB = 0;
+};
+
+static DdPlan plan_decomposition(const int ne_[3], int nc, const gn_dd_opts* o) {
+  for (int a = 0; a < 3; ++a) {
+    if (o->nparts[a] < 1) argfail("nparts must be >= 1");
+    if (!o->cuts[a]) argfail("missing cuts");
+    if (o->cuts[a][0] != 0 || o->cuts[a][o->nparts[a]] != ne_[a]) argfail("cuts must span 0..ne");
+    for (int q = 0; q < o->nparts[a]; ++q)
+      if (o->cuts[a][q + 1] <= o->cuts[a][q]) argfail("cuts must increase");
+  }
+  const int n_sub = o->nparts[0] * o->nparts[1] * o->nparts[2];
+  if (n_sub > 1 && o->overlap < 1) argfail("overlap must be >= 1");
+  const int O = std::max(o->overlap, 0);
+  DdPlan pl;
+  for (int a = 0; a < 3; ++a) {
+    const int P = o->nparts[a], ne = ne_[a];
+    pl.cnt[a].assign(ne + 1, 0);
+    pl.plo[a].assign(ne + 1, -1);
+    pl.ec[a].assign(ne, 0);
+    for (int q = 0; q < P; ++q) {
+      const int e0 = std::max(0, o->cuts[a][q] - O), e1 = std::min(ne, o->cuts[a][q + 1] + O);
+      const int i0 = e0 + (e0 > 0 ? 1 : 0), i1 = e1 - (e1 < ne ? 1 : 0);   // inclusive node range
+      pl.eR0[a].push_back(e0);
+      pl.eR1[a].push_back(e1);
+      pl.iR0[a].push_back(i0);
+      pl.iR1[a].push_back(i1);
+      for (int i = i0; i <= i1; ++i) {
+        if (pl.cnt[a][i] == 0) pl.plo[a][i] = q;
+        ++pl.cnt[a][i];
+      }
+      for (int e = e0; e < e1; ++e) ++pl.ec[a][e];
+    }
+    for (int i = 0; i <= ne; ++i)
+      if (pl.cnt[a][i] == 0) argfail("a node lies in no subdomain interior: overlap too small");
+    for (int i = 0; i <= ne; ++i)
+      if (pl.cnt[a][i] > 0)
+        for (int q = pl.plo[a][i]; q < pl.plo[a][i] + pl.cnt[a][i]; ++q)
+          if (i < pl.iR0[a][q] || i > pl.iR1[a][q]) argfail("non-contiguous subdomain cover");
+  }
+  pl.sub.resize(n_sub);
+  for (int r = 0; r < o->nparts[2]; ++r)
+    for (int q = 0; q < o->nparts[1]; ++q)
+      for (int pp = 0; pp < o->nparts[0]; ++pp) {
+        const int j = pp + o->nparts[0] * (q + o->nparts[1] * r);
+        SubDesc& sd = pl.sub[j];
+        std::memset(&sd, 0, sizeof(sd));
+        const int idx[3] = {pp, q, r};
+        for (int a = 0; a < 3; ++a) {
+          sd.elo[a] = pl.eR0[a][idx[a]];
+          sd.ehi[a] = pl.eR1[a][idx[a]];
+          sd.ilo[a] = pl.iR0[a][idx[a]];
+          sd.in_[a] = pl.iR1[a][idx[a]] - pl.iR0[a][idx[a]] + 1;
+          sd.blo[a] = sd.elo[a];
+          sd.bn[a] = sd.ehi[a] - sd.elo[a] + 1;
+        }
+        axis_perm(sd.in_, sd.permI);
+        axis_perm(sd.bn, sd.permB);
+        sd.nI = sd.in_[0] * sd.in_[1] * sd.in_[2] * nc;
+        sd.nB = sd.bn[0] * sd.bn[1] * sd.bn[2] * nc;
+        sd.NBI = (sd.nI + TILE - 1) / TILE;
+        sd.NBB = (sd.nB + TILE - 1) / TILE;
+        sd.bwI = std::min(sd.nI - 1, band_width_dofs(sd.in_, sd.permI, nc));
+        sd.bwB = std::min(sd.nB - 1, band_width_dofs(sd.bn, sd.permB, nc));
+        sd.wI = std::max(std::min(sd.NBI - 1, (band_width_dofs(sd.in_, sd.permI, nc) + TILE - 1) / TILE), 0);
+        sd.wB = std::max(std::min(sd.NBB - 1, (band_width_dofs(sd.bn, sd.permB, nc) + TILE - 1) / TILE), 0);
+        sd.offTI = pl.offTI;
+        sd.offDI = pl.offDI;
+        sd.offVI = pl.offVI;
+        sd.offTB = pl.offTB;
+        sd.offDB = pl.offDB;
+        sd.offVB = pl.offVB;
+        pl.offTI += (int64_t)sd.NBI * (sd.wI + 1);
+        pl.offDI += sd.NBI;
+        pl.offVI += (int64_t)sd.NBI * TILE;
+        pl.offTB += (int64_t)sd.NBB * (sd.wB + 1);
+        pl.offDB += sd.NBB;
+        pl.offVB += (int64_t)sd.NBB * TILE;
+        pl.maxNBI = std::max(pl.maxNBI, sd.NBI);
+        pl.maxNBB = std::max(pl.maxNBB, sd.NBB);
+        pl.maxNI = std::max(pl.maxNI, sd.nI);
+        pl.maxNB = std::max(pl.maxNB, sd.nB);
+        pl.maxw = std::max(pl.maxw, sd.wI);
+        pl.maxwB = std::max(pl.maxwB, sd.wB);
+      }
+  return pl;
+}
+
+// Resident device bytes of an operator and its preconditioner from the sizes
+// alone (no device work): every allocation that gn_assemble, gn_setup_geneo,
+// the first solve (history of maxit iterations) and the batched workspace make
+// and keep, each rounded as the allocator rounds it.  The mask is unknown
+// here, so the free-to-full map is counted for every DOF; m_j is nev (fixed
+// count), nev_max (threshold: an upper bound) or the mode count (zero-energy
+// modes, every subdomain taken as floating).
+static int64_t estimate_footprint(const int ne[3], int nc, const gn_dd_opts* o, int nrhs, int maxit,
+                                  bool batched) {
+  int64_t t = 0;
+  auto add = [&](int64_t bytes) { t += (int64_t)pool_round((size_t)std::max<int64_t>(bytes, 1)); };
+  const int64_t nn[3] = {ne[0] + 1, ne[1] + 1, ne[2] + 1};
+  const int64_t n_node = nn[0] * nn[1] * nn[2], n_elem = (int64_t)ne[0] * ne[1] * ne[2];
+  const int64_t n_dof = n_node * nc, nd = 8 * nc;
+  const int KC = gnk::mc_width();
+  // problem
+  for (int a = 0; a < 3; ++a) add(nn[a] * 8);
+  add(n_dof);
+  add(n_dof * 4);
+  add(n_elem * nd * nd * 8);
+  add(n_node * 27 * nc * nc * 8);
+  add(n_dof * nrhs * 8);
+  for (int v = 0; v < 5; ++v) add(n_dof * 8);
+  const int64_t pstride = std::max<int64_t>((n_node + 255) / 256, gnk::reduce_blocks());
+  add(pstride * 8);
+  add(64 * 8);
+  add(4);
+  add((2 * (int64_t)maxit + 2) * 8);
+  if (batched) {
+    for (int v = 0; v < 5; ++v) add(n_dof * KC * 8);
+    add(pstride * KC * 8);
+    add((int64_t)S_N * KC * 8);
+    add((2 * (int64_t)maxit + 2) * KC * 8);
+  }
+  if (!o) return t;
+  // preconditioner
+  const DdPlan pl = plan_decomposition(ne, nc, o);
+  const int n_sub = (int)pl.sub.size();
+  for (int a = 0; a < 3; ++a) {
+    add(nn[a] * 4);
+    add(nn[a] * 4);
+    add((int64_t)ne[a] * 4);
+    add((int64_t)o->nparts[a] * 4);
+    add((int64_t)o->nparts[a] * 4);
+  }
+  for (int c = 0; c < 3; ++c) add((int64_t)std::max(n_sub, 1) * (int64_t)sizeof(SubDesc));
+  const int64_t fb = o->local_prec == 32 ? 4 : 8;
+  add(pl.offTI * TILE2 * fb);                 // backward (transposed) band
+  add(pl.offTI * TILE2 * fb);                 // forward band
+  add(pl.offDI * TILE2 * fb);                 // inverse diagonal tiles
+  add(pl.offVI * 8);
+  add(TILE2 * 8);
+  add(TILE2 * 4);
+  int64_t NH = 0, phi = 0;
+  if (o->coarse != 0 && n_sub > 1) {
+    const int m = o->coarse == 2 ? (nc == 3 ? 6 : 1) : (o->nev > 0 ? o->nev : o->nev_max);
+    for (const SubDesc& sd : pl.sub) {
+      NH += m;
+      phi += (int64_t)sd.nI * m;
+    }
+  }
+  const int64_t NBH = (NH + TILE - 1) / TILE;
+  if (NH > 0) {
+    add(phi * 8);
+    add(NBH * NBH * TILE2 * 8);
+    for (int v = 0; v < 3; ++v) add(NBH * TILE * 8);
+  }
+  if (batched) {
+    add(pl.offVI * KC * 8);
+    for (int v = 0; v < 3; ++v) add(std::max<int64_t>(NBH, 1) * TILE * KC * 8);
+  }
+  return t;
+}
+
+extern "C" gn_status gn_footprint(const gn_grid* grid, int32_t pde, const gn_dd_opts* opts, int64_t* bytes) {
+  GN_TRY
+  if (!grid || !bytes) argfail("null argument");
+  if (pde != 0 && pde != 1) argfail("pde must be 0 (diffusion) or 1 (elasticity)");
+  for (int a = 0; a < 3; ++a)
+    if (grid->ne[a] < 1) argfail("ne must be >= 1 on every axis");
+  if (opts && opts->local_prec != 64 && opts->local_prec != 32) argfail("local_prec must be 64 or 32");
+  *bytes = estimate_footprint(grid->ne, pde == 1 ? 3 : 1, opts, 1, 2000, true);
+  return GN_OK;
+  GN_CATCH
+}
+
 extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* stream, gn_precond** out,
                                     gn_setup_report* rep) {
   if (out) *out = nullptr;
@@ -432,13 +719,11 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   if (!p || !o || !out) argfail("null argument");
   hipStream_t s = (hipStream_t)stream;
   const double t0 = now_s();
+  const double ta0 = gnh::dev_alloc_seconds();
   const int nc = p->nc;
   for (int a = 0; a < 3; ++a) {
     if (o->nparts[a] < 1) argfail("nparts must be >= 1");
     if (!o->cuts[a]) argfail("missing cuts");
-    if (o->cuts[a][0] != 0 || o->cuts[a][o->nparts[a]] != p->ne[a]) argfail("cuts must span 0..ne");
-    for (int q = 0; q < o->nparts[a]; ++q)
-      if (o->cuts[a][q + 1] <= o->cuts[a][q]) argfail("cuts must increase");
   }
   const int n_sub = o->nparts[0] * o->nparts[1] * o->nparts[2];
   if (n_sub > 1 && o->overlap < 1) argfail("overlap must be >= 1");
@@ -458,87 +743,27 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   pc->n_sub = n_sub;
   pc->overlap = O;
   pc->local_prec = o->local_prec;
+  if (o->pou < 0 || o->pou > 1) argfail("pou must be 0 (standard) or 1 (smooth)");
+  pc->pou = o->pou;
   if (o->local_kernel < 0 || o->local_kernel > 1) argfail("local_kernel must be 0 or 1");
   pc->local_kernel = o->local_kernel;
   for (int a = 0; a < 3; ++a) {
     pc->nparts[a] = o->nparts[a];
     pc->cuts[a].assign(o->cuts[a], o->cuts[a] + o->nparts[a] + 1);
   }
-  // per-axis ranges: element range of part q, its I node range and Ibar node range
-  std::vector<int> eR0[3], eR1[3], iR0[3], iR1[3];
+  const DdPlan plan = plan_decomposition(p->ne, nc, o);
   for (int a = 0; a < 3; ++a) {
-    int P = o->nparts[a], ne = p->ne[a];
-    std::vector<int> cnt(ne + 1, 0), plo(ne + 1, -1), ec(ne, 0);
-    for (int q = 0; q < P; ++q) {
-      int e0 = std::max(0, pc->cuts[a][q] - O), e1 = std::min(ne, pc->cuts[a][q + 1] + O);
-      int i0 = e0 + (e0 > 0 ? 1 : 0), i1 = e1 - (e1 < ne ? 1 : 0);   // inclusive node range
-      eR0[a].push_back(e0);
-      eR1[a].push_back(e1);
-      iR0[a].push_back(i0);
-      iR1[a].push_back(i1);
-      for (int i = i0; i <= i1; ++i) {
-        if (cnt[i] == 0) plo[i] = q;
-        ++cnt[i];
-      }
-      for (int e = e0; e < e1; ++e) ++ec[e];
-    }
-    for (int i = 0; i <= ne; ++i)
-      if (cnt[i] == 0) argfail("a node lies in no subdomain interior: overlap too small");
-    for (int i = 0; i <= ne; ++i)
-      if (cnt[i] > 0)
-        for (int q = plo[i]; q < plo[i] + cnt[i]; ++q)
-          if (i < iR0[a][q] || i > iR1[a][q]) argfail("non-contiguous subdomain cover");
-    pc->d_cnt[a] = upload(pc->owned, cnt.data(), cnt.size(), s);
-    pc->d_plo[a] = upload(pc->owned, plo.data(), plo.size(), s);
-    pc->d_ecnt[a] = upload(pc->owned, ec.data(), ec.size(), s);
+    pc->d_cnt[a] = upload(pc->owned, plan.cnt[a].data(), plan.cnt[a].size(), s);
+    pc->d_plo[a] = upload(pc->owned, plan.plo[a].data(), plan.plo[a].size(), s);
+    pc->d_ecnt[a] = upload(pc->owned, plan.ec[a].data(), plan.ec[a].size(), s);
+    pc->d_er0[a] = upload(pc->owned, plan.eR0[a].data(), plan.eR0[a].size(), s);
+    pc->d_er1[a] = upload(pc->owned, plan.eR1[a].data(), plan.eR1[a].size(), s);
   }
-  // subdomain descriptors
-  pc->sub.resize(n_sub);
-  int64_t offTI = 0, offDI = 0, offVI = 0, offTB = 0, offDB = 0, offVB = 0;
-  int maxNBI = 0, maxNBB = 0, maxNI = 0, maxNB_ = 0, maxw = 0;
-  for (int r = 0; r < o->nparts[2]; ++r)
-    for (int q = 0; q < o->nparts[1]; ++q)
-      for (int pp = 0; pp < o->nparts[0]; ++pp) {
-        int j = pp + o->nparts[0] * (q + o->nparts[1] * r);
-        SubDesc& sd = pc->sub[j];
-        std::memset(&sd, 0, sizeof(sd));
-        int idx[3] = {pp, q, r};
-        for (int a = 0; a < 3; ++a) {
-          sd.elo[a] = eR0[a][idx[a]];
-          sd.ehi[a] = eR1[a][idx[a]];
-          sd.ilo[a] = iR0[a][idx[a]];
-          sd.in_[a] = iR1[a][idx[a]] - iR0[a][idx[a]] + 1;
-          sd.blo[a] = sd.elo[a];
-          sd.bn[a] = sd.ehi[a] - sd.elo[a] + 1;
-        }
-        axis_perm(sd.in_, sd.permI);
-        axis_perm(sd.bn, sd.permB);
-        sd.nI = sd.in_[0] * sd.in_[1] * sd.in_[2] * nc;
-        sd.nB = sd.bn[0] * sd.bn[1] * sd.bn[2] * nc;
-        sd.NBI = (sd.nI + TILE - 1) / TILE;
-        sd.NBB = (sd.nB + TILE - 1) / TILE;
-        sd.wI = std::min(sd.NBI - 1, (band_width_dofs(sd.in_, sd.permI, nc) + TILE - 1) / TILE);
-        sd.wB = std::min(sd.NBB - 1, (band_width_dofs(sd.bn, sd.permB, nc) + TILE - 1) / TILE);
-        sd.wI = std::max(sd.wI, 0);
-        sd.wB = std::max(sd.wB, 0);
-        sd.offTI = offTI;
-        sd.offDI = offDI;
-        sd.offVI = offVI;
-        sd.offTB = offTB;
-        sd.offDB = offDB;
-        sd.offVB = offVB;
-        offTI += (int64_t)sd.NBI * (sd.wI + 1);
-        offDI += sd.NBI;
-        offVI += (int64_t)sd.NBI * TILE;
-        offTB += (int64_t)sd.NBB * (sd.wB + 1);
-        offDB += sd.NBB;
-        offVB += (int64_t)sd.NBB * TILE;
-        maxNBI = std::max(maxNBI, sd.NBI);
-        maxNBB = std::max(maxNBB, sd.NBB);
-        maxNI = std::max(maxNI, sd.nI);
-        maxNB_ = std::max(maxNB_, sd.nB);
-        maxw = std::max(maxw, sd.wI);
-      }
+  pc->sub = plan.sub;
+  const int64_t offTI = plan.offTI, offDI = plan.offDI, offVI = plan.offVI, offTB = plan.offTB,
+                offDB = plan.offDB, offVB = plan.offVB;
+  const int maxNBI = plan.maxNBI, maxNBB = plan.maxNBB, maxNI = plan.maxNI, maxNB_ = plan.maxNB, maxw = plan.maxw;
+  (void)offVB;
   pc->tilesI = offTI;
   pc->vecI = offVI;
   pc->maxNBI = maxNBI;
@@ -883,7 +1108,17 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
                                               "(raise eig_block)"};
       break;
     }
-    // V now holds the Ritz vectors of the last Rayleigh-Ritz step (h_nu)
+    // V now holds the Ritz vectors of the last Rayleigh-Ritz step (h_nu).  Each
+    // eigenvalue is reported as the Rayleigh quotient p^T A_N p / p^T B p of its
+    // Ritz vector, summed from element energies: 1/nu - s would lose about
+    // log10(s / lambda) digits to cancellation when lambda is far below s.
+    std::vector<double> h_rq((size_t)n_sub * b);
+    {
+      double* d_rq = dalloc<double>(tmp, (size_t)n_sub * b);
+      gnk::eig_rq(p, pc, b, V, d_rq, s);
+      GN_HIP(hipMemcpyAsync(h_rq.data(), d_rq, sizeof(double) * h_rq.size(), hipMemcpyDeviceToHost, s));
+      GN_HIP(hipStreamSynchronize(s));
+    }
     pc->n_eval = b;
     pc->lam.assign((size_t)n_sub * b, 0.0);
     pc->lam_n.assign(n_sub, b);
@@ -891,8 +1126,8 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     for (int j = 0; j < n_sub; ++j) {
       std::vector<double> lam(b);
       for (int k = 0; k < b; ++k) {
-        double nk = h_nu[(size_t)j * b + k];
-        lam[k] = nk > 1e-12 / shift ? 1.0 / nk - shift : INFINITY;
+        const double nk = h_nu[(size_t)j * b + k], rq = h_rq[(size_t)j * b + k];
+        lam[k] = nk > 1e-12 / shift ? (std::isfinite(rq) ? rq : 1.0 / nk - shift) : INFINITY;
         pc->lam[(size_t)j * b + k] = lam[k];
       }
       int finite = 0;
@@ -983,15 +1218,23 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   // algorithmic bytes of one preconditioner application (for the roofline report)
   {
     const double fb = pc->local_prec == 32 ? 4.0 : 8.0;
-    double tb = 0.0, pb = 0.0;
+    double tb = 0.0, tbt = 0.0, pb = 0.0;
     for (const SubDesc& sd : pc->sub) {
-      // forward + backward sweep over the band (lower-triangle tiles touched) + inverse diagonals
+      // algorithmic: the forward sweep reads the factor's band once (row r holds
+      // min(r, bw) + 1 entries), the backward sweep reads it once more; the
+      // gather reads r on I_j, z_j is written, Phi_j is read for the restriction
+      double entries = 0.0;
+      for (int r = 0; r < sd.nI; ++r) entries += (double)std::min(r, sd.bwI) + 1.0;
+      const double vec = (double)sd.nI * 8.0 * 2.0 + (double)sd.nI * sd.m * 8.0;
+      tb += 2.0 * entries * fb + vec;
+      // as stored: whole band tiles (lower-triangle tiles touched) and inverse diagonals
       double tiles = 0.0;
       for (int K = 0; K < sd.NBI; ++K) tiles += std::min(K, sd.wI);
-      tb += 2.0 * (tiles + sd.NBI) * TILE2 * fb + (double)sd.nI * 8.0 * (1 + 1) + (double)sd.nI * sd.m * 8.0;
+      tbt += 2.0 * (tiles + sd.NBI) * TILE2 * fb + vec;
       pb += (double)sd.nI * 8.0 + (double)sd.nI * sd.m * 8.0;
     }
     pc->trsv_bytes = tb;
+    pc->trsv_tile_bytes = tbt;
     pc->prolong_bytes = pb + (double)p->n_dof * 8.0 * 2.0;
     // batched: the band is read once for all 16 columns; the gather writes the
     // 16-wide local vectors, which both sweeps read and write once more
@@ -1019,6 +1262,9 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     rep->t_eigen_s = t2 - t1;
     rep->t_coarse_s = t3 - t2;
     rep->t_total_s = now_s() - t0;
+    rep->t_alloc_s = gnh::dev_alloc_seconds() - ta0;
+    rep->apply_bytes = pc->trsv_bytes;
+    rep->apply_tile_bytes = pc->trsv_tile_bytes;
     rep->hbm_bytes = hb;
     rep->eig_resid = eig_resid;
   }
@@ -1139,7 +1385,8 @@ void gnh::ensure_batch_workspace(gn_problem* p, gn_precond* pc, int maxit, hipSt
   }
   if (p->histm_stride < 2 * maxit + 2) {
     if (p->d_histm) {
-      (void)hipFree(p->d_histm);
+      GN_HIP(hipStreamSynchronize(s));
+      gnh::dev_free(p->d_histm);
       p->owned.erase(std::remove(p->owned.begin(), p->owned.end(), (void*)p->d_histm), p->owned.end());
     }
     p->histm_stride = 2 * maxit + 2;
@@ -1169,11 +1416,14 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
   if (!(opts->rtol > 0) || opts->maxit < 1) argfail("rtol > 0 and maxit >= 1 required");
   if (pc && pc->prob != p) argfail("preconditioner built for another problem");
   hipStream_t s = (hipStream_t)stream;
+  if (gnk::count_nonfinite(p->n_free, nrhs, ld, b_dev, p->d_count, s) != 0)
+    argfail("right-hand side holds NaN or infinite entries");
   const int chunk = opts->check_every > 0 ? opts->check_every : 8;
   const int64_t n = p->n_dof;
   if (p->hist_cap < 2 * opts->maxit + 2) {
     if (p->d_hist) {
-      (void)hipFree(p->d_hist);
+      GN_HIP(hipStreamSynchronize(s));
+      gnh::dev_free(p->d_hist);
       p->owned.erase(std::remove(p->owned.begin(), p->owned.end(), (void*)p->d_hist), p->owned.end());
     }
     p->d_hist = dalloc<double>(p->owned, (size_t)2 * opts->maxit + 2);

@@ -68,25 +68,10 @@ __global__ __launch_bounds__(NT) void k_extract_local(const SubDesc* __restrict_
 // (eqm:matrixForm: A_{Omega_j} over the elements of Omega_j, A_{Omega_j^o} over
 // the elements that also belong to another subdomain, X the PoU diagonal).
 // ---------------------------------------------------------------------------
-struct PouAxes {
-  const int* cnt0; const int* cnt1; const int* cnt2;      // node coverage counts
-  const int* ec0; const int* ec1; const int* ec2;         // element coverage counts
-};
-
-__device__ inline double pou_value(const SubDesc& sd, const PouAxes& pa, const uint8_t* dir, int NX,
-                                   int NY, int NC, int gi, int gj, int gk, int c) {
-  if (gi < sd.ilo[0] || gi >= sd.ilo[0] + sd.in_[0] || gj < sd.ilo[1] ||
-      gj >= sd.ilo[1] + sd.in_[1] || gk < sd.ilo[2] || gk >= sd.ilo[2] + sd.in_[2])
-    return 0.0;
-  int64_t node = gi + (int64_t)NX * (gj + (int64_t)NY * gk);
-  if (dir[node * NC + c]) return 0.0;
-  return 1.0 / (double)(pa.cnt0[gi] * pa.cnt1[gj] * pa.cnt2[gk]);
-}
-
 template <int NC>
 __global__ __launch_bounds__(NT) void k_extract_pencil(const SubDesc* __restrict__ subs, int nex, int ney, int nez,
                                                        const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
-                                                       PouAxes pa, double shift, double* __restrict__ L) {
+                                                       PouDev pa, double shift, double* __restrict__ L) {
   const SubDesc& sd = subs[blockIdx.y];
   int r = blockIdx.x * NT + threadIdx.x;
   int nrows = sd.NBB * TILE;
@@ -102,7 +87,7 @@ __global__ __launch_bounds__(NT) void k_extract_pencil(const SubDesc* __restrict
   box_global_node(sd.blo, sd.bn, sd.permB, ln, g);
   int64_t node = g[0] + (int64_t)NX * (g[1] + (int64_t)NY * g[2]);
   bool dr = dir[node * NC + c];
-  double xr = pou_value(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
+  double xr = pou_x(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
   for (int d = 0; d < 27; ++d) {
     int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
     int h[3] = {g[0] + dx, g[1] + dy, g[2] + dz};
@@ -128,7 +113,7 @@ __global__ __launch_bounds__(NT) void k_extract_pencil(const SubDesc* __restrict
           int64_t e = ex + (int64_t)nex * (ey + (int64_t)ney * ez);
           int a1 = (g[0] - ex) + 2 * (g[1] - ey) + 4 * (g[2] - ez);
           int a2 = (h[0] - ex) + 2 * (h[1] - ey) + 4 * (h[2] - ez);
-          bool ov = pa.ec0[ex] * pa.ec1[ey] * pa.ec2[ez] >= 2;
+          bool ov = pou_overlap_elem(pa, ex, ey, ez);
           const double* row = Ke + e * (64 * NC * NC) + (int64_t)(a1 * NC + c) * (8 * NC) + a2 * NC;
 #pragma unroll
           for (int c2 = 0; c2 < NC; ++c2) {
@@ -146,7 +131,7 @@ __global__ __launch_bounds__(NT) void k_extract_pencil(const SubDesc* __restrict
       if (dr || dir[node2 * NC + c2]) {
         v = (r2 == r) ? 1.0 : 0.0;
       } else {
-        double x2 = pou_value(sd, pa, dir, NX, NY, NC, h[0], h[1], h[2], c2);
+        double x2 = pou_x(sd, pa, dir, NX, NY, NC, h[0], h[1], h[2], c2);
         v = vN[c2] + shift * xr * x2 * vO[c2];
       }
       int K = r / TILE, J = r2 / TILE;
@@ -162,23 +147,6 @@ struct BandRef {
   int64_t offT, offD;
   int NB, w;
 };
-
-// acc(i, c) -= sum_k X(i,k) Y(c,k) for the thread's 4 outputs; X,Y column-major tiles in LDS
-__device__ inline void tile_nt_update(double acc[4], const double* Xs, const double* Ys, int i, int c0) {
-#pragma unroll 8
-  for (int k = 0; k < TILE; ++k) {
-    double x = Xs[k * (TILE + 1) + i];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] -= x * Ys[k * (TILE + 1) + c0 + 8 * q];
-  }
-}
-
-__device__ inline void load_tile_lds(double* dst, const double* src) {
-  for (int t = threadIdx.x; t < TILE2; t += NT) {
-    int col = t / TILE, row = t % TILE;
-    dst[col * (TILE + 1) + row] = src[t];
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Left-looking band Cholesky on FP64 matrix cores.  Block row K, tile t (column
@@ -381,104 +349,6 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
   if (threadIdx.x == 0) info[blockIdx.x] = fail;
 }
 
-__global__ __launch_bounds__(NT) void k_band_chol(const BandRef* __restrict__ mats, double* __restrict__ T,
-                                                  double* __restrict__ D, int* __restrict__ info) {
-  __shared__ double Xs[TILE * (TILE + 1)];
-  __shared__ double Ys[TILE * (TILE + 1)];
-  __shared__ double Ss[TILE * (TILE + 1)];
-  __shared__ int fail;
-  const BandRef br = mats[blockIdx.x];
-  const int w = br.w, NB = br.NB;
-  const int i = threadIdx.x % TILE;       // output row
-  const int c0 = threadIdx.x / TILE;      // output columns c0, c0+8, c0+16, c0+24
-  if (threadIdx.x == 0) fail = 0;
-  __syncthreads();
-  for (int K = 0; K < NB; ++K) {
-    for (int t = 0; t <= w; ++t) {
-      int J = K - w + t;
-      if (J < 0) continue;
-      double* tk = T + tile_off(br.offT, K, t, w);
-      double acc[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = tk[(c0 + 8 * q) * TILE + i];
-      for (int t2 = 0; t2 < t; ++t2) {
-        int J2 = K - w + t2;
-        if (J2 < 0) continue;
-        __syncthreads();
-        load_tile_lds(Xs, T + tile_off(br.offT, K, t2, w));
-        if (t == w)
-          load_tile_lds(Ys, T + tile_off(br.offT, K, t2, w));
-        else
-          load_tile_lds(Ys, T + tile_off(br.offT, J, t2 - t + w, w));
-        __syncthreads();
-        tile_nt_update(acc, Xs, Ys, i, c0);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Ss[(c0 + 8 * q) * (TILE + 1) + i] = acc[q];
-      if (t < w) {
-        // L(K,J) = S * Dinv_J^T : out(i,c) = sum_k S(i,k) Dinv_J(c,k)
-        load_tile_lds(Ys, D + (br.offD + J) * TILE2);
-        __syncthreads();
-        double o[4] = {0, 0, 0, 0};
-        for (int k = 0; k < TILE; ++k) {
-          double s = Ss[k * (TILE + 1) + i];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) o[q] += s * Ys[k * (TILE + 1) + c0 + 8 * q];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) tk[(c0 + 8 * q) * TILE + i] = o[q];
-        __threadfence_block();
-      } else {
-        __syncthreads();
-        // dense Cholesky of the diagonal tile in LDS (lower)
-        for (int k = 0; k < TILE; ++k) {
-          if (threadIdx.x == 0) {
-            double dkk = Ss[k * (TILE + 1) + k];
-            if (!(dkk > 0.0)) {
-              if (!fail) fail = K * TILE + k + 1;
-              dkk = 1.0;
-            }
-            Ss[k * (TILE + 1) + k] = sqrt(dkk);
-          }
-          __syncthreads();
-          double piv = Ss[k * (TILE + 1) + k];
-          if (threadIdx.x > k && threadIdx.x < TILE) Ss[k * (TILE + 1) + threadIdx.x] /= piv;
-          __syncthreads();
-          for (int e = threadIdx.x; e < TILE2; e += NT) {
-            int rr = e % TILE, cc = e / TILE;
-            if (cc > k && rr >= cc)
-              Ss[cc * (TILE + 1) + rr] -= Ss[k * (TILE + 1) + rr] * Ss[k * (TILE + 1) + cc];
-          }
-          __syncthreads();
-        }
-        // zero the strict upper part, store L_KK
-        for (int e = threadIdx.x; e < TILE2; e += NT) {
-          int rr = e % TILE, cc = e / TILE;
-          tk[cc * TILE + rr] = (rr >= cc) ? Ss[cc * (TILE + 1) + rr] : 0.0;
-        }
-        // inverse of the lower-triangular tile: column cc by forward substitution
-        if (threadIdx.x < TILE) {
-          int cc = threadIdx.x;
-          double xv[TILE];
-#pragma unroll
-          for (int r2 = 0; r2 < TILE; ++r2) xv[r2] = 0.0;
-          for (int r2 = cc; r2 < TILE; ++r2) {
-            double s = (r2 == cc) ? 1.0 : 0.0;
-            for (int k = cc; k < r2; ++k) s -= Ss[k * (TILE + 1) + r2] * xv[k];
-            xv[r2] = s / Ss[r2 * (TILE + 1) + r2];
-          }
-          double* dk = D + (br.offD + K) * TILE2;
-          for (int r2 = 0; r2 < TILE; ++r2) dk[cc * TILE + r2] = xv[r2];
-        }
-        __threadfence_block();
-      }
-      __syncthreads();
-    }
-  }
-  if (threadIdx.x == 0) info[blockIdx.x] = fail;
-}
-
 // ---------------------------------------------------------------------------
 // FP64 -> FP32 copy of the local factors (mixed-precision local solves)
 // ---------------------------------------------------------------------------
@@ -550,7 +420,7 @@ void extract_local(const gn_problem* p, const gn_precond* pc, double* L, int max
 void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, double* L, int maxNB,
                     hipStream_t s) {
   dim3 grid((unsigned)((maxNB * TILE + NT - 1) / NT), (unsigned)pc->n_sub);
-  PouAxes pa{pc->d_cnt[0], pc->d_cnt[1], pc->d_cnt[2], pc->d_ecnt[0], pc->d_ecnt[1], pc->d_ecnt[2]};
+  const PouDev pa = gnh::pou_dev(p, pc);
   if (p->nc == 3)
     hipLaunchKernelGGL(k_extract_pencil<3>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1],
                        p->ne[2], p->d_Ke, p->d_dir, pa, shift, L);

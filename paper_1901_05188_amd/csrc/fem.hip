@@ -368,8 +368,7 @@ void element_matrices(gn_problem* p, const double* d_mats, int n_mat, const int*
   Geo g = make_geo(p);
   int n_elem = (int)p->n_elem;
   if (p->pde == 1) {
-    double* dC = nullptr;
-    GN_HIP(hipMalloc((void**)&dC, sizeof(double) * 36 * (size_t)n_elem));
+    double* dC = (double*)gnh::dev_alloc(sizeof(double) * 36 * (size_t)n_elem);
     hipLaunchKernelGGL(k_material, dim3((n_elem + 127) / 128), dim3(128), 0, s, n_elem, d_mats,
                        d_emat, d_eang, d_etilt, dC);
     GN_CHECK_LAUNCH();
@@ -378,7 +377,7 @@ void element_matrices(gn_problem* p, const double* d_mats, int n_mat, const int*
                        p->ne[0], p->ne[1], n_elem, dC, p->d_Ke);
     GN_CHECK_LAUNCH();
     GN_HIP(hipStreamSynchronize(s));
-    GN_HIP(hipFree(dC));
+    gnh::dev_free(dC);
   } else {
     int64_t nt = (int64_t)n_elem * 8;
     hipLaunchKernelGGL(k_ke_scalar, dim3((unsigned)((nt + 127) / 128)), dim3(128), 0, s, g,

@@ -22,28 +22,13 @@ constexpr int NT = 256;
 // ---------------------------------------------------------------------------
 // B V on the Ibar box (matrix-free from element matrices), b columns
 // ---------------------------------------------------------------------------
-struct PouAx {
-  const int* cnt0; const int* cnt1; const int* cnt2;
-  const int* ec0; const int* ec1; const int* ec2;
-};
-
-__device__ inline double xpou(const SubDesc& sd, const PouAx& pa, const uint8_t* dir, int NX, int NY,
-                              int NC, int gi, int gj, int gk, int c) {
-  if (gi < sd.ilo[0] || gi >= sd.ilo[0] + sd.in_[0] || gj < sd.ilo[1] ||
-      gj >= sd.ilo[1] + sd.in_[1] || gk < sd.ilo[2] || gk >= sd.ilo[2] + sd.in_[2])
-    return 0.0;
-  int64_t node = gi + (int64_t)NX * (gj + (int64_t)NY * gk);
-  if (dir[node * NC + c]) return 0.0;
-  return 1.0 / (double)(pa.cnt0[gi] * pa.cnt1[gj] * pa.cnt2[gk]);
-}
-
 // B = X A_O X stored once per set-up in node-ELL form on the Ibar box:
 // BE[k][r], k = d*NC + c2 (27 lattice offsets x components), structure of
 // arrays over the padded rows of each subdomain (base offVB * 27 * NC).
 template <int NC>
 __global__ __launch_bounds__(NT) void k_extract_b(const SubDesc* __restrict__ subs, int nex, int ney,
                                                   const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
-                                                  PouAx pa, double* __restrict__ BE) {
+                                                  PouDev pa, double* __restrict__ BE) {
   const SubDesc& sd = subs[blockIdx.y];
   const int r = blockIdx.x * NT + threadIdx.x;
   const int npad = sd.NBB * TILE;
@@ -57,7 +42,7 @@ __global__ __launch_bounds__(NT) void k_extract_b(const SubDesc* __restrict__ su
   const int ln = r / NC, c = r % NC;
   int g[3];
   box_global_node(sd.blo, sd.bn, sd.permB, ln, g);
-  const double xr = xpou(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
+  const double xr = pou_x(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
   for (int d = 0; d < 27; ++d) {
     int h[3] = {g[0] + d % 3 - 1, g[1] + (d / 3) % 3 - 1, g[2] + d / 9 - 1};
     double vO[NC];
@@ -76,7 +61,7 @@ __global__ __launch_bounds__(NT) void k_extract_b(const SubDesc* __restrict__ su
       for (int ez = lo[2]; ez <= hi[2]; ++ez)
         for (int ey = lo[1]; ey <= hi[1]; ++ey)
           for (int ex = lo[0]; ex <= hi[0]; ++ex) {
-            if (pa.ec0[ex] * pa.ec1[ey] * pa.ec2[ez] < 2) continue;   // not in Omega_j^o
+            if (!pou_overlap_elem(pa, ex, ey, ez)) continue;   // not in Omega_j^o
             int64_t e = ex + (int64_t)nex * (ey + (int64_t)ney * ez);
             int a1 = (g[0] - ex) + 2 * (g[1] - ey) + 4 * (g[2] - ez);
             int a2 = (h[0] - ex) + 2 * (h[1] - ey) + 4 * (h[2] - ez);
@@ -85,7 +70,7 @@ __global__ __launch_bounds__(NT) void k_extract_b(const SubDesc* __restrict__ su
             for (int c2 = 0; c2 < NC; ++c2) vO[c2] += row[c2];
           }
 #pragma unroll
-      for (int c2 = 0; c2 < NC; ++c2) vO[c2] *= xr * xpou(sd, pa, dir, NX, NY, NC, h[0], h[1], h[2], c2);
+      for (int c2 = 0; c2 < NC; ++c2) vO[c2] *= xr * pou_x(sd, pa, dir, NX, NY, NC, h[0], h[1], h[2], c2);
     }
 #pragma unroll
     for (int c2 = 0; c2 < NC; ++c2) base[(int64_t)(d * NC + c2) * npad + r] = vO[c2];
@@ -218,133 +203,16 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
   }
 }
 
-// ---------------------------------------------------------------------------
-// in-place V <- P^-1 V with the banded factor of P (forward then backward), b <= 64
-// columns, on FP64 matrix cores.  Each block-row step is a dense contraction of
-// 32 x 32 band tiles with 32 x 16 right-hand-side blocks:
-//   forward   Y_K = Dinv_K (V_K - sum_t L(K,t) Y_{K-w+t})
-//   backward  X_K = Dinv_K^T (Y_K - sum_d L(K+d,K)^T X_{K+d})
-// The columns are independent: workgroup j holds two waves (rows 0..15 and
-// 16..31 of the block row) per 16-column block of subdomain j.  The waves of a
-// row half load the same tiles at nearly the same time, so each band tile is
-// fetched from HBM once per sweep for all column blocks.
 // v_mfma_f64_16x16x4f64 lane layout: A[l%16][l/16], B[l/16][l%16],
 // result item j of lane l = D[4j + l/16][l%16].
-// ---------------------------------------------------------------------------
 typedef double gn_d4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(512) void k_trsm_pencil(const SubDesc* __restrict__ subs, int n_sub, int b,
-                                                     const double* __restrict__ T, const double* __restrict__ D,
-                                                     double* __restrict__ V) {
-  __shared__ double sSall[4][TILE][16 + 1];
-  const int j = blockIdx.x;
-  if (j >= n_sub) return;
-  const SubDesc& sd = subs[j];
-  const int NB = sd.NBB, w = sd.wB;
-  const double* Tb = T + sd.offTB * TILE2;
-  const double* Db = D + sd.offDB * TILE2;
-  double* Vb = V + sd.offVB * b;
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wid = wv & 1, cb = wv >> 1;   // row half, column block
-  double (*sS)[16 + 1] = sSall[cb];
-  const int lr = lane & 15, lk = lane >> 4;
-  const int rb = wid * 16;
-  const int col = cb * 16 + lr;          // < 64: the buffers carry 64 doubles of tail padding
-  const bool ok = col < b;
-  gn_d4 acc[4];
-#define GN_ZERO4(X_) _Pragma("unroll") for (int u = 0; u < 4; ++u) X_[u] = gn_d4{0, 0, 0, 0};
-  // ---- forward ----
-  for (int K = 0; K < NB; ++K) {
-    GN_ZERO4(acc)
-    for (int t = max(0, w - K); t < w; ++t) {
-      const double* tile = Tb + ((int64_t)K * (w + 1) + t) * TILE2;
-      const double* yj = Vb + (int64_t)(K - w + t) * TILE * b;
-      double av[8], bv[8];
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        const int k = 4 * ks + lk;
-        av[ks] = tile[k * TILE + rb + lr];
-        bv[ks] = yj[k * b + col];
-      }
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks)
-        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], ok ? bv[ks] : 0.0, acc[ks & 3], 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int row = rb + 4 * i + lk;
-      double a4 = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
-      sS[row][lr] = ok ? Vb[(int64_t)(K * TILE + row) * b + col] - a4 : 0.0;
-    }
-    __syncthreads();
-    const double* dk = Db + (int64_t)K * TILE2;
-    GN_ZERO4(acc)
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-      const int k = 4 * ks + lk;
-      acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dk[k * TILE + rb + lr], sS[k][lr], acc[ks & 3], 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int row = rb + 4 * i + lk;
-      double o4 = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
-      if (ok) Vb[(int64_t)(K * TILE + row) * b + col] = o4;
-    }
-    __threadfence_block();
-    __syncthreads();
-  }
-  // ---- backward ----
-  for (int K = NB - 1; K >= 0; --K) {
-    GN_ZERO4(acc)
-    const int dmax = min(w, NB - 1 - K);
-    for (int d = 1; d <= dmax; ++d) {
-      const double* tile = Tb + ((int64_t)(K + d) * (w + 1) + (w - d)) * TILE2;
-      const double* xj = Vb + (int64_t)(K + d) * TILE * b;
-      double av[8], bv[8];
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        const int k = 4 * ks + lk;
-        av[ks] = tile[(rb + lr) * TILE + k];   // L(k, row) of block (K+d, K): transposed operand
-        bv[ks] = xj[k * b + col];
-      }
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks)
-        acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], ok ? bv[ks] : 0.0, acc[ks & 3], 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int row = rb + 4 * i + lk;
-      double a4 = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
-      sS[row][lr] = ok ? Vb[(int64_t)(K * TILE + row) * b + col] - a4 : 0.0;
-    }
-    __syncthreads();
-    const double* dk = Db + (int64_t)K * TILE2;
-    GN_ZERO4(acc)
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-      const int k = 4 * ks + lk;
-      acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(dk[(rb + lr) * TILE + k], sS[k][lr], acc[ks & 3], 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int row = rb + 4 * i + lk;
-      double o4 = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
-      if (ok) Vb[(int64_t)(K * TILE + row) * b + col] = o4;
-    }
-    __threadfence_block();
-    __syncthreads();
-  }
-#undef GN_ZERO4
-}
-
-// Barrier that orders LDS traffic only: outstanding global loads stay in flight.
+// Barrier that orders LDS traffic only: global loads in flight stay in flight.
 __device__ inline void geneo_lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
-
 
 // ---------------------------------------------------------------------------
 // Block solves, one wave per SIMD: four waves per workgroup (row half x tile
@@ -1047,6 +915,74 @@ __global__ __launch_bounds__(NT) void k_zem_modes(const SubDesc* __restrict__ su
   out[5] = c == 0 ? -d1 : (c == 1 ? d0 : 0.0);
 }
 
+// Rayleigh quotients lambda_k = p_k^T A_N p_k / p_k^T B p_k of the b columns of
+// V on each subdomain's Ibar box (eq-geneo with v = p), both energies summed
+// element by element: A_N over the elements of Omega_j, B = X A_O X over those
+// that also lie in another subdomain.  Every term is an element energy
+// (non-negative up to rounding), so the quotient keeps the digits that
+// 1/nu - s cancels when lambda is far below the shift.  Workgroup (j, chunk of
+// 16 columns): lane c % 16 of the column chunk, 16 element lanes striding the
+// elements of the box; the partial energies are added in a fixed order.
+template <int NC>
+__global__ __launch_bounds__(NT) void k_eig_rq(const SubDesc* __restrict__ subs, int nex, int ney,
+                                               const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
+                                               PouDev pa, int b, const double* __restrict__ V,
+                                               double* __restrict__ lam) {
+  constexpr int ND = 8 * NC;
+  __shared__ double sa[16][17], sb[16][17];
+  const SubDesc& sd = subs[blockIdx.x];
+  const int cl = threadIdx.x & 15, el = threadIdx.x >> 4;
+  const int col = blockIdx.y * 16 + cl;
+  const int NX = nex + 1, NY = ney + 1;
+  const int n0 = sd.ehi[0] - sd.elo[0], n1 = sd.ehi[1] - sd.elo[1], n2 = sd.ehi[2] - sd.elo[2];
+  const int nel = n0 * n1 * n2;
+  double ea = 0.0, eb = 0.0;
+  if (col < b) {
+    const double* Vb = V + sd.offVB * b + col;
+    for (int t = el; t < nel; t += 16) {
+      const int ex = sd.elo[0] + t % n0, ey = sd.elo[1] + (t / n0) % n1, ez = sd.elo[2] + t / (n0 * n1);
+      double pv[ND], xv[ND];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int g0 = ex + (a & 1), g1 = ey + ((a >> 1) & 1), g2 = ez + (a >> 2);
+        const int rb = box_local_node(sd.blo, sd.bn, sd.permB, g0, g1, g2) * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          pv[a * NC + c] = Vb[(int64_t)(rb + c) * b];
+          xv[a * NC + c] = pou_x(sd, pa, dir, NX, NY, NC, g0, g1, g2, c) * pv[a * NC + c];
+        }
+      }
+      const bool ov = pou_overlap_elem(pa, ex, ey, ez);
+      const double* K = Ke + (ex + (int64_t)nex * (ey + (int64_t)ney * ez)) * (ND * ND);
+      double sA = 0.0, sB = 0.0;
+      for (int i = 0; i < ND; ++i) {
+        double kp = 0.0, kx = 0.0;
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+          const double k = K[i * ND + j];
+          kp += k * pv[j];
+          kx += k * xv[j];
+        }
+        sA += pv[i] * kp;
+        sB += xv[i] * kx;
+      }
+      ea += sA;
+      if (ov) eb += sB;
+    }
+  }
+  sa[el][cl] = ea;
+  sb[el][cl] = eb;
+  __syncthreads();
+  if (el == 0 && col < b) {
+    double ta = 0.0, tb = 0.0;
+    for (int q = 0; q < 16; ++q) {
+      ta += sa[q][cl];
+      tb += sb[q][cl];
+    }
+    lam[(int64_t)blockIdx.x * b + col] = tb > 0.0 ? ta / tb : INFINITY;
+  }
+}
+
 // Ritz residual sums of one subdomain: the GRAM_SPLIT row-split partials added
 // in fixed order (the same sums k_small_eig forms)
 __global__ void k_resid_sum(int b, const double* __restrict__ resp, double* __restrict__ res) {
@@ -1108,7 +1044,7 @@ __global__ __launch_bounds__(NT) void k_normalise(const SubDesc* __restrict__ su
 // Phi_j (I-box rows x m_j, row-major) = X p on the I box
 template <int NC>
 __global__ __launch_bounds__(NT) void k_build_phi(const SubDesc* __restrict__ subs, int NX, int NY,
-                                                  const uint8_t* __restrict__ dir, PouAx pa, int b,
+                                                  const uint8_t* __restrict__ dir, PouDev pa, int b,
                                                   const double* __restrict__ V, double* __restrict__ Phi) {
   const SubDesc& sd = subs[blockIdx.y];
   int r = blockIdx.x * NT + threadIdx.x;
@@ -1116,7 +1052,7 @@ __global__ __launch_bounds__(NT) void k_build_phi(const SubDesc* __restrict__ su
   int g[3];
   box_global_node(sd.ilo, sd.in_, sd.permI, r / NC, g);
   int c = r % NC;
-  double x = xpou(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
+  double x = pou_x(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
   int rb = box_local_node(sd.blo, sd.bn, sd.permB, g[0], g[1], g[2]) * NC + c;
   const double* vr = V + sd.offVB * b + (int64_t)rb * b;
   double* out = Phi + sd.offPhi + (int64_t)r * sd.m;
@@ -1366,13 +1302,22 @@ __global__ __launch_bounds__(NT) void k_trinv_update(int NB, int K, const double
 
 namespace gnk {
 
-static PouAx pou_axes(const gn_precond* pc) {
-  return PouAx{pc->d_cnt[0], pc->d_cnt[1], pc->d_cnt[2], pc->d_ecnt[0], pc->d_ecnt[1], pc->d_ecnt[2]};
-}
+static PouDev pou_axes(const gn_precond* pc) { return gnh::pou_dev(pc->prob, pc); }
 
 void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s) {
   hipLaunchKernelGGL(k_vinit, dim3((maxNBB * TILE + NT - 1) / NT, pc->n_sub), dim3(NT), 0, s,
                      pc->d_sub, b, V);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_rq(const gn_problem* p, const gn_precond* pc, int b, const double* V, double* lam, hipStream_t s) {
+  dim3 grid((unsigned)pc->n_sub, (unsigned)((b + 15) / 16));
+  if (p->nc == 3)
+    hipLaunchKernelGGL(k_eig_rq<3>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke, p->d_dir,
+                       pou_axes(pc), b, V, lam);
+  else
+    hipLaunchKernelGGL(k_eig_rq<1>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke, p->d_dir,
+                       pou_axes(pc), b, V, lam);
   GN_CHECK_LAUNCH();
 }
 
@@ -1479,15 +1424,9 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
       return;
     }
   }
-  // one workgroup per subdomain, two waves (row halves) per 16-column block: the
-  // waves of a row half read the same band tiles, so each tile leaves HBM once
-  // (in place: the right-hand sides are copied into V first)
-  size_t vlen = 0;
-  for (const SubDesc& sd : pc->sub) vlen = std::max(vlen, (size_t)(sd.offVB + (int64_t)sd.NBB * TILE) * b);
-  if (Vin != V) GN_HIP(hipMemcpyAsync(V, Vin, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(k_trsm_pencil, dim3(pc->n_sub), dim3(128 * ((b + 15) / 16)), 0, s, pc->d_sub, pc->n_sub, b,
-                     T, D, V);
-  GN_CHECK_LAUNCH();
+  throw gn_error{GN_ERR_ARG, "GenEO pencil band of " + std::to_string(maxw) +
+                                 " tiles is wider than the block solves take (30 tiles, or the LDS ring of " +
+                                 std::to_string(b) + " columns does not fit): use more subdomains"};
 }
 
 int gram_split() { return GRAM_SPLIT; }

@@ -58,6 +58,7 @@ struct SubDesc {
   int m;                // number of coarse vectors
   int coff;             // first coarse index i(j, 0)
   int64_t offPhi;       // offset (doubles) of Phi_j (NBI*TILE rows x m, row-major)
+  int bwI, bwB;         // half bandwidth in DOFs of the local matrix and of the pencil
 };
 
 // local DOF index <-> global node on a box with an axis permutation
@@ -79,6 +80,73 @@ __host__ __device__ inline void box_global_node(const int lo[3], const int n[3],
   gijk[0] = g[0] + lo[0];
   gijk[1] = g[1] + lo[1];
   gijk[2] = g[2] + lo[2];
+}
+
+// ---------------------------------------------------------------------------
+// partition of unity X_j (Section 3.2, def:pou; Section 3.3.1)
+// ---------------------------------------------------------------------------
+// Per-axis tables of the tensor-product decomposition: for node index i along
+// axis a, cnt[a][i] parts hold i in their I range, the first being plo[a][i];
+// ecnt[a][e] parts hold element e in their element range; er0/er1[a][q] is
+// the element range [er0, er1) of part q (overlap included).
+struct PouDev {
+  const int* cnt[3];
+  const int* plo[3];
+  const int* ecnt[3];
+  const int* er0[3];
+  const int* er1[3];
+  int ne[3];
+  int kind;   // 0: one over the number of subdomains; 1: smooth (distance-weighted)
+};
+
+// Element layers between node index i and the artificial ends of the element
+// range [e0, e1) along one axis (ends on the physical boundary do not count).
+__host__ __device__ inline int pou_dist(int i, int e0, int e1, int ne) {
+  int d = 1 << 28;
+  if (e0 > 0) d = i - e0 < d ? i - e0 : d;
+  if (e1 < ne) d = e1 - i < d ? e1 - i : d;
+  return d > 0 ? d : 0;
+}
+
+// X_j at DOF c of node (gi, gj, gk): zero off the I box of subdomain sd and on
+// Dirichlet DOFs.  kind 0 gives 1 / #{subdomains whose I box holds the node};
+// kind 1 weights subdomain j by the distance of the node to the artificial
+// boundary of Omega_j (in element layers, the smallest over the box's
+// artificial faces) and divides by the sum of those weights over all
+// subdomains, so the weights fall linearly to zero across each overlap.  The
+// weights are small integers, so the sums are exact.
+__device__ inline double pou_x(const SubDesc& sd, const PouDev& pa, const uint8_t* dir, int NX, int NY,
+                               int NC, int gi, int gj, int gk, int c) {
+  if (gi < sd.ilo[0] || gi >= sd.ilo[0] + sd.in_[0] || gj < sd.ilo[1] || gj >= sd.ilo[1] + sd.in_[1] ||
+      gk < sd.ilo[2] || gk >= sd.ilo[2] + sd.in_[2])
+    return 0.0;
+  const int64_t node = gi + (int64_t)NX * (gj + (int64_t)NY * gk);
+  if (dir[node * NC + c]) return 0.0;
+  if (pa.kind == 0) return 1.0 / (double)(pa.cnt[0][gi] * pa.cnt[1][gj] * pa.cnt[2][gk]);
+  const int g[3] = {gi, gj, gk};
+  int wj = 1 << 28;
+  for (int a = 0; a < 3; ++a) {
+    const int d = pou_dist(g[a], sd.elo[a], sd.ehi[a], pa.ne[a]);
+    wj = d < wj ? d : wj;
+  }
+  double sum = 0.0;
+  for (int q2 = pa.plo[2][gk]; q2 < pa.plo[2][gk] + pa.cnt[2][gk]; ++q2)
+    for (int q1 = pa.plo[1][gj]; q1 < pa.plo[1][gj] + pa.cnt[1][gj]; ++q1)
+      for (int q0 = pa.plo[0][gi]; q0 < pa.plo[0][gi] + pa.cnt[0][gi]; ++q0) {
+        const int q[3] = {q0, q1, q2};
+        int wk = 1 << 28;
+        for (int a = 0; a < 3; ++a) {
+          const int d = pou_dist(g[a], pa.er0[a][q[a]], pa.er1[a][q[a]], pa.ne[a]);
+          wk = d < wk ? d : wk;
+        }
+        sum += (double)wk;
+      }
+  return sum > 0.0 ? (double)wj / sum : 0.0;
+}
+
+// element e lies in at least two subdomains (Omega_j^o for each subdomain holding it)
+__device__ inline bool pou_overlap_elem(const PouDev& pa, int ex, int ey, int ez) {
+  return pa.ecnt[0][ex] * pa.ecnt[1][ey] * pa.ecnt[2][ez] >= 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -118,6 +186,7 @@ struct gn_problem {
   double* d_scal = nullptr;    // device scalars
   double* d_hist = nullptr;    // alpha/beta history
   int hist_cap = 0;
+  unsigned* d_count = nullptr; // counter of the input checks
   // batched (multi-RHS) CG workspace: 16 columns of each vector, per-column
   // partial sums, scalars and alpha/beta history
   double *d_Xm = nullptr, *d_Rm = nullptr, *d_Pm = nullptr, *d_Qm = nullptr, *d_Zm = nullptr;
@@ -150,6 +219,9 @@ struct gn_precond {
   int* d_cnt[3] = {nullptr, nullptr, nullptr};   // #parts whose I-range holds node index
   int* d_plo[3] = {nullptr, nullptr, nullptr};   // first such part
   int* d_ecnt[3] = {nullptr, nullptr, nullptr};  // #parts whose element range holds element
+  int* d_er0[3] = {nullptr, nullptr, nullptr};   // element range [er0, er1) of each part
+  int* d_er1[3] = {nullptr, nullptr, nullptr};
+  int pou = 0;                                   // 0 standard, 1 smooth partition of unity
   // local factors
   double* d_LI = nullptr;    // band tiles (FP64) or nullptr
   float* d_LIf = nullptr;    // band tiles (FP32) or nullptr
@@ -169,6 +241,7 @@ struct gn_precond {
   double* d_z0 = nullptr;    // one zero tile (FP64) read by masked prefetch slots
   float* d_zf = nullptr;     // one zero tile (FP32)
   double trsv_bytes = 0.0, prolong_bytes = 0.0;
+  double trsv_tile_bytes = 0.0;  // the same launch counted over whole 32 x 32 band tiles
   double trsv_bytes_mc = 0.0;  // gather + banded solves of one 16-column batch
   double* d_tm = nullptr;      // local vectors of a batch: (offVI + row) * 16 + column
   double *d_gm = nullptr, *d_um = nullptr, *d_ym = nullptr;  // coarse vectors, column * NBH*TILE
@@ -208,6 +281,8 @@ void update_xr(int64_t n, double* x, double* r, const double* p, const double* q
                double* part, hipStream_t s);
 void update_p(int64_t n, double* p, const double* z, const double* scal, hipStream_t s);
 void copy(int64_t n, double* dst, const double* src, const double* done, hipStream_t s);
+// NaN / infinite entries of ncol device columns (synchronises the stream)
+unsigned count_nonfinite(int64_t n, int ncol, int64_t ld, const double* x, unsigned* d_count, hipStream_t s);
 void residual_partial(int64_t n, const double* b, const double* q, double* part, hipStream_t s);
 void sub_partial(int64_t n, const double* b, const double* q, double* r, double* part, hipStream_t s);
 // band.hip
@@ -264,6 +339,7 @@ void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const
 void eig_normalise(const gn_precond* pc, int b, int ncol, double* V, hipStream_t s);
 void zem_modes(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s);
 void eig_resid_sum(int n_sub, int b, const double* resp, double* res, hipStream_t s);
+void eig_rq(const gn_problem* p, const gn_precond* pc, int b, const double* V, double* lam, hipStream_t s);
 void build_phi(const gn_problem* p, const gn_precond* pc, int b, int maxNI, const double* V,
                hipStream_t s);
 void aphi(const gn_problem* p, const gn_precond* pc, int b, int maxNB, double* Y, hipStream_t s);
@@ -279,6 +355,14 @@ void tri_inv(int NB, const double* L, const double* Dinv, double* Z, hipStream_t
 // host helpers of the solve paths (api.hip)
 // ---------------------------------------------------------------------------
 namespace gnh {
+// caching device allocator (api.hip): blocks freed with dev_free are kept for
+// reuse by later allocations of about the same size; dev_free only after the
+// work that used the block has finished
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+int64_t dev_size(const void* p);     // rounded size of a block from dev_alloc (0 if unknown)
+double dev_alloc_seconds();          // cumulative time spent in hipMalloc/hipFree
+PouDev pou_dev(const gn_problem* p, const gn_precond* pc);
 constexpr double kEps = 2.220446049250313e-16;
 // restarts stop once b - A x is within this factor of eps || |A| |x| ||
 constexpr double kFloorFactor = 1.0;

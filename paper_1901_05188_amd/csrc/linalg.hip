@@ -232,6 +232,16 @@ __global__ __launch_bounds__(RTHR) void k_sub(int64_t n, const double* __restric
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
+// number of NaN / infinite entries in ncol columns of length n (leading dim ld)
+__global__ void k_count_nonfinite(int64_t n, int ncol, int64_t ld, const double* __restrict__ x,
+                                  unsigned* __restrict__ count) {
+  unsigned c = 0;
+  const int64_t tot = n * ncol;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x)
+    c += isfinite(x[(t / n) * ld + t % n]) ? 0u : 1u;
+  if (c) atomicAdd(count, c);
+}
+
 __global__ void k_copy(int64_t n, double* __restrict__ dst, const double* __restrict__ src,
                        const double* __restrict__ done) {
   if (done && *done != 0.0) return;
@@ -331,6 +341,16 @@ void sub_partial(int64_t n, const double* b, const double* q, double* r, double*
   hipLaunchKernelGGL(k_sub, dim3(RBLK), dim3(RTHR), 0, s, n, b, q, r, part);
   GN_CHECK_LAUNCH();
 }
+unsigned count_nonfinite(int64_t n, int ncol, int64_t ld, const double* x, unsigned* d_count, hipStream_t s) {
+  unsigned h = 0;
+  GN_HIP(hipMemsetAsync(d_count, 0, sizeof(unsigned), s));
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(RBLK), dim3(RTHR), 0, s, n, ncol, ld, x, d_count);
+  GN_CHECK_LAUNCH();
+  GN_HIP(hipMemcpyAsync(&h, d_count, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  GN_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
 void copy(int64_t n, double* dst, const double* src, const double* done, hipStream_t s) {
   hipLaunchKernelGGL(k_copy, dim3(RBLK), dim3(RTHR), 0, s, n, dst, src, done);
   GN_CHECK_LAUNCH();

@@ -265,12 +265,37 @@ struct Request {
   std::vector<gn_solve_report> rep;
 };
 
+// Host copy of an operator's description (gn_server_register): the server
+// builds the operator from it when a request needs it and the budget allows,
+// and may destroy and rebuild it later.
+struct Spec {
+  int ne[3] = {0, 0, 0};
+  std::vector<double> xn[3];
+  int map_kind = 0;
+  double map_par[3] = {0, 0, 0};
+  int pde = 0, n_mat = 0;
+  std::vector<double> mat, elem_angle, elem_tilt, elem_k, body, traction;
+  std::vector<int32_t> elem_mat;
+  std::vector<uint8_t> dirichlet;
+  int nrhs = 1;
+  gn_dd_opts dd{};
+  std::vector<int32_t> cuts[3];
+};
+
 struct Operator {
   int id = -1;
   gn_problem* p = nullptr;
   gn_precond* pc = nullptr;
   hipStream_t s = nullptr;
-  int64_t bytes = 0;
+  int64_t bytes = 0;        // measured footprint while resident (budget share)
+  int64_t est = 0;          // a-priori footprint (server-built operators)
+  int64_t n_free = 0;
+  std::unique_ptr<Spec> spec;   // set: the server builds, evicts and rebuilds the operator
+  bool resident = true;
+  bool building = false;
+  bool evict_req = false;
+  double last_use = 0.0;
+  int builds = 0, evictions = 0;
   std::deque<SlotColumn> queue;
   std::thread worker;
   bool stop = false;
@@ -282,7 +307,7 @@ struct Operator {
 
 struct gn_server {
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_mem;
   int device = 0;
   int slots = 16, chunk = 8, maxit_cap = 2000;
   int64_t budget = 0, used = 0;
@@ -311,29 +336,186 @@ static void fail_operator(gn_server* sv, Operator& o, gn_status st) {
   }
   o.inflight = 0;
   sv->cv_done.notify_all();
+  sv->cv_mem.notify_all();
+}
+
+// Reserve `need` bytes of the budget for operator self (lock held): while they
+// do not fit, ask the least recently used idle server-built operator to evict
+// itself and wait for the memory to come back.  Returns false when even
+// evicting every idle server-built operator cannot make room (the resident
+// caller-registered operators and the busy ones hold the rest).
+static bool reserve_budget(gn_server* sv, std::unique_lock<std::mutex>& lk, Operator* self, int64_t need) {
+  for (;;) {
+    if (self && self->stop) return false;
+    if (sv->used + need <= sv->budget) {
+      sv->used += need;
+      return true;
+    }
+    int64_t fixed = 0;    // resident caller-registered operators: never evicted
+    Operator* victim = nullptr;
+    bool pending = false; // memory that will come back: evictions, builds, busy server-built operators
+    for (auto& up : sv->ops) {
+      Operator* o = up.get();
+      if (!o || o == self) continue;
+      if (!o->spec) {
+        if (o->resident) fixed += o->bytes;
+        continue;
+      }
+      if (o->building || o->evict_req) {
+        pending = true;
+        continue;
+      }
+      if (!o->resident) continue;
+      if (o->queue.empty() && o->inflight == 0) {
+        if (!victim || o->last_use < victim->last_use) victim = o;
+      } else {
+        pending = true;
+      }
+    }
+    if (fixed + need > sv->budget) return false;
+    if (victim) {
+      victim->evict_req = true;
+      sv->cv_work.notify_all();
+    } else if (!pending) {
+      return false;
+    }
+    sv->cv_mem.wait(lk);
+  }
+}
+
+// Build a server-registered operator on its own stream (lock not held).
+static gn_status build_operator(Operator& o, std::string& err) {
+  const Spec& sp = *o.spec;
+  gn_grid g{};
+  for (int a = 0; a < 3; ++a) {
+    g.ne[a] = sp.ne[a];
+    g.xn[a] = sp.xn[a].data();
+  }
+  g.map_kind = sp.map_kind;
+  g.map_par = sp.map_par;
+  gn_material m{};
+  m.pde = sp.pde;
+  m.n_mat = sp.n_mat;
+  m.mat = sp.mat.empty() ? nullptr : sp.mat.data();
+  m.elem_mat = sp.elem_mat.empty() ? nullptr : sp.elem_mat.data();
+  m.elem_angle = sp.elem_angle.empty() ? nullptr : sp.elem_angle.data();
+  m.elem_tilt = sp.elem_tilt.empty() ? nullptr : sp.elem_tilt.data();
+  m.elem_k = sp.elem_k.empty() ? nullptr : sp.elem_k.data();
+  gn_loads l{};
+  l.dirichlet = sp.dirichlet.data();
+  l.body = sp.body.empty() ? nullptr : sp.body.data();
+  l.nrhs = sp.nrhs;
+  l.traction = sp.traction.empty() ? nullptr : sp.traction.data();
+  gn_dd_opts dd = sp.dd;
+  for (int a = 0; a < 3; ++a) dd.cuts[a] = sp.cuts[a].data();
+  gn_problem* p = nullptr;
+  gn_precond* pc = nullptr;
+  gn_status st = gn_assemble(&g, &m, &l, o.s, &p);
+  if (st == GN_OK) {
+    gn_setup_report rep{};
+    st = gn_setup_geneo(p, &dd, o.s, &pc, &rep);
+    if (st != GN_OK) gn_destroy_problem(p);
+  }
+  if (st != GN_OK) {
+    err = gn_last_error();
+    return st;
+  }
+  o.p = p;
+  o.pc = pc;
+  return GN_OK;
 }
 
 static void worker_main(gn_server* sv, Operator* op_ptr) {
   Operator& o = *op_ptr;
   (void)hipSetDevice(sv->device);
   std::unique_ptr<SlotEngine> eng;
-  try {
-    eng.reset(new SlotEngine(o.p, o.pc, sv->slots, sv->chunk, sv->maxit_cap, o.s));
-  } catch (const gn_error& e) {
-    std::lock_guard<std::mutex> lk(sv->mu);
-    fail_operator(sv, o, e.code);
-    return;
-  }
+  auto make_engine = [&]() -> bool {
+    try {
+      eng.reset(new SlotEngine(o.p, o.pc, sv->slots, sv->chunk, sv->maxit_cap, o.s));
+      return true;
+    } catch (const gn_error& e) {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      fail_operator(sv, o, e.code);
+      return false;
+    }
+  };
+  if (o.resident && !make_engine()) return;
   std::vector<SlotResult> res;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(sv->mu);
-      sv->cv_work.wait(lk, [&] { return o.stop || !o.queue.empty() || eng->busy(); });
-      if (o.queue.empty() && !eng->busy()) return;   // stop requested and drained
+      sv->cv_work.wait(lk, [&] {
+        return o.stop || !o.queue.empty() || (eng && eng->busy()) || (o.evict_req && o.queue.empty());
+      });
+      const bool busy = eng && eng->busy();
+      if (o.stop && o.queue.empty() && !busy) return;   // stop requested and drained
+      if (o.evict_req && o.queue.empty() && !busy) {
+        // evict: free the operator's device memory; it is rebuilt on demand
+        lk.unlock();
+        eng.reset();
+        (void)hipStreamSynchronize(o.s);
+        gn_destroy_precond(o.pc);
+        gn_destroy_problem(o.p);
+        lk.lock();
+        o.pc = nullptr;
+        o.p = nullptr;
+        sv->used -= o.bytes;
+        o.bytes = 0;
+        o.resident = false;
+        o.evict_req = false;
+        ++o.evictions;
+        sv->cv_mem.notify_all();
+        continue;
+      }
+      o.evict_req = false;
+      if (!o.resident) {
+        // admission: the operator is built once its a-priori footprint fits
+        o.building = true;
+        if (!reserve_budget(sv, lk, &o, o.est)) {
+          o.building = false;
+          fail_operator(sv, o, GN_ERR_OOM);
+          o.failed = false;          // later requests may fit once others are removed
+          continue;
+        }
+        lk.unlock();
+        std::string err;
+        const gn_status st = build_operator(o, err);
+        int64_t measured = 0;
+        if (st == GN_OK) {
+          try {
+            gnh::ensure_batch_workspace(o.p, o.pc, sv->maxit_cap, o.s);
+            GN_HIP(hipStreamSynchronize(o.s));
+            measured = gnh::resident_bytes(o.p->owned) + gnh::resident_bytes(o.pc->owned);
+          } catch (const gn_error& e) {
+            lk.lock();
+            sv->used -= o.est;
+            o.building = false;
+            fail_operator(sv, o, e.code);
+            return;
+          }
+        }
+        lk.lock();
+        sv->used -= o.est;
+        o.building = false;
+        if (st != GN_OK) {
+          gn_set_error(st, err);
+          fail_operator(sv, o, st);
+          return;
+        }
+        sv->used += measured;
+        o.bytes = measured;
+        o.resident = true;
+        ++o.builds;
+        sv->cv_mem.notify_all();
+        lk.unlock();
+        if (!make_engine()) return;
+        lk.lock();
+      }
       while (!o.queue.empty() && eng->free_slots() > 0) {
         eng->admit(o.queue.front());
         o.queue.pop_front();
       }
+      o.last_use = now_s();
     }
     res.clear();
     gn_status err = GN_OK;
@@ -360,7 +542,11 @@ static void worker_main(gn_server* sv, Operator* op_ptr) {
         q.t_done = t;
       }
     }
-    if (!res.empty()) sv->cv_done.notify_all();
+    o.last_use = t;
+    if (!res.empty()) {
+      sv->cv_done.notify_all();
+      if (o.inflight == 0) sv->cv_mem.notify_all();   // an idle operator can now be evicted
+    }
   }
 }
 
@@ -399,7 +585,7 @@ extern "C" gn_status gn_server_create(const gn_server_opts* opts, gn_server** ou
   SV_CATCH
 }
 
-extern "C" gn_status gn_footprint(const gn_problem* p, const gn_precond* pc, int64_t* bytes) {
+extern "C" gn_status gn_resident_bytes(const gn_problem* p, const gn_precond* pc, int64_t* bytes) {
   SV_TRY
   if (!p || !bytes) throw gn_error{GN_ERR_ARG, "null argument"};
   if (pc && pc->prob != p) throw gn_error{GN_ERR_ARG, "preconditioner built for another problem"};
@@ -420,20 +606,108 @@ extern "C" gn_status gn_server_add(gn_server* sv, gn_problem* p, gn_precond* pc,
   GN_HIP(hipStreamSynchronize(nullptr));
   const int64_t b = gnh::resident_bytes(p->owned) + (pc ? gnh::resident_bytes(pc->owned) : 0);
   if (bytes) *bytes = b;
-  if (sv->used + b > sv->budget)
+  // idle server-built operators are evicted to make room if needed
+  if (!reserve_budget(sv, lk, nullptr, b))
     throw gn_error{GN_ERR_OOM, "operator footprint exceeds the server's remaining HBM budget"};
   std::unique_ptr<Operator> o(new Operator());
   o->p = p;
   o->pc = pc;
   o->bytes = b;
+  o->n_free = p->n_free;
+  o->last_use = now_s();
   GN_HIP(hipStreamCreateWithFlags(&o->s, hipStreamNonBlocking));
   const int id = (int)sv->ops.size();
   o->id = id;
   Operator* raw = o.get();
   sv->ops.push_back(std::move(o));
-  sv->used += b;
   raw->worker = std::thread(worker_main, sv, raw);
   *op = id;
+  return GN_OK;
+  SV_CATCH
+}
+
+extern "C" gn_status gn_server_register(gn_server* sv, const gn_grid* grid, const gn_material* mat,
+                                        const gn_loads* loads, const gn_dd_opts* opts, int32_t* op,
+                                        int64_t* est_bytes) {
+  SV_TRY
+  if (!sv || !grid || !mat || !loads || !opts || !op) throw gn_error{GN_ERR_ARG, "null argument"};
+  std::unique_ptr<Spec> sp(new Spec());
+  int64_t n_elem = 1, n_node = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (grid->ne[a] < 1 || !grid->xn[a]) throw gn_error{GN_ERR_ARG, "bad grid"};
+    sp->ne[a] = grid->ne[a];
+    sp->xn[a].assign(grid->xn[a], grid->xn[a] + grid->ne[a] + 1);
+    n_elem *= grid->ne[a];
+    n_node *= grid->ne[a] + 1;
+  }
+  sp->map_kind = grid->map_kind;
+  if (grid->map_kind == 1) {
+    if (!grid->map_par) throw gn_error{GN_ERR_ARG, "ramp map needs map_par"};
+    for (int a = 0; a < 3; ++a) sp->map_par[a] = grid->map_par[a];
+  }
+  if (mat->pde != 0 && mat->pde != 1) throw gn_error{GN_ERR_ARG, "pde must be 0 or 1"};
+  const int nc = mat->pde == 1 ? 3 : 1;
+  sp->pde = mat->pde;
+  sp->n_mat = mat->n_mat;
+  auto copy_d = [](std::vector<double>& dst, const double* src, int64_t n) {
+    if (src) dst.assign(src, src + n);
+  };
+  if (mat->pde == 1) {
+    if (!mat->mat || !mat->elem_mat || mat->n_mat < 1) throw gn_error{GN_ERR_ARG, "elasticity needs materials"};
+    copy_d(sp->mat, mat->mat, 9 * (int64_t)mat->n_mat);
+    sp->elem_mat.assign(mat->elem_mat, mat->elem_mat + n_elem);
+    copy_d(sp->elem_angle, mat->elem_angle, n_elem);
+    copy_d(sp->elem_tilt, mat->elem_tilt, n_elem);
+  } else {
+    if (!mat->elem_k) throw gn_error{GN_ERR_ARG, "diffusion needs elem_k"};
+    copy_d(sp->elem_k, mat->elem_k, n_elem);
+  }
+  if (!loads->dirichlet || loads->nrhs < 1) throw gn_error{GN_ERR_ARG, "bad loads"};
+  sp->dirichlet.assign(loads->dirichlet, loads->dirichlet + n_node * nc);
+  copy_d(sp->body, loads->body, n_elem * nc);
+  sp->nrhs = loads->nrhs;
+  copy_d(sp->traction, loads->traction, (int64_t)loads->nrhs * grid->ne[0] * grid->ne[1] * nc);
+  sp->dd = *opts;
+  for (int a = 0; a < 3; ++a) {
+    if (opts->nparts[a] < 1 || !opts->cuts[a]) throw gn_error{GN_ERR_ARG, "bad cuts"};
+    sp->cuts[a].assign(opts->cuts[a], opts->cuts[a] + opts->nparts[a] + 1);
+    sp->dd.cuts[a] = nullptr;
+  }
+  int64_t est = 0;
+  if (gn_footprint(grid, mat->pde, opts, &est) != GN_OK) throw gn_error{GN_ERR_ARG, gn_last_error()};
+  int64_t n_free = 0;
+  for (uint8_t d : sp->dirichlet) n_free += d ? 0 : 1;
+  if (n_free == 0) throw gn_error{GN_ERR_ARG, "no free DOFs"};
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (est > sv->budget) throw gn_error{GN_ERR_OOM, "operator footprint exceeds the server's HBM budget"};
+  std::unique_ptr<Operator> o(new Operator());
+  o->spec = std::move(sp);
+  o->resident = false;
+  o->est = est;
+  o->n_free = n_free;
+  GN_HIP(hipStreamCreateWithFlags(&o->s, hipStreamNonBlocking));
+  const int id = (int)sv->ops.size();
+  o->id = id;
+  Operator* raw = o.get();
+  sv->ops.push_back(std::move(o));
+  raw->worker = std::thread(worker_main, sv, raw);
+  *op = id;
+  if (est_bytes) *est_bytes = est;
+  return GN_OK;
+  SV_CATCH
+}
+
+extern "C" gn_status gn_server_operator_info(gn_server* sv, int32_t op, int32_t* resident, int32_t* builds,
+                                             int32_t* evictions, int64_t* bytes) {
+  SV_TRY
+  if (!sv) throw gn_error{GN_ERR_ARG, "null argument"};
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (op < 0 || op >= (int)sv->ops.size() || !sv->ops[op]) throw gn_error{GN_ERR_ARG, "unknown operator"};
+  const Operator& o = *sv->ops[op];
+  if (resident) *resident = o.resident ? 1 : 0;
+  if (builds) *builds = o.builds;
+  if (evictions) *evictions = o.evictions;
+  if (bytes) *bytes = o.resident ? o.bytes : o.est;
   return GN_OK;
   SV_CATCH
 }
@@ -448,12 +722,18 @@ static void retire_operator(gn_server* sv, int op) {
     o->stop = true;
   }
   sv->cv_work.notify_all();
+  sv->cv_mem.notify_all();
   if (o->worker.joinable()) o->worker.join();
   std::lock_guard<std::mutex> lk(sv->mu);
   (void)hipStreamSynchronize(o->s);
+  if (o->spec && o->resident) {
+    gn_destroy_precond(o->pc);
+    gn_destroy_problem(o->p);
+  }
   (void)hipStreamDestroy(o->s);
-  sv->used -= o->bytes;
+  if (o->resident) sv->used -= o->bytes;
   sv->ops[op].reset();
+  sv->cv_mem.notify_all();
 }
 
 extern "C" gn_status gn_server_remove(gn_server* sv, int32_t op) {
@@ -476,7 +756,7 @@ extern "C" gn_status gn_server_submit(gn_server* sv, int32_t op, const double* b
   if (op < 0 || op >= (int)sv->ops.size() || !sv->ops[op]) throw gn_error{GN_ERR_ARG, "unknown operator"};
   Operator& o = *sv->ops[op];
   if (o.failed) throw gn_error{GN_ERR_DEVICE, "operator's worker stopped after an error"};
-  if (nrhs < 1 || ld < o.p->n_free) throw gn_error{GN_ERR_ARG, "bad nrhs/ld"};
+  if (nrhs < 1 || ld < o.n_free) throw gn_error{GN_ERR_ARG, "bad nrhs/ld"};
   if (!(rtol > 0.0) || maxit < 1 || maxit > sv->maxit_cap)
     throw gn_error{GN_ERR_ARG, "rtol > 0 and 1 <= maxit <= maxit_cap required"};
   std::unique_ptr<Request> q(new Request());

@@ -1,11 +1,16 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle.
 
 Tolerances (FP64 path): assembled A x and b agree to 1e-12 of the row scale
-sum_j |A_ij x_j|; preconditioner applications to 1e-10 relative; GenEO
-eigenvalues to 1e-10 * max(|lambda|, 1e-3 * lambda_cut); solutions to 1e-8
-relative after both sides converge to 1e-12; iteration counts within
-max(1, 2%).  Mixed precision (FP32 local factors): solutions to 1e-7.
+sum_j |A_ij x_j|; preconditioner applications to 1e-10 relative, or three
+times the case's FP64 condition where that is larger (tests/oracle_runs.py,
+minv_gate: on the 3x2x2 laminate an eps-size perturbation of the element
+matrices alone moves the oracle's M^-1 r by about 1e-10); GenEO eigenvalues to
+1e-10 * max(|lambda|, 1e-3 * lambda_cut); solutions to 1e-8 relative after both
+sides converge to 1e-12; iteration counts within max(1, 2%).  Mixed precision
+(FP32 local factors): solutions to 1e-7.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -54,8 +59,11 @@ def precond(name, coarse=True, local_prec=64):
     if key not in _PCS:
         w = orc.workload(name)
         print(f"[gpu] setup {name} coarse={coarse} prec={local_prec}", flush=True)
+        # eigenpairs converged to the rounding level (eig_tol 1e-14; the default
+        # 1e-12 is the throughput setting, checked on c1 and the configurations),
+        # so that the comparison measures the implementation, not the stopping test
         _PCS[key] = _gp().Preconditioner.from_workload(problem(name), w, local_prec=local_prec,
-                                                       coarse=coarse)
+                                                       coarse=coarse, eig_tol=1e-14)
     return _PCS[key]
 
 
@@ -116,25 +124,7 @@ def test_one_level_apply_matches_oracle(name):
 
 
 def _check_eigenvalues(name, pc):
-    g = orc.geneo_run(name)
-    w = orc.workload(name)
-    g2 = orc.geneo_run_shift(name, 1e-1)
-    for j in range(w.n_sub):
-        lam, m = pc.eigenvalues(j)
-        lref = g.lam[j]
-        assert m == g.m[j], (j, m, g.m[j], lam[:m + 2], lref[:m + 2])
-        k = m + 1
-        # exact zeros (rigid-body / constant modes of floating subdomains) carry
-        # only rounding: both sides must put them below 1e-9 * lambda_{m+1}
-        zero = 1e-9 * abs(lref[m])
-        z = np.abs(lref[:k]) < zero
-        assert np.all(np.abs(lam[:k][z]) < zero), (j, lam[:k], lref[:k])
-        # every other eigenvalue agrees to 1e-10 relative, or to 20x the oracle's own
-        # change under a change of the (algorithmic) shift, whichever is larger
-        self_d = np.abs(g2.lam[j][:k] - lref[:k])
-        tol = np.maximum(1e-10 * np.abs(lref[:k]), 20 * self_d)
-        err = np.abs(lam[:k] - lref[:k])
-        assert np.all(err[~z] <= tol[~z]), (j, lam[:k], lref[:k], err, tol)
+    orc.check_eigenvalues(orc.workload(name), orc.geneo_run(name), pc.eigenvalues)
 
 
 @pytest.mark.parametrize("name", ALL)
@@ -150,7 +140,7 @@ def test_geneo_block_widths(name, block):
     solves take their other workgroup shapes and must give the same pairs."""
     w = orc.workload(name)
     print(f"[gpu] setup {name} eig_block={block}", flush=True)
-    pc = _gp().Preconditioner.from_workload(problem(name), w, eig_block=block)
+    pc = _gp().Preconditioner.from_workload(problem(name), w, eig_block=block, eig_tol=1e-14)
     try:
         _check_eigenvalues(name, pc)
     finally:
@@ -166,14 +156,11 @@ def test_two_level_apply_matches_oracle(name):
     z = torch.zeros((1, pc.prob.n_free), dtype=torch.float64, device=DEV)
     pc.apply(_t(r[None, :]), z)
     ref = g.apply(r)
-    # the coarse space is defined up to rounding of the eigenvectors: the oracle's
-    # own M^-1 r moves by delta_self when its shift changes (1e-2 -> 1e-1); the
-    # gate is 1e-10 or 20 x that self-consistency, whichever is larger
-    g2 = orc.geneo_run_shift(name, 1e-1)
-    delta_self = np.linalg.norm(g2.apply(r) - ref) / np.linalg.norm(ref)
     err = np.linalg.norm(z[0].cpu().numpy() - ref) / np.linalg.norm(ref)
-    print(f"[gpu] {name} M^-1 r rel err {err:.2e} (oracle self {delta_self:.2e})")
-    assert err <= max(1e-10, 20 * delta_self)
+    tol = orc.minv_gate(name, seed=3)
+    print(f"[gpu] {name} M^-1 r rel err {err:.2e} (gate {tol:.1e}, FP64 condition "
+          f"{orc.minv_eps_sensitivity(name, True, 3):.1e})", flush=True)
+    assert err <= tol
 
 
 @pytest.mark.parametrize("name", ALL)
@@ -243,18 +230,17 @@ def test_matrix_core_local_kernel_single_column(name, local_prec):
     A, b, free, Ke = orc.system(name)
     g = orc.geneo_run(name)
     w = orc.workload(name)
-    pc = _gp().Preconditioner.from_workload(problem(name), w, local_prec=local_prec, local_kernel=1)
+    pc = _gp().Preconditioner.from_workload(problem(name), w, local_prec=local_prec, local_kernel=1,
+                                            eig_tol=1e-14)
     rng = np.random.default_rng(6)
     r = rng.standard_normal(pc.prob.n_free)
     z = torch.zeros((1, pc.prob.n_free), dtype=torch.float64, device=DEV)
     pc.apply(_t(r[None, :]), z)
     ref = g.apply(r)
     err = np.linalg.norm(z[0].cpu().numpy() - ref) / np.linalg.norm(ref)
-    g2 = orc.geneo_run_shift(name, 1e-1)
-    delta_self = np.linalg.norm(g2.apply(r) - ref) / np.linalg.norm(ref)
     print(f"[gpu] {name} matrix-core local kernel, prec {local_prec}: M^-1 r rel err {err:.2e}")
     # FP32 factors: M^-1 itself changes at the FP32 level; the solve below is the gate
-    assert err <= (max(1e-10, 20 * delta_self) if local_prec == 64 else 1e-3), err
+    assert err <= (orc.minv_gate(name, seed=6) if local_prec == 64 else 1e-3), err
     u_ref = np.linalg.solve(A.toarray(), b[:, 0])
     bt = _t(b[:, 0][None, :])
     x = torch.zeros_like(bt)
@@ -293,6 +279,41 @@ def test_repeatable_bitwise():
     assert torch.equal(x1, x2)
 
 
+SMOOTH = ["diff_2x2x2|pou=sarkis", "lam_3x2x2_uneven|overlap=2,pou=sarkis"]
+
+
+@pytest.mark.parametrize("name", SMOOTH)
+def test_smooth_partition_of_unity_matches_oracle(name):
+    """The smooth (Sarkis) partition of unity (Section 3.2, Section 3.3.1) on
+    overlap-2 decompositions, where it differs from the standard one: GenEO
+    eigenvalues and counts (its pencil B = X A_O X and basis X p depend on X),
+    two-level M^-1 r, and the PCG solution and iteration count."""
+    w = orc.workload(name)
+    g = orc.geneo_run(name)
+    assert w.pou == "sarkis" and w.overlap == 2
+    print(f"[gpu] setup {name}", flush=True)
+    pc = _gp().Preconditioner.from_workload(problem(name.partition("|")[0]), w, eig_tol=1e-14)
+    try:
+        orc.check_eigenvalues(w, g, pc.eigenvalues)
+        r = np.random.default_rng(3).standard_normal(w.n_free)
+        z = torch.zeros((1, w.n_free), dtype=torch.float64, device=DEV)
+        pc.apply(_t(r[None, :]), z)
+        ref = g.apply(r)
+        err = np.linalg.norm(z[0].cpu().numpy() - ref) / np.linalg.norm(ref)
+        tol = orc.minv_gate(name, seed=3)
+        print(f"[gpu] {name} M^-1 r rel err {err:.2e} (gate {tol:.1e})", flush=True)
+        assert err <= tol
+        A, b, free, Ke = orc.system(name)
+        u_ref, info = opcg.pcg(A, b[:, 0], g.apply, rtol=1e-12, maxit=2000)
+        bt = _t(b[:, 0][None, :])
+        x = torch.zeros_like(bt)
+        st, rep = _gp().solve(pc.prob, pc, bt, x, rtol=1e-12, maxit=2000)
+        assert np.linalg.norm(x[0].cpu().numpy() - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
+        assert abs(rep[0]["iters_first"] - info["iters"]) <= max(1, int(0.02 * info["iters"]))
+    finally:
+        pc.close()
+
+
 def test_error_paths():
     gp = _gp()
     w = orc.workload("lam_2x2")
@@ -308,6 +329,34 @@ def test_error_paths():
     x = torch.zeros_like(b)
     st, rep = gp.solve(p, None, b, x, rtol=1e-12, maxit=1)
     assert st == 1 and rep[0]["iters"] == 1 and rep[0]["converged"] == 0
+    # a NaN or an infinity in the right-hand side is refused before any iteration
+    for bad_value in (float("nan"), float("inf")):
+        bad = b.clone()
+        bad[0, 5] = bad_value
+        with pytest.raises(gp.GenPCGError) as e:
+            gp.solve(p, None, bad, x, rtol=1e-8, maxit=10)
+        assert e.value.code == -1 and "NaN" in str(e.value)
+    # an eigensolver held to one Rayleigh-Ritz step does not converge
+    with pytest.raises(gp.GenPCGError) as e:
+        gp.Preconditioner.from_workload(p, w, eig_maxit=1)
+    assert e.value.code == -4
+
+
+def test_indefinite_material_is_not_spd():
+    """A Poisson ratio above 1/2 makes the isotropic stiffness indefinite: the
+    local Cholesky factorisations meet a non-positive pivot (GN_ERR_NOT_SPD)
+    and set-up fails without a handle; every kernel still exits normally."""
+    gp = _gp()
+    w = gen.small_case("laminate", seed=21, nxy=(8, 6), n_ply=2, nparts=(2, 2, 1), nev=6)
+    bad = w.mats.copy()
+    bad[:] = gen.iso_consts(10000.0, 0.7)
+    prob = gp.Problem.from_workload(dataclasses.replace(w, mats=bad))
+    try:
+        with pytest.raises(gp.GenPCGError) as e:
+            gp.Preconditioner.from_workload(prob, w)
+        assert e.value.code == -3
+    finally:
+        prob.close()
 
 
 @pytest.mark.parametrize("name", ["lam_3x2x2_uneven", "diff_3x3x1"])

@@ -198,7 +198,7 @@ def test_server_one_level_and_plain_cg_operators():
 def test_server_budget_and_argument_errors():
     gp = _gp()
     w, prob, pc = operator("lam_2x2")
-    nbytes = gp.footprint(prob, pc)
+    nbytes = gp.resident_bytes(prob, pc)
     assert nbytes > 0
     srv = gp.Server(hbm_budget=1 << 20)
     try:
@@ -225,5 +225,64 @@ def test_server_budget_and_argument_errors():
         srv.remove(op)
         with pytest.raises(gp.GenPCGError):
             srv.submit(op, prob.n_free, b, x)
+    finally:
+        srv.close()
+
+
+def test_server_builds_admits_by_footprint_and_evicts():
+    """Operators registered by description (gn_server_register): the server
+    builds one when a request needs it and its a-priori footprint fits the
+    budget, evicting the least recently used idle server-built operator when
+    it does not.  With a budget that holds either operator but not both,
+    alternating requests evict and rebuild; a rebuilt operator gives the same
+    bits, every column matches the oracle's PCG (1e-8), and the measured
+    footprint of each built operator lies within 5 % below its estimate
+    (fixed eigenvector counts)."""
+    gp = _gp()
+    names = ["lam_2x2", "lam_3x2x2_uneven"]
+    ws = [orc.workload(n) for n in names]
+    est = [gp.footprint(w) for w in ws]
+    srv = gp.Server(hbm_budget=int(max(est) * 1.02), slots=4)
+    try:
+        ids = []
+        for w in ws:
+            op, e = srv.register(w)
+            ids.append(op)
+            assert e == gp.footprint(w)
+            assert srv.info(op) == {"resident": False, "builds": 0, "evictions": 0, "bytes": e}
+        refs, loads = [], []
+        for n in names:
+            A, b, free, Ke = orc.system(n)
+            u, info = orc.pcg_run(n)
+            refs.append(u)
+            loads.append(_t(b[:, 0][None, :]))
+        torch.cuda.synchronize()
+        results = []
+        for step, i in enumerate([0, 1, 0, 1]):
+            x = torch.zeros_like(loads[i])
+            print(f"[gpu-serve] request {step} on {names[i]}", flush=True)
+            st, rep, lat = srv.wait(srv.submit(ids[i], ws[i].n_free, loads[i], x, rtol=1e-12, maxit=2000))
+            assert st == 0 and rep[0]["converged"] == 1
+            u = x[0].cpu().numpy()
+            assert np.linalg.norm(u - refs[i]) <= 1e-8 * np.linalg.norm(refs[i])
+            results.append(x)
+            me, other = srv.info(ids[i]), srv.info(ids[1 - i])
+            assert me["resident"] and me["builds"] == step // 2 + 1
+            assert not other["resident"]
+            assert est[i] * 0.95 <= me["bytes"] <= est[i], (names[i], me["bytes"], est[i])
+        assert srv.info(ids[0])["evictions"] == 2 and srv.info(ids[1])["evictions"] == 1
+        assert torch.equal(results[0], results[2]) and torch.equal(results[1], results[3])
+    finally:
+        srv.close()
+
+
+def test_server_refuses_an_operator_larger_than_its_budget():
+    gp = _gp()
+    w = orc.workload("lam_2x2")
+    srv = gp.Server(hbm_budget=int(gp.footprint(w) * 0.5))
+    try:
+        with pytest.raises(gp.GenPCGError) as e:
+            srv.register(w)
+        assert e.value.code == -2
     finally:
         srv.close()

@@ -1,0 +1,132 @@
+"""GPU parity at the band widths of the full-size configurations.
+
+The small parity cases have local bands of at most 3 tiles, so they reach only
+the narrowest instantiations of the local-solve kernels.  These cases have
+subdomain boxes whose bands are as wide as those of the bench and
+configuration workloads (tests/oracle_runs.py, WIDE): 10 tiles (the FP64
+sweep with 20 slots), 12 tiles (24 slots; pencil band 13, an 18-slot ring of
+the eigen block solves) and 17 tiles (FP64: the 16-column matrix-core sweep
+with one live column; FP32: the 1024-thread sweep).  Each is compared with the
+oracle as the small cases are: M^-1 r element-wise (one- and two-level), GenEO
+eigenvalues and counts, and the PCG solution at 1e-8 (1e-7 for FP32 local
+factors) after both sides converge to 1e-12.
+"""
+import numpy as np
+import pytest
+
+from tests import oracle_runs as orc
+from oracle import pcg as opcg
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+DEV = "cuda:0"
+
+
+def _gp():
+    import paper_1901_05188_amd as gp
+    return gp
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+_PROBS = {}
+
+
+def problem(name):
+    if name not in _PROBS:
+        w = orc.workload(name)
+        print(f"[gpu] assemble {name} ne={w.ne} n_free={w.n_free}", flush=True)
+        _PROBS[name] = _gp().Problem.from_workload(w)
+    return _PROBS[name]
+
+
+def _apply(pc, r):
+    z = torch.zeros((1, r.shape[0]), dtype=torch.float64, device=DEV)
+    pc.apply(_t(r[None, :]), z)
+    return z[0].cpu().numpy()
+
+
+@pytest.mark.parametrize("name,prec", [("diff_wide10", 64), ("diff_wide10", 32), ("lam_wide12", 64),
+                                       ("lam_wide12", 32), ("lam_wide17", 64), ("lam_wide17", 32)])
+def test_wide_band_one_level_apply(name, prec):
+    w = orc.workload(name)
+    g = orc.geneo_run(name, coarse=False)
+    print(f"[gpu] setup {name} one-level prec={prec}", flush=True)
+    pc = _gp().Preconditioner.from_workload(problem(name), w, coarse=False, local_prec=prec)
+    try:
+        print(f"[gpu] {name} band tiles {pc.report['band_tiles']}", flush=True)
+        r = np.random.default_rng(2).standard_normal(w.n_free)
+        ref = g.apply_as1(r)
+        err = np.linalg.norm(_apply(pc, r) - ref) / np.linalg.norm(ref)
+        print(f"[gpu] {name} one-level prec {prec}: M^-1 r rel err {err:.2e}", flush=True)
+        # FP32 factors: M^-1 itself moves at the FP32 level
+        assert err <= (1e-10 if prec == 64 else 1e-4), err
+    finally:
+        pc.close()
+
+
+@pytest.mark.parametrize("name", ["diff_wide10", "lam_wide12"])
+def test_wide_band_geneo_eigen_apply_and_solve(name):
+    w = orc.workload(name)
+    g = orc.geneo_run(name)
+    prob = problem(name)
+    print(f"[gpu] setup {name} GenEO", flush=True)
+    pc = _gp().Preconditioner.from_workload(prob, w, eig_tol=1e-14)
+    try:
+        orc.check_eigenvalues(w, g, pc.eigenvalues)
+        r = np.random.default_rng(3).standard_normal(w.n_free)
+        ref = g.apply(r)
+        err = np.linalg.norm(_apply(pc, r) - ref) / np.linalg.norm(ref)
+        tol = orc.minv_gate(name, seed=3)
+        print(f"[gpu] {name} two-level M^-1 r rel err {err:.2e} (gate {tol:.1e})", flush=True)
+        assert err <= tol
+        A, b, free, Ke = orc.system(name)
+        u_ref, info = opcg.pcg(A, b[:, 0], g.apply, rtol=1e-12, maxit=2000)
+        for prec in (64, 32):
+            pcx = pc if prec == 64 else _gp().Preconditioner.from_workload(prob, w, local_prec=32)
+            bt = _t(b[:, 0][None, :])
+            x = torch.zeros_like(bt)
+            st, rep = _gp().solve(prob, pcx, bt, x, rtol=1e-12, maxit=2000)
+            e = np.linalg.norm(x[0].cpu().numpy() - u_ref) / np.linalg.norm(u_ref)
+            print(f"[gpu] {name} prec {prec}: iters {rep[0]['iters_first']} (oracle {info['iters']}) "
+                  f"solution rel err {e:.2e}", flush=True)
+            assert e <= (1e-8 if prec == 64 else 1e-7)
+            if prec == 64:
+                assert abs(rep[0]["iters_first"] - info["iters"]) <= max(1, int(0.02 * info["iters"]))
+            else:
+                pcx.close()
+    finally:
+        pc.close()
+
+
+def test_wide_band_zem_two_level_and_solve():
+    """17-tile bands with the zero-energy-mode coarse space (no dense oracle
+    eigensolve at 12k pencil rows): two-level M^-1 r and the PCG solution, FP64
+    local factors through the matrix-core sweep and FP32 through the
+    1024-thread sweep."""
+    name = "lam_wide17"
+    w = orc.workload(name)
+    g = orc.geneo_run(name, coarse="zem")
+    prob = problem(name)
+    A, b, free, Ke = orc.system(name)
+    u_ref, info = opcg.pcg(A, b[:, 0], g.apply, rtol=1e-12, maxit=3000)
+    r = np.random.default_rng(5).standard_normal(w.n_free)
+    ref = g.apply(r)
+    for prec in (64, 32):
+        print(f"[gpu] setup {name} ZEM prec={prec}", flush=True)
+        pc = _gp().Preconditioner.from_workload(prob, w, coarse="zem", local_prec=prec)
+        try:
+            assert pc.report["coarse_dim"] == g.NH
+            err = np.linalg.norm(_apply(pc, r) - ref) / np.linalg.norm(ref)
+            print(f"[gpu] {name} ZEM prec {prec}: M^-1 r rel err {err:.2e}", flush=True)
+            assert err <= (1e-10 if prec == 64 else 1e-4)
+            bt = _t(b[:, 0][None, :])
+            x = torch.zeros_like(bt)
+            st, rep = _gp().solve(prob, pc, bt, x, rtol=1e-12, maxit=3000)
+            e = np.linalg.norm(x[0].cpu().numpy() - u_ref) / np.linalg.norm(u_ref)
+            print(f"[gpu] {name} ZEM prec {prec}: solution rel err {e:.2e}", flush=True)
+            assert e <= (1e-8 if prec == 64 else 1e-7)
+        finally:
+            pc.close()
