@@ -180,12 +180,61 @@ def measured_traffic(workload, prec):
         return None
 
 
+def _run_stream(srv, ids, n_free, reqs, loads, rtol):
+    """Submit requests at their arrival times; wait for all.  Returns per-request
+    latencies, the columns' reports and the wall time."""
+    tickets = []
+    tstart = time.perf_counter()
+    for i, r in enumerate(reqs):
+        dt = tstart + r["t"] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        b, x = loads[i]
+        x.zero_()
+        tickets.append(srv.submit(ids[r["op"]], n_free[r["op"]], b, x, rtol=rtol, maxit=5000))
+    lat, reps, sts = [], [], []
+    for t in tickets:
+        st, rep, l = srv.wait(t)
+        lat.append(l)
+        reps.append(rep)
+        sts.append(st)
+    return lat, reps, sts, time.perf_counter() - tstart
+
+
+def _stream_summary(reqs, lat, reps, sts, wall, n_free, rtol, rate):
+    import numpy as np
+    lat_s = sorted(lat)
+    q = lambda f: lat_s[min(len(lat_s) - 1, int(round(f * (len(lat_s) - 1))))]
+    cols = [c for rep in reps for c in rep]
+    dofcols = sum(len(rep) * n_free[r["op"]] for r, rep in zip(reqs, reps))
+    at_rtol = sum(1 for c in cols if c["true_rel_res"] <= rtol)
+    at_floor = sum(1 for c in cols if c["true_rel_res"] > rtol and c["true_rel_res"] <= 4 * c["res_floor"])
+    return {"requests": len(reqs), "columns": len(cols), "arrival_rate_per_s": rate,
+            "arrival_span_s": reqs[-1]["t"], "wall_s": wall, "requests_per_s": len(reqs) / wall,
+            "dof_rhs_per_s": dofcols / wall,
+            "latency_ms": {"p50": 1000 * q(0.5), "p99": 1000 * q(0.99)},
+            "pcg_iters": {"mean": float(np.mean([c["iters"] for c in cols])),
+                          "max": int(max(c["iters"] for c in cols))},
+            "all_converged": all(st == 0 for st in sts) and all(c["converged"] == 1 for c in cols),
+            "max_true_rel_res": max(c["true_rel_res"] for c in cols),
+            # true residual b - A x at rtol, or (the rest) at the FP64 rounding floor of x
+            "columns_true_res_at_rtol": at_rtol, "columns_true_res_at_fp64_floor": at_floor,
+            "columns_neither": len(cols) - at_rtol - at_floor}
+
+
 def serving_leg(gp, n_req, rate, rtol, dev):
-    """Serving stream: the 16-operator laminate catalogue (4 sizes 0.2-2M DOFs x
-    4 random layups, FP32 local factors inside FP64 PCG) resident on the GPU,
-    the first n_req requests of the Poisson stream (1-16 patch-traction load
-    cases each) submitted at their arrival times to the request server;
-    latency is submit to completion of the request's last column."""
+    """Serving: the 16-operator laminate catalogue (4 sizes 0.2-2M DOFs x 4
+    random layups, FP32 local factors inside FP64 PCG), requests of 1-16
+    patch-traction load cases from the Poisson stream, submitted at their
+    arrival times; latency is submit to completion of the request's last
+    column.  Three streams:
+      overloaded   the catalogue resident, the first n_req requests at `rate`
+                   (above what one GPU completes: the queue grows);
+      sustainable  the same operators, requests at a rate the server keeps up
+                   with (latency = service time plus little queueing);
+      budgeted     the catalogue registered by description on a server whose
+                   HBM budget holds about half of it: operators are built when
+                   requested and their footprint fits, idle ones evicted (LRU)."""
     import numpy as np
     import torch
     from workloads import generate as gen
@@ -200,7 +249,12 @@ def serving_leg(gp, n_req, rate, rtol, dev):
     t_build = time.perf_counter() - t0
     srv = gp.Server(maxit_cap=5000)
     ids = [srv.add(p, pc) for (_, p, pc) in ops]
+    n_free = [p.n_free for (_, p, _) in ops]
     resident = sum(gp.resident_bytes(p, pc) for (_, p, pc) in ops)
+    est = [gp.footprint(w, local_prec=32) for (w, _, _) in ops]
+    # measured footprint of each operator (with the server's batched workspace)
+    # against the a-priori estimate
+    meas = [srv.info(i)["bytes"] for i in ids]
     log(f"serving: catalogue of {len(ops)} operators built in {t_build:.1f}s, {resident / 1e9:.1f} GB resident")
     reqs = gen.c4_requests(len(ops), n_req=n_req, rate=rate)
     loads = []
@@ -210,59 +264,61 @@ def serving_leg(gp, n_req, rate, rtol, dev):
         p.load_vectors(b, traction=gen.patch_tractions(w, r["k"], np.random.default_rng(r["seed"])))
         loads.append((b, torch.zeros_like(b)))
     torch.cuda.synchronize()
-    tickets = []
-    tstart = time.perf_counter()
-    for i, r in enumerate(reqs):
-        dt = tstart + r["t"] - time.perf_counter()
-        if dt > 0:
-            time.sleep(dt)
-        b, x = loads[i]
-        tickets.append(srv.submit(ids[r["op"]], ops[r["op"]][1].n_free, b, x, rtol=rtol, maxit=5000))
-    lat, iters, worst, conv, dofcols, at_target = [], [], 0.0, True, 0, True
-    for i, t in enumerate(tickets):
-        st, rep, l = srv.wait(t)
-        lat.append(l)
-        iters += [c["iters"] for c in rep]
-        worst = max(worst, max(c["true_rel_res"] for c in rep))
-        conv &= st == 0 and all(c["converged"] == 1 for c in rep)
-        # the true residual meets rtol, or sits at the FP64 rounding floor of its x
-        at_target &= all(c["true_rel_res"] <= max(rtol, 4 * c["res_floor"]) for c in rep)
-        dofcols += len(rep) * ops[reqs[i]["op"]][1].n_free
-    wall = time.perf_counter() - tstart
+    lat, reps, sts, wall = _run_stream(srv, ids, n_free, reqs, loads, rtol)
+    over = _stream_summary(reqs, lat, reps, sts, wall, n_free, rtol, rate)
     # one request again, alone on an idle server: the same bits as in the mix
     i0 = max(range(len(reqs)), key=lambda i: reqs[i]["k"])
     b0, x0 = loads[i0]
+    x_mix = x0.clone()
     xa = torch.zeros_like(x0)
     torch.cuda.synchronize()
-    srv.wait(srv.submit(ids[reqs[i0]["op"]], ops[reqs[i0]["op"]][1].n_free, b0, xa, rtol=rtol, maxit=5000))
-    same = bool(torch.equal(xa, x0))
+    srv.wait(srv.submit(ids[reqs[i0]["op"]], n_free[reqs[i0]["op"]], b0, xa, rtol=rtol, maxit=5000))
+    same = bool(torch.equal(xa, x_mix))
+    # a rate the server sustains: about 60 % of the overloaded stream's throughput
+    rate2 = round(0.6 * over["requests_per_s"], 2)
+    n2 = min(len(reqs), 40)
+    reqs2 = [dict(r, t=i / rate2) for i, r in enumerate(reqs[:n2])]
+    lat2, reps2, sts2, wall2 = _run_stream(srv, ids, n_free, reqs2, loads[:n2], rtol)
+    sustain = _stream_summary(reqs2, lat2, reps2, sts2, wall2, n_free, rtol, rate2)
+    sustain["arrivals"] = "evenly spaced, the first requests of the stream"
     srv.close()
     # its error against FP64 local factors on the same operator
     w, p, _ = ops[reqs[i0]["op"]]
     pc64 = gp.Preconditioner.from_workload(p, w, local_prec=64)
-    x64 = torch.zeros_like(x0)
+    x64 = torch.zeros_like(x_mix)
     gp.solve(p, pc64, b0, x64, rtol=rtol, maxit=5000)
-    err64 = float(torch.max(torch.linalg.norm(x0 - x64, dim=1) / torch.linalg.norm(x64, dim=1)))
+    err64 = float(torch.max(torch.linalg.norm(x_mix - x64, dim=1) / torch.linalg.norm(x64, dim=1)))
     pc64.close()
     for (_, p, pc) in ops:
         pc.close()
         p.close()
-    lat_s = sorted(lat)
-    q = lambda f: lat_s[min(len(lat_s) - 1, int(round(f * (len(lat_s) - 1))))]
+    # budgeted: operators registered by description, built on demand
+    budget = int(0.5 * sum(est))
+    srv = gp.Server(maxit_cap=5000, hbm_budget=budget)
+    ids_b = [srv.register(w, local_prec=32)[0] for w in cat]
+    n3 = min(len(reqs), 30)
+    rate3 = rate2
+    reqs3 = [dict(r, t=i / rate3) for i, r in enumerate(reqs[:n3])]
+    lat3, reps3, sts3, wall3 = _run_stream(srv, ids_b, n_free, reqs3, loads[:n3], rtol)
+    budgeted = _stream_summary(reqs3, lat3, reps3, sts3, wall3, n_free, rtol, rate3)
+    infos = [srv.info(i) for i in ids_b]
+    budgeted.update({"hbm_budget_GB": budget / 1e9, "catalogue_estimate_GB": sum(est) / 1e9,
+                     "builds": sum(i["builds"] for i in infos), "evictions": sum(i["evictions"] for i in infos),
+                     "resident_at_end": sum(1 for i in infos if i["resident"])})
+    srv.close()
+    del loads
     out = {"workload": "laminate catalogue 16 operators (0.2/0.5/1/2 M DOFs x 4 layups), FP32 local factors, "
                        "Poisson arrivals, 1-16 patch tractions per request",
-           "requests": len(reqs), "columns": len(iters), "arrival_rate_per_s": rate,
-           "arrival_span_s": reqs[-1]["t"], "wall_s": wall,
-           "requests_per_s": len(reqs) / wall, "dof_rhs_per_s": dofcols / wall,
-           "latency_ms": {"p50": 1000 * q(0.5), "p99": 1000 * q(0.99)},
-           "pcg_iters": {"mean": float(np.mean(iters)), "max": int(max(iters))},
-           "all_converged": bool(conv), "max_true_rel_res": worst,
-           "all_true_res_at_rtol_or_fp64_floor": bool(at_target),
+           "overloaded": over, "sustainable": sustain, "budgeted": budgeted,
            "alone_equals_mix_bitwise": same, "rel_err_vs_fp64_local": err64,
-           "catalogue_build_s": t_build, "resident_GB": resident / 1e9}
-    log(f"serving: {len(reqs)} requests ({len(iters)} columns) in {wall:.1f}s, p50 {out['latency_ms']['p50']:.0f} ms "
-        f"p99 {out['latency_ms']['p99']:.0f} ms, {out['dof_rhs_per_s']:.3e} DOF-RHS/s, alone==mix {same}, "
-        f"err vs FP64 {err64:.1e}")
+           "catalogue_build_s": t_build, "resident_GB": resident / 1e9,
+           "footprint_estimate_over_measured": {"min": min(e / m for e, m in zip(est, meas)),
+                                                "max": max(e / m for e, m in zip(est, meas))}}
+    log(f"serving: overloaded {over['requests']} req at {rate}/s: {over['requests_per_s']:.2f} req/s, p50 "
+        f"{over['latency_ms']['p50']:.0f} ms p99 {over['latency_ms']['p99']:.0f} ms; sustainable at {rate2}/s: p50 "
+        f"{sustain['latency_ms']['p50']:.0f} ms p99 {sustain['latency_ms']['p99']:.0f} ms; budgeted "
+        f"{budget / 1e9:.0f} GB: {budgeted['builds']} builds, {budgeted['evictions']} evictions, p50 "
+        f"{budgeted['latency_ms']['p50']:.0f} ms; alone==mix {same}; err vs FP64 {err64:.1e}")
     return out
 
 

@@ -153,9 +153,12 @@ gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t n
  * eig_filter is the largest Chebyshev filter degree per Rayleigh-Ritz step
  * (0 = 4; 1 = plain subspace iteration); the degree ramps up 1, 2, ... from the
  * first step.
- * local_kernel selects the kernel of single-column local solves: 0 = automatic
- * (the register-pipelined sweep when the band fits it), 1 = always the
- * 16-column matrix-core kernel of the batched solves.
+ * local_kernel selects the kernel of single-column local solves: 0 = the
+ * register-pipelined sweep when the band fits it, its launch shape (512 or 1024
+ * threads per subdomain) timed at set-up when both fit and the choice kept for
+ * later preconditioners of the same band shape in the process; 1 = always the
+ * 16-column matrix-core kernel of the batched solves; 2 = the sweep with the
+ * first shape that fits, untimed.
  * pou selects the partition of unity X_j (Section 3.2, def:pou; Section 3.3.1):
  * 0 = the standard one (one over the number of subdomains whose V_h0 holds the
  * DOF, zero on the subdomain boundary); 1 = the smoother one of Sarkis that the
@@ -241,6 +244,14 @@ typedef struct gn_solve_opts {
                            problem for plain CG, until destroyed); 0 = kernel
                            by kernel.  Same arithmetic either way.  Not used
                            while kernel profiling (gn_profile_enable) is on.    */
+  int32_t flexible;     /* 1 = flexible CG: beta = z_{k+1}^T (r_{k+1} - r_k) /
+                           z_k^T r_k (Polak-Ribiere), which keeps CG converging
+                           when the preconditioner changes between applications,
+                           as with the inexact coarse solve of Section 3.3.3
+                           (gn_dd_opts.coarse_solve = 1), where the paper
+                           switches to a flexible Krylov method; equal to the
+                           standard beta for a fixed preconditioner.  Columns
+                           are then solved one after another.                   */
 } gn_solve_opts;
 
 typedef struct gn_solve_report {

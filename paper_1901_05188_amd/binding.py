@@ -70,7 +70,7 @@ class gn_setup_report(C.Structure):
 
 class gn_solve_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32),
-                ("sequential", C.c_int32), ("graphs", C.c_int32)]
+                ("sequential", C.c_int32), ("graphs", C.c_int32), ("flexible", C.c_int32)]
 
 
 class gn_server_opts(C.Structure):
@@ -349,7 +349,7 @@ class Preconditioner:
 
 
 def solve(prob: Problem, pc: Optional[Preconditioner], b, x, rtol=1e-8, maxit=1000, check_every=8,
-          stream=None, sequential=False, graphs=True):
+          stream=None, sequential=False, graphs=True, flexible=False):
     """PCG (x0 = 0) on (nrhs, n_free) float64 CUDA tensors; returns (status, reports).
 
     Several right-hand sides are solved in batches of up to 16 columns that
@@ -357,7 +357,8 @@ def solve(prob: Problem, pc: Optional[Preconditioner], b, x, rtol=1e-8, maxit=10
     of check_every iterations of a single-column solve from a captured HIP graph."""
     nrhs = 1 if b.dim() == 1 else b.shape[0]
     assert b.shape == x.shape and b.shape[-1] == prob.n_free and b.is_contiguous() and x.is_contiguous()
-    o = gn_solve_opts(float(rtol), int(maxit), int(check_every), int(bool(sequential)), int(bool(graphs)))
+    o = gn_solve_opts(float(rtol), int(maxit), int(check_every), int(bool(sequential)), int(bool(graphs)),
+                      int(bool(flexible)))
     reps = (gn_solve_report * nrhs)()
     st = _check(lib().gn_solve(prob.handle, pc.handle if pc is not None else None, _tensor_ptr(b),
                                _tensor_ptr(x), nrhs, prob.n_free, C.byref(o), _stream(stream), reps))

@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgenpcg.so")
-SOURCES = ["fem.hip", "linalg.hip", "band.hip", "precond.hip", "geneo.hip", "multi.hip", "api.hip", "serve.hip"]
+SOURCES = ["fem.hip", "linalg.hip", "band.hip", "precond.hip", "geneo.hip", "coarse.hip", "multi.hip", "api.hip",
+           "serve.hip"]
 ARCH = os.environ.get("GENPCG_ARCH", "gfx950")
 
 

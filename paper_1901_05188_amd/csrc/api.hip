@@ -57,7 +57,8 @@ static void argfail(const std::string& m) { throw gn_error{GN_ERR_ARG, m}; }
 namespace {
 std::mutex g_pool_mu;
 std::multimap<size_t, void*> g_pool_free;   // rounded size -> idle block
-std::map<void*, size_t> g_pool_size;        // every live or idle block -> rounded size
+std::map<void*, size_t> g_pool_size;        // every live or idle block -> its size
+std::map<void*, size_t> g_pool_used;        // live blocks -> the rounded size asked for
 size_t g_pool_cached = 0;
 double g_pool_alloc_s = 0.0;                // seconds spent in hipMalloc/hipFree
 
@@ -89,6 +90,7 @@ void* gnh::dev_alloc(size_t bytes) {
     void* p = it->second;
     g_pool_cached -= it->first;
     g_pool_free.erase(it);
+    g_pool_used[p] = sz;
     return p;
   }
   void* p = nullptr;
@@ -106,6 +108,7 @@ void* gnh::dev_alloc(size_t bytes) {
                    "device allocation of " + std::to_string(sz) + " bytes: " + hipGetErrorString(e)};
   }
   g_pool_size[p] = sz;
+  g_pool_used[p] = sz;
   return p;
 }
 
@@ -114,14 +117,17 @@ void gnh::dev_free(void* p) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
   auto it = g_pool_size.find(p);
   if (it == g_pool_size.end()) return;
+  g_pool_used.erase(p);
   g_pool_free.emplace(it->second, p);
   g_pool_cached += it->second;
 }
 
+// the rounded size a live block was asked for (a reused idle block may be up
+// to 1/8 larger; that slack is the pool's, not the handle's)
 int64_t gnh::dev_size(const void* p) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
-  auto it = g_pool_size.find(const_cast<void*>(p));
-  return it == g_pool_size.end() ? 0 : (int64_t)it->second;
+  auto it = g_pool_used.find(const_cast<void*>(p));
+  return it == g_pool_used.end() ? 0 : (int64_t)it->second;
 }
 
 double gnh::dev_alloc_seconds() {
@@ -688,7 +694,32 @@ static int64_t estimate_footprint(const int ne[3], int nc, const gn_dd_opts* o, 
   const int64_t NBH = (NH + TILE - 1) / TILE;
   if (NH > 0) {
     add(phi * 8);
-    add(NBH * NBH * TILE2 * 8);
+    if (o->coarse_solve == 1) {
+      // block-sparse A_H over the interacting subdomain pairs, inverted diagonal
+      // blocks, inner CG vectors and partial sums
+      const int m = (int)(NH / n_sub);
+      int64_t blocks = 0;
+      for (int j1 = 0; j1 < n_sub; ++j1)
+        for (int j2 = 0; j2 < n_sub; ++j2) {
+          bool hit12 = true, hit21 = true;
+          for (int a = 0; a < 3; ++a) {
+            const SubDesc &s1 = pl.sub[j1], &s2 = pl.sub[j2];
+            hit12 &= std::min(s1.ilo[a] + s1.in_[a], s2.blo[a] + s2.bn[a]) > std::max(s1.ilo[a], s2.blo[a]);
+            hit21 &= std::min(s2.ilo[a] + s2.in_[a], s1.blo[a] + s1.bn[a]) > std::max(s2.ilo[a], s1.blo[a]);
+          }
+          blocks += (hit12 || hit21) ? 1 : 0;
+        }
+      add((int64_t)(n_sub + 1) * 4);
+      add(blocks * (int64_t)sizeof(BsrBlock));
+      add(blocks * m * m * 8);
+      add((int64_t)n_sub * 8);
+      add((int64_t)n_sub * m * m * 8);
+      add(5 * NBH * TILE * 8);
+      add(3 * 256 * 8);
+      add(4 * 8);
+    } else {
+      add(NBH * NBH * TILE2 * 8);
+    }
     for (int v = 0; v < 3; ++v) add(NBH * TILE * 8);
   }
   if (batched) {
@@ -745,7 +776,12 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   pc->local_prec = o->local_prec;
   if (o->pou < 0 || o->pou > 1) argfail("pou must be 0 (standard) or 1 (smooth)");
   pc->pou = o->pou;
-  if (o->local_kernel < 0 || o->local_kernel > 1) argfail("local_kernel must be 0 or 1");
+  if (o->coarse_solve < 0 || o->coarse_solve > 1) argfail("coarse_solve must be 0 (exact) or 1 (inexact CG)");
+  if (o->coarse_rtol < 0 || o->coarse_maxit < 0) argfail("coarse_rtol and coarse_maxit must not be negative");
+  pc->coarse_solve = o->coarse_solve;
+  pc->coarse_rtol = o->coarse_rtol > 0 ? o->coarse_rtol : 1e-4;
+  pc->coarse_maxit = o->coarse_maxit > 0 ? o->coarse_maxit : 200;
+  if (o->local_kernel < 0 || o->local_kernel > 2) argfail("local_kernel must be 0, 1 or 2");
   pc->local_kernel = o->local_kernel;
   for (int a = 0; a < 3; ++a) {
     pc->nparts[a] = o->nparts[a];
@@ -1106,6 +1142,32 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
         throw gn_error{GN_ERR_EIG_NOCONV, "GenEO eigensolver block of " + std::to_string(b) +
                                               " vectors too small for the eigenvalues below 1.5 x threshold "
                                               "(raise eig_block)"};
+      {
+        // Refinement in the original pencil.  The iteration applies
+        // T = P^-1 B through the banded factor, whose backward error, amplified
+        // by the condition of P, limits how well the Ritz vectors can match the
+        // pencil's eigenvectors.  One inverse-iteration step in defect form
+        // (V += P^-1 (B V - P V diag(nu)) diag(1/nu), with P V and B V from
+        // P = A_N + s B and B themselves) passes only the small defect through
+        // the solve; a last Rayleigh-Ritz step on span(V) then forms its Gram
+        // matrices V^T P V and V^T B V from the same exact products.
+        double* PE = dalloc<double>(tmp, (size_t)offVB * 27 * nc);
+        gnk::eig_extract_p(p, pc, maxNBB, shift, PE, s);
+        gnk::eig_bapply(p, pc, PE, b, maxNBB, V, Z, s);       // Z = P V
+        gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);      // BV = B V
+        gnk::eig_defect(pc, b, maxNBB, BV, Z, nu, BZ, s);     // BZ = B V - P V diag(nu)
+        gnk::eig_trsm(pc, b, LB, DB, TBB, BZ, Z, s);          // Z = P^-1 (defect)
+        ++eig_solves;
+        gnk::eig_defect_add(pc, b, maxNBB, Z, nu, 1e-12 / shift, V, s);
+        gnk::eig_bapply(p, pc, PE, b, maxNBB, V, Z, s);       // Z = P V
+        gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);      // BV = B V
+        gnk::eig_gram(pc, b, V, Z, BV, nullptr, nullptr, GP, GB, nullptr, s);
+        gnk::eig_small(n_sub, b, GP, GB, resp, res, Y, nu, nullptr, s);
+        gnk::eig_vupdate(pc, b, maxNBB, V, BV, Y, Z, BZ, s);  // Z = V Y, BZ = (B V) Y
+        std::swap(V, Z);
+        GN_HIP(hipMemcpyAsync(h_nu.data(), nu, sizeof(double) * h_nu.size(), hipMemcpyDeviceToHost, s));
+        GN_HIP(hipStreamSynchronize(s));
+      }
       break;
     }
     // V now holds the Ritz vectors of the last Rayleigh-Ritz step (h_nu).  Each
@@ -1167,6 +1229,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
       gnk::build_phi(p, pc, b, maxNI, V, s);
       gnk::aphi(p, pc, b, maxNB_, Z, s);
       // pairs (j1, j2) with I_j1 cap Ibar_j2 nonempty
+      std::vector<std::pair<int, int>> pair_list;
       std::vector<char> pbuf;
       int np = 0;
       const int psz = gnk::pair_size();
@@ -1184,6 +1247,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
           if (!ok) continue;
           pbuf.resize((size_t)(np + 1) * psz);
           gnk::make_pair(pbuf.data() + (size_t)np * psz, j1, j2, lo, hi);
+          pair_list.emplace_back(j1, j2);
           ++np;
         }
       char* d_pairs = upload(tmp, pbuf.data(), pbuf.size(), s);
@@ -1193,14 +1257,59 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
       double* DH = dalloc<double>(tmp, (size_t)pc->NBH * TILE2);
       GN_HIP(hipMemsetAsync(AH, 0, sizeof(double) * ahlen, s));
       gnk::ah_pairs(p, pc, d_pairs, np, b, Z, AH, s);
-      GN_HIP(hipMemsetAsync(d_info + n_sub, 0, sizeof(int), s));
-      gnk::dense_chol(pc->NBH, AH, DH, d_info + n_sub, s);
-      int hinfo = 0;
-      GN_HIP(hipMemcpyAsync(&hinfo, d_info + n_sub, sizeof(int), hipMemcpyDeviceToHost, s));
-      GN_HIP(hipStreamSynchronize(s));
-      if (hinfo) throw gn_error{GN_ERR_COARSE_SINGULAR, "coarse matrix not positive definite"};
-      pc->d_Z = dalloc<double>(pc->owned, ahlen);
-      gnk::tri_inv(pc->NBH, AH, DH, pc->d_Z, s);
+      if (pc->coarse_solve == 0) {
+        GN_HIP(hipMemsetAsync(d_info + n_sub, 0, sizeof(int), s));
+        gnk::dense_chol(pc->NBH, AH, DH, d_info + n_sub, s);
+        int hinfo = 0;
+        GN_HIP(hipMemcpyAsync(&hinfo, d_info + n_sub, sizeof(int), hipMemcpyDeviceToHost, s));
+        GN_HIP(hipStreamSynchronize(s));
+        if (hinfo) throw gn_error{GN_ERR_COARSE_SINGULAR, "coarse matrix not positive definite"};
+        pc->d_Z = dalloc<double>(pc->owned, ahlen);
+        gnk::tri_inv(pc->NBH, AH, DH, pc->d_Z, s);
+      } else {
+        // inexact coarse solve: A_H kept block-sparse (the symmetric closure of
+        // the interacting pairs), the diagonal blocks inverted
+        if (maxm > 64) argfail("inexact coarse solve needs at most 64 vectors per subdomain");
+        std::vector<std::vector<int>> nbr(n_sub);
+        for (const auto& pr : pair_list) {
+          nbr[pr.first].push_back(pr.second);
+          nbr[pr.second].push_back(pr.first);
+        }
+        std::vector<int> ptr(n_sub + 1, 0);
+        std::vector<BsrBlock> blk;
+        std::vector<int64_t> doff(n_sub, 0);
+        int64_t off = 0, dsz = 0;
+        for (int j = 0; j < n_sub; ++j) {
+          std::sort(nbr[j].begin(), nbr[j].end());
+          nbr[j].erase(std::unique(nbr[j].begin(), nbr[j].end()), nbr[j].end());
+          for (int j2 : nbr[j]) {
+            blk.push_back(BsrBlock{j, j2, off});
+            off += (int64_t)pc->sub[j].m * pc->sub[j2].m;
+          }
+          ptr[j + 1] = (int)blk.size();
+          doff[j] = dsz;
+          dsz += (int64_t)pc->sub[j].m * pc->sub[j].m;
+        }
+        pc->bsr_nnz = (int64_t)blk.size();
+        pc->d_bsr_ptr = upload(pc->owned, ptr.data(), ptr.size(), s);
+        pc->d_bsr_blk = upload(pc->owned, blk.data(), std::max<size_t>(blk.size(), 1), s);
+        pc->d_bsr_val = dalloc<double>(pc->owned, (size_t)std::max<int64_t>(off, 1));
+        pc->d_dinv_off = upload(pc->owned, doff.data(), doff.size(), s);
+        pc->d_dinv = dalloc<double>(pc->owned, (size_t)std::max<int64_t>(dsz, 1));
+        gnk::bsr_from_dense(pc, AH, s);
+        GN_HIP(hipMemsetAsync(d_info, 0, sizeof(int) * n_sub, s));
+        gnk::block_inverse(pc, d_info, s);
+        GN_HIP(hipMemcpyAsync(info.data(), d_info, sizeof(int) * n_sub, hipMemcpyDeviceToHost, s));
+        GN_HIP(hipStreamSynchronize(s));
+        for (int j = 0; j < n_sub; ++j)
+          if (info[j]) throw gn_error{GN_ERR_COARSE_SINGULAR, "diagonal block of the coarse matrix not positive definite"};
+        pc->coarse_grid = gnk::coarse_cg_grid(pc);
+        pc->d_cvec = dalloc<double>(pc->owned, (size_t)5 * pc->NBH * TILE);
+        pc->d_cpart = dalloc<double>(pc->owned, (size_t)3 * pc->coarse_grid);
+        pc->d_cstat = dalloc<double>(pc->owned, 4);
+        GN_HIP(hipMemsetAsync(pc->d_cvec, 0, sizeof(double) * 5 * pc->NBH * TILE, s));
+        GN_HIP(hipMemsetAsync(pc->d_cstat, 0, sizeof(double) * 4, s));
+      }
       pc->d_g = dalloc<double>(pc->owned, (size_t)pc->NBH * TILE);
       pc->d_u = dalloc<double>(pc->owned, (size_t)pc->NBH * TILE);
       pc->d_y = dalloc<double>(pc->owned, (size_t)pc->NBH * TILE);
@@ -1213,6 +1322,8 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   } else {
     upload_descs(pc, s);
   }
+  // launch shape of the single-column local solves (timed when several fit)
+  gnk::local_solve_tune(p, pc, s);
   GN_HIP(hipStreamSynchronize(s));
   dfree_all(tmp);
   // algorithmic bytes of one preconditioner application (for the roofline report)
@@ -1306,7 +1417,8 @@ static void precond_full(gn_problem* p, gn_precond* pc, const double* r, double*
                          const double* done, hipStream_t s) {
   if (gnk::pf_supported(p, pc)) {
     gnk::local_solve(p, pc, r, done, s);
-    gnk::coarse_solve(pc, done, s);
+    if (pc->coarse_solve == 1) gnk::coarse_cg(pc, pc->d_g, pc->d_y, done, s);
+    else gnk::coarse_solve(pc, done, s);
     gnk::prolong(p, pc, r, z, part, done, s);
   } else {
     // bands too wide for the single-column register pipeline: the batched
@@ -1432,7 +1544,10 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
   double* scal = p->d_scal;
   const double* done = scal + S_DONE;
   gn_status ret = GN_OK;
-  if (nrhs > 1 && !opts->sequential) {
+  // flexible CG (a preconditioner that varies between applications: the
+  // inexact coarse solve) runs the columns one after another
+  const int flex = opts->flexible != 0 ? 1 : 0;
+  if (nrhs > 1 && !opts->sequential && !flex) {
     // up to 16 columns share every launch; a finished column's slot takes the
     // next column at the following chunk boundary
     const double tstart = now_s();
@@ -1489,7 +1604,13 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
         gnk::finalize(p->d_part, nbs, OP_ALPHA, scal, p->d_hist, opts->rtol, st);
         gnk::update_xr(n, p->d_x, p->d_r, p->d_p, p->d_q, scal, p->d_part, st);
         gnk::finalize(p->d_part, nbr, OP_RR, scal, p->d_hist, opts->rtol, st);
-        if (pc) {
+        if (pc && flex) {
+          // Polak-Ribiere beta: z.r of the new residual, then z.q (r_new - r_old = -alpha q)
+          precond_full(p, pc, p->d_r, p->d_z, p->d_part, done, st);
+          gnk::finalize(p->d_part, nbp, OP_RZN, scal, p->d_hist, opts->rtol, st);
+          gnk::dot_partial(n, p->d_z, p->d_q, p->d_part, done, st);
+          gnk::finalize(p->d_part, nbr, OP_BETAF, scal, p->d_hist, opts->rtol, st);
+        } else if (pc) {
           precond_full(p, pc, p->d_r, p->d_z, p->d_part, done, st);
           gnk::finalize(p->d_part, nbp, OP_BETA, scal, p->d_hist, opts->rtol, st);
         } else {
@@ -1500,14 +1621,15 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
         gnk::update_p(n, p->d_p, p->d_z, scal, st);
       }
     };
-    const bool use_graph = opts->graphs != 0 && !g_prof_on;
+    // the cooperative launch of the inexact coarse solve is issued kernel by kernel
+    const bool use_graph = opts->graphs != 0 && !g_prof_on && !(pc && pc->coarse_solve == 1);
     ChunkGraph& cg = pc ? pc->cg : p->cg;
     auto run_chunk = [&]() {
       if (!use_graph) {
         launch_chunk(s);
         return;
       }
-      if (!cg.exec || cg.chunk != chunk || cg.hist != p->d_hist) {
+      if (!cg.exec || cg.chunk != chunk || cg.hist != p->d_hist || cg.flexible != flex) {
         // capture on a private stream (the caller's may be the null stream),
         // replay on the caller's
         cg.release();
@@ -1535,6 +1657,7 @@ extern "C" gn_status gn_solve(gn_problem* p, gn_precond* pc, const double* b_dev
         }
         cg.chunk = chunk;
         cg.hist = p->d_hist;
+        cg.flexible = flex;
       }
       GN_HIP(hipGraphLaunch(cg.exec, s));
     };

@@ -77,6 +77,74 @@ __global__ __launch_bounds__(NT) void k_extract_b(const SubDesc* __restrict__ su
   }
 }
 
+// P = A_N + s X A_O X in the same node-ELL form as B (k_extract_b), for the
+// final Rayleigh-Ritz step in the original pencil: A_N over every element of
+// Omega_j, A_O over those also in another subdomain, Dirichlet rows and
+// columns as identity (as the pencil band is extracted for its factor).
+template <int NC>
+__global__ __launch_bounds__(NT) void k_extract_p(const SubDesc* __restrict__ subs, int nex, int ney,
+                                                  const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
+                                                  PouDev pa, double shift, double* __restrict__ PE) {
+  const SubDesc& sd = subs[blockIdx.y];
+  const int r = blockIdx.x * NT + threadIdx.x;
+  const int npad = sd.NBB * TILE;
+  if (r >= npad) return;
+  double* base = PE + sd.offVB * (27 * NC);
+  if (r >= sd.nB) {
+    for (int k = 0; k < 27 * NC; ++k) base[(int64_t)k * npad + r] = 0.0;
+    return;
+  }
+  const int NX = nex + 1, NY = ney + 1;
+  const int ln = r / NC, c = r % NC;
+  int g[3];
+  box_global_node(sd.blo, sd.bn, sd.permB, ln, g);
+  const int64_t node = g[0] + (int64_t)NX * (g[1] + (int64_t)NY * g[2]);
+  const bool dr = dir[node * NC + c];
+  const double xr = pou_x(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
+  for (int d = 0; d < 27; ++d) {
+    int h[3] = {g[0] + d % 3 - 1, g[1] + (d / 3) % 3 - 1, g[2] + d / 9 - 1};
+    double vN[NC], vO[NC];
+#pragma unroll
+    for (int c2 = 0; c2 < NC; ++c2) vN[c2] = vO[c2] = 0.0;
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) in &= (h[a] >= sd.blo[a] && h[a] < sd.blo[a] + sd.bn[a]);
+    if (in) {
+      int lo[3], hi[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = max(max(g[a], h[a]) - 1, sd.elo[a]);
+        hi[a] = min(min(g[a], h[a]), sd.ehi[a] - 1);
+      }
+      for (int ez = lo[2]; ez <= hi[2]; ++ez)
+        for (int ey = lo[1]; ey <= hi[1]; ++ey)
+          for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+            const int64_t e = ex + (int64_t)nex * (ey + (int64_t)ney * ez);
+            const int a1 = (g[0] - ex) + 2 * (g[1] - ey) + 4 * (g[2] - ez);
+            const int a2 = (h[0] - ex) + 2 * (h[1] - ey) + 4 * (h[2] - ez);
+            const bool ov = pou_overlap_elem(pa, ex, ey, ez);
+            const double* row = Ke + e * (64 * NC * NC) + (int64_t)(a1 * NC + c) * (8 * NC) + a2 * NC;
+#pragma unroll
+            for (int c2 = 0; c2 < NC; ++c2) {
+              vN[c2] += row[c2];
+              if (ov) vO[c2] += row[c2];
+            }
+          }
+      const int64_t node2 = h[0] + (int64_t)NX * (h[1] + (int64_t)NY * h[2]);
+#pragma unroll
+      for (int c2 = 0; c2 < NC; ++c2) {
+        if (dr || dir[node2 * NC + c2]) {
+          vN[c2] = (d == 13 && c2 == c) ? 1.0 : 0.0;
+        } else {
+          vN[c2] += shift * xr * pou_x(sd, pa, dir, NX, NY, NC, h[0], h[1], h[2], c2) * vO[c2];
+        }
+      }
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < NC; ++c2) base[(int64_t)(d * NC + c2) * npad + r] = vN[c2];
+  }
+}
+
 // out = B V for b columns. A thread computes R consecutive nodes (one
 // component) of one BCW-column chunk. Consecutive nodes lie along the fastest
 // local axis a0 (the box's shortest), where the neighbours of R nodes are R + 2
@@ -983,6 +1051,34 @@ __global__ __launch_bounds__(NT) void k_eig_rq(const SubDesc* __restrict__ subs,
   }
 }
 
+// Defect of the Ritz pairs in the original pencil, rho = B V - P V diag(nu)
+// (P V and B V from the node-ELL products), and the correction
+// V += (P^-1 rho) diag(1/nu): one inverse-iteration step in defect form, whose
+// banded solve acts on the small residual only, so its backward error (of the
+// order of the condition of P times the solved vector) no longer limits the
+// eigenvectors.  Columns with nu ~ 0 (the null space of B) are left alone.
+__global__ __launch_bounds__(NT) void k_defect(const SubDesc* __restrict__ subs, int b,
+                                               const double* __restrict__ BV, const double* __restrict__ PV,
+                                               const double* __restrict__ nu, double* __restrict__ rho) {
+  const SubDesc& sd = subs[blockIdx.y];
+  const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= (int64_t)sd.NBB * TILE * b) return;
+  const int col = (int)(t % b);
+  const int64_t i = sd.offVB * b + t;
+  rho[i] = BV[i] - nu[(int64_t)blockIdx.y * b + col] * PV[i];
+}
+
+__global__ __launch_bounds__(NT) void k_defect_add(const SubDesc* __restrict__ subs, int b,
+                                                   const double* __restrict__ D, const double* __restrict__ nu,
+                                                   double nu_min, double* __restrict__ V) {
+  const SubDesc& sd = subs[blockIdx.y];
+  const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= (int64_t)sd.NBB * TILE * b) return;
+  const double nk = nu[(int64_t)blockIdx.y * b + (int)(t % b)];
+  const int64_t i = sd.offVB * b + t;
+  if (nk > nu_min) V[i] += D[i] / nk;
+}
+
 // Ritz residual sums of one subdomain: the GRAM_SPLIT row-split partials added
 // in fixed order (the same sums k_small_eig forms)
 __global__ void k_resid_sum(int b, const double* __restrict__ resp, double* __restrict__ res) {
@@ -1321,6 +1417,20 @@ void eig_rq(const gn_problem* p, const gn_precond* pc, int b, const double* V, d
   GN_CHECK_LAUNCH();
 }
 
+void eig_defect(const gn_precond* pc, int b, int maxNBB, const double* BV, const double* PV, const double* nu,
+                double* rho, hipStream_t s) {
+  dim3 grid((unsigned)(((int64_t)maxNBB * TILE * b + NT - 1) / NT), pc->n_sub);
+  hipLaunchKernelGGL(k_defect, grid, dim3(NT), 0, s, pc->d_sub, b, BV, PV, nu, rho);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_defect_add(const gn_precond* pc, int b, int maxNBB, const double* D, const double* nu, double nu_min,
+                    double* V, hipStream_t s) {
+  dim3 grid((unsigned)(((int64_t)maxNBB * TILE * b + NT - 1) / NT), pc->n_sub);
+  hipLaunchKernelGGL(k_defect_add, grid, dim3(NT), 0, s, pc->d_sub, b, D, nu, nu_min, V);
+  GN_CHECK_LAUNCH();
+}
+
 void eig_resid_sum(int n_sub, int b, const double* resp, double* res, hipStream_t s) {
   hipLaunchKernelGGL(k_resid_sum, dim3(n_sub), dim3(128), 0, s, b, resp, res);
   GN_CHECK_LAUNCH();
@@ -1336,6 +1446,18 @@ void zem_modes(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, dou
   else
     hipLaunchKernelGGL(k_zem_modes<1>, grid, dim3(NT), 0, s, pc->d_sub, p->d_xn[0], p->d_xn[1], p->d_xn[2],
                        p->map_kind, p->map_par[0], p->map_par[1], mtan, b, V);
+  GN_CHECK_LAUNCH();
+}
+
+void eig_extract_p(const gn_problem* p, const gn_precond* pc, int maxNBB, double shift, double* PE,
+                   hipStream_t s) {
+  dim3 grid((maxNBB * TILE + NT - 1) / NT, pc->n_sub);
+  if (p->nc == 3)
+    hipLaunchKernelGGL(k_extract_p<3>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke,
+                       p->d_dir, pou_axes(pc), shift, PE);
+  else
+    hipLaunchKernelGGL(k_extract_p<1>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke,
+                       p->d_dir, pou_axes(pc), shift, PE);
   GN_CHECK_LAUNCH();
 }
 

@@ -37,8 +37,10 @@ void gn_set_error(gn_status code, const std::string& msg);
 
 // device-resident CG scalars and the recurrence steps of the single-block finalize kernel;
 // S_RTOL is the relative tolerance of a batched column (0: the launch argument)
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITER, S_MAXIT, S_BREAK, S_RTOL, S_N };
-enum { OP_BB = 0, OP_RZ0, OP_ALPHA, OP_RR, OP_BETA, OP_RESTART };
+// S_RZN holds z.r of the new residual while the flexible (Polak-Ribiere) beta
+// waits for z.q
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITER, S_MAXIT, S_BREAK, S_RTOL, S_RZN, S_N };
+enum { OP_BB = 0, OP_RZ0, OP_ALPHA, OP_RR, OP_BETA, OP_RESTART, OP_RZN, OP_BETAF };
 
 // ---------------------------------------------------------------------------
 // per-subdomain description (plain data, mirrored on the device)
@@ -59,6 +61,13 @@ struct SubDesc {
   int coff;             // first coarse index i(j, 0)
   int64_t offPhi;       // offset (doubles) of Phi_j (NBI*TILE rows x m, row-major)
   int bwI, bwB;         // half bandwidth in DOFs of the local matrix and of the pencil
+};
+
+// one nonzero block (A_H)_{j1,j2} of the block-sparse coarse matrix: m_j1 x m_j2
+// values, row-major, at `off`
+struct BsrBlock {
+  int j1, j2;
+  int64_t off;
 };
 
 // local DOF index <-> global node on a box with an axis permutation
@@ -159,6 +168,7 @@ __device__ inline bool pou_overlap_elem(const PouDev& pa, int ex, int ey, int ez
 struct ChunkGraph {
   hipGraphExec_t exec = nullptr;
   int chunk = 0;
+  int flexible = 0;
   const double* hist = nullptr;
   void release() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -214,7 +224,8 @@ struct gn_precond {
   SubDesc* d_subxI = nullptr;
   SubDesc* d_subxB = nullptr;
   int local_prec = 64;
-  int local_kernel = 0;        // 0 automatic, 1 batched matrix-core kernel for single columns
+  int local_kernel = 0;        // 0 tuned, 1 batched matrix-core kernel for single columns, 2 fixed rule
+  int pf_G = 0, pf_sp = 0, pf_padw = 0;   // launch shape of the single-column sweep (0: not set)
   // per-axis node coverage (PoU counts) and part ranges for the gather-form prolongation
   int* d_cnt[3] = {nullptr, nullptr, nullptr};   // #parts whose I-range holds node index
   int* d_plo[3] = {nullptr, nullptr, nullptr};   // first such part
@@ -247,6 +258,21 @@ struct gn_precond {
   double *d_gm = nullptr, *d_um = nullptr, *d_ym = nullptr;  // coarse vectors, column * NBH*TILE
   double* d_Z = nullptr;     // L_H^-1 as dense tiles (NBH x NBH tiles, lower)
   int NBH = 0;
+  // inexact coarse solve (coarse_solve = 1): A_H block-sparse by subdomain
+  // pairs, the inverses of its diagonal blocks, and the inner CG state
+  int coarse_solve = 0;
+  double coarse_rtol = 1e-4;
+  int coarse_maxit = 200;
+  int* d_bsr_ptr = nullptr;      // n_sub + 1: blocks of block row j at [ptr[j], ptr[j+1])
+  BsrBlock* d_bsr_blk = nullptr; // block row, block column and value offset of each block
+  double* d_bsr_val = nullptr;
+  int64_t* d_dinv_off = nullptr; // offset of (A_H)_jj^-1 (m_j x m_j, row-major) per subdomain
+  double* d_dinv = nullptr;
+  double* d_cvec = nullptr;      // inner CG vectors: r, z, p (two buffers), q; NBH*TILE each
+  double* d_cpart = nullptr;     // per-workgroup partial sums of the inner CG
+  double* d_cstat = nullptr;     // inner iterations of the last applications (diagnostics)
+  int coarse_grid = 0;           // workgroups of the cooperative inner CG launch
+  int64_t bsr_nnz = 0;
   std::vector<double> lam;   // eigenvalues per subdomain (n_eval each)
   std::vector<int> lam_n;
   int n_eval = 0;
@@ -295,9 +321,15 @@ void band_transpose(const void* d_refs, int n, int maxNB, const double* T, const
                     hipStream_t s);
 // precond.hip
 bool pf_supported(const gn_problem* p, const gn_precond* pc);
+void local_solve_tune(const gn_problem* p, gn_precond* pc, hipStream_t s);
 void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, const double* done,
                  hipStream_t s);
 void coarse_solve(const gn_precond* pc, const double* done, hipStream_t s);
+// inexact coarse solve: y = (CG on A_H, block-Jacobi) g for one column
+void coarse_cg(const gn_precond* pc, const double* g, double* y, const double* done, hipStream_t s);
+int coarse_cg_grid(const gn_precond* pc);
+void block_inverse(const gn_precond* pc, int* info, hipStream_t s);
+void bsr_from_dense(const gn_precond* pc, const double* AH, hipStream_t s);
 int prolong_blocks(const gn_problem* p);
 void prolong(const gn_problem* p, const gn_precond* pc, const double* r, double* z, double* part,
              const double* done, hipStream_t s);
@@ -321,6 +353,8 @@ void precond_mc(const gn_problem* p, const gn_precond* pc, const double* r, doub
 // geneo.hip
 void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s);
 void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double* BE, hipStream_t s);
+void eig_extract_p(const gn_problem* p, const gn_precond* pc, int maxNBB, double shift, double* PE,
+                   hipStream_t s);
 void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int b, int maxNBB,
                 const double* V, double* out, hipStream_t s);
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, const double* TB, const double* Vin,
@@ -340,6 +374,10 @@ void eig_normalise(const gn_precond* pc, int b, int ncol, double* V, hipStream_t
 void zem_modes(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s);
 void eig_resid_sum(int n_sub, int b, const double* resp, double* res, hipStream_t s);
 void eig_rq(const gn_problem* p, const gn_precond* pc, int b, const double* V, double* lam, hipStream_t s);
+void eig_defect(const gn_precond* pc, int b, int maxNBB, const double* BV, const double* PV, const double* nu,
+                double* rho, hipStream_t s);
+void eig_defect_add(const gn_precond* pc, int b, int maxNBB, const double* D, const double* nu, double nu_min,
+                    double* V, hipStream_t s);
 void build_phi(const gn_problem* p, const gn_precond* pc, int b, int maxNI, const double* V,
                hipStream_t s);
 void aphi(const gn_problem* p, const gn_precond* pc, int b, int maxNB, double* Y, hipStream_t s);
@@ -360,7 +398,7 @@ namespace gnh {
 // work that used the block has finished
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
-int64_t dev_size(const void* p);     // rounded size of a block from dev_alloc (0 if unknown)
+int64_t dev_size(const void* p);     // rounded size a live block was asked for (0 if unknown)
 double dev_alloc_seconds();          // cumulative time spent in hipMalloc/hipFree
 PouDev pou_dev(const gn_problem* p, const gn_precond* pc);
 constexpr double kEps = 2.220446049250313e-16;

@@ -302,6 +302,16 @@ __global__ void k_finalize(const double* __restrict__ part, int nb, int op, doub
       hist[2 * (it - 1) + 1] = beta;
       break;
     }
+    case OP_RZN:     // z.r of the new residual (flexible CG)
+      scal[S_RZN] = s;
+      break;
+    case OP_BETAF: {  // s = z.q: beta = z^T (r_new - r_old) / z_old^T r_old = -alpha z.q / rz_old
+      double beta = -scal[S_ALPHA] * s / scal[S_RZ];
+      scal[S_BETA] = beta;
+      scal[S_RZ] = scal[S_RZN];
+      hist[2 * (it - 1) + 1] = beta;
+      break;
+    }
   }
 }
 

@@ -739,7 +739,12 @@ void precond_mc(const gn_problem* p, const gn_precond* pc, const double* r, doub
 #undef GN_MC
     GN_CHECK_LAUNCH();
   }
-  if (pc->NH > 0) {
+  if (pc->NH > 0 && pc->coarse_solve == 1) {
+    // inexact coarse solve: one inner CG per column (finished columns skip theirs)
+    const int64_t NHc = (int64_t)pc->NBH * TILE;
+    for (int c = 0; c < k; ++c)
+      coarse_cg(pc, gm + c * NHc, ym + c * NHc, scal ? scal + c * S_N + S_DONE : nullptr, s);
+  } else if (pc->NH > 0) {
     GnProfScope prof(PROF_COARSE, (double)pc->NBH * (pc->NBH + 1) * TILE2 * 8.0, s);
     hipLaunchKernelGGL(k_coarse_fwd_mc, dim3(pc->NBH), dim3(TILE * MC_K), 0, s, pc->NBH, pc->d_Z, gm, um, k, scal);
     GN_CHECK_LAUNCH();

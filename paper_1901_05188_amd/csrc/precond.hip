@@ -14,6 +14,10 @@
 // k_prolong: gather-form sum z = sum_j R_j^T t_j: each output DOF visits the
 //   (at most 8) subdomains whose box holds it, in a fixed order, so the result
 //   is deterministic without atomics; fused with the partial r.z.
+#include <array>
+#include <map>
+#include <mutex>
+
 #include "gn_internal.h"
 
 namespace {
@@ -397,52 +401,50 @@ namespace gnk {
 int max_lds_doubles() { return 18 * 1024; }
 
 namespace {
-// Launch shape of the single-column sweep: G column groups of TILE / G columns.
-// 512 threads (G = 16, two columns per thread and tile) while 2w slots fit the
-// registers; 1024 threads (G = 32, one column) for wider bands.
+// Launch shapes of the single-column sweep: G column groups of TILE / G
+// columns; 512 threads (G = 16, two columns per thread and tile) or 1024 (G =
+// 32, one column).  A shape holds sp = (TILE / G) w register slots per buffer,
+// rounded up to an instantiated count.  Slot limits without spills (compiler
+// resource reports): G = 16: 44 (FP64: 252 registers at 44); G = 32: 24 (FP64,
+// 128 registers) or 32 (FP32).
 struct PfShape {
   int G, sp, padw;
   bool ok;
 };
-PfShape pf_shape(const gn_precond* pc) {
-  PfShape sh{16, 0, 0, false};
-  if (pc->local_kernel == 1) return sh;
-  // register slots per buffer without spills: G = 16 (two columns per thread,
-  // up to 256 registers): 32; G = 32 (one column, 128 registers): 16 (FP64) /
-  // 32 (FP32)
+int pf_slots(int sp) {
+  return sp <= 8 ? 8 : sp <= 12 ? 12 : sp <= 16 ? 16 : sp <= 20 ? 20 : sp <= 24 ? 24 : sp <= 32 ? 32 : sp <= 40 ? 40 : 44;
+}
+std::vector<PfShape> pf_candidates(const gn_precond* pc) {
+  std::vector<PfShape> out;
   for (int G : {16, 32}) {
-    const int spmax = (G == 32 && pc->local_prec != 32) ? 16 : 32;
+    const int spmax = G == 16 ? 44 : (pc->local_prec == 32 ? 32 : 24);
     const int sp = (TILE / G) * pc->maxwI;
     if (sp > spmax) continue;
-    // the kernel's slot count: sp rounded up to an instantiated size
-    const int spt = sp <= 8 ? 8 : sp <= 12 ? 12 : sp <= 16 ? 16 : sp <= 20 ? 20 : sp <= 24 ? 24 : 32;
+    const int spt = pf_slots(sp);
     // zero tiles on both sides of the LDS vector cover every window read: the
     // forward window starts w tiles before the row, the reads of the unused
     // slots reach spt / (TILE / G) tiles past it
     const int padw = pc->maxwI + spt / (TILE / G) + 1;
     const int stat = 2 * G * (TILE + 1);     // doubles of the static reduction arrays
     if ((pc->maxNBI + 2 * padw) * TILE + stat > 20 * 1024 - 64) continue;
-    sh.G = G;
-    sh.sp = sp;
-    sh.padw = padw;
-    sh.ok = true;
-    return sh;
+    out.push_back(PfShape{G, sp, padw, true});
   }
-  return sh;
+  return out;
 }
-}  // namespace
+PfShape pf_shape(const gn_precond* pc) {
+  if (pc->local_kernel == 1) return PfShape{16, 0, 0, false};
+  if (pc->pf_G > 0) return PfShape{pc->pf_G, pc->pf_sp, pc->pf_padw, true};
+  const std::vector<PfShape> c = pf_candidates(pc);
+  return c.empty() ? PfShape{16, 0, 0, false} : c.front();
+}
 
-void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, const double* done,
-                 hipStream_t s) {
+void launch_pf(const gn_problem* p, const gn_precond* pc, const PfShape& sh, const double* r, const double* done,
+               hipStream_t s) {
   const bool f32 = pc->local_prec == 32;
   const double* Phi = pc->NH > 0 ? pc->d_Phi : nullptr;
-  double bytes = pc->trsv_bytes;
-  GnProfScope prof(PROF_TRSV, bytes, s);
-  const PfShape sh = pf_shape(pc);
-  if (sh.ok) {
-    if (!pc->d_LIb) throw gn_error{GN_ERR_ARG, "backward band missing for the single-column sweep"};
-    const int need_sp = sh.sp, padw = sh.padw;
-    size_t dynpf = (size_t)(pc->maxNBI + 2 * padw) * TILE * sizeof(double);
+  if (!pc->d_LIb) throw gn_error{GN_ERR_ARG, "backward band missing for the single-column sweep"};
+  const int need_sp = sh.sp, padw = sh.padw;
+  const size_t dynpf = (size_t)(pc->maxNBI + 2 * padw) * TILE * sizeof(double);
 #define GN_PF(FT, NC, SPV, GV)                                                                    \
   do {                                                                                            \
     auto kfn = k_local_solve_pf<FT, NC, SPV, GV>;                                                 \
@@ -455,32 +457,104 @@ void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, con
                        (const FT*)pc->d_LIb, pc->d_t, Phi, pc->d_g, done, padw,                   \
                        (const FT*)(f32 ? (const void*)pc->d_zf : (const void*)pc->d_z0));         \
   } while (0)
-#define GN_PF_SP(FT, NC, GV)                              \
+#define GN_PF_SP16(FT, NC)                                \
   do {                                                    \
-    if (need_sp <= 8) GN_PF(FT, NC, 8, GV);               \
-    else if (need_sp <= 12) GN_PF(FT, NC, 12, GV);        \
-    else if (need_sp <= 16) GN_PF(FT, NC, 16, GV);        \
-    else if (need_sp <= 20) GN_PF(FT, NC, 20, GV);        \
-    else if (need_sp <= 24) GN_PF(FT, NC, 24, GV);        \
-    else GN_PF(FT, NC, 32, GV);                           \
+    if (need_sp <= 8) GN_PF(FT, NC, 8, 16);               \
+    else if (need_sp <= 12) GN_PF(FT, NC, 12, 16);        \
+    else if (need_sp <= 16) GN_PF(FT, NC, 16, 16);        \
+    else if (need_sp <= 20) GN_PF(FT, NC, 20, 16);        \
+    else if (need_sp <= 24) GN_PF(FT, NC, 24, 16);        \
+    else if (need_sp <= 32) GN_PF(FT, NC, 32, 16);        \
+    else if (need_sp <= 40) GN_PF(FT, NC, 40, 16);        \
+    else GN_PF(FT, NC, 44, 16);                           \
+  } while (0)
+#define GN_PF_SP32(FT, NC)                                \
+  do {                                                    \
+    if (need_sp <= 8) GN_PF(FT, NC, 8, 32);               \
+    else if (need_sp <= 12) GN_PF(FT, NC, 12, 32);        \
+    else if (need_sp <= 16) GN_PF(FT, NC, 16, 32);        \
+    else if (need_sp <= 20) GN_PF(FT, NC, 20, 32);        \
+    else if (need_sp <= 24) GN_PF(FT, NC, 24, 32);        \
+    else GN_PF(FT, NC, 32, 32);                           \
   } while (0)
 #define GN_PF_G(FT, NC)                                   \
   do {                                                    \
-    if (sh.G == 16) GN_PF_SP(FT, NC, 16);                 \
-    else GN_PF_SP(FT, NC, 32);                            \
+    if (sh.G == 16) GN_PF_SP16(FT, NC);                   \
+    else GN_PF_SP32(FT, NC);                              \
   } while (0)
-    if (f32) {
-      if (p->nc == 3) GN_PF_G(float, 3); else GN_PF_G(float, 1);
-    } else {
-      if (p->nc == 3) GN_PF_G(double, 3); else GN_PF_G(double, 1);
-    }
-#undef GN_PF_G
-#undef GN_PF_SP
-#undef GN_PF
-    GN_CHECK_LAUNCH();
-    return;
+  if (f32) {
+    if (p->nc == 3) GN_PF_G(float, 3); else GN_PF_G(float, 1);
+  } else {
+    if (p->nc == 3) GN_PF_G(double, 3); else GN_PF_G(double, 1);
   }
-  throw gn_error{GN_ERR_ARG, "local band too wide for the single-column sweep kernel"};
+#undef GN_PF_G
+#undef GN_PF_SP32
+#undef GN_PF_SP16
+#undef GN_PF
+  GN_CHECK_LAUNCH();
+}
+
+// Shapes chosen per process for a band shape (components, precision, band
+// width, largest subdomain): every later preconditioner of that shape takes
+// the same kernel, so its applications are bit-for-bit repeatable.
+std::mutex g_tune_mu;
+std::map<std::array<int, 4>, std::pair<int, int>> g_tune;   // key -> (G, sp)
+}  // namespace
+
+// Autotuner of the single-column sweep: when more than one shape fits the
+// band, each is timed on this preconditioner's own factors (one warm-up and
+// three timed launches, HIP events on the set-up stream) and the fastest kept.
+void local_solve_tune(const gn_problem* p, gn_precond* pc, hipStream_t s) {
+  pc->pf_G = 0;
+  if (pc->local_kernel == 1) return;
+  const std::vector<PfShape> cand = pf_candidates(pc);
+  if (cand.empty()) return;
+  const std::array<int, 4> key{p->nc, pc->local_prec, pc->maxwI, pc->maxNBI};
+  PfShape best = cand.front();
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      for (const PfShape& c : cand)
+        if (c.G == it->second.first) best = c;
+      cached = true;
+    }
+  }
+  if (!cached && cand.size() > 1 && pc->local_kernel == 0) {
+    hipEvent_t e0, e1;
+    GN_HIP(hipEventCreate(&e0));
+    GN_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    for (const PfShape& c : cand) {
+      launch_pf(p, pc, c, p->d_r, nullptr, s);
+      GN_HIP(hipEventRecord(e0, s));
+      for (int k = 0; k < 3; ++k) launch_pf(p, pc, c, p->d_r, nullptr, s);
+      GN_HIP(hipEventRecord(e1, s));
+      GN_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      GN_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = {best.G, best.sp};
+  }
+  pc->pf_G = best.G;
+  pc->pf_sp = best.sp;
+  pc->pf_padw = best.padw;
+}
+
+void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, const double* done,
+                 hipStream_t s) {
+  GnProfScope prof(PROF_TRSV, pc->trsv_bytes, s);
+  const PfShape sh = pf_shape(pc);
+  if (!sh.ok) throw gn_error{GN_ERR_ARG, "local band too wide for the single-column sweep kernel"};
+  launch_pf(p, pc, sh, r, done, s);
 }
 
 bool pf_supported(const gn_problem* p, const gn_precond* pc) {

@@ -470,8 +470,12 @@ static void worker_main(gn_server* sv, Operator* op_ptr) {
       o.evict_req = false;
       if (!o.resident) {
         // admission: the operator is built once its a-priori footprint fits
+        // the estimate counts nev vectors per subdomain; cluster completion
+        // can add a few (0.1 % of the bytes on the laminate catalogue), so the
+        // build reserves 1/32 more and settles on the measured footprint
         o.building = true;
-        if (!reserve_budget(sv, lk, &o, o.est)) {
+        const int64_t reserve = o.est + o.est / 32;
+        if (!reserve_budget(sv, lk, &o, reserve)) {
           o.building = false;
           fail_operator(sv, o, GN_ERR_OOM);
           o.failed = false;          // later requests may fit once others are removed
@@ -488,14 +492,14 @@ static void worker_main(gn_server* sv, Operator* op_ptr) {
             measured = gnh::resident_bytes(o.p->owned) + gnh::resident_bytes(o.pc->owned);
           } catch (const gn_error& e) {
             lk.lock();
-            sv->used -= o.est;
+            sv->used -= reserve;
             o.building = false;
             fail_operator(sv, o, e.code);
             return;
           }
         }
         lk.lock();
-        sv->used -= o.est;
+        sv->used -= reserve;
         o.building = false;
         if (st != GN_OK) {
           gn_set_error(st, err);

@@ -3,10 +3,11 @@
 The small parity cases have local bands of at most 3 tiles, so they reach only
 the narrowest instantiations of the local-solve kernels.  These cases have
 subdomain boxes whose bands are as wide as those of the bench and
-configuration workloads (tests/oracle_runs.py, WIDE): 10 tiles (the FP64
-sweep with 20 slots), 12 tiles (24 slots; pencil band 13, an 18-slot ring of
-the eigen block solves) and 17 tiles (FP64: the 16-column matrix-core sweep
-with one live column; FP32: the 1024-thread sweep).  Each is compared with the
+configuration workloads (tests/oracle_runs.py, WIDE): 10 tiles (the sweep
+with 20 slots), 12 tiles (24 slots; pencil band 13, an 18-slot ring of the eigen
+block solves) and 17 tiles (the sweep with 40 slots per thread, or the
+1024-thread shape, whichever the set-up's timing picks; and, forced, the
+16-column matrix-core kernel with one live column).  Each is compared with the
 oracle as the small cases are: M^-1 r element-wise (one- and two-level), GenEO
 eigenvalues and counts, and the PCG solution at 1e-8 (1e-7 for FP32 local
 factors) after both sides converge to 1e-12.
@@ -48,13 +49,14 @@ def _apply(pc, r):
     return z[0].cpu().numpy()
 
 
-@pytest.mark.parametrize("name,prec", [("diff_wide10", 64), ("diff_wide10", 32), ("lam_wide12", 64),
-                                       ("lam_wide12", 32), ("lam_wide17", 64), ("lam_wide17", 32)])
-def test_wide_band_one_level_apply(name, prec):
+@pytest.mark.parametrize("name,prec,kernel", [("diff_wide10", 64, 0), ("diff_wide10", 32, 0), ("lam_wide12", 64, 0),
+                                              ("lam_wide12", 32, 0), ("lam_wide17", 64, 0), ("lam_wide17", 32, 0),
+                                              ("lam_wide17", 64, 1), ("lam_wide17", 64, 2)])
+def test_wide_band_one_level_apply(name, prec, kernel):
     w = orc.workload(name)
     g = orc.geneo_run(name, coarse=False)
-    print(f"[gpu] setup {name} one-level prec={prec}", flush=True)
-    pc = _gp().Preconditioner.from_workload(problem(name), w, coarse=False, local_prec=prec)
+    print(f"[gpu] setup {name} one-level prec={prec} local_kernel={kernel}", flush=True)
+    pc = _gp().Preconditioner.from_workload(problem(name), w, coarse=False, local_prec=prec, local_kernel=kernel)
     try:
         print(f"[gpu] {name} band tiles {pc.report['band_tiles']}", flush=True)
         r = np.random.default_rng(2).standard_normal(w.n_free)
