@@ -117,8 +117,10 @@ def cpu_baseline(config):
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1901_05188_amd", "csrc", "precond.hip")
 
 
-def traffic_file(workload, prec):
-    return os.path.join(ROOT, "profiles", f"local_solve_traffic_{workload}_fp{prec}.json")
+def traffic_file(workload, prec, threads):
+    """Counter summary of the local-solve kernel for a workload, factor precision
+    and launch shape (threads per subdomain)."""
+    return os.path.join(ROOT, "profiles", f"local_solve_traffic_{workload}_fp{prec}_{threads}t.json")
 
 
 def _sha256(path):
@@ -167,11 +169,11 @@ def summarize_counters(fetch_csv, write_csv, kernel_prefix="k_local_solve", floo
     return out
 
 
-def measured_traffic(workload, prec):
+def measured_traffic(workload, prec, threads):
     """HBM bytes per working local-solve launch from the committed counter
     summary, or None if it is missing or was taken on another kernel source."""
     try:
-        with open(traffic_file(workload, prec)) as f:
+        with open(traffic_file(workload, prec, threads)) as f:
             t = json.load(f)
         if t.get("source_sha256") != _sha256(TRAFFIC_SOURCE):
             return None
@@ -369,6 +371,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c5")
     ap.add_argument("--local-prec", type=int, default=64)
+    ap.add_argument("--local-kernel", type=int, default=0,
+                    help="single-column local-solve kernel: 0 = timed choice of launch shape, 3 / 4 = 512 / "
+                         "1024 threads per subdomain (to take counters of the shape a timed run chose)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-local-factor comparison leg")
@@ -392,7 +397,12 @@ def main():
     if args.summarize_counters:
         out = summarize_counters(*args.summarize_counters)
         name = make_workload(args.config).name
-        path = traffic_file(name, args.local_prec)
+        if args.local_kernel not in (3, 4):
+            raise SystemExit("--summarize-counters needs --local-kernel 3 or 4: the launch shape the counter runs used")
+        threads = 512 if args.local_kernel == 3 else 1024
+        if not out["kernel"].endswith(f", {threads // 32}>"):
+            raise SystemExit(f"counter runs used {out['kernel']}, not the {threads}-thread shape")
+        path = traffic_file(name, args.local_prec, threads)
         os.makedirs(os.path.dirname(path), exist_ok=True)
         with open(path, "w") as f:
             json.dump(out, f, indent=1)
@@ -418,7 +428,7 @@ def main():
         measurements)."""
         t0 = time.perf_counter()
         prob = gp.Problem.from_workload(wl)
-        pc = gp.Preconditioner.from_workload(prob, wl, local_prec=args.local_prec)
+        pc = gp.Preconditioner.from_workload(prob, wl, local_prec=args.local_prec, local_kernel=args.local_kernel)
         b = torch.zeros((prob.nrhs, prob.n_free), dtype=torch.float64, device=dev)
         prob.rhs(b)
         x = torch.zeros_like(b)
@@ -492,9 +502,19 @@ def main():
     bytes_per_app = tr["bytes"] / launches
     bytes_per_launch = bytes_per_app * min(applications, launches) / launches
     tr_gbs = bytes_per_launch / (tr_ms * 1e-3) / 1e9 if tr["launches"] else 0.0
-    traffic = measured_traffic(w.name, args.local_prec)
+    threads = pc.report["local_threads"]
+    ftype = "double" if args.local_prec == 64 else "float"
+    nc = 3 if w.pde == 1 else 1
+    # template arguments <FT, NC, slots, G> up to the slots, which the band fixes
+    instance = (f"k_local_solve_pf<{ftype}, {nc}, *, {threads // 32}>" if threads
+                else "k_band_solve_mc (16-column matrix-core kernel)")
+    traffic = measured_traffic(w.name, args.local_prec, threads) if threads else None
+    if traffic and not (traffic["kernel"].startswith(f"k_local_solve_pf<{ftype}, {nc},")
+                        and traffic["kernel"].endswith(f", {threads // 32}>")):
+        traffic = None     # counters taken on another kernel
     tile_bytes = pc.report["apply_tile_bytes"]
     roof = {"bound": "hbm", "kernel": "k_local_solve (batched banded fwd+bwd triangular solves)",
+            "kernel_instance": instance, "local_threads": threads,
             "achieved": round(tr_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(tr_gbs / HBM_PEAK_GBS, 4),
             # HBM bytes per working launch from the committed counter runs of this

@@ -158,7 +158,8 @@ gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t n
  * threads per subdomain) timed at set-up when both fit and the choice kept for
  * later preconditioners of the same band shape in the process; 1 = always the
  * 16-column matrix-core kernel of the batched solves; 2 = the sweep with the
- * first shape that fits, untimed.
+ * first shape that fits, untimed; 3 / 4 = the sweep with 512 / 1024 threads
+ * per subdomain (GN_ERR_ARG when the band does not fit that shape).
  * pou selects the partition of unity X_j (Section 3.2, def:pou; Section 3.3.1):
  * 0 = the standard one (one over the number of subdomains whose V_h0 holds the
  * DOF, zero on the subdomain boundary); 1 = the smoother one of Sarkis that the
@@ -172,7 +173,11 @@ gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t n
  * for overlapping subdomain pairs) preconditioned by the inverses of its
  * diagonal blocks, stopped at coarse_rtol (0 = 1e-4) relative residual or
  * coarse_maxit (0 = 200) iterations.  The preconditioner then varies from one
- * application to the next: solve with gn_solve_opts.flexible = 1. */
+ * application to the next: solve with gn_solve_opts.flexible = 1.
+ * eig_refine (0 = 1, at most 8) is the number of refinement steps in the
+ * original pencil once the iteration has converged: each adds
+ * P^-1 (B v - nu P v) / nu to every Ritz vector v, with B v and P v formed from
+ * the element matrices, and takes a Rayleigh-Ritz step on the block. */
 typedef struct gn_dd_opts {
   int32_t nparts[3];
   const int32_t* cuts[3];
@@ -192,6 +197,7 @@ typedef struct gn_dd_opts {
   int32_t coarse_solve;
   double coarse_rtol;
   int32_t coarse_maxit;
+  int32_t eig_refine;
 } gn_dd_opts;
 
 typedef struct gn_setup_report {
@@ -212,6 +218,9 @@ typedef struct gn_setup_report {
                                 gather of r, the write of z_j and Phi_j^T r        */
   double apply_tile_bytes;   /* the same launch counted over the stored 32 x 32 band
                                 tiles and inverse diagonal tiles                   */
+  int32_t local_threads;     /* threads per subdomain of the single-column local
+                                solve (512 or 1024); 0 when the 16-column
+                                matrix-core kernel serves single columns          */
 } gn_setup_report;
 
 /* Build the preconditioner: local Dirichlet factors A_j = L_j L_j^T
@@ -225,6 +234,14 @@ gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* opts, void* stream,
  * them, into host array out; *m receives m_j, *n_avail the number computed. */
 gn_status gn_precond_eigenvalues(const gn_precond* pc, int32_t sub, double* out, int32_t cap,
                                  int32_t* m, int32_t* n_avail);
+
+/* The coarse basis (Section 3.3.2: Phi_{i(j,k)} = X^(j) p_k^j padded by zeros,
+ * i(j,k) = sum_{l<j} m_l + k) copied into the host array out in the free
+ * numbering: N_H columns of n_free values, column-major, leading dimension
+ * ld >= n_free; *nh (may be NULL) receives N_H.  out = NULL only queries N_H.
+ * Synchronizes the device.  A preconditioner without a coarse space has
+ * N_H = 0. */
+gn_status gn_precond_coarse_basis(const gn_precond* pc, double* out, int64_t ld, int64_t* nh);
 
 /* z = M^-1 r for one column (device pointers, free numbering). */
 gn_status gn_precond_apply(gn_precond* pc, const double* r_dev, double* z_dev, void* stream);
@@ -341,13 +358,16 @@ gn_status gn_server_add(gn_server* sv, gn_problem* p, gn_precond* pc, int32_t* o
  * host arrays of grid, mat, loads and opts are copied (nothing on the device),
  * *est_bytes (may be NULL) receives its gn_footprint estimate.  The server
  * builds it (gn_assemble + gn_setup_geneo on the operator's stream) when a
- * request for it arrives and its estimate fits in the budget; while it does
- * not fit, the least recently used idle server-built operator (no queued or
- * running column) is destroyed to make room, and rebuilt when a later request
- * needs it.  Requests wait meanwhile; they fail with GN_ERR_OOM when even
- * evicting every idle server-built operator cannot make room, and with the
- * set-up's status if the build fails.  Right-hand sides use the operator's
- * free numbering (the mask in loads). */
+ * request for it arrives and its estimate plus 1/32 (the build's reservation,
+ * replaced by the measured footprint once built) fits in the budget; while it
+ * does not fit, the least recently used idle server-built operator (no queued
+ * or running column) is destroyed to make room, and rebuilt when a later
+ * request needs it.  Requests wait meanwhile; they fail with GN_ERR_OOM (the
+ * message names the bytes) when even evicting every idle server-built operator
+ * cannot make room, and with the set-up's status and message if the build
+ * fails.  Registration itself returns GN_ERR_OOM when the reservation exceeds
+ * the whole budget.  Right-hand sides use the operator's free numbering (the
+ * mask in loads). */
 gn_status gn_server_register(gn_server* sv, const gn_grid* grid, const gn_material* mat, const gn_loads* loads,
                              const gn_dd_opts* opts, int32_t* op, int64_t* est_bytes);
 

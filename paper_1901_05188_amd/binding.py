@@ -20,7 +20,7 @@ GN_OK, GN_WARN_MAXIT, GN_PENDING = 0, 1, 2
 STATUS = {0: "OK", 1: "WARN_MAXIT", 2: "PENDING", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_NOT_SPD",
           -4: "ERR_EIG_NOCONV", -5: "ERR_COARSE_SINGULAR", -6: "ERR_DEVICE", -7: "ERR_BREAKDOWN"}
 EXPORTS = ["gn_assemble", "gn_problem_info", "gn_problem_rhs", "gn_load_vectors", "gn_matvec",
-           "gn_setup_geneo", "gn_precond_eigenvalues", "gn_precond_apply", "gn_solve", "gn_footprint", "gn_resident_bytes",
+           "gn_setup_geneo", "gn_precond_eigenvalues", "gn_precond_coarse_basis", "gn_precond_apply", "gn_solve", "gn_footprint", "gn_resident_bytes",
            "gn_server_create", "gn_server_add", "gn_server_register", "gn_server_operator_info",
            "gn_server_remove", "gn_server_submit", "gn_server_wait",
            "gn_server_destroy", "gn_profile_enable", "gn_profile_read", "gn_trim_memory", "gn_destroy_problem",
@@ -56,7 +56,7 @@ class gn_dd_opts(C.Structure):
                 ("shift", C.c_double), ("eig_tol", C.c_double), ("eig_maxit", C.c_int32),
                 ("eig_block", C.c_int32), ("eig_filter", C.c_int32), ("local_kernel", C.c_int32),
                 ("pou", C.c_int32), ("coarse_solve", C.c_int32), ("coarse_rtol", C.c_double),
-                ("coarse_maxit", C.c_int32)]
+                ("coarse_maxit", C.c_int32), ("eig_refine", C.c_int32)]
 
 
 class gn_setup_report(C.Structure):
@@ -65,7 +65,7 @@ class gn_setup_report(C.Structure):
                 ("t_local_s", C.c_double), ("t_eigen_s", C.c_double), ("t_coarse_s", C.c_double),
                 ("t_total_s", C.c_double), ("hbm_bytes", C.c_int64), ("eig_resid", C.c_double),
                 ("eig_solves", C.c_int32), ("t_alloc_s", C.c_double), ("apply_bytes", C.c_double),
-                ("apply_tile_bytes", C.c_double)]
+                ("apply_tile_bytes", C.c_double), ("local_threads", C.c_int32)]
 
 
 class gn_solve_opts(C.Structure):
@@ -210,7 +210,7 @@ def _workload_spec(w):
 
 def _dd_struct(nparts, cuts, overlap=1, nev=0, threshold=0.0, nev_max=0, local_prec=64, coarse=True, shift=0.0,
                eig_tol=0.0, eig_maxit=0, eig_block=0, eig_filter=0, local_kernel=0, pou=0, coarse_solve=0,
-               coarse_rtol=0.0, coarse_maxit=0):
+               coarse_rtol=0.0, coarse_maxit=0, eig_refine=0):
     o = gn_dd_opts()
     keep = []
     for a in range(3):
@@ -227,6 +227,7 @@ def _dd_struct(nparts, cuts, overlap=1, nev=0, threshold=0.0, nev_max=0, local_p
     o.pou = {"standard": 0, "sarkis": 1}[pou] if isinstance(pou, str) else int(pou)
     o.coarse_solve = {"exact": 0, "cg": 1}[coarse_solve] if isinstance(coarse_solve, str) else int(coarse_solve)
     o.coarse_rtol, o.coarse_maxit = float(coarse_rtol), int(coarse_maxit)
+    o.eig_refine = int(eig_refine)
     return o, keep
 
 
@@ -308,10 +309,10 @@ class Preconditioner:
     def __init__(self, prob: Problem, nparts: Sequence[int], cuts, overlap=1, nev=0, threshold=0.0,
                  nev_max=0, local_prec=64, coarse=True, shift=0.0, eig_tol=0.0, eig_maxit=0,
                  eig_block=0, eig_filter=0, local_kernel=0, pou=0, coarse_solve=0, coarse_rtol=0.0,
-                 coarse_maxit=0, stream=None):
+                 coarse_maxit=0, eig_refine=0, stream=None):
         o, keep = _dd_struct(nparts, cuts, overlap, nev, threshold, nev_max, local_prec, coarse, shift, eig_tol,
                              eig_maxit, eig_block, eig_filter, local_kernel, pou, coarse_solve, coarse_rtol,
-                             coarse_maxit)
+                             coarse_maxit, eig_refine)
         rep = gn_setup_report()
         h = C.c_void_p()
         _check(lib().gn_setup_geneo(prob.handle, C.byref(o), _stream(stream), C.byref(h), C.byref(rep)))
@@ -330,6 +331,16 @@ class Preconditioner:
         m, n = C.c_int32(), C.c_int32()
         _check(lib().gn_precond_eigenvalues(self.handle, int(sub), buf, 128, C.byref(m), C.byref(n)))
         return np.array(buf[: n.value]), m.value
+
+    def coarse_basis(self) -> np.ndarray:
+        """The coarse basis Phi as a host array (n_free, N_H) (gn_precond_coarse_basis)."""
+        nh = C.c_int64()
+        _check(lib().gn_precond_coarse_basis(self.handle, None, 0, C.byref(nh)))
+        n_free = self.prob.n_free
+        out = np.zeros((nh.value, n_free), dtype=np.float64)   # column-major n_free x N_H
+        if nh.value:
+            _check(lib().gn_precond_coarse_basis(self.handle, _dptr(out, C.c_double), n_free, None))
+        return out.T
 
     def apply(self, r, z, stream=None):
         assert r.shape == z.shape and r.shape[-1] == self.prob.n_free

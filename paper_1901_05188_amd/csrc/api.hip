@@ -608,6 +608,10 @@ static DdPlan plan_decomposition(const int ne_[3], int nc, const gn_dd_opts* o) 
         sd.bwB = std::min(sd.nB - 1, band_width_dofs(sd.bn, sd.permB, nc));
         sd.wI = std::max(std::min(sd.NBI - 1, (band_width_dofs(sd.in_, sd.permI, nc) + TILE - 1) / TILE), 0);
         sd.wB = std::max(std::min(sd.NBB - 1, (band_width_dofs(sd.bn, sd.permB, nc) + TILE - 1) / TILE), 0);
+        // the single-column sweep finds entries outside the band only in its two
+        // outermost band tiles, which needs 32 w - bw < 32
+        if (TILE * sd.wI - sd.bwI > TILE - 1 || sd.bwI < 0)
+          throw gn_error{GN_ERR_DEVICE, "band planner: inconsistent band width in tiles"};
         sd.offTI = pl.offTI;
         sd.offDI = pl.offDI;
         sd.offVI = pl.offVI;
@@ -762,6 +766,8 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   const int O = std::max(o->overlap, 0);
   const double shift = o->shift > 0 ? o->shift : 1e-2;
   const double eig_tol = o->eig_tol > 0 ? o->eig_tol : 1e-12;
+  if (o->eig_refine < 0 || o->eig_refine > 8) argfail("eig_refine must lie in [0, 8]");
+  const int eig_refine = o->eig_refine > 0 ? o->eig_refine : 1;
   const int eig_maxit = o->eig_maxit > 0 ? o->eig_maxit : 300;
   if (o->eig_filter < 0 || o->eig_filter > 8) argfail("eig_filter must lie in [0, 8]");
   if (o->coarse < 0 || o->coarse > 2) argfail("coarse must be 0, 1 or 2");
@@ -781,7 +787,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   pc->coarse_solve = o->coarse_solve;
   pc->coarse_rtol = o->coarse_rtol > 0 ? o->coarse_rtol : 1e-4;
   pc->coarse_maxit = o->coarse_maxit > 0 ? o->coarse_maxit : 200;
-  if (o->local_kernel < 0 || o->local_kernel > 2) argfail("local_kernel must be 0, 1 or 2");
+  if (o->local_kernel < 0 || o->local_kernel > 4) argfail("local_kernel must lie in [0, 4]");
   pc->local_kernel = o->local_kernel;
   for (int a = 0; a < 3; ++a) {
     pc->nparts[a] = o->nparts[a];
@@ -1151,20 +1157,24 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
         // P = A_N + s B and B themselves) passes only the small defect through
         // the solve; a last Rayleigh-Ritz step on span(V) then forms its Gram
         // matrices V^T P V and V^T B V from the same exact products.
+        // Further steps (eig_refine) shrink the error components of the block
+        // again by the ratio of the wanted to the unwanted nu.
         double* PE = dalloc<double>(tmp, (size_t)offVB * 27 * nc);
         gnk::eig_extract_p(p, pc, maxNBB, shift, PE, s);
-        gnk::eig_bapply(p, pc, PE, b, maxNBB, V, Z, s);       // Z = P V
-        gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);      // BV = B V
-        gnk::eig_defect(pc, b, maxNBB, BV, Z, nu, BZ, s);     // BZ = B V - P V diag(nu)
-        gnk::eig_trsm(pc, b, LB, DB, TBB, BZ, Z, s);          // Z = P^-1 (defect)
-        ++eig_solves;
-        gnk::eig_defect_add(pc, b, maxNBB, Z, nu, 1e-12 / shift, V, s);
-        gnk::eig_bapply(p, pc, PE, b, maxNBB, V, Z, s);       // Z = P V
-        gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);      // BV = B V
-        gnk::eig_gram(pc, b, V, Z, BV, nullptr, nullptr, GP, GB, nullptr, s);
-        gnk::eig_small(n_sub, b, GP, GB, resp, res, Y, nu, nullptr, s);
-        gnk::eig_vupdate(pc, b, maxNBB, V, BV, Y, Z, BZ, s);  // Z = V Y, BZ = (B V) Y
-        std::swap(V, Z);
+        for (int step = 0; step < eig_refine; ++step) {
+          gnk::eig_bapply(p, pc, PE, b, maxNBB, V, Z, s);       // Z = P V
+          gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);      // BV = B V
+          gnk::eig_defect(pc, b, maxNBB, BV, Z, nu, BZ, s);     // BZ = B V - P V diag(nu)
+          gnk::eig_trsm(pc, b, LB, DB, TBB, BZ, Z, s);          // Z = P^-1 (defect)
+          ++eig_solves;
+          gnk::eig_defect_add(pc, b, maxNBB, Z, nu, 1e-12 / shift, V, s);
+          gnk::eig_bapply(p, pc, PE, b, maxNBB, V, Z, s);       // Z = P V
+          gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);      // BV = B V
+          gnk::eig_gram(pc, b, V, Z, BV, nullptr, nullptr, GP, GB, nullptr, s);
+          gnk::eig_small(n_sub, b, GP, GB, resp, res, Y, nu, nullptr, s);
+          gnk::eig_vupdate(pc, b, maxNBB, V, BV, Y, Z, BZ, s);  // Z = V Y, BZ = (B V) Y
+          std::swap(V, Z);
+        }
         GN_HIP(hipMemcpyAsync(h_nu.data(), nu, sizeof(double) * h_nu.size(), hipMemcpyDeviceToHost, s));
         GN_HIP(hipStreamSynchronize(s));
       }
@@ -1376,6 +1386,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     rep->t_alloc_s = gnh::dev_alloc_seconds() - ta0;
     rep->apply_bytes = pc->trsv_bytes;
     rep->apply_tile_bytes = pc->trsv_tile_bytes;
+    rep->local_threads = gnk::pf_supported(p, pc) ? 32 * pc->pf_G : 0;
     rep->hbm_bytes = hb;
     rep->eig_resid = eig_resid;
   }
@@ -1408,6 +1419,37 @@ extern "C" gn_status gn_precond_eigenvalues(const gn_precond* pc, int32_t sub, d
   if (out)
     for (int k = 0; k < std::min(n, (int)cap); ++k) out[k] = pc->lam[(size_t)sub * pc->n_eval + k];
   return GN_OK;
+}
+
+extern "C" gn_status gn_precond_coarse_basis(const gn_precond* pc, double* out, int64_t ld, int64_t* nh) {
+  GN_TRY
+  if (!pc) argfail("null argument");
+  const gn_problem* p = pc->prob;
+  if (nh) *nh = pc->NH;
+  if (!out || pc->NH == 0) return GN_OK;
+  if (ld < p->n_free) argfail("ld must be >= n_free");
+  std::vector<double> phi((size_t)pc->phi_len);
+  std::vector<int> f2f((size_t)p->n_free);
+  GN_HIP(hipDeviceSynchronize());
+  GN_HIP(hipMemcpy(phi.data(), pc->d_Phi, sizeof(double) * phi.size(), hipMemcpyDeviceToHost));
+  GN_HIP(hipMemcpy(f2f.data(), p->d_free2full, sizeof(int) * f2f.size(), hipMemcpyDeviceToHost));
+  std::vector<int64_t> full2free((size_t)p->n_dof, -1);
+  for (int64_t i = 0; i < p->n_free; ++i) full2free[f2f[i]] = i;
+  for (int64_t c = 0; c < pc->NH; ++c) std::fill(out + c * ld, out + c * ld + p->n_free, 0.0);
+  const int nc = p->nc;
+  for (int j = 0; j < pc->n_sub; ++j) {
+    const SubDesc& sd = pc->sub[j];
+    for (int row = 0; row < sd.nI; ++row) {
+      int g[3];
+      box_global_node(sd.ilo, sd.in_, sd.permI, row / nc, g);
+      const int64_t node = g[0] + (int64_t)p->nn[0] * (g[1] + (int64_t)p->nn[1] * g[2]);
+      const int64_t f = full2free[node * nc + row % nc];
+      if (f < 0) continue;   // Dirichlet DOF: Phi is zero there
+      for (int k = 0; k < sd.m; ++k) out[(sd.coff + k) * ld + f] = phi[sd.offPhi + (int64_t)row * sd.m + k];
+    }
+  }
+  return GN_OK;
+  GN_CATCH
 }
 
 static void ensure_batch_precond(gn_precond* pc, hipStream_t s);

@@ -1316,8 +1316,7 @@ __global__ __launch_bounds__(NT) void k_trsm_tile(int NB, int K, double* __restr
   }
 }
 
-// A(I,J) -= L(I,K) L(J,K)^T for K < J <= I (blockIdx.x enumerates the pairs)
-// one 16 x 16 quadrant per wave of the tile product X Y, X(r,k) at xs[k*TILE + r];
+// One 16 x 16 quadrant per wave of the tile product X Y, X(r,k) at xs[k*TILE + r];
 // Y(k,c) at ys[c*TILE + k] (TRANSY = false) or ys[k*TILE + c] (TRANSY = true)
 template <bool TRANSY>
 __device__ inline void tile_mma(const double* __restrict__ xs, const double* __restrict__ ys, int qr, int qc,
@@ -1336,27 +1335,6 @@ __device__ inline void tile_mma(const double* __restrict__ xs, const double* __r
   for (int ks = 0; ks < 8; ++ks) acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], acc[ks & 3], 0, 0, 0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) out[i] = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
-}
-
-// trailing update A(I,J) -= L(I,K) L(J,K)^T for the lower block triangle, one tile
-// per workgroup on FP64 matrix cores
-__global__ __launch_bounds__(NT) void k_syrk_tile(int NB, int K, double* __restrict__ A) {
-  int m = NB - K - 1;
-  int idx = blockIdx.x;
-  // row-major enumeration of the lower triangle of an m x m block matrix
-  int I0 = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-  while ((I0 + 1) * (I0 + 2) / 2 <= idx) ++I0;
-  while (I0 * (I0 + 1) / 2 > idx) --I0;
-  int J0 = idx - I0 * (I0 + 1) / 2;
-  if (I0 >= m) return;
-  int I = K + 1 + I0, J = K + 1 + J0;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int lr = lane & 15, lk = lane >> 4, qr = wid & 1, qc = wid >> 1;
-  double o[4];
-  tile_mma<true>(A + ((int64_t)I * NB + K) * TILE2, A + ((int64_t)J * NB + K) * TILE2, qr, qc, lr, lk, o);
-  double* t = A + ((int64_t)I * NB + J) * TILE2;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) t[(qc * 16 + lr) * TILE + qr * 16 + 4 * i + lk] -= o[i];
 }
 
 // Explicit inverse Z = L^-1 of the coarse factor, right-looking over block
@@ -1391,6 +1369,80 @@ __global__ __launch_bounds__(NT) void k_trinv_update(int NB, int K, const double
   double* zt = Z + ((int64_t)I * NB + J) * TILE2;
 #pragma unroll
   for (int i = 0; i < 4; ++i) zt[(qc * 16 + lr) * TILE + qr * 16 + 4 * i + lk] += o[i];
+}
+
+// Panel forms of the two updates above.  The coarse factor and its inverse are
+// built in panels of CPANEL tile columns (rows): inside a panel the tile steps
+// run as before, restricted to the panel, and the rest of the matrix receives
+// the whole panel's contribution in one pass, CPANEL tile products summed in
+// the matrix-core accumulators per output tile.  Each trailing tile is then
+// read and written once per panel instead of once per tile column, which is
+// what bounded the tile-by-tile updates.
+constexpr int CPANEL = 8;
+
+// acc += X Y over one tile pair (the accumulating form of tile_mma)
+template <bool TRANSY>
+__device__ inline void tile_mma_acc(const double* __restrict__ xs, const double* __restrict__ ys, int qr, int qc,
+                                    int lr, int lk, gn_d4 acc[4]) {
+  double av[8], bv[8];
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) {
+    const int k = 4 * ks + lk;
+    av[ks] = xs[k * TILE + qr * 16 + lr];
+    bv[ks] = TRANSY ? ys[k * TILE + qc * 16 + lr] : ys[(qc * 16 + lr) * TILE + k];
+  }
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) acc[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], acc[ks & 3], 0, 0, 0);
+}
+
+// A(I,J) -= sum_{k0 <= k < k1} L(I,k) L(J,k)^T over the tiles J0 <= J < J1,
+// J <= I < NB (one workgroup per tile; blockIdx.x runs down column J0, then
+// J0 + 1, ...: column J holds NB - J tiles)
+__global__ __launch_bounds__(NT) void k_syrk_panel(int NB, int k0, int k1, int J0, int J1, double* __restrict__ A) {
+  int idx = blockIdx.x, J = J0;
+  if (J1 - J0 > CPANEL) {
+    // many columns: invert the count c(J) = sum_{J0 <= J' < J} (NB - J') in closed form
+    const double b = 2.0 * (NB - J0) + 1.0;
+    int d = (int)((b - sqrt(b * b - 8.0 * idx)) * 0.5);
+    d = max(d, 0);
+    while (d > 0 && (int64_t)d * (2 * (NB - J0) - d + 1) / 2 > idx) --d;
+    while ((int64_t)(d + 1) * (2 * (NB - J0) - d) / 2 <= idx) ++d;
+    idx -= (int)((int64_t)d * (2 * (NB - J0) - d + 1) / 2);
+    J += d;
+  } else {
+    while (J < J1 && idx >= NB - J) idx -= NB - J, ++J;
+  }
+  if (J >= J1) return;
+  const int I = J + idx;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4, qr = wid & 1, qc = wid >> 1;
+  gn_d4 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = gn_d4{0, 0, 0, 0};
+  for (int k = k0; k < k1; ++k)
+    tile_mma_acc<true>(A + ((int64_t)I * NB + k) * TILE2, A + ((int64_t)J * NB + k) * TILE2, qr, qc, lr, lk, acc);
+  double* t = A + ((int64_t)I * NB + J) * TILE2;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    t[(qc * 16 + lr) * TILE + qr * 16 + 4 * i + lk] -= (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+}
+
+// Z(I,J) += sum_{max(k0,J) <= k < k1} L(I,k) Z(k,J) for I in [I0, NB), J in [0, k1)
+// (blockIdx.x = J, blockIdx.y = I - I0)
+__global__ __launch_bounds__(NT) void k_trinv_panel(int NB, int k0, int k1, int I0, const double* __restrict__ L,
+                                                    double* __restrict__ Z) {
+  const int J = blockIdx.x, I = I0 + blockIdx.y;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4, qr = wid & 1, qc = wid >> 1;
+  gn_d4 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = gn_d4{0, 0, 0, 0};
+  for (int k = max(k0, J); k < k1; ++k)
+    tile_mma_acc<false>(L + ((int64_t)I * NB + k) * TILE2, Z + ((int64_t)k * NB + J) * TILE2, qr, qc, lr, lk, acc);
+  double* zt = Z + ((int64_t)I * NB + J) * TILE2;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    zt[(qc * 16 + lr) * TILE + qr * 16 + 4 * i + lk] += (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
 }
 
 
@@ -1651,27 +1703,60 @@ void make_pair(void* dst, int j1, int j2, const int lo[3], const int hi[3]) {
   }
 }
 
+// number of tiles (I, J) with J0 <= J < J1 and J <= I < NB
+static int64_t trapezoid_tiles(int NB, int J0, int J1) {
+  int64_t n = 0;
+  for (int J = J0; J < J1; ++J) n += NB - J;
+  return n;
+}
+
+// Right-looking tiled Cholesky in panels of CPANEL tile columns: inside a
+// panel each column is factored (k_potrf_tile, k_trsm_tile) and updates the
+// panel's later columns; then one k_syrk_panel launch applies the panel to
+// the trailing matrix.
 void dense_chol(int NB, double* A, double* Dinv, int* info, hipStream_t s) {
-  for (int K = 0; K < NB; ++K) {
-    hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(NT), 0, s, NB, K, A, Dinv, info);
-    GN_CHECK_LAUNCH();
-    int m = NB - K - 1;
-    if (m > 0) {
-      hipLaunchKernelGGL(k_trsm_tile, dim3(m), dim3(NT), 0, s, NB, K, A, Dinv);
+  for (int K0 = 0; K0 < NB; K0 += CPANEL) {
+    const int K1 = std::min(NB, K0 + CPANEL);
+    for (int K = K0; K < K1; ++K) {
+      hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(NT), 0, s, NB, K, A, Dinv, info);
       GN_CHECK_LAUNCH();
-      hipLaunchKernelGGL(k_syrk_tile, dim3(m * (m + 1) / 2), dim3(NT), 0, s, NB, K, A);
+      const int m = NB - K - 1;
+      if (m > 0) {
+        hipLaunchKernelGGL(k_trsm_tile, dim3(m), dim3(NT), 0, s, NB, K, A, Dinv);
+        GN_CHECK_LAUNCH();
+      }
+      if (K + 1 < K1) {
+        const int64_t nt = trapezoid_tiles(NB, K + 1, K1);
+        hipLaunchKernelGGL(k_syrk_panel, dim3((unsigned)nt), dim3(NT), 0, s, NB, K, K + 1, K + 1, K1, A);
+        GN_CHECK_LAUNCH();
+      }
+    }
+    if (K1 < NB) {
+      const int64_t nt = trapezoid_tiles(NB, K1, NB);
+      hipLaunchKernelGGL(k_syrk_panel, dim3((unsigned)nt), dim3(NT), 0, s, NB, K0, K1, K1, NB, A);
       GN_CHECK_LAUNCH();
     }
   }
 }
 
+// Z = L^-1 by block rows in panels of CPANEL: each row of the panel is
+// finished (k_trinv_row) and passed to the panel's later rows
+// (k_trinv_update restricted to them); then one k_trinv_panel launch adds the
+// panel's rows to the running sums of every later row.
 void tri_inv(int NB, const double* L, const double* Dinv, double* Z, hipStream_t s) {
   GN_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)NB * NB * TILE2, s));
-  for (int K = 0; K < NB; ++K) {
-    hipLaunchKernelGGL(k_trinv_row, dim3(K + 1), dim3(NT), 0, s, NB, K, Dinv, Z);
-    GN_CHECK_LAUNCH();
-    if (K + 1 < NB) {
-      hipLaunchKernelGGL(k_trinv_update, dim3((NB - K - 1) * (K + 1)), dim3(NT), 0, s, NB, K, L, Z);
+  for (int K0 = 0; K0 < NB; K0 += CPANEL) {
+    const int K1 = std::min(NB, K0 + CPANEL);
+    for (int K = K0; K < K1; ++K) {
+      hipLaunchKernelGGL(k_trinv_row, dim3(K + 1), dim3(NT), 0, s, NB, K, Dinv, Z);
+      GN_CHECK_LAUNCH();
+      if (K + 1 < K1) {
+        hipLaunchKernelGGL(k_trinv_update, dim3((K1 - K - 1) * (K + 1)), dim3(NT), 0, s, NB, K, L, Z);
+        GN_CHECK_LAUNCH();
+      }
+    }
+    if (K1 < NB) {
+      hipLaunchKernelGGL(k_trinv_panel, dim3(K1, NB - K1), dim3(NT), 0, s, NB, K0, K1, K1, L, Z);
       GN_CHECK_LAUNCH();
     }
   }

@@ -64,6 +64,16 @@ __device__ inline void lds_barrier() {
 // while the current one is reduced, and only LDS-ordering barriers separate the
 // steps.  The subdomain vector lives in LDS with w zero tiles of padding on both
 // sides, so no step needs a bounds branch.  SP >= 2w register slots per buffer.
+//
+// Stored tiles hold exact zeros outside the band (row r, column c with
+// r - c > bw) and in the upper triangle of each inverse diagonal tile.  A load
+// that would only fetch such a zero is redirected: tiles wholly outside the
+// matrix (the first w block rows of the forward band, the last w of the
+// backward one) to the shared zero tile Z0, and single entries outside the
+// band or the triangle to one fixed entry of the same tile that is itself
+// zero whenever any entry of the tile is.  The products are unchanged bit for
+// bit (each redirected load still reads 0), and the cache lines that hold
+// nothing but zeros are never fetched.
 template <typename FT, int NC, int SP, int G>
 __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __restrict__ subs, int NX, int NY,
                                                            const double* __restrict__ r, const FT* __restrict__ T,
@@ -119,6 +129,11 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
   const FT* Tb = T + sd.offTI * TILE2;
   const FT* Db = D + sd.offDI * TILE2;
   const int ns = CW * w;
+  // zero-entry redirection (see above): the entry (row, column) of a tile sits
+  // at column * TILE + row; ZR = (TILE - 1, 0), ZC = (0, TILE - 1)
+  constexpr unsigned ZR = TILE - 1, ZC = (TILE - 1) * TILE;
+  const int ic = i - CW * gq;          // row minus the thread's first column (row) in a tile
+  const int bw = sd.bwI;
   // Two register buffers: block row K is consumed from one while the loads of
   // rows K+1 (other buffer, issued one step earlier) and K+2 (this buffer,
   // issued right after the consumption) are in flight.
@@ -129,19 +144,26 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
   // every slot address is a uniform tile pointer plus the thread's 32-bit offset
   // inside the tile (one offset register for all slots)
   const unsigned toff = (unsigned)((CW * gq) * TILE + i);
+  // forward tile t of block row K is L(K, K - w + t); its entry (i, c) lies
+  // outside the band when 32 (w - t) + i - c > bw, possible for t <= 1 only
+  // (32 w - bw < 32)
 #define GN_LOAD_FWD_LV(K_, LV, OFF)                                                      \
   {                                                                                      \
-    const FT* rowp = Tb + (int64_t)(K_) * (w + 1) * TILE2;                               \
+    const int Kl = (K_);                                                                 \
+    const FT* rowp = Tb + (int64_t)Kl * (w + 1) * TILE2;                                 \
     _Pragma("unroll") for (int u = 0; u < SP; ++u) {                                     \
       const int t = u / CW, q = u % CW;                                                  \
-      const FT* tp = (u < ns) ? rowp + t * TILE2 : Z0;                                   \
-      LV[u] = tp[(OFF) + (unsigned)(q * TILE)];                                          \
+      const FT* tp = (u < ns && Kl - w + t >= 0) ? rowp + t * TILE2 : Z0;                \
+      unsigned o = (OFF) + (unsigned)(q * TILE);                                         \
+      if (t <= 1) o = (ic - q > bw - TILE * (w - t)) ? ZR : o;                           \
+      LV[u] = tp[o];                                                                     \
     }                                                                                    \
   }
 #define GN_LOAD_FWD_DN(K_, DN, OFF)                                                      \
   {                                                                                      \
     const FT* dk = Db + (int64_t)(K_) * TILE2;                                           \
-    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[(OFF) + (unsigned)(q * TILE)]; \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q)                                       \
+      DN[q] = dk[(q > ic) ? ZC : (OFF) + (unsigned)(q * TILE)];                          \
   }
 #define GN_STEP_FWD(K_, LV, DN)                                                          \
   {                                                                                      \
@@ -197,19 +219,25 @@ __global__ __launch_bounds__(32 * G) void k_local_solve_pf(const SubDesc* __rest
   // backward block row K: tile d-1 of row K of the transposed band holds
   // L(K+d, K)^T (entry (i, rr) = L(K+d, K)(rr, i)) and tile w holds D_K^T
   const FT* TBb = TBk + sd.offTI * TILE2;
+  // backward tile t holds L(K + t + 1, K)^T: its entry (i, rr) is
+  // L(K + t + 1, K)(rr, i), outside the band when 32 (t + 1) + rr - i > bw
 #define GN_LOAD_BWD_LV(K_, LV, OFF)                                                      \
   {                                                                                      \
-    const FT* rowp = TBb + (int64_t)(K_) * (w + 1) * TILE2;                              \
+    const int Kl = (K_);                                                                 \
+    const FT* rowp = TBb + (int64_t)Kl * (w + 1) * TILE2;                                \
     _Pragma("unroll") for (int u = 0; u < SP; ++u) {                                     \
       const int t = u / CW, q = u % CW;                                                  \
-      const FT* tp = (u < ns) ? rowp + t * TILE2 : Z0;                                   \
-      LV[u] = tp[(OFF) + (unsigned)(q * TILE)];                                          \
+      const FT* tp = (u < ns && Kl + t + 1 < NB) ? rowp + t * TILE2 : Z0;                \
+      unsigned o = (OFF) + (unsigned)(q * TILE);                                         \
+      o = (q - ic > bw - TILE * (t + 1)) ? ZC : o;                                       \
+      LV[u] = tp[o];                                                                     \
     }                                                                                    \
   }
 #define GN_LOAD_BWD_DN(K_, DN, OFF)                                                      \
   {                                                                                      \
     const FT* dk = TBb + ((int64_t)(K_) * (w + 1) + w) * TILE2;                          \
-    _Pragma("unroll") for (int q = 0; q < CW; ++q) DN[q] = dk[(OFF) + (unsigned)(q * TILE)]; \
+    _Pragma("unroll") for (int q = 0; q < CW; ++q)                                       \
+      DN[q] = dk[(q < ic) ? ZR : (OFF) + (unsigned)(q * TILE)];                          \
   }
 #define GN_STEP_BWD(K_, LV, DN)                                                          \
   {                                                                                      \
@@ -502,17 +530,33 @@ std::map<std::array<int, 4>, std::pair<int, int>> g_tune;   // key -> (G, sp)
 }  // namespace
 
 // Autotuner of the single-column sweep: when more than one shape fits the
-// band, each is timed on this preconditioner's own factors (one warm-up and
-// three timed launches, HIP events on the set-up stream) and the fastest kept.
+// band, each is timed on this preconditioner's own factors (one warm-up
+// launch, then the shortest of four launches timed one by one with HIP events
+// on the set-up stream) and the fastest kept.
 void local_solve_tune(const gn_problem* p, gn_precond* pc, hipStream_t s) {
   pc->pf_G = 0;
   if (pc->local_kernel == 1) return;
-  const std::vector<PfShape> cand = pf_candidates(pc);
+  std::vector<PfShape> cand = pf_candidates(pc);
+  if (pc->local_kernel >= 3) {
+    // a fixed launch shape: 512 (G = 16) or 1024 (G = 32) threads
+    const int G = pc->local_kernel == 3 ? 16 : 32;
+    std::vector<PfShape> keep;
+    for (const PfShape& c : cand)
+      if (c.G == G) keep.push_back(c);
+    if (keep.empty())
+      throw gn_error{GN_ERR_ARG, "local band does not fit the " + std::to_string(32 * G) +
+                                     "-thread single-column sweep (local_kernel " +
+                                     std::to_string(pc->local_kernel) + ")"};
+    pc->pf_G = keep.front().G;
+    pc->pf_sp = keep.front().sp;
+    pc->pf_padw = keep.front().padw;
+    return;
+  }
   if (cand.empty()) return;
   const std::array<int, 4> key{p->nc, pc->local_prec, pc->maxwI, pc->maxNBI};
   PfShape best = cand.front();
   bool cached = false;
-  {
+  if (pc->local_kernel == 0) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
@@ -528,12 +572,16 @@ void local_solve_tune(const gn_problem* p, gn_precond* pc, hipStream_t s) {
     float best_ms = 1e30f;
     for (const PfShape& c : cand) {
       launch_pf(p, pc, c, p->d_r, nullptr, s);
-      GN_HIP(hipEventRecord(e0, s));
-      for (int k = 0; k < 3; ++k) launch_pf(p, pc, c, p->d_r, nullptr, s);
-      GN_HIP(hipEventRecord(e1, s));
-      GN_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      GN_HIP(hipEventElapsedTime(&ms, e0, e1));
+      float ms = 1e30f;
+      for (int k = 0; k < 4; ++k) {
+        GN_HIP(hipEventRecord(e0, s));
+        launch_pf(p, pc, c, p->d_r, nullptr, s);
+        GN_HIP(hipEventRecord(e1, s));
+        GN_HIP(hipEventSynchronize(e1));
+        float t = 0.f;
+        GN_HIP(hipEventElapsedTime(&t, e0, e1));
+        ms = std::min(ms, t);
+      }
       if (ms < best_ms) {
         best_ms = ms;
         best = c;

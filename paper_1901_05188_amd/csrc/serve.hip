@@ -261,6 +261,7 @@ struct Request {
   int remaining = 0;
   double t_submit = 0.0, t_done = 0.0;
   gn_status st = GN_OK;
+  std::string msg;   // why the request failed (empty: it did not)
   bool done = false;
   std::vector<gn_solve_report> rep;
 };
@@ -322,7 +323,7 @@ static void merge_status(gn_status& into, gn_status st) {
 }
 
 // finish every column of op that is queued or in flight with status st (lock held)
-static void fail_operator(gn_server* sv, Operator& o, gn_status st) {
+static void fail_operator(gn_server* sv, Operator& o, gn_status st, const std::string& msg = std::string()) {
   const int op = o.id;
   o.failed = true;
   o.queue.clear();
@@ -330,6 +331,7 @@ static void fail_operator(gn_server* sv, Operator& o, gn_status st) {
     Request& q = *kv.second;
     if (q.op != op || q.done) continue;
     merge_status(q.st, st);
+    if (q.msg.empty()) q.msg = msg;
     q.remaining = 0;
     q.done = true;
     q.t_done = now_s();
@@ -435,7 +437,7 @@ static void worker_main(gn_server* sv, Operator* op_ptr) {
       return true;
     } catch (const gn_error& e) {
       std::lock_guard<std::mutex> lk(sv->mu);
-      fail_operator(sv, o, e.code);
+      fail_operator(sv, o, e.code, e.msg);
       return false;
     }
   };
@@ -477,7 +479,10 @@ static void worker_main(gn_server* sv, Operator* op_ptr) {
         const int64_t reserve = o.est + o.est / 32;
         if (!reserve_budget(sv, lk, &o, reserve)) {
           o.building = false;
-          fail_operator(sv, o, GN_ERR_OOM);
+          fail_operator(sv, o, GN_ERR_OOM,
+                        "operator " + std::to_string(o.id) + " needs " + std::to_string(reserve) +
+                            " bytes to build (estimate + 1/32); the budget of " + std::to_string(sv->budget) +
+                            " bytes cannot make room for it");
           o.failed = false;          // later requests may fit once others are removed
           continue;
         }
@@ -494,7 +499,7 @@ static void worker_main(gn_server* sv, Operator* op_ptr) {
             lk.lock();
             sv->used -= reserve;
             o.building = false;
-            fail_operator(sv, o, e.code);
+            fail_operator(sv, o, e.code, e.msg);
             return;
           }
         }
@@ -503,7 +508,7 @@ static void worker_main(gn_server* sv, Operator* op_ptr) {
         o.building = false;
         if (st != GN_OK) {
           gn_set_error(st, err);
-          fail_operator(sv, o, st);
+          fail_operator(sv, o, st, err);
           return;
         }
         sv->used += measured;
@@ -523,16 +528,19 @@ static void worker_main(gn_server* sv, Operator* op_ptr) {
     }
     res.clear();
     gn_status err = GN_OK;
+    std::string err_msg;
     try {
       eng->step(res);
     } catch (const gn_error& e) {
       err = e.code;
+      err_msg = e.msg;
     } catch (...) {
       err = GN_ERR_DEVICE;
+      err_msg = "unexpected exception in the solve loop";
     }
     std::lock_guard<std::mutex> lk(sv->mu);
     if (err != GN_OK) {
-      fail_operator(sv, o, err);
+      fail_operator(sv, o, err, err_msg);
       return;
     }
     const double t = now_s();
@@ -683,7 +691,9 @@ extern "C" gn_status gn_server_register(gn_server* sv, const gn_grid* grid, cons
   for (uint8_t d : sp->dirichlet) n_free += d ? 0 : 1;
   if (n_free == 0) throw gn_error{GN_ERR_ARG, "no free DOFs"};
   std::lock_guard<std::mutex> lk(sv->mu);
-  if (est > sv->budget) throw gn_error{GN_ERR_OOM, "operator footprint exceeds the server's HBM budget"};
+  // a build reserves the estimate plus 1/32 (see the worker's admission step)
+  if (est + est / 32 > sv->budget)
+    throw gn_error{GN_ERR_OOM, "operator footprint " + std::to_string(est) + " bytes (+1/32 build margin) exceeds the server's HBM budget of " + std::to_string(sv->budget) + " bytes"};
   std::unique_ptr<Operator> o(new Operator());
   o->spec = std::move(sp);
   o->resident = false;
@@ -804,8 +814,9 @@ extern "C" gn_status gn_server_wait(gn_server* sv, int64_t ticket, double timeou
   if (reports) std::copy(q->rep.begin(), q->rep.end(), reports);
   if (latency_s) *latency_s = q->t_done - q->t_submit;
   const gn_status st = q->st;
+  const std::string msg = q->msg.empty() ? std::string("request failed on the device") : q->msg;
   sv->reqs.erase(it);
-  if (st < 0) gn_set_error(st, "request failed on the device");
+  if (st < 0) gn_set_error(st, msg.c_str());
   return st;
   SV_CATCH
 }
