@@ -118,6 +118,21 @@ gn_status gn_problem_rhs(const gn_problem* p, double* b_dev, int64_t ld, void* s
 gn_status gn_load_vectors(gn_problem* p, const double* body, int32_t nrhs, const double* traction,
                           double* b_dev, int64_t ld, void* stream);
 
+/* gn_load_vectors for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments and bit-identical output, but the staged host loads and the
+ * full-numbering load live in a static device workspace of 32 MiB per device
+ * (held until the process ends) instead of temporary allocations; the call
+ * makes no hipMalloc/hipFree.  It needs
+ * 8 * (round32(n_elem * ncomp if body) + round32(nrhs * ne[0] * ne[1] * ncomp
+ * if traction) + n_dof * nrhs) bytes, round32 rounding up to a multiple of 32;
+ * a larger request returns GN_ERR_ARG before any device work.  Every call on a
+ * device shares that device's workspace: calls that overlap in time on one
+ * device (other threads, other streams) race and must be serialized by the
+ * caller.  Returns after b_dev is written. */
+gn_status gn_load_vectors_noalloc(gn_problem* p, const double* body, int32_t nrhs, const double* traction,
+                                  double* b_dev, int64_t ld, void* stream);
+
 /* y = A x for ncol columns (device pointers, free numbering, leading dim ld). */
 gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t ncol,
                     int64_t ld, void* stream);

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libgenpcg.so")
 GN_OK, GN_WARN_MAXIT, GN_PENDING = 0, 1, 2
 STATUS = {0: "OK", 1: "WARN_MAXIT", 2: "PENDING", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_NOT_SPD",
           -4: "ERR_EIG_NOCONV", -5: "ERR_COARSE_SINGULAR", -6: "ERR_DEVICE", -7: "ERR_BREAKDOWN"}
-EXPORTS = ["gn_assemble", "gn_problem_info", "gn_problem_rhs", "gn_load_vectors", "gn_matvec",
+EXPORTS = ["gn_assemble", "gn_problem_info", "gn_problem_rhs", "gn_load_vectors", "gn_load_vectors_noalloc",
+           "gn_matvec",
            "gn_setup_geneo", "gn_precond_eigenvalues", "gn_precond_coarse_basis", "gn_precond_apply", "gn_solve", "gn_footprint", "gn_resident_bytes",
            "gn_server_create", "gn_server_add", "gn_server_register", "gn_server_operator_info",
            "gn_server_remove", "gn_server_submit", "gn_server_wait",
@@ -279,6 +280,19 @@ class Problem:
         tr = None if traction is None else np.ascontiguousarray(traction, dtype=np.float64)
         _check(lib().gn_load_vectors(self.handle, _dptr(bd, C.c_double), nrhs, _dptr(tr, C.c_double),
                                      _tensor_ptr(out), self.n_free, _stream(stream)))
+        return out
+
+    def load_vectors_noalloc(self, out, body=None, traction=None, stream=None):
+        """load_vectors through gn_load_vectors_noalloc: the library's static
+        device workspace instead of temporary allocations (32 MiB per device;
+        concurrent calls on one device race)."""
+        nrhs = 1 if out.dim() == 1 else out.shape[0]
+        assert out.is_cuda and out.dtype.is_floating_point and out.is_contiguous()
+        assert out.shape[-1] == self.n_free
+        bd = None if body is None else np.ascontiguousarray(body, dtype=np.float64)
+        tr = None if traction is None else np.ascontiguousarray(traction, dtype=np.float64)
+        _check(lib().gn_load_vectors_noalloc(self.handle, _dptr(bd, C.c_double), nrhs, _dptr(tr, C.c_double),
+                                             _tensor_ptr(out), self.n_free, _stream(stream)))
         return out
 
     def matvec(self, x, y, stream=None):

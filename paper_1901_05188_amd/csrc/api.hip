@@ -463,6 +463,62 @@ extern "C" gn_status gn_load_vectors(gn_problem* p, const double* body, int32_t 
   GN_CATCH
 }
 
+// ---------------------------------------------------------------------------
+// load vectors without allocation: the staging of the host loads and the
+// full-numbering load live in a static device array
+// ---------------------------------------------------------------------------
+#define GN_SCRATCH_DOUBLES ((size_t)4 << 20)     // 32 MiB per device
+static __device__ __align__(256) double scratch[GN_SCRATCH_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {nullptr};
+// device address of this device's copy of `scratch` (looked up once per device)
+double* scratch_address() {
+  int dev = 0;
+  GN_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw gn_error{GN_ERR_DEVICE, "device index beyond the static workspace table"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    GN_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" gn_status gn_load_vectors_noalloc(gn_problem* p, const double* body, int32_t nrhs,
+                                             const double* traction, double* b_dev, int64_t ld, void* stream) {
+  GN_TRY
+  if (!p || !b_dev) argfail("null argument");
+  if (nrhs < 1 || ld < p->n_free) argfail("bad nrhs/ld");
+  hipStream_t s = (hipStream_t)stream;
+  const int nc = p->nc;
+  const int64_t nbody = body ? p->n_elem * nc : 0;
+  const int64_t ntrac = traction ? (int64_t)nrhs * p->ne[0] * p->ne[1] * nc : 0;
+  auto pad = [](int64_t n) { return (n + 31) / 32 * 32; };
+  const int64_t need = pad(nbody) + pad(ntrac) + p->n_dof * nrhs;
+  if (need > (int64_t)GN_SCRATCH_DOUBLES)
+    argfail("load vectors need " + std::to_string(need * 8) + " bytes of workspace; the static workspace holds " +
+            std::to_string(GN_SCRATCH_DOUBLES * 8) + " (use gn_load_vectors)");
+  for (int64_t i = 0; i < nbody; ++i)
+    if (!std::isfinite(body[i])) argfail("non-finite body force");
+  for (int64_t i = 0; i < ntrac; ++i)
+    if (!std::isfinite(traction[i])) argfail("non-finite traction");
+  double* ws = scratch_address();
+  double* d_body = body ? ws : nullptr;
+  double* d_trac = traction ? ws + pad(nbody) : nullptr;
+  double* d_full = ws + pad(nbody) + pad(ntrac);   // every entry is written by the load kernel
+  if (body) GN_HIP(hipMemcpyAsync(d_body, body, sizeof(double) * nbody, hipMemcpyHostToDevice, s));
+  if (traction) GN_HIP(hipMemcpyAsync(d_trac, traction, sizeof(double) * ntrac, hipMemcpyHostToDevice, s));
+  gnk::assemble_load(p, d_body, d_trac, nrhs, d_full, s);
+  for (int c = 0; c < nrhs; ++c) gnk::gather_free(p, d_full + (int64_t)c * p->n_dof, b_dev + c * ld, s);
+  GN_HIP(hipStreamSynchronize(s));
+  return GN_OK;
+  GN_CATCH
+}
+
 extern "C" gn_status gn_matvec(gn_problem* p, const double* x_dev, double* y_dev, int32_t ncol,
                                int64_t ld, void* stream) {
   GN_TRY
