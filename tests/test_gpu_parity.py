@@ -1,10 +1,14 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle.
 
 Tolerances (FP64 path): assembled A x and b agree to 1e-12 of the row scale
-sum_j |A_ij x_j|; preconditioner applications to 1e-10 relative, or three
-times the case's FP64 condition where that is larger (tests/oracle_runs.py,
-minv_gate: on the 3x2x2 laminate an eps-size perturbation of the element
-matrices alone moves the oracle's M^-1 r by about 1e-10); GenEO eigenvalues to
+sum_j |A_ij x_j|, and the operators to 32 eps in the normwise measure
+||A_gpu x - A x|| / || |A| |x| || (oracle_runs.operator_eta; 2-9 eps observed:
+the two sides round their element integrals differently); preconditioner
+applications to 1e-10 relative, or three times the case's FP64 condition
+where that is larger (tests/oracle_runs.py, minv_gate: on the 3x2x2 laminate
+an eps-size perturbation of the element matrices alone moves the oracle's
+M^-1 r by about 1e-10), the condition scaled to the measured operator
+difference; GenEO eigenvalues to
 1e-10 * max(|lambda|, 1e-3 * lambda_cut); solutions to 1e-8 relative after both
 sides converge to 1e-12; iteration counts within max(1, 2%).  Mixed precision
 (FP32 local factors): solutions to 1e-7.
@@ -51,6 +55,21 @@ def problem(name):
     return _PROBS[name]
 
 
+_ETA = {}
+
+
+def op_eta(name):
+    """operator_eta of the GPU's assembled operator against the oracle's."""
+    if name not in _ETA:
+        A, b, free, Ke = orc.system(name)
+        p = problem(name)
+        X = orc.eta_vectors(p.n_free)
+        Y = torch.zeros(X.shape, dtype=torch.float64, device=DEV)
+        p.matvec(_t(X), Y)
+        _ETA[name] = orc.operator_eta(A, X, Y.cpu().numpy())
+    return _ETA[name]
+
+
 _PCS = {}
 
 
@@ -85,6 +104,9 @@ def test_assembled_matvec_matches_oracle(name):
         ref = A @ X[k]
         scale = absA @ np.abs(X[k])
         assert np.all(np.abs(Y[k] - ref) <= 1e-12 * scale + 1e-300), name
+    eta = op_eta(name)
+    print(f"[gpu] {name} operator difference {eta / np.finfo(float).eps:.1f} eps", flush=True)
+    assert eta <= 32 * np.finfo(float).eps
 
 
 @pytest.mark.parametrize("name", ALL)
@@ -157,7 +179,7 @@ def test_two_level_apply_matches_oracle(name):
     pc.apply(_t(r[None, :]), z)
     ref = g.apply(r)
     err = np.linalg.norm(z[0].cpu().numpy() - ref) / np.linalg.norm(ref)
-    tol = orc.minv_gate(name, seed=3)
+    tol = orc.minv_gate(name, seed=3, eta=op_eta(name))
     print(f"[gpu] {name} M^-1 r rel err {err:.2e} (gate {tol:.1e}, FP64 condition "
           f"{orc.minv_eps_sensitivity(name, True, 3):.1e})", flush=True)
     assert err <= tol
@@ -240,7 +262,7 @@ def test_matrix_core_local_kernel_single_column(name, local_prec):
     err = np.linalg.norm(z[0].cpu().numpy() - ref) / np.linalg.norm(ref)
     print(f"[gpu] {name} matrix-core local kernel, prec {local_prec}: M^-1 r rel err {err:.2e}")
     # FP32 factors: M^-1 itself changes at the FP32 level; the solve below is the gate
-    assert err <= (orc.minv_gate(name, seed=6) if local_prec == 64 else 1e-3), err
+    assert err <= (orc.minv_gate(name, seed=6, eta=op_eta(name)) if local_prec == 64 else 1e-3), err
     u_ref = np.linalg.solve(A.toarray(), b[:, 0])
     bt = _t(b[:, 0][None, :])
     x = torch.zeros_like(bt)
@@ -300,7 +322,7 @@ def test_smooth_partition_of_unity_matches_oracle(name):
         pc.apply(_t(r[None, :]), z)
         ref = g.apply(r)
         err = np.linalg.norm(z[0].cpu().numpy() - ref) / np.linalg.norm(ref)
-        tol = orc.minv_gate(name, seed=3)
+        tol = orc.minv_gate(name, seed=3, eta=op_eta(name.partition("|")[0]))
         print(f"[gpu] {name} M^-1 r rel err {err:.2e} (gate {tol:.1e})", flush=True)
         assert err <= tol
         A, b, free, Ke = orc.system(name)
@@ -501,3 +523,51 @@ def test_inexact_coarse_solve_with_flexible_cg_matches_oracle(name):
             assert abs(rep[0]["iters_first"] - info["iters"]) <= max(2, int(0.05 * info["iters"]))
     finally:
         pc.close()
+
+
+@pytest.mark.parametrize("name", ["lam_2x2", "diff_2x2x2", "lam_3x2x2_uneven"])
+def test_coarse_basis_matches_oracle(name):
+    """gn_precond_coarse_basis (Section 3.3.2: Phi_{i(j,k)} = X^(j) p_k^j padded by
+    zeros): N_H columns, subdomain j's block zero outside I_j, and spanning the
+    oracle's block: the energy-norm residual of each GPU column off span(oracle
+    Phi_j) below 1e-9 (1e-13 to 2e-11 observed; a wrong eigenvector would leave
+    O(1)).  The GPU's coarse correction R_H^T A_H^-1 R_H r, taken as the
+    difference of the two- and one-level applications, must equal the host's
+    dense FP64 recomputation from the GPU's own basis and operator
+    (A_H = Phi^T (A Phi) with A Phi from gn_matvec) to the case's M^-1 r gate:
+    the A_H build and the coarse solve add nothing beyond FP64 rounding."""
+    import scipy.linalg as sla
+    w = orc.workload(name)
+    g = orc.geneo_run(name)
+    A, b, free, Ke = orc.system(name)
+    pc = precond(name)
+    Phi = pc.coarse_basis()
+    assert Phi.shape == (w.n_free, g.NH) and pc.report["coarse_dim"] == g.NH
+    d = g.dec
+    for j in range(w.n_sub):
+        a, c = g.offsets[j], g.offsets[j + 1]
+        outside = np.ones(w.n_free, dtype=bool)
+        outside[d.I[j]] = False
+        assert not np.any(Phi[outside, a:c]), j
+        if c == a:
+            continue          # no eigenvalue below the threshold on this subdomain
+        Po, Pg = g.Phi[:, a:c], Phi[:, a:c]
+        coef = np.linalg.solve(Po.T @ (A @ Po), Po.T @ (A @ Pg))
+        R = Pg - Po @ coef
+        res = np.sqrt(np.einsum("ik,ik->k", R, A @ R) / np.einsum("ik,ik->k", Pg, A @ Pg))
+        assert res.max() <= 1e-9, (j, res)
+    AP = torch.zeros((g.NH, w.n_free), dtype=torch.float64, device=DEV)
+    problem(name).matvec(_t(Phi.T), AP)
+    AP = AP.cpu().numpy().T
+    AH = Phi.T @ AP
+    AH = 0.5 * (AH + AH.T)
+    r = np.random.default_rng(3).standard_normal(w.n_free)
+    host = Phi @ sla.cho_solve(sla.cho_factor(AH, lower=True), Phi.T @ r)
+    z2 = torch.zeros((1, w.n_free), dtype=torch.float64, device=DEV)
+    z1 = torch.zeros_like(z2)
+    pc.apply(_t(r[None, :]), z2)
+    precond(name, coarse=False).apply(_t(r[None, :]), z1)
+    gpu = (z2 - z1)[0].cpu().numpy()
+    err = np.linalg.norm(gpu - host) / np.linalg.norm(host)
+    print(f"[gpu] {name} coarse correction vs host recomputation {err:.2e}", flush=True)
+    assert err <= orc.minv_gate(name, seed=3)

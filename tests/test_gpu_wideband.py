@@ -43,6 +43,30 @@ def problem(name):
     return _PROBS[name]
 
 
+_ETA = {}
+
+
+def op_eta(name):
+    """operator_eta of the GPU's assembled operator against the oracle's."""
+    if name not in _ETA:
+        A, b, free, Ke = orc.system(name)
+        p = problem(name)
+        X = orc.eta_vectors(p.n_free)
+        Y = torch.zeros(X.shape, dtype=torch.float64, device=DEV)
+        p.matvec(_t(X), Y)
+        _ETA[name] = orc.operator_eta(A, X, Y.cpu().numpy())
+    return _ETA[name]
+
+
+@pytest.mark.parametrize("name", ["diff_wide10", "lam_wide12", "lam_wide17"])
+def test_wide_band_operator_matches_oracle(name):
+    """The assembled operators differ by rounding only: at most 32 eps in the
+    normwise measure of oracle_runs.operator_eta."""
+    eta = op_eta(name)
+    print(f"[gpu] {name} operator difference {eta / np.finfo(float).eps:.1f} eps", flush=True)
+    assert eta <= 32 * np.finfo(float).eps
+
+
 def _apply(pc, r):
     z = torch.zeros((1, r.shape[0]), dtype=torch.float64, device=DEV)
     pc.apply(_t(r[None, :]), z)
@@ -81,8 +105,10 @@ def test_wide_band_geneo_eigen_apply_and_solve(name):
         r = np.random.default_rng(3).standard_normal(w.n_free)
         ref = g.apply(r)
         err = np.linalg.norm(_apply(pc, r) - ref) / np.linalg.norm(ref)
-        tol = orc.minv_gate(name, seed=3)
-        print(f"[gpu] {name} two-level M^-1 r rel err {err:.2e} (gate {tol:.1e})", flush=True)
+        tol = orc.minv_gate(name, seed=3, eta=op_eta(name))
+        print(f"[gpu] {name} two-level M^-1 r rel err {err:.2e} (gate {tol:.1e}, FP64 condition "
+              f"{orc.minv_eps_sensitivity(name):.1e}, operator difference "
+              f"{op_eta(name) / np.finfo(float).eps:.1f} eps)", flush=True)
         assert err <= tol
         A, b, free, Ke = orc.system(name)
         u_ref, info = opcg.pcg(A, b[:, 0], g.apply, rtol=1e-12, maxit=2000)
