@@ -114,7 +114,7 @@ def cpu_baseline(config):
             "host": {"nproc": nproc, "cpu_model": _cpu_model()}}
 
 
-TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1901_05188_amd", "csrc", "precond.hip")
+TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1901_05188_amd", "csrc", "local_solve.hip")
 
 
 def traffic_file(workload, prec, threads):

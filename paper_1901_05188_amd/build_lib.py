@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgenpcg.so")
-SOURCES = ["fem.hip", "linalg.hip", "band.hip", "precond.hip", "geneo.hip", "coarse.hip", "multi.hip", "api.hip",
+SOURCES = ["fem.hip", "linalg.hip", "band.hip", "local_solve.hip", "precond.hip", "geneo.hip", "coarse.hip", "multi.hip", "api.hip",
            "serve.hip"]
 ARCH = os.environ.get("GENPCG_ARCH", "gfx950")
 

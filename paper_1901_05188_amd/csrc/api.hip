@@ -778,7 +778,16 @@ static int64_t estimate_footprint(const int ne[3], int nc, const gn_dd_opts* o, 
       add(3 * 256 * 8);
       add(4 * 8);
     } else {
+      // Z (Z^T in its upper tiles), the transposed diagonal tiles, the unit
+      // tables and row starts of the coarse products, their partial sums
       add(NBH * NBH * TILE2 * 8);
+      add(NBH * TILE2 * 8);
+      const int64_t uf = gnk::coarse_units(NBH, false), ub = gnk::coarse_units(NBH, true);
+      add(uf * (int64_t)sizeof(int4));
+      add(ub * (int64_t)sizeof(int4));
+      add((NBH + 1) * 4);
+      add((NBH + 1) * 4);
+      add(std::max(uf, ub) * TILE * 8);
     }
     for (int v = 0; v < 3; ++v) add(NBH * TILE * 8);
   }
@@ -1332,6 +1341,26 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
         if (hinfo) throw gn_error{GN_ERR_COARSE_SINGULAR, "coarse matrix not positive definite"};
         pc->d_Z = dalloc<double>(pc->owned, ahlen);
         gnk::tri_inv(pc->NBH, AH, DH, pc->d_Z, s);
+        // Z^T in the upper tiles and the work units of the coarse products
+        pc->d_Zdt = dalloc<double>(pc->owned, (size_t)pc->NBH * TILE2);
+        gnk::z_transpose(pc, s);
+        for (int upper = 0; upper < 2; ++upper) {
+          std::vector<int4> units;
+          std::vector<int> rowstart(pc->NBH + 1, 0);
+          for (int R = 0; R < pc->NBH; ++R) {
+            rowstart[R] = (int)units.size();
+            const int c0 = upper ? R : 0, c1 = upper ? pc->NBH : R + 1;
+            for (int c = c0; c < c1; c += gnk::COARSE_UNIT_TILES)
+              units.push_back(int4{R, c, std::min(c1, c + gnk::COARSE_UNIT_TILES), 0});
+          }
+          rowstart[pc->NBH] = (int)units.size();
+          if ((int64_t)units.size() != gnk::coarse_units(pc->NBH, upper != 0))
+            throw gn_error{GN_ERR_DEVICE, "coarse unit table size mismatch"};
+          (upper ? pc->n_cu_b : pc->n_cu_f) = (int)units.size();
+          (upper ? pc->d_cu_b : pc->d_cu_f) = upload(pc->owned, units.data(), units.size(), s);
+          (upper ? pc->d_rs_b : pc->d_rs_f) = upload(pc->owned, rowstart.data(), rowstart.size(), s);
+        }
+        pc->d_zpart = dalloc<double>(pc->owned, (size_t)std::max(pc->n_cu_f, pc->n_cu_b) * TILE);
       } else {
         // inexact coarse solve: A_H kept block-sparse (the symmetric closure of
         // the interacting pairs), the diagonal blocks inverted

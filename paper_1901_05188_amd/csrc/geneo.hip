@@ -401,12 +401,23 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
     }                                                                                          \
     geneo_lds_barrier();                                                                       \
   }
+  // Band tiles hold exact zeros outside the band (row r, column c with
+  // r - c > bw): a lane whose entry lies there reads the tile's entry (31, 0)
+  // (forward) or (0, 31) (backward), which is zero whenever any entry is, and
+  // tiles wholly before or after the matrix read the zero tile Z0, so cache
+  // lines holding nothing but zeros are not fetched; the products are unchanged.
+  const int bwp = sd.bwB;
+  const int lrow = rb + lr - lk;            // row minus column inside the tile, less 4 ks
   // ---- forward: Y_K = Dinv_K (V_K - sum_t L(K,t) Y_{K-w+t}) ----
-#define R2_FWD_TILE(K_, t_) (((t_) < w) ? Tb + ((int64_t)(K_) * W1 + (t_)) * TILE2 : Z0)
+  // tile t of row K is L(K, K - w + t); entry (i, c) lies outside the band when
+  // 32 (w - t) + i - c > bw
+#define R2_FWD_TILE(K_, t_) (((t_) < w && (K_) - w + (t_) >= 0) ? Tb + ((int64_t)(K_) * W1 + (t_)) * TILE2 : Z0)
 #define R2_LOAD_A_FWD(S_, K_, t_)                                                              \
   {                                                                                            \
     const double* tp = R2_FWD_TILE(K_, t_);                                                    \
-    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) a[S_][ks] = tp[(4 * ks + lk) * TILE + rb + lr]; \
+    const int lim = bwp - TILE * (w - (t_));                                                   \
+    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                           \
+      a[S_][ks] = tp[(lrow - 4 * ks > lim) ? TILE - 1 : (4 * ks + lk) * TILE + rb + lr];        \
   }
 #define R2_LOAD_DV_FWD(K_)                                                                     \
   {                                                                                            \
@@ -435,11 +446,15 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
   for (int e = threadIdx.x; e < ringlen; e += 256) ring[e] = 0.0;
   // ---- backward: X_K = Dinv_K^T (Y_K - sum_d L(K+d,K)^T X_{K+d}), d = t + 1 ----
   const double* TBb = TBk + sd.offTB * TILE2;
-#define R2_BWD_TILE(K_, t_) (((t_) < w) ? TBb + ((int64_t)(K_) * W1 + (t_)) * TILE2 : Z0)
+  // tile t of row K holds L(K + t + 1, K)^T: its entry (i, c) is
+  // L(K + t + 1, K)(c, i), outside the band when 32 (t + 1) + c - i > bw
+#define R2_BWD_TILE(K_, t_) (((t_) < w && (K_) + (t_) + 1 < NB) ? TBb + ((int64_t)(K_) * W1 + (t_)) * TILE2 : Z0)
 #define R2_LOAD_A_BWD(S_, K_, t_)                                                              \
   {                                                                                            \
     const double* tp = R2_BWD_TILE(K_, t_);                                                    \
-    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) a[S_][ks] = tp[(4 * ks + lk) * TILE + rb + lr]; \
+    const int lim = bwp - TILE * ((t_) + 1);                                                   \
+    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                           \
+      a[S_][ks] = tp[(4 * ks - lrow > lim) ? (TILE - 1) * TILE : (4 * ks + lk) * TILE + rb + lr]; \
   }
 #define R2_LOAD_DV_BWD(K_)                                                                     \
   {                                                                                            \

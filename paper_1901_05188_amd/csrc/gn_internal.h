@@ -256,8 +256,18 @@ struct gn_precond {
   double trsv_bytes_mc = 0.0;  // gather + banded solves of one 16-column batch
   double* d_tm = nullptr;      // local vectors of a batch: (offVI + row) * 16 + column
   double *d_gm = nullptr, *d_um = nullptr, *d_ym = nullptr;  // coarse vectors, column * NBH*TILE
-  double* d_Z = nullptr;     // L_H^-1 as dense tiles (NBH x NBH tiles, lower)
+  double* d_Z = nullptr;     // L_H^-1 as dense tiles (NBH x NBH tiles): Z(K,J) for J <= K;
+                             // the strictly upper tiles (J,K) hold Z(K,J)^T
+  double* d_Zdt = nullptr;   // Z(K,K)^T, one tile per K
   int NBH = 0;
+  // work units of the coarse products (one workgroup each): {row, first tile,
+  // last tile + 1, 0}, row by row; rowstart[R] = first unit of row R
+  int4* d_cu_f = nullptr;    // y = Z g: row K, tiles J in [0, K]
+  int4* d_cu_b = nullptr;    // y = Z^T u: row J, tiles K in [J, NBH)
+  int* d_rs_f = nullptr;
+  int* d_rs_b = nullptr;
+  int n_cu_f = 0, n_cu_b = 0;
+  double* d_zpart = nullptr; // 32 partial sums per unit
   // inexact coarse solve (coarse_solve = 1): A_H block-sparse by subdomain
   // pairs, the inverses of its diagonal blocks, and the inner CG state
   int coarse_solve = 0;
@@ -325,6 +335,15 @@ void local_solve_tune(const gn_problem* p, gn_precond* pc, hipStream_t s);
 void local_solve(const gn_problem* p, const gn_precond* pc, const double* r, const double* done,
                  hipStream_t s);
 void coarse_solve(const gn_precond* pc, const double* done, hipStream_t s);
+// tiles per work unit of the coarse products, and the units of an NB-tile-row factor
+constexpr int COARSE_UNIT_TILES = 64;
+inline int64_t coarse_units(int64_t NB, bool upper) {
+  int64_t n = 0;
+  for (int64_t R = 0; R < NB; ++R) n += ((upper ? NB - R : R + 1) + COARSE_UNIT_TILES - 1) / COARSE_UNIT_TILES;
+  return n;
+}
+// after tri_inv: Z^T into the upper tiles and d_Zdt (d_Zdt allocated)
+void z_transpose(gn_precond* pc, hipStream_t s);
 // inexact coarse solve: y = (CG on A_H, block-Jacobi) g for one column
 void coarse_cg(const gn_precond* pc, const double* g, double* y, const double* done, hipStream_t s);
 int coarse_cg_grid(const gn_precond* pc);
