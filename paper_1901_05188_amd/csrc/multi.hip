@@ -360,13 +360,15 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
   double dv[8], vv[4];
   gn_d4 acc[4];
 #define MC_ZERO4() _Pragma("unroll") for (int u = 0; u < 4; ++u) acc[u] = gn_d4{0, 0, 0, 0};
-  // forward tile of slot s at block row K: (K, t), t = kg + 4 s (zero tile if t >= w)
+  // forward tile of slot s at block row K: (K, t), t = kg + 4 s (the zero tile
+  // if t >= w, or if the tile lies before the first block row: its stored
+  // zeros are then not fetched)
 #define MC_LOAD_FWD(K_)                                                                         \
   {                                                                                             \
     const int KK = (K_);                                                                        \
     _Pragma("unroll") for (int s = 0; s < SPW; ++s) {                                           \
       const int t = kg + 4 * s;                                                                 \
-      const FT* tile = (t < w) ? Tb + ((int64_t)KK * W1 + t) * TILE2 : Z0;                      \
+      const FT* tile = (t < w && KK - w + t >= 0) ? Tb + ((int64_t)KK * W1 + t) * TILE2 : Z0;   \
       _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) av[s][ks] = tile[(4 * ks + lk) * TILE + rb + lr]; \
     }                                                                                           \
   }
@@ -438,7 +440,7 @@ __global__ __launch_bounds__(512) void k_band_solve_mc(const SubDesc* __restrict
     const int KK = (K_);                                                                        \
     _Pragma("unroll") for (int s = 0; s < SPW; ++s) {                                           \
       const int d = 1 + kg + 4 * s;                                                             \
-      const FT* tile = (d <= w) ? TBb + ((int64_t)KK * W1 + (d - 1)) * TILE2 : Z0;              \
+      const FT* tile = (d <= w && KK + d < NB) ? TBb + ((int64_t)KK * W1 + (d - 1)) * TILE2 : Z0; \
       _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) av[s][ks] = tile[(4 * ks + lk) * TILE + rb + lr]; \
     }                                                                                           \
   }

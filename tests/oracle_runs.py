@@ -30,15 +30,18 @@ CASES = {
 #               as the SPE10-shaped diffusion), pencil band 10 tiles;
 #  lam_wide12   local band 12 tiles (24 slots, as the ramped laminate), pencil
 #               band 13 tiles (an 18-slot ring of the eigen block solves);
-#  lam_wide17   local band 17 tiles: FP64 goes through the 16-column
-#               matrix-core sweep with one live column, FP32 through the
-#               1024-thread sweep (as the 12-ply laminate); compared one-level
-#               and with the zero-energy-mode coarse space (no dense eigensolve).
+#  lam_wide17   local band 17 tiles (34 slots of the 512-thread sweep;
+#               forced, the 16-column matrix-core kernel with one live column);
+#               compared one-level and with the zero-energy-mode coarse space
+#               (no dense eigensolve);
+#  lam_wide22   local band 22 tiles, the widest of the 12-ply laminate: the
+#               512-thread FP64 sweep at its 44-slot limit; one-level only.
 WIDE = {
     "diff_wide10": lambda: gen.small_case("diffusion", seed=31, ne=(32, 16, 16), nparts=(2, 1, 1), overlap=2,
                                           threshold=0.15, nev_max=16),
     "lam_wide12": lambda: gen.small_case("laminate", seed=32, nxy=(14, 13), n_ply=7, nparts=(2, 1, 1), nev=8),
     "lam_wide17": lambda: gen.small_case("laminate", seed=33, nxy=(14, 20), n_ply=11, nparts=(2, 1, 1), nev=8),
+    "lam_wide22": lambda: gen.small_case("laminate", seed=34, nxy=(22, 17), n_ply=9, nparts=(2, 1, 1), nev=8),
 }
 
 

@@ -5,9 +5,11 @@ the narrowest instantiations of the local-solve kernels.  These cases have
 subdomain boxes whose bands are as wide as those of the bench and
 configuration workloads (tests/oracle_runs.py, WIDE): 10 tiles (the sweep
 with 20 slots), 12 tiles (24 slots; pencil band 13, an 18-slot ring of the eigen
-block solves) and 17 tiles (the sweep with 40 slots per thread, or the
+block solves), 17 tiles (the sweep with 34 slots per thread, or the
 1024-thread shape, whichever the set-up's timing picks; and, forced, the
-16-column matrix-core kernel with one live column).  Each is compared with the
+16-column matrix-core kernel with one live column) and 22 tiles (the widest
+local band of the 12-ply laminate: the 512-thread FP64 sweep at its 44-slot
+limit, and the 1024-thread FP32 sweep).  Each is compared with the
 oracle as the small cases are: M^-1 r element-wise (one- and two-level), GenEO
 eigenvalues and counts, and the PCG solution at 1e-8 (1e-7 for FP32 local
 factors) after both sides converge to 1e-12.
@@ -58,7 +60,7 @@ def op_eta(name):
     return _ETA[name]
 
 
-@pytest.mark.parametrize("name", ["diff_wide10", "lam_wide12", "lam_wide17"])
+@pytest.mark.parametrize("name", ["diff_wide10", "lam_wide12", "lam_wide17", "lam_wide22"])
 def test_wide_band_operator_matches_oracle(name):
     """The assembled operators differ by rounding only: at most 32 eps in the
     normwise measure of oracle_runs.operator_eta."""
@@ -75,14 +77,20 @@ def _apply(pc, r):
 
 @pytest.mark.parametrize("name,prec,kernel", [("diff_wide10", 64, 0), ("diff_wide10", 32, 0), ("lam_wide12", 64, 0),
                                               ("lam_wide12", 32, 0), ("lam_wide17", 64, 0), ("lam_wide17", 32, 0),
-                                              ("lam_wide17", 64, 1), ("lam_wide17", 64, 2)])
+                                              ("lam_wide17", 64, 1), ("lam_wide17", 64, 2), ("lam_wide22", 64, 0),
+                                              ("lam_wide22", 64, 3), ("lam_wide22", 32, 4)])
 def test_wide_band_one_level_apply(name, prec, kernel):
     w = orc.workload(name)
     g = orc.geneo_run(name, coarse=False)
     print(f"[gpu] setup {name} one-level prec={prec} local_kernel={kernel}", flush=True)
     pc = _gp().Preconditioner.from_workload(problem(name), w, coarse=False, local_prec=prec, local_kernel=kernel)
     try:
-        print(f"[gpu] {name} band tiles {pc.report['band_tiles']}", flush=True)
+        print(f"[gpu] {name} band tiles {pc.report['band_tiles']}, {pc.report['local_threads']} threads per "
+              f"subdomain", flush=True)
+        if name == "lam_wide22":
+            assert pc.report["band_tiles"] == 22
+        if kernel in (3, 4):
+            assert pc.report["local_threads"] == (512 if kernel == 3 else 1024)
         r = np.random.default_rng(2).standard_normal(w.n_free)
         ref = g.apply_as1(r)
         err = np.linalg.norm(_apply(pc, r) - ref) / np.linalg.norm(ref)
