@@ -1586,8 +1586,14 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
       rl2 = maxw1 * TILE * rw2 + 32;
       lds2 = sizeof(double) * ((size_t)rl2 + (size_t)3 * TILE * 17);
     }
-    const int W2 = std::max(6, (maxw + 5) / 6 * 6);
-    if (lds2 <= 160 * 1024 && W2 <= 30 && pc->d_z0 && TB) {
+    // the smallest instantiated slot count W >= maxw (W / 2 a multiple of the
+    // prefetch depth P): slots past the band multiply zero tiles, so a W close
+    // to the band saves matrix-core work (the kernel keeps the units about two
+    // thirds busy at the c5 widths)
+    int W2 = 0;
+    for (int wc : {6, 12, 14, 16, 18, 20, 24, 30})
+      if (W2 == 0 && wc >= maxw) W2 = wc;
+    if (lds2 <= 160 * 1024 && W2 > 0 && pc->d_z0 && TB) {
 #define GN_R2(WV, PV, NV)                                                                             \
   do {                                                                                                \
     GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV, PV, NV>,                                 \
@@ -1603,7 +1609,10 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
       switch (W2) {
         case 6: GN_R2W(6, 3); break;
         case 12: GN_R2W(12, 6); break;
+        case 14: GN_R2W(14, 7); break;
+        case 16: GN_R2W(16, 4); break;
         case 18: GN_R2W(18, 3); break;
+        case 20: GN_R2W(20, 5); break;
         case 24: GN_R2W(24, 6); break;
         default: GN_R2W(30, 3); break;
       }
