@@ -1294,6 +1294,8 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     // ---- coarse basis, coarse matrix, coarse factor ------------------------
     if (pc->NH > 0) {
       int64_t phi = 0;
+      pc->max_m = 0;
+      for (int j = 0; j < n_sub; ++j) pc->max_m = std::max(pc->max_m, pc->sub[j].m);
       for (int j = 0; j < n_sub; ++j) {
         pc->sub[j].offPhi = phi;
         phi += (int64_t)pc->sub[j].nI * pc->sub[j].m;

@@ -1272,45 +1272,72 @@ __device__ inline void lds_tile(double* dst, const double* src) {
   }
 }
 
-__global__ __launch_bounds__(NT) void k_potrf_tile(int NB, int K, double* __restrict__ A,
+// a double from lane l of the wave (l uniform)
+__device__ inline double gn_readlane_d(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Cholesky factor L(K,K) of the diagonal tile and its inverse Dinv_K, one wave
+// in registers: lane r (and its mirror r + 32) holds row r of the tile, the
+// column of step k comes from lane k by readlane; then lane c forms column c of
+// the inverse by forward substitution over the factor's rows (from LDS).  A
+// non-positive pivot records its index (first one only) in *info and is
+// replaced by 1 so the factorization runs to the end.
+__global__ __launch_bounds__(64) void k_potrf_tile(int NB, int K, double* __restrict__ A,
                                                    double* __restrict__ Dinv, int* __restrict__ info) {
-  __shared__ double S[TILE * (TILE + 1)];
+  __shared__ double S[TILE][TILE + 1];   // S[row][column]
   double* tk = A + ((int64_t)K * NB + K) * TILE2;
-  lds_tile(S, tk);
+  const int lane = threadIdx.x;
+  for (int e = lane; e < TILE2; e += 64) S[e % TILE][e / TILE] = tk[e];
   __syncthreads();
+  const int r = lane & (TILE - 1);
+  double a[TILE];
+#pragma unroll
+  for (int c = 0; c < TILE; ++c) a[c] = S[r][c];
+  int fail = 0;
+#pragma unroll
   for (int k = 0; k < TILE; ++k) {
-    if (threadIdx.x == 0) {
-      double d = S[k * (TILE + 1) + k];
-      if (!(d > 0.0)) {
-        if (*info == 0) *info = K * TILE + k + 1;
-        d = 1.0;
-      }
-      S[k * (TILE + 1) + k] = sqrt(d);
+    double dkk = gn_readlane_d(a[k], k);
+    if (!(dkk > 0.0)) {
+      if (fail == 0) fail = K * TILE + k + 1;
+      dkk = 1.0;
     }
-    __syncthreads();
-    double piv = S[k * (TILE + 1) + k];
-    if (threadIdx.x > k && threadIdx.x < TILE) S[k * (TILE + 1) + threadIdx.x] /= piv;
-    __syncthreads();
-    for (int e = threadIdx.x; e < TILE2; e += NT) {
-      int rr = e % TILE, cc = e / TILE;
-      if (cc > k && rr >= cc) S[cc * (TILE + 1) + rr] -= S[k * (TILE + 1) + rr] * S[k * (TILE + 1) + cc];
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < TILE2; e += NT) {
-    int rr = e % TILE, cc = e / TILE;
-    tk[cc * TILE + rr] = (rr >= cc) ? S[cc * (TILE + 1) + rr] : 0.0;
-  }
-  if (threadIdx.x < TILE) {
-    int cc = threadIdx.x;
-    double* dk = Dinv + (int64_t)K * TILE2;
-    for (int r2 = 0; r2 < cc; ++r2) dk[cc * TILE + r2] = 0.0;
-    for (int r2 = cc; r2 < TILE; ++r2) {
-      double s = (r2 == cc) ? 1.0 : 0.0;
-      for (int k = cc; k < r2; ++k) s -= S[k * (TILE + 1) + r2] * dk[cc * TILE + k];
-      dk[cc * TILE + r2] = s / S[r2 * (TILE + 1) + r2];
+    const double piv = sqrt(dkk);
+    a[k] = r == k ? piv : (r > k ? a[k] / piv : a[k]);
+#pragma unroll
+    for (int c = k + 1; c < TILE; ++c) {
+      const double lck = gn_readlane_d(a[k], c);
+      if (r >= c) a[c] -= a[k] * lck;
     }
   }
+  if (lane == 0 && fail != 0 && *info == 0) *info = fail;
+  __syncthreads();
+  if (lane < TILE) {
+#pragma unroll
+    for (int c = 0; c < TILE; ++c) S[r][c] = c <= r ? a[c] : 0.0;
+  }
+  __syncthreads();
+  const int c = r;
+  double xc[TILE];
+#pragma unroll
+  for (int i = 0; i < TILE; ++i) {
+    double sum = i == c ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < i; ++k) sum -= S[i][k] * xc[k];
+    xc[i] = i >= c ? sum / S[i][i] : 0.0;
+  }
+  for (int e = lane; e < TILE2; e += 64) tk[e] = S[e % TILE][e / TILE];
+  __syncthreads();   // every lane has read the factor
+  if (lane < TILE) {
+#pragma unroll
+    for (int i = 0; i < TILE; ++i) S[i][c] = xc[i];
+  }
+  __syncthreads();
+  double* dk = Dinv + (int64_t)K * TILE2;
+  for (int e = lane; e < TILE2; e += 64) dk[e] = S[e % TILE][e / TILE];
 }
 
 // L(I,K) = A(I,K) Dinv_K^T for I = K+1+blockIdx.x
@@ -1411,22 +1438,12 @@ __device__ inline void tile_mma_acc(const double* __restrict__ xs, const double*
 }
 
 // A(I,J) -= sum_{k0 <= k < k1} L(I,k) L(J,k)^T over the tiles J0 <= J < J1,
-// J <= I < NB (one workgroup per tile; blockIdx.x runs down column J0, then
-// J0 + 1, ...: column J holds NB - J tiles)
+// J <= I < NB, J1 - J0 <= CPANEL (the updates inside a panel; one workgroup per
+// tile; blockIdx.x runs down column J0, then J0 + 1, ...: column J holds NB - J
+// tiles)
 __global__ __launch_bounds__(NT) void k_syrk_panel(int NB, int k0, int k1, int J0, int J1, double* __restrict__ A) {
   int idx = blockIdx.x, J = J0;
-  if (J1 - J0 > CPANEL) {
-    // many columns: invert the count c(J) = sum_{J0 <= J' < J} (NB - J') in closed form
-    const double b = 2.0 * (NB - J0) + 1.0;
-    int d = (int)((b - sqrt(b * b - 8.0 * idx)) * 0.5);
-    d = max(d, 0);
-    while (d > 0 && (int64_t)d * (2 * (NB - J0) - d + 1) / 2 > idx) --d;
-    while ((int64_t)(d + 1) * (2 * (NB - J0) - d) / 2 <= idx) ++d;
-    idx -= (int)((int64_t)d * (2 * (NB - J0) - d + 1) / 2);
-    J += d;
-  } else {
-    while (J < J1 && idx >= NB - J) idx -= NB - J, ++J;
-  }
+  while (J < J1 && idx >= NB - J) idx -= NB - J, ++J;   // at most CPANEL columns
   if (J >= J1) return;
   const int I = J + idx;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1442,22 +1459,79 @@ __global__ __launch_bounds__(NT) void k_syrk_panel(int NB, int k0, int k1, int J
     t[(qc * 16 + lr) * TILE + qr * 16 + 4 * i + lk] -= (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
 }
 
-// Z(I,J) += sum_{max(k0,J) <= k < k1} L(I,k) Z(k,J) for I in [I0, NB), J in [0, k1)
-// (blockIdx.x = J, blockIdx.y = I - I0)
-__global__ __launch_bounds__(NT) void k_trinv_panel(int NB, int k0, int k1, int I0, const double* __restrict__ L,
-                                                    double* __restrict__ Z) {
-  const int J = blockIdx.x, I = I0 + blockIdx.y;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int lr = lane & 15, lk = lane >> 4, qr = wid & 1, qc = wid >> 1;
-  gn_d4 acc[4];
+// Trailing updates in 2 x 2 blocks of tiles: each wave owns one whole output
+// tile (its four 16 x 16 quadrants), so a wave loads each operand tile once for
+// four quadrant products instead of once per quadrant, and the four waves of a
+// workgroup share their operand tiles through the L1 cache.
+// acc[r][c][.] += X(r quadrant rows, :) Y(:, c quadrant columns) over one tile pair
+template <bool TRANSY>
+__device__ inline void tile_mma_full_acc(const double* __restrict__ xs, const double* __restrict__ ys, int lr,
+                                         int lk, gn_d4 acc[2][2][2]) {
+  double av[2][8], bv[2][8];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) acc[u] = gn_d4{0, 0, 0, 0};
+  for (int ks = 0; ks < 8; ++ks) {
+    const int k = 4 * ks + lk;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      av[r][ks] = xs[k * TILE + r * 16 + lr];
+      bv[r][ks] = TRANSY ? ys[k * TILE + r * 16 + lr] : ys[(r * 16 + lr) * TILE + k];
+    }
+  }
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        acc[r][c][ks & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][ks], bv[c][ks], acc[r][c][ks & 1], 0, 0, 0);
+}
+
+// the wave's output tile t (column-major) += sgn * acc
+__device__ inline void tile_store_acc(double* __restrict__ t, double sgn, int lr, int lk, gn_d4 acc[2][2][2]) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        t[(c * 16 + lr) * TILE + r * 16 + 4 * i + lk] += sgn * (acc[r][c][0][i] + acc[r][c][1][i]);
+}
+
+// A(I,J) -= sum_{k0 <= k < k1} L(I,k) L(J,k)^T for J0 <= J <= I < NB: block
+// (blockIdx.x, blockIdx.y) covers I = J0 + 2 bx + (0, 1), J = J0 + 2 by + (0, 1)
+// (blocks wholly above the diagonal return at once; wave = (I offset, J offset))
+__global__ __launch_bounds__(NT) void k_syrk_panel2(int NB, int k0, int k1, int J0, double* __restrict__ A) {
+  if (blockIdx.x < blockIdx.y) return;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int I = J0 + 2 * (int)blockIdx.x + (wv & 1), J = J0 + 2 * (int)blockIdx.y + (wv >> 1);
+  if (I >= NB || J > I) return;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  gn_d4 acc[2][2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[r][c][0] = acc[r][c][1] = gn_d4{0, 0, 0, 0};
+  for (int k = k0; k < k1; ++k)
+    tile_mma_full_acc<true>(A + ((int64_t)I * NB + k) * TILE2, A + ((int64_t)J * NB + k) * TILE2, lr, lk, acc);
+  tile_store_acc(A + ((int64_t)I * NB + J) * TILE2, -1.0, lr, lk, acc);
+}
+
+// Z(I,J) += sum_{max(k0,J) <= k < k1} L(I,k) Z(k,J) for I in [I0, NB), J in [0, k1):
+// block (blockIdx.x, blockIdx.y) covers J = 2 bx + (0, 1), I = I0 + 2 by + (0, 1)
+__global__ __launch_bounds__(NT) void k_trinv_panel2(int NB, int k0, int k1, int I0, const double* __restrict__ L,
+                                                     double* __restrict__ Z) {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int J = 2 * (int)blockIdx.x + (wv & 1), I = I0 + 2 * (int)blockIdx.y + (wv >> 1);
+  if (J >= k1 || I >= NB) return;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  gn_d4 acc[2][2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[r][c][0] = acc[r][c][1] = gn_d4{0, 0, 0, 0};
   for (int k = max(k0, J); k < k1; ++k)
-    tile_mma_acc<false>(L + ((int64_t)I * NB + k) * TILE2, Z + ((int64_t)k * NB + J) * TILE2, qr, qc, lr, lk, acc);
-  double* zt = Z + ((int64_t)I * NB + J) * TILE2;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    zt[(qc * 16 + lr) * TILE + qr * 16 + 4 * i + lk] += (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
+    tile_mma_full_acc<false>(L + ((int64_t)I * NB + k) * TILE2, Z + ((int64_t)k * NB + J) * TILE2, lr, lk, acc);
+  tile_store_acc(Z + ((int64_t)I * NB + J) * TILE2, 1.0, lr, lk, acc);
 }
 
 
@@ -1736,13 +1810,13 @@ static int64_t trapezoid_tiles(int NB, int J0, int J1) {
 
 // Right-looking tiled Cholesky in panels of CPANEL tile columns: inside a
 // panel each column is factored (k_potrf_tile, k_trsm_tile) and updates the
-// panel's later columns; then one k_syrk_panel launch applies the panel to
+// panel's later columns; then one k_syrk_panel2 launch applies the panel to
 // the trailing matrix.
 void dense_chol(int NB, double* A, double* Dinv, int* info, hipStream_t s) {
   for (int K0 = 0; K0 < NB; K0 += CPANEL) {
     const int K1 = std::min(NB, K0 + CPANEL);
     for (int K = K0; K < K1; ++K) {
-      hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(NT), 0, s, NB, K, A, Dinv, info);
+      hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(64), 0, s, NB, K, A, Dinv, info);
       GN_CHECK_LAUNCH();
       const int m = NB - K - 1;
       if (m > 0) {
@@ -1756,8 +1830,8 @@ void dense_chol(int NB, double* A, double* Dinv, int* info, hipStream_t s) {
       }
     }
     if (K1 < NB) {
-      const int64_t nt = trapezoid_tiles(NB, K1, NB);
-      hipLaunchKernelGGL(k_syrk_panel, dim3((unsigned)nt), dim3(NT), 0, s, NB, K0, K1, K1, NB, A);
+      const unsigned nb2 = (unsigned)((NB - K1 + 1) / 2);
+      hipLaunchKernelGGL(k_syrk_panel2, dim3(nb2, nb2), dim3(NT), 0, s, NB, K0, K1, K1, A);
       GN_CHECK_LAUNCH();
     }
   }
@@ -1765,7 +1839,7 @@ void dense_chol(int NB, double* A, double* Dinv, int* info, hipStream_t s) {
 
 // Z = L^-1 by block rows in panels of CPANEL: each row of the panel is
 // finished (k_trinv_row) and passed to the panel's later rows
-// (k_trinv_update restricted to them); then one k_trinv_panel launch adds the
+// (k_trinv_update restricted to them); then one k_trinv_panel2 launch adds the
 // panel's rows to the running sums of every later row.
 void tri_inv(int NB, const double* L, const double* Dinv, double* Z, hipStream_t s) {
   GN_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)NB * NB * TILE2, s));
@@ -1780,7 +1854,8 @@ void tri_inv(int NB, const double* L, const double* Dinv, double* Z, hipStream_t
       }
     }
     if (K1 < NB) {
-      hipLaunchKernelGGL(k_trinv_panel, dim3(K1, NB - K1), dim3(NT), 0, s, NB, K0, K1, K1, L, Z);
+      hipLaunchKernelGGL(k_trinv_panel2, dim3((unsigned)((K1 + 1) / 2), (unsigned)((NB - K1 + 1) / 2)), dim3(NT), 0,
+                         s, NB, K0, K1, K1, L, Z);
       GN_CHECK_LAUNCH();
     }
   }

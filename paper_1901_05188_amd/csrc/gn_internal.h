@@ -260,6 +260,7 @@ struct gn_precond {
                              // the strictly upper tiles (J,K) hold Z(K,J)^T
   double* d_Zdt = nullptr;   // Z(K,K)^T, one tile per K
   int NBH = 0;
+  int max_m = 0;             // largest m_j (rows of Phi_j hold m_j coefficients)
   // work units of the coarse products (one workgroup each): {row, first tile,
   // last tile + 1, 0}, row by row; rowstart[R] = first unit of row R
   int4* d_cu_f = nullptr;    // y = Z g: row K, tiles J in [0, K]

@@ -731,7 +731,9 @@ void precond_mc(const gn_problem* p, const gn_precond* pc, const double* r, doub
   do {                                         \
     if (spw <= 1) GN_MC(FT, 1);                \
     else if (spw <= 2) GN_MC(FT, 2);           \
+    else if (spw <= 3) GN_MC(FT, 3);           \
     else if (spw <= 4) GN_MC(FT, 4);           \
+    else if (spw <= 5) GN_MC(FT, 5);           \
     else if (spw <= 6) GN_MC(FT, 6);           \
     else if (spw <= 8) GN_MC(FT, 8);           \
     else throw gn_error{GN_ERR_ARG, "local band wider than 32 tiles"}; \

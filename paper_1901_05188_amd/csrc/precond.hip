@@ -142,32 +142,36 @@ __global__ __launch_bounds__(NT) void k_prolong(const SubDesc* __restrict__ subs
 // the rows of Phi_j contiguous), ahead of the gather, which then reads t_j only:
 // the same sum per (row, subdomain) in the same order as forming it inside the
 // gather, streamed over Phi instead of gathered node by node.
-__global__ __launch_bounds__(NT) void k_phi_add(const SubDesc* __restrict__ subs, const double* __restrict__ Phi,
-                                                const double* __restrict__ y, double* __restrict__ tvec,
-                                                const double* __restrict__ done) {
+// t_j += Phi_j y_j, one wave per 64 rows of Phi_j.  The wave's rows are one
+// contiguous block of 64 m doubles: it is read with consecutive lanes on
+// consecutive doubles into LDS (rows padded to m + 1 doubles), then each lane
+// forms its row's sum in the order k = 0 .. m - 1 from LDS.  (Loading the rows
+// lane by lane had each load instruction touch 64 addresses m doubles apart.)
+constexpr int PHI_ROWS = 64;
+__global__ __launch_bounds__(PHI_ROWS) void k_phi_add(const SubDesc* __restrict__ subs,
+                                                      const double* __restrict__ Phi,
+                                                      const double* __restrict__ y, double* __restrict__ tvec,
+                                                      const double* __restrict__ done) {
+  extern __shared__ double sph[];   // PHI_ROWS x (m + 1)
   if (done && *done != 0.0) return;
   const SubDesc& sd = subs[blockIdx.y];
-  const int row = blockIdx.x * NT + threadIdx.x;
   const int m = sd.m;
-  if (m == 0 || row >= sd.nI) return;
-  const double* ph = Phi + sd.offPhi + (int64_t)row * m;
-  const double* yy = y + sd.coff;
-  double v = tvec[sd.offVI + row];
-  // eight coefficients of the row in flight at once (indices clamped into the
-  // row), then the products in order k = 0 .. m - 1
-  for (int k0 = 0; k0 < m; k0 += 8) {
-    double p[8], q[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int k = min(k0 + u, m - 1);
-      p[u] = ph[k];
-      q[u] = yy[k];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (k0 + u < m) v += p[u] * q[u];
+  const int r0 = blockIdx.x * PHI_ROWS;
+  if (m == 0 || r0 >= sd.nI) return;
+  const int nr = min(PHI_ROWS, sd.nI - r0);
+  const double* ph = Phi + sd.offPhi + (int64_t)r0 * m;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < nr * m; e += PHI_ROWS) {
+    const int r = e / m, k = e - r * m;
+    sph[r * (m + 1) + k] = ph[e];
   }
-  tvec[sd.offVI + row] = v;
+  __syncthreads();
+  if (lane >= nr) return;
+  const double* yy = y + sd.coff;
+  const double* mine = sph + lane * (m + 1);
+  double v = tvec[sd.offVI + r0 + lane];
+  for (int k = 0; k < m; ++k) v += mine[k] * yy[k];
+  tvec[sd.offVI + r0 + lane] = v;
 }
 
 }  // namespace
@@ -207,8 +211,9 @@ void prolong(const gn_problem* p, const gn_precond* pc, const double* r, double*
   PartAxes pa{pc->d_cnt[0], pc->d_cnt[1], pc->d_cnt[2], pc->d_plo[0], pc->d_plo[1], pc->d_plo[2]};
   GnProfScope prof(PROF_PROLONG, pc->prolong_bytes, s);
   if (pc->NH > 0) {
-    hipLaunchKernelGGL(k_phi_add, dim3((unsigned)((pc->maxNBI * TILE + NT - 1) / NT), (unsigned)pc->n_sub), dim3(NT),
-                       0, s, pc->d_sub, pc->d_Phi, pc->d_y, pc->d_t, done);
+    hipLaunchKernelGGL(k_phi_add, dim3((unsigned)((pc->maxNBI * TILE + PHI_ROWS - 1) / PHI_ROWS), (unsigned)pc->n_sub),
+                       dim3(PHI_ROWS), sizeof(double) * PHI_ROWS * (pc->max_m + 1), s, pc->d_sub, pc->d_Phi,
+                       pc->d_y, pc->d_t, done);
     GN_CHECK_LAUNCH();
   }
   const double* Phi = nullptr;   // folded into the local vectors above
