@@ -149,7 +149,8 @@ __global__ __launch_bounds__(NT) void k_extract_p(const SubDesc* __restrict__ su
 // component) of one BCW-column chunk. Consecutive nodes lie along the fastest
 // local axis a0 (the box's shortest), where the neighbours of R nodes are R + 2
 // consecutive rows: each of the nine neighbour lines (offsets along the two
-// other axes) costs R + 2 row loads instead of 3 R.
+// other axes) costs R + 2 row loads instead of 3 R.  Launched for scalar
+// problems; vector problems use k_bapply_node below.
 constexpr int BCW = 4;
 template <int NC>
 constexpr int bapply_rows() { return NC == 1 ? 4 : 2; }
@@ -268,6 +269,100 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
 #pragma unroll
       for (int q = 0; q < BCW; ++q)
         if (col0 + q < b) out[sd.offVB * b + (int64_t)row * b + col0 + q] = acc[i][q];
+  }
+}
+
+// out = B V for vector problems: a thread computes all NC component rows of one
+// node for one BCW-column chunk, so each neighbour value it loads from V feeds
+// NC rows (the one-component layout above loads every neighbour value once per
+// component).  Coefficients come straight from the node-ELL planes (the chunk
+// lanes of a node read the same addresses; staging them in LDS instead measured
+// slower, at the lower occupancy it allows); a line whose coefficients are zero
+// on every lane of the wave loads no V.  Every output sums over the same
+// sequence (line, dx, c2) as the one-component kernel.
+template <int NC>
+__global__ __launch_bounds__(NT) void k_bapply_node(const SubDesc* __restrict__ subs, const double* __restrict__ BE,
+                                                    int b, const double* __restrict__ V, double* __restrict__ out,
+                                                    int gx, int ntot) {
+  const int per = (ntot + 7) / 8;
+  const int lin = blockIdx.x;
+  const int item = (lin % 8) * per + lin / 8;
+  if (item >= ntot) return;
+  const int bx = item % gx, by = item / gx;
+  const SubDesc& sd = subs[by];
+  const int npad = sd.NBB * TILE;
+  const int nchunk = (b + BCW - 1) / BCW;
+  const int tid = bx * NT + threadIdx.x;
+  const int col0 = (tid % nchunk) * BCW;
+  const int ln = tid / nchunk;
+  if (ln * NC >= npad) return;
+  const double* Vb = V + sd.offVB * b;
+  const double* base = BE + sd.offVB * (27 * NC);
+  int st[3];
+  st[sd.permB[0]] = 1;
+  st[sd.permB[1]] = sd.bn[sd.permB[0]];
+  st[sd.permB[2]] = sd.bn[sd.permB[0]] * sd.bn[sd.permB[1]];
+  const int nmax = sd.nB - 1;
+  double acc[NC][BCW];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int q = 0; q < BCW; ++q) acc[c][q] = 0.0;
+  const int a0 = sd.permB[0];
+  const int ax1 = a0 == 0 ? 1 : 0, ax2 = a0 == 2 ? 1 : 2;
+  const int s0 = a0 == 0 ? 1 : (a0 == 1 ? 3 : 9);
+  const int s1 = ax1 == 0 ? 1 : 3, s2 = ax2 == 1 ? 3 : 9;
+  for (int yz = 0; yz < 9; ++yz) {
+    const int o1 = yz % 3, o2 = yz / 3;
+    const int dn = (o1 - 1) * st[ax1] + (o2 - 1) * st[ax2];
+    const int dl = o1 * s1 + o2 * s2;
+    double bv[3][NC][NC];
+    bool nz = false;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int row = ln * NC + c;
+      const bool rin = row < npad;
+      const int rowc = rin ? row : npad - 1;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2) {
+          const double t = base[(int64_t)((dl + dx * s0) * NC + c2) * npad + rowc];
+          bv[dx][c][c2] = rin ? t : 0.0;
+          nz |= bv[dx][c][c2] != 0.0;
+        }
+    }
+    if (!__any(nz)) continue;
+    // nodes ln - 1, ln, ln + 1 of this line (clamped into the box: their
+    // coefficients are zero where the neighbour lies outside it)
+    double v[3][NC][BCW];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int c2 = 0; c2 < NC; ++c2) {
+        const int r2 = min(max((ln - 1 + j + dn) * NC + c2, 0), nmax);
+        // a chunk may run up to BCW - 1 columns past the row end into the next
+        // row or the 64-double tail of the buffer: loads stay in bounds, stores are masked
+        const double* vr = Vb + (int64_t)r2 * b + col0;
+#pragma unroll
+        for (int q = 0; q < BCW; ++q) v[j][c2][q] = vr[q];
+      }
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2)
+#pragma unroll
+          for (int q = 0; q < BCW; ++q) acc[c][q] += bv[dx][c][c2] * v[dx][c2][q];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int row = ln * NC + c;
+    if (row < npad)
+#pragma unroll
+      for (int q = 0; q < BCW; ++q)
+        if (col0 + q < b) out[sd.offVB * b + (int64_t)row * b + col0 + q] = acc[c][q];
   }
 }
 
@@ -1617,26 +1712,28 @@ void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int
                 const double* V, double* out, hipStream_t s) {
   const int nchunk = (b + BCW - 1) / BCW;
   const int nc = p->nc;
-  const int R = nc == 3 ? bapply_rows<3>() : bapply_rows<1>();
-  // threads per subdomain: node groups of R x components x column chunks
-  const int64_t nodes = (maxNBB * TILE + nc - 1) / nc;
-  const int gx = (int)((((nodes + R - 1) / R) * nc * nchunk + NT - 1) / NT);
+  if (nc == 3) {
+    // one thread per node and column chunk, all three component rows
+    const int64_t nodes = (maxNBB * TILE + 2) / 3;
+    const int gx = (int)((nodes * nchunk + NT - 1) / NT);
+    const int ntot = gx * pc->n_sub;
+    hipLaunchKernelGGL((k_bapply_node<3>), dim3((unsigned)(8 * ((ntot + 7) / 8))), dim3(NT), 0, s, pc->d_sub, BE,
+                       b, V, out, gx, ntot);
+    GN_CHECK_LAUNCH();
+    return;
+  }
+  // scalar problems: threads per subdomain = node groups of R x column chunks
+  constexpr int R = bapply_rows<1>();
+  const int64_t nodes = maxNBB * TILE;
+  const int gx = (int)((((nodes + R - 1) / R) * nchunk + NT - 1) / NT);
   const int ntot = gx * pc->n_sub;
   dim3 grid((unsigned)(8 * ((ntot + 7) / 8)));
-  // coefficient rows in LDS when they fit in 48 KB (b >= 17 scalar, b >= 29 elasticity)
-  const size_t lds = sizeof(double) * 27 * nc * (nc == 3 ? bapply_span<3>(nchunk) : bapply_span<1>(nchunk));
-  const bool in_lds = lds <= 48 * 1024;
-  if (nc == 3) {
-    if (in_lds)
-      hipLaunchKernelGGL((k_bapply<3, true>), grid, dim3(NT), lds, s, pc->d_sub, BE, b, V, out, gx, ntot);
-    else
-      hipLaunchKernelGGL((k_bapply<3, false>), grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out, gx, ntot);
-  } else {
-    if (in_lds)
-      hipLaunchKernelGGL((k_bapply<1, true>), grid, dim3(NT), lds, s, pc->d_sub, BE, b, V, out, gx, ntot);
-    else
-      hipLaunchKernelGGL((k_bapply<1, false>), grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out, gx, ntot);
-  }
+  // coefficient rows in LDS when they fit in 48 KB (b >= 17)
+  const size_t lds = sizeof(double) * 27 * bapply_span<1>(nchunk);
+  if (lds <= 48 * 1024)
+    hipLaunchKernelGGL((k_bapply<1, true>), grid, dim3(NT), lds, s, pc->d_sub, BE, b, V, out, gx, ntot);
+  else
+    hipLaunchKernelGGL((k_bapply<1, false>), grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out, gx, ntot);
   GN_CHECK_LAUNCH();
 }
 
