@@ -155,40 +155,51 @@ __global__ void k_material(int n_elem, const double* mats, const int* emat, cons
     for (int j = 0; j < 6; ++j) o[i * 6 + j] = 0.5 * (C[i][j] + C[j][i]);
 }
 
-// one thread per (element, row i) of the 24x24 element stiffness
-__global__ void k_ke_elastic(Geo g, int nex, int ney, int n_elem, const double* Cm, double* Ke) {
+// one thread per (element, row i) of the 24x24 element stiffness.  Row i =
+// 3 a_i + c_i of B^T C B det J w needs only the three rows of C that meet the
+// nonzero strain entries of column i of B: (c_i, 4 or 3, 5 or 4), scaled by the
+// gradient components (x,z,y), (y,z,x) or (z,y,x) of node a_i.  Every private
+// array is indexed by compile-time constants (the node a_i and component c_i
+// are picked by selects), so nothing spills to scratch memory.
+__global__ __launch_bounds__(128) void k_ke_elastic(Geo g, int nex, int ney, int n_elem, const double* Cm,
+                                                    double* Ke) {
   int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (int64_t)n_elem * 24) return;
   int e = (int)(tid / 24), i = (int)(tid % 24);
   int ex = e % nex, ey = (e / nex) % ney, ez = e / (nex * ney);
   double X[8][3];
   elem_coords(g, ex, ey, ez, X);
-  double C[6][6];
+  const int ai = i / 3, ci = i % 3;
+  const int r1 = ci == 0 ? 4 : 3, r2 = ci == 2 ? 4 : 5;
   const double* cp = Cm + (int64_t)e * 36;
-  for (int r = 0; r < 6; ++r)
-    for (int s2 = 0; s2 < 6; ++s2) C[r][s2] = cp[r * 6 + s2];
+  double crow[3][6];
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    crow[0][b] = cp[ci * 6 + b];
+    crow[1][b] = cp[r1 * 6 + b];
+    crow[2][b] = cp[r2 * 6 + b];
+  }
   double acc[24];
 #pragma unroll
   for (int k = 0; k < 24; ++k) acc[k] = 0.0;
   const double gp = 0.57735026918962576451;  // 1/sqrt(3)
-  int ai = i / 3, ci = i % 3;
   for (int q = 0; q < 8; ++q) {
     double G[8][3], N[8];
     double det = grad_at(X, (q & 1) ? gp : -gp, ((q >> 1) & 1) ? gp : -gp,
                          ((q >> 2) & 1) ? gp : -gp, G, N);
-    double bi[6] = {0, 0, 0, 0, 0, 0};
-    double gx = G[ai][0], gy = G[ai][1], gz = G[ai][2];
-    if (ci == 0) { bi[0] = gx; bi[4] = gz; bi[5] = gy; }
-    else if (ci == 1) { bi[1] = gy; bi[3] = gz; bi[5] = gx; }
-    else { bi[2] = gz; bi[3] = gy; bi[4] = gx; }
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      gx = a == ai ? G[a][0] : gx;
+      gy = a == ai ? G[a][1] : gy;
+      gz = a == ai ? G[a][2] : gz;
+    }
+    const double g0 = ci == 0 ? gx : (ci == 1 ? gy : gz);
+    const double g1 = ci == 2 ? gy : gz;
+    const double g2 = ci == 0 ? gy : gx;
     double v[6];
 #pragma unroll
-    for (int b = 0; b < 6; ++b) {
-      double s2 = 0.0;
-#pragma unroll
-      for (int r = 0; r < 6; ++r) s2 += bi[r] * C[r][b];
-      v[b] = s2 * det;
-    }
+    for (int b = 0; b < 6; ++b) v[b] = (g0 * crow[0][b] + g1 * crow[1][b] + g2 * crow[2][b]) * det;
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       double hx = G[a][0], hy = G[a][1], hz = G[a][2];
@@ -202,7 +213,8 @@ __global__ void k_ke_elastic(Geo g, int nex, int ney, int n_elem, const double* 
   for (int k = 0; k < 24; ++k) o[k] = acc[k];
 }
 
-__global__ void k_ke_scalar(Geo g, int nex, int ney, int n_elem, const double* kel, double* Ke) {
+__global__ __launch_bounds__(128) void k_ke_scalar(Geo g, int nex, int ney, int n_elem, const double* kel,
+                                                   double* Ke) {
   int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (int64_t)n_elem * 8) return;
   int e = (int)(tid / 8), i = (int)(tid % 8);
@@ -217,9 +229,15 @@ __global__ void k_ke_scalar(Geo g, int nex, int ney, int n_elem, const double* k
     double G[8][3], N[8];
     double det = grad_at(X, (q & 1) ? gp : -gp, ((q >> 1) & 1) ? gp : -gp,
                          ((q >> 2) & 1) ? gp : -gp, G, N);
+    double gx = 0.0, gy = 0.0, gz = 0.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      acc[k] += (G[i][0] * G[k][0] + G[i][1] * G[k][1] + G[i][2] * G[k][2]) * det;
+    for (int a = 0; a < 8; ++a) {
+      gx = a == i ? G[a][0] : gx;
+      gy = a == i ? G[a][1] : gy;
+      gz = a == i ? G[a][2] : gz;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] += (gx * G[k][0] + gy * G[k][1] + gz * G[k][2]) * det;
   }
   double ke = kel[e];
   double* o = Ke + (int64_t)e * 64 + i * 8;

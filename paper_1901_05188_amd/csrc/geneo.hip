@@ -1099,61 +1099,78 @@ __global__ __launch_bounds__(NT) void k_zem_modes(const SubDesc* __restrict__ su
 // that also lie in another subdomain.  Every term is an element energy
 // (non-negative up to rounding), so the quotient keeps the digits that
 // 1/nu - s cancels when lambda is far below the shift.  Workgroup (j, chunk of
-// 16 columns): lane c % 16 of the column chunk, 16 element lanes striding the
-// elements of the box; the partial energies are added in a fixed order.
+// 32 columns): the element matrices of RQ_EL elements at a time are staged in
+// LDS (each read from memory once), lane c % 32 takes column c of the chunk and
+// lane group c / 32 one of the staged elements; the partial energies are added
+// in a fixed order.
+constexpr int RQ_EL = NT / 32;
 template <int NC>
 __global__ __launch_bounds__(NT) void k_eig_rq(const SubDesc* __restrict__ subs, int nex, int ney,
                                                const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
                                                PouDev pa, int b, const double* __restrict__ V,
                                                double* __restrict__ lam) {
   constexpr int ND = 8 * NC;
-  __shared__ double sa[16][17], sb[16][17];
+  __shared__ double sK[RQ_EL][ND * ND];
+  __shared__ double sa[RQ_EL][33], sb[RQ_EL][33];
   const SubDesc& sd = subs[blockIdx.x];
-  const int cl = threadIdx.x & 15, el = threadIdx.x >> 4;
-  const int col = blockIdx.y * 16 + cl;
+  const int cl = threadIdx.x & 31, el = threadIdx.x >> 5;
+  const int col = blockIdx.y * 32 + cl;
+  const bool cok = col < b;
   const int NX = nex + 1, NY = ney + 1;
   const int n0 = sd.ehi[0] - sd.elo[0], n1 = sd.ehi[1] - sd.elo[1], n2 = sd.ehi[2] - sd.elo[2];
   const int nel = n0 * n1 * n2;
+  const double* Vb = V + sd.offVB * b + (cok ? col : 0);
   double ea = 0.0, eb = 0.0;
-  if (col < b) {
-    const double* Vb = V + sd.offVB * b + col;
-    for (int t = el; t < nel; t += 16) {
-      const int ex = sd.elo[0] + t % n0, ey = sd.elo[1] + (t / n0) % n1, ez = sd.elo[2] + t / (n0 * n1);
-      double pv[ND], xv[ND];
-#pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const int g0 = ex + (a & 1), g1 = ey + ((a >> 1) & 1), g2 = ez + (a >> 2);
-        const int rb = box_local_node(sd.blo, sd.bn, sd.permB, g0, g1, g2) * NC;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          pv[a * NC + c] = Vb[(int64_t)(rb + c) * b];
-          xv[a * NC + c] = pou_x(sd, pa, dir, NX, NY, NC, g0, g1, g2, c) * pv[a * NC + c];
-        }
+  for (int t0 = 0; t0 < nel; t0 += RQ_EL) {
+    __syncthreads();   // the previous batch's matrices are no longer read
+    for (int f = threadIdx.x; f < RQ_EL * ND * ND; f += NT) {
+      const int q = f / (ND * ND), t = t0 + q;
+      double k = 0.0;
+      if (t < nel) {
+        const int ex = sd.elo[0] + t % n0, ey = sd.elo[1] + (t / n0) % n1, ez = sd.elo[2] + t / (n0 * n1);
+        k = Ke[(ex + (int64_t)nex * (ey + (int64_t)ney * ez)) * (ND * ND) + f % (ND * ND)];
       }
-      const bool ov = pou_overlap_elem(pa, ex, ey, ez);
-      const double* K = Ke + (ex + (int64_t)nex * (ey + (int64_t)ney * ez)) * (ND * ND);
-      double sA = 0.0, sB = 0.0;
-      for (int i = 0; i < ND; ++i) {
-        double kp = 0.0, kx = 0.0;
-#pragma unroll
-        for (int j = 0; j < ND; ++j) {
-          const double k = K[i * ND + j];
-          kp += k * pv[j];
-          kx += k * xv[j];
-        }
-        sA += pv[i] * kp;
-        sB += xv[i] * kx;
-      }
-      ea += sA;
-      if (ov) eb += sB;
+      sK[q][f % (ND * ND)] = k;
     }
+    __syncthreads();
+    const int t = t0 + el;
+    if (t >= nel || !cok) continue;
+    const int ex = sd.elo[0] + t % n0, ey = sd.elo[1] + (t / n0) % n1, ez = sd.elo[2] + t / (n0 * n1);
+    double pv[ND], xv[ND];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int g0 = ex + (a & 1), g1 = ey + ((a >> 1) & 1), g2 = ez + (a >> 2);
+      const int rb = box_local_node(sd.blo, sd.bn, sd.permB, g0, g1, g2) * NC;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        pv[a * NC + c] = Vb[(int64_t)(rb + c) * b];
+        xv[a * NC + c] = pou_x(sd, pa, dir, NX, NY, NC, g0, g1, g2, c) * pv[a * NC + c];
+      }
+    }
+    const bool ov = pou_overlap_elem(pa, ex, ey, ez);
+    const double* K = sK[el];
+    double sA = 0.0, sB = 0.0;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      double kp = 0.0, kx = 0.0;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        const double k = K[i * ND + j];
+        kp += k * pv[j];
+        kx += k * xv[j];
+      }
+      sA += pv[i] * kp;
+      sB += xv[i] * kx;
+    }
+    ea += sA;
+    if (ov) eb += sB;
   }
   sa[el][cl] = ea;
   sb[el][cl] = eb;
   __syncthreads();
-  if (el == 0 && col < b) {
+  if (el == 0 && cok) {
     double ta = 0.0, tb = 0.0;
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < RQ_EL; ++q) {
       ta += sa[q][cl];
       tb += sb[q][cl];
     }
@@ -1643,7 +1660,7 @@ void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s
 }
 
 void eig_rq(const gn_problem* p, const gn_precond* pc, int b, const double* V, double* lam, hipStream_t s) {
-  dim3 grid((unsigned)pc->n_sub, (unsigned)((b + 15) / 16));
+  dim3 grid((unsigned)pc->n_sub, (unsigned)((b + 31) / 32));
   if (p->nc == 3)
     hipLaunchKernelGGL(k_eig_rq<3>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke, p->d_dir,
                        pou_axes(pc), b, V, lam);
