@@ -645,6 +645,7 @@ static DdPlan plan_decomposition(const int ne_[3], int nc, const gn_dd_opts* o) 
         const int j = pp + o->nparts[0] * (q + o->nparts[1] * r);
         SubDesc& sd = pl.sub[j];
         std::memset(&sd, 0, sizeof(sd));
+        sd.id = j;
         const int idx[3] = {pp, q, r};
         for (int a = 0; a < 3; ++a) {
           sd.elo[a] = pl.eR0[a][idx[a]];
@@ -1061,6 +1062,16 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
       std::vector<double> h_coef((size_t)n_sub * ncoef, 0.0);
       std::vector<int> solves_hist;
       int solves = 0;
+      // Subdomains whose wanted pairs have all converged are locked: the
+      // iteration's kernels skip them (h_act[j] = 0 on the host, d_act on the
+      // device), so their Ritz pairs stay those that passed the test, and the
+      // last iterations cost only what the slowest subdomains need.  Their
+      // residual figures and guard-band test are kept from that check.
+      std::vector<int> h_act(n_sub, 1);
+      std::vector<double> j_worst(n_sub, 0.0), j_strict(n_sub, 0.0);
+      std::vector<char> j_short(n_sub, 0);
+      int* d_act = dalloc<int>(tmp, n_sub);
+      GN_HIP(hipMemcpyAsync(d_act, h_act.data(), sizeof(int) * n_sub, hipMemcpyHostToDevice, s));
       // convergence of the Ritz pairs pnu whose residuals are in h_res
       auto check = [&](const std::vector<double>& pnu) -> bool {
         bool all = true;
@@ -1068,6 +1079,14 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
         double worst = 0.0;          // largest scaled residual over the wanted pairs
         double strict_worst = 0.0;   // largest relative residual of the coarse-space pairs
         for (int j = 0; j < n_sub; ++j) {
+          if (!h_act[j]) {
+            worst = std::max(worst, j_worst[j]);
+            strict_worst = std::max(strict_worst, j_strict[j]);
+            block_short |= j_short[j] != 0;
+            continue;
+          }
+          bool jall = true, jshort = false;
+          double jworst = 0.0, jstrict = 0.0;
           // wanted pairs: nev+1 (fixed) or those below 1.5*threshold plus one (capped)
           int nw;
           if (fixed) {
@@ -1079,7 +1098,7 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
               double lam = nk > 0 ? 1.0 / nk - shift : 1e300;
               if (lam < 1.5 * o->threshold) nw = k + 1;
             }
-            if (std::min(nw + 1, o->nev_max + 1) > b - guard / 2) block_short = true;
+            if (std::min(nw + 1, o->nev_max + 1) > b - guard / 2) jshort = true;
             nw = std::min(std::min(nw + 1, o->nev_max + 1), b - guard / 2);
           }
           nwant[j] = nw;
@@ -1107,11 +1126,20 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
             double rel = zz > 0 ? std::sqrt(rs / zz) : 0.0;
             // scaled so that the tolerance of every pair reads as eig_tol
             const double scaled = k < nin ? rel : rel * (eig_tol / std::sqrt(eig_tol));
-            if (!(scaled <= eig_tol)) all = false;
-            if (!(scaled <= worst)) worst = std::isfinite(scaled) ? std::max(worst, scaled) : 1e300;
-            if (k < nin && std::isfinite(rel)) strict_worst = std::max(strict_worst, rel);
+            if (!(scaled <= eig_tol)) jall = false;
+            if (!(scaled <= jworst)) jworst = std::isfinite(scaled) ? std::max(jworst, scaled) : 1e300;
+            if (k < nin && std::isfinite(rel)) jstrict = std::max(jstrict, rel);
           }
+          j_worst[j] = jworst;
+          j_strict[j] = jstrict;
+          j_short[j] = jshort;
+          worst = std::max(worst, jworst);
+          strict_worst = std::max(strict_worst, jstrict);
+          block_short |= jshort;
+          if (!jall) all = false;
+          else h_act[j] = 0;
         }
+        GN_HIP(hipMemcpyAsync(d_act, h_act.data(), sizeof(int) * n_sub, hipMemcpyHostToDevice, s));
         worst_hist.push_back(worst);
         solves_hist.push_back(solves);
         eig_resid = strict_worst;
@@ -1130,12 +1158,12 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
       for (int it = 0; it < eig_maxit; ++it) {
         const int d = std::min(dmax, it + 1);
         // Z = T V = P^-1 B V
-        gnk::eig_trsm(pc, b, LB, DB, TBB, BV, Z, s);
+        gnk::eig_trsm(pc, b, LB, DB, TBB, BV, Z, s, d_act);
         ++solves;
         if (d == 1) {
           // Rayleigh-Ritz on span(Z): P Z = B V, so Z^T P Z = Z^T (B V)
-          gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
-          gnk::eig_gram(pc, b, Z, BV, BZ, V, nu, GP, GB, resp, s);
+          gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s, d_act);
+          gnk::eig_gram(pc, b, Z, BV, BZ, V, nu, GP, GB, resp, s, d_act);
         } else {
           // filter interval [0, nu_cut] per subdomain, nu_cut = smallest Ritz value
           // of the last Rayleigh-Ritz step; scaled so that nu = 1/s maps to 1
@@ -1158,10 +1186,10 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
           }
           GN_HIP(hipMemcpyAsync(d_coef, h_coef.data(), sizeof(double) * h_coef.size(), hipMemcpyHostToDevice, s));
           // Y1 = a1 (Z - c V), with the Ritz residuals of the current block
-          gnk::eig_cheb_first(pc, b, Z, V, nu, d_coef, ncoef, A1, resp, s);
+          gnk::eig_cheb_first(pc, b, Z, V, nu, d_coef, ncoef, A1, resp, s, d_act);
           // Z = T V gives the residuals of the current pairs (those of the last
           // Rayleigh-Ritz step): stop here when they have converged
-          gnk::eig_resid_sum(n_sub, b, resp, res, s);
+          gnk::eig_resid_sum(n_sub, b, resp, res, s, d_act);
           GN_HIP(hipMemcpyAsync(h_res.data(), res, sizeof(double) * h_res.size(), hipMemcpyDeviceToHost, s));
           GN_HIP(hipStreamSynchronize(s));
           eig_solves = solves_prev + solves;
@@ -1171,23 +1199,23 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
             break;
           }
           double *Y0 = V, *BY0 = BV, *Yc = A1, *BYc = B1;
-          gnk::eig_bapply(p, pc, BE, b, maxNBB, Yc, BYc, s);
+          gnk::eig_bapply(p, pc, BE, b, maxNBB, Yc, BYc, s, d_act);
           for (int i = 2; i < d; ++i) {
-            gnk::eig_trsm(pc, b, LB, DB, TBB, BYc, Z, s);
+            gnk::eig_trsm(pc, b, LB, DB, TBB, BYc, Z, s, d_act);
             ++solves;
-            gnk::eig_cheb_step(pc, b, maxNBB, Z, Yc, Y0, d_coef, ncoef, i - 2, s);   // Y0 <- Y_i
-            gnk::eig_bapply(p, pc, BE, b, maxNBB, Y0, BY0, s);
+            gnk::eig_cheb_step(pc, b, maxNBB, Z, Yc, Y0, d_coef, ncoef, i - 2, s, d_act);   // Y0 <- Y_i
+            gnk::eig_bapply(p, pc, BE, b, maxNBB, Y0, BY0, s, d_act);
             std::swap(Y0, Yc);
             std::swap(BY0, BYc);
           }
           // W = T Y_{d-1}: Rayleigh-Ritz on span(W) with P W = B Y_{d-1}
-          gnk::eig_trsm(pc, b, LB, DB, TBB, BYc, Z, s);
+          gnk::eig_trsm(pc, b, LB, DB, TBB, BYc, Z, s, d_act);
           ++solves;
-          gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s);
-          gnk::eig_gram(pc, b, Z, BYc, BZ, nullptr, nullptr, GP, GB, nullptr, s);
+          gnk::eig_bapply(p, pc, BE, b, maxNBB, Z, BZ, s, d_act);
+          gnk::eig_gram(pc, b, Z, BYc, BZ, nullptr, nullptr, GP, GB, nullptr, s, d_act);
         }
-        gnk::eig_small(n_sub, b, GP, GB, resp, res, Y, nu, nullptr, s);
-        gnk::eig_vupdate(pc, b, maxNBB, Z, BZ, Y, V, BV, s);
+        gnk::eig_small(n_sub, b, GP, GB, resp, res, Y, nu, nullptr, s, d_act);
+        gnk::eig_vupdate(pc, b, maxNBB, Z, BZ, Y, V, BV, s, d_act);
         GN_HIP(hipMemcpyAsync(h_res.data(), res, sizeof(double) * h_res.size(), hipMemcpyDeviceToHost, s));
         // residuals refer to the Ritz pairs of the previous iteration (h_nu before this copy)
         std::vector<double> prev_nu = h_nu;

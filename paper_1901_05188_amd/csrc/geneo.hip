@@ -161,7 +161,7 @@ constexpr int bapply_span(int nchunk) { return (NT / (nchunk * NC) + 2) * bapply
 template <int NC, bool LDSC>
 __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs, const double* __restrict__ BE,
                                                int b, const double* __restrict__ V, double* __restrict__ out,
-                                               int gx, int ntot) {
+                                               int gx, int ntot, const int* __restrict__ act) {
   constexpr int R = bapply_rows<NC>();
   extern __shared__ double sBE[];   // LDSC: the workgroup's coefficient rows, 27 NC planes of span
   // consecutive workgroups are dealt round-robin to the 8 XCDs; the 1-D grid
@@ -173,6 +173,7 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
   const int item = (lin % 8) * per + lin / 8;
   if (item >= ntot) return;
   const int bx = item % gx, by = item / gx;
+  if (act && act[by] == 0) return;
   const SubDesc& sd = subs[by];
   const int npad = sd.NBB * TILE;
   const int nchunk = (b + BCW - 1) / BCW;
@@ -283,12 +284,13 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
 template <int NC>
 __global__ __launch_bounds__(NT) void k_bapply_node(const SubDesc* __restrict__ subs, const double* __restrict__ BE,
                                                     int b, const double* __restrict__ V, double* __restrict__ out,
-                                                    int gx, int ntot) {
+                                                    int gx, int ntot, const int* __restrict__ act) {
   const int per = (ntot + 7) / 8;
   const int lin = blockIdx.x;
   const int item = (lin % 8) * per + lin / 8;
   if (item >= ntot) return;
   const int bx = item % gx, by = item / gx;
+  if (act && act[by] == 0) return;
   const SubDesc& sd = subs[by];
   const int npad = sd.NBB * TILE;
   const int nchunk = (b + BCW - 1) / BCW;
@@ -394,14 +396,16 @@ template <int W, int P, int NCB>
 __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ subs, int n_sub, int csplit, int b,
                                                     int ringlen, const double* __restrict__ T,
                                                     const double* __restrict__ D, const double* __restrict__ TBk,
-                                                    const double* __restrict__ Z0, const double* Vin, double* V) {
+                                                    const double* __restrict__ Z0, const double* Vin, double* V,
+                                                    const int* __restrict__ act) {
   constexpr int WS = W / 2;                 // tile slots per wave and step
   static_assert(W % 2 == 0 && WS % P == 0, "W / 2 must be a multiple of the prefetch depth");
   extern __shared__ double smem[];
   double* ring = smem;                      // W1 slots x TILE rows x RW columns (+16 pad)
   double* sS = smem + ringlen;              // NCB right-hand-side tiles, 32 x 16 (+1)
   double* sP = sS + NCB * (TILE * 17);      // partial sums [parity][block], 2 NCB tiles
-  const SubDesc& sd = subs[blockIdx.x % n_sub];
+  const SubDesc& sd = subs[blockIdx.x % n_sub];   // subdomains in the XCD-balanced order
+  if (act && act[sd.id] == 0) return;
   const int c0 = csplit > 1 ? (int)(blockIdx.x / n_sub) * (16 * NCB) : 0;
   const int RW = csplit > 1 ? 16 * NCB : b; // columns held in the ring
   const int NB = sd.NBB, w = sd.wB, W1 = w + 1;
@@ -591,8 +595,10 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
                                              const double* __restrict__ Z, const double* __restrict__ BV,
                                              const double* __restrict__ BZ, const double* __restrict__ V,
                                              const double* __restrict__ nu, double* __restrict__ GPp,
-                                             double* __restrict__ GBp, double* __restrict__ resp) {
+                                             double* __restrict__ GBp, double* __restrict__ resp,
+                                             const int* __restrict__ act) {
   __shared__ double sres[4][64], szz[4][64];
+  if (act && act[blockIdx.x] == 0) return;
   const SubDesc& sd = subs[blockIdx.x];
   const int64_t base = sd.offVB * b;
   const int g = blockIdx.y;
@@ -691,8 +697,10 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
 __global__ __launch_bounds__(NT) void k_small_eig(int b, const double* __restrict__ GPp,
                                                   const double* __restrict__ GBp, const double* __restrict__ resp,
                                                   double* __restrict__ res, double* __restrict__ Y,
-                                                  double* __restrict__ nu_out, int* __restrict__ flag) {
+                                                  double* __restrict__ nu_out, int* __restrict__ flag,
+                                                  const int* __restrict__ act) {
   extern __shared__ double sm[];
+  if (act && act[blockIdx.x] == 0) return;
   const int ld = b + 1;
   double* P = sm;              // b x ld
   double* C = P + b * ld;      // b x ld
@@ -927,8 +935,9 @@ template <int KS, int CB>   // K-steps and 16-column blocks covered: 4 KS >= b, 
 __global__ __launch_bounds__(NT) void k_vupdate(const SubDesc* __restrict__ subs, int b,
                                                 const double* __restrict__ Z, const double* __restrict__ BZ,
                                                 const double* __restrict__ Y, double* __restrict__ V,
-                                                double* __restrict__ BV) {
+                                                double* __restrict__ BV, const int* __restrict__ act) {
   __shared__ double sY[64 * 65];
+  if (act && act[blockIdx.y] == 0) return;
   const SubDesc& sd = subs[blockIdx.y];
   const int nrow = sd.NBB * TILE;           // padded row counts are multiples of 32
   if (blockIdx.x * (NT / 64) * 16 >= nrow) return;   // the whole workgroup, before the barrier
@@ -991,8 +1000,10 @@ __global__ __launch_bounds__(NT) void k_vupdate(const SubDesc* __restrict__ subs
 __global__ __launch_bounds__(NT) void k_cheb_first(const SubDesc* __restrict__ subs, int b,
                                                    const double* __restrict__ Z, const double* __restrict__ V,
                                                    const double* __restrict__ nu, const double* __restrict__ coef,
-                                                   int ncoef, double* __restrict__ Y1, double* __restrict__ resp) {
+                                                   int ncoef, double* __restrict__ Y1, double* __restrict__ resp,
+                                                   const int* __restrict__ act) {
   __shared__ double sres[4][64], szz[4][64];
+  if (act && act[blockIdx.x] == 0) return;
   const SubDesc& sd = subs[blockIdx.x];
   const int64_t base = sd.offVB * b;
   const int g = blockIdx.y;
@@ -1042,7 +1053,8 @@ __global__ __launch_bounds__(NT) void k_cheb_first(const SubDesc* __restrict__ s
 __global__ __launch_bounds__(NT) void k_cheb_step(const SubDesc* __restrict__ subs, int b,
                                                   const double* __restrict__ TY, const double* __restrict__ Y1,
                                                   double* __restrict__ Y0, const double* __restrict__ coef,
-                                                  int ncoef, int step) {
+                                                  int ncoef, int step, const int* __restrict__ act) {
+  if (act && act[blockIdx.y] == 0) return;
   const SubDesc& sd = subs[blockIdx.y];
   const int64_t n = (int64_t)sd.NBB * TILE * b;
   const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -1208,7 +1220,9 @@ __global__ __launch_bounds__(NT) void k_defect_add(const SubDesc* __restrict__ s
 
 // Ritz residual sums of one subdomain: the GRAM_SPLIT row-split partials added
 // in fixed order (the same sums k_small_eig forms)
-__global__ void k_resid_sum(int b, const double* __restrict__ resp, double* __restrict__ res) {
+__global__ void k_resid_sum(int b, const double* __restrict__ resp, double* __restrict__ res,
+                            const int* __restrict__ act) {
+  if (act && act[blockIdx.x] == 0) return;
   const double* rp = resp + (int64_t)blockIdx.x * GRAM_SPLIT * 2 * b;
   for (int e = threadIdx.x; e < 2 * b; e += blockDim.x) {
     double t = 0.0;
@@ -1684,8 +1698,8 @@ void eig_defect_add(const gn_precond* pc, int b, int maxNBB, const double* D, co
   GN_CHECK_LAUNCH();
 }
 
-void eig_resid_sum(int n_sub, int b, const double* resp, double* res, hipStream_t s) {
-  hipLaunchKernelGGL(k_resid_sum, dim3(n_sub), dim3(128), 0, s, b, resp, res);
+void eig_resid_sum(int n_sub, int b, const double* resp, double* res, hipStream_t s, const int* act) {
+  hipLaunchKernelGGL(k_resid_sum, dim3(n_sub), dim3(128), 0, s, b, resp, res, act);
   GN_CHECK_LAUNCH();
 }
 
@@ -1726,7 +1740,7 @@ void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double
 }
 
 void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int b, int maxNBB,
-                const double* V, double* out, hipStream_t s) {
+                const double* V, double* out, hipStream_t s, const int* act) {
   const int nchunk = (b + BCW - 1) / BCW;
   const int nc = p->nc;
   if (nc == 3) {
@@ -1735,7 +1749,7 @@ void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int
     const int gx = (int)((nodes * nchunk + NT - 1) / NT);
     const int ntot = gx * pc->n_sub;
     hipLaunchKernelGGL((k_bapply_node<3>), dim3((unsigned)(8 * ((ntot + 7) / 8))), dim3(NT), 0, s, pc->d_sub, BE,
-                       b, V, out, gx, ntot);
+                       b, V, out, gx, ntot, act);
     GN_CHECK_LAUNCH();
     return;
   }
@@ -1748,14 +1762,14 @@ void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int
   // coefficient rows in LDS when they fit in 48 KB (b >= 17)
   const size_t lds = sizeof(double) * 27 * bapply_span<1>(nchunk);
   if (lds <= 48 * 1024)
-    hipLaunchKernelGGL((k_bapply<1, true>), grid, dim3(NT), lds, s, pc->d_sub, BE, b, V, out, gx, ntot);
+    hipLaunchKernelGGL((k_bapply<1, true>), grid, dim3(NT), lds, s, pc->d_sub, BE, b, V, out, gx, ntot, act);
   else
-    hipLaunchKernelGGL((k_bapply<1, false>), grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out, gx, ntot);
+    hipLaunchKernelGGL((k_bapply<1, false>), grid, dim3(NT), 0, s, pc->d_sub, BE, b, V, out, gx, ntot, act);
   GN_CHECK_LAUNCH();
 }
 
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, const double* TB, const double* Vin,
-              double* V, hipStream_t s) {
+              double* V, hipStream_t s, const int* act) {
   if (b > 64) throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
   int maxw = 0;
   for (const SubDesc& sd : pc->sub) maxw = std::max(maxw, sd.wB);
@@ -1787,7 +1801,7 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
     GN_HIP(hipFuncSetAttribute((const void*)k_trsm_ring<WV, PV, NV>,                                 \
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));               \
     hipLaunchKernelGGL((k_trsm_ring<WV, PV, NV>), dim3(pc->n_sub * cs2), dim3(256), lds2, s,         \
-                       pc->d_subxB, pc->n_sub, cs2, b, rl2, T, D, TB, pc->d_z0, Vin, V);              \
+                       pc->d_subxB, pc->n_sub, cs2, b, rl2, T, D, TB, pc->d_z0, Vin, V, act);         \
   } while (0)
 #define GN_R2W(WV, PV)                     \
   do {                                     \
@@ -1818,44 +1832,45 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
 int gram_split() { return GRAM_SPLIT; }
 
 void eig_cheb_first(const gn_precond* pc, int b, const double* Z, const double* V, const double* nu,
-                    const double* coef, int ncoef, double* Y1, double* resp, hipStream_t s) {
+                    const double* coef, int ncoef, double* Y1, double* resp, hipStream_t s, const int* act) {
   hipLaunchKernelGGL(k_cheb_first, dim3(pc->n_sub, GRAM_SPLIT), dim3(NT), 0, s, pc->d_sub, b, Z, V, nu, coef,
-                     ncoef, Y1, resp);
+                     ncoef, Y1, resp, act);
   GN_CHECK_LAUNCH();
 }
 
 void eig_cheb_step(const gn_precond* pc, int b, int maxNBB, const double* TY, const double* Y1, double* Y0,
-                   const double* coef, int ncoef, int step, hipStream_t s) {
+                   const double* coef, int ncoef, int step, hipStream_t s, const int* act) {
   dim3 grid((unsigned)(((int64_t)maxNBB * TILE * b + NT - 1) / NT), pc->n_sub);
-  hipLaunchKernelGGL(k_cheb_step, grid, dim3(NT), 0, s, pc->d_sub, b, TY, Y1, Y0, coef, ncoef, step);
+  hipLaunchKernelGGL(k_cheb_step, grid, dim3(NT), 0, s, pc->d_sub, b, TY, Y1, Y0, coef, ncoef, step, act);
   GN_CHECK_LAUNCH();
 }
 
 void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, const double* BZ,
-              const double* V, const double* nu, double* GPp, double* GBp, double* resp, hipStream_t s) {
+              const double* V, const double* nu, double* GPp, double* GBp, double* resp, hipStream_t s,
+              const int* act) {
   hipLaunchKernelGGL(k_gram, dim3(pc->n_sub, GRAM_SPLIT), dim3(NT), 0, s, pc->d_sub, b, Z, BV, BZ, V, nu,
-                     GPp, GBp, resp);
+                     GPp, GBp, resp, act);
   GN_CHECK_LAUNCH();
 }
 
 void eig_small(int n_sub, int b, const double* GPp, const double* GBp, const double* resp, double* res,
-               double* Y, double* nu, int* flag, hipStream_t s) {
+               double* Y, double* nu, int* flag, hipStream_t s, const int* act) {
   size_t lds = sizeof(double) * 3 * b * (b + 1);
   GN_HIP(hipFuncSetAttribute((const void*)k_small_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
-  hipLaunchKernelGGL(k_small_eig, dim3(n_sub), dim3(NT), lds, s, b, GPp, GBp, resp, res, Y, nu, flag);
+  hipLaunchKernelGGL(k_small_eig, dim3(n_sub), dim3(NT), lds, s, b, GPp, GBp, resp, res, Y, nu, flag, act);
   GN_CHECK_LAUNCH();
 }
 
 void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const double* BZ,
-                 const double* Y, double* V, double* BV, hipStream_t s) {
+                 const double* Y, double* V, double* BV, hipStream_t s, const int* act) {
   if (b > 64) throw gn_error{GN_ERR_ARG, "eigensolver block larger than 64"};
   const int waves = maxNBB * TILE / 16;       // 16-row blocks of the largest subdomain
   const dim3 grid((waves + NT / 64 - 1) / (NT / 64), pc->n_sub);
   if (b <= 32)
-    hipLaunchKernelGGL((k_vupdate<8, 2>), grid, dim3(NT), 0, s, pc->d_sub, b, Z, BZ, Y, V, BV);
+    hipLaunchKernelGGL((k_vupdate<8, 2>), grid, dim3(NT), 0, s, pc->d_sub, b, Z, BZ, Y, V, BV, act);
   else
-    hipLaunchKernelGGL((k_vupdate<16, 4>), grid, dim3(NT), 0, s, pc->d_sub, b, Z, BZ, Y, V, BV);
+    hipLaunchKernelGGL((k_vupdate<16, 4>), grid, dim3(NT), 0, s, pc->d_sub, b, Z, BZ, Y, V, BV, act);
   GN_CHECK_LAUNCH();
 }
 

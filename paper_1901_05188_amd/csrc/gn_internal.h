@@ -61,6 +61,7 @@ struct SubDesc {
   int coff;             // first coarse index i(j, 0)
   int64_t offPhi;       // offset (doubles) of Phi_j (NBI*TILE rows x m, row-major)
   int bwI, bwB;         // half bandwidth in DOFs of the local matrix and of the pencil
+  int id;               // index j of the subdomain (the reordered copies keep it)
 };
 
 // one nonzero block (A_H)_{j1,j2} of the block-sparse coarse matrix: m_j1 x m_j2
@@ -376,23 +377,25 @@ void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double
 void eig_extract_p(const gn_problem* p, const gn_precond* pc, int maxNBB, double shift, double* PE,
                    hipStream_t s);
 void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int b, int maxNBB,
-                const double* V, double* out, hipStream_t s);
+                const double* V, double* out, hipStream_t s, const int* act = nullptr);
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, const double* TB, const double* Vin,
-              double* V, hipStream_t s);
+              double* V, hipStream_t s, const int* act = nullptr);
 int gram_split();
 void eig_cheb_first(const gn_precond* pc, int b, const double* Z, const double* V, const double* nu,
-                    const double* coef, int ncoef, double* Y1, double* resp, hipStream_t s);
+                    const double* coef, int ncoef, double* Y1, double* resp, hipStream_t s,
+                    const int* act = nullptr);
 void eig_cheb_step(const gn_precond* pc, int b, int maxNBB, const double* TY, const double* Y1, double* Y0,
-                   const double* coef, int ncoef, int step, hipStream_t s);
+                   const double* coef, int ncoef, int step, hipStream_t s, const int* act = nullptr);
 void eig_gram(const gn_precond* pc, int b, const double* Z, const double* BV, const double* BZ,
-              const double* V, const double* nu, double* GPp, double* GBp, double* resp, hipStream_t s);
+              const double* V, const double* nu, double* GPp, double* GBp, double* resp, hipStream_t s,
+              const int* act = nullptr);
 void eig_small(int n_sub, int b, const double* GPp, const double* GBp, const double* resp, double* res,
-               double* Y, double* nu, int* flag, hipStream_t s);
+               double* Y, double* nu, int* flag, hipStream_t s, const int* act = nullptr);
 void eig_vupdate(const gn_precond* pc, int b, int maxNBB, const double* Z, const double* BZ,
-                 const double* Y, double* V, double* BV, hipStream_t s);
+                 const double* Y, double* V, double* BV, hipStream_t s, const int* act = nullptr);
 void eig_normalise(const gn_precond* pc, int b, int ncol, double* V, hipStream_t s);
 void zem_modes(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s);
-void eig_resid_sum(int n_sub, int b, const double* resp, double* res, hipStream_t s);
+void eig_resid_sum(int n_sub, int b, const double* resp, double* res, hipStream_t s, const int* act = nullptr);
 void eig_rq(const gn_problem* p, const gn_precond* pc, int b, const double* V, double* lam, hipStream_t s);
 void eig_defect(const gn_precond* pc, int b, int maxNBB, const double* BV, const double* PV, const double* nu,
                 double* rho, hipStream_t s);
