@@ -182,7 +182,9 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
   extern __shared__ double rowL[];   // RL: w tiles, column-major with TILE + 1 stride
   __shared__ double part[4][TILE][TILE + 1];
   __shared__ double Ss[TILE][TILE + 1];
-  __shared__ double Xs[TILE][TILE + 1];
+  // the inverse of the diagonal tile is formed while no partial product is
+  // live (between the two barriers of the diagonal step), in part[3]
+  double(*Xs)[TILE + 1] = part[3];
   __shared__ int fail;
   const BandRef br = mats[blockIdx.x];
   const int w = br.w, NB = br.NB;
@@ -432,9 +434,10 @@ void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, dou
 
 void band_chol(const void* d_refs, int n, int maxw, double* T, double* D, int* info, hipStream_t s) {
   // the row tiles in LDS when they fit beside the kernel's static arrays
-  // (about 50 KB: the four partial products and two exchange tiles)
+  // (the four partial products and the exchange tile, 41.3 KB)
   const size_t rl = sizeof(double) * (size_t)std::max(maxw, 1) * TILE * (TILE + 1);
-  if (rl + 52 * 1024 <= 160 * 1024) {
+  const size_t fixed = sizeof(double) * 5 * TILE * (TILE + 1) + 64;
+  if (rl + fixed <= 160 * 1024) {
     GN_HIP(hipFuncSetAttribute((const void*)k_band_chol_mfma<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)rl));
     hipLaunchKernelGGL(k_band_chol_mfma<true>, dim3(n), dim3(NT), rl, s, (const BandRef*)d_refs, T, D, info);
