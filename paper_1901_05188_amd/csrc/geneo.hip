@@ -1589,11 +1589,11 @@ __global__ __launch_bounds__(NT) void k_syrk_panel(int NB, int k0, int k1, int J
 // tile (its four 16 x 16 quadrants), so a wave loads each operand tile once for
 // four quadrant products instead of once per quadrant, and the four waves of a
 // workgroup share their operand tiles through the L1 cache.
-// acc[r][c][.] += X(r quadrant rows, :) Y(:, c quadrant columns) over one tile pair
+// acc[r][c][.] += X(r quadrant rows, :) Y(:, c quadrant columns) over one tile
+// pair: its operands (tile_full_load), loaded ahead of the products (tile_full_mma)
 template <bool TRANSY>
-__device__ inline void tile_mma_full_acc(const double* __restrict__ xs, const double* __restrict__ ys, int lr,
-                                         int lk, gn_d4 acc[2][2][2]) {
-  double av[2][8], bv[2][8];
+__device__ inline void tile_full_load(const double* __restrict__ xs, const double* __restrict__ ys, int lr, int lk,
+                                      double av[2][8], double bv[2][8]) {
 #pragma unroll
   for (int ks = 0; ks < 8; ++ks) {
     const int k = 4 * ks + lk;
@@ -1603,60 +1603,81 @@ __device__ inline void tile_mma_full_acc(const double* __restrict__ xs, const do
       bv[r][ks] = TRANSY ? ys[k * TILE + r * 16 + lr] : ys[(r * 16 + lr) * TILE + k];
     }
   }
+}
+// (one accumulator chain per quadrant: the four quadrants' products interleave,
+// so each chain's previous product has left the pipeline when the next issues)
+__device__ inline void tile_full_mma(const double av[2][8], const double bv[2][8], gn_d4 acc[2][2]) {
 #pragma unroll
   for (int ks = 0; ks < 8; ++ks)
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int c = 0; c < 2; ++c)
-        acc[r][c][ks & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][ks], bv[c][ks], acc[r][c][ks & 1], 0, 0, 0);
+        acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][ks], bv[c][ks], acc[r][c], 0, 0, 0);
+}
+// acc += sum_{k = ka}^{kb - 1} X(k) Y(k), the operands of step k + 1 in flight
+// during the products of step k (two register sets, used alternately)
+template <bool TRANSY, typename XF, typename YF>
+__device__ inline void tile_full_sum(int ka, int kb, XF xs, YF ys, int lr, int lk, gn_d4 acc[2][2]) {
+  if (ka >= kb) return;
+  double a0[2][8], b0[2][8], a1[2][8], b1[2][8];
+  tile_full_load<TRANSY>(xs(ka), ys(ka), lr, lk, a0, b0);
+  for (int k = ka; k < kb; k += 2) {
+    if (k + 1 < kb) tile_full_load<TRANSY>(xs(k + 1), ys(k + 1), lr, lk, a1, b1);
+    tile_full_mma(a0, b0, acc);
+    if (k + 1 >= kb) break;
+    if (k + 2 < kb) tile_full_load<TRANSY>(xs(k + 2), ys(k + 2), lr, lk, a0, b0);
+    tile_full_mma(a1, b1, acc);
+  }
 }
 
 // the wave's output tile t (column-major) += sgn * acc
-__device__ inline void tile_store_acc(double* __restrict__ t, double sgn, int lr, int lk, gn_d4 acc[2][2][2]) {
+__device__ inline void tile_store_acc(double* __restrict__ t, double sgn, int lr, int lk, gn_d4 acc[2][2]) {
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        t[(c * 16 + lr) * TILE + r * 16 + 4 * i + lk] += sgn * (acc[r][c][0][i] + acc[r][c][1][i]);
+        t[(c * 16 + lr) * TILE + r * 16 + 4 * i + lk] += sgn * acc[r][c][i];
 }
 
 // A(I,J) -= sum_{k0 <= k < k1} L(I,k) L(J,k)^T for J0 <= J <= I < NB: block
 // (blockIdx.x, blockIdx.y) covers I = J0 + 2 bx + (0, 1), J = J0 + 2 by + (0, 1)
 // (blocks wholly above the diagonal return at once; wave = (I offset, J offset))
-__global__ __launch_bounds__(NT) void k_syrk_panel2(int NB, int k0, int k1, int J0, double* __restrict__ A) {
+__global__ __launch_bounds__(NT, 2) void k_syrk_panel2(int NB, int k0, int k1, int J0, double* __restrict__ A) {
   if (blockIdx.x < blockIdx.y) return;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int I = J0 + 2 * (int)blockIdx.x + (wv & 1), J = J0 + 2 * (int)blockIdx.y + (wv >> 1);
   if (I >= NB || J > I) return;
   const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-  gn_d4 acc[2][2][2];
+  gn_d4 acc[2][2];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < 2; ++c) acc[r][c][0] = acc[r][c][1] = gn_d4{0, 0, 0, 0};
-  for (int k = k0; k < k1; ++k)
-    tile_mma_full_acc<true>(A + ((int64_t)I * NB + k) * TILE2, A + ((int64_t)J * NB + k) * TILE2, lr, lk, acc);
+    for (int c = 0; c < 2; ++c) acc[r][c] = gn_d4{0, 0, 0, 0};
+  tile_full_sum<true>(
+      k0, k1, [&](int k) { return A + ((int64_t)I * NB + k) * TILE2; },
+      [&](int k) { return A + ((int64_t)J * NB + k) * TILE2; }, lr, lk, acc);
   tile_store_acc(A + ((int64_t)I * NB + J) * TILE2, -1.0, lr, lk, acc);
 }
 
 // Z(I,J) += sum_{max(k0,J) <= k < k1} L(I,k) Z(k,J) for I in [I0, NB), J in [0, k1):
 // block (blockIdx.x, blockIdx.y) covers J = 2 bx + (0, 1), I = I0 + 2 by + (0, 1)
-__global__ __launch_bounds__(NT) void k_trinv_panel2(int NB, int k0, int k1, int I0, const double* __restrict__ L,
+__global__ __launch_bounds__(NT, 2) void k_trinv_panel2(int NB, int k0, int k1, int I0, const double* __restrict__ L,
                                                      double* __restrict__ Z) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int J = 2 * (int)blockIdx.x + (wv & 1), I = I0 + 2 * (int)blockIdx.y + (wv >> 1);
   if (J >= k1 || I >= NB) return;
   const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-  gn_d4 acc[2][2][2];
+  gn_d4 acc[2][2];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < 2; ++c) acc[r][c][0] = acc[r][c][1] = gn_d4{0, 0, 0, 0};
-  for (int k = max(k0, J); k < k1; ++k)
-    tile_mma_full_acc<false>(L + ((int64_t)I * NB + k) * TILE2, Z + ((int64_t)k * NB + J) * TILE2, lr, lk, acc);
+    for (int c = 0; c < 2; ++c) acc[r][c] = gn_d4{0, 0, 0, 0};
+  tile_full_sum<false>(
+      max(k0, J), k1, [&](int k) { return L + ((int64_t)I * NB + k) * TILE2; },
+      [&](int k) { return Z + ((int64_t)k * NB + J) * TILE2; }, lr, lk, acc);
   tile_store_acc(Z + ((int64_t)I * NB + J) * TILE2, 1.0, lr, lk, acc);
 }
 
