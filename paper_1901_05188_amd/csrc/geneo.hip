@@ -1546,7 +1546,7 @@ __global__ __launch_bounds__(NT) void k_trinv_update(int NB, int K, const double
 // the matrix-core accumulators per output tile.  Each trailing tile is then
 // read and written once per panel instead of once per tile column, which is
 // what bounded the tile-by-tile updates.
-constexpr int CPANEL = 8;
+constexpr int CPANEL = 16;
 
 // acc += X Y over one tile pair (the accumulating form of tile_mma)
 template <bool TRANSY>
