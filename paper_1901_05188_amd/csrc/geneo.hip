@@ -212,8 +212,9 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
   const int s0 = a0 == 0 ? 1 : (a0 == 1 ? 3 : 9);
   const int s1 = ax1 == 0 ? 1 : 3, s2 = ax2 == 1 ? 3 : 9;
   // B = X A_O X vanishes on the core of the subdomain and on neighbours outside
-  // overlap elements, and the zeros come in blocks of rows: a line whose
-  // coefficients are zero on every lane of the wave is skipped. A lane with a
+  // overlap elements, and the zeros come in blocks of rows: a lane whose
+  // coefficients on a line are all zero skips the line (its V loads are masked
+  // off; skipping adds nothing it would not have added). A lane with a
   // zero coefficient on a line that runs adds 0 * v = +-0, which leaves its
   // sums unchanged (v is finite: row indices are clamped into the box and the
   // buffers' tails are zero). The sums run line by line, then along a0,
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
           nz |= bv[i][dx][c2] != 0.0;
         }
     }
-    if (!__any(nz)) continue;
+    if (!nz) continue;   // per lane: rows whose coefficients on this line are all zero load no V
     // rows of nodes ln0 - 1 .. ln0 + R on this line; out-of-box neighbours have bv = 0
     double v[R + 2][NC][BCW];
 #pragma unroll
@@ -278,8 +279,8 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
 // NC rows (the one-component layout above loads every neighbour value once per
 // component).  Coefficients come straight from the node-ELL planes (the chunk
 // lanes of a node read the same addresses; staging them in LDS instead measured
-// slower, at the lower occupancy it allows); a line whose coefficients are zero
-// on every lane of the wave loads no V.  Every output sums over the same
+// slower, at the lower occupancy it allows); a lane whose coefficients on a
+// line are all zero loads no V for it.  Every output sums over the same
 // sequence (line, dx, c2) as the one-component kernel.
 template <int NC>
 __global__ __launch_bounds__(NT) void k_bapply_node(const SubDesc* __restrict__ subs, const double* __restrict__ BE,
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(NT) void k_bapply_node(const SubDesc* __restrict__ 
           nz |= bv[dx][c][c2] != 0.0;
         }
     }
-    if (!__any(nz)) continue;
+    if (!nz) continue;   // per lane: a node whose coefficients on this line are all zero loads no V
     // nodes ln - 1, ln, ln + 1 of this line (clamped into the box: their
     // coefficients are zero where the neighbour lies outside it)
     double v[3][NC][BCW];
