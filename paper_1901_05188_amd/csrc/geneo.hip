@@ -400,7 +400,10 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
                                                     const double* __restrict__ Z0, const double* Vin, double* V,
                                                     const int* __restrict__ act) {
   constexpr int WS = W / 2;                 // tile slots per wave and step
-  static_assert(W % 2 == 0 && WS % P == 0, "W / 2 must be a multiple of the prefetch depth");
+  // DEEP (P = W): the A registers hold two block rows, K and K + 1, and each
+  // slot is reloaded with row K + 2 (two rows of band tiles in flight)
+  constexpr bool DEEP = P == W;
+  static_assert(W % 2 == 0 && (DEEP || WS % P == 0), "W / 2 must be a multiple of the prefetch depth");
   extern __shared__ double smem[];
   double* ring = smem;                      // W1 slots x TILE rows x RW columns (+16 pad)
   double* sS = smem + ringlen;              // NCB right-hand-side tiles, 32 x 16 (+1)
@@ -427,13 +430,14 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
   for (int e = threadIdx.x; e < ringlen; e += 256) ring[e] = 0.0;
   double a[P][8];
   double dv[8], vv[4];
-  gn_d4 acc[NCB][8];
-#define R2_ZERO() _Pragma("unroll") for (int q = 0; q < NCB; ++q) _Pragma("unroll") for (int u = 0; u < 8; ++u) acc[q][u] = gn_d4{0, 0, 0, 0};
+  gn_d4 acc[NCB][2];   // two chains per column block: consecutive products of a chain are NCB MFMAs apart
+#define R2_ZERO() _Pragma("unroll") for (int q = 0; q < NCB; ++q) _Pragma("unroll") for (int u = 0; u < 2; ++u) acc[q][u] = gn_d4{0, 0, 0, 0};
   const int rstride = TILE * RW;
   // products of one block row: slots m = 0 .. WS-1 of this wave's parity, slot
   // m multiplying ring slot (SLOT0 + 2 m) mod W1; the A registers of slot m are
-  // reloaded with slot m + P of the row (or of row KN past the end)
-#define R2_PRODUCTS(KR, KN, SLOT0, LOADA)                                                      \
+  // reloaded with slot m + P of the row (or of row KN past the end); DEEP: the
+  // row's A registers start at BASE, slot m is reloaded with slot m of row KN
+#define R2_PRODUCTS(KR, KN, SLOT0, LOADA, BASE)                                                \
   {                                                                                            \
     R2_ZERO()                                                                                  \
     int slot = (SLOT0);                                                                        \
@@ -442,7 +446,7 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
       _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                         \
         bnxt[q][ks] = ring[slot * rstride + (4 * ks + lk) * RW + q * 16 + lr];                 \
     _Pragma("unroll") for (int m = 0; m < WS; ++m) {                                           \
-      const int sl = m % P;                                                                    \
+      const int sl = DEEP ? (BASE) + m : m % P;                                               \
       _Pragma("unroll") for (int q = 0; q < NCB; ++q)                                          \
         _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) bcur[q][ks] = bnxt[q][ks];            \
       if (m + 1 < WS) {                                                                        \
@@ -454,9 +458,10 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
       }                                                                                        \
       _Pragma("unroll") for (int ks = 0; ks < 8; ++ks)                                         \
         _Pragma("unroll") for (int q = 0; q < NCB; ++q)                                        \
-          acc[q][ks] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][ks], bcur[q][ks], acc[q][ks], 0, 0, 0); \
+          acc[q][ks & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sl][ks], bcur[q][ks], acc[q][ks & 1], 0, 0, 0); \
       __builtin_amdgcn_sched_barrier(0);                                                       \
-      if (m + P < WS) LOADA(sl, (KR), 2 * (m + P) + half)                                      \
+      if (DEEP) LOADA(sl, (KN), 2 * m + half)                                                  \
+      else if (m + P < WS) LOADA(sl, (KR), 2 * (m + P) + half)                                 \
       else LOADA(sl, (KN), 2 * (m + P - WS) + half)                                            \
       __builtin_amdgcn_sched_barrier(0);                                                       \
     }                                                                                          \
@@ -468,8 +473,7 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
     double psum[NCB][4];                                                                       \
     _Pragma("unroll") for (int q = 0; q < NCB; ++q)                                            \
       _Pragma("unroll") for (int i = 0; i < 4; ++i)                                            \
-        psum[q][i] = ((acc[q][0][i] + acc[q][1][i]) + (acc[q][2][i] + acc[q][3][i])) +         \
-                     ((acc[q][4][i] + acc[q][5][i]) + (acc[q][6][i] + acc[q][7][i]));          \
+        psum[q][i] = acc[q][0][i] + acc[q][1][i];                                              \
     /* every wave leaves its partial sums of all blocks, the owner its right-hand */          \
     /* side; after one barrier the owner forms S = V - (P0 + P1) as it reads it */             \
     _Pragma("unroll") for (int q = 0; q < NCB; ++q)                                            \
@@ -526,18 +530,37 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
     _Pragma("unroll") for (int i = 0; i < 4; ++i)                                              \
       vv[i] = Vi[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + ocol];                          \
   }
+  // the diagonal tile and right-hand side of row K are loaded just before its
+  // products and used in its exchange: the products cover their latency, and
+  // no register is copied before a reload (which would make the wave wait for
+  // every load in flight, the next rows' band tiles included).  Ring slot of
+  // tile t of row K: block K - w + t, i.e. (K + 1 + t) % W1
+  if constexpr (DEEP) {
 #pragma unroll
-  for (int sl = 0; sl < P; ++sl) R2_LOAD_A_FWD(sl, 0, 2 * sl + half)
-  __syncthreads();
-  for (int K = 0; K < NB; ++K) {
-    // the diagonal tile and right-hand side of row K, loaded here and used in
-    // its exchange: the products cover their latency, and no register is copied
-    // before a reload (which would make the wave wait for every load in flight,
-    // the next row's band tiles included)
-    if (own >= 0) R2_LOAD_DV_FWD(K)
-    // ring slot of tile t of row K: block K - w + t, i.e. (K + 1 + t) % W1
-    R2_PRODUCTS(K, min(K + 1, NB - 1), (K + 1 + half) % W1, R2_LOAD_A_FWD)
-    R2_FINISH(K)
+    for (int sl = 0; sl < WS; ++sl) {
+      R2_LOAD_A_FWD(sl, 0, 2 * sl + half)
+      R2_LOAD_A_FWD(WS + sl, min(1, NB - 1), 2 * sl + half)
+    }
+    __syncthreads();
+    for (int K = 0; K < NB; K += 2) {
+      if (own >= 0) R2_LOAD_DV_FWD(K)
+      R2_PRODUCTS(K, min(K + 2, NB - 1), (K + 1 + half) % W1, R2_LOAD_A_FWD, 0)
+      R2_FINISH(K)
+      if (K + 1 < NB) {
+        if (own >= 0) R2_LOAD_DV_FWD(K + 1)
+        R2_PRODUCTS(K + 1, min(K + 3, NB - 1), (K + 2 + half) % W1, R2_LOAD_A_FWD, WS)
+        R2_FINISH(K + 1)
+      }
+    }
+  } else {
+#pragma unroll
+    for (int sl = 0; sl < P; ++sl) R2_LOAD_A_FWD(sl, 0, 2 * sl + half)
+    __syncthreads();
+    for (int K = 0; K < NB; ++K) {
+      if (own >= 0) R2_LOAD_DV_FWD(K)
+      R2_PRODUCTS(K, min(K + 1, NB - 1), (K + 1 + half) % W1, R2_LOAD_A_FWD, 0)
+      R2_FINISH(K)
+    }
   }
 #undef R2_LOAD_DV_FWD
 #undef R2_LOAD_A_FWD
@@ -563,14 +586,33 @@ __global__ __launch_bounds__(256) void k_trsm_ring(const SubDesc* __restrict__ s
     _Pragma("unroll") for (int i = 0; i < 4; ++i)                                              \
       vv[i] = Vb[(int64_t)((K_) * TILE + rb + 4 * i + lk) * b + ocol];                          \
   }
+  // ring slot of tile t of row K: block K + 1 + t
+  if constexpr (DEEP) {
 #pragma unroll
-  for (int sl = 0; sl < P; ++sl) R2_LOAD_A_BWD(sl, NB - 1, 2 * sl + half)
-  __syncthreads();
-  for (int K = NB - 1; K >= 0; --K) {
-    if (own >= 0) R2_LOAD_DV_BWD(K)
-    // ring slot of tile t of row K: block K + 1 + t
-    R2_PRODUCTS(K, max(K - 1, 0), (K + 1 + half) % W1, R2_LOAD_A_BWD)
-    R2_FINISH(K)
+    for (int sl = 0; sl < WS; ++sl) {
+      R2_LOAD_A_BWD(sl, NB - 1, 2 * sl + half)
+      R2_LOAD_A_BWD(WS + sl, max(NB - 2, 0), 2 * sl + half)
+    }
+    __syncthreads();
+    for (int K = NB - 1; K >= 0; K -= 2) {
+      if (own >= 0) R2_LOAD_DV_BWD(K)
+      R2_PRODUCTS(K, max(K - 2, 0), (K + 1 + half) % W1, R2_LOAD_A_BWD, 0)
+      R2_FINISH(K)
+      if (K - 1 >= 0) {
+        if (own >= 0) R2_LOAD_DV_BWD(K - 1)
+        R2_PRODUCTS(K - 1, max(K - 3, 0), (K + half) % W1, R2_LOAD_A_BWD, WS)
+        R2_FINISH(K - 1)
+      }
+    }
+  } else {
+#pragma unroll
+    for (int sl = 0; sl < P; ++sl) R2_LOAD_A_BWD(sl, NB - 1, 2 * sl + half)
+    __syncthreads();
+    for (int K = NB - 1; K >= 0; --K) {
+      if (own >= 0) R2_LOAD_DV_BWD(K)
+      R2_PRODUCTS(K, max(K - 1, 0), (K + 1 + half) % W1, R2_LOAD_A_BWD, 0)
+      R2_FINISH(K)
+    }
   }
 #undef R2_LOAD_DV_BWD
 #undef R2_LOAD_A_BWD
@@ -1191,6 +1233,70 @@ __global__ __launch_bounds__(NT) void k_eig_rq(const SubDesc* __restrict__ subs,
   }
 }
 
+// The same quotients for scalar problems, whose element matrices (64 values)
+// are read straight from memory: workgroup (j, chunk of 16 columns), lane
+// c % 16 of the column chunk, 16 element lanes striding the elements of the
+// box; the partial energies are added in a fixed order.
+template <int NC>
+__global__ __launch_bounds__(NT) void k_eig_rq_direct(const SubDesc* __restrict__ subs, int nex, int ney,
+                                               const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
+                                               PouDev pa, int b, const double* __restrict__ V,
+                                               double* __restrict__ lam) {
+  constexpr int ND = 8 * NC;
+  __shared__ double sa[16][17], sb[16][17];
+  const SubDesc& sd = subs[blockIdx.x];
+  const int cl = threadIdx.x & 15, el = threadIdx.x >> 4;
+  const int col = blockIdx.y * 16 + cl;
+  const int NX = nex + 1, NY = ney + 1;
+  const int n0 = sd.ehi[0] - sd.elo[0], n1 = sd.ehi[1] - sd.elo[1], n2 = sd.ehi[2] - sd.elo[2];
+  const int nel = n0 * n1 * n2;
+  double ea = 0.0, eb = 0.0;
+  if (col < b) {
+    const double* Vb = V + sd.offVB * b + col;
+    for (int t = el; t < nel; t += 16) {
+      const int ex = sd.elo[0] + t % n0, ey = sd.elo[1] + (t / n0) % n1, ez = sd.elo[2] + t / (n0 * n1);
+      double pv[ND], xv[ND];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int g0 = ex + (a & 1), g1 = ey + ((a >> 1) & 1), g2 = ez + (a >> 2);
+        const int rb = box_local_node(sd.blo, sd.bn, sd.permB, g0, g1, g2) * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          pv[a * NC + c] = Vb[(int64_t)(rb + c) * b];
+          xv[a * NC + c] = pou_x(sd, pa, dir, NX, NY, NC, g0, g1, g2, c) * pv[a * NC + c];
+        }
+      }
+      const bool ov = pou_overlap_elem(pa, ex, ey, ez);
+      const double* K = Ke + (ex + (int64_t)nex * (ey + (int64_t)ney * ez)) * (ND * ND);
+      double sA = 0.0, sB = 0.0;
+      for (int i = 0; i < ND; ++i) {
+        double kp = 0.0, kx = 0.0;
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+          const double k = K[i * ND + j];
+          kp += k * pv[j];
+          kx += k * xv[j];
+        }
+        sA += pv[i] * kp;
+        sB += xv[i] * kx;
+      }
+      ea += sA;
+      if (ov) eb += sB;
+    }
+  }
+  sa[el][cl] = ea;
+  sb[el][cl] = eb;
+  __syncthreads();
+  if (el == 0 && col < b) {
+    double ta = 0.0, tb = 0.0;
+    for (int q = 0; q < 16; ++q) {
+      ta += sa[q][cl];
+      tb += sb[q][cl];
+    }
+    lam[(int64_t)blockIdx.x * b + col] = tb > 0.0 ? ta / tb : INFINITY;
+  }
+}
+
 // Defect of the Ritz pairs in the original pencil, rho = B V - P V diag(nu)
 // (P V and B V from the node-ELL products), and the correction
 // V += (P^-1 rho) diag(1/nu): one inverse-iteration step in defect form, whose
@@ -1696,13 +1802,12 @@ void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s
 }
 
 void eig_rq(const gn_problem* p, const gn_precond* pc, int b, const double* V, double* lam, hipStream_t s) {
-  dim3 grid((unsigned)pc->n_sub, (unsigned)((b + 31) / 32));
   if (p->nc == 3)
-    hipLaunchKernelGGL(k_eig_rq<3>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke, p->d_dir,
-                       pou_axes(pc), b, V, lam);
+    hipLaunchKernelGGL(k_eig_rq<3>, dim3((unsigned)pc->n_sub, (unsigned)((b + 31) / 32)), dim3(NT), 0, s, pc->d_sub,
+                       p->ne[0], p->ne[1], p->d_Ke, p->d_dir, pou_axes(pc), b, V, lam);
   else
-    hipLaunchKernelGGL(k_eig_rq<1>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke, p->d_dir,
-                       pou_axes(pc), b, V, lam);
+    hipLaunchKernelGGL(k_eig_rq_direct<1>, dim3((unsigned)pc->n_sub, (unsigned)((b + 15) / 16)), dim3(NT), 0, s,
+                       pc->d_sub, p->ne[0], p->ne[1], p->d_Ke, p->d_dir, pou_axes(pc), b, V, lam);
   GN_CHECK_LAUNCH();
 }
 
@@ -1832,8 +1937,8 @@ void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, con
   } while (0)
       switch (W2) {
         case 6: GN_R2W(6, 3); break;
-        case 12: GN_R2W(12, 6); break;
-        case 14: GN_R2W(14, 7); break;
+        case 12: GN_R2W(12, 12); break;
+        case 14: GN_R2W(14, 14); break;
         case 16: GN_R2W(16, 4); break;
         case 18: GN_R2W(18, 3); break;
         case 20: GN_R2W(20, 5); break;
