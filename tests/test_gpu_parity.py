@@ -381,6 +381,24 @@ def test_indefinite_material_is_not_spd():
         prob.close()
 
 
+def test_pencil_band_too_wide_is_refused():
+    """Two subdomains of a 62 x 30 x 30 diffusion box: each Ibar box has a
+    31 x 31-node cross-section, a scalar pencil band of 32 tiles, wider than
+    the eigen block solves take (30 tiles; the local band, 32 tiles, still fits
+    the batched solves).  Set-up fails with GN_ERR_ARG naming the band, raised
+    on the host before any block-solve kernel is launched."""
+    gp = _gp()
+    w = gen.small_case("diffusion", seed=26, ne=(62, 30, 30), nparts=(2, 1, 1), overlap=1, threshold=0.15,
+                       nev_max=8)
+    prob = gp.Problem.from_workload(w)
+    try:
+        with pytest.raises(gp.GenPCGError) as e:
+            gp.Preconditioner.from_workload(prob, w)
+        assert e.value.code == -1 and "wider than the block solves take" in str(e.value), str(e.value)
+    finally:
+        prob.close()
+
+
 @pytest.mark.parametrize("name", ["lam_3x2x2_uneven", "diff_3x3x1"])
 def test_graph_replayed_chunks_match_eager_launches(name):
     """CG chunks replayed from a captured HIP graph give the bits of the
