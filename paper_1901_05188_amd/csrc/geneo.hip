@@ -275,14 +275,14 @@ __global__ __launch_bounds__(NT) void k_bapply(const SubDesc* __restrict__ subs,
 }
 
 // out = B V for vector problems: a thread computes all NC component rows of one
-// node for one BCW-column chunk, so each neighbour value it loads from V feeds
+// node for one CW-column chunk, so each neighbour value it loads from V feeds
 // NC rows (the one-component layout above loads every neighbour value once per
 // component).  Coefficients come straight from the node-ELL planes (the chunk
 // lanes of a node read the same addresses; staging them in LDS instead measured
 // slower, at the lower occupancy it allows); a lane whose coefficients on a
 // line are all zero loads no V for it.  Every output sums over the same
 // sequence (line, dx, c2) as the one-component kernel.
-template <int NC>
+template <int NC, int CW>
 __global__ __launch_bounds__(NT) void k_bapply_node(const SubDesc* __restrict__ subs, const double* __restrict__ BE,
                                                     int b, const double* __restrict__ V, double* __restrict__ out,
                                                     int gx, int ntot, const int* __restrict__ act) {
@@ -294,9 +294,9 @@ __global__ __launch_bounds__(NT) void k_bapply_node(const SubDesc* __restrict__ 
   if (act && act[by] == 0) return;
   const SubDesc& sd = subs[by];
   const int npad = sd.NBB * TILE;
-  const int nchunk = (b + BCW - 1) / BCW;
+  const int nchunk = (b + CW - 1) / CW;
   const int tid = bx * NT + threadIdx.x;
-  const int col0 = (tid % nchunk) * BCW;
+  const int col0 = (tid % nchunk) * CW;
   const int ln = tid / nchunk;
   if (ln * NC >= npad) return;
   const double* Vb = V + sd.offVB * b;
@@ -306,11 +306,11 @@ __global__ __launch_bounds__(NT) void k_bapply_node(const SubDesc* __restrict__ 
   st[sd.permB[1]] = sd.bn[sd.permB[0]];
   st[sd.permB[2]] = sd.bn[sd.permB[0]] * sd.bn[sd.permB[1]];
   const int nmax = sd.nB - 1;
-  double acc[NC][BCW];
+  double acc[NC][CW];
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int q = 0; q < BCW; ++q) acc[c][q] = 0.0;
+    for (int q = 0; q < CW; ++q) acc[c][q] = 0.0;
   const int a0 = sd.permB[0];
   const int ax1 = a0 == 0 ? 1 : 0, ax2 = a0 == 2 ? 1 : 2;
   const int s0 = a0 == 0 ? 1 : (a0 == 1 ? 3 : 9);
@@ -338,17 +338,17 @@ __global__ __launch_bounds__(NT) void k_bapply_node(const SubDesc* __restrict__ 
     if (!nz) continue;   // per lane: a node whose coefficients on this line are all zero loads no V
     // nodes ln - 1, ln, ln + 1 of this line (clamped into the box: their
     // coefficients are zero where the neighbour lies outside it)
-    double v[3][NC][BCW];
+    double v[3][NC][CW];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
       for (int c2 = 0; c2 < NC; ++c2) {
         const int r2 = min(max((ln - 1 + j + dn) * NC + c2, 0), nmax);
-        // a chunk may run up to BCW - 1 columns past the row end into the next
+        // a chunk may run up to CW - 1 columns past the row end into the next
         // row or the 64-double tail of the buffer: loads stay in bounds, stores are masked
         const double* vr = Vb + (int64_t)r2 * b + col0;
 #pragma unroll
-        for (int q = 0; q < BCW; ++q) v[j][c2][q] = vr[q];
+        for (int q = 0; q < CW; ++q) v[j][c2][q] = vr[q];
       }
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx)
@@ -357,14 +357,14 @@ __global__ __launch_bounds__(NT) void k_bapply_node(const SubDesc* __restrict__ 
 #pragma unroll
         for (int c2 = 0; c2 < NC; ++c2)
 #pragma unroll
-          for (int q = 0; q < BCW; ++q) acc[c][q] += bv[dx][c][c2] * v[dx][c2][q];
+          for (int q = 0; q < CW; ++q) acc[c][q] += bv[dx][c][c2] * v[dx][c2][q];
   }
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int row = ln * NC + c;
     if (row < npad)
 #pragma unroll
-      for (int q = 0; q < BCW; ++q)
+      for (int q = 0; q < CW; ++q)
         if (col0 + q < b) out[sd.offVB * b + (int64_t)row * b + col0 + q] = acc[c][q];
   }
 }
@@ -1872,11 +1872,13 @@ void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int
   const int nc = p->nc;
   if (nc == 3) {
     // one thread per node and column chunk, all three component rows
+    constexpr int CW = 8;
+    const int nchunk8 = (b + CW - 1) / CW;
     const int64_t nodes = (maxNBB * TILE + 2) / 3;
-    const int gx = (int)((nodes * nchunk + NT - 1) / NT);
+    const int gx = (int)((nodes * nchunk8 + NT - 1) / NT);
     const int ntot = gx * pc->n_sub;
-    hipLaunchKernelGGL((k_bapply_node<3>), dim3((unsigned)(8 * ((ntot + 7) / 8))), dim3(NT), 0, s, pc->d_sub, BE,
-                       b, V, out, gx, ntot, act);
+    hipLaunchKernelGGL((k_bapply_node<3, CW>), dim3((unsigned)(8 * ((ntot + 7) / 8))), dim3(NT), 0, s, pc->d_sub,
+                       BE, b, V, out, gx, ntot, act);
     GN_CHECK_LAUNCH();
     return;
   }
