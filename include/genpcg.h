@@ -96,9 +96,20 @@ typedef struct gn_loads {
 } gn_loads;
 
 /* Assemble A (27-point node-block matrix, FP64) and b on the device
- * (eqn:fe_matrix_system, 2x2x2 Gauss).  Returns a problem handle. */
+ * (eqn:fe_matrix_system, 2x2x2 Gauss).  Returns a problem handle.  The host
+ * arrays are read during the call; the material and load arrays are copied to
+ * the device and kept with the problem (gn_reassemble). */
 gn_status gn_assemble(const gn_grid* grid, const gn_material* mat, const gn_loads* loads,
                       void* stream, gn_problem** out);
+
+/* Assemble again, on the device, from the inputs the problem holds
+ * (eqn:fe_matrix_system, the same kernels as gn_assemble): the element
+ * matrices, A and b are recomputed in place, with no host array and no
+ * transfer from the host.  Results equal those of gn_assemble bit for bit.
+ * Synchronizes the stream.  Preconditioners built on p must not be used
+ * while the call runs (they read A and the element matrices); errors:
+ * GN_ERR_ARG (null problem), GN_ERR_DEVICE. */
+gn_status gn_reassemble(gn_problem* p, void* stream);
 
 /* Sizes: number of free DOFs, stored matrix entries, number of load columns. */
 gn_status gn_problem_info(const gn_problem* p, int64_t* n_free, int64_t* nnz, int32_t* nrhs);

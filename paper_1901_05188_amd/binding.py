@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgenpcg.so")
 GN_OK, GN_WARN_MAXIT, GN_PENDING = 0, 1, 2
 STATUS = {0: "OK", 1: "WARN_MAXIT", 2: "PENDING", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_NOT_SPD",
           -4: "ERR_EIG_NOCONV", -5: "ERR_COARSE_SINGULAR", -6: "ERR_DEVICE", -7: "ERR_BREAKDOWN"}
-EXPORTS = ["gn_assemble", "gn_problem_info", "gn_problem_rhs", "gn_load_vectors", "gn_load_vectors_noalloc",
+EXPORTS = ["gn_assemble", "gn_reassemble", "gn_problem_info", "gn_problem_rhs", "gn_load_vectors", "gn_load_vectors_noalloc",
            "gn_matvec",
            "gn_setup_geneo", "gn_precond_eigenvalues", "gn_precond_coarse_basis", "gn_precond_apply", "gn_solve", "gn_footprint", "gn_resident_bytes",
            "gn_server_create", "gn_server_add", "gn_server_register", "gn_server_operator_info",
@@ -98,6 +98,7 @@ def lib():
         vp = C.c_void_p
         L.gn_assemble.argtypes = [C.POINTER(gn_grid), C.POINTER(gn_material), C.POINTER(gn_loads), vp,
                                   C.POINTER(vp)]
+        L.gn_reassemble.argtypes = [vp, vp]
         L.gn_problem_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int32)]
         L.gn_problem_rhs.argtypes = [vp, vp, C.c_int64, vp]
@@ -260,6 +261,12 @@ class Problem:
                    elem_tilt=w.elem_tilt, elem_k=w.elem_k, dirichlet=w.dirichlet, body=w.body,
                    nrhs=w.nrhs, traction=w.traction, map_kind=w.map_kind, map_par=w.map_par,
                    stream=stream)
+
+    def reassemble(self, stream=None):
+        """Recompute the element matrices, A and b on the device from the inputs
+        the problem holds (gn_reassemble: no host transfer)."""
+        _check(lib().gn_reassemble(self.handle, _stream(stream)))
+        return self
 
     def rhs(self, out, stream=None):
         """Copy the assembled load into a (nrhs, n_free) float64 CUDA tensor (column = row of out)."""

@@ -292,6 +292,14 @@ extern "C" gn_status gn_profile_read(const char* group, double* total_ms, int64_
 // ---------------------------------------------------------------------------
 // assembly
 // ---------------------------------------------------------------------------
+// Element matrices, A and b from the inputs held on the device (eqn:fe_matrix_system).
+static void assemble_on_device(gn_problem* p, hipStream_t s) {
+  gnk::element_matrices(p, p->d_mats, p->n_mat, p->d_emat, p->d_eang, p->d_etilt, p->d_ek, s);
+  gnk::assemble_matrix(p, s);
+  gnk::assemble_load(p, p->d_body, p->d_trac, p->nrhs, p->d_b, s);
+  GN_HIP(hipStreamSynchronize(s));
+}
+
 extern "C" gn_status gn_assemble(const gn_grid* grid, const gn_material* mat, const gn_loads* loads,
                                  void* stream, gn_problem** out) {
   if (out) *out = nullptr;
@@ -354,7 +362,6 @@ extern "C" gn_status gn_assemble(const gn_grid* grid, const gn_material* mat, co
     if (!loads->dirichlet[d]) f2f.push_back((int)d);
   p->n_free = (int64_t)f2f.size();
   if (p->n_free == 0) argfail("no free DOFs");
-  std::vector<void*> tmp;
   for (int a = 0; a < 3; ++a) p->d_xn[a] = upload(p->owned, grid->xn[a], (size_t)p->nn[a], s);
   p->d_dir = upload(p->owned, loads->dirichlet, (size_t)p->n_dof, s);
   p->h_dir.assign(loads->dirichlet, loads->dirichlet + p->n_dof);
@@ -363,25 +370,20 @@ extern "C" gn_status gn_assemble(const gn_grid* grid, const gn_material* mat, co
   p->d_Ke = dalloc<double>(p->owned, (size_t)p->n_elem * nd * nd);
   p->d_A = dalloc<double>(p->owned, (size_t)p->n_node * 27 * nc * nc);
   p->d_b = dalloc<double>(p->owned, (size_t)p->n_dof * p->nrhs);
-  const double *d_mats = nullptr, *d_eang = nullptr, *d_etilt = nullptr, *d_ek = nullptr;
-  const int* d_emat = nullptr;
+  // the inputs stay on the device with the problem (gn_reassemble)
   if (p->pde == 1) {
-    d_mats = upload(tmp, mat->mat, (size_t)9 * mat->n_mat, s);
-    d_emat = upload(tmp, mat->elem_mat, (size_t)p->n_elem, s);
-    if (mat->elem_angle) d_eang = upload(tmp, mat->elem_angle, (size_t)p->n_elem, s);
-    if (mat->elem_tilt) d_etilt = upload(tmp, mat->elem_tilt, (size_t)p->n_elem, s);
+    p->n_mat = mat->n_mat;
+    p->d_mats = upload(p->owned, mat->mat, (size_t)9 * mat->n_mat, s);
+    p->d_emat = upload(p->owned, mat->elem_mat, (size_t)p->n_elem, s);
+    if (mat->elem_angle) p->d_eang = upload(p->owned, mat->elem_angle, (size_t)p->n_elem, s);
+    if (mat->elem_tilt) p->d_etilt = upload(p->owned, mat->elem_tilt, (size_t)p->n_elem, s);
   } else {
-    d_ek = upload(tmp, mat->elem_k, (size_t)p->n_elem, s);
+    p->d_ek = upload(p->owned, mat->elem_k, (size_t)p->n_elem, s);
   }
-  const double *d_body = nullptr, *d_trac = nullptr;
-  if (loads->body) d_body = upload(tmp, loads->body, (size_t)p->n_elem * nc, s);
+  if (loads->body) p->d_body = upload(p->owned, loads->body, (size_t)p->n_elem * nc, s);
   if (loads->traction)
-    d_trac = upload(tmp, loads->traction, (size_t)loads->nrhs * p->ne[0] * p->ne[1] * nc, s);
-  gnk::element_matrices(p, d_mats, mat->n_mat, d_emat, d_eang, d_etilt, d_ek, s);
-  gnk::assemble_matrix(p, s);
-  gnk::assemble_load(p, d_body, d_trac, p->nrhs, p->d_b, s);
-  GN_HIP(hipStreamSynchronize(s));
-  dfree_all(tmp);
+    p->d_trac = upload(p->owned, loads->traction, (size_t)loads->nrhs * p->ne[0] * p->ne[1] * nc, s);
+  assemble_on_device(p, s);
   // CG workspace
   p->d_x = dalloc<double>(p->owned, (size_t)p->n_dof);
   p->d_r = dalloc<double>(p->owned, (size_t)p->n_dof);
@@ -406,6 +408,23 @@ extern "C" gn_status gn_assemble(const gn_grid* grid, const gn_material* mat, co
   catch (...) {
     if (p) { dfree_all(p->owned); delete p; }
     gn_set_error(GN_ERR_DEVICE, "unexpected exception in gn_assemble");
+    return GN_ERR_DEVICE;
+  }
+}
+
+extern "C" gn_status gn_reassemble(gn_problem* p, void* stream) {
+  if (!p) {
+    gn_set_error(GN_ERR_ARG, "null problem");
+    return GN_ERR_ARG;
+  }
+  try {
+    assemble_on_device(p, (hipStream_t)stream);
+    return GN_OK;
+  } catch (const gn_error& e) {
+    gn_set_error(e.code, e.msg);
+    return e.code;
+  } catch (...) {
+    gn_set_error(GN_ERR_DEVICE, "unexpected exception in gn_reassemble");
     return GN_ERR_DEVICE;
   }
 }
@@ -713,6 +732,17 @@ static int64_t estimate_footprint(const int ne[3], int nc, const gn_dd_opts* o, 
   add(n_elem * nd * nd * 8);
   add(n_node * 27 * nc * nc * 8);
   add(n_dof * nrhs * 8);
+  // the assembly's inputs kept with the problem, every optional array counted
+  if (nc == 3) {
+    add(9 * 8);            // material rows (a few)
+    add(n_elem * 4);       // element material ids
+    add(n_elem * 8);       // ply angles
+    add(n_elem * 8);       // tilts
+  } else {
+    add(n_elem * 8);       // conductivities
+  }
+  add(n_elem * nc * 8);                         // body force
+  add((int64_t)nrhs * ne[0] * ne[1] * nc * 8);  // top-face tractions
   for (int v = 0; v < 5; ++v) add(n_dof * 8);
   const int64_t pstride = std::max<int64_t>((n_node + 255) / 256, gnk::reduce_blocks());
   add(pstride * 8);

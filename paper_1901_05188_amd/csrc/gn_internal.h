@@ -191,6 +191,11 @@ struct gn_problem {
   uint8_t* d_dir = nullptr;    // Dirichlet mask, full numbering
   std::vector<uint8_t> h_dir;  // the same mask on the host
   int* d_free2full = nullptr;  // n_free
+  // the assembly's inputs, kept on the device for gn_reassemble (null where absent)
+  int n_mat = 0;
+  const double *d_mats = nullptr, *d_eang = nullptr, *d_etilt = nullptr, *d_ek = nullptr;
+  const int* d_emat = nullptr;
+  const double *d_body = nullptr, *d_trac = nullptr;
   // CG workspace (full numbering)
   double *d_x = nullptr, *d_r = nullptr, *d_p = nullptr, *d_q = nullptr, *d_z = nullptr;
   double* d_part = nullptr;    // block partial sums

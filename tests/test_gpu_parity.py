@@ -120,6 +120,40 @@ def test_load_vector_matches_oracle(name):
     assert np.allclose(got, b, rtol=1e-12, atol=1e-14 * np.abs(b).max())
 
 
+@pytest.mark.parametrize("name", ["lam_ramp_traction", "diff_2x2x2"])
+def test_reassembly_gives_the_same_bits(name):
+    """gn_reassemble recomputes the element matrices, A and b on the device from
+    the inputs the problem keeps (no host arrays): A x and b equal those of the
+    first assembly bit for bit, and a preconditioner built afterwards applies
+    as one built on a fresh assembly."""
+    gp = _gp()
+    w = orc.workload(name)
+    prob = gp.Problem.from_workload(w)
+    try:
+        X = _t(np.random.default_rng(2).standard_normal((3, prob.n_free)))
+        y0, y1 = torch.zeros_like(X), torch.zeros_like(X)
+        b0 = torch.zeros((prob.nrhs, prob.n_free), dtype=torch.float64, device=DEV)
+        b1 = torch.zeros_like(b0)
+        prob.matvec(X, y0)
+        prob.rhs(b0)
+        prob.reassemble()
+        prob.matvec(X, y1)
+        prob.rhs(b1)
+        assert torch.equal(y0, y1) and torch.equal(b0, b1)
+        pc = gp.Preconditioner.from_workload(prob, w, eig_tol=1e-14)   # the settings of precond()
+        try:
+            r = X[:1].contiguous()
+            z1, z2 = torch.zeros_like(r), torch.zeros_like(r)
+            pc.apply(r, z1)
+            pc2 = precond(name)
+            pc2.apply(r, z2)
+            assert torch.equal(z1, z2)
+        finally:
+            pc.close()
+    finally:
+        prob.close()
+
+
 @pytest.mark.parametrize("name", ["lam_2x2", "diff_2x2x2"])
 def test_plain_cg_matches_dense_solve(name):
     A, b, free, Ke = orc.system(name)
