@@ -1457,19 +1457,39 @@ __global__ __launch_bounds__(NT) void k_ah_pairs(const SubDesc* __restrict__ sub
   if (m1 == 0 || m2 == 0) return;
   int n0 = pr.hi[0] - pr.lo[0], n1 = pr.hi[1] - pr.lo[1], n2 = pr.hi[2] - pr.lo[2];
   int nnodes = n0 * n1 * n2;
-  for (int pidx = threadIdx.x; pidx < m1 * m2; pidx += NT) {
-    int k = pidx / m2, l = pidx % m2;
+  // entry (k, l) of the block: a sum over the nodes of the intersection; with
+  // fewer entries than threads, nsplit threads share an entry (every nsplit-th
+  // node each) and their partial sums are added in a fixed order
+  const int nent = m1 * m2;
+  const int nsplit = nent < NT ? NT / nent : 1;
+  __shared__ double red[NT];
+  for (int p0 = 0; p0 < nent; p0 += NT) {
+    const int pidx = p0 + threadIdx.x % (nsplit > 1 ? nent : NT), ch = nsplit > 1 ? threadIdx.x / nent : 0;
     double s = 0.0;
-    for (int t = 0; t < nnodes; ++t) {
-      int gi = pr.lo[0] + t % n0, gj = pr.lo[1] + (t / n0) % n1, gk = pr.lo[2] + t / (n0 * n1);
-      int l1 = box_local_node(s1.ilo, s1.in_, s1.permI, gi, gj, gk);
-      int l2 = box_local_node(s2.blo, s2.bn, s2.permB, gi, gj, gk);
+    if (pidx < nent && ch < nsplit) {
+      const int k = pidx / m2, l = pidx % m2;
+      for (int t = ch; t < nnodes; t += nsplit) {
+        int gi = pr.lo[0] + t % n0, gj = pr.lo[1] + (t / n0) % n1, gk = pr.lo[2] + t / (n0 * n1);
+        int l1 = box_local_node(s1.ilo, s1.in_, s1.permI, gi, gj, gk);
+        int l2 = box_local_node(s2.blo, s2.bn, s2.permB, gi, gj, gk);
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        s += Phi[s1.offPhi + (int64_t)(l1 * NC + c) * m1 + k] * Y[s2.offVB * b + (int64_t)(l2 * NC + c) * b + l];
+        for (int c = 0; c < NC; ++c)
+          s += Phi[s1.offPhi + (int64_t)(l1 * NC + c) * m1 + k] * Y[s2.offVB * b + (int64_t)(l2 * NC + c) * b + l];
+      }
     }
-    int row = s1.coff + k, col = s2.coff + l;
-    AH[((int64_t)(row / TILE) * NBH + col / TILE) * TILE2 + (col % TILE) * TILE + row % TILE] = s;
+    if (nsplit > 1) {
+      red[threadIdx.x] = s;
+      __syncthreads();
+      if (threadIdx.x < nent) {
+        s = 0.0;
+        for (int q = 0; q < nsplit; ++q) s += red[q * nent + threadIdx.x];
+      }
+    }
+    if (pidx < nent && ch == 0) {
+      const int k = pidx / m2, l = pidx % m2;
+      int row = s1.coff + k, col = s2.coff + l;
+      AH[((int64_t)(row / TILE) * NBH + col / TILE) * TILE2 + (col % TILE) * TILE + row % TILE] = s;
+    }
   }
 }
 
