@@ -1417,8 +1417,10 @@ __global__ __launch_bounds__(NT) void k_aphi(const SubDesc* __restrict__ subs, i
   int c = r % NC;
   int64_t node = g[0] + (int64_t)NX * (g[1] + (int64_t)NY * g[2]);
   double* yr = Y + sd.offVB * b + (int64_t)r * b;
-  for (int k0 = 0; k0 < sd.m; k0 += 8) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k0 = 0; k0 < sd.m; k0 += 16) {   // up to 16 columns per pass over the stencil
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
     for (int d = 0; d < 27; ++d) {
       int h[3] = {g[0] + d % 3 - 1, g[1] + (d / 3) % 3 - 1, g[2] + d / 9 - 1};
       bool in = true;
@@ -1431,12 +1433,12 @@ __global__ __launch_bounds__(NT) void k_aphi(const SubDesc* __restrict__ subs, i
         double av = A[((int64_t)(d * NC + c) * NC + c2) * n_node + node];
         const double* ph = Phi + sd.offPhi + (int64_t)(ln2 * NC + c2) * sd.m + k0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < 16; ++q)
           if (k0 + q < sd.m) acc[q] += av * ph[q];
       }
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
+    for (int q = 0; q < 16; ++q)
       if (k0 + q < sd.m) yr[k0 + q] = acc[q];
   }
 }
