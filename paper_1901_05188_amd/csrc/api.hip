@@ -933,18 +933,18 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
   std::vector<BandRefH> refs(n_sub);
   for (int j = 0; j < n_sub; ++j) refs[j] = BandRefH{pc->sub[j].offTI, pc->sub[j].offDI, pc->sub[j].NBI, pc->sub[j].wI};
   BandRefH* d_refs = upload(tmp, refs.data(), refs.size(), s);
-  gnk::band_chol(d_refs, n_sub, pc->maxwI, LI, DI, d_info, s);
+  // transposed backward band: the backward sweeps stream it like the forward
+  // ones; FP64 factors write it as they are computed, FP32 ones convert later
+  if (o->local_prec == 32) pc->d_LIb = dalloc<float>(pc->owned, (size_t)offTI * TILE2);
+  else pc->d_LIb = dalloc<double>(pc->owned, (size_t)offTI * TILE2);
+  const bool tb_done = gnk::band_chol(d_refs, n_sub, pc->maxwI, LI, DI, d_info, s,
+                                      o->local_prec == 32 ? nullptr : (double*)pc->d_LIb);
   GN_HIP(hipMemcpyAsync(info.data(), d_info, sizeof(int) * n_sub, hipMemcpyDeviceToHost, s));
   GN_HIP(hipStreamSynchronize(s));
   for (int j = 0; j < n_sub; ++j)
     if (info[j]) throw gn_error{GN_ERR_NOT_SPD, "local matrix of subdomain " + std::to_string(j) +
                                                     " not positive definite (row " + std::to_string(info[j] - 1) + ")"};
-  {
-    // transposed backward band: the backward sweeps stream it like the forward ones
-    if (o->local_prec == 32) pc->d_LIb = dalloc<float>(pc->owned, (size_t)offTI * TILE2);
-    else pc->d_LIb = dalloc<double>(pc->owned, (size_t)offTI * TILE2);
-    gnk::band_transpose(d_refs, n_sub, maxNBI, LI, DI, pc->d_LIb, o->local_prec == 32, s);
-  }
+  if (!tb_done) gnk::band_transpose(d_refs, n_sub, maxNBI, LI, DI, pc->d_LIb, o->local_prec == 32, s);
   if (o->local_prec == 32) {
     pc->d_LIf = dalloc<float>(pc->owned, (size_t)offTI * TILE2);
     pc->d_DIf = dalloc<float>(pc->owned, (size_t)offDI * TILE2);
@@ -1039,14 +1039,16 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     GN_HIP(hipMemsetAsync(d_info, 0, sizeof(int) * n_sub, s));
     int maxwB = 0;
     for (const SubDesc& sd : pc->sub) maxwB = std::max(maxwB, sd.wB);
-    gnk::band_chol(d_refs, n_sub, maxwB, LB, DB, d_info, s);
+    // the pencils' transposed bands (backward sweeps of the block solves) are
+    // written by the factorization as it goes
+    double* TBB = dalloc<double>(tmp, (size_t)offTB * TILE2);
+    const bool tbb_done = gnk::band_chol(d_refs, n_sub, maxwB, LB, DB, d_info, s, TBB);
     GN_HIP(hipMemcpyAsync(info.data(), d_info, sizeof(int) * n_sub, hipMemcpyDeviceToHost, s));
     GN_HIP(hipStreamSynchronize(s));
     for (int j = 0; j < n_sub; ++j)
       if (info[j]) throw gn_error{GN_ERR_NOT_SPD, "GenEO pencil of subdomain " + std::to_string(j) + " not definite"};
-    // transposed pencil band for the backward sweeps of the block solves
-    double* TBB = dalloc<double>(tmp, (size_t)offTB * TILE2);
-    gnk::band_transpose(d_refs, n_sub, maxNBB, LB, DB, TBB, false, s);
+    if (!tbb_done) gnk::band_transpose(d_refs, n_sub, maxNBB, LB, DB, TBB, false, s);
+
     const bool auto_block = o->eig_block <= 0;
     std::vector<double> h_nu;
     int solves_prev = 0;   // block solves of earlier attempts with a smaller block

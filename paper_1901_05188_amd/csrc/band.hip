@@ -178,7 +178,8 @@ __device__ inline void bc_lds_fence() {
 // the traffic of the products, and no memory latency on the X side.
 template <bool RL>
 __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict__ mats, double* __restrict__ T,
-                                                       double* __restrict__ D, int* __restrict__ info) {
+                                                       double* __restrict__ D, int* __restrict__ info,
+                                                       double* __restrict__ TB) {
   extern __shared__ double rowL[];   // RL: w tiles, column-major with TILE + 1 stride
   __shared__ double part[4][TILE][TILE + 1];
   __shared__ double Ss[TILE][TILE + 1];
@@ -283,6 +284,9 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
           const int row = qr * 16 + 4 * i + lk, col = qc * 16 + lr;
           const double l = (acc[0][i] + acc[1][i]) + (acc[2][i] + acc[3][i]);
           tk[col * TILE + row] = l;
+          // the transposed band (backward sweeps): block row J, slot w - t - 1
+          // holds L(K, J)^T
+          if (RL && TB) TB[tile_off(br.offT, J, w - t - 1, w) + row * TILE + col] = l;
           if (RL) rowL[t * (TILE * (TILE + 1)) + col * (TILE + 1) + row] = l;
         }
       } else if (wid == 0) {
@@ -340,6 +344,7 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
           const int r = e % TILE, c = e / TILE;
           tk[c * TILE + r] = (r >= c) ? Ss[r][c] : 0.0;
           dk[c * TILE + r] = Xs[r][c];
+          if (RL && TB) TB[tile_off(br.offT, K, w, w) + e] = Xs[c][r];   // slot w: Dinv_K^T
         }
       }
       __threadfence_block();
@@ -432,7 +437,7 @@ void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, dou
   GN_CHECK_LAUNCH();
 }
 
-void band_chol(const void* d_refs, int n, int maxw, double* T, double* D, int* info, hipStream_t s) {
+bool band_chol(const void* d_refs, int n, int maxw, double* T, double* D, int* info, hipStream_t s, double* TB) {
   // the row tiles in LDS when they fit beside the kernel's static arrays
   // (the four partial products and the exchange tile, 41.3 KB)
   const size_t rl = sizeof(double) * (size_t)std::max(maxw, 1) * TILE * (TILE + 1);
@@ -440,11 +445,14 @@ void band_chol(const void* d_refs, int n, int maxw, double* T, double* D, int* i
   if (rl + fixed <= 160 * 1024) {
     GN_HIP(hipFuncSetAttribute((const void*)k_band_chol_mfma<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)rl));
-    hipLaunchKernelGGL(k_band_chol_mfma<true>, dim3(n), dim3(NT), rl, s, (const BandRef*)d_refs, T, D, info);
-  } else {
-    hipLaunchKernelGGL(k_band_chol_mfma<false>, dim3(n), dim3(NT), 0, s, (const BandRef*)d_refs, T, D, info);
+    hipLaunchKernelGGL(k_band_chol_mfma<true>, dim3(n), dim3(NT), rl, s, (const BandRef*)d_refs, T, D, info, TB);
+    GN_CHECK_LAUNCH();
+    return TB != nullptr;
   }
+  // (without the row in LDS the registers have no room for the transposed stores)
+  hipLaunchKernelGGL(k_band_chol_mfma<false>, dim3(n), dim3(NT), 0, s, (const BandRef*)d_refs, T, D, info, nullptr);
   GN_CHECK_LAUNCH();
+  return false;
 }
 
 void band_transpose(const void* d_refs, int n, int maxNB, const double* T, const double* D, void* TB, bool f32,

@@ -332,7 +332,12 @@ void sub_partial(int64_t n, const double* b, const double* q, double* r, double*
 void extract_local(const gn_problem* p, const gn_precond* pc, double* L, int maxNB, hipStream_t s);
 void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, double* L, int maxNB,
                     hipStream_t s);
-void band_chol(const void* d_refs, int n, int maxw, double* T, double* D, int* info, hipStream_t s);
+// TB (may be null): also write the transposed band of the backward sweeps
+// (the layout of band_transpose, FP64; block rows past the end left unwritten)
+// when the row-in-LDS form runs; returns whether TB was written (otherwise
+// band_transpose makes it)
+bool band_chol(const void* d_refs, int n, int maxw, double* T, double* D, int* info, hipStream_t s,
+               double* TB = nullptr);
 void to_f32(int64_t n, const double* a, float* b, hipStream_t s);
 void band_transpose(const void* d_refs, int n, int maxNB, const double* T, const double* D, void* TB, bool f32,
                     hipStream_t s);
