@@ -148,27 +148,31 @@ __global__ __launch_bounds__(NT) void k_prolong(const SubDesc* __restrict__ subs
 // forms its row's sum in the order k = 0 .. m - 1 from LDS.  (Loading the rows
 // lane by lane had each load instruction touch 64 addresses m doubles apart.)
 constexpr int PHI_ROWS = 64;
-__global__ __launch_bounds__(PHI_ROWS) void k_phi_add(const SubDesc* __restrict__ subs,
-                                                      const double* __restrict__ Phi,
-                                                      const double* __restrict__ y, double* __restrict__ tvec,
-                                                      const double* __restrict__ done) {
-  extern __shared__ double sph[];   // PHI_ROWS x (m + 1)
+// blockDim.x / 64 waves per workgroup, each with its own 64-row block (fewer,
+// larger workgroups than one wave each)
+__global__ __launch_bounds__(4 * PHI_ROWS) void k_phi_add(const SubDesc* __restrict__ subs,
+                                                          const double* __restrict__ Phi,
+                                                          const double* __restrict__ y, double* __restrict__ tvec,
+                                                          const double* __restrict__ done) {
+  extern __shared__ double sph[];   // waves x PHI_ROWS x (m + 1)
   if (done && *done != 0.0) return;
   const SubDesc& sd = subs[blockIdx.y];
   const int m = sd.m;
-  const int r0 = blockIdx.x * PHI_ROWS;
-  if (m == 0 || r0 >= sd.nI) return;
-  const int nr = min(PHI_ROWS, sd.nI - r0);
+  const int nwv = blockDim.x / PHI_ROWS;
+  if (m == 0 || (int)blockIdx.x * nwv * PHI_ROWS >= sd.nI) return;   // the whole workgroup
+  const int wv = threadIdx.x / PHI_ROWS, lane = threadIdx.x % PHI_ROWS;
+  const int r0 = (blockIdx.x * nwv + wv) * PHI_ROWS;
+  const int nr = max(0, min(PHI_ROWS, sd.nI - r0));
+  double* mys = sph + wv * PHI_ROWS * (m + 1);
   const double* ph = Phi + sd.offPhi + (int64_t)r0 * m;
-  const int lane = threadIdx.x;
   for (int e = lane; e < nr * m; e += PHI_ROWS) {
     const int r = e / m, k = e - r * m;
-    sph[r * (m + 1) + k] = ph[e];
+    mys[r * (m + 1) + k] = ph[e];
   }
   __syncthreads();
   if (lane >= nr) return;
   const double* yy = y + sd.coff;
-  const double* mine = sph + lane * (m + 1);
+  const double* mine = mys + lane * (m + 1);
   double v = tvec[sd.offVI + r0 + lane];
   for (int k = 0; k < m; ++k) v += mine[k] * yy[k];
   tvec[sd.offVI + r0 + lane] = v;
@@ -211,9 +215,12 @@ void prolong(const gn_problem* p, const gn_precond* pc, const double* r, double*
   PartAxes pa{pc->d_cnt[0], pc->d_cnt[1], pc->d_cnt[2], pc->d_plo[0], pc->d_plo[1], pc->d_plo[2]};
   GnProfScope prof(PROF_PROLONG, pc->prolong_bytes, s);
   if (pc->NH > 0) {
-    hipLaunchKernelGGL(k_phi_add, dim3((unsigned)((pc->maxNBI * TILE + PHI_ROWS - 1) / PHI_ROWS), (unsigned)pc->n_sub),
-                       dim3(PHI_ROWS), sizeof(double) * PHI_ROWS * (pc->max_m + 1), s, pc->d_sub, pc->d_Phi,
-                       pc->d_y, pc->d_t, done);
+    // four waves per workgroup while their rows fit in 64 KB of LDS
+    const int nwv = sizeof(double) * 4 * PHI_ROWS * (pc->max_m + 1) <= 64 * 1024 ? 4 : 1;
+    const int rows = nwv * PHI_ROWS;
+    hipLaunchKernelGGL(k_phi_add, dim3((unsigned)((pc->maxNBI * TILE + rows - 1) / rows), (unsigned)pc->n_sub),
+                       dim3(rows), sizeof(double) * rows * (pc->max_m + 1), s, pc->d_sub, pc->d_Phi, pc->d_y,
+                       pc->d_t, done);
     GN_CHECK_LAUNCH();
   }
   const double* Phi = nullptr;   // folded into the local vectors above
