@@ -1073,7 +1073,6 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
       gnk::eig_vinit(pc, b, maxNBB, V, s);
       h_nu.assign((size_t)n_sub * b, 0.0);
       std::vector<double> h_res((size_t)n_sub * 2 * b);
-      std::vector<int> nwant(n_sub, 0);
       std::vector<double> worst_hist;
       bool converged = false;
       double* BE = dalloc<double>(tmp, (size_t)offVB * 27 * nc);
@@ -1133,7 +1132,6 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
             if (std::min(nw + 1, o->nev_max + 1) > b - guard / 2) jshort = true;
             nw = std::min(std::min(nw + 1, o->nev_max + 1), b - guard / 2);
           }
-          nwant[j] = nw;
           // pairs whose eigenvectors enter the coarse space (m_j of them, with a
           // generous cluster margin) need the full residual tolerance; the others
           // only decide m_j through their eigenvalues, whose error is of the order
