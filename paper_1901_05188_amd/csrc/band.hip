@@ -156,16 +156,9 @@ struct BandRef {
 // The four waves split the tile products of S (wave q takes t2 = t0 + q + 4m,
 // each a full 32 x 32 product on v_mfma_f64_16x16x4f64 with the operands of the
 // next product already in flight) and add their partials through LDS; the
-// diagonal tile is factored and inverted by one wave.
+// diagonal tile is factored and inverted by all four waves together.
 // ---------------------------------------------------------------------------
 typedef double bc_d4 __attribute__((ext_vector_type(4)));
-
-__device__ inline double bc_readlane(double v, int l) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
 
 __device__ inline void bc_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -183,9 +176,6 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
   extern __shared__ double rowL[];   // RL: w tiles, column-major with TILE + 1 stride
   __shared__ double part[4][TILE][TILE + 1];
   __shared__ double Ss[TILE][TILE + 1];
-  // the inverse of the diagonal tile is formed while no partial product is
-  // live (between the two barriers of the diagonal step), in part[3]
-  double(*Xs)[TILE + 1] = part[3];
   __shared__ int fail;
   const BandRef br = mats[blockIdx.x];
   const int w = br.w, NB = br.NB;
@@ -289,62 +279,98 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
           if (RL && TB) TB[tile_off(br.offT, J, w - t - 1, w) + row * TILE + col] = l;
           if (RL) rowL[t * (TILE * (TILE + 1)) + col * (TILE + 1) + row] = l;
         }
-      } else if (wid == 0) {
-        // dense Cholesky of the diagonal tile (lower), one wave, in registers:
-        // lane r (and its mirror r + 32) holds row r; column k's entries come
-        // from lane c by readlane
-        const int r = lane & (TILE - 1);
-        double a[TILE];
+      } else {
+        // diagonal tile: Gaussian elimination of [S | I] without pivoting, by
+        // all threads, one LDS barrier per column.  With d_k the k-th pivot and
+        // m_rk = S_k(r, k) / d_k its multipliers, S_{k+1}(r, j) = S_k(r, j) -
+        // m_rk S_k(j, k) (j > k, lower triangle; S_k(j, k) = S_k(k, j)), and the
+        // identity's rows take the same row operations, Y(r, c) -= m_rk Y(k, c),
+        // which leaves Y = Lu^-1 for the unit lower factor Lu of S = Lu diag(d) Lu^T.
+        // Then L = Lu diag(d)^1/2 (L(r, k) = S_k(r, k) / sqrt(d_k)) and
+        // L^-1 = diag(d)^-1/2 Y.  Column k of S_k and row k of Y are final once
+        // step k - 1 is done; their owners publish them to LDS (col[k][.],
+        // yr[k][.]) for step k.  Each thread owns four entries in registers: the
+        // 528 of the lower triangle of S, then the 496 strictly below the
+        // diagonal of Y.  col and yr start as zero, with yr(k, k) = 1, so every
+        // step updates every entry without a test: an S entry (r, j) with j < k
+        // and a Y entry (r, c) with c > k or r < k read a zero factor and keep
+        // their value exactly; an entry whose column (S) or row (Y) was
+        // published by step k - 1 may change afterwards, but only its
+        // published copy is read again.
+        double(*col)[TILE + 1] = part[0];
+        double(*yr)[TILE + 1] = part[1];
+        int er[4], ej[4];
+        double m[4];
+        constexpr int NS = TILE * (TILE + 1) / 2;   // 528
 #pragma unroll
-        for (int c = 0; c < TILE; ++c) a[c] = Ss[r][c];
+        for (int u = 0; u < 4; ++u) {
+          const int e = threadIdx.x + NT * u;
+          col[e / TILE][e % TILE] = 0.0;
+          yr[e / TILE][e % TILE] = (e / TILE == e % TILE) ? 1.0 : 0.0;
+        }
+        bc_lds_fence();
+        __builtin_amdgcn_s_barrier();
+        bc_lds_fence();
 #pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = threadIdx.x + NT * u;
+          const bool sx = e < NS;
+          const int f = sx ? e : e - NS;            // S: f = r (r + 1) / 2 + j; Y: f = r (r - 1) / 2 + c
+          int rr = (int)((sqrtf(8.0f * (float)f + 1.0f) - 1.0f) * 0.5f);
+          if ((rr + 1) * (rr + 2) / 2 <= f) ++rr;
+          if (rr * (rr + 1) / 2 > f) --rr;
+          // rr (rr + 1) / 2 <= f < (rr + 1) (rr + 2) / 2
+          if (sx) {
+            er[u] = rr;
+            ej[u] = f - rr * (rr + 1) / 2;
+            m[u] = Ss[er[u]][ej[u]];
+            if (ej[u] == 0) col[0][er[u]] = m[u];
+          } else {
+            er[u] = rr + 1;                          // strictly lower: rows 1..31
+            ej[u] = f - rr * (rr + 1) / 2;
+            m[u] = 0.0;
+          }
+        }
+        bc_lds_fence();
+        __builtin_amdgcn_s_barrier();
+        bc_lds_fence();
         for (int k = 0; k < TILE; ++k) {
-          double dkk = bc_readlane(a[k], k);
-          if (!(dkk > 0.0)) {
-            if (lane == 0 && !fail) fail = K * TILE + k + 1;
-            dkk = 1.0;
-          }
-          const double piv = sqrt(dkk);
-          a[k] = r == k ? piv : (r > k ? a[k] / piv : a[k]);
+          const int k1 = min(k + 1, TILE - 1);
+          double a[4], bb[4];
 #pragma unroll
-          for (int c = k + 1; c < TILE; ++c) {
-            const double lck = bc_readlane(a[k], c);
-            if (r >= c) a[c] -= a[k] * lck;
+          for (int u = 0; u < 4; ++u) {
+            const bool sx = threadIdx.x + NT * u < NS;
+            a[u] = col[k][er[u]];
+            bb[u] = sx ? col[k][ej[u]] : yr[k][ej[u]];
           }
+          double d = col[k][k];
+          if (!(d > 0.0)) {
+            if (threadIdx.x == 0 && !fail) fail = K * TILE + k + 1;
+            d = 1.0;
+          }
+          const double rd = 1.0 / d;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const bool sx = threadIdx.x + NT * u < NS;
+            m[u] -= (a[u] * rd) * bb[u];
+            if (sx ? (ej[u] == k + 1) : (er[u] == k + 1)) *(sx ? &col[k1][er[u]] : &yr[k1][ej[u]]) = m[u];
+          }
+          bc_lds_fence();
+          __builtin_amdgcn_s_barrier();
+          bc_lds_fence();
         }
-        bc_lds_fence();
-        if (lane < TILE) {
-#pragma unroll
-          for (int c = 0; c < TILE; ++c) Ss[r][c] = c <= r ? a[c] : 0.0;
-        }
-        bc_lds_fence();
-        // inverse of the lower-triangular factor: lane c forms column c in
-        // registers, reading the rows of the factor from LDS (broadcast)
-        {
-          const int c = r;
-          double xc[TILE];
-#pragma unroll
-          for (int i = 0; i < TILE; ++i) {
-            double s0 = i == c ? 1.0 : 0.0, s1 = 0.0;
-#pragma unroll
-            for (int k = 0; k < i; k += 2) {
-              s0 -= Ss[i][k] * xc[k];
-              if (k + 1 < i) s1 -= Ss[i][k + 1] * xc[k + 1];
-            }
-            xc[i] = i >= c ? (s0 + s1) / Ss[i][i] : 0.0;
-          }
-          if (lane < TILE) {
-#pragma unroll
-            for (int i = 0; i < TILE; ++i) Xs[i][c] = xc[i];
-          }
-        }
-        bc_lds_fence();
         double* dk = D + (br.offD + K) * TILE2;
-        for (int e = lane; e < TILE2; e += 64) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = threadIdx.x + NT * u;
           const int r = e % TILE, c = e / TILE;
-          tk[c * TILE + r] = (r >= c) ? Ss[r][c] : 0.0;
-          dk[c * TILE + r] = Xs[r][c];
-          if (RL && TB) TB[tile_off(br.offT, K, w, w) + e] = Xs[c][r];   // slot w: Dinv_K^T
+          const double dc = col[c][c] > 0.0 ? col[c][c] : 1.0;
+          const double dr = col[r][r] > 0.0 ? col[r][r] : 1.0;
+          const double l = r > c ? col[c][r] / sqrt(dc) : (r == c ? sqrt(dc) : 0.0);
+          const double x = r > c ? yr[r][c] / sqrt(dr) : (r == c ? 1.0 / sqrt(dr) : 0.0);
+          tk[c * TILE + r] = l;
+          dk[c * TILE + r] = x;
+          if (RL && TB) TB[tile_off(br.offT, K, w, w) + r * TILE + c] = x;   // slot w: Dinv_K^T
         }
       }
       __threadfence_block();
