@@ -289,9 +289,9 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
         // Then L = Lu diag(d)^1/2 (L(r, k) = S_k(r, k) / sqrt(d_k)) and
         // L^-1 = diag(d)^-1/2 Y.  Column k of S_k and row k of Y are final once
         // step k - 1 is done; their owners publish them to LDS (col[k][.],
-        // yr[k][.]) for step k.  Each thread owns four entries in registers: the
-        // 528 of the lower triangle of S, then the 496 strictly below the
-        // diagonal of Y.  col and yr start as zero, with yr(k, k) = 1, so every
+        // yr[k][.]) for step k.  Each thread owns up to five entries in
+        // registers: of the 528 of the lower triangle of S and of the 496
+        // strictly below the diagonal of Y.  col and yr start as zero, with yr(k, k) = 1, so every
         // step updates every entry without a test: an S entry (r, j) with j < k
         // and a Y entry (r, c) with c > k or r < k read a zero factor and keep
         // their value exactly; an entry whose column (S) or row (Y) was
@@ -299,9 +299,13 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
         // published copy is read again.
         double(*col)[TILE + 1] = part[0];
         double(*yr)[TILE + 1] = part[1];
-        int er[4], ej[4];
-        double m[4];
-        constexpr int NS = TILE * (TILE + 1) / 2;   // 528
+        double* sink = &part[2][0][0] + threadIdx.x;   // unpublished stores land here
+        // entries: S slots f = tid, tid + 256, tid + 512 (tid < 16) of the 528,
+        // Y slots f = tid, tid + 256 (tid < 240) of the 496; a thread without a
+        // third S or second Y entry takes (0, 0) there, which is never published
+        constexpr int NSL = 3, NYL = 2;
+        int sr[NSL], sj[NSL], yrw[NYL], yc[NYL];
+        double ms[NSL], my[NYL];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int e = threadIdx.x + NT * u;
@@ -312,23 +316,24 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
         __builtin_amdgcn_s_barrier();
         bc_lds_fence();
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = threadIdx.x + NT * u;
-          const bool sx = e < NS;
-          const int f = sx ? e : e - NS;            // S: f = r (r + 1) / 2 + j; Y: f = r (r - 1) / 2 + c
+        for (int u = 0; u < NSL + NYL; ++u) {
+          const bool isS = u < NSL;
+          const int f = threadIdx.x + NT * (isS ? u : u - NSL);
+          const bool ok = isS ? f < TILE * (TILE + 1) / 2 : f < TILE * (TILE - 1) / 2;
+          // S: f = r (r + 1) / 2 + j; Y: f = rr (rr + 1) / 2 + c with r = rr + 1
           int rr = (int)((sqrtf(8.0f * (float)f + 1.0f) - 1.0f) * 0.5f);
           if ((rr + 1) * (rr + 2) / 2 <= f) ++rr;
           if (rr * (rr + 1) / 2 > f) --rr;
-          // rr (rr + 1) / 2 <= f < (rr + 1) (rr + 2) / 2
-          if (sx) {
-            er[u] = rr;
-            ej[u] = f - rr * (rr + 1) / 2;
-            m[u] = Ss[er[u]][ej[u]];
-            if (ej[u] == 0) col[0][er[u]] = m[u];
+          const int c = f - rr * (rr + 1) / 2;
+          if (isS) {
+            sr[u] = ok ? rr : 0;
+            sj[u] = ok ? c : 0;
+            ms[u] = Ss[sr[u]][sj[u]];
+            if (ok && c == 0) col[0][rr] = ms[u];
           } else {
-            er[u] = rr + 1;                          // strictly lower: rows 1..31
-            ej[u] = f - rr * (rr + 1) / 2;
-            m[u] = 0.0;
+            yrw[u - NSL] = ok ? rr + 1 : 0;
+            yc[u - NSL] = ok ? c : 0;
+            my[u - NSL] = 0.0;
           }
         }
         bc_lds_fence();
@@ -336,12 +341,16 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
         bc_lds_fence();
         for (int k = 0; k < TILE; ++k) {
           const int k1 = min(k + 1, TILE - 1);
-          double a[4], bb[4];
+          double as[NSL], bs[NSL], ay[NYL], by[NYL];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const bool sx = threadIdx.x + NT * u < NS;
-            a[u] = col[k][er[u]];
-            bb[u] = sx ? col[k][ej[u]] : yr[k][ej[u]];
+          for (int u = 0; u < NSL; ++u) {
+            as[u] = col[k][sr[u]];
+            bs[u] = col[k][sj[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < NYL; ++u) {
+            ay[u] = col[k][yrw[u]];
+            by[u] = yr[k][yc[u]];
           }
           double d = col[k][k];
           if (!(d > 0.0)) {
@@ -350,10 +359,14 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
           }
           const double rd = 1.0 / d;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const bool sx = threadIdx.x + NT * u < NS;
-            m[u] -= (a[u] * rd) * bb[u];
-            if (sx ? (ej[u] == k + 1) : (er[u] == k + 1)) *(sx ? &col[k1][er[u]] : &yr[k1][ej[u]]) = m[u];
+          for (int u = 0; u < NSL; ++u) {
+            ms[u] -= (as[u] * rd) * bs[u];
+            *(sj[u] == k + 1 ? &col[k1][sr[u]] : sink) = ms[u];
+          }
+#pragma unroll
+          for (int u = 0; u < NYL; ++u) {
+            my[u] -= (ay[u] * rd) * by[u];
+            *(yrw[u] == k + 1 ? &yr[k1][yc[u]] : sink) = my[u];
           }
           bc_lds_fence();
           __builtin_amdgcn_s_barrier();
