@@ -280,107 +280,20 @@ __global__ __launch_bounds__(NT) void k_band_chol_mfma(const BandRef* __restrict
           if (RL) rowL[t * (TILE * (TILE + 1)) + col * (TILE + 1) + row] = l;
         }
       } else {
-        // diagonal tile: Gaussian elimination of [S | I] without pivoting, by
-        // all threads, one LDS barrier per column.  With d_k the k-th pivot and
-        // m_rk = S_k(r, k) / d_k its multipliers, S_{k+1}(r, j) = S_k(r, j) -
-        // m_rk S_k(j, k) (j > k, lower triangle; S_k(j, k) = S_k(k, j)), and the
-        // identity's rows take the same row operations, Y(r, c) -= m_rk Y(k, c),
-        // which leaves Y = Lu^-1 for the unit lower factor Lu of S = Lu diag(d) Lu^T.
-        // Then L = Lu diag(d)^1/2 (L(r, k) = S_k(r, k) / sqrt(d_k)) and
-        // L^-1 = diag(d)^-1/2 Y.  Column k of S_k and row k of Y are final once
-        // step k - 1 is done; their owners publish them to LDS (col[k][.],
-        // yr[k][.]) for step k.  Each thread owns up to five entries in
-        // registers: of the 528 of the lower triangle of S and of the 496
-        // strictly below the diagonal of Y.  col and yr start as zero, with yr(k, k) = 1, so every
-        // step updates every entry without a test: an S entry (r, j) with j < k
-        // and a Y entry (r, c) with c > k or r < k read a zero factor and keep
-        // their value exactly; an entry whose column (S) or row (Y) was
-        // published by step k - 1 may change afterwards, but only its
-        // published copy is read again.
+        // diagonal tile: factor and inverse by elimination of [S | I] on all
+        // four waves (tile_spd_eliminate), then the stores of L(K,K), Dinv_K
+        // and (RL) Dinv_K^T
         double(*col)[TILE + 1] = part[0];
         double(*yr)[TILE + 1] = part[1];
-        double* sink = &part[2][0][0] + threadIdx.x;   // unpublished stores land here
-        // entries: S slots f = tid, tid + 256, tid + 512 (tid < 16) of the 528,
-        // Y slots f = tid, tid + 256 (tid < 240) of the 496; a thread without a
-        // third S or second Y entry takes (0, 0) there, which is never published
-        constexpr int NSL = 3, NYL = 2;
-        int sr[NSL], sj[NSL], yrw[NYL], yc[NYL];
-        double ms[NSL], my[NYL];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = threadIdx.x + NT * u;
-          col[e / TILE][e % TILE] = 0.0;
-          yr[e / TILE][e % TILE] = (e / TILE == e % TILE) ? 1.0 : 0.0;
-        }
-        bc_lds_fence();
-        __builtin_amdgcn_s_barrier();
-        bc_lds_fence();
-#pragma unroll
-        for (int u = 0; u < NSL + NYL; ++u) {
-          const bool isS = u < NSL;
-          const int f = threadIdx.x + NT * (isS ? u : u - NSL);
-          const bool ok = isS ? f < TILE * (TILE + 1) / 2 : f < TILE * (TILE - 1) / 2;
-          // S: f = r (r + 1) / 2 + j; Y: f = rr (rr + 1) / 2 + c with r = rr + 1
-          int rr = (int)((sqrtf(8.0f * (float)f + 1.0f) - 1.0f) * 0.5f);
-          if ((rr + 1) * (rr + 2) / 2 <= f) ++rr;
-          if (rr * (rr + 1) / 2 > f) --rr;
-          const int c = f - rr * (rr + 1) / 2;
-          if (isS) {
-            sr[u] = ok ? rr : 0;
-            sj[u] = ok ? c : 0;
-            ms[u] = Ss[sr[u]][sj[u]];
-            if (ok && c == 0) col[0][rr] = ms[u];
-          } else {
-            yrw[u - NSL] = ok ? rr + 1 : 0;
-            yc[u - NSL] = ok ? c : 0;
-            my[u - NSL] = 0.0;
-          }
-        }
-        bc_lds_fence();
-        __builtin_amdgcn_s_barrier();
-        bc_lds_fence();
-        for (int k = 0; k < TILE; ++k) {
-          const int k1 = min(k + 1, TILE - 1);
-          double as[NSL], bs[NSL], ay[NYL], by[NYL];
-#pragma unroll
-          for (int u = 0; u < NSL; ++u) {
-            as[u] = col[k][sr[u]];
-            bs[u] = col[k][sj[u]];
-          }
-#pragma unroll
-          for (int u = 0; u < NYL; ++u) {
-            ay[u] = col[k][yrw[u]];
-            by[u] = yr[k][yc[u]];
-          }
-          double d = col[k][k];
-          if (!(d > 0.0)) {
-            if (threadIdx.x == 0 && !fail) fail = K * TILE + k + 1;
-            d = 1.0;
-          }
-          const double rd = 1.0 / d;
-#pragma unroll
-          for (int u = 0; u < NSL; ++u) {
-            ms[u] -= (as[u] * rd) * bs[u];
-            *(sj[u] == k + 1 ? &col[k1][sr[u]] : sink) = ms[u];
-          }
-#pragma unroll
-          for (int u = 0; u < NYL; ++u) {
-            my[u] -= (ay[u] * rd) * by[u];
-            *(yrw[u] == k + 1 ? &yr[k1][yc[u]] : sink) = my[u];
-          }
-          bc_lds_fence();
-          __builtin_amdgcn_s_barrier();
-          bc_lds_fence();
-        }
+        const int f = tile_spd_eliminate(Ss, col, yr, &part[2][0][0]);
+        if (threadIdx.x == 0 && f != 0 && !fail) fail = K * TILE + f;
         double* dk = D + (br.offD + K) * TILE2;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int e = threadIdx.x + NT * u;
           const int r = e % TILE, c = e / TILE;
-          const double dc = col[c][c] > 0.0 ? col[c][c] : 1.0;
-          const double dr = col[r][r] > 0.0 ? col[r][r] : 1.0;
-          const double l = r > c ? col[c][r] / sqrt(dc) : (r == c ? sqrt(dc) : 0.0);
-          const double x = r > c ? yr[r][c] / sqrt(dr) : (r == c ? 1.0 / sqrt(dr) : 0.0);
+          double l, x;
+          tile_spd_entry(col, yr, r, c, l, x);
           tk[c * TILE + r] = l;
           dk[c * TILE + r] = x;
           if (RL && TB) TB[tile_off(br.offT, K, w, w) + r * TILE + c] = x;   // slot w: Dinv_K^T

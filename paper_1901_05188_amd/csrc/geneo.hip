@@ -1527,72 +1527,28 @@ __device__ inline void lds_tile(double* dst, const double* src) {
   }
 }
 
-// a double from lane l of the wave (l uniform)
-__device__ inline double gn_readlane_d(double v, int l) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
-// Cholesky factor L(K,K) of the diagonal tile and its inverse Dinv_K, one wave
-// in registers: lane r (and its mirror r + 32) holds row r of the tile, the
-// column of step k comes from lane k by readlane; then lane c forms column c of
-// the inverse by forward substitution over the factor's rows (from LDS).  A
-// non-positive pivot records its index (first one only) in *info and is
-// replaced by 1 so the factorization runs to the end.
-__global__ __launch_bounds__(64) void k_potrf_tile(int NB, int K, double* __restrict__ A,
+// Cholesky factor L(K,K) of the diagonal tile and its inverse Dinv_K by one
+// workgroup (tile_spd_eliminate).  A non-positive pivot records its index
+// (first one only) in *info and is taken as 1 so the factorization runs to the
+// end.
+__global__ __launch_bounds__(NT) void k_potrf_tile(int NB, int K, double* __restrict__ A,
                                                    double* __restrict__ Dinv, int* __restrict__ info) {
+  static_assert(NT == 256, "the tile elimination takes 256 threads");
   __shared__ double S[TILE][TILE + 1];   // S[row][column]
+  __shared__ double col[TILE][TILE + 1], yr[TILE][TILE + 1], sink[NT];
   double* tk = A + ((int64_t)K * NB + K) * TILE2;
-  const int lane = threadIdx.x;
-  for (int e = lane; e < TILE2; e += 64) S[e % TILE][e / TILE] = tk[e];
+  for (int e = threadIdx.x; e < TILE2; e += NT) S[e % TILE][e / TILE] = tk[e];
   __syncthreads();
-  const int r = lane & (TILE - 1);
-  double a[TILE];
-#pragma unroll
-  for (int c = 0; c < TILE; ++c) a[c] = S[r][c];
-  int fail = 0;
-#pragma unroll
-  for (int k = 0; k < TILE; ++k) {
-    double dkk = gn_readlane_d(a[k], k);
-    if (!(dkk > 0.0)) {
-      if (fail == 0) fail = K * TILE + k + 1;
-      dkk = 1.0;
-    }
-    const double piv = sqrt(dkk);
-    a[k] = r == k ? piv : (r > k ? a[k] / piv : a[k]);
-#pragma unroll
-    for (int c = k + 1; c < TILE; ++c) {
-      const double lck = gn_readlane_d(a[k], c);
-      if (r >= c) a[c] -= a[k] * lck;
-    }
-  }
-  if (lane == 0 && fail != 0 && *info == 0) *info = fail;
-  __syncthreads();
-  if (lane < TILE) {
-#pragma unroll
-    for (int c = 0; c < TILE; ++c) S[r][c] = c <= r ? a[c] : 0.0;
-  }
-  __syncthreads();
-  const int c = r;
-  double xc[TILE];
-#pragma unroll
-  for (int i = 0; i < TILE; ++i) {
-    double sum = i == c ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < i; ++k) sum -= S[i][k] * xc[k];
-    xc[i] = i >= c ? sum / S[i][i] : 0.0;
-  }
-  for (int e = lane; e < TILE2; e += 64) tk[e] = S[e % TILE][e / TILE];
-  __syncthreads();   // every lane has read the factor
-  if (lane < TILE) {
-#pragma unroll
-    for (int i = 0; i < TILE; ++i) S[i][c] = xc[i];
-  }
-  __syncthreads();
+  const int f = tile_spd_eliminate(S, col, yr, sink);
+  if (threadIdx.x == 0 && f != 0 && *info == 0) *info = K * TILE + f;
   double* dk = Dinv + (int64_t)K * TILE2;
-  for (int e = lane; e < TILE2; e += 64) dk[e] = S[e % TILE][e / TILE];
+  for (int e = threadIdx.x; e < TILE2; e += NT) {
+    const int r = e % TILE, c = e / TILE;
+    double l, x;
+    tile_spd_entry(col, yr, r, c, l, x);
+    tk[e] = l;
+    dk[e] = x;
+  }
 }
 
 // L(I,K) = A(I,K) Dinv_K^T for I = K+1+blockIdx.x
@@ -2096,7 +2052,7 @@ void dense_chol(int NB, double* A, double* Dinv, int* info, hipStream_t s) {
   for (int K0 = 0; K0 < NB; K0 += CPANEL) {
     const int K1 = std::min(NB, K0 + CPANEL);
     for (int K = K0; K < K1; ++K) {
-      hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(64), 0, s, NB, K, A, Dinv, info);
+      hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(NT), 0, s, NB, K, A, Dinv, info);
       GN_CHECK_LAUNCH();
       const int m = NB - K - 1;
       if (m > 0) {

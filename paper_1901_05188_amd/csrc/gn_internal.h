@@ -516,6 +516,115 @@ struct GnProfScope {
 enum { PROF_SPMV = 0, PROF_TRSV, PROF_PROLONG, PROF_COARSE, PROF_VEC, PROF_NGROUP };
 
 // ---------------------------------------------------------------------------
+// Cholesky factor and inverse of one SPD TILE x TILE tile by a workgroup of
+// 256 threads: Gaussian elimination of [S | I] without pivoting, one LDS
+// barrier per column.  With d_k the k-th pivot and m_rk = S_k(r, k) / d_k its
+// multipliers, S_{k+1}(r, j) = S_k(r, j) - m_rk S_k(j, k) on the lower triangle
+// (S_k(j, k) = S_k(k, j)), and the identity's rows take the same row
+// operations, Y(r, c) -= m_rk Y(k, c), which leaves Y = Lu^-1 for the unit
+// lower factor Lu of S = Lu diag(d) Lu^T.  Then L = Lu diag(d)^1/2, i.e.
+// L(r, k) = S_k(r, k) / sqrt(d_k), and L^-1 = diag(d)^-1/2 Y.
+// Column k of S_k and row k of Y are final once step k - 1 is done; their
+// owners publish them to LDS (col[k][.], yr[k][.]) for step k.  A thread holds
+// three entries of the lower triangle of S (528) and two of the strictly
+// lower part of Y (496) in registers; where it has fewer it takes entry
+// (0, 0), which is never published.  col and yr start as zero, with
+// yr(k, k) = 1, so every step updates every entry without a test: an S entry
+// (r, j) with j < k and a Y entry (r, c) with c > k or r < k read a zero factor
+// and keep their value exactly; an entry already published may change
+// afterwards, but only its published copy is read again.
+//   S: the tile, S[r][c] (lower triangle read); col, yr: work tiles; sink: 256
+//   doubles that take the stores of entries not being published.  All in LDS.
+//   On return (after a barrier) col[k][r] = S_k(r, k) for r >= k and
+//   yr[r][c] = Y(r, c) for c < r; tile_spd_entry forms L and L^-1 from them.
+//   Returns 1 + the first step whose pivot is not positive (that pivot is
+//   taken as 1 and the elimination runs to the end), or 0.
+// ---------------------------------------------------------------------------
+__device__ inline void tile_lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+__device__ inline int tile_spd_eliminate(const double (*S)[TILE + 1], double (*col)[TILE + 1],
+                                         double (*yr)[TILE + 1], double* sink) {
+  constexpr int NTH = 256, NSL = 3, NYL = 2;
+  const int tid = threadIdx.x;
+  int sr[NSL], sj[NSL], yrw[NYL], yc[NYL];
+  double ms[NSL], my[NYL];
+#pragma unroll
+  for (int u = 0; u < TILE2 / NTH; ++u) {
+    const int e = tid + NTH * u;
+    col[e / TILE][e % TILE] = 0.0;
+    yr[e / TILE][e % TILE] = (e / TILE == e % TILE) ? 1.0 : 0.0;
+  }
+  tile_lds_barrier();
+#pragma unroll
+  for (int u = 0; u < NSL + NYL; ++u) {
+    const bool isS = u < NSL;
+    const int f = tid + NTH * (isS ? u : u - NSL);
+    const bool ok = isS ? f < TILE * (TILE + 1) / 2 : f < TILE * (TILE - 1) / 2;
+    // S: f = r (r + 1) / 2 + j; Y: f = rr (rr + 1) / 2 + c with r = rr + 1
+    int rr = (int)((sqrtf(8.0f * (float)f + 1.0f) - 1.0f) * 0.5f);
+    if ((rr + 1) * (rr + 2) / 2 <= f) ++rr;
+    if (rr * (rr + 1) / 2 > f) --rr;
+    const int c = f - rr * (rr + 1) / 2;
+    if (isS) {
+      sr[u] = ok ? rr : 0;
+      sj[u] = ok ? c : 0;
+      ms[u] = S[sr[u]][sj[u]];
+      if (ok && c == 0) col[0][rr] = ms[u];
+    } else {
+      yrw[u - NSL] = ok ? rr + 1 : 0;
+      yc[u - NSL] = ok ? c : 0;
+      my[u - NSL] = 0.0;
+    }
+  }
+  tile_lds_barrier();
+  int fail = 0;
+  for (int k = 0; k < TILE; ++k) {
+    const int k1 = k + 1 < TILE ? k + 1 : TILE - 1;
+    double as[NSL], bs[NSL], ay[NYL], by[NYL];
+#pragma unroll
+    for (int u = 0; u < NSL; ++u) {
+      as[u] = col[k][sr[u]];
+      bs[u] = col[k][sj[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < NYL; ++u) {
+      ay[u] = col[k][yrw[u]];
+      by[u] = yr[k][yc[u]];
+    }
+    double d = col[k][k];
+    if (!(d > 0.0)) {
+      if (fail == 0) fail = k + 1;
+      d = 1.0;
+    }
+    const double rd = 1.0 / d;
+#pragma unroll
+    for (int u = 0; u < NSL; ++u) {
+      ms[u] -= (as[u] * rd) * bs[u];
+      *(sj[u] == k + 1 ? &col[k1][sr[u]] : sink + tid) = ms[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NYL; ++u) {
+      my[u] -= (ay[u] * rd) * by[u];
+      *(yrw[u] == k + 1 ? &yr[k1][yc[u]] : sink + tid) = my[u];
+    }
+    tile_lds_barrier();
+  }
+  return fail;
+}
+// Entry (r, c) of L and of L^-1 from the results of tile_spd_eliminate (a pivot
+// that was not positive is taken as 1, as there).
+__device__ inline void tile_spd_entry(const double (*col)[TILE + 1], const double (*yr)[TILE + 1], int r, int c,
+                                      double& l, double& x) {
+  const double dc = col[c][c] > 0.0 ? col[c][c] : 1.0;
+  const double dr = col[r][r] > 0.0 ? col[r][r] : 1.0;
+  l = r > c ? col[c][r] / sqrt(dc) : (r == c ? sqrt(dc) : 0.0);
+  x = r > c ? yr[r][c] / sqrt(dr) : (r == c ? 1.0 / sqrt(dr) : 0.0);
+}
+
+// ---------------------------------------------------------------------------
 // device reduction helpers (fixed order: deterministic for a fixed launch shape)
 // ---------------------------------------------------------------------------
 __device__ inline double wave_sum(double v) {
