@@ -669,9 +669,10 @@ __global__ __launch_bounds__(NT) void k_gram(const SubDesc* __restrict__ subs, i
         a[u] = Z[ro + acol];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+          // column blocks past b are neither loaded nor multiplied
           int col = min(q * 16 + lr, 63);
-          bvv[u][q] = BV[ro + col];
-          bzv[u][q] = BZ[ro + col];
+          bvv[u][q] = q < ncb ? BV[ro + col] : 0.0;
+          bzv[u][q] = q < ncb ? BZ[ro + col] : 0.0;
         }
       }
 #pragma unroll
