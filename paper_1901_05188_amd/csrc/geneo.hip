@@ -970,8 +970,9 @@ __global__ __launch_bounds__(NT) void k_small_eig(int b, const double* __restric
 
 // V = Z Y and BV = (B Z) Y (the B-image of the new block without another B
 // application) on FP64 matrix cores: each wave takes 16 rows of one subdomain
-// (grid.y) and all b columns, A operands straight from Z and BZ (16 rows x 4
-// columns per K-step, all K-steps loaded before the first product), B operands
+// (grid.y) and all b columns, A operands straight from Z and BZ (lane group lk
+// holds columns KS lk .. KS lk + KS - 1 of its row, all loaded before the
+// first product), B operands
 // from Y, staged in LDS once per workgroup (rows padded to b + 1 doubles, so
 // the four 16-lane groups of a read hit different banks).  Columns past b are
 // masked to zero on both operands, so no padding value enters a product.
@@ -995,19 +996,30 @@ __global__ __launch_bounds__(NT) void k_vupdate(const SubDesc* __restrict__ subs
   if (r0 >= nrow) return;                   // no barrier follows
   const int lr = lane & 15, lk = lane >> 4;
   const int64_t arow = sd.offVB * b + (int64_t)(r0 + lr) * b;
+  // the K index of step ks in lane group lk is KS lk + ks (any order of the
+  // sum serves): each lane reads KS consecutive columns of its row, which the
+  // compiler merges into 16-byte loads
   double za[KS], ba[KS];
+  if (b == 4 * KS) {                        // full width: no column is masked
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const int k = 4 * ks + lk;
-    za[ks] = k < b ? Z[arow + k] : 0.0;
-    ba[ks] = k < b ? BZ[arow + k] : 0.0;
+    for (int ks = 0; ks < KS; ++ks) {
+      za[ks] = Z[arow + KS * lk + ks];
+      ba[ks] = BZ[arow + KS * lk + ks];
+    }
+  } else {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = KS * lk + ks;
+      za[ks] = k < b ? Z[arow + k] : 0.0;
+      ba[ks] = k < b ? BZ[arow + k] : 0.0;
+    }
   }
   gn_d4 az[CB], ab[CB];
 #pragma unroll
   for (int q = 0; q < CB; ++q) az[q] = ab[q] = gn_d4{0, 0, 0, 0};
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
-    const int k = 4 * ks + lk;
+    const int k = KS * lk + ks;
 #pragma unroll
     for (int q = 0; q < CB; ++q) {
       const int c = q * 16 + lr;
