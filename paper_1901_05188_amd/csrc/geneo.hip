@@ -1106,6 +1106,10 @@ __global__ __launch_bounds__(NT) void k_cheb_first(const SubDesc* __restrict__ s
 }
 
 // Y0 <- a (TY - c Y1) - beta Y0 in place (step i: coef[2 + 2(i-2)], coef[3 + 2(i-2)])
+// Two entries per thread (a subdomain block holds an even count, 32 NBB b,
+// from an even offset): 16-byte accesses; the launcher checks the buffers'
+// 16-byte alignment.
+typedef double gn_d2 __attribute__((ext_vector_type(2)));
 __global__ __launch_bounds__(NT) void k_cheb_step(const SubDesc* __restrict__ subs, int b,
                                                   const double* __restrict__ TY, const double* __restrict__ Y1,
                                                   double* __restrict__ Y0, const double* __restrict__ coef,
@@ -1113,12 +1117,18 @@ __global__ __launch_bounds__(NT) void k_cheb_step(const SubDesc* __restrict__ su
   if (act && act[blockIdx.y] == 0) return;
   const SubDesc& sd = subs[blockIdx.y];
   const int64_t n = (int64_t)sd.NBB * TILE * b;
-  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t e = 2 * ((int64_t)blockIdx.x * NT + threadIdx.x);
   if (e >= n) return;
   const double* cf = coef + (int64_t)blockIdx.y * ncoef;
   const double c = cf[1], a = cf[2 + 2 * step], beta = cf[3 + 2 * step];
   const int64_t o = sd.offVB * b + e;
-  Y0[o] = a * (TY[o] - c * Y1[o]) - beta * Y0[o];
+  const gn_d2 ty = *reinterpret_cast<const gn_d2*>(TY + o);
+  const gn_d2 y1 = *reinterpret_cast<const gn_d2*>(Y1 + o);
+  const gn_d2 y0 = *reinterpret_cast<const gn_d2*>(Y0 + o);
+  gn_d2 out;
+  out[0] = a * (ty[0] - c * y1[0]) - beta * y0[0];
+  out[1] = a * (ty[1] - c * y1[1]) - beta * y0[1];
+  *reinterpret_cast<gn_d2*>(Y0 + o) = out;
 }
 
 // Zero-energy modes on the Ibar box of the subdomains with m_j > 0 (their
@@ -1960,7 +1970,9 @@ void eig_cheb_first(const gn_precond* pc, int b, const double* Z, const double* 
 
 void eig_cheb_step(const gn_precond* pc, int b, int maxNBB, const double* TY, const double* Y1, double* Y0,
                    const double* coef, int ncoef, int step, hipStream_t s, const int* act) {
-  dim3 grid((unsigned)(((int64_t)maxNBB * TILE * b + NT - 1) / NT), pc->n_sub);
+  if ((((uintptr_t)TY | (uintptr_t)Y1 | (uintptr_t)Y0) & 15) != 0)
+    throw gn_error{GN_ERR_ARG, "Chebyshev step buffers not 16-byte aligned"};
+  dim3 grid((unsigned)(((int64_t)maxNBB * TILE * b / 2 + NT - 1) / NT), pc->n_sub);
   hipLaunchKernelGGL(k_cheb_step, grid, dim3(NT), 0, s, pc->d_sub, b, TY, Y1, Y0, coef, ncoef, step, act);
   GN_CHECK_LAUNCH();
 }
