@@ -1033,7 +1033,12 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
     double* LB = dalloc<double>(tmp, (size_t)offTB * TILE2);
     double* DB = dalloc<double>(tmp, (size_t)offDB * TILE2);
     GN_HIP(hipMemsetAsync(LB, 0, sizeof(double) * (size_t)offTB * TILE2, s));
-    gnk::extract_pencil(p, pc, shift, LB, maxNBB, s);
+    // B = X A_O X for the iteration's products and P = A_N + s B for the
+    // refinement's, in node-ELL planes, from the same pass over the element
+    // matrices as the pencil's band
+    double* BE = dalloc<double>(tmp, (size_t)offVB * 27 * nc);
+    double* PE = dalloc<double>(tmp, (size_t)offVB * 27 * nc);
+    gnk::extract_pencil(p, pc, shift, LB, maxNBB, s, PE, BE);
     for (int j = 0; j < n_sub; ++j) refs[j] = BandRefH{pc->sub[j].offTB, pc->sub[j].offDB, pc->sub[j].NBB, pc->sub[j].wB};
     GN_HIP(hipMemcpyAsync(d_refs, refs.data(), sizeof(BandRefH) * n_sub, hipMemcpyHostToDevice, s));
     GN_HIP(hipMemsetAsync(d_info, 0, sizeof(int) * n_sub, s));
@@ -1075,8 +1080,6 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
       std::vector<double> h_res((size_t)n_sub * 2 * b);
       std::vector<double> worst_hist;
       bool converged = false;
-      double* BE = dalloc<double>(tmp, (size_t)offVB * 27 * nc);
-      gnk::eig_extract_b(p, pc, maxNBB, BE, s);
       gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);
       // Chebyshev-filtered subspace iteration: outer iteration it applies a filter
       // of degree d = min(dmax, it + 1) in T = P^-1 B (d block solves), then one
@@ -1282,8 +1285,6 @@ extern "C" gn_status gn_setup_geneo(gn_problem* p, const gn_dd_opts* o, void* st
         // matrices V^T P V and V^T B V from the same exact products.
         // Further steps (eig_refine) shrink the error components of the block
         // again by the ratio of the wanted to the unwanted nu.
-        double* PE = dalloc<double>(tmp, (size_t)offVB * 27 * nc);
-        gnk::eig_extract_p(p, pc, maxNBB, shift, PE, s);
         for (int step = 0; step < eig_refine; ++step) {
           gnk::eig_bapply(p, pc, PE, b, maxNBB, V, Z, s);       // Z = P V
           gnk::eig_bapply(p, pc, BE, b, maxNBB, V, BV, s);      // BV = B V

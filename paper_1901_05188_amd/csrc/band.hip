@@ -66,19 +66,30 @@ __global__ __launch_bounds__(NT) void k_extract_local(const SubDesc* __restrict_
 // ---------------------------------------------------------------------------
 // pencil P = A_N + s X A_O X on the Ibar_j box, from element matrices
 // (eqm:matrixForm: A_{Omega_j} over the elements of Omega_j, A_{Omega_j^o} over
-// the elements that also belong to another subdomain, X the PoU diagonal).
+// the elements that also belong to another subdomain, X the PoU diagonal),
+// Dirichlet rows and columns as identity: its lower band into L and, in the
+// same pass (PE, BE not null), all of P and B = X A_O X in node-ELL planes
+// (27 NC planes of npad rows from sd.offVB 27 NC) for the eigensolver's
+// products.  B takes no identity: its Dirichlet rows and columns are zero
+// (X vanishes there).
 // ---------------------------------------------------------------------------
 template <int NC>
 __global__ __launch_bounds__(NT) void k_extract_pencil(const SubDesc* __restrict__ subs, int nex, int ney, int nez,
                                                        const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
-                                                       PouDev pa, double shift, double* __restrict__ L) {
+                                                       PouDev pa, double shift, double* __restrict__ L,
+                                                       double* __restrict__ PE, double* __restrict__ BE) {
   const SubDesc& sd = subs[blockIdx.y];
   int r = blockIdx.x * NT + threadIdx.x;
   int nrows = sd.NBB * TILE;
   if (r >= nrows) return;
   const int w = sd.wB;
+  const bool planes = PE != nullptr;
+  double* pe = planes ? PE + sd.offVB * (27 * NC) : nullptr;
+  double* be = planes ? BE + sd.offVB * (27 * NC) : nullptr;
   if (r >= sd.nB) {
     L[tile_off(sd.offTB, r / TILE, w, w) + (r % TILE) * TILE + (r % TILE)] = 1.0;
+    if (planes)
+      for (int k = 0; k < 27 * NC; ++k) pe[(int64_t)k * nrows + r] = be[(int64_t)k * nrows + r] = 0.0;
     return;
   }
   const int NX = nex + 1, NY = ney + 1;
@@ -94,9 +105,16 @@ __global__ __launch_bounds__(NT) void k_extract_pencil(const SubDesc* __restrict
     bool in = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) in &= (h[a] >= sd.blo[a] && h[a] < sd.blo[a] + sd.bn[a]);
-    if (!in) continue;
-    int ln2 = box_local_node(sd.blo, sd.bn, sd.permB, h[0], h[1], h[2]);
-    if (ln2 * NC > r) continue;
+    const int ln2 = in ? box_local_node(sd.blo, sd.bn, sd.permB, h[0], h[1], h[2]) : 0;
+    // the band takes the neighbours at or before row r; the planes take all
+    if (!in || (ln2 * NC > r && !planes)) {
+      if (planes) {
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2)
+          pe[(int64_t)(d * NC + c2) * nrows + r] = be[(int64_t)(d * NC + c2) * nrows + r] = 0.0;
+      }
+      continue;
+    }
     double vN[NC], vO[NC];
 #pragma unroll
     for (int c2 = 0; c2 < NC; ++c2) vN[c2] = vO[c2] = 0.0;
@@ -126,16 +144,21 @@ __global__ __launch_bounds__(NT) void k_extract_pencil(const SubDesc* __restrict
 #pragma unroll
     for (int c2 = 0; c2 < NC; ++c2) {
       int r2 = ln2 * NC + c2;
-      if (r2 > r) continue;
+      const double x2 = pou_x(sd, pa, dir, NX, NY, NC, h[0], h[1], h[2], c2);
       double v;
       if (dr || dir[node2 * NC + c2]) {
         v = (r2 == r) ? 1.0 : 0.0;
       } else {
-        double x2 = pou_x(sd, pa, dir, NX, NY, NC, h[0], h[1], h[2], c2);
         v = vN[c2] + shift * xr * x2 * vO[c2];
       }
-      int K = r / TILE, J = r2 / TILE;
-      L[tile_off(sd.offTB, K, J - K + w, w) + (r2 % TILE) * TILE + (r % TILE)] = v;
+      if (r2 <= r) {
+        int K = r / TILE, J = r2 / TILE;
+        L[tile_off(sd.offTB, K, J - K + w, w) + (r2 % TILE) * TILE + (r % TILE)] = v;
+      }
+      if (planes) {
+        pe[(int64_t)(d * NC + c2) * nrows + r] = v;
+        be[(int64_t)(d * NC + c2) * nrows + r] = xr != 0.0 ? vO[c2] * (xr * x2) : 0.0;
+      }
     }
   }
 }
@@ -377,15 +400,16 @@ void extract_local(const gn_problem* p, const gn_precond* pc, double* L, int max
 }
 
 void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, double* L, int maxNB,
-                    hipStream_t s) {
+                    hipStream_t s, double* PE, double* BE) {
+  if ((PE == nullptr) != (BE == nullptr)) throw gn_error{GN_ERR_ARG, "pencil planes: PE and BE go together"};
   dim3 grid((unsigned)((maxNB * TILE + NT - 1) / NT), (unsigned)pc->n_sub);
   const PouDev pa = gnh::pou_dev(p, pc);
   if (p->nc == 3)
     hipLaunchKernelGGL(k_extract_pencil<3>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1],
-                       p->ne[2], p->d_Ke, p->d_dir, pa, shift, L);
+                       p->ne[2], p->d_Ke, p->d_dir, pa, shift, L, PE, BE);
   else
     hipLaunchKernelGGL(k_extract_pencil<1>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1],
-                       p->ne[2], p->d_Ke, p->d_dir, pa, shift, L);
+                       p->ne[2], p->d_Ke, p->d_dir, pa, shift, L, PE, BE);
   GN_CHECK_LAUNCH();
 }
 

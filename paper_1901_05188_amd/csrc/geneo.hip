@@ -22,129 +22,10 @@ constexpr int NT = 256;
 // ---------------------------------------------------------------------------
 // B V on the Ibar box (matrix-free from element matrices), b columns
 // ---------------------------------------------------------------------------
-// B = X A_O X stored once per set-up in node-ELL form on the Ibar box:
-// BE[k][r], k = d*NC + c2 (27 lattice offsets x components), structure of
-// arrays over the padded rows of each subdomain (base offVB * 27 * NC).
-template <int NC>
-__global__ __launch_bounds__(NT) void k_extract_b(const SubDesc* __restrict__ subs, int nex, int ney,
-                                                  const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
-                                                  PouDev pa, double* __restrict__ BE) {
-  const SubDesc& sd = subs[blockIdx.y];
-  const int r = blockIdx.x * NT + threadIdx.x;
-  const int npad = sd.NBB * TILE;
-  if (r >= npad) return;
-  double* base = BE + sd.offVB * (27 * NC);
-  if (r >= sd.nB) {
-    for (int k = 0; k < 27 * NC; ++k) base[(int64_t)k * npad + r] = 0.0;
-    return;
-  }
-  const int NX = nex + 1, NY = ney + 1;
-  const int ln = r / NC, c = r % NC;
-  int g[3];
-  box_global_node(sd.blo, sd.bn, sd.permB, ln, g);
-  const double xr = pou_x(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
-  for (int d = 0; d < 27; ++d) {
-    int h[3] = {g[0] + d % 3 - 1, g[1] + (d / 3) % 3 - 1, g[2] + d / 9 - 1};
-    double vO[NC];
-#pragma unroll
-    for (int c2 = 0; c2 < NC; ++c2) vO[c2] = 0.0;
-    bool in = xr != 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) in &= (h[a] >= sd.blo[a] && h[a] < sd.blo[a] + sd.bn[a]);
-    if (in) {
-      int lo[3], hi[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = max(max(g[a], h[a]) - 1, sd.elo[a]);
-        hi[a] = min(min(g[a], h[a]), sd.ehi[a] - 1);
-      }
-      for (int ez = lo[2]; ez <= hi[2]; ++ez)
-        for (int ey = lo[1]; ey <= hi[1]; ++ey)
-          for (int ex = lo[0]; ex <= hi[0]; ++ex) {
-            if (!pou_overlap_elem(pa, ex, ey, ez)) continue;   // not in Omega_j^o
-            int64_t e = ex + (int64_t)nex * (ey + (int64_t)ney * ez);
-            int a1 = (g[0] - ex) + 2 * (g[1] - ey) + 4 * (g[2] - ez);
-            int a2 = (h[0] - ex) + 2 * (h[1] - ey) + 4 * (h[2] - ez);
-            const double* row = Ke + e * (64 * NC * NC) + (int64_t)(a1 * NC + c) * (8 * NC) + a2 * NC;
-#pragma unroll
-            for (int c2 = 0; c2 < NC; ++c2) vO[c2] += row[c2];
-          }
-#pragma unroll
-      for (int c2 = 0; c2 < NC; ++c2) vO[c2] *= xr * pou_x(sd, pa, dir, NX, NY, NC, h[0], h[1], h[2], c2);
-    }
-#pragma unroll
-    for (int c2 = 0; c2 < NC; ++c2) base[(int64_t)(d * NC + c2) * npad + r] = vO[c2];
-  }
-}
-
-// P = A_N + s X A_O X in the same node-ELL form as B (k_extract_b), for the
-// final Rayleigh-Ritz step in the original pencil: A_N over every element of
-// Omega_j, A_O over those also in another subdomain, Dirichlet rows and
-// columns as identity (as the pencil band is extracted for its factor).
-template <int NC>
-__global__ __launch_bounds__(NT) void k_extract_p(const SubDesc* __restrict__ subs, int nex, int ney,
-                                                  const double* __restrict__ Ke, const uint8_t* __restrict__ dir,
-                                                  PouDev pa, double shift, double* __restrict__ PE) {
-  const SubDesc& sd = subs[blockIdx.y];
-  const int r = blockIdx.x * NT + threadIdx.x;
-  const int npad = sd.NBB * TILE;
-  if (r >= npad) return;
-  double* base = PE + sd.offVB * (27 * NC);
-  if (r >= sd.nB) {
-    for (int k = 0; k < 27 * NC; ++k) base[(int64_t)k * npad + r] = 0.0;
-    return;
-  }
-  const int NX = nex + 1, NY = ney + 1;
-  const int ln = r / NC, c = r % NC;
-  int g[3];
-  box_global_node(sd.blo, sd.bn, sd.permB, ln, g);
-  const int64_t node = g[0] + (int64_t)NX * (g[1] + (int64_t)NY * g[2]);
-  const bool dr = dir[node * NC + c];
-  const double xr = pou_x(sd, pa, dir, NX, NY, NC, g[0], g[1], g[2], c);
-  for (int d = 0; d < 27; ++d) {
-    int h[3] = {g[0] + d % 3 - 1, g[1] + (d / 3) % 3 - 1, g[2] + d / 9 - 1};
-    double vN[NC], vO[NC];
-#pragma unroll
-    for (int c2 = 0; c2 < NC; ++c2) vN[c2] = vO[c2] = 0.0;
-    bool in = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) in &= (h[a] >= sd.blo[a] && h[a] < sd.blo[a] + sd.bn[a]);
-    if (in) {
-      int lo[3], hi[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = max(max(g[a], h[a]) - 1, sd.elo[a]);
-        hi[a] = min(min(g[a], h[a]), sd.ehi[a] - 1);
-      }
-      for (int ez = lo[2]; ez <= hi[2]; ++ez)
-        for (int ey = lo[1]; ey <= hi[1]; ++ey)
-          for (int ex = lo[0]; ex <= hi[0]; ++ex) {
-            const int64_t e = ex + (int64_t)nex * (ey + (int64_t)ney * ez);
-            const int a1 = (g[0] - ex) + 2 * (g[1] - ey) + 4 * (g[2] - ez);
-            const int a2 = (h[0] - ex) + 2 * (h[1] - ey) + 4 * (h[2] - ez);
-            const bool ov = pou_overlap_elem(pa, ex, ey, ez);
-            const double* row = Ke + e * (64 * NC * NC) + (int64_t)(a1 * NC + c) * (8 * NC) + a2 * NC;
-#pragma unroll
-            for (int c2 = 0; c2 < NC; ++c2) {
-              vN[c2] += row[c2];
-              if (ov) vO[c2] += row[c2];
-            }
-          }
-      const int64_t node2 = h[0] + (int64_t)NX * (h[1] + (int64_t)NY * h[2]);
-#pragma unroll
-      for (int c2 = 0; c2 < NC; ++c2) {
-        if (dr || dir[node2 * NC + c2]) {
-          vN[c2] = (d == 13 && c2 == c) ? 1.0 : 0.0;
-        } else {
-          vN[c2] += shift * xr * pou_x(sd, pa, dir, NX, NY, NC, h[0], h[1], h[2], c2) * vO[c2];
-        }
-      }
-    }
-#pragma unroll
-    for (int c2 = 0; c2 < NC; ++c2) base[(int64_t)(d * NC + c2) * npad + r] = vN[c2];
-  }
-}
-
+// B = X A_O X and P = A_N + s B are stored once per set-up in node-ELL form on
+// the Ibar box by the pencil extraction: E[k][r], k = d*NC + c2 (27 lattice
+// offsets x components), structure of arrays over the padded rows of each
+// subdomain (base offVB * 27 * NC).
 // out = B V for b columns. A thread computes R consecutive nodes (one
 // component) of one BCW-column chunk. Consecutive nodes lie along the fastest
 // local axis a0 (the box's shortest), where the neighbours of R nodes are R + 2
@@ -1841,29 +1722,6 @@ void zem_modes(const gn_problem* p, const gn_precond* pc, int b, int maxNBB, dou
   else
     hipLaunchKernelGGL(k_zem_modes<1>, grid, dim3(NT), 0, s, pc->d_sub, p->d_xn[0], p->d_xn[1], p->d_xn[2],
                        p->map_kind, p->map_par[0], p->map_par[1], mtan, b, V);
-  GN_CHECK_LAUNCH();
-}
-
-void eig_extract_p(const gn_problem* p, const gn_precond* pc, int maxNBB, double shift, double* PE,
-                   hipStream_t s) {
-  dim3 grid((maxNBB * TILE + NT - 1) / NT, pc->n_sub);
-  if (p->nc == 3)
-    hipLaunchKernelGGL(k_extract_p<3>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke,
-                       p->d_dir, pou_axes(pc), shift, PE);
-  else
-    hipLaunchKernelGGL(k_extract_p<1>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke,
-                       p->d_dir, pou_axes(pc), shift, PE);
-  GN_CHECK_LAUNCH();
-}
-
-void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double* BE, hipStream_t s) {
-  dim3 grid((maxNBB * TILE + NT - 1) / NT, pc->n_sub);
-  if (p->nc == 3)
-    hipLaunchKernelGGL(k_extract_b<3>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke,
-                       p->d_dir, pou_axes(pc), BE);
-  else
-    hipLaunchKernelGGL(k_extract_b<1>, grid, dim3(NT), 0, s, pc->d_sub, p->ne[0], p->ne[1], p->d_Ke,
-                       p->d_dir, pou_axes(pc), BE);
   GN_CHECK_LAUNCH();
 }
 

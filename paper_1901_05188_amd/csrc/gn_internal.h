@@ -330,8 +330,9 @@ void residual_partial(int64_t n, const double* b, const double* q, double* part,
 void sub_partial(int64_t n, const double* b, const double* q, double* r, double* part, hipStream_t s);
 // band.hip
 void extract_local(const gn_problem* p, const gn_precond* pc, double* L, int maxNB, hipStream_t s);
+// PE, BE (both or neither): also P and B in node-ELL planes, from sd.offVB 27 nc
 void extract_pencil(const gn_problem* p, const gn_precond* pc, double shift, double* L, int maxNB,
-                    hipStream_t s);
+                    hipStream_t s, double* PE = nullptr, double* BE = nullptr);
 // TB (may be null): also write the transposed band of the backward sweeps
 // (the layout of band_transpose, FP64; block rows past the end left unwritten)
 // when the row-in-LDS form runs; returns whether TB was written (otherwise
@@ -383,9 +384,6 @@ void precond_mc(const gn_problem* p, const gn_precond* pc, const double* r, doub
                 int pstride, const double* scal, double* tm, double* gm, double* um, double* ym, hipStream_t s);
 // geneo.hip
 void eig_vinit(const gn_precond* pc, int b, int maxNBB, double* V, hipStream_t s);
-void eig_extract_b(const gn_problem* p, const gn_precond* pc, int maxNBB, double* BE, hipStream_t s);
-void eig_extract_p(const gn_problem* p, const gn_precond* pc, int maxNBB, double shift, double* PE,
-                   hipStream_t s);
 void eig_bapply(const gn_problem* p, const gn_precond* pc, const double* BE, int b, int maxNBB,
                 const double* V, double* out, hipStream_t s, const int* act = nullptr);
 void eig_trsm(const gn_precond* pc, int b, const double* T, const double* D, const double* TB, const double* Vin,
